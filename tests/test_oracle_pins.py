@@ -1,0 +1,494 @@
+"""Pins of the FP64 oracle to facts other than itself (CPU only).
+
+Each test checks the oracle against something the paper or mathematics fixes:
+lattice identities (Sec. 2.1, Eqs. 1-3, 5-8, 11), Table 1's tau_D / D pair,
+Poiseuille flow (exact at the magic relaxation time, second order otherwise:
+Sec. 2.1.1), exact mass conservation, exact moment recurrences and the
+continuum Gaussian for the advection-diffusion LBM (Sec. 2.1.2, Eqs. 12-13),
+the exact discrete two-mode solution of the steady 1-D advection-diffusion-
+sink problem, flux balances at steady state, and an independent push-form
+brute force on tiny grids.  A plausible mistake in the oracle (a wrong weight,
+sign, opposite index, equilibrium term, inlet/outlet rule or sink form) fails
+at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------------ lattice
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D2Q5, O.D3Q19, O.D3Q7])
+def test_lattice_isotropy(lat):
+    c, w, opp, cs2 = O.lattice_tables(lat)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs((w[:, None] * c).sum(0)).max() < 1e-16
+    second = np.einsum("i,ia,ib->ab", w, c, c)
+    dim = 3 if lat in (O.D3Q19, O.D3Q7) else 2
+    assert np.allclose(second[:dim, :dim], cs2 * np.eye(dim), atol=1e-15, rtol=0)
+    for i in range(len(w)):
+        assert (c[opp[i]] == -c[i]).all()
+        assert w[opp[i]] == w[i]
+
+
+def test_d2q9_matches_equations_1_to_8_and_11():
+    c, w, opp, cs2 = O.lattice_tables(O.D2Q9)
+    # Eqs. 6-8: 4/9 rest, 1/9 axes, 1/36 diagonals (exact rationals)
+    exact = [Fraction(4, 9)] + [Fraction(1, 9)] * 4 + [Fraction(1, 36)] * 4
+    assert [float(e) for e in exact] == list(w)
+    assert sum(exact) == 1
+    # Eqs. 1-3: c0 rest, c1/c3 = (+-1,0), c2/c4 = (0,+-1), c5..c8 diagonals
+    assert tuple(c[0]) == (0, 0, 0)
+    assert {tuple(c[1][:2]), tuple(c[3][:2])} == {(1, 0), (-1, 0)}
+    assert {tuple(c[2][:2]), tuple(c[4][:2])} == {(0, 1), (0, -1)}
+    assert all(abs(c[i][0]) == 1 and abs(c[i][1]) == 1 for i in range(5, 9))
+    # Eq. 11 (south boundary): the unknowns 5, 2, 6 move north and take the
+    # values of 7, 4, 8 -> those are their opposites.
+    for a, b in [(5, 7), (2, 4), (6, 8)]:
+        assert opp[a] == b and c[a][1] == 1
+    assert cs2 == 1.0 / 3.0
+
+
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
+def test_equilibrium_moments(lat):
+    c, w, opp, cs2 = O.lattice_tables(lat)
+    rng = np.random.default_rng(7)
+    dim = 3 if lat == O.D3Q19 else 2
+    for _ in range(20):
+        rho = 0.8 + 0.4 * rng.random()
+        u = np.zeros(3)
+        u[:dim] = 0.1 * (rng.random(dim) - 0.5)
+        f = O.feq(lat, rho, u)
+        assert abs(f.sum() - rho) < 1e-15
+        assert np.abs((c * f[:, None]).sum(0) - rho * u).max() < 1e-16
+        P = np.einsum("i,ia,ib->ab", f, c, c)
+        want = rho * (cs2 * np.eye(3) + np.outer(u, u))
+        assert np.abs(P[:dim, :dim] - want[:dim, :dim]).max() < 1e-15
+
+
+@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+def test_ad_equilibrium_moments(lat):
+    c, w, opp, cs2 = O.lattice_tables(lat)
+    u = np.array([0.03, -0.02, 0.01 if lat == O.D3Q7 else 0.0])
+    g = O.geq(lat, 0.7, u)
+    assert abs(g.sum() - 0.7) < 1e-15
+    assert np.abs((c * g[:, None]).sum(0) - 0.7 * u).max() < 1e-16
+
+
+def test_table1_tau_d_and_diffusivity_consistent():
+    """Table 1: tau_D = 0.5036 and D = 0.0012 mm^2/s satisfy
+    D = c_s^2 (tau_D - 1/2) dx^2/dt with the oracle's D2Q5 c_s^2 = 1/3,
+    dx = 1 mm (60 x 65 lattice on 60 x 65 mm) and dt = 1 s."""
+    vals = {}
+    with open(os.path.join(HERE, "golden", "table1_lbm.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v, _ = line.split()
+            vals[k] = float(v)
+    cs2 = O.lattice_tables(O.D2Q5)[3]
+    assert abs(cs2 * (vals["tau_D"] - 0.5) - vals["D"]) < 1e-15
+
+
+# ------------------------------------------------------------------ fluid
+def _poiseuille_error(H, tau, g=1e-6, steps=None):
+    ny, nx = H + 2, 4
+    cls = np.zeros((ny, nx), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    nu = (tau - 0.5) / 3
+    steps = steps or int(25 * H * H / nu)
+    f, U, _ = O.fluid_run(cls, O.fluid_init(cls), tau, 0.0, steps, periodic=(1, 0, 0),
+                          force=(g, 0.0, 0.0))
+    y = np.arange(ny)
+    exact = g / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+    ux = U[0].reshape(ny, nx)[:, 1]
+    return np.abs(ux[1:-1] - exact[1:-1]).max() / exact.max()
+
+
+@pytest.mark.parametrize("H", [8, 16])
+def test_poiseuille_exact_at_magic_tau(H):
+    """BGK + half-way bounce-back put the wall exactly half-way when
+    (tau - 1/2)^2 = 3/16: the parabola is reproduced to round-off."""
+    assert _poiseuille_error(H, (2.0 + math.sqrt(3.0)) / 4.0) < 1e-10
+
+
+def test_poiseuille_second_order():
+    """Sec. 2.1.1 claims second-order accuracy: the error falls ~4x per
+    doubling of the channel height."""
+    e8, e16 = _poiseuille_error(8, 0.8), _poiseuille_error(16, 0.8)
+    assert 3.6 < e8 / e16 < 4.4
+    assert e16 < 3e-3
+
+
+def test_channel_inlet_outlet_develops_parabola():
+    """Production boundaries (velocity inlet, pressure outlet): the
+    mid-length momentum profile j = rho u of a long empty channel is the
+    parabola carrying the injected mass flux (rho itself rises along the
+    channel with the driving pressure), and inflow equals outflow at steady
+    state."""
+    nx, ny, tau, uin = 200, 18, 0.8, 0.01
+    cls = np.zeros((ny, nx), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    r = O.fluid_solve(cls, tau, uin, 1e-8, 100000)
+    assert r["status"] == "OK"
+    U, rho = O.fluid_moments(cls, r["f"])
+    ux = (rho * U[0]).reshape(ny, nx)[1:-1, nx // 2]
+    y = np.arange(1, ny - 1)
+    shape = (y - 0.5) * (ny - 1.5 - y)
+    par = shape * (uin * (ny - 2)) / shape.sum()
+    assert np.abs(ux - par).max() / par.max() < 1e-2
+    fin, fout = O.fluid_fluxes(cls, r["f"], uin)
+    assert fin == pytest.approx(uin * (ny - 2), rel=1e-14)   # exactly u_in per inlet node
+    assert abs(fout - fin) / fin < 1e-7
+
+
+def _porous(nx, ny, seed, frac=0.3):
+    st, cls, _ = O.geom_discs(nx, ny, 2, 4, frac, 0, seed)
+    assert st == "OK"
+    return cls
+
+
+def test_mass_conservation_periodic_porous_fluid():
+    cls = _porous(64, 32, 11)
+    f0 = O.fluid_init(cls)
+    f1, _, _ = O.fluid_run(cls, f0, 0.7, 0.0, 1, periodic=(1, 0, 0), force=(2e-6, 0, 0))
+    f, _, _ = O.fluid_run(cls, f0, 0.7, 0.0, 3000, periodic=(1, 0, 0), force=(2e-6, 0, 0))
+    M0, M1 = f0.sum(), f.sum()
+    # round-off only: well under 1e-15 per step, accumulated
+    assert abs(f1.sum() - M0) / M0 < 1e-14
+    assert abs(M1 - M0) / M0 < 1e-11
+    U, _ = O.fluid_moments(cls, f, force=(2e-6, 0, 0))
+    assert U[0].max() > 1e-5          # the flow did develop
+
+
+def test_mass_conservation_3d_periodic():
+    st, cls, _ = O.geom_fibres(24, 12, 12, 1, 2, 0.2, 5)
+    assert st == "OK"
+    f0 = O.fluid_init(cls)
+    f, _, _ = O.fluid_run(cls, f0, 0.8, 0.0, 300, periodic=(1, 0, 0), force=(1e-5, 0, 0))
+    assert abs(f.sum() - f0.sum()) / f0.sum() < 1e-13
+
+
+def test_ad_closed_box_sink_removes_exactly_kC():
+    """Periodic box with biofilm nodes: each step removes k * sum(C) over
+    the biofilm, to round-off."""
+    cls = O.biofilm_layer(_porous(48, 24, 3))
+    nx, ny = 48, 24
+    rng = np.random.default_rng(1)
+    u = np.zeros((2, nx * ny))
+    u[0] = 0.02 * (cls.ravel() == O.FLUID)
+    g = O.ad_init(cls, u, 1.0) * (1.0 + 0.1 * rng.random((5, nx * ny)))
+    k = 2e-3
+    bf = cls.ravel() == O.BIOFILM
+    for _ in range(5):
+        g2, C = O.ad_step(cls, g, u, 0.05, 1.0, k, periodic=(1, 0, 0))
+        dM = g2.sum() - g.sum()
+        assert abs(dM - (-k * C[bf].sum())) < 1e-13 * g.sum()
+        g = g2
+
+
+def _gauss_setup(nx, ny, tau, ux, s0, x0, y0):
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    C0 = np.exp(-((X - x0) ** 2 + (Y - y0) ** 2) / (2 * s0 ** 2)).ravel()
+    c, w, opp, cs2 = O.lattice_tables(O.D2Q5)
+    g = np.array([w[i] * C0 * (1 + c[i, 0] * ux / cs2) for i in range(5)])
+    u = np.zeros((2, nx * ny))
+    u[0] = ux
+    return X.ravel(), Y.ravel(), C0, g, u, cs2
+
+
+def test_gaussian_pulse_exact_moment_recurrences():
+    """From the linear moment recurrences of the D2Q5 BGK map (started at
+    equilibrium, uniform u): the centroid moves exactly u per step and the
+    central second moment V obeys
+        V(t+1) - V(t) = 2 s_t + (c_s^2 - u^2) M,
+        s_t = (1-w)(c_s^2 - u^2) M / w * (1 - (1-w)^t),  w = 1/tau_D."""
+    nx, ny, tau, ux, T = 300, 64, 0.8, 0.05, 300
+    X, Y, C0, g, u, cs2 = _gauss_setup(nx, ny, tau, ux, 6.0, 80.0, 32.0)
+    D = (tau - 0.5) * cs2
+    _, C = O.ad_run(np.zeros((ny, nx), np.uint8), g, u, D, 1.0, 0.0, T, periodic=(1, 1, 0))
+    M0, M = C0.sum(), C.sum()
+    assert abs(M - M0) / M0 < 1e-13
+    X0 = (X * C0).sum() / M0
+    assert abs((X * C).sum() / M - X0 - ux * T) < 1e-10
+    om = 1.0 / tau
+    V0 = (X * X * C0).sum() - (X * C0).sum() ** 2 / M0
+    pred = V0 + sum(2 * (1 - om) * (cs2 - ux ** 2) * M0 / om * (1 - (1 - om) ** t)
+                    + (cs2 - ux ** 2) * M0 for t in range(T))
+    V = (X * X * C).sum() - (X * C).sum() ** 2 / M
+    assert abs(V - pred) / pred < 1e-11
+
+
+def test_gaussian_pulse_continuum():
+    """Continuum limit: Gaussian with variance s0^2 + 2 D_eff t, where the
+    linear equilibrium gives D_eff = (tau-1/2)(c_s^2 - u^2) along the flow."""
+    nx, ny, tau, ux, T, s0 = 240, 96, 0.8, 0.05, 300, 8.0
+    X, Y, C0, g, u, cs2 = _gauss_setup(nx, ny, tau, ux, s0, 80.0, 48.0)
+    _, C = O.ad_run(np.zeros((ny, nx), np.uint8), g, u, (tau - 0.5) * cs2, 1.0, 0.0, T,
+                    periodic=(1, 1, 0))
+    sx2 = s0 ** 2 + 2 * (tau - 0.5) * (cs2 - ux ** 2) * T
+    sy2 = s0 ** 2 + 2 * (tau - 0.5) * cs2 * T
+    ex = C0.sum() / (2 * np.pi * math.sqrt(sx2 * sy2)) * np.exp(
+        -(X - 80.0 - ux * T) ** 2 / (2 * sx2) - (Y - 48.0) ** 2 / (2 * sy2))
+    assert np.linalg.norm(C - ex) / np.linalg.norm(ex) < 2e-3
+
+
+def _ad_channel(N, u, k):
+    ny = 3
+    cls = np.zeros((ny, N), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    if k > 0:
+        cls[1] = O.BIOFILM
+    uu = np.zeros((2, ny * N))
+    uu[0] = u
+    return cls, uu
+
+
+def _two_mode(N, tau, u, k, outlet, c_in, c_out):
+    """Exact steady solution of the D2Q5 map on a y-uniform channel: in the
+    bulk every population is a combination of r^x modes, r a root of
+    (b + G a) r^2 - (a (A + b) + G (1 + a^2)) r + (A + G a) = 0 with
+    a = 1 - 1/tau, A = w(1+3u)/tau - w k, b = w(1-3u)/tau - w k,
+    G = 1/3 + (2/3) k tau, w = 1/6; the inlet and outlet link rules fix the
+    two amplitudes."""
+    w, om = 1.0 / 6.0, 1.0 / tau
+    a = 1 - om
+    A = om * w * (1 + 3 * u) - w * k
+    B = om * w * (1 - 3 * u) - w * k
+    G = 1.0 / 3.0 + (2.0 / 3.0) * k / om
+    roots = np.roots([B + G * a, -(a * (A + B) + G * (1 + a * a)), A + G * a])
+    a1 = lambda r: A * r / (r - a)      # post-collision +x amplitude
+    a3 = lambda r: B / (1 - a * r)      # post-collision -x amplitude
+    M = np.zeros((2, 2))
+    rhs = np.array([2 * w * c_in, 0.0 if outlet == 0 else 2 * w * c_out])
+    for m, r in enumerate(roots):
+        M[0, m] = a1(r) / r + a3(r)
+        M[1, m] = (a3(r) * r ** N - a3(r) * r ** (N - 1)) if outlet == 0 else \
+                  (a3(r) * r ** N + a1(r) * r ** (N - 1))
+    amp = np.linalg.solve(M, rhs)
+    x = np.arange(N)
+    return sum(amp[m] * roots[m] ** x for m in range(2))
+
+
+@pytest.mark.parametrize("N,tau,u,k,outlet,c_out", [
+    (64, 0.7, 0.01, 1e-3, 0, 0.0),
+    (50, 0.6, 0.02, 5e-3, 0, 0.0),
+    (40, 1.0, 0.03, 1e-2, 0, 0.0),
+    (64, 0.7, 0.01, 1e-3, 1, 0.3),
+    (64, 0.7, 0.01, 0.0, 1, 0.3),
+])
+def test_ad_1d_exact_discrete_solution(N, tau, u, k, outlet, c_out):
+    cls, uu = _ad_channel(N, u, k)
+    D = (tau - 0.5) / 3
+    g = O.ad_init(cls, uu, 1.0)
+    _, C = O.ad_run(cls, g, uu, D, 1.0, k, 200000, outlet, c_out)
+    C = C.reshape(3, N)[1]
+    assert np.abs(C - _two_mode(N, tau, u, k, outlet, 1.0, c_out)).max() < 1e-12
+
+
+def test_ad_no_sink_zero_gradient_is_uniform():
+    cls, uu = _ad_channel(64, 0.02, 0.0)
+    r = O.ad_solve(cls, uu, 0.1, 1.0, 0.0, 1e-14, 5000)
+    C = r["C"].reshape(3, 64)[1]
+    assert np.abs(C - 1.0).max() < 1e-14
+
+
+def test_ad_1d_continuum_second_order():
+    """Dirichlet-Dirichlet, no sink: C = c_in + (c_out - c_in)
+    (e^{u xi/D} - 1)/(e^{u L/D} - 1), xi = x + 1/2, L = N; error O(dx^2)."""
+    errs = []
+    for N in (32, 64, 128):
+        tau = 0.8
+        D = (tau - 0.5) / 3
+        u = 0.1 * 32 / N
+        cls, uu = _ad_channel(N, u, 0.0)
+        r = O.ad_solve(cls, uu, D, 1.0, 0.0, 1e-13, 2_000_000, outlet=1, c_out=0.0)
+        assert r["status"] == "OK"
+        C = r["C"].reshape(3, N)[1]
+        xi = np.arange(N) + 0.5
+        ex = 1.0 - (np.exp(u * xi / D) - 1) / (np.exp(u * N / D) - 1)
+        errs.append(np.abs(C - ex).max())
+    assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 3.0
+    assert errs[2] < 1e-2
+
+
+def test_ad_steady_flux_balance_porous():
+    """At steady state inflow - outflow = substrate consumed by the sink."""
+    cls = O.biofilm_layer(_porous(64, 24, 5, 0.25))
+    assert O.percolates(cls)
+    fl = O.fluid_solve(cls, 0.8, 0.02, 1e-9, 60000)
+    assert fl["status"] == "OK"
+    ad = O.ad_solve(cls, fl["U"], 0.1, 1.0, 5e-3, 1e-12, 200000)
+    assert ad["status"] == "OK"
+    fin, fout, sink = O.ad_fluxes(cls, ad["g"], 1.0, 5e-3)
+    assert sink > 0
+    assert abs((fin - fout) - sink) / sink < 1e-6
+    fi, fo = O.fluid_fluxes(cls, fl["f"], 0.02)
+    assert abs(fi - fo) / fi < 1e-6
+
+
+# ---------------------------------------------------------- stop semantics
+def test_blocked_medium_never_settles():
+    """A medium that does not percolate cannot carry the imposed inflow:
+    mass accumulates and the solve never converges (why the library rejects
+    such masks up front)."""
+    cls = O.biofilm_layer(_porous(64, 24, 4, 0.25))
+    assert not O.percolates(cls)
+    r = O.fluid_solve(cls, 0.8, 0.02, 1e-6, 5000)
+    assert r["status"] == "NOT_CONVERGED"
+    _, rho = O.fluid_moments(cls, r["f"])
+    assert rho[cls.ravel() == O.FLUID].mean() > 1.05
+
+
+def test_solve_status_codes():
+    cls = O.biofilm_layer(_porous(48, 20, 5, 0.2))
+    assert O.percolates(cls)
+    assert O.fluid_solve(cls, 0.8, 0.01, 1e-6, 1)["status"] == "NOT_CONVERGED"
+    r = O.fluid_solve(cls, 0.8, 0.01, 1e-6, 1)
+    assert r["iters"] == 1
+    r = O.fluid_solve(cls, 0.8, 0.01, 1e-3, 100000)
+    assert r["status"] == "OK" and r["iters"] % 100 == 0 and r["residual"] <= 1e-3
+    # unstable: tau -> 1/2 with a strong inflow blows up
+    assert O.fluid_solve(cls, 0.5001, 0.09, 1e-6, 20000)["status"] == "EDIVERGED"
+    # a floor above tol: round-off plateau -> STALLED
+    cls2, uu = _ad_channel(16, 0.02, 1e-2)
+    r = O.ad_solve(cls2, uu, 0.1, 1.0, 1e-2, 1e-30, 10_000_000, check_every=10, stall_checks=20)
+    assert r["status"] in ("STALLED", "OK")
+    if r["status"] == "OK":
+        assert r["residual"] == 0.0
+
+
+# --------------------------------------------------------------- brute force
+def _push_fluid(cls, f, tau, u_in, c, w, opp):
+    """Independent push form of one fluid step on a tiny grid: every stored
+    post-collision population is sent along its velocity; one that would
+    enter a blocked node returns reversed; one leaving through x < 0 returns
+    reversed with the moving-wall term; one leaving through x >= nx returns
+    as 2 w rho_out minus itself.  Then collide with Eq. 5."""
+    ny, nx = cls.shape
+    q = len(w)
+    N = nx * ny
+    arr = np.full((q, N), np.nan)
+    for y in range(ny):
+        for x in range(nx):
+            n = x + nx * y
+            if cls[y, x] != O.FLUID:
+                continue
+            for i in range(q):
+                p = f[i, n]
+                tx, ty = x + c[i, 0], y + c[i, 1]
+                j = opp[i]
+                if tx < 0:
+                    arr[j, n] = p + 6 * w[j] * c[j, 0] * u_in
+                elif tx >= nx:
+                    arr[j, n] = -p + 2 * w[j] * 1.0
+                elif ty < 0 or ty >= ny or cls[ty, tx] != O.FLUID:
+                    arr[j, n] = p
+                else:
+                    arr[i, tx + nx * ty] = p
+    out = np.zeros((q, N))
+    for n in range(N):
+        if cls.ravel()[n] != O.FLUID:
+            continue
+        fi = arr[:, n]
+        assert not np.isnan(fi).any()
+        rho = sum(fi)
+        ux = sum(c[i, 0] * fi[i] for i in range(q)) / rho
+        uy = sum(c[i, 1] * fi[i] for i in range(q)) / rho
+        for i in range(q):
+            cu = c[i, 0] * ux + c[i, 1] * uy
+            fe = w[i] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy))
+            out[i, n] = fi[i] - (fi[i] - fe) / tau
+    return out
+
+
+def _push_ad(cls, g, u, tau_d, c_in, k, c, w, opp):
+    ny, nx = cls.shape
+    q = len(w)
+    N = nx * ny
+    arr = np.full((q, N), np.nan)
+    blocked = lambda t: t in (O.SOLID, O.WALL)
+    for y in range(ny):
+        for x in range(nx):
+            n = x + nx * y
+            if blocked(cls[y, x]):
+                continue
+            for i in range(q):
+                p = g[i, n]
+                tx, ty = x + c[i, 0], y + c[i, 1]
+                j = opp[i]
+                if tx < 0:
+                    arr[j, n] = -p + 2 * w[j] * c_in
+                elif tx >= nx:
+                    arr[j, n] = g[j, n]          # ghost column copies the node
+                elif ty < 0 or ty >= ny or blocked(cls[ty, tx]):
+                    arr[j, n] = p
+                else:
+                    arr[i, tx + nx * ty] = p
+    out = np.zeros((q, N))
+    for n in range(N):
+        if blocked(cls.ravel()[n]):
+            continue
+        gi = arr[:, n]
+        assert not np.isnan(gi).any()
+        C = sum(gi)
+        kk = k if cls.ravel()[n] == O.BIOFILM else 0.0
+        for i in range(q):
+            cu = c[i, 0] * u[0, n] + c[i, 1] * u[1, n]
+            ge = w[i] * C * (1 + 3 * cu)
+            out[i, n] = gi[i] - (gi[i] - ge) / tau_d - w[i] * kk * C
+    return out
+
+
+def _tiny_mask():
+    cls = np.zeros((5, 6), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    cls[2, 3] = O.SOLID
+    cls[1, 3] = O.BIOFILM
+    return cls
+
+
+def test_bruteforce_push_fluid():
+    cls = _tiny_mask()
+    c, w, opp, _ = O.lattice_tables(O.D2Q9)
+    rng = np.random.default_rng(3)
+    f = O.fluid_init(cls) * (1 + 0.2 * rng.random((9, cls.size))) * (cls.ravel() == 0)
+    for _ in range(4):
+        want = _push_fluid(cls, f, 0.73, 0.04, c, w, opp)
+        got, _, _ = O.fluid_step(cls, f, 0.73, 0.04)
+        assert np.abs(got - want).max() < 1e-15
+        f = got
+
+
+def test_bruteforce_push_ad():
+    cls = _tiny_mask()
+    c, w, opp, _ = O.lattice_tables(O.D2Q5)
+    rng = np.random.default_rng(4)
+    u = 0.05 * (rng.random((2, cls.size)) - 0.5)
+    act = ~np.isin(cls.ravel(), [O.SOLID, O.WALL])
+    g = rng.random((5, cls.size)) * act
+    D = 0.08
+    tau_d = 0.5 + D * 3
+    for _ in range(4):
+        want = _push_ad(cls, g, u, tau_d, 0.9, 0.01, c, w, opp)
+        got, _ = O.ad_step(cls, g, u, D, 0.9, 0.01)
+        assert np.abs(got - want).max() < 1e-15
+        g = got
+
+
+def test_inlet_injects_exactly_u_in_per_node():
+    cls = _tiny_mask()
+    rng = np.random.default_rng(5)
+    f = O.fluid_init(cls) * (1 + 0.1 * rng.random((9, cls.size))) * (cls.ravel() == 0)
+    fin, _ = O.fluid_fluxes(cls, f, 0.03)
+    assert fin == pytest.approx(0.03 * 3, rel=1e-14)
