@@ -1,0 +1,197 @@
+"""Benchmark: coupled steady solves of the anode-compartment LBM on one GPU.
+
+One step = one pass of the hot path over the workload: fluid steady solve
+from rest (D2Q9 / D3Q19 BGK with bounce-back, velocity inlet, pressure
+outlet) to the residual tolerance, export of the velocity, then the
+substrate steady solve (D2Q5 / D3Q7 advection-diffusion with the biofilm
+sink) in that velocity, and the FP64 fluxes.  The electrode mask is built
+before the timed region (inputs resident in HBM).  value = lattice-node
+updates of both solvers per second over the timed steps, in MLUPS.
+
+Prints one JSON line with a roofline object for the dominant kernel (the
+fluid stream-collide step) and the FP64 CPU oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--storage fp32s]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM peak (fluid+AD LBM); served p50/p99 steady-solve latency"
+HBM_PEAK_GBS = 8000.0
+STORAGES = {"fp32": 0, "fp32s": 1, "fp16s": 2, "fp64": 3}
+DTYPES = {"fp32": "f32", "fp32s": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
+KERNEL_SRC = os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "kernels.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def algo_bytes(q, sb, extra=0):
+    """per active-node update: q populations read + q written, 1-byte class"""
+    return 2 * q * sb + 1 + extra
+
+
+def traffic_for(kernel, workload, storage):
+    try:
+        with open(TRAFFIC) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get("%s|%s|%s" % (kernel, workload, storage))
+    if not rec or rec.get("kernel_sha") != kernel_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
+    """FP64 oracle on a bounded sample of the same workload: repeated
+    100-step fluid and substrate segments until ~10 s of CPU time."""
+    import numpy as np
+    import oracle as O
+    f = O.fluid_init(cls)
+    nz = w["nz"]
+    n_f = int((cls == O.FLUID).sum())
+    n_a = int(np.isin(cls, [O.FLUID, O.BIOFILM]).sum())
+    t0 = time.perf_counter()
+    steps = 0
+    U = None
+    while True:
+        f, U, _ = O.fluid_run(cls, f, w["tau"], w["u_in"], 100)
+        steps += 100
+        el = time.perf_counter() - t0
+        if el >= min_seconds / 2 or el >= max_seconds / 2:
+            break
+    tf = time.perf_counter() - t0
+    g = O.ad_init(cls, U, w["c_in"])
+    t1 = time.perf_counter()
+    asteps = 0
+    while True:
+        g, _ = O.ad_run(cls, g, U, w["D"], w["c_in"], w["k"], 100)
+        asteps += 100
+        el = time.perf_counter() - t1
+        if el >= min_seconds / 2 or el >= max_seconds / 2:
+            break
+    ta = time.perf_counter() - t1
+    upd = steps * n_f + asteps * n_a
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": upd / (tf + ta) / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d fluid + %d substrate FP64 steps from rest on the same %s mask "
+                      "(%.1f s)" % (steps, asteps, w["name"], tf + ta)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--storage", default="fp32s", choices=sorted(STORAGES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the served stream and slab decomposition would shard across GPUs; "
+              "they are not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1802_07525_amd as lbm
+    from paper_1802_07525_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    lbm.load()
+    w = inputs.WORKLOADS[args.workload]
+    storage = STORAGES[args.storage]
+    if w["nz"] > 1:
+        st, cls, _ = lbm.lbm_geom_fibres(w["nx"], w["ny"], w["nz"], w["r_min"], w["r_max"],
+                                         w["solid"], w["seed"])
+    else:
+        st, cls, _ = lbm.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
+                                        w["overlap"], w["seed"])
+    assert st == 0
+    cls = lbm.lbm_biofilm_layer(cls)
+    max_iter = args.max_iter or w["max_iter"]
+    ctx = lbm.lbm_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+    p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                        storage=storage)
+    s = lbm.lbm_solver_create(ctx, cls, p)
+
+    def one_step():
+        sf, fi = lbm.lbm_solver_fluid(s, w["tol"], max_iter, 0)
+        if sf < 0:
+            raise RuntimeError("fluid solve failed: %s %s" % (lbm.status_name(sf),
+                                                              lbm.lbm_last_error(ctx)))
+        sa, ai = lbm.lbm_solver_ad(s, w["tol"], max_iter, 0)
+        if sa < 0:
+            raise RuntimeError("substrate solve failed: %s %s" % (lbm.status_name(sa),
+                                                                  lbm.lbm_last_error(ctx)))
+        return sf, fi, sa, ai
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [one_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    upd = sum(fi["iters"] * fi["active_nodes"] + ai["iters"] * ai["active_nodes"]
+              for _, fi, _, ai in recs)
+    value = upd / el / 1e6
+    sf, fi, sa, ai = recs[-1]
+    dim = 3 if w["nz"] > 1 else 2
+    qf, qa = (19, 7) if dim == 3 else (9, 5)
+    sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
+    cb = 8 if storage == 3 else 4
+    # dominant kernel: fluid step; HIP-event time over its launches in the timed region
+    f_ms = sum(r[1]["kernel_ms"] for r in recs)
+    f_launch = sum(r[1]["launches"] for r in recs)
+    a_ms = sum(r[3]["kernel_ms"] for r in recs)
+    a_launch = sum(r[3]["launches"] for r in recs)
+    avg_f = f_ms / max(f_launch, 1)
+    bytes_f = algo_bytes(qf, sb) * fi["active_nodes"]
+    achieved = bytes_f / (avg_f * 1e-3) / 1e9
+    # isolated per-launch HIP-event timing of the same kernel on the same state
+    _, iso_ms = lbm.lbm_solver_time_steps(s, 0, 200)
+    bytes_a = algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
+    kernel_name = "k_fluid_step<%s,%s>" % ("D3Q19" if dim == 3 else "D2Q9", args.storage)
+    traffic = traffic_for(kernel_name, args.workload, args.storage)
+    out = {
+        "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.storage], "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [w["nx"], w["ny"], w["nz"]],
+                   "storage": args.storage, "tau": w["tau"], "u_in": w["u_in"], "D": w["D"],
+                   "k_sink": w["k"], "tol": w["tol"], "seed": w["seed"],
+                   "fluid_status": lbm.status_name(sf), "fluid_iters": fi["iters"],
+                   "ad_status": lbm.status_name(sa), "ad_iters": ai["iters"],
+                   "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"]},
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algo_bytes_per_launch": bytes_f,
+                     "avg_launch_ms": avg_f, "avg_launch_ms_isolated": iso_ms,
+                     "ad_kernel_gbs": bytes_a / (a_ms / max(a_launch, 1) * 1e-3) / 1e9,
+                     "ad_avg_launch_ms": a_ms / max(a_launch, 1)},
+    }
+    lbm.lbm_solver_destroy(s)
+    lbm.lbm_ctx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cls, w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,321 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for the
+ * anode compartment of a microbial fuel cell, after Tsompanas et al.,
+ * "Modelling Microbial Fuel Cells using lattice Boltzmann methods"
+ * (arXiv 1802.07525).
+ *
+ * The library computes the two coupled steady states of the paper's model
+ * loop (Sec. 2, steps 2 and 3): the BGK fluid flow through a porous anode
+ * with bounce-back on electrode and biofilm nodes (Sec. 2.1.1, Eqs. 1-11),
+ * and the advection-diffusion of substrate in that frozen flow with
+ * zero-flux solids, a Dirichlet inlet and consumption on biofilm nodes
+ * (Sec. 2.1.2, Eqs. 12-13).  Both are re-converged whenever the biofilm
+ * changes (Sec. 2.3).  Everything that steps a lattice runs in hand-written
+ * HIP kernels on one GPU; the host side only validates, builds masks and
+ * decides when to stop.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid: nx * ny * nz nodes (nz = 1 for 2-D), linear index
+ *   n = x + nx * (y + ny * z), x fastest.  Flow enters at x = 0 and leaves
+ *   at x = nx - 1 (Sec. 3: influent from the left, effluent to the right).
+ * Node classes (uint8): LBM_FLUID, LBM_SOLID (electrode), LBM_WALL
+ *   (chassis), LBM_BIOFILM.  Rows y = 0 and y = ny - 1 (and planes z = 0,
+ *   nz - 1 in 3-D) must be WALL or SOLID; columns x = 0 and x = nx - 1 must
+ *   hold no SOLID or BIOFILM.  The fluid sees SOLID, WALL and BIOFILM as
+ *   blocked (the biofilm is impermeable, Sec. 2.3 and Sec. 4); the
+ *   substrate sees only SOLID and WALL as blocked and is consumed on
+ *   BIOFILM.
+ * Lattices: D2Q9 / D2Q5 in 2-D, D3Q19 / D3Q7 in 3-D.  D2Q9 directions
+ *   follow Eqs. 1-3 with 1=(1,0), 2=(0,1), 3=(-1,0), 4=(0,-1), 5=(1,1),
+ *   6=(-1,1), 7=(-1,-1), 8=(1,-1) (opposites 1-3, 2-4, 5-7, 6-8 as Eq. 11
+ *   pairs them); D2Q5 is 0..4 of that.  D3Q19: 0 rest; 1..6 = +x,-x,+y,-y,
+ *   +z,-z; 7..18 = (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),
+ *   (1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1); D3Q7 is 0..6.
+ * Units: lattice units throughout.  tau > 1/2 is the fluid relaxation time
+ *   of Eq. 4 (nu = (tau - 1/2)/3); D > 0 is the substrate diffusivity, and
+ *   the substrate relaxation time of Eq. 12 is tau_D = 1/2 + D / c_s^2 with
+ *   c_s^2 = 1/3 (D2Q5) or 1/4 (D3Q7) -- the relation Table 1's tau_D and D
+ *   satisfy.
+ * Memory: the caller owns every pointer it passes and keeps it valid for
+ *   the call; the library never frees caller memory and copies what it
+ *   keeps.  Handles are owned by the library until their destroy call.
+ *   Array arguments are host (CPU) memory unless a call says otherwise.
+ * Threads: a context (and the solvers made from it) is used by one host
+ *   thread at a time.  Server calls are thread-safe.
+ * Errors: every call that can fail returns lbm_status.  LBM_NOT_CONVERGED
+ *   and LBM_STALLED still fill every output.  LBM_EDEVICE means a HIP call
+ *   failed; lbm_last_error() then holds the HIP message.  No call aborts
+ *   the process.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_NOT_CONVERGED = 1, /* max_iter reached; outputs hold the last state */
+    LBM_STALLED = 2,       /* residual stopped improving above tol */
+    LBM_EINVAL = -1,       /* bad argument, mask or geometry */
+    LBM_ENOMEM = -2,       /* device or host allocation failed */
+    LBM_EDEVICE = -3,      /* a HIP call failed (see lbm_last_error) */
+    LBM_EDIVERGED = -4,    /* NaN/Inf, or |u| > 0.3 in the fluid */
+    LBM_EBUSY = -5,        /* resource in use (server full, call in flight) */
+    LBM_ENOTFOUND = -6     /* unknown ticket or field */
+} lbm_status;
+
+/* Population storage.  Arithmetic is FP64 for LBM_FP64 and FP32 for the
+ * others.  Shifted forms store f_i - w_i rho0 (rho0 = 1) for the fluid and
+ * g_i - w_i c_ref (c_ref = c_in) for the substrate, an exact change of
+ * variables that keeps the stored values small. */
+typedef enum {
+    LBM_FP32 = 0,
+    LBM_FP32_SHIFTED = 1,
+    LBM_FP16_SHIFTED = 2,
+    LBM_FP64 = 3
+} lbm_storage;
+
+enum { LBM_FLUID = 0, LBM_SOLID = 1, LBM_WALL = 2, LBM_BIOFILM = 3 };
+
+/* Substrate outlet: the paper names Dirichlet input and output (Sec. 2.1.2)
+ * without an output value; the default is a zero-gradient outlet. */
+typedef enum { LBM_OUT_ZERO_GRADIENT = 0, LBM_OUT_DIRICHLET = 1 } lbm_ad_outlet;
+
+/* which solver a call addresses */
+enum { LBM_SOLVER_FLUID = 0, LBM_SOLVER_AD = 1 };
+
+/* fields for lbm_solver_get / lbm_solver_device_ptr */
+typedef enum {
+    LBM_FIELD_U = 0,       /* velocity, host double [dim][N]; 0 on blocked */
+    LBM_FIELD_RHO = 1,     /* density, host double [N]; 0 on blocked */
+    LBM_FIELD_C = 2,       /* concentration, host double [N]; 0 on SOLID/WALL */
+    LBM_FIELD_CLASS = 3,   /* uint8 [N] */
+    LBM_FIELD_LINKS_F = 4, /* fluid link mask, uint16 (2-D) / uint32 (3-D) [N] */
+    LBM_FIELD_LINKS_C = 5, /* substrate link mask, uint8 [N] */
+    LBM_FIELD_F = 6,       /* fluid populations f*, host double [Q][N], unshifted */
+    LBM_FIELD_G = 7,       /* substrate populations g*, host double [Q][N], unshifted */
+    LBM_FIELD_U_DEVICE = 8 /* device velocity buffer the AD solve reads (see device_ptr) */
+} lbm_field;
+
+typedef struct {
+    int32_t nx, ny, nz; /* nz = 1 for 2-D */
+} lbm_grid;
+
+typedef struct {
+    double tau;           /* fluid relaxation time, > 1/2 */
+    double u_in;          /* inlet plug velocity, |u_in| < 0.1 */
+    double D;             /* substrate diffusivity, > 0 */
+    double c_in;          /* inlet concentration (also the shift reference) */
+    double k_sink;        /* first-order consumption on BIOFILM, 0 <= k < 1 */
+    int32_t outlet;       /* lbm_ad_outlet */
+    double c_out;         /* outlet value for LBM_OUT_DIRICHLET */
+    int32_t storage;      /* lbm_storage */
+    int32_t check_every;  /* residual cadence K, even and >= 2 (100 if 0) */
+    int32_t stall_checks; /* stall window in checks (100 if 0; < 0 disables) */
+} lbm_params;
+
+typedef struct {
+    int64_t iters;        /* steps taken by this solve */
+    double residual;      /* residual at the last check (NaN if none) */
+    int64_t checks;       /* residual checks performed */
+    int64_t active_nodes; /* nodes the solver updates */
+    double seconds;       /* wall time of the solve, device-synchronous */
+    double kernel_ms;     /* HIP-event time over the step-kernel launches */
+    int64_t launches;     /* step-kernel launches covered by kernel_ms */
+    double mlups;         /* active-node updates per second / 1e6 */
+    double gbps;          /* algorithmic bytes / kernel_ms: per active-node update,
+                             each population read and written once, the 1-byte
+                             node class, and (substrate) the velocity read */
+    double flux_in;       /* per step, on the final state, FP64 */
+    double flux_out;
+    double sink_total;    /* substrate consumed per step (AD solves) */
+} lbm_info;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_solver lbm_solver;
+
+/* ---------------------------------------------------------------- misc */
+const char *lbm_status_str(int status);
+const char *lbm_version(void);
+
+/* Context on GPU `device`.  hip_stream: a hipStream_t to enqueue on (e.g.
+ * torch's current stream), or NULL for a stream the context creates (at the
+ * default priority).  Errors: EINVAL (bad device), EDEVICE. */
+lbm_status lbm_ctx_create(int device, void *hip_stream, lbm_ctx **out);
+void lbm_ctx_destroy(lbm_ctx *ctx);
+/* Last error text of this context ("" if none); valid until the next call. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+/* hipStream_t the context enqueues on. */
+void *lbm_ctx_stream(lbm_ctx *ctx);
+
+/* ------------------------------------------------ geometry (host only) */
+/* These run on the CPU with integer arithmetic and are bit-exact by
+ * specification; they need no GPU and no context. */
+
+/* Seeded random porous electrode (the paper's "random geometry", Sec. 3):
+ * discs in the region [nx/4, 3nx/4) x [1, ny-1), radius drawn in
+ * [r_min, r_max], placed until the SOLID share of the region reaches
+ * solid_frac.  overlap = 0 keeps discs strictly apart; 1 allows overlap.
+ * Draw order per attempt: centre x, centre y, radius (SplitMix64, integer
+ * in [lo, hi] = lo + next mod (hi - lo + 1)).  cls_out: uint8 [N], written
+ * whole (chassis rows WALL).  achieved (may be NULL): SOLID share reached.
+ * EINVAL on bad sizes or when 10^6 attempts do not reach the target. */
+typedef struct {
+    int32_t r_min, r_max;
+    double solid_frac;
+    int32_t overlap;
+} lbm_disc_params;
+lbm_status lbm_geom_discs(lbm_grid g, const lbm_disc_params *p, uint64_t seed,
+                          uint8_t *cls_out, double *achieved);
+
+/* Seeded fibrous electrode (3-D): infinite cylinders through points of
+ * [nx/4, 3nx/4) x [1, ny-1) x [1, nz-1) with integer directions in
+ * [-4, 4]^3 \ {0} and radius in [r_min, r_max]; voxel p is SOLID iff
+ * |(p - q) x d|^2 <= r^2 |d|^2.  Same stop rule and errors as discs. */
+typedef struct {
+    int32_t r_min, r_max;
+    double solid_frac;
+} lbm_fibre_params;
+lbm_status lbm_geom_fibres(lbm_grid g, const lbm_fibre_params *p, uint64_t seed,
+                           uint8_t *cls_out, double *achieved);
+
+/* One-cell biofilm layer: every FLUID node with a SOLID lattice neighbour
+ * (D2Q9 / D3Q19 directions) becomes BIOFILM, judged on the input mask. */
+lbm_status lbm_biofilm_layer(lbm_grid g, uint8_t *cls_inout);
+
+/* Link mask: bit i of word n is set iff the pull source n - c_i is inside
+ * the grid and blocked for that solver.  which = LBM_SOLVER_FLUID writes
+ * uint16 (2-D) or uint32 (3-D) words; LBM_SOLVER_AD writes uint8 words. */
+lbm_status lbm_links(lbm_grid g, const uint8_t *cls, int which, void *links_out);
+
+/* Link list: the set bits of lbm_links as ascending pairs
+ * (n, i) -> out[2k] = n, out[2k+1] = i, for at most cap pairs.  Returns the
+ * total count (which may exceed cap), or a negative lbm_status. */
+int64_t lbm_link_list(lbm_grid g, const uint8_t *cls, int which, int64_t *out, int64_t cap);
+
+/* 1 iff FLUID nodes of column 0 connect to column nx-1 along fluid-lattice
+ * links (breadth-first search); 0 otherwise; negative on bad arguments. */
+int lbm_percolates(lbm_grid g, const uint8_t *cls);
+
+/* Biofilm growth pick of the coupled loop: among FLUID nodes with
+ * 1 <= x <= nx-2 and a BIOFILM lattice neighbour (ascending n), weight
+ * max(C, 0), pick the first whose running weight exceeds xi * W (W the
+ * total); W = 0 picks candidate floor(xi * count).  C: host double [N].
+ * Returns the node index, or -1 if there is no candidate. */
+int64_t lbm_growth_pick(lbm_grid g, const uint8_t *cls, const double *C, double xi);
+
+/* SplitMix64 stream of `seed`: out[k] = k-th output. */
+void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
+
+/* ---------------------------------------------------- one-shot solves */
+/* Steady fluid flow (Sec. 2.1.1) from rest on the mask cls (host uint8 [N]),
+ * run until the residual max|U(t) - U(t-1)| / |u_in| over FLUID nodes,
+ * evaluated every 100 steps, is <= tol, or max_iter steps.  u_out: host
+ * double [dim][N] (0 on blocked nodes).  info may be NULL. */
+lbm_status lbm_fluid_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
+                            double u_in, double tol, int64_t max_iter, int storage,
+                            double *u_out, lbm_info *info);
+
+/* Steady substrate field (Sec. 2.1.2) in the frozen velocity u (host double
+ * [dim][N]), started from equilibrium at c_in; residual
+ * max|C(t) - C(t-1)| / |c_in| over FLUID and BIOFILM nodes.  c_field:
+ * host double [N] (0 on SOLID/WALL).  info may be NULL. */
+lbm_status lbm_ad_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const double *u,
+                         double D, double c_in, double k_sink, int outlet, double c_out,
+                         double tol, int64_t max_iter, int storage, double *c_field,
+                         lbm_info *info);
+
+/* ----------------------------------------------------- stateful solver */
+/* A solver owns the device state of one domain: both solvers' populations
+ * (A/B pull buffers), the velocity the substrate solve reads, the node
+ * descriptors and the residual/flux scratch.  Validates the mask (EINVAL,
+ * including a medium that does not percolate) and parameters; ENOMEM if
+ * the device buffers do not fit. */
+lbm_status lbm_solver_create(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls,
+                             const lbm_params *p, lbm_solver **out);
+void lbm_solver_destroy(lbm_solver *s);
+
+/* Steady solves.  warm = 0 starts the fluid at rest (rho = 1, u = 0) and
+ * the substrate at equilibrium with c_in in the current velocity; warm = 1
+ * continues from the retained state.  The fluid solve ends by exporting
+ * its velocity to the buffer the substrate solve reads.  info may be NULL. */
+lbm_status lbm_solver_fluid(lbm_solver *s, double tol, int64_t max_iter, int warm,
+                            lbm_info *info);
+lbm_status lbm_solver_ad(lbm_solver *s, double tol, int64_t max_iter, int warm,
+                         lbm_info *info);
+
+/* Exactly nsteps steps of one solver with no residual checks (cold = 1:
+ * initialise first).  kernel_ms (may be NULL): HIP-event time over the
+ * launches.  For the fluid this does not export the velocity; call
+ * lbm_solver_export_u for that. */
+lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold,
+                            double *kernel_ms);
+/* Per-launch timing: nsteps single steps of one solver (state must be
+ * initialised), each bracketed by its own pair of HIP events on the
+ * context's stream; *avg_ms = mean event-to-event time per launch.  The
+ * state advances by nsteps steps. */
+lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *avg_ms);
+/* Recompute the substrate solve's velocity from the stored fluid state. */
+lbm_status lbm_solver_export_u(lbm_solver *s);
+/* Replace the substrate solve's velocity: host double [dim][N]. */
+lbm_status lbm_solver_set_u(lbm_solver *s, const double *u);
+
+/* Copy a field to host memory (layout and type in lbm_field). */
+lbm_status lbm_solver_get(lbm_solver *s, int field, void *dst);
+/* Set populations from host double [Q][N] (unshifted values), field
+ * LBM_FIELD_F or LBM_FIELD_G; blocked nodes are zeroed. */
+lbm_status lbm_solver_put(lbm_solver *s, int field, const double *src);
+/* Device pointer and byte size of LBM_FIELD_U_DEVICE (float [dim][N], or
+ * double for LBM_FP64), valid until the solver is destroyed. */
+lbm_status lbm_solver_device_ptr(lbm_solver *s, int field, void **ptr, size_t *bytes);
+
+/* FP64 fluxes per step on the current states: out[0] fluid inflow,
+ * out[1] fluid outflow, out[2] substrate inflow, out[3] substrate outflow,
+ * out[4] substrate consumed on BIOFILM (deterministic two-pass sums). */
+lbm_status lbm_solver_fluxes(lbm_solver *s, double *out5);
+
+/* Change node classes (e.g. FLUID -> BIOFILM as the biofilm grows,
+ * Sec. 2.3).  idx: host int64 [n] node indices, new_cls: host uint8 [n].
+ * Nodes that become blocked for a solver lose its populations; nodes that
+ * become active start from rest (fluid) or equilibrium at c_in (substrate).
+ * Link masks of the neighbourhood are rebuilt.  EINVAL if a change breaks
+ * the mask rules or percolation (the solver is then left unchanged). */
+lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint8_t *new_cls,
+                                   int64_t n);
+
+/* Checkpoint: the stored populations of both solvers, the velocity buffer
+ * and the class mask, with a header naming grid, storage and parameters.
+ * Restoring it resumes bit-exactly (the kernels are deterministic). */
+lbm_status lbm_solver_state_size(lbm_solver *s, size_t *bytes);
+lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes);
+lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes);
+
+/* Coupled biofilm loop (model loop of Sec. 2 with Sec. 2.3's re-solves;
+ * simplified growth): cold fluid and substrate solves, then n_updates
+ * times pick a new biofilm cell with lbm_growth_pick on the current C and
+ * xi[m] (host double [n_updates] in [0, 1)), mark it BIOFILM, re-converge
+ * fluid then substrate warm to tol (max_iter each), and add that update's
+ * sink_total to *J_accum (FP64).  picked: int64 [n_updates]; J: double
+ * [n_updates + 1] (J[0] before any growth); iters_fluid / iters_ad: int64
+ * [n_updates + 1].  Any output pointer except J_accum may be NULL. */
+lbm_status lbm_coupled_run(lbm_solver *s, int n_updates, const double *xi, double tol,
+                           int64_t max_iter, int64_t *picked, double *J, double *J_accum,
+                           int64_t *iters_fluid, int64_t *iters_ad);
+
+/* ------------------------------------------------------------ diagnostics */
+/* Device-to-device copy of `bytes` bytes by a plain streaming kernel, reps
+ * times, HIP-event timed: *gbps = 2 * bytes / time (read + write),
+ * *ms_per_copy = average duration. */
+lbm_status lbm_copy_bandwidth(lbm_ctx *ctx, size_t bytes, int reps, double *gbps,
+                              double *ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

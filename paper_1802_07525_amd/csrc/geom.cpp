@@ -1,0 +1,475 @@
+// geom.cpp -- host-side integer geometry: seeded electrodes, biofilm layer,
+// link masks, node descriptors, percolation and the biofilm growth pick.
+//
+// The paper's electrode is a random porous geometry (Sec. 3) whose figure is
+// not published; the generators below are seeded stand-ins specified in
+// integer arithmetic so that any two implementations agree byte for byte.
+#include <math.h>
+#include <string.h>
+
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+namespace lbmh {
+
+static Dirs make_dirs(int q, const int (*c)[3])
+{
+    Dirs d;
+    d.q = q;
+    for (int i = 0; i < q; ++i)
+        for (int k = 0; k < 3; ++k)
+            d.c[i][k] = c[i][k];
+    return d;
+}
+
+// Same direction numbering as the kernels (lbm.h documents it).
+static const int C_D2Q9[9][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
+                                 {1, 1, 0},  {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+static const int C_D3Q19[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                   {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                   {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                   {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+const Dirs &fluid_dirs(int nz)
+{
+    static const Dirs d2 = make_dirs(9, C_D2Q9), d3 = make_dirs(19, C_D3Q19);
+    return nz > 1 ? d3 : d2;
+}
+const Dirs &ad_dirs(int nz)
+{
+    static const Dirs d2 = make_dirs(5, C_D2Q9), d3 = make_dirs(7, C_D3Q19);
+    return nz > 1 ? d3 : d2;
+}
+
+bool fluid_blocked(uint8_t k)
+{
+    return k == LBM_SOLID || k == LBM_WALL || k == LBM_BIOFILM;
+}
+bool ad_blocked(uint8_t k)
+{
+    return k == LBM_SOLID || k == LBM_WALL;
+}
+
+// ---- SplitMix64 (Steele, Lea & Flood 2014) ------------------------------
+struct SplitMix64 {
+    uint64_t state;
+    uint64_t next()
+    {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z ^= z >> 30;
+        z *= 0xBF58476D1CE4E5B9ULL;
+        z ^= z >> 27;
+        z *= 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    // integer in [lo, hi] by modulo of one draw
+    int64_t pick(int64_t lo, int64_t hi) { return lo + (int64_t)(next() % (uint64_t)(hi - lo + 1)); }
+};
+
+static inline int64_t idx3(const lbm_grid &g, int64_t x, int64_t y, int64_t z)
+{
+    return x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+}
+
+static void fill_chassis(const lbm_grid &g, uint8_t *cls)
+{
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+            const bool wall = y == 0 || y == g.ny - 1 || (g.nz > 1 && (z == 0 || z == g.nz - 1));
+            memset(cls + idx3(g, 0, y, z), wall ? LBM_WALL : LBM_FLUID, (size_t)g.nx);
+        }
+}
+
+std::string check_mask(const lbm_grid &g, const uint8_t *cls)
+{
+    if (g.nx < 2 || g.ny < 3 || g.nz < 1 || g.nz == 2)
+        return "grid must have nx >= 2, ny >= 3 and nz == 1 or nz >= 3";
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+            const bool chassis = y == 0 || y == g.ny - 1 || (g.nz > 1 && (z == 0 || z == g.nz - 1));
+            for (int x = 0; x < g.nx; ++x) {
+                const uint8_t k = cls[idx3(g, x, y, z)];
+                if (k > LBM_BIOFILM)
+                    return "unknown node class " + std::to_string(k);
+                if (chassis && !(k == LBM_WALL || k == LBM_SOLID))
+                    return "chassis rows/planes must be WALL or SOLID";
+                if ((x == 0 || x == g.nx - 1) && (k == LBM_SOLID || k == LBM_BIOFILM))
+                    return "inlet/outlet columns must hold no SOLID or BIOFILM";
+            }
+        }
+    return "";
+}
+
+} // namespace lbmh
+
+using namespace lbmh;
+
+extern "C" {
+
+void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out)
+{
+    SplitMix64 r{seed};
+    for (int64_t k = 0; k < count; ++k)
+        out[k] = r.next();
+}
+
+lbm_status lbm_geom_discs(lbm_grid g, const lbm_disc_params *p, uint64_t seed, uint8_t *cls,
+                          double *achieved)
+{
+    if (!p || !cls || g.nz != 1 || g.nx < 4 || g.ny < 3 || p->r_min < 0 || p->r_max < p->r_min ||
+        !(p->solid_frac >= 0.0 && p->solid_frac <= 1.0))
+        return LBM_EINVAL;
+    fill_chassis(g, cls);
+    const int64_t xa = g.nx / 4, xb = 3 * (int64_t)g.nx / 4, ya = 1, yb = g.ny - 1;
+    const int64_t region = (xb - xa) * (yb - ya);
+    const int64_t target = (int64_t)ceil(p->solid_frac * (double)region);
+    struct Disc {
+        int64_t x, y, r;
+    };
+    std::vector<Disc> placed;
+    SplitMix64 rng{seed};
+    int64_t solid = 0, attempts = 0;
+    lbm_status st = LBM_OK;
+    while (solid < target) {
+        if (attempts == 1000000) {
+            st = LBM_EINVAL;
+            break;
+        }
+        ++attempts;
+        Disc d;
+        d.x = rng.pick(xa, xb - 1);
+        d.y = rng.pick(ya, yb - 1);
+        d.r = rng.pick(p->r_min, p->r_max);
+        if (!p->overlap) {
+            bool apart = true;
+            for (const Disc &o : placed) {
+                const int64_t dx = d.x - o.x, dy = d.y - o.y, rr = d.r + o.r;
+                if (dx * dx + dy * dy <= rr * rr) {
+                    apart = false;
+                    break;
+                }
+            }
+            if (!apart)
+                continue;
+        }
+        placed.push_back(d);
+        const int64_t y0 = d.y - d.r < ya ? ya : d.y - d.r, y1 = d.y + d.r >= yb ? yb - 1 : d.y + d.r;
+        const int64_t x0 = d.x - d.r < xa ? xa : d.x - d.r, x1 = d.x + d.r >= xb ? xb - 1 : d.x + d.r;
+        for (int64_t y = y0; y <= y1; ++y)
+            for (int64_t x = x0; x <= x1; ++x) {
+                const int64_t dx = x - d.x, dy = y - d.y;
+                if (dx * dx + dy * dy <= d.r * d.r) {
+                    uint8_t &c = cls[idx3(g, x, y, 0)];
+                    if (c != LBM_SOLID) {
+                        c = LBM_SOLID;
+                        ++solid;
+                    }
+                }
+            }
+    }
+    if (achieved)
+        *achieved = (double)solid / (double)region;
+    return st;
+}
+
+lbm_status lbm_geom_fibres(lbm_grid g, const lbm_fibre_params *p, uint64_t seed, uint8_t *cls,
+                           double *achieved)
+{
+    if (!p || !cls || g.nx < 4 || g.ny < 3 || g.nz < 3 || p->r_min < 0 || p->r_max < p->r_min ||
+        !(p->solid_frac >= 0.0 && p->solid_frac <= 1.0))
+        return LBM_EINVAL;
+    fill_chassis(g, cls);
+    const int64_t xa = g.nx / 4, xb = 3 * (int64_t)g.nx / 4;
+    const int64_t region = (xb - xa) * (int64_t)(g.ny - 2) * (g.nz - 2);
+    const int64_t target = (int64_t)ceil(p->solid_frac * (double)region);
+    SplitMix64 rng{seed};
+    int64_t solid = 0, attempts = 0;
+    lbm_status st = LBM_OK;
+    while (solid < target) {
+        if (attempts == 1000000) {
+            st = LBM_EINVAL;
+            break;
+        }
+        ++attempts;
+        const int64_t qx = rng.pick(xa, xb - 1), qy = rng.pick(1, g.ny - 2), qz = rng.pick(1, g.nz - 2);
+        int64_t dx, dy, dz;
+        do {
+            dx = rng.pick(-4, 4);
+            dy = rng.pick(-4, 4);
+            dz = rng.pick(-4, 4);
+        } while (dx == 0 && dy == 0 && dz == 0);
+        const int64_t r = rng.pick(p->r_min, p->r_max);
+        const int64_t lim = r * r * (dx * dx + dy * dy + dz * dz);
+        for (int64_t z = 1; z < g.nz - 1; ++z)
+            for (int64_t y = 1; y < g.ny - 1; ++y) {
+                const int64_t py = y - qy, pz = z - qz;
+                for (int64_t x = xa; x < xb; ++x) {
+                    const int64_t px = x - qx;
+                    const int64_t ax = py * dz - pz * dy, ay = pz * dx - px * dz, az = px * dy - py * dx;
+                    if (ax * ax + ay * ay + az * az <= lim) {
+                        uint8_t &c = cls[idx3(g, x, y, z)];
+                        if (c != LBM_SOLID) {
+                            c = LBM_SOLID;
+                            ++solid;
+                        }
+                    }
+                }
+            }
+    }
+    if (achieved)
+        *achieved = (double)solid / (double)region;
+    return st;
+}
+
+lbm_status lbm_biofilm_layer(lbm_grid g, uint8_t *cls)
+{
+    if (!cls || g.nx < 1 || g.ny < 1 || g.nz < 1)
+        return LBM_EINVAL;
+    const Dirs &D = fluid_dirs(g.nz);
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    std::vector<uint8_t> before(cls, cls + N);
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                const int64_t n = idx3(g, x, y, z);
+                if (before[n] != LBM_FLUID)
+                    continue;
+                for (int i = 1; i < D.q; ++i) {
+                    const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
+                    if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+                        continue;
+                    if (before[idx3(g, sx, sy, sz)] == LBM_SOLID) {
+                        cls[n] = LBM_BIOFILM;
+                        break;
+                    }
+                }
+            }
+    return LBM_OK;
+}
+
+} // extern "C"
+
+namespace lbmh {
+
+template <bool FLUID>
+static void links_impl(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+{
+    const Dirs &D = FLUID ? fluid_dirs(g.nz) : ad_dirs(g.nz);
+    for (int64_t n = lo; n < hi; ++n) {
+        const int x = (int)(n % g.nx);
+        const int y = (int)((n / g.nx) % g.ny);
+        const int z = (int)(n / ((int64_t)g.nx * g.ny));
+        uint32_t bits = 0;
+        for (int i = 1; i < D.q; ++i) {
+            const int sx = x - D.c[i][0], sy = y - D.c[i][1], sz = z - D.c[i][2];
+            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+                continue;
+            const uint8_t k = cls[idx3(g, sx, sy, sz)];
+            if (FLUID ? fluid_blocked(k) : ad_blocked(k))
+                bits |= 1u << i;
+        }
+        out[n - lo] = bits;
+    }
+}
+
+void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+{
+    links_impl<true>(g, cls, out, lo, hi);
+}
+void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+{
+    links_impl<false>(g, cls, out, lo, hi);
+}
+
+void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t lo, int64_t hi)
+{
+    const int qf = fluid_dirs(g.nz).q, qa = ad_dirs(g.nz).q;
+    std::vector<uint32_t> lf((size_t)(hi - lo)), la((size_t)(hi - lo));
+    links_fluid(g, cls, lf.data(), lo, hi);
+    links_ad(g, cls, la.data(), lo, hi);
+    for (int64_t n = lo; n < hi; ++n) {
+        const uint8_t k = cls[n];
+        uint32_t d = 0;
+        if (k == LBM_FLUID)
+            d |= 1u | (lf[n - lo] & ((1u << qf) - 2u));
+        if (k == LBM_FLUID || k == LBM_BIOFILM) {
+            for (int i = 1; i < qa; ++i)
+                if (la[n - lo] & (1u << i))
+                    d |= 1u << lbmk::desc_ad_link_bit(qf, i);
+            d |= 1u << lbmk::desc_ad_active_bit(qf, qa);
+        }
+        if (k == LBM_BIOFILM)
+            d |= 1u << lbmk::desc_biofilm_bit(qf, qa);
+        desc[n - lo] = d;
+    }
+}
+
+bool percolates(const lbm_grid &g, const uint8_t *cls)
+{
+    const Dirs &D = fluid_dirs(g.nz);
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    std::vector<uint8_t> seen((size_t)N, 0);
+    std::deque<int64_t> todo;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+            const int64_t n = idx3(g, 0, y, z);
+            if (cls[n] == LBM_FLUID) {
+                seen[n] = 1;
+                todo.push_back(n);
+            }
+        }
+    while (!todo.empty()) {
+        const int64_t n = todo.front();
+        todo.pop_front();
+        const int x = (int)(n % g.nx);
+        if (x == g.nx - 1)
+            return true;
+        const int y = (int)((n / g.nx) % g.ny);
+        const int z = (int)(n / ((int64_t)g.nx * g.ny));
+        for (int i = 1; i < D.q; ++i) {
+            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
+            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+                continue;
+            const int64_t m = idx3(g, sx, sy, sz);
+            if (!seen[m] && cls[m] == LBM_FLUID) {
+                seen[m] = 1;
+                todo.push_back(m);
+            }
+        }
+    }
+    return false;
+}
+
+int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi)
+{
+    const Dirs &D = fluid_dirs(g.nz);
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    std::vector<int64_t> cand;
+    for (int64_t n = 0; n < N; ++n) {
+        if (cls[n] != LBM_FLUID)
+            continue;
+        const int x = (int)(n % g.nx);
+        if (x < 1 || x > g.nx - 2)
+            continue;
+        const int y = (int)((n / g.nx) % g.ny);
+        const int z = (int)(n / ((int64_t)g.nx * g.ny));
+        for (int i = 1; i < D.q; ++i) {
+            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
+            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+                continue;
+            if (cls[idx3(g, sx, sy, sz)] == LBM_BIOFILM) {
+                cand.push_back(n);
+                break;
+            }
+        }
+    }
+    if (cand.empty())
+        return -1;
+    double W = 0.0;
+    for (int64_t n : cand)
+        W += C[n] > 0.0 ? C[n] : 0.0;
+    if (W == 0.0) {
+        int64_t k = (int64_t)floor(xi * (double)cand.size());
+        if (k >= (int64_t)cand.size())
+            k = (int64_t)cand.size() - 1;
+        return cand[(size_t)k];
+    }
+    const double target = xi * W;
+    double run = 0.0;
+    int64_t last = -1;
+    for (int64_t n : cand) {
+        const double w = C[n] > 0.0 ? C[n] : 0.0;
+        run += w;
+        if (w > 0.0)
+            last = n;
+        if (run > target)
+            return n;
+    }
+    return last;
+}
+
+lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    return st;
+}
+
+lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where)
+{
+    if (e == hipSuccess)
+        return LBM_OK;
+    if (ctx)
+        ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+}
+
+} // namespace lbmh
+
+extern "C" {
+
+lbm_status lbm_links(lbm_grid g, const uint8_t *cls, int which, void *out)
+{
+    if (!cls || !out || g.nx < 1 || g.ny < 1 || g.nz < 1 || (which != 0 && which != 1))
+        return LBM_EINVAL;
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    std::vector<uint32_t> w((size_t)N);
+    if (which == LBM_SOLVER_FLUID)
+        links_fluid(g, cls, w.data(), 0, N);
+    else
+        links_ad(g, cls, w.data(), 0, N);
+    for (int64_t n = 0; n < N; ++n) {
+        if (which == LBM_SOLVER_AD)
+            static_cast<uint8_t *>(out)[n] = (uint8_t)w[n];
+        else if (g.nz > 1)
+            static_cast<uint32_t *>(out)[n] = w[n];
+        else
+            static_cast<uint16_t *>(out)[n] = (uint16_t)w[n];
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_link_list(lbm_grid g, const uint8_t *cls, int which, int64_t *out, int64_t cap)
+{
+    if (!cls || g.nx < 1 || g.ny < 1 || g.nz < 1 || (which != 0 && which != 1) || cap < 0 ||
+        (cap > 0 && !out))
+        return LBM_EINVAL;
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int q = which == 0 ? fluid_dirs(g.nz).q : ad_dirs(g.nz).q;
+    std::vector<uint32_t> w((size_t)N);
+    if (which == 0)
+        links_fluid(g, cls, w.data(), 0, N);
+    else
+        links_ad(g, cls, w.data(), 0, N);
+    int64_t count = 0;
+    for (int64_t n = 0; n < N; ++n)
+        for (int i = 1; i < q; ++i)
+            if (w[n] & (1u << i)) {
+                if (count < cap) {
+                    out[2 * count] = n;
+                    out[2 * count + 1] = i;
+                }
+                ++count;
+            }
+    return count;
+}
+
+int lbm_percolates(lbm_grid g, const uint8_t *cls)
+{
+    if (!cls || g.nx < 1 || g.ny < 1 || g.nz < 1)
+        return LBM_EINVAL;
+    return percolates(g, cls) ? 1 : 0;
+}
+
+int64_t lbm_growth_pick(lbm_grid g, const uint8_t *cls, const double *C, double xi)
+{
+    if (!cls || !C || g.nx < 1 || g.ny < 1 || g.nz < 1)
+        return -1;
+    return growth_pick(g, cls, C, xi);
+}
+
+} // extern "C"

@@ -1,0 +1,961 @@
+// kernels.hip -- gfx950 kernels of the anode-compartment LBM path
+// (Tsompanas et al., arXiv 1802.07525, Sec. 2.1).
+//
+// Design (bandwidth-bound; no MFMA):
+//  * Structure-of-arrays populations h[i][N] in two buffers (A/B) and a pull
+//    scheme: one thread owns one node, gathers its Q incoming populations
+//    (streaming, Eq. 4 left side, with the boundary rules folded in), takes
+//    the moments (Eqs. 9-10 / Eq. 13), relaxes towards the equilibrium
+//    (Eq. 5 / Eq. 12) and writes Q values at its own index: every population
+//    is read once and written once per step, all stores are coalesced.
+//  * A per-node descriptor word carries the node's activity and one bounce-
+//    back bit per direction, so a step reads one small word per node instead
+//    of the neighbours' classes.
+//  * 256-thread blocks of 64 x 4 nodes (four wave64 rows).  Blocks are
+//    renumbered so that each of the eight XCDs receives a contiguous band of
+//    tiles: neighbouring rows meet in the same L2.
+//  * Storage policies: FP64; FP32; FP32 or FP16 holding the shifted value
+//    h = f - w_i * ref.  Arithmetic is FP32 for the FP32/FP16 forms.
+//  * Residual checks are fused into the step kernel: on the step before a
+//    check the kernel stores U (or C); on the check step it takes
+//    max |U(t) - U(t-1)| in FP64, reduces it across the wave with shuffles,
+//    across the block in LDS, and commits one 64-bit atomic max per block.
+//  * Every step kernel starts by reading the control word and returns when a
+//    stop has been decided, so the host may queue steps ahead of decisions.
+#include "lbm_kernels.h"
+
+#include <math.h>
+
+namespace lbmk {
+
+// ---------------------------------------------------------------- lattices
+// D2Q9 of Sec. 2.1 (Eqs. 1-3, weights Eqs. 6-8); c5..c8 = NE, NW, SW, SE so
+// that Eq. 11's pairs 5-7, 2-4, 6-8 are opposites.
+struct D2Q9 {
+    static constexpr int Q = 9, DIM = 2;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr double inv_cs2 = 3.0;
+};
+// Substrate lattice in 2-D: the axis directions of D2Q9.
+struct D2Q5 {
+    static constexpr int Q = 5, DIM = 2;
+    static constexpr int cx[5] = {0, 1, 0, -1, 0};
+    static constexpr int cy[5] = {0, 0, 1, 0, -1};
+    static constexpr int cz[5] = {0, 0, 0, 0, 0};
+    static constexpr int op[5] = {0, 3, 4, 1, 2};
+    static constexpr double w[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    static constexpr double inv_cs2 = 3.0;
+};
+// 3-D fluid lattice: rest, six axes, twelve edge diagonals (opposite pairs).
+struct D3Q19 {
+    static constexpr int Q = 19, DIM = 3;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int op[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                     1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr double inv_cs2 = 3.0;
+};
+// 3-D substrate lattice: rest and six axes, c_s^2 = 1/4.
+struct D3Q7 {
+    static constexpr int Q = 7, DIM = 3;
+    static constexpr int cx[7] = {0, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[7] = {0, 0, 0, 1, -1, 0, 0};
+    static constexpr int cz[7] = {0, 0, 0, 0, 0, 1, -1};
+    static constexpr int op[7] = {0, 2, 1, 4, 3, 6, 5};
+    static constexpr double w[7] = {1.0 / 4, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8};
+    static constexpr double inv_cs2 = 4.0;
+};
+
+// ---------------------------------------------------------- storage forms
+struct SF64 {
+    typedef double T;
+    typedef double C;
+    static constexpr bool shifted = false;
+};
+struct SF32 {
+    typedef float T;
+    typedef float C;
+    static constexpr bool shifted = false;
+};
+struct SF32S {
+    typedef float T;
+    typedef float C;
+    static constexpr bool shifted = true;
+};
+struct SF16S {
+    typedef _Float16 T; // round-to-nearest-even on store
+    typedef float C;
+    static constexpr bool shifted = true;
+};
+
+template <class S>
+__device__ __forceinline__ typename S::C ld(const typename S::T *p)
+{
+    return static_cast<typename S::C>(*p);
+}
+template <class S>
+__device__ __forceinline__ void st(typename S::T *p, typename S::C v)
+{
+    *p = static_cast<typename S::T>(v);
+}
+
+// Contiguous band of tiles per XCD: hardware block b runs on XCD b mod 8.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
+    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+struct NodePos {
+    int x, y, z;
+    bool inb;
+    long long n;
+};
+
+__device__ __forceinline__ NodePos tile_node(const Geo &g)
+{
+    NodePos p;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % g.ntx;
+    const int r1 = tile / g.ntx;
+    const int ty = r1 % g.nty;
+    p.z = r1 / g.nty;
+    p.x = tx * 64 + (threadIdx.x & 63);
+    p.y = ty * 4 + (threadIdx.x >> 6);
+    p.inb = (p.x < g.nx) && (p.y < g.ny);
+    p.n = p.inb ? (p.x + (long long)g.nx * (p.y + (long long)g.ny * p.z)) : 0;
+    return p;
+}
+
+// max over the block of two non-negative FP64 values given as bit patterns
+// (ordering of the bits equals ordering of the values; NaN sorts last),
+// committed with one atomic per block.
+__device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned long long b,
+                                                 unsigned long long *da,
+                                                 unsigned long long *db)
+{
+    __shared__ unsigned long long sa[4], sb[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long oa = __shfl_xor(a, off);
+        unsigned long long ob = __shfl_xor(b, off);
+        a = oa > a ? oa : a;
+        b = ob > b ? ob : b;
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[wv] = a;
+        sb[wv] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long ma = sa[0], mb = sb[0];
+        for (int k = 1; k < 4; ++k) {
+            ma = sa[k] > ma ? sa[k] : ma;
+            mb = sb[k] > mb ? sb[k] : mb;
+        }
+        atomicMax(da, ma);
+        atomicMax(db, mb);
+    }
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v)
+{
+    return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// ------------------------------------------------------------ fluid step
+// Pull rules per direction i (source s = n - c_i), first match wins:
+//   inlet  (x == 0, c_ix = +1):   h_i = h*_opp(n) + 6 w_i u_in
+//   outlet (x == nx-1, c_ix = -1): h_i = -h*_opp(n) + 2 w_i (rho_out - shift)
+//   blocked source (descriptor bit): h_i = h*_opp(n)     (Eq. 11, half-way)
+//   otherwise:                      h_i = h*_i(s)         (streaming)
+template <class L, class S, class DT, int MODE>
+__global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
+{
+    typedef typename S::T T;
+    typedef typename S::C C;
+    if (a.ctrl->stop)
+        return;
+    const NodePos p = tile_node(a.g);
+    const long long N = a.g.N;
+    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
+    const bool act = (d & DT(1)) != 0;
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    C ux = C(0), uy = C(0), uz = C(0);
+    if (act) {
+        const long long n = p.n;
+        C f[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
+            if (i == 0) {
+                f[0] = ld<S>(src + n);
+            } else {
+                const T *so = src + (long long)o * N + n;
+                if (cx == 1 && p.x == 0) {
+                    f[i] = ld<S>(so) + C(6.0 * L::w[i]) * C(a.u_in);
+                } else if (cx == -1 && p.x == a.g.nx - 1) {
+                    f[i] = (S::shifted ? C(0) : C(2.0 * L::w[i])) - ld<S>(so);
+                } else if (d & (DT(1) << i)) {
+                    f[i] = ld<S>(so);
+                } else {
+                    const long long off = cx + (long long)a.g.nx * (cy + (long long)a.g.ny * cz);
+                    f[i] = ld<S>(src + (long long)i * N + n - off);
+                }
+            }
+        }
+        C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            rs += f[i];
+            if (L::cx[i] == 1) jx += f[i];
+            if (L::cx[i] == -1) jx -= f[i];
+            if (L::cy[i] == 1) jy += f[i];
+            if (L::cy[i] == -1) jy -= f[i];
+            if (L::cz[i] == 1) jz += f[i];
+            if (L::cz[i] == -1) jz -= f[i];
+        }
+        const C rho = S::shifted ? C(1) + rs : rs;
+        const C inv = C(1) / rho;
+        ux = jx * inv;
+        uy = jy * inv;
+        uz = jz * inv;
+        const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+        const C om = C(a.omega);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            C cu = C(0);
+            if (L::cx[i] == 1) cu += ux;
+            if (L::cx[i] == -1) cu -= ux;
+            if (L::cy[i] == 1) cu += uy;
+            if (L::cy[i] == -1) cu -= uy;
+            if (L::cz[i] == 1) cu += uz;
+            if (L::cz[i] == -1) cu -= uz;
+            cu *= C(3);
+            // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
+            // minus the shift w_i when stored shifted (rs = rho - shift).
+            const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
+            st<S>(dst + (long long)i * N + n, f[i] + om * (feq - f[i]));
+        }
+    }
+    if constexpr (MODE == MODE_STORE) {
+        if (act) {
+            C *up = static_cast<C *>(a.uprev);
+            up[p.n] = ux;
+            up[N + p.n] = uy;
+            if (L::DIM == 3)
+                up[2 * N + p.n] = uz;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->res_bits = 0ull;
+            a.ctrl->umax_bits = 0ull;
+        }
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        unsigned long long rb = 0ull, ub = 0ull;
+        if (act) {
+            const C *up = static_cast<const C *>(a.uprev);
+            double dm = fabs((double)ux - (double)up[p.n]);
+            double t = fabs((double)uy - (double)up[N + p.n]);
+            dm = (t > dm || t != t) ? t : dm;
+            double um = fmax(fabs((double)ux), fabs((double)uy));
+            if (L::DIM == 3) {
+                t = fabs((double)uz - (double)up[2 * N + p.n]);
+                dm = (t > dm || t != t) ? t : dm;
+                um = fmax(um, fabs((double)uz));
+            }
+            if (ux != ux || uy != uy || uz != uz)
+                dm = um = __longlong_as_double(0x7ff8000000000000ll);
+            rb = dbits(dm * a.inv_uin);
+            ub = dbits(um);
+        }
+        block_max_commit(rb, ub, &a.ctrl->res_bits, &a.ctrl->umax_bits);
+    }
+}
+
+// -------------------------------------------------------- substrate step
+// Pull rules (source s = n - c_i):
+//   inlet  (x == 0, c_ix = +1):    h_i = -h*_opp(n) + 2 w_i (c_in - ref)
+//   outlet (x == nx-1, c_ix = -1): zero gradient h_i = h*_i(n), or
+//                                  Dirichlet h_i = -h*_opp(n) + 2 w_i (c_out - ref)
+//   blocked source (SOLID/WALL):   h_i = h*_opp(n)       (zero flux)
+//   otherwise:                     h_i = h*_i(s)
+// Collision (Eq. 12) with the linear equilibrium w_i C (1 + c_i.u / c_s^2)
+// and the biofilm consumption - w_i k C.
+template <class L, int QF, class S, class DT, int MODE>
+__global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
+{
+    typedef typename S::T T;
+    typedef typename S::C C;
+    constexpr int ACT = QF - 1 + L::Q;
+    constexpr int BIO = ACT + 1;
+    constexpr int LNK = QF - 1;
+    if (a.ctrl->stop)
+        return;
+    const NodePos p = tile_node(a.g);
+    const long long N = a.g.N;
+    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
+    const bool act = ((d >> ACT) & DT(1)) != 0;
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    C cfull = C(0);
+    if (act) {
+        const long long n = p.n;
+        C g[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
+            if (i == 0) {
+                g[0] = ld<S>(src + n);
+            } else {
+                const T *so = src + (long long)o * N + n;
+                if (cx == 1 && p.x == 0) {
+                    g[i] = C(2.0 * L::w[i] * a.cin_s) - ld<S>(so);
+                } else if (cx == -1 && p.x == a.g.nx - 1) {
+                    g[i] = a.outlet ? C(2.0 * L::w[i] * a.cout_s) - ld<S>(so)
+                                    : ld<S>(src + (long long)i * N + n);
+                } else if ((d >> (LNK + i)) & DT(1)) {
+                    g[i] = ld<S>(so);
+                } else {
+                    const long long off = cx + (long long)a.g.nx * (cy + (long long)a.g.ny * cz);
+                    g[i] = ld<S>(src + (long long)i * N + n - off);
+                }
+            }
+        }
+        C cs = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            cs += g[i];
+        cfull = S::shifted ? C(a.c_ref) + cs : cs;
+        const C *U = static_cast<const C *>(a.u);
+        const C ux = U[n], uy = U[N + n];
+        const C uz = (L::DIM == 3) ? U[2 * N + n] : C(0);
+        const C om = C(a.omega);
+        const C kc = ((d >> BIO) & DT(1)) ? C(a.k_sink) * cfull : C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            C cu = C(0);
+            if (L::cx[i] == 1) cu += ux;
+            if (L::cx[i] == -1) cu -= ux;
+            if (L::cy[i] == 1) cu += uy;
+            if (L::cy[i] == -1) cu -= uy;
+            if (L::cz[i] == 1) cu += uz;
+            if (L::cz[i] == -1) cu -= uz;
+            const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
+            st<S>(dst + (long long)i * N + n, g[i] + om * (geq - g[i]) - C(L::w[i]) * kc);
+        }
+    }
+    if constexpr (MODE == MODE_STORE) {
+        if (act)
+            static_cast<C *>(a.cprev)[p.n] = cfull;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->res_bits = 0ull;
+            a.ctrl->umax_bits = 0ull;
+        }
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        unsigned long long rb = 0ull;
+        if (act) {
+            double dv = fabs((double)cfull - (double)static_cast<const C *>(a.cprev)[p.n]);
+            if (cfull != cfull)
+                dv = __longlong_as_double(0x7ff8000000000000ll);
+            rb = dbits(dv * a.inv_cin);
+        }
+        block_max_commit(rb, 0ull, &a.ctrl->res_bits, &a.ctrl->umax_bits);
+    }
+}
+
+// ------------------------------------------------------- init / export
+template <class L, class S, class DT>
+__global__ void __launch_bounds__(256) k_fluid_init(typename S::T *f, const DT *desc, long long N)
+{
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const bool act = (desc[n] & DT(1)) != 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        st<S>(f + (long long)i * N + n,
+              act ? (S::shifted ? typename S::C(0) : typename S::C(L::w[i])) : typename S::C(0));
+}
+
+template <class L, int QF, class S, class DT>
+__global__ void __launch_bounds__(256) k_ad_init(typename S::T *gp, const DT *desc,
+                                                  const typename S::C *U, long long N,
+                                                  double c_init, double c_ref)
+{
+    typedef typename S::C C;
+    constexpr int ACT = QF - 1 + L::Q;
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const bool act = ((desc[n] >> ACT) & DT(1)) != 0;
+    const C ux = act ? U[n] : C(0), uy = act ? U[N + n] : C(0);
+    const C uz = (act && L::DIM == 3) ? U[2 * N + n] : C(0);
+    const C cs = S::shifted ? C(c_init - c_ref) : C(c_init);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        C cu = C(0);
+        if (L::cx[i] == 1) cu += ux;
+        if (L::cx[i] == -1) cu -= ux;
+        if (L::cy[i] == 1) cu += uy;
+        if (L::cy[i] == -1) cu -= uy;
+        if (L::cz[i] == 1) cu += uz;
+        if (L::cz[i] == -1) cu -= uz;
+        const C v = C(L::w[i]) * (cs + C(c_init) * (C(L::inv_cs2) * cu));
+        st<S>(gp + (long long)i * N + n, act ? v : C(0));
+    }
+}
+
+template <class L, class S, class DT, class O>
+__global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, const DT *desc,
+                                                       long long N, O *U, O *RHO)
+{
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const bool act = (desc[n] & DT(1)) != 0;
+    O rs = O(0), jx = O(0), jy = O(0), jz = O(0);
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const O v = static_cast<O>(f[(long long)i * N + n]);
+            rs += v;
+            if (L::cx[i] == 1) jx += v;
+            if (L::cx[i] == -1) jx -= v;
+            if (L::cy[i] == 1) jy += v;
+            if (L::cy[i] == -1) jy -= v;
+            if (L::cz[i] == 1) jz += v;
+            if (L::cz[i] == -1) jz -= v;
+        }
+    }
+    const O rho = act ? (S::shifted ? O(1) + rs : rs) : O(0);
+    const O inv = act ? O(1) / rho : O(0);
+    if (U) {
+        U[n] = jx * inv;
+        U[N + n] = jy * inv;
+        if (L::DIM == 3)
+            U[2 * N + n] = jz * inv;
+    }
+    if (RHO)
+        RHO[n] = rho;
+}
+
+template <class L, int QF, class S, class DT>
+__global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, const DT *desc,
+                                                    long long N, double c_ref, double k_sink,
+                                                    double *Cout)
+{
+    constexpr int ACT = QF - 1 + L::Q;
+    constexpr int BIO = ACT + 1;
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const DT d = desc[n];
+    if (!((d >> ACT) & DT(1))) {
+        Cout[n] = 0.0;
+        return;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        s += static_cast<double>(gp[(long long)i * N + n]);
+    if (S::shifted)
+        s += c_ref;
+    const double k = ((d >> BIO) & DT(1)) ? k_sink : 0.0;
+    Cout[n] = s / (1.0 - k);
+}
+
+template <class L, class S, class DT>
+__global__ void __launch_bounds__(256) k_pops_export(const typename S::T *h, const DT *desc,
+                                                      long long N, int act_bit, double ref,
+                                                      double *out)
+{
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const bool act = ((desc[n] >> act_bit) & DT(1)) != 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double v = static_cast<double>(h[(long long)i * N + n]);
+        out[(long long)i * N + n] = act ? (S::shifted ? v + L::w[i] * ref : v) : 0.0;
+    }
+}
+
+template <class L, class S, class DT>
+__global__ void __launch_bounds__(256) k_pops_import(typename S::T *h, const DT *desc, long long N,
+                                                      int act_bit, double ref, const double *in)
+{
+    const long long n = blockIdx.x * 256ll + threadIdx.x;
+    if (n >= N)
+        return;
+    const bool act = ((desc[n] >> act_bit) & DT(1)) != 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double v = in[(long long)i * N + n];
+        const double s = S::shifted ? v - L::w[i] * ref : v;
+        h[(long long)i * N + n] = static_cast<typename S::T>(act ? s : 0.0);
+    }
+}
+
+template <class S>
+__global__ void __launch_bounds__(256) k_pops_set_nodes(typename S::T *h, long long N, int Q,
+                                                        const long long *idx, int count,
+                                                        const double *vals)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= count)
+        return;
+    const long long n = idx[k];
+    for (int i = 0; i < Q; ++i)
+        h[(long long)i * N + n] = static_cast<typename S::T>(vals[i]);
+}
+
+// ---------------------------------------------------------------- fluxes
+// Per node, in FP64 on the unshifted values:
+//   fluid in   = sum over inlet links (incoming - outgoing)
+//   fluid out  = sum over outlet links (outgoing - incoming)
+//   sub in/out = same for the substrate links, sink = k * sum g* / (1 - k)
+// Each block reduces a fixed node range in a fixed tree order; the second
+// pass sums the block partials in index order: the result is reproducible.
+template <class LF, class LA, class S, class DT>
+__global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
+                                                        const typename S::T *gp, const DT *desc,
+                                                        Geo g, double u_in, double c_in,
+                                                        double c_ref, double k_sink, int outlet,
+                                                        double c_out, double *part)
+{
+    constexpr int ACT = LF::Q - 1 + LA::Q;
+    constexpr int BIO = ACT + 1;
+    const long long N = g.N;
+    const long long per = (N + gridDim.x - 1) / gridDim.x;
+    const long long lo = blockIdx.x * per;
+    const long long hi = lo + per < N ? lo + per : N;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double fs = S::shifted ? 1.0 : 0.0;
+    const double gs = S::shifted ? c_ref : 0.0;
+    for (long long n = lo + threadIdx.x; n < hi; n += 256) {
+        const int x = (int)(n % g.nx);
+        if (x != 0 && x != g.nx - 1) {
+            if (!gp)
+                continue;
+        }
+        const DT d = desc[n];
+        if (f && (d & DT(1)) && (x == 0 || x == g.nx - 1)) {
+#pragma unroll
+            for (int i = 1; i < LF::Q; ++i) {
+                const int o = LF::op[i];
+                const double fo = static_cast<double>(f[(long long)o * N + n]) + fs * LF::w[o];
+                if (x == 0 && LF::cx[i] == 1) {
+                    const double incoming = fo + 6.0 * LF::w[i] * u_in;
+                    acc[0] += incoming - fo;
+                }
+                if (x == g.nx - 1 && LF::cx[i] == -1) {
+                    const double incoming = -fo + 2.0 * LF::w[i];
+                    acc[1] += fo - incoming;
+                }
+            }
+        }
+        if (gp && ((d >> ACT) & DT(1))) {
+            if (x == 0 || x == g.nx - 1) {
+#pragma unroll
+                for (int i = 1; i < LA::Q; ++i) {
+                    const int o = LA::op[i];
+                    const double go = static_cast<double>(gp[(long long)o * N + n]) + gs * LA::w[o];
+                    if (x == 0 && LA::cx[i] == 1) {
+                        const double incoming = -go + 2.0 * LA::w[i] * c_in;
+                        acc[2] += incoming - go;
+                    }
+                    if (x == g.nx - 1 && LA::cx[i] == -1) {
+                        const double gi = static_cast<double>(gp[(long long)i * N + n]) + gs * LA::w[i];
+                        const double incoming = outlet ? -go + 2.0 * LA::w[i] * c_out : gi;
+                        acc[3] += go - incoming;
+                    }
+                }
+            }
+            if ((d >> BIO) & DT(1)) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < LA::Q; ++i)
+                    s += static_cast<double>(gp[(long long)i * N + n]) + gs * LA::w[i];
+                acc[4] += k_sink * s / (1.0 - k_sink);
+            }
+        }
+    }
+    __shared__ double red[5][256];
+    for (int k = 0; k < 5; ++k)
+        red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 5; ++k)
+                red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k)
+            part[k * gridDim.x + blockIdx.x] = red[k][0];
+}
+
+__global__ void k_flux_final(const double *part, int nb, double *out5)
+{
+    const int k = threadIdx.x;
+    if (k < 5) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b)
+            s += part[k * nb + b];
+        out5[k] = s;
+    }
+}
+
+// ------------------------------------------------------------- control
+__global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->res_bits = 0ull;
+        c->umax_bits = 0ull;
+        c->tol = tol;
+        c->best = __longlong_as_double(0x7ff0000000000000ll); // +inf
+        c->r_last = __longlong_as_double(0x7ff8000000000000ll);
+        c->t = 0;
+        c->t_stop = -1;
+        c->checks = 0;
+        c->stop = STOP_RUN;
+        c->since_best = 0;
+        c->window = window;
+        c->is_fluid = is_fluid;
+        c->K = K;
+    }
+}
+
+// After a check step: OK at r <= tol; DIVERGED on NaN/Inf or |u| > 0.3
+// (fluid); STALLED after `window` checks without a new minimum.
+__global__ void k_decide(Ctrl *c)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || c->stop != STOP_RUN)
+        return;
+    c->t += c->K;
+    c->checks += 1;
+    const double r = __longlong_as_double((long long)c->res_bits);
+    const double um = __longlong_as_double((long long)c->umax_bits);
+    c->r_last = r;
+    int stop = STOP_RUN;
+    if (r != r || isinf(r) || um != um || (c->is_fluid && um > 0.3)) {
+        stop = STOP_DIVERGED;
+    } else if (r <= c->tol) {
+        stop = STOP_OK;
+    } else if (r < c->best) {
+        c->best = r;
+        c->since_best = 0;
+    } else {
+        c->since_best += 1;
+        if (c->window > 0 && c->since_best >= c->window)
+            stop = STOP_STALLED;
+    }
+    if (stop != STOP_RUN) {
+        c->t_stop = c->t;
+        c->stop = stop;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src,
+                                              float4 *__restrict__ dst, long long n4)
+{
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n4; i += (long long)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ dispatch
+Geo make_geo(int nx, int ny, int nz)
+{
+    Geo g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.ntx = (nx + 63) / 64;
+    g.nty = (ny + 3) / 4;
+    g.ntiles = g.ntx * g.nty * nz;
+    g.N = (long long)nx * ny * nz;
+    return g;
+}
+
+size_t storage_bytes(int s)
+{
+    return s == ST_F64 ? 8 : (s == ST_F16S ? 2 : 4);
+}
+size_t compute_bytes(int s)
+{
+    return s == ST_F64 ? 8 : 4;
+}
+bool storage_shifted(int s)
+{
+    return s == ST_F32S || s == ST_F16S;
+}
+
+static inline dim3 flat_grid(long long N)
+{
+    return dim3((unsigned)((N + 255) / 256));
+}
+
+template <class F>
+static hipError_t by_storage(int storage, F &&fn)
+{
+    switch (storage) {
+    case ST_F32:
+        return fn(SF32{});
+    case ST_F32S:
+        return fn(SF32S{});
+    case ST_F16S:
+        return fn(SF16S{});
+    case ST_F64:
+        return fn(SF64{});
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class LF, class LA, class DT, class F>
+static hipError_t with_lattices(F &&fn)
+{
+    return fn(LF{}, LA{}, DT{});
+}
+
+template <class F>
+static hipError_t by_dim(int dim, F &&fn)
+{
+    if (dim == 2)
+        return fn(D2Q9{}, D2Q5{}, uint16_t{});
+    if (dim == 3)
+        return fn(D3Q19{}, D3Q7{}, uint32_t{});
+    return hipErrorInvalidValue;
+}
+
+hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            dim3 grid(a.g.ntiles), block(256);
+            if (mode == MODE_STORE)
+                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_STORE>), grid, block, 0, st, a);
+            else if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_CHECK>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_PLAIN>), grid, block, 0, st, a);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            dim3 grid(a.g.ntiles), block(256);
+            if (mode == MODE_STORE)
+                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_STORE>), grid, block, 0, st, a);
+            else if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_CHECK>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_PLAIN>), grid, block, 0, st, a);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,
+                      hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            hipLaunchKernelGGL((k_fluid_init<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st,
+                               static_cast<typename S::T *>(f), static_cast<const DT *>(desc), g.N);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void *u,
+                   const Geo &g, double c_init, double c_ref, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            hipLaunchKernelGGL((k_ad_init<LA, LF::Q, S, DT>), flat_grid(g.N), dim3(256), 0, st,
+                               static_cast<typename S::T *>(gp), static_cast<const DT *>(desc),
+                               static_cast<const typename S::C *>(u), g.N, c_init,
+                               S::shifted ? c_ref : 0.0);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
+                        void *U, void *RHO, int out_double, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            typedef typename S::C C;
+            if (out_double)
+                hipLaunchKernelGGL((k_fluid_export<LF, S, DT, double>), flat_grid(g.N), dim3(256), 0,
+                                   st, static_cast<const typename S::T *>(f),
+                                   static_cast<const DT *>(desc), g.N, static_cast<double *>(U),
+                                   static_cast<double *>(RHO));
+            else
+                hipLaunchKernelGGL((k_fluid_export<LF, S, DT, C>), flat_grid(g.N), dim3(256), 0, st,
+                                   static_cast<const typename S::T *>(f),
+                                   static_cast<const DT *>(desc), g.N, static_cast<C *>(U),
+                                   static_cast<C *>(RHO));
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
+                     double c_ref, double k_sink, double *C, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT>), flat_grid(g.N), dim3(256), 0, st,
+                               static_cast<const typename S::T *>(gp),
+                               static_cast<const DT *>(desc), g.N, c_ref, k_sink, C);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
+                       const Geo &g, double c_ref, double *out, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            const typename S::T *hp = static_cast<const typename S::T *>(h);
+            const DT *dp = static_cast<const DT *>(desc);
+            if (which == 0)
+                hipLaunchKernelGGL((k_pops_export<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                   dp, g.N, 0, 1.0, out);
+            else
+                hipLaunchKernelGGL((k_pops_export<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                   dp, g.N, LF::Q - 1 + LA::Q, c_ref, out);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t pops_import(int which, int dim, int storage, void *h, const void *desc,
+                       const Geo &g, double c_ref, const double *in, hipStream_t st)
+{
+    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            typename S::T *hp = static_cast<typename S::T *>(h);
+            const DT *dp = static_cast<const DT *>(desc);
+            if (which == 0)
+                hipLaunchKernelGGL((k_pops_import<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                   dp, g.N, 0, 1.0, in);
+            else
+                hipLaunchKernelGGL((k_pops_import<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                   dp, g.N, LF::Q - 1 + LA::Q, c_ref, in);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g,
+                          const long long *idx, int count, const double *vals_q, hipStream_t st)
+{
+    if (count <= 0)
+        return hipSuccess;
+    const int Q = which == 0 ? (dim == 3 ? 19 : 9) : (dim == 3 ? 7 : 5);
+    return by_storage(storage, [&](auto s) {
+        typedef decltype(s) S;
+        hipLaunchKernelGGL((k_pops_set_nodes<S>), dim3((count + 255) / 256), dim3(256), 0, st,
+                           static_cast<typename S::T *>(h), g.N, Q, idx, count, vals_q);
+        return hipGetLastError();
+    });
+}
+
+hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
+                  const Geo &g, double u_in, double c_in, double c_ref, double k_sink, int outlet,
+                  double c_out, double *partials, double *out5, hipStream_t st)
+{
+    hipError_t e = by_dim(dim, [&](auto lf, auto la, auto dt) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typedef decltype(dt) DT;
+            hipLaunchKernelGGL((k_flux_partials<LF, LA, S, DT>), dim3(FLUX_BLOCKS), dim3(256), 0, st,
+                               static_cast<const typename S::T *>(f),
+                               static_cast<const typename S::T *>(gp), static_cast<const DT *>(desc),
+                               g, u_in, c_in, c_ref, k_sink, outlet, c_out, partials);
+            return hipGetLastError();
+        });
+    });
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_flux_final, dim3(1), dim3(64), 0, st, partials, (int)FLUX_BLOCKS, out5);
+    return hipGetLastError();
+}
+
+hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, tol, window, is_fluid, K);
+    return hipGetLastError();
+}
+
+hipError_t decide(Ctrl *c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    const long long n4 = (long long)(bytes / 16);
+    long long blocks = (n4 + 255) / 256;
+    if (blocks > 256 * 64)
+        blocks = 256 * 64;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const float4 *>(src), static_cast<float4 *>(dst), n4);
+    return hipGetLastError();
+}
+
+} // namespace lbmk

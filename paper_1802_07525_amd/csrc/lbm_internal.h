@@ -1,0 +1,80 @@
+// lbm_internal.h -- internal types of the library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.h"
+
+struct lbm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+};
+
+namespace lbmh {
+
+// ---- host geometry (geom.cpp) -------------------------------------------
+struct Dirs {
+    int q;
+    int c[19][3];
+};
+// fluid (D2Q9 / D3Q19) or substrate (D2Q5 / D3Q7) directions of a grid
+const Dirs &fluid_dirs(int nz);
+const Dirs &ad_dirs(int nz);
+
+bool fluid_blocked(uint8_t k);
+bool ad_blocked(uint8_t k);
+
+// mask rules: classes <= 3, chassis rows/planes not active, inlet/outlet
+// columns free of SOLID/BIOFILM.  Returns empty string if fine.
+std::string check_mask(const lbm_grid &g, const uint8_t *cls);
+bool percolates(const lbm_grid &g, const uint8_t *cls);
+void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
+void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
+// descriptor words (lbm_kernels.h layout) for nodes [lo, hi)
+void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t lo, int64_t hi);
+int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi);
+
+// ---- error helpers -------------------------------------------------------
+lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
+lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);
+
+} // namespace lbmh
+
+struct lbm_solver {
+    lbm_ctx *ctx = nullptr;
+    lbm_grid grid{};
+    lbm_params p{};
+    int dim = 2, qf = 9, qa = 5;
+    lbmk::Geo geo{};
+    std::vector<uint8_t> cls;
+    size_t desc_bytes = 2;       // per node
+    int64_t n_fluid = 0, n_ad = 0;
+    double c_ref = 0.0;          // substrate shift reference (0 if unshifted)
+
+    void *d_desc = nullptr;
+    void *d_f[2] = {nullptr, nullptr};
+    void *d_g[2] = {nullptr, nullptr};
+    void *d_u = nullptr;         // compute type [dim][N]
+    void *d_uprev = nullptr;     // compute type [dim][N]
+    void *d_cprev = nullptr;     // compute type [N]
+    lbmk::Ctrl *d_ctrl = nullptr; // [2]: fluid, substrate
+    double *d_partials = nullptr;
+    double *d_out5 = nullptr;
+    double *d_stage = nullptr;   // lazily sized double staging buffer
+    size_t stage_bytes = 0;
+    long long *d_idx = nullptr;  // small scratch for cell updates
+    double *d_vals = nullptr;
+    int fcur = 0, gcur = 0;
+    bool fluid_ready = false, ad_ready = false;
+
+    lbmk::Ctrl *h_ctrl = nullptr; // pinned ring of control snapshots
+    hipEvent_t ev_ring[8] = {};
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+};

@@ -1,0 +1,134 @@
+// lbm_kernels.h -- host-side launch interface of the gfx950 kernels.
+//
+// The kernels themselves live in kernels.hip; this header is what the
+// solver runtime (solver.cpp, api.cpp) calls.  All launches are
+// asynchronous on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbmk {
+
+enum { ST_F32 = 0, ST_F32S = 1, ST_F16S = 2, ST_F64 = 3 };
+enum { MODE_PLAIN = 0, MODE_STORE = 1, MODE_CHECK = 2 };
+enum { STOP_RUN = 0, STOP_OK = 1, STOP_STALLED = 2, STOP_DIVERGED = 3 };
+
+// Per-solve control block in device memory.  The step kernels read `stop`
+// first and return at once when it is set, so the host may enqueue steps
+// ahead of the residual decision without changing the state past the stop.
+struct Ctrl {
+    unsigned long long res_bits;  // max residual of the current check (FP64 bits)
+    unsigned long long umax_bits; // max |u| of the current check (FP64 bits)
+    double tol;
+    double best;                  // smallest residual so far
+    double r_last;                // residual of the latest check
+    long long t;                  // steps covered by completed checks
+    long long t_stop;             // step at which stop was decided
+    long long checks;
+    int stop;                     // STOP_*
+    int since_best;               // checks since the last new minimum
+    int window;                   // stall window in checks (<= 0: off)
+    int is_fluid;                 // apply the |u| > 0.3 divergence test
+    int K;                        // steps per check
+    int pad;
+};
+
+// Domain geometry as the kernels see it.  Tiles are 64 x 4 nodes (one
+// 256-thread block, four wave64 rows) of one z-plane.
+struct Geo {
+    int nx, ny, nz;
+    int ntx, nty;    // tiles along x and y
+    int ntiles;      // ntx * nty * nz
+    long long N;     // nx * ny * nz
+};
+
+Geo make_geo(int nx, int ny, int nz);
+
+// Descriptor word per node (uint16 in 2-D, uint32 in 3-D):
+//   bit 0                 node is FLUID (fluid solver updates it)
+//   bits 1..QF-1          fluid pull source n - c_i is blocked (bounce back)
+//   bits QF..QF+QA-2      substrate pull source n - c_i is blocked (i = 1..QA-1)
+//   bit  QF+QA-1          node is FLUID or BIOFILM (substrate solver updates it)
+//   bit  QF+QA            node is BIOFILM (consumption)
+inline int desc_ad_link_bit(int qf, int i) { return qf - 1 + i; }
+inline int desc_ad_active_bit(int qf, int qa) { return qf - 1 + qa; }
+inline int desc_biofilm_bit(int qf, int qa) { return qf + qa; }
+
+struct FluidArgs {
+    const void *src;
+    void *dst;
+    const void *desc;
+    void *uprev;    // compute-type [dim][N] velocity kept for the residual
+    Ctrl *ctrl;
+    Geo g;
+    double omega;   // 1 / tau
+    double u_in;
+    double inv_uin; // 1 / |u_in|
+};
+
+struct AdArgs {
+    const void *src;
+    void *dst;
+    const void *desc;
+    const void *u;  // compute-type [dim][N] frozen velocity
+    void *cprev;    // compute-type [N] concentration kept for the residual
+    Ctrl *ctrl;
+    Geo g;
+    double omega;   // 1 / tau_D
+    double cin_s;   // c_in - shift reference (0 reference when unshifted)
+    double cout_s;  // c_out - shift reference
+    double c_ref;   // shift reference (0 when unshifted)
+    double k_sink;
+    double inv_cin; // 1 / |c_in|
+    int outlet;     // 0 zero-gradient, 1 Dirichlet
+};
+
+size_t storage_bytes(int storage);  // bytes per stored population
+size_t compute_bytes(int storage);  // bytes per compute-type value
+bool storage_shifted(int storage);
+
+hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStream_t st);
+hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t st);
+
+// f = rest state on FLUID nodes, 0 elsewhere.
+hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,
+                      hipStream_t st);
+// g = equilibrium at c_init in velocity u on active nodes, 0 elsewhere.
+hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void *u,
+                   const Geo &g, double c_init, double c_ref, hipStream_t st);
+
+// Velocity (and density) of a stored fluid state.  out_double selects the
+// output type (double, else the compute type); RHO may be null.
+hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
+                        void *U, void *RHO, int out_double, hipStream_t st);
+// Concentration of a stored substrate state, as double.
+hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
+                     double c_ref, double k_sink, double *C, hipStream_t st);
+
+// Stored populations <-> unshifted double [Q][N] (0 on inactive nodes).
+hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
+                       const Geo &g, double c_ref, double *out, hipStream_t st);
+hipError_t pops_import(int which, int dim, int storage, void *h, const void *desc,
+                       const Geo &g, double c_ref, const double *in, hipStream_t st);
+
+// Set the populations of the listed nodes to vals[i] (stored form).
+hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g,
+                          const long long *idx, int count, const double *vals_q,
+                          hipStream_t st);
+
+// Deterministic FP64 fluxes: out[0..4] = fluid in, fluid out, substrate in,
+// substrate out, substrate consumed.  f or gp may be null (then 0).
+// partials: device double [5 * FLUX_BLOCKS].
+enum { FLUX_BLOCKS = 512 };
+hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
+                  const Geo &g, double u_in, double c_in, double c_ref, double k_sink,
+                  int outlet, double c_out, double *partials, double *out5, hipStream_t st);
+
+hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, hipStream_t st);
+hipError_t decide(Ctrl *c, hipStream_t st);
+
+hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st);
+
+} // namespace lbmk

@@ -1,0 +1,904 @@
+// solver.cpp -- solver objects: device state, steady-state loops, fields,
+// cell updates, checkpoint/resume and the coupled biofilm loop.
+//
+// Steady loop.  The paper runs each LBM "until an equilibrium is reached"
+// (Sec. 3).  Here a solve enqueues chunks of K steps; the step before each
+// check stores U (or C), the check step reduces the residual on the device,
+// and a one-thread kernel applies the stop rule and raises a stop flag that
+// every later step kernel honours by returning at once.  The host copies the
+// control block into pinned memory after each chunk and keeps at most three
+// chunks in flight, so the GPU never waits on the host for a decision and the
+// state at the stop is exactly the state of the deciding check.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbmh;
+
+#define HIPCHK(expr, where)                                                                      \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return hip_err(s->ctx, e_, where);                                                   \
+    } while (0)
+
+namespace {
+
+const int RING = 8;
+const int MAX_INFLIGHT = 3;
+
+inline size_t sbytes(const lbm_solver *s) { return lbmk::storage_bytes(s->p.storage); }
+inline size_t cbytes(const lbm_solver *s) { return lbmk::compute_bytes(s->p.storage); }
+inline bool shifted(const lbm_solver *s) { return lbmk::storage_shifted(s->p.storage); }
+
+lbm_status validate_params(lbm_ctx *ctx, const lbm_params &p)
+{
+    if (!(p.tau > 0.5) || !isfinite(p.tau))
+        return set_err(ctx, LBM_EINVAL, "tau must be > 1/2");
+    if (!(fabs(p.u_in) < 0.1) || p.u_in == 0.0)
+        return set_err(ctx, LBM_EINVAL, "u_in must be nonzero with |u_in| < 0.1");
+    if (!(p.D > 0.0) || !isfinite(p.D))
+        return set_err(ctx, LBM_EINVAL, "D must be > 0");
+    if (!(p.c_in != 0.0) || !isfinite(p.c_in))
+        return set_err(ctx, LBM_EINVAL, "c_in must be finite and nonzero");
+    if (!(p.k_sink >= 0.0 && p.k_sink < 1.0))
+        return set_err(ctx, LBM_EINVAL, "k_sink must be in [0, 1)");
+    if (p.outlet != LBM_OUT_ZERO_GRADIENT && p.outlet != LBM_OUT_DIRICHLET)
+        return set_err(ctx, LBM_EINVAL, "unknown outlet mode");
+    if (!isfinite(p.c_out))
+        return set_err(ctx, LBM_EINVAL, "c_out must be finite");
+    if (p.storage < LBM_FP32 || p.storage > LBM_FP64)
+        return set_err(ctx, LBM_EINVAL, "unknown storage");
+    if (p.check_every < 2 || (p.check_every & 1))
+        return set_err(ctx, LBM_EINVAL, "check_every must be even and >= 2");
+    return LBM_OK;
+}
+
+lbm_status upload_desc(lbm_solver *s)
+{
+    const int64_t N = s->geo.N;
+    std::vector<uint32_t> d((size_t)N);
+    build_desc(s->grid, s->cls.data(), d.data(), 0, N);
+    int64_t nf = 0, na = 0;
+    const int aab = lbmk::desc_ad_active_bit(s->qf, s->qa);
+    for (int64_t n = 0; n < N; ++n) {
+        nf += d[n] & 1u;
+        na += (d[n] >> aab) & 1u;
+    }
+    s->n_fluid = nf;
+    s->n_ad = na;
+    if (s->desc_bytes == 2) {
+        std::vector<uint16_t> p16((size_t)N);
+        for (int64_t n = 0; n < N; ++n)
+            p16[n] = (uint16_t)d[n];
+        HIPCHK(hipMemcpy(s->d_desc, p16.data(), (size_t)N * 2, hipMemcpyHostToDevice), "desc upload");
+    } else {
+        HIPCHK(hipMemcpy(s->d_desc, d.data(), (size_t)N * 4, hipMemcpyHostToDevice), "desc upload");
+    }
+    return LBM_OK;
+}
+
+lbm_status dev_alloc(lbm_solver *s, void **p, size_t bytes, const char *what)
+{
+    if (*p)
+        return LBM_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_err(s->ctx, LBM_ENOMEM, std::string("device allocation failed: ") + what);
+    }
+    HIPCHK(hipMemsetAsync(*p, 0, bytes, s->ctx->stream), what);
+    return LBM_OK;
+}
+
+lbm_status ensure_fluid(lbm_solver *s)
+{
+    const size_t N = (size_t)s->geo.N;
+    lbm_status st;
+    for (int b = 0; b < 2; ++b)
+        if ((st = dev_alloc(s, &s->d_f[b], (size_t)s->qf * N * sbytes(s), "fluid populations")))
+            return st;
+    return dev_alloc(s, &s->d_uprev, (size_t)s->dim * N * cbytes(s), "velocity history");
+}
+
+lbm_status ensure_ad(lbm_solver *s)
+{
+    const size_t N = (size_t)s->geo.N;
+    lbm_status st;
+    for (int b = 0; b < 2; ++b)
+        if ((st = dev_alloc(s, &s->d_g[b], (size_t)s->qa * N * sbytes(s), "substrate populations")))
+            return st;
+    return dev_alloc(s, &s->d_cprev, N * cbytes(s), "concentration history");
+}
+
+lbm_status ensure_stage(lbm_solver *s, size_t bytes)
+{
+    if (s->stage_bytes >= bytes)
+        return LBM_OK;
+    if (s->d_stage) {
+        HIPCHK(hipStreamSynchronize(s->ctx->stream), "stage sync");
+        HIPCHK(hipFree(s->d_stage), "stage free");
+        s->d_stage = nullptr;
+        s->stage_bytes = 0;
+    }
+    void *p = nullptr;
+    lbm_status st = dev_alloc(s, &p, bytes, "staging buffer");
+    if (st)
+        return st;
+    s->d_stage = static_cast<double *>(p);
+    s->stage_bytes = bytes;
+    return LBM_OK;
+}
+
+hipError_t launch_step(lbm_solver *s, int which, int mode, int src)
+{
+    if (which == LBM_SOLVER_FLUID) {
+        lbmk::FluidArgs a;
+        a.src = s->d_f[src];
+        a.dst = s->d_f[src ^ 1];
+        a.desc = s->d_desc;
+        a.uprev = s->d_uprev;
+        a.ctrl = s->d_ctrl;
+        a.g = s->geo;
+        a.omega = 1.0 / s->p.tau;
+        a.u_in = s->p.u_in;
+        a.inv_uin = 1.0 / fabs(s->p.u_in);
+        return lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+    }
+    const double cs2 = s->dim == 3 ? 0.25 : 1.0 / 3.0;
+    lbmk::AdArgs a;
+    a.src = s->d_g[src];
+    a.dst = s->d_g[src ^ 1];
+    a.desc = s->d_desc;
+    a.u = s->d_u;
+    a.cprev = s->d_cprev;
+    a.ctrl = s->d_ctrl + 1;
+    a.g = s->geo;
+    a.omega = 1.0 / (0.5 + s->p.D / cs2);
+    a.cin_s = s->p.c_in - s->c_ref;
+    a.cout_s = s->p.c_out - s->c_ref;
+    a.c_ref = s->c_ref;
+    a.k_sink = s->p.k_sink;
+    a.inv_cin = 1.0 / fabs(s->p.c_in);
+    a.outlet = s->p.outlet;
+    return lbmk::ad_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+}
+
+lbm_status init_solver(lbm_solver *s, int which)
+{
+    hipStream_t st = s->ctx->stream;
+    if (which == LBM_SOLVER_FLUID) {
+        HIPCHK(lbmk::fluid_init(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, st),
+               "fluid init");
+        s->fluid_ready = true;
+    } else {
+        HIPCHK(lbmk::ad_init(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->d_u, s->geo,
+                             s->p.c_in, s->c_ref, st),
+               "substrate init");
+        s->ad_ready = true;
+    }
+    return LBM_OK;
+}
+
+// algorithmic bytes per active-node update: each population read once and
+// written once, the 1-byte node class, and (substrate) the frozen velocity
+double algo_bytes(const lbm_solver *s, int which)
+{
+    if (which == LBM_SOLVER_FLUID)
+        return 2.0 * s->qf * (double)sbytes(s) + 1.0;
+    return 2.0 * s->qa * (double)sbytes(s) + (double)(s->dim * cbytes(s)) + 1.0;
+}
+
+lbm_status fill_fluxes(lbm_solver *s, double *out5)
+{
+    HIPCHK(lbmk::fluxes(s->dim, s->p.storage, s->fluid_ready ? s->d_f[s->fcur] : nullptr,
+                        s->ad_ready ? s->d_g[s->gcur] : nullptr, s->d_desc, s->geo, s->p.u_in,
+                        s->p.c_in, s->c_ref, s->p.k_sink, s->p.outlet, s->p.c_out, s->d_partials,
+                        s->d_out5, s->ctx->stream),
+           "fluxes");
+    HIPCHK(hipMemcpyAsync(out5, s->d_out5, 5 * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream),
+           "flux copy");
+    HIPCHK(hipStreamSynchronize(s->ctx->stream), "flux sync");
+    return LBM_OK;
+}
+
+lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int warm,
+                  lbm_info *info)
+{
+    if (!(tol >= 0.0) || max_iter < 1)
+        return set_err(s->ctx, LBM_EINVAL, "tol must be >= 0 and max_iter >= 1");
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    lbm_status stt = which == LBM_SOLVER_FLUID ? ensure_fluid(s) : ensure_ad(s);
+    if (stt)
+        return stt;
+    const bool ready = which == LBM_SOLVER_FLUID ? s->fluid_ready : s->ad_ready;
+    if (!warm || !ready)
+        if ((stt = init_solver(s, which)))
+            return stt;
+    hipStream_t stream = s->ctx->stream;
+    const int K = s->p.check_every;
+    const int window = s->p.stall_checks == 0 ? 100 : (s->p.stall_checks < 0 ? 0 : s->p.stall_checks);
+    lbmk::Ctrl *ctrl = s->d_ctrl + which;
+    HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K, stream), "ctrl reset");
+    int &cur = which == LBM_SOLVER_FLUID ? s->fcur : s->gcur;
+    const int cur0 = cur;
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipEventRecord(s->ev_a, stream), "event");
+    int64_t launched = 0, head = 0, tail = 0;
+    bool stopped = false;
+    while (launched < max_iter && !stopped) {
+        const int64_t rem = max_iter - launched;
+        if (rem >= K) {
+            for (int j = 1; j <= K; ++j) {
+                const int mode = j == K - 1 ? lbmk::MODE_STORE : (j == K ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN);
+                HIPCHK(launch_step(s, which, mode, (int)((cur0 + launched + j - 1) & 1)), "step launch");
+            }
+            HIPCHK(lbmk::decide(ctrl, stream), "decide");
+            launched += K;
+        } else {
+            for (int64_t j = 1; j <= rem; ++j)
+                HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, (int)((cur0 + launched + j - 1) & 1)),
+                       "step launch");
+            launched += rem;
+        }
+        const int slot = (int)(head % RING);
+        HIPCHK(hipMemcpyAsync(&s->h_ctrl[slot], ctrl, sizeof(lbmk::Ctrl), hipMemcpyDeviceToHost, stream),
+               "ctrl snapshot");
+        HIPCHK(hipEventRecord(s->ev_ring[slot], stream), "event");
+        ++head;
+        while (tail < head) {
+            const int sl = (int)(tail % RING);
+            if (head - tail > MAX_INFLIGHT) {
+                HIPCHK(hipEventSynchronize(s->ev_ring[sl]), "event sync");
+            } else {
+                hipError_t q = hipEventQuery(s->ev_ring[sl]);
+                if (q == hipErrorNotReady)
+                    break;
+                HIPCHK(q, "event query");
+            }
+            if (s->h_ctrl[sl].stop != lbmk::STOP_RUN)
+                stopped = true;
+            ++tail;
+        }
+    }
+    HIPCHK(hipEventRecord(s->ev_b, stream), "event");
+    HIPCHK(hipStreamSynchronize(stream), "solve sync");
+    lbmk::Ctrl fin;
+    HIPCHK(hipMemcpy(&fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
+    const auto t1 = std::chrono::steady_clock::now();
+    const int64_t t_final = fin.stop != lbmk::STOP_RUN ? fin.t_stop : launched;
+    cur = (int)((cur0 + t_final) & 1);
+    lbm_status result = LBM_NOT_CONVERGED;
+    if (fin.stop == lbmk::STOP_OK)
+        result = LBM_OK;
+    else if (fin.stop == lbmk::STOP_STALLED)
+        result = LBM_STALLED;
+    else if (fin.stop == lbmk::STOP_DIVERGED)
+        result = set_err(s->ctx, LBM_EDIVERGED, "solution diverged (NaN/Inf or |u| > 0.3)");
+    if (which == LBM_SOLVER_FLUID)
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, s->d_u,
+                                  nullptr, 0, stream),
+               "velocity export");
+    if (info) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b), "event time");
+        memset(info, 0, sizeof(*info));
+        info->iters = t_final;
+        info->residual = fin.checks > 0 ? fin.r_last : NAN;
+        info->checks = fin.checks;
+        info->active_nodes = which == LBM_SOLVER_FLUID ? s->n_fluid : s->n_ad;
+        info->seconds = std::chrono::duration<double>(t1 - t0).count();
+        info->kernel_ms = ms;
+        info->launches = t_final;
+        const double upd = (double)t_final * (double)info->active_nodes;
+        info->mlups = info->seconds > 0 ? upd / info->seconds / 1e6 : 0.0;
+        info->gbps = ms > 0 ? upd * algo_bytes(s, which) / (ms * 1e-3) / 1e9 : 0.0;
+        double f5[5];
+        lbm_status fs = fill_fluxes(s, f5);
+        if (fs)
+            return fs;
+        if (which == LBM_SOLVER_FLUID) {
+            info->flux_in = f5[0];
+            info->flux_out = f5[1];
+        } else {
+            info->flux_in = f5[2];
+            info->flux_out = f5[3];
+            info->sink_total = f5[4];
+        }
+    } else {
+        HIPCHK(hipStreamSynchronize(stream), "sync");
+    }
+    return result;
+}
+
+lbm_status get_field(lbm_solver *s, int field, void *dst)
+{
+    const size_t N = (size_t)s->geo.N;
+    hipStream_t st = s->ctx->stream;
+    lbm_status e;
+    switch (field) {
+    case LBM_FIELD_U:
+    case LBM_FIELD_RHO: {
+        if (!s->fluid_ready)
+            return set_err(s->ctx, LBM_EINVAL, "fluid state not initialised");
+        if ((e = ensure_stage(s, (size_t)(s->dim + 1) * N * 8)))
+            return e;
+        double *U = s->d_stage, *R = s->d_stage + (size_t)s->dim * N;
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, U, R, 1, st),
+               "export");
+        if (field == LBM_FIELD_U)
+            HIPCHK(hipMemcpyAsync(dst, U, (size_t)s->dim * N * 8, hipMemcpyDeviceToHost, st), "copy");
+        else
+            HIPCHK(hipMemcpyAsync(dst, R, N * 8, hipMemcpyDeviceToHost, st), "copy");
+        break;
+    }
+    case LBM_FIELD_C:
+        if (!s->ad_ready)
+            return set_err(s->ctx, LBM_EINVAL, "substrate state not initialised");
+        if ((e = ensure_stage(s, N * 8)))
+            return e;
+        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->geo, s->c_ref,
+                               s->p.k_sink, s->d_stage, st),
+               "export");
+        HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, hipMemcpyDeviceToHost, st), "copy");
+        break;
+    case LBM_FIELD_CLASS:
+        memcpy(dst, s->cls.data(), N);
+        return LBM_OK;
+    case LBM_FIELD_LINKS_F:
+        return lbm_links(s->grid, s->cls.data(), LBM_SOLVER_FLUID, dst);
+    case LBM_FIELD_LINKS_C:
+        return lbm_links(s->grid, s->cls.data(), LBM_SOLVER_AD, dst);
+    case LBM_FIELD_F:
+    case LBM_FIELD_G: {
+        const int which = field == LBM_FIELD_F ? 0 : 1;
+        if (which == 0 ? !s->fluid_ready : !s->ad_ready)
+            return set_err(s->ctx, LBM_EINVAL, "state not initialised");
+        const int q = which == 0 ? s->qf : s->qa;
+        if ((e = ensure_stage(s, (size_t)q * N * 8)))
+            return e;
+        HIPCHK(lbmk::pops_export(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
+                                 s->d_desc, s->geo, s->c_ref, s->d_stage, st),
+               "export");
+        HIPCHK(hipMemcpyAsync(dst, s->d_stage, (size_t)q * N * 8, hipMemcpyDeviceToHost, st), "copy");
+        break;
+    }
+    default:
+        return set_err(s->ctx, LBM_ENOTFOUND, "unknown field");
+    }
+    HIPCHK(hipStreamSynchronize(st), "get sync");
+    return LBM_OK;
+}
+
+struct StateHeader {
+    char magic[8];
+    int32_t nx, ny, nz, storage;
+    int32_t qf, qa, fluid_ready, ad_ready;
+    double tau, u_in, D, c_in, k_sink, c_out;
+    int32_t outlet, check_every;
+    int64_t N;
+    uint64_t f_bytes, g_bytes, u_bytes;
+};
+
+size_t state_size(const lbm_solver *s)
+{
+    const size_t N = (size_t)s->geo.N;
+    return sizeof(StateHeader) + N + (size_t)s->qf * N * sbytes(s) + (size_t)s->qa * N * sbytes(s) +
+           (size_t)s->dim * N * cbytes(s);
+}
+
+} // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *pp,
+                                int require_percolation, lbm_solver **out);
+
+lbm_status lbm_solver_create(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *p,
+                             lbm_solver **out)
+{
+    return lbm_solver_create_ex(ctx, g, cls, p, 1, out);
+}
+
+lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *pp,
+                                int require_percolation, lbm_solver **out)
+{
+    if (!ctx || !cls || !pp || !out)
+        return set_err(ctx, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    std::string m = check_mask(g, cls);
+    if (!m.empty())
+        return set_err(ctx, LBM_EINVAL, m);
+    const int64_t N64 = (int64_t)g.nx * g.ny * g.nz;
+    if (N64 > ((int64_t)1 << 31) / 19)
+        return set_err(ctx, LBM_EINVAL, "grid too large");
+    lbm_params p = *pp;
+    if (p.check_every == 0)
+        p.check_every = 100;
+    lbm_status st = validate_params(ctx, p);
+    if (st)
+        return st;
+    if (require_percolation && !percolates(g, cls))
+        return set_err(ctx, LBM_EINVAL, "the fluid domain does not connect inlet to outlet");
+    hipError_t he = hipSetDevice(ctx->device);
+    if (he != hipSuccess)
+        return hip_err(ctx, he, "set device");
+    lbm_solver *s = new lbm_solver();
+    s->ctx = ctx;
+    s->grid = g;
+    s->p = p;
+    s->dim = g.nz > 1 ? 3 : 2;
+    s->qf = s->dim == 3 ? 19 : 9;
+    s->qa = s->dim == 3 ? 7 : 5;
+    s->geo = lbmk::make_geo(g.nx, g.ny, g.nz);
+    s->cls.assign(cls, cls + N64);
+    s->desc_bytes = s->dim == 3 ? 4 : 2;
+    s->c_ref = lbmk::storage_shifted(p.storage) ? p.c_in : 0.0;
+    const size_t N = (size_t)N64;
+    auto fail = [&](lbm_status e) {
+        lbm_solver_destroy(s);
+        return e;
+    };
+    if ((st = dev_alloc(s, &s->d_desc, N * s->desc_bytes, "descriptors")))
+        return fail(st);
+    if ((st = dev_alloc(s, &s->d_u, (size_t)s->dim * N * cbytes(s), "velocity")))
+        return fail(st);
+    void *tmp = nullptr;
+    if ((st = dev_alloc(s, &tmp, 2 * sizeof(lbmk::Ctrl), "control")))
+        return fail(st);
+    s->d_ctrl = static_cast<lbmk::Ctrl *>(tmp);
+    tmp = nullptr;
+    if ((st = dev_alloc(s, &tmp, 5 * lbmk::FLUX_BLOCKS * sizeof(double), "flux partials")))
+        return fail(st);
+    s->d_partials = static_cast<double *>(tmp);
+    tmp = nullptr;
+    if ((st = dev_alloc(s, &tmp, 8 * sizeof(double), "flux out")))
+        return fail(st);
+    s->d_out5 = static_cast<double *>(tmp);
+    if ((st = upload_desc(s)))
+        return fail(st);
+    he = hipHostMalloc((void **)&s->h_ctrl, RING * sizeof(lbmk::Ctrl), hipHostMallocDefault);
+    if (he != hipSuccess) {
+        s->h_ctrl = nullptr;
+        return fail(hip_err(ctx, he, "pinned control ring"));
+    }
+    for (int k = 0; k < RING; ++k)
+        if ((he = hipEventCreateWithFlags(&s->ev_ring[k], hipEventDisableTiming)) != hipSuccess)
+            return fail(hip_err(ctx, he, "event"));
+    if ((he = hipEventCreate(&s->ev_a)) != hipSuccess || (he = hipEventCreate(&s->ev_b)) != hipSuccess)
+        return fail(hip_err(ctx, he, "event"));
+    if ((he = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return fail(hip_err(ctx, he, "create sync"));
+    *out = s;
+    return LBM_OK;
+}
+
+void lbm_solver_destroy(lbm_solver *s)
+{
+    if (!s)
+        return;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    void *bufs[] = {s->d_desc, s->d_f[0], s->d_f[1], s->d_g[0], s->d_g[1], s->d_u, s->d_uprev,
+                    s->d_cprev, s->d_ctrl, s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals};
+    for (void *b : bufs)
+        if (b)
+            (void)hipFree(b);
+    if (s->h_ctrl)
+        (void)hipHostFree(s->h_ctrl);
+    for (int k = 0; k < RING; ++k)
+        if (s->ev_ring[k])
+            (void)hipEventDestroy(s->ev_ring[k]);
+    if (s->ev_a)
+        (void)hipEventDestroy(s->ev_a);
+    if (s->ev_b)
+        (void)hipEventDestroy(s->ev_b);
+    delete s;
+}
+
+lbm_status lbm_solver_fluid(lbm_solver *s, double tol, int64_t max_iter, int warm, lbm_info *info)
+{
+    if (!s)
+        return LBM_EINVAL;
+    if (!percolates(s->grid, s->cls.data()))
+        return set_err(s->ctx, LBM_EINVAL, "the fluid domain does not connect inlet to outlet");
+    return steady(s, LBM_SOLVER_FLUID, tol, max_iter, warm, info);
+}
+
+lbm_status lbm_solver_ad(lbm_solver *s, double tol, int64_t max_iter, int warm, lbm_info *info)
+{
+    if (!s)
+        return LBM_EINVAL;
+    return steady(s, LBM_SOLVER_AD, tol, max_iter, warm, info);
+}
+
+lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, double *kernel_ms)
+{
+    if (!s || (which != 0 && which != 1) || nsteps < 0)
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    lbm_status st = which == 0 ? ensure_fluid(s) : ensure_ad(s);
+    if (st)
+        return st;
+    const bool ready = which == 0 ? s->fluid_ready : s->ad_ready;
+    if (cold || !ready)
+        if ((st = init_solver(s, which)))
+            return st;
+    hipStream_t stream = s->ctx->stream;
+    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every, stream), "ctrl");
+    int &cur = which == 0 ? s->fcur : s->gcur;
+    HIPCHK(hipEventRecord(s->ev_a, stream), "event");
+    for (int64_t t = 0; t < nsteps; ++t) {
+        HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, cur), "step launch");
+        cur ^= 1;
+    }
+    HIPCHK(hipEventRecord(s->ev_b, stream), "event");
+    HIPCHK(hipStreamSynchronize(stream), "steps sync");
+    if (kernel_ms) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b), "event time");
+        *kernel_ms = ms;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *avg_ms)
+{
+    if (!s || (which != 0 && which != 1) || nsteps < 1 || !avg_ms)
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    const bool ready = which == 0 ? s->fluid_ready : s->ad_ready;
+    if (!ready)
+        return set_err(s->ctx, LBM_EINVAL, "state not initialised");
+    hipStream_t stream = s->ctx->stream;
+    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every, stream), "ctrl");
+    std::vector<hipEvent_t> ev((size_t)2 * nsteps);
+    for (auto &e : ev)
+        HIPCHK(hipEventCreate(&e), "event");
+    int &cur = which == 0 ? s->fcur : s->gcur;
+    hipError_t err = hipSuccess;
+    for (int t = 0; t < nsteps && err == hipSuccess; ++t) {
+        err = hipEventRecord(ev[2 * t], stream);
+        if (err == hipSuccess)
+            err = launch_step(s, which, lbmk::MODE_PLAIN, cur);
+        if (err == hipSuccess)
+            err = hipEventRecord(ev[2 * t + 1], stream);
+        cur ^= 1;
+    }
+    if (err == hipSuccess)
+        err = hipStreamSynchronize(stream);
+    double sum = 0.0;
+    for (int t = 0; t < nsteps && err == hipSuccess; ++t) {
+        float ms = 0.f;
+        err = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
+        sum += ms;
+    }
+    for (auto &e : ev)
+        (void)hipEventDestroy(e);
+    HIPCHK(err, "per-launch timing");
+    *avg_ms = sum / nsteps;
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_export_u(lbm_solver *s)
+{
+    if (!s)
+        return LBM_EINVAL;
+    if (!s->fluid_ready)
+        return set_err(s->ctx, LBM_EINVAL, "fluid state not initialised");
+    HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, s->d_u, nullptr,
+                              0, s->ctx->stream),
+           "velocity export");
+    HIPCHK(hipStreamSynchronize(s->ctx->stream), "sync");
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_set_u(lbm_solver *s, const double *u)
+{
+    if (!s || !u)
+        return LBM_EINVAL;
+    const size_t n = (size_t)s->dim * (size_t)s->geo.N;
+    if (cbytes(s) == 8) {
+        HIPCHK(hipMemcpy(s->d_u, u, n * 8, hipMemcpyHostToDevice), "set u");
+    } else {
+        std::vector<float> f(n);
+        for (size_t k = 0; k < n; ++k)
+            f[k] = (float)u[k];
+        HIPCHK(hipMemcpy(s->d_u, f.data(), n * 4, hipMemcpyHostToDevice), "set u");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_get(lbm_solver *s, int field, void *dst)
+{
+    if (!s || !dst)
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    return get_field(s, field, dst);
+}
+
+lbm_status lbm_solver_put(lbm_solver *s, int field, const double *src)
+{
+    if (!s || !src || (field != LBM_FIELD_F && field != LBM_FIELD_G))
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    const int which = field == LBM_FIELD_F ? 0 : 1;
+    lbm_status st = which == 0 ? ensure_fluid(s) : ensure_ad(s);
+    if (st)
+        return st;
+    const size_t N = (size_t)s->geo.N;
+    const int q = which == 0 ? s->qf : s->qa;
+    if ((st = ensure_stage(s, (size_t)q * N * 8)))
+        return st;
+    hipStream_t stream = s->ctx->stream;
+    HIPCHK(hipMemcpyAsync(s->d_stage, src, (size_t)q * N * 8, hipMemcpyHostToDevice, stream), "copy");
+    HIPCHK(lbmk::pops_import(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
+                             s->d_desc, s->geo, s->c_ref, s->d_stage, stream),
+           "import");
+    HIPCHK(hipStreamSynchronize(stream), "sync");
+    if (which == 0)
+        s->fluid_ready = true;
+    else
+        s->ad_ready = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_device_ptr(lbm_solver *s, int field, void **ptr, size_t *bytes)
+{
+    if (!s || !ptr)
+        return LBM_EINVAL;
+    if (field != LBM_FIELD_U_DEVICE)
+        return set_err(s->ctx, LBM_ENOTFOUND, "only LBM_FIELD_U_DEVICE has a device pointer");
+    *ptr = s->d_u;
+    if (bytes)
+        *bytes = (size_t)s->dim * (size_t)s->geo.N * cbytes(s);
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_fluxes(lbm_solver *s, double *out5)
+{
+    if (!s || !out5)
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    return fill_fluxes(s, out5);
+}
+
+lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint8_t *new_cls, int64_t n)
+{
+    if (!s || n < 0 || (n > 0 && (!idx || !new_cls)))
+        return LBM_EINVAL;
+    const int64_t N = s->geo.N;
+    std::vector<uint8_t> trial = s->cls;
+    for (int64_t k = 0; k < n; ++k) {
+        if (idx[k] < 0 || idx[k] >= N || new_cls[k] > LBM_BIOFILM)
+            return set_err(s->ctx, LBM_EINVAL, "bad cell index or class");
+        trial[(size_t)idx[k]] = new_cls[k];
+    }
+    std::string m = check_mask(s->grid, trial.data());
+    if (!m.empty())
+        return set_err(s->ctx, LBM_EINVAL, m);
+    if (!percolates(s->grid, trial.data()))
+        return set_err(s->ctx, LBM_EINVAL, "update would disconnect inlet from outlet");
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    // populations of nodes whose activity changes: four lists
+    std::vector<long long> f_off, f_on, g_off, g_on;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t j = idx[k];
+        const uint8_t a = s->cls[(size_t)j], b = trial[(size_t)j];
+        const bool fa = a == LBM_FLUID, fb = b == LBM_FLUID;
+        const bool ga = a == LBM_FLUID || a == LBM_BIOFILM, gb = b == LBM_FLUID || b == LBM_BIOFILM;
+        if (fa && !fb)
+            f_off.push_back(j);
+        if (!fa && fb)
+            f_on.push_back(j);
+        if (ga && !gb)
+            g_off.push_back(j);
+        if (!ga && gb)
+            g_on.push_back(j);
+    }
+    s->cls.swap(trial);
+    lbm_status st = upload_desc(s);
+    if (st)
+        return st;
+    if (!s->d_idx) {
+        void *p = nullptr;
+        if ((st = dev_alloc(s, &p, 4096 * sizeof(long long), "index scratch")))
+            return st;
+        s->d_idx = static_cast<long long *>(p);
+        p = nullptr;
+        if ((st = dev_alloc(s, &p, 32 * sizeof(double), "value scratch")))
+            return st;
+        s->d_vals = static_cast<double *>(p);
+    }
+    hipStream_t stream = s->ctx->stream;
+    const bool sh = shifted(s);
+    static const double wf2[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static const double wf3[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static const double wa2[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    static const double wa3[7] = {1.0 / 4, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8};
+    auto apply = [&](int which, const std::vector<long long> &list, bool on) -> lbm_status {
+        if (list.empty())
+            return LBM_OK;
+        void *buf = which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur];
+        if (!buf)
+            return LBM_OK; // solver never run: nothing stored yet
+        const int q = which == 0 ? s->qf : s->qa;
+        const double *w = which == 0 ? (s->dim == 3 ? wf3 : wf2) : (s->dim == 3 ? wa3 : wa2);
+        double vals[19];
+        for (int i = 0; i < q; ++i) {
+            if (!on)
+                vals[i] = 0.0;
+            else if (which == 0)
+                vals[i] = sh ? 0.0 : w[i];                      // rest state
+            else
+                vals[i] = w[i] * (s->p.c_in - s->c_ref);         // equilibrium at c_in, u = 0
+        }
+        HIPCHK(hipMemcpyAsync(s->d_vals, vals, q * sizeof(double), hipMemcpyHostToDevice, stream), "vals");
+        for (size_t off = 0; off < list.size(); off += 4096) {
+            const int cnt = (int)std::min<size_t>(4096, list.size() - off);
+            HIPCHK(hipMemcpyAsync(s->d_idx, list.data() + off, cnt * sizeof(long long),
+                                  hipMemcpyHostToDevice, stream),
+                   "idx");
+            HIPCHK(lbmk::pops_set_nodes(which, s->dim, s->p.storage, buf, s->geo, s->d_idx, cnt, s->d_vals,
+                                        stream),
+                   "cell reset");
+            HIPCHK(hipStreamSynchronize(stream), "sync");
+        }
+        return LBM_OK;
+    };
+    if ((st = apply(0, f_off, false)) || (st = apply(0, f_on, true)) || (st = apply(1, g_off, false)) ||
+        (st = apply(1, g_on, true)))
+        return st;
+    HIPCHK(hipStreamSynchronize(stream), "sync");
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_state_size(lbm_solver *s, size_t *bytes)
+{
+    if (!s || !bytes)
+        return LBM_EINVAL;
+    *bytes = state_size(s);
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
+{
+    if (!s || !dst || bytes < state_size(s))
+        return LBM_EINVAL;
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    const size_t N = (size_t)s->geo.N;
+    StateHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, "LBMSTAT1", 8);
+    h.nx = s->grid.nx;
+    h.ny = s->grid.ny;
+    h.nz = s->grid.nz;
+    h.storage = s->p.storage;
+    h.qf = s->qf;
+    h.qa = s->qa;
+    h.fluid_ready = s->fluid_ready;
+    h.ad_ready = s->ad_ready;
+    h.tau = s->p.tau;
+    h.u_in = s->p.u_in;
+    h.D = s->p.D;
+    h.c_in = s->p.c_in;
+    h.k_sink = s->p.k_sink;
+    h.c_out = s->p.c_out;
+    h.outlet = s->p.outlet;
+    h.check_every = s->p.check_every;
+    h.N = (int64_t)N;
+    h.f_bytes = (uint64_t)s->qf * N * sbytes(s);
+    h.g_bytes = (uint64_t)s->qa * N * sbytes(s);
+    h.u_bytes = (uint64_t)s->dim * N * cbytes(s);
+    char *p = static_cast<char *>(dst);
+    memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    memcpy(p, s->cls.data(), N);
+    p += N;
+    hipStream_t st = s->ctx->stream;
+    if (s->fluid_ready)
+        HIPCHK(hipMemcpyAsync(p, s->d_f[s->fcur], h.f_bytes, hipMemcpyDeviceToHost, st), "state f");
+    else
+        memset(p, 0, h.f_bytes);
+    p += h.f_bytes;
+    if (s->ad_ready)
+        HIPCHK(hipMemcpyAsync(p, s->d_g[s->gcur], h.g_bytes, hipMemcpyDeviceToHost, st), "state g");
+    else
+        memset(p, 0, h.g_bytes);
+    p += h.g_bytes;
+    HIPCHK(hipMemcpyAsync(p, s->d_u, h.u_bytes, hipMemcpyDeviceToHost, st), "state u");
+    HIPCHK(hipStreamSynchronize(st), "state sync");
+    return LBM_OK;
+}
+
+lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
+{
+    if (!s || !src || bytes < sizeof(StateHeader))
+        return LBM_EINVAL;
+    StateHeader h;
+    memcpy(&h, src, sizeof(h));
+    if (memcmp(h.magic, "LBMSTAT1", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
+        h.nz != s->grid.nz || h.storage != s->p.storage || bytes < state_size(s))
+        return set_err(s->ctx, LBM_EINVAL, "checkpoint does not match this solver");
+    const size_t N = (size_t)s->geo.N;
+    const char *p = static_cast<const char *>(src) + sizeof(h);
+    std::string m = check_mask(s->grid, reinterpret_cast<const uint8_t *>(p));
+    if (!m.empty())
+        return set_err(s->ctx, LBM_EINVAL, "checkpoint mask: " + m);
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    lbm_status st;
+    if ((st = ensure_fluid(s)) || (st = ensure_ad(s)))
+        return st;
+    s->cls.assign(reinterpret_cast<const uint8_t *>(p), reinterpret_cast<const uint8_t *>(p) + N);
+    if ((st = upload_desc(s)))
+        return st;
+    p += N;
+    s->fcur = 0;
+    s->gcur = 0;
+    HIPCHK(hipMemcpy(s->d_f[0], p, h.f_bytes, hipMemcpyHostToDevice), "state f");
+    p += h.f_bytes;
+    HIPCHK(hipMemcpy(s->d_g[0], p, h.g_bytes, hipMemcpyHostToDevice), "state g");
+    p += h.g_bytes;
+    HIPCHK(hipMemcpy(s->d_u, p, h.u_bytes, hipMemcpyHostToDevice), "state u");
+    s->fluid_ready = h.fluid_ready != 0;
+    s->ad_ready = h.ad_ready != 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_coupled_run(lbm_solver *s, int n_updates, const double *xi, double tol, int64_t max_iter,
+                           int64_t *picked, double *J, double *J_accum, int64_t *iters_fluid,
+                           int64_t *iters_ad)
+{
+    if (!s || n_updates < 0 || (n_updates > 0 && !xi) || !J_accum)
+        return LBM_EINVAL;
+    for (int m = 0; m < n_updates; ++m)
+        if (!(xi[m] >= 0.0 && xi[m] < 1.0))
+            return set_err(s->ctx, LBM_EINVAL, "xi must lie in [0, 1)");
+    const size_t N = (size_t)s->geo.N;
+    std::vector<double> C(N);
+    double acc = 0.0;
+    lbm_info fi, ai;
+    for (int m = 0; m <= n_updates; ++m) {
+        if (m > 0) {
+            lbm_status st = get_field(s, LBM_FIELD_C, C.data());
+            if (st)
+                return st;
+            const int64_t p = growth_pick(s->grid, s->cls.data(), C.data(), xi[m - 1]);
+            if (picked)
+                picked[m - 1] = p;
+            if (p < 0)
+                return set_err(s->ctx, LBM_EINVAL, "no biofilm growth candidate left");
+            const uint8_t bio = LBM_BIOFILM;
+            if ((st = lbm_solver_update_cells(s, &p, &bio, 1)))
+                return st;
+        }
+        lbm_status sf = lbm_solver_fluid(s, tol, max_iter, m > 0, &fi);
+        if (iters_fluid)
+            iters_fluid[m] = fi.iters;
+        if (sf < 0)
+            return sf;
+        lbm_status sa = lbm_solver_ad(s, tol, max_iter, m > 0, &ai);
+        if (iters_ad)
+            iters_ad[m] = ai.iters;
+        if (sa < 0)
+            return sa;
+        if (J)
+            J[m] = ai.sink_total;
+        if (m > 0)
+            acc += ai.sink_total;
+    }
+    *J_accum = acc;
+    return LBM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Fixed-step parity from identical starting states (all four storage forms,
+2-D and 3-D, full tiles and ragged tails), converged iteration-matched
+parity on the 128 x 64 workload, fluxes, status codes, cell updates and
+checkpoint/resume.
+
+Tolerances follow from the arithmetic.  FP64 storage differs from the
+oracle only by summation order and fused multiply-adds (~1e-16 per
+operation): 1e-12.  The reduced-precision forms round every stored value
+each step (2^-24 relative for FP32, 2^-11 for FP16) and, near a steady
+state, the same rounding recurs step after step, so population errors grow
+about linearly with the step count n: the population bounds are
+a * (n + 1) with a = 1e-8 (FP32: values ~w_i, unit round-off 6e-8 spread
+over the moments), 1e-9 (FP32 shifted: values ~1e-2) and 5e-7 (FP16
+shifted).  Velocity and concentration must stay within 1e-4 (FP32 forms)
+and 5e-3 (FP16 storage) relative L2, the targets of the method's
+precision forms.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import masks, max_abs, rel_l2
+from paper_1802_07525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP32S, FP16S, FP64 = 0, 1, 2, 3
+NAMES = {FP32: "fp32", FP32S: "fp32s", FP16S: "fp16s", FP64: "fp64"}
+
+# population error per step (rel L2; FP64: max abs) and field bound (rel L2)
+POP_RATE = {FP64: None, FP32: 1e-8, FP32S: 1e-9, FP16S: 5e-7}
+FIELD_TOL = {FP64: 1e-12, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3}
+TOL_CONV = {FP64: 1e-9, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3}
+
+
+def _pop_ok(storage, got, want, sel, n):
+    if storage == FP64:
+        return max_abs(got, want, sel) < 1e-12
+    return rel_l2(got, want, sel) < POP_RATE[storage] * (n + 1)
+
+C1 = inputs.WORKLOADS["c1"]
+RAGGED = inputs.scaled(C1, 100, 37, r_min=2, r_max=4, solid=0.25, seed=11)
+
+
+def _solver(lbm, cls, w, storage, **over):
+    p = dict(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+             storage=storage)
+    p.update(over)
+    return lbm.Solver(cls, **p)
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S], ids=NAMES.get)
+@pytest.mark.parametrize("w", [C1, RAGGED], ids=["128x64", "100x37"])
+def test_fluid_fixed_steps(gpu_lib, storage, w):
+    lbm = gpu_lib
+    cls = masks(w, lbm)
+    fluid = cls.ravel() == O.FLUID
+    with _solver(lbm, cls, w, storage) as s:
+        f_or = O.fluid_init(cls)
+        done = 0
+        for n in (1, 10, 200):
+            st, _ = s.steps(lbm.LBM_SOLVER_FLUID, n - done, cold=(done == 0))
+            assert st == 0, s.error()
+            f_or, _, _ = O.fluid_run(cls, f_or, w["tau"], w["u_in"], n - done)
+            done = n
+            F = s.get(lbm.LBM_FIELD_F)
+            U_or, rho_or = O.fluid_moments(cls, f_or)
+            U = s.get(lbm.LBM_FIELD_U)
+            assert _pop_ok(storage, F, f_or, fluid, n), (n, rel_l2(F, f_or, fluid))
+            assert rel_l2(U, U_or, fluid) < FIELD_TOL[storage], (n, rel_l2(U, U_or, fluid))
+            assert np.all(F[:, ~fluid] == 0) and np.all(U[:, ~fluid] == 0)
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S], ids=NAMES.get)
+@pytest.mark.parametrize("outlet", [0, 1])
+def test_ad_fixed_steps(gpu_lib, storage, outlet):
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    # frozen velocity: the oracle's own fluid field after 400 steps
+    _, U, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], 400)
+    with _solver(lbm, cls, w, storage, outlet=outlet, c_out=0.25) as s:
+        assert s and lbm.lbm_solver_set_u(s.h, U) == 0
+        g_or = O.ad_init(cls, U, w["c_in"])
+        done = 0
+        for n in (1, 10, 200):
+            st, _ = s.steps(lbm.LBM_SOLVER_AD, n - done, cold=(done == 0))
+            assert st == 0, s.error()
+            g_or, _ = O.ad_run(cls, g_or, U, w["D"], w["c_in"], w["k"], n - done, outlet, 0.25)
+            done = n
+            G = s.get(lbm.LBM_FIELD_G)
+            C = s.get(lbm.LBM_FIELD_C)
+            C_or = O.ad_moment(cls, g_or, w["k"])
+            assert _pop_ok(storage, G, g_or, act, n), (n, rel_l2(G, g_or, act))
+            assert rel_l2(C, C_or, act) < FIELD_TOL[storage], (n, rel_l2(C, C_or, act))
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32S], ids=NAMES.get)
+def test_3d_fixed_steps(gpu_lib, storage):
+    lbm = gpu_lib
+    w = inputs.scaled(inputs.WORKLOADS["c3"], 70, 22, 18, seed=9)
+    cls = masks(w, lbm)
+    fl = cls.ravel() == O.FLUID
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    with _solver(lbm, cls, w, storage) as s:
+        st, _ = s.steps(lbm.LBM_SOLVER_FLUID, 120, cold=1)
+        assert st == 0, s.error()
+        f_or, U_or, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], 120)
+        U_or, _ = O.fluid_moments(cls, f_or)
+        assert rel_l2(s.get(lbm.LBM_FIELD_U), U_or, fl) < FIELD_TOL[storage]
+        # substrate in the oracle's velocity
+        assert lbm.lbm_solver_set_u(s.h, U_or) == 0
+        st, _ = s.steps(lbm.LBM_SOLVER_AD, 80, cold=1)
+        assert st == 0
+        g_or, _ = O.ad_run(cls, O.ad_init(cls, U_or, w["c_in"]), U_or, w["D"], w["c_in"], w["k"], 80)
+        C_or = O.ad_moment(cls, g_or, w["k"])
+        assert rel_l2(s.get(lbm.LBM_FIELD_C), C_or, act) < FIELD_TOL[storage]
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32S, FP16S], ids=NAMES.get)
+def test_c1_converged_iteration_matched(gpu_lib, storage):
+    """128 x 64 workload: fluid steady (1e-8 or 10k steps), then substrate in
+    the exported velocity.  The oracle runs the same number of steps."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    fl = cls.ravel() == O.FLUID
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    with _solver(lbm, cls, w, storage) as s:
+        st, info = s.fluid(w["tol"], w["max_iter"])
+        assert st in (0, 1, 2), s.error()
+        f_or, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], info["iters"])
+        U_or, _ = O.fluid_moments(cls, f_or)
+        assert rel_l2(s.get(lbm.LBM_FIELD_U), U_or, fl) < TOL_CONV[storage]
+        if storage == FP64:
+            r = O.fluid_solve(cls, w["tau"], w["u_in"], w["tol"], w["max_iter"])
+            assert r["iters"] == info["iters"]
+            assert {"OK": 0, "NOT_CONVERGED": 1, "STALLED": 2}[r["status"]] == st
+        st2, info2 = s.ad(w["tol"], w["max_iter"])
+        assert st2 in (0, 1, 2), s.error()
+        g_or, _ = O.ad_run(cls, O.ad_init(cls, U_or, w["c_in"]), U_or, w["D"], w["c_in"], w["k"],
+                           info2["iters"])
+        C_or = O.ad_moment(cls, g_or, w["k"])
+        assert rel_l2(s.get(lbm.LBM_FIELD_C), C_or, act) < TOL_CONV[storage]
+        fin, fout, sink = O.ad_fluxes(cls, g_or, w["c_in"], w["k"])
+        assert abs(info2["sink_total"] - sink) / sink < TOL_CONV[storage]
+        assert abs(info2["flux_in"] - fin) / abs(fin) < TOL_CONV[storage]
+
+
+def test_fluxes_and_steady_balance(gpu_lib):
+    """Open medium run to steady state in FP64: inflow equals outflow for
+    the fluid, inflow - outflow equals consumption for the substrate, and
+    both match the oracle's sums on the oracle's state."""
+    lbm = gpu_lib
+    w = inputs.scaled(C1, 96, 40, r_min=2, r_max=4, solid=0.2, seed=5, tau=0.8, u_in=0.02,
+                      D=0.1, k=5e-3)
+    cls = masks(w, lbm)
+    assert O.percolates(cls)
+    with _solver(lbm, cls, w, FP64) as s:
+        st, fi = s.fluid(1e-9, 100000)
+        assert st == 0, s.error()
+        st, ai = s.ad(1e-11, 200000)
+        assert st == 0, s.error()
+        assert abs(fi["flux_in"] - fi["flux_out"]) / fi["flux_in"] < 1e-6
+        assert abs(ai["flux_in"] - ai["flux_out"] - ai["sink_total"]) / ai["sink_total"] < 1e-6
+        fo = O.fluid_solve(cls, w["tau"], w["u_in"], 1e-9, 100000)
+        ao = O.ad_solve(cls, fo["U"], w["D"], w["c_in"], w["k"], 1e-11, 200000)
+        fin, fout, sink = O.ad_fluxes(cls, ao["g"], w["c_in"], w["k"])
+        assert abs(ai["sink_total"] - sink) / sink < 1e-8
+        assert fo["iters"] == fi["iters"] and ao["iters"] == ai["iters"]
+
+
+def test_status_codes(gpu_lib):
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    with _solver(lbm, cls, w, FP32S) as s:
+        st, info = s.fluid(1e-8, 1)
+        assert st == lbm.LBM_NOT_CONVERGED and info["iters"] == 1
+        st, info = s.fluid(1e-8, 150)
+        assert st == lbm.LBM_NOT_CONVERGED and info["iters"] == 150 and info["checks"] == 1
+        st, info = s.fluid(1.0, 10000)
+        assert st == lbm.LBM_OK and info["iters"] == 100
+    with _solver(lbm, cls, w, FP32, tau=0.5001, u_in=0.09) as s:
+        st, info = s.fluid(1e-8, 20000)
+        assert st == lbm.LBM_EDIVERGED
+    blocked = cls.copy()
+    blocked.reshape(64, 128)[1:-1, 64] = O.SOLID
+    with pytest.raises(lbm.LBMError):
+        _solver(lbm, blocked, w, FP32S)
+    bad = cls.copy()
+    bad.reshape(64, 128)[0, 5] = O.FLUID
+    with pytest.raises(lbm.LBMError):
+        _solver(lbm, bad, w, FP32S)
+
+
+@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=NAMES.get)
+def test_checkpoint_resume_bit_exact(gpu_lib, storage):
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    with _solver(lbm, cls, w, storage) as a, _solver(lbm, cls, w, storage) as b:
+        assert a.steps(0, 300, cold=1)[0] == 0
+        assert a.steps(1, 1, cold=1)[0] == 0  # initialise the substrate state
+        blob = lbm.lbm_solver_get_state(a.h)
+        assert a.steps(0, 250)[0] == 0 and a.steps(1, 250)[0] == 0
+        assert lbm.lbm_solver_put_state(b.h, blob) == 0
+        assert b.steps(0, 250)[0] == 0 and b.steps(1, 250)[0] == 0
+        assert np.array_equal(a.get(lbm.LBM_FIELD_F), b.get(lbm.LBM_FIELD_F))
+        assert np.array_equal(a.get(lbm.LBM_FIELD_G), b.get(lbm.LBM_FIELD_G))
+
+
+def test_update_cells_matches_oracle(gpu_lib):
+    """Growing a biofilm cell drops its fluid populations and keeps its
+    substrate ones; the next steps match the oracle on the new mask."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    with _solver(lbm, cls, w, FP64) as s:
+        assert s.steps(0, 200, cold=1)[0] == 0
+        f_or, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], 200)
+        C = np.ones(cls.size)
+        p = O.growth_pick(cls, C, 0.37)
+        assert lbm.lbm_growth_pick(cls, C, 0.37) == p
+        assert lbm.lbm_solver_update_cells(s.h, [p], [O.BIOFILM]) == 0
+        cls2 = cls.copy().ravel()
+        cls2[p] = O.BIOFILM
+        cls2 = cls2.reshape(cls.shape)
+        f_or[:, p] = 0.0
+        assert np.array_equal(s.get(lbm.LBM_FIELD_CLASS), cls2.ravel())
+        assert np.array_equal(s.get(lbm.LBM_FIELD_LINKS_F), O.links(cls2, 0).ravel())
+        assert s.steps(0, 50)[0] == 0
+        f_or, _, _ = O.fluid_run(cls2, f_or, w["tau"], w["u_in"], 50)
+        assert max_abs(s.get(lbm.LBM_FIELD_F), f_or) < 1e-12

@@ -1,0 +1,110 @@
+"""CPU tests of the HIP library's host side (no GPU calls): the shared
+library loads, exports every entry point include/lbm.h declares, and its
+integer geometry (seeded electrodes, biofilm layer, link masks, link list,
+percolation, growth pick) is byte-equal to the oracle's independent code."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1802_07525_amd as L
+from paper_1802_07525_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    names = _header_functions()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares a signature for every header function
+    assert set(names) <= set(L.exported_symbols())
+
+
+def test_status_strings_and_version():
+    lib = L.load()
+    assert lib.lbm_status_str(0) == b"LBM_OK"
+    assert lib.lbm_status_str(-4) == b"LBM_EDIVERGED"
+    assert b"gfx950" in lib.lbm_version()
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+@pytest.mark.parametrize("overlap,fs", [(0, 0.3), (1, 0.55)])
+def test_discs_byte_equal_to_oracle(seed, overlap, fs):
+    st, a, fa = L.lbm_geom_discs(160, 80, 3, 6, fs, overlap, seed)
+    so, b, fb = O.geom_discs(160, 80, 3, 6, fs, overlap, seed)
+    assert st == 0 and so == "OK"
+    assert np.array_equal(a, b) and fa == fb
+
+
+@pytest.mark.parametrize("key", ["c1", "c5"])
+def test_workload_masks_byte_equal(key):
+    w = inputs.WORKLOADS[key]
+    _, a, _ = L.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"], w["overlap"],
+                               w["seed"])
+    _, b, _ = O.geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"], w["overlap"],
+                           w["seed"])
+    a, b = L.lbm_biofilm_layer(a), O.biofilm_layer(b)
+    assert np.array_equal(a, b)
+    for which in (0, 1):
+        assert np.array_equal(L.lbm_links(a, which), O.links(b, which))
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_fibres_and_3d_links_byte_equal(seed):
+    st, a, fa = L.lbm_geom_fibres(48, 24, 20, 2, 4, 0.2, seed)
+    so, b, fb = O.geom_fibres(48, 24, 20, 2, 4, 0.2, seed)
+    assert st == 0 and np.array_equal(a, b) and fa == fb
+    a, b = L.lbm_biofilm_layer(a), O.biofilm_layer(b)
+    assert np.array_equal(a, b)
+    for which in (0, 1):
+        la, lb = L.lbm_links(a, which), O.links(b, which)
+        assert la.dtype == lb.dtype and np.array_equal(la, lb)
+    assert L.lbm_percolates(a) == O.percolates(b)
+
+
+def test_link_list_is_ascending_set_bits():
+    _, a, _ = L.lbm_geom_discs(64, 32, 2, 4, 0.3, 0, 7)
+    a = L.lbm_biofilm_layer(a)
+    for which, q in ((0, 9), (1, 5)):
+        lst = L.lbm_link_list(a, which)
+        bits = O.links(a, which).ravel()
+        want = [(n, i) for n in range(a.size) for i in range(1, q) if (int(bits[n]) >> i) & 1]
+        assert [tuple(r) for r in lst] == want
+
+
+def test_percolation_and_growth_pick_match_oracle():
+    rng = np.random.default_rng(5)
+    for seed in range(1, 15):
+        _, a, _ = L.lbm_geom_discs(64, 24, 2, 4, 0.25, 0, seed)
+        a = L.lbm_biofilm_layer(a)
+        assert L.lbm_percolates(a) == O.percolates(a)
+        C = rng.random(a.size) - 0.05
+        for xi in rng.random(5):
+            assert L.lbm_growth_pick(a, C, xi) == O.growth_pick(a, C, xi)
+
+
+def test_splitmix64_matches_oracle():
+    for seed in (0, 1, 1234567, 2 ** 63 + 11):
+        assert np.array_equal(L.lbm_splitmix64(seed, 64), O.splitmix64(seed, 64))
+
+
+def test_geometry_rejects_bad_arguments():
+    st, _, _ = L.lbm_geom_discs(3, 2, 3, 6, 0.3, 0, 1)
+    assert st == L.LBM_EINVAL
+    st, _, _ = L.lbm_geom_discs(64, 32, 6, 3, 0.3, 0, 1)
+    assert st == L.LBM_EINVAL
+    # unreachable target with non-overlapping discs -> EINVAL after 10^6 attempts
+    st, _, _ = L.lbm_geom_discs(16, 10, 5, 5, 0.9, 0, 1)
+    assert st == L.LBM_EINVAL
