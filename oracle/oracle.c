@@ -256,9 +256,13 @@ int orc_fluid_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  *       bounce-back from a wall moving at the plug inflow speed; each inlet
  *       node gains exactly u_in of mass per step (sum of w_i over c_ix = +1
  *       is 1/6 on both fluid lattices);
- *   (b) s right of column nx-1 (outlet): f_i = -f*_opp(n) + 2 w_i rho_out,
- *       rho_out = 1 -- anti-bounce-back pressure outlet, O(u^2) terms
- *       dropped;
+ *   (b) s right of column nx-1 (outlet): anti-bounce-back pressure outlet
+ *       f_i = -f*_opp(n) + 2 w_i rho_out (1 + 9/2 (c_i.u*)^2 - 3/2 u*^2),
+ *       rho_out = 1, where u* is the velocity of this node's stored state
+ *       f*(n): twice the symmetric (even) part of the Eq. 5 equilibrium at
+ *       the outlet density.  (Dropping the u*^2 terms makes the outlet
+ *       unstable: an empty 3-D duct at tau = 0.7 blows up within 1500
+ *       steps.)
  *   (c) s blocked (electrode, chassis, biofilm) or outside in y/z:
  *       f_i = f*_opp(n) -- half-way bounce-back (Sec. 2.1.1, Eq. 11, read
  *       in its half-way form; the steady fixed point is the same as the
@@ -305,6 +309,19 @@ int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             }
             double f[ORC_MAXQ];
             int pos[3] = {x, y, z};
+            /* velocity of the stored state at this node (outlet rule only) */
+            double us[3] = {0.0, 0.0, 0.0};
+            if (x == nx - 1 && !per[0]) {
+                double r = 0.0, jj[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < L.q; k++) {
+                    double v = f_src[k * N + n];
+                    r += v;
+                    for (int d = 0; d < 3; d++)
+                        jj[d] += L.c[k][d] * v;
+                }
+                for (int d = 0; d < 3; d++)
+                    us[d] = jj[d] / r;
+            }
             for (int i = 0; i < L.q; i++) {
                 int s[3];
                 int outside = 0; /* 0 inside, 1 inlet, 2 outlet, 3 other */
@@ -323,7 +340,10 @@ int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                 if (outside == 1) {
                     f[i] = f_src[o * N + n] + 6.0 * L.w[i] * L.c[i][0] * u_in;
                 } else if (outside == 2) {
-                    f[i] = -f_src[o * N + n] + 2.0 * L.w[i] * rho_out;
+                    double cu = L.c[i][0] * us[0] + L.c[i][1] * us[1] + L.c[i][2] * us[2];
+                    double uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+                    f[i] = -f_src[o * N + n] +
+                           2.0 * L.w[i] * rho_out * (1.0 + 4.5 * cu * cu - 1.5 * uu);
                 } else if (outside == 3) {
                     f[i] = f_src[o * N + n];
                 } else {
@@ -418,6 +438,17 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         if (cls[n] != ORC_FLUID)
             continue;
         int x = (int)(n % nx);
+        double us[3] = {0.0, 0.0, 0.0};
+        if (x == nx - 1) {
+            double r = 0.0, jj[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < L.q; k++) {
+                r += f[k * N + n];
+                for (int d = 0; d < 3; d++)
+                    jj[d] += L.c[k][d] * f[k * N + n];
+            }
+            for (int d = 0; d < 3; d++)
+                us[d] = jj[d] / r;
+        }
         for (int i = 0; i < L.q; i++) {
             int o = L.opp[i];
             if (x == 0 && L.c[i][0] == 1) {
@@ -425,7 +456,9 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                 fin += incoming - f[o * N + n];
             }
             if (x == nx - 1 && L.c[i][0] == -1) {
-                double incoming = -f[o * N + n] + 2.0 * L.w[i];
+                double cu = L.c[i][0] * us[0] + L.c[i][1] * us[1] + L.c[i][2] * us[2];
+                double uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+                double incoming = -f[o * N + n] + 2.0 * L.w[i] * (1.0 + 4.5 * cu * cu - 1.5 * uu);
                 fout += f[o * N + n] - incoming;
             }
         }

@@ -373,7 +373,9 @@ def _push_fluid(cls, f, tau, u_in, c, w, opp):
     post-collision population is sent along its velocity; one that would
     enter a blocked node returns reversed; one leaving through x < 0 returns
     reversed with the moving-wall term; one leaving through x >= nx returns
-    as 2 w rho_out minus itself.  Then collide with Eq. 5."""
+    as twice the even part of the equilibrium at rho_out = 1 (with the
+    velocity u* of the node's stored state) minus itself.  Then collide with
+    Eq. 5."""
     ny, nx = cls.shape
     q = len(w)
     N = nx * ny
@@ -390,7 +392,11 @@ def _push_fluid(cls, f, tau, u_in, c, w, opp):
                 if tx < 0:
                     arr[j, n] = p + 6 * w[j] * c[j, 0] * u_in
                 elif tx >= nx:
-                    arr[j, n] = -p + 2 * w[j] * 1.0
+                    rs = f[:, n].sum()
+                    usx = sum(c[k, 0] * f[k, n] for k in range(q)) / rs
+                    usy = sum(c[k, 1] * f[k, n] for k in range(q)) / rs
+                    cu = c[j, 0] * usx + c[j, 1] * usy
+                    arr[j, n] = -p + 2 * w[j] * 1.0 * (1 + 4.5 * cu * cu - 1.5 * (usx ** 2 + usy ** 2))
                 elif ty < 0 or ty >= ny or cls[ty, tx] != O.FLUID:
                     arr[j, n] = p
                 else:
