@@ -469,13 +469,18 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 }
 
 /* Steady-state driver shared by both solvers' loops: residual bookkeeping.
- * Reading of "run until an equilibrium is reached" (Sec. 3): the residual
- * r(t) = max over active nodes and components of |X(t) - X(t-1)| / scale is
- * evaluated at t = K, 2K, ...; stop at the first check with r <= tol (OK),
+ * Reading of "run until an equilibrium is reached" (Sec. 3): at checks
+ * t = K, 2K, ... the residual is the largest change per step over the check
+ * interval, r(t) = max over active nodes and components of
+ * |X(t) - X(t-K)| / (K * scale), X the moments of the stored state (X(0)
+ * those of the starting state).  Stop at the first check with r <= tol (OK),
  * at t >= max_iter (NOT_CONVERGED), on NaN/Inf or |u| > 0.3 (DIVERGED), or
  * after stall_checks consecutive checks without a new minimum of r
  * (STALLED: a round-off floor above tol).  stall_checks <= 0 disables the
- * stall test. */
+ * stall test.  (A single-step difference is not used: dead-end pore nodes
+ * keep an undamped momentum that bounce-back reverses every step, so in
+ * reduced precision the one-step change never settles although the field
+ * does.) */
 typedef struct {
     double best;
     int since_best;
@@ -507,7 +512,7 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                     int64_t *iters, double *residual)
 {
     orc_lattice L;
-    if (make_lattice(lat_id, &L) || check_every < 2 || max_iter < 1)
+    if (make_lattice(lat_id, &L) || check_every < 1 || max_iter < 1)
         return ORC_EINVAL;
     const int64_t N = (int64_t)nx * ny * nz;
     const int K = check_every;
@@ -525,16 +530,15 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
+    orc_fluid_moments(lat_id, nx, ny, nz, cls, NULL, f, Uprev, NULL);
     for (;;) {
-        int need_u = ((t + 1) % K == K - 1) || ((t + 1) % K == 0);
+        int need_u = (t + 1) % K == 0;
         orc_fluid_step(lat_id, nx, ny, nz, cls, tau, u_in, NULL, NULL, a, b,
                        need_u ? Ucur : NULL, NULL);
         double *tmp = a;
         a = b;
         b = tmp;
         t++;
-        if (t % K == K - 1)
-            memcpy(Uprev, Ucur, sizeof(double) * L.dim * N);
         if (t % K == 0) {
             double rmax = 0.0, umax = 0.0;
             int bad = 0;
@@ -545,13 +549,14 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                     double v = Ucur[d * N + n];
                     if (isnan(v) || isinf(v))
                         bad = 1;
-                    double dv = fabs(v - Uprev[d * N + n]) / fabs(u_in);
+                    double dv = fabs(v - Uprev[d * N + n]) / ((double)K * fabs(u_in));
                     if (dv > rmax)
                         rmax = dv;
                     if (fabs(v) > umax)
                         umax = fabs(v);
                 }
             }
+            memcpy(Uprev, Ucur, sizeof(double) * L.dim * N);
             r = bad ? NAN : rmax;
             int dec = residual_decide(r, umax, tol, &st);
             if (dec != -100) {
@@ -771,7 +776,7 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                  int64_t *iters, double *residual)
 {
     orc_lattice L;
-    if (make_lattice(lat_id, &L) || check_every < 2 || max_iter < 1)
+    if (make_lattice(lat_id, &L) || check_every < 1 || max_iter < 1)
         return ORC_EINVAL;
     const int64_t N = (int64_t)nx * ny * nz;
     const int K = check_every;
@@ -789,16 +794,15 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
+    orc_ad_moment(lat_id, nx, ny, nz, cls, k_sink, g, Cprev);
     for (;;) {
-        int need_c = ((t + 1) % K == K - 1) || ((t + 1) % K == 0);
+        int need_c = (t + 1) % K == 0;
         orc_ad_step(lat_id, nx, ny, nz, cls, D, c_in, k_sink, outlet_mode,
                     c_out, NULL, u, a, b, need_c ? Ccur : NULL);
         double *tmp = a;
         a = b;
         b = tmp;
         t++;
-        if (t % K == K - 1)
-            memcpy(Cprev, Ccur, sizeof(double) * N);
         if (t % K == 0) {
             double rmax = 0.0;
             int bad = 0;
@@ -808,10 +812,11 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                 double v = Ccur[n];
                 if (isnan(v) || isinf(v))
                     bad = 1;
-                double dv = fabs(v - Cprev[n]) / fabs(c_in);
+                double dv = fabs(v - Cprev[n]) / ((double)K * fabs(c_in));
                 if (dv > rmax)
                     rmax = dv;
             }
+            memcpy(Cprev, Ccur, sizeof(double) * N);
             r = bad ? NAN : rmax;
             int dec = residual_decide(r, 0.0, tol, &st);
             if (dec != -100) {

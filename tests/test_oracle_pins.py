@@ -147,7 +147,7 @@ def test_channel_inlet_outlet_develops_parabola():
     assert np.abs(ux - par).max() / par.max() < 1e-2
     fin, fout = O.fluid_fluxes(cls, r["f"], uin)
     assert fin == pytest.approx(uin * (ny - 2), rel=1e-14)   # exactly u_in per inlet node
-    assert abs(fout - fin) / fin < 1e-7
+    assert abs(fout - fin) / fin < 1e-6   # residual level: tol 1e-8 per step over ~200 columns
 
 
 def _porous(nx, ny, seed, frac=0.3):
