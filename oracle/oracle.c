@@ -475,16 +475,18 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  * |X(t) - X(t-K)| / (K * scale), X the moments of the stored state (X(0)
  * those of the starting state).  Stop at the first check with r <= tol (OK),
  * at t >= max_iter (NOT_CONVERGED), on NaN/Inf or |u| > 0.3 (DIVERGED), or
- * after stall_checks consecutive checks without a new minimum of r
- * (STALLED: a round-off floor above tol).  stall_checks <= 0 disables the
- * stall test.  (A single-step difference is not used: dead-end pore nodes
+ * after stall_checks consecutive checks that set neither a new maximum of r
+ * nor a new minimum since the last maximum (STALLED: the residual sits flat
+ * on a round-off floor above tol; a transient that rises before it decays
+ * is not a stall).  stall_checks <= 0 disables the stall test.  (A single-step difference is not used: dead-end pore nodes
  * keep an undamped momentum that bounce-back reverses every step, so in
  * reduced precision the one-step change never settles although the field
  * does.) */
 typedef struct {
-    double best;
+    double best; /* smallest r since the largest */
     int since_best;
     int window;
+    double peak; /* largest r so far */
 } orc_stall;
 
 static int residual_decide(double r, double umax, double tol, orc_stall *st)
@@ -493,7 +495,11 @@ static int residual_decide(double r, double umax, double tol, orc_stall *st)
         return ORC_EDIVERGED;
     if (r <= tol)
         return ORC_OK;
-    if (r < st->best) {
+    if (r > st->peak) {
+        st->peak = r;
+        st->best = r;
+        st->since_best = 0;
+    } else if (r < st->best) {
         st->best = r;
         st->since_best = 0;
     } else {
@@ -526,7 +532,7 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         return ORC_EINVAL;
     }
     double *a = f, *b = fb;
-    orc_stall st = {INFINITY, 0, stall_checks};
+    orc_stall st = {INFINITY, 0, stall_checks, -INFINITY};
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
@@ -790,7 +796,7 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         return ORC_EINVAL;
     }
     double *a = g, *b = gb;
-    orc_stall st = {INFINITY, 0, stall_checks};
+    orc_stall st = {INFINITY, 0, stall_checks, -INFINITY};
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
