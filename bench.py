@@ -122,7 +122,8 @@ def main():
         st, cls, _ = lbm.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
                                         w["overlap"], w["seed"])
     assert st == 0
-    cls = lbm.lbm_biofilm_layer(cls)
+    if w.get("layer", True):
+        cls = lbm.lbm_biofilm_layer(cls)
     max_iter = args.max_iter or w["max_iter"]
     ctx = lbm.lbm_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],

@@ -117,7 +117,8 @@ typedef struct {
     double c_out;         /* outlet value for LBM_OUT_DIRICHLET */
     int32_t storage;      /* lbm_storage */
     int32_t check_every;  /* residual cadence K, even and >= 2 (100 if 0) */
-    int32_t stall_checks; /* stall window in checks (100 if 0; < 0 disables) */
+    int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
+                             1000 otherwise; < 0 disables */
 } lbm_params;
 
 typedef struct {
@@ -215,17 +216,20 @@ void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
 
 /* ---------------------------------------------------- one-shot solves */
 /* Steady fluid flow (Sec. 2.1.1) from rest on the mask cls (host uint8 [N]),
- * run until the residual max|U(t) - U(t-1)| / |u_in| over FLUID nodes,
- * evaluated every 100 steps, is <= tol, or max_iter steps.  u_out: host
- * double [dim][N] (0 on blocked nodes).  info may be NULL. */
+ * run until the residual -- the largest velocity change per step over the
+ * check interval K = 100, max |U(t) - U(t-K)| / (K |u_in|) over FLUID
+ * nodes, evaluated at t = K, 2K, ... -- is <= tol, or max_iter steps.
+ * Also stops on NaN/Inf or |u| > 0.3 (EDIVERGED) and after stall_checks
+ * checks without a new residual minimum (STALLED).  u_out: host double
+ * [dim][N] (0 on blocked nodes).  info may be NULL. */
 lbm_status lbm_fluid_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
                             double u_in, double tol, int64_t max_iter, int storage,
                             double *u_out, lbm_info *info);
 
 /* Steady substrate field (Sec. 2.1.2) in the frozen velocity u (host double
  * [dim][N]), started from equilibrium at c_in; residual
- * max|C(t) - C(t-1)| / |c_in| over FLUID and BIOFILM nodes.  c_field:
- * host double [N] (0 on SOLID/WALL).  info may be NULL. */
+ * max |C(t) - C(t-K)| / (K |c_in|) over FLUID and BIOFILM nodes.
+ * c_field: host double [N] (0 on SOLID/WALL).  info may be NULL. */
 lbm_status lbm_ad_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const double *u,
                          double D, double c_in, double k_sink, int outlet, double c_out,
                          double tol, int64_t max_iter, int storage, double *c_field,

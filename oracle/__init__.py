@@ -190,7 +190,7 @@ def fluid_fluxes(cls, f, u_in, lat=None):
     return a.value, b.value
 
 
-STALL_CHECKS = 100
+STALL_CHECKS = 1000
 
 
 def fluid_solve(cls, tau, u_in, tol, max_iter, check_every=100, f=None, lat=None,

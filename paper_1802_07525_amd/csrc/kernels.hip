@@ -15,11 +15,13 @@
 //    renumbered so that each of the eight XCDs receives a contiguous band of
 //    tiles: neighbouring rows meet in the same L2.
 //  * Storage policies: FP64; FP32; FP32 or FP16 holding the shifted value
-//    h = f - w_i * ref.  Arithmetic is FP32 for the FP32/FP16 forms.
-//  * Residual checks are fused into the step kernel: on the step before a
-//    check the kernel stores U (or C); on the check step it takes
-//    max |U(t) - U(t-1)| in FP64, reduces it across the wave with shuffles,
-//    across the block in LDS, and commits one 64-bit atomic max per block.
+//    h = f - w_i * ref.  Arithmetic is FP32 for the FP32/FP16 forms; FP16
+//    stores round stochastically (see pop_value).
+//  * Residual checks are fused into the step kernel: on a check step it takes
+//    max |U(t) - U(t-K)| / K in FP64 against the moments saved at the
+//    previous check (and saves the new ones), reduces it across the wave
+//    with shuffles, across the block in LDS, and commits one 64-bit atomic
+//    max per block.
 //  * Every step kernel starts by reading the control word and returns when a
 //    stop has been decided, so the host may queue steps ahead of decisions.
 #include "lbm_kernels.h"
@@ -107,6 +109,54 @@ __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
 {
     *p = static_cast<typename S::T>(v);
 }
+// Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a
+// node, a direction and a step.
+__device__ __forceinline__ unsigned int sr_hash(unsigned int n, unsigned int i, unsigned int t)
+{
+    unsigned int x = n * 0x9E3779B1u ^ i * 0x85EBCA77u ^ t * 0xC2B2AE3Du;
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Stored value of a population.  FP16 storage rounds stochastically: the 13
+// float mantissa bits below the FP16 mantissa get a uniform random addend
+// before they are cut, so a value is rounded up with probability equal to
+// its fraction of an FP16 ulp.  Near a steady state round-to-nearest would
+// repeat the same error every step -- a constant source that slow modes
+// amplify by their relaxation time -- while these errors average to zero.
+// The addend comes from a hash of (node, direction, step): runs are
+// reproducible.  (Values below the FP16 normal range, |v| < 2^-14, get the
+// remaining bits rounded to nearest by the conversion.)
+template <class S>
+__device__ __forceinline__ typename S::T pop_value(typename S::C v, unsigned int n, unsigned int i,
+                                                   unsigned int t)
+{
+    if constexpr (sizeof(typename S::T) == 2) {
+        unsigned int b = __float_as_uint(v);
+        b = (b + (sr_hash(n, i, t) & 0x1FFFu)) & ~0x1FFFu;
+        return static_cast<typename S::T>(__uint_as_float(b));
+    } else {
+        return static_cast<typename S::T>(v);
+    }
+}
+
+// Streaming store for domains far larger than the last-level cache: the
+// next step reads these values from HBM anyway, so they need not displace
+// cached data on the way.
+template <class S, bool NT>
+__device__ __forceinline__ void st_pop(typename S::T *p, typename S::C v, unsigned int n,
+                                       unsigned int i, unsigned int t)
+{
+    const typename S::T h = pop_value<S>(v, n, i, t);
+    if constexpr (NT)
+        __builtin_nontemporal_store(h, p);
+    else
+        *p = h;
+}
 
 // Contiguous band of tiles per XCD: hardware block b runs on XCD b mod 8.
 __device__ __forceinline__ int xcd_tile(int b, int nb)
@@ -176,10 +226,12 @@ __device__ __forceinline__ unsigned long long dbits(double v)
 // ------------------------------------------------------------ fluid step
 // Pull rules per direction i (source s = n - c_i), first match wins:
 //   inlet  (x == 0, c_ix = +1):   h_i = h*_opp(n) + 6 w_i u_in
-//   outlet (x == nx-1, c_ix = -1): h_i = -h*_opp(n) + 2 w_i (rho_out - shift)
+//   outlet (x == nx-1, c_ix = -1): h_i = -h*_opp(n) + 2 w_i (rho_out (1 + P_i) - shift),
+//       P_i = 9/2 (c_i.u*)^2 - 3/2 u*^2 with u* the velocity of this node's
+//       stored state (twice the even part of the equilibrium, rho_out = 1)
 //   blocked source (descriptor bit): h_i = h*_opp(n)     (Eq. 11, half-way)
 //   otherwise:                      h_i = h*_i(s)         (streaming)
-template <class L, class S, class DT, int MODE>
+template <class L, class S, class DT, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 {
     typedef typename S::T T;
@@ -195,25 +247,53 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
     C ux = C(0), uy = C(0), uz = C(0);
     if (act) {
         const long long n = p.n;
+        // One unconditional load per direction from a selected address (the
+        // source node, or this node's opposite population when the link is
+        // reversed), then the inlet/outlet terms by select: the loads carry no
+        // branches between them and issue back to back.
+        const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
+        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
+        C ox = C(0), oy = C(0), oz = C(0); // u* of the stored state (outlet column)
+        if (xout) {
+            C r = C(0), qx = C(0), qy = C(0), qz = C(0);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const C v = ld<S>(src + (long long)i * N + n);
+                r += v;
+                if (L::cx[i] == 1) qx += v;
+                if (L::cx[i] == -1) qx -= v;
+                if (L::cy[i] == 1) qy += v;
+                if (L::cy[i] == -1) qy -= v;
+                if (L::cz[i] == 1) qz += v;
+                if (L::cz[i] == -1) qz -= v;
+            }
+            const C ir = C(1) / (S::shifted ? C(1) + r : r);
+            ox = qx * ir;
+            oy = qy * ir;
+            oz = qz * ir;
+        }
+        const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
         C f[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
             if (i == 0) {
                 f[0] = ld<S>(src + n);
-            } else {
-                const T *so = src + (long long)o * N + n;
-                if (cx == 1 && p.x == 0) {
-                    f[i] = ld<S>(so) + C(6.0 * L::w[i]) * C(a.u_in);
-                } else if (cx == -1 && p.x == a.g.nx - 1) {
-                    f[i] = (S::shifted ? C(0) : C(2.0 * L::w[i])) - ld<S>(so);
-                } else if (d & (DT(1) << i)) {
-                    f[i] = ld<S>(so);
-                } else {
-                    const long long off = cx + (long long)a.g.nx * (cy + (long long)a.g.ny * cz);
-                    f[i] = ld<S>(src + (long long)i * N + n - off);
-                }
+                continue;
             }
+            const bool in_i = cx == 1 && xin, out_i = cx == -1 && xout;
+            const bool rev = in_i || out_i || ((d >> i) & DT(1));
+            const long long off = cx + cy * row + cz * plane;
+            const long long idx = rev ? (long long)o * N + n : (long long)i * N + n - off;
+            C v = ld<S>(src + idx);
+            if (cx == 1)
+                v = in_i ? v + C(6.0 * L::w[i]) * C(a.u_in) : v;
+            if (cx == -1) {
+                const C cu = -ox + C(cy) * oy + C(cz) * oz;
+                const C even = C(4.5) * cu * cu - ousq;
+                v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(0) : C(1)) + even) - v : v;
+            }
+            f[i] = v;
         }
         C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -246,26 +326,14 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
             // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
             // minus the shift w_i when stored shifted (rs = rho - shift).
             const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
-            st<S>(dst + (long long)i * N + n, f[i] + om * (feq - f[i]));
-        }
-    }
-    if constexpr (MODE == MODE_STORE) {
-        if (act) {
-            C *up = static_cast<C *>(a.uprev);
-            up[p.n] = ux;
-            up[N + p.n] = uy;
-            if (L::DIM == 3)
-                up[2 * N + p.n] = uz;
-        }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.ctrl->res_bits = 0ull;
-            a.ctrl->umax_bits = 0ull;
+            st_pop<S, NT>(dst + (long long)i * N + n, f[i] + om * (feq - f[i]), (unsigned int)n, i,
+                          a.step);
         }
     }
     if constexpr (MODE == MODE_CHECK) {
         unsigned long long rb = 0ull, ub = 0ull;
         if (act) {
-            const C *up = static_cast<const C *>(a.uprev);
+            C *up = static_cast<C *>(a.uprev);
             double dm = fabs((double)ux - (double)up[p.n]);
             double t = fabs((double)uy - (double)up[N + p.n]);
             dm = (t > dm || t != t) ? t : dm;
@@ -279,6 +347,10 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
                 dm = um = __longlong_as_double(0x7ff8000000000000ll);
             rb = dbits(dm * a.inv_uin);
             ub = dbits(um);
+            up[p.n] = ux;
+            up[N + p.n] = uy;
+            if (L::DIM == 3)
+                up[2 * N + p.n] = uz;
         }
         block_max_commit(rb, ub, &a.ctrl->res_bits, &a.ctrl->umax_bits);
     }
@@ -293,7 +365,7 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 //   otherwise:                     h_i = h*_i(s)
 // Collision (Eq. 12) with the linear equilibrium w_i C (1 + c_i.u / c_s^2)
 // and the biofilm consumption - w_i k C.
-template <class L, int QF, class S, class DT, int MODE>
+template <class L, int QF, class S, class DT, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
 {
     typedef typename S::T T;
@@ -312,26 +384,30 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
     C cfull = C(0);
     if (act) {
         const long long n = p.n;
+        const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
+        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
         C g[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
             if (i == 0) {
                 g[0] = ld<S>(src + n);
-            } else {
-                const T *so = src + (long long)o * N + n;
-                if (cx == 1 && p.x == 0) {
-                    g[i] = C(2.0 * L::w[i] * a.cin_s) - ld<S>(so);
-                } else if (cx == -1 && p.x == a.g.nx - 1) {
-                    g[i] = a.outlet ? C(2.0 * L::w[i] * a.cout_s) - ld<S>(so)
-                                    : ld<S>(src + (long long)i * N + n);
-                } else if ((d >> (LNK + i)) & DT(1)) {
-                    g[i] = ld<S>(so);
-                } else {
-                    const long long off = cx + (long long)a.g.nx * (cy + (long long)a.g.ny * cz);
-                    g[i] = ld<S>(src + (long long)i * N + n - off);
-                }
+                continue;
             }
+            const bool in_i = cx == 1 && xin;
+            // zero-gradient outlet copies this node's own population i
+            const bool copy_i = cx == -1 && xout && !a.outlet;
+            const bool abb_i = cx == -1 && xout && a.outlet;
+            const bool rev = in_i || abb_i || ((d >> (LNK + i)) & DT(1));
+            const long long off = cx + cy * row + cz * plane;
+            const long long idx = rev ? (long long)o * N + n
+                                      : (copy_i ? (long long)i * N + n : (long long)i * N + n - off);
+            C v = ld<S>(src + idx);
+            if (cx == 1)
+                v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
+            if (cx == -1)
+                v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
+            g[i] = v;
         }
         C cs = C(0);
 #pragma unroll
@@ -353,24 +429,19 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
             if (L::cz[i] == 1) cu += uz;
             if (L::cz[i] == -1) cu -= uz;
             const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
-            st<S>(dst + (long long)i * N + n, g[i] + om * (geq - g[i]) - C(L::w[i]) * kc);
-        }
-    }
-    if constexpr (MODE == MODE_STORE) {
-        if (act)
-            static_cast<C *>(a.cprev)[p.n] = cfull;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.ctrl->res_bits = 0ull;
-            a.ctrl->umax_bits = 0ull;
+            st_pop<S, NT>(dst + (long long)i * N + n, g[i] + om * (geq - g[i]) - C(L::w[i]) * kc,
+                          (unsigned int)n, 32u + i, a.step);
         }
     }
     if constexpr (MODE == MODE_CHECK) {
         unsigned long long rb = 0ull;
         if (act) {
-            double dv = fabs((double)cfull - (double)static_cast<const C *>(a.cprev)[p.n]);
+            C *cp = static_cast<C *>(a.cprev);
+            double dv = fabs((double)cfull - (double)cp[p.n]);
             if (cfull != cfull)
                 dv = __longlong_as_double(0x7ff8000000000000ll);
             rb = dbits(dv * a.inv_cin);
+            cp[p.n] = cfull;
         }
         block_max_commit(rb, 0ull, &a.ctrl->res_bits, &a.ctrl->umax_bits);
     }
@@ -452,10 +523,10 @@ __global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, co
         RHO[n] = rho;
 }
 
-template <class L, int QF, class S, class DT>
+template <class L, int QF, class S, class DT, class O>
 __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, const DT *desc,
                                                     long long N, double c_ref, double k_sink,
-                                                    double *Cout)
+                                                    O *Cout)
 {
     constexpr int ACT = QF - 1 + L::Q;
     constexpr int BIO = ACT + 1;
@@ -464,17 +535,17 @@ __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, cons
         return;
     const DT d = desc[n];
     if (!((d >> ACT) & DT(1))) {
-        Cout[n] = 0.0;
+        Cout[n] = O(0);
         return;
     }
-    double s = 0.0;
+    O s = O(0);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        s += static_cast<double>(gp[(long long)i * N + n]);
+        s += static_cast<O>(gp[(long long)i * N + n]);
     if (S::shifted)
-        s += c_ref;
-    const double k = ((d >> BIO) & DT(1)) ? k_sink : 0.0;
-    Cout[n] = s / (1.0 - k);
+        s += O(c_ref);
+    const O k = ((d >> BIO) & DT(1)) ? O(k_sink) : O(0);
+    Cout[n] = s / (O(1) - k);
 }
 
 template <class L, class S, class DT>
@@ -553,6 +624,17 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
         }
         const DT d = desc[n];
         if (f && (d & DT(1)) && (x == 0 || x == g.nx - 1)) {
+            double r = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+#pragma unroll
+            for (int k = 0; k < LF::Q; ++k) {
+                const double v = static_cast<double>(f[(long long)k * N + n]) + fs * LF::w[k];
+                r += v;
+                qx += LF::cx[k] * v;
+                qy += LF::cy[k] * v;
+                qz += LF::cz[k] * v;
+            }
+            const double ux = qx / r, uy = qy / r, uz = qz / r;
+            const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
             for (int i = 1; i < LF::Q; ++i) {
                 const int o = LF::op[i];
@@ -562,7 +644,8 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                     acc[0] += incoming - fo;
                 }
                 if (x == g.nx - 1 && LF::cx[i] == -1) {
-                    const double incoming = -fo + 2.0 * LF::w[i];
+                    const double cu = LF::cx[i] * ux + LF::cy[i] * uy + LF::cz[i] * uz;
+                    const double incoming = -fo + 2.0 * LF::w[i] * (1.0 + 4.5 * cu * cu - 1.5 * uu);
                     acc[1] += fo - incoming;
                 }
             }
@@ -627,6 +710,7 @@ __global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int 
         c->umax_bits = 0ull;
         c->tol = tol;
         c->best = __longlong_as_double(0x7ff0000000000000ll); // +inf
+        c->peak = __longlong_as_double((long long)0xfff0000000000000ull); // -inf
         c->r_last = __longlong_as_double(0x7ff8000000000000ll);
         c->t = 0;
         c->t_stop = -1;
@@ -640,7 +724,8 @@ __global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int 
 }
 
 // After a check step: OK at r <= tol; DIVERGED on NaN/Inf or |u| > 0.3
-// (fluid); STALLED after `window` checks without a new minimum.
+// (fluid); STALLED after `window` checks that set neither a new maximum of
+// r nor a new minimum since the last maximum (a flat round-off floor).
 __global__ void k_decide(Ctrl *c)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0 || c->stop != STOP_RUN)
@@ -649,12 +734,18 @@ __global__ void k_decide(Ctrl *c)
     c->checks += 1;
     const double r = __longlong_as_double((long long)c->res_bits);
     const double um = __longlong_as_double((long long)c->umax_bits);
+    c->res_bits = 0ull; // re-arm the maxima for the next check
+    c->umax_bits = 0ull;
     c->r_last = r;
     int stop = STOP_RUN;
     if (r != r || isinf(r) || um != um || (c->is_fluid && um > 0.3)) {
         stop = STOP_DIVERGED;
     } else if (r <= c->tol) {
         stop = STOP_OK;
+    } else if (r > c->peak) {
+        c->peak = r;
+        c->best = r;
+        c->since_best = 0;
     } else if (r < c->best) {
         c->best = r;
         c->since_best = 0;
@@ -669,11 +760,25 @@ __global__ void k_decide(Ctrl *c)
     }
 }
 
+// Plain streaming copy used to calibrate bandwidth and counters: each block
+// moves 16 KiB (four 16-byte vectors per thread, all loads issued first).
 __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src,
                                               float4 *__restrict__ dst, long long n4)
 {
-    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n4; i += (long long)gridDim.x * 256)
-        dst[i] = src[i];
+    const long long base = blockIdx.x * 1024ll + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long i = base + 256ll * k;
+        if (i < n4)
+            v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long i = base + 256ll * k;
+        if (i < n4)
+            dst[i] = v[k];
+    }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -749,12 +854,19 @@ hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStr
             typedef decltype(s) S;
             typedef decltype(dt) DT;
             dim3 grid(a.g.ntiles), block(256);
-            if (mode == MODE_STORE)
-                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_STORE>), grid, block, 0, st, a);
-            else if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_CHECK>), grid, block, 0, st, a);
+            const bool nt = a.streaming_stores != 0;
+#define LBM_FLUID_LAUNCH(M)                                                                       \
+    do {                                                                                          \
+        if (nt)                                                                                   \
+            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, true>), grid, block, 0, st, a);      \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, false>), grid, block, 0, st, a);     \
+    } while (0)
+            if (mode == MODE_CHECK)
+                LBM_FLUID_LAUNCH(MODE_CHECK);
             else
-                hipLaunchKernelGGL((k_fluid_step<LF, S, DT, MODE_PLAIN>), grid, block, 0, st, a);
+                LBM_FLUID_LAUNCH(MODE_PLAIN);
+#undef LBM_FLUID_LAUNCH
             return hipGetLastError();
         });
     });
@@ -769,12 +881,19 @@ hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t 
             typedef decltype(s) S;
             typedef decltype(dt) DT;
             dim3 grid(a.g.ntiles), block(256);
-            if (mode == MODE_STORE)
-                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_STORE>), grid, block, 0, st, a);
-            else if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_CHECK>), grid, block, 0, st, a);
+            const bool nt = a.streaming_stores != 0;
+#define LBM_AD_LAUNCH(M)                                                                          \
+    do {                                                                                          \
+        if (nt)                                                                                   \
+            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, true>), grid, block, 0, st, a);  \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, false>), grid, block, 0, st, a); \
+    } while (0)
+            if (mode == MODE_CHECK)
+                LBM_AD_LAUNCH(MODE_CHECK);
             else
-                hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, MODE_PLAIN>), grid, block, 0, st, a);
+                LBM_AD_LAUNCH(MODE_PLAIN);
+#undef LBM_AD_LAUNCH
             return hipGetLastError();
         });
     });
@@ -838,7 +957,7 @@ hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, c
 }
 
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     double c_ref, double k_sink, double *C, hipStream_t st)
+                     double c_ref, double k_sink, void *C, int out_double, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -846,9 +965,18 @@ hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, con
             typedef decltype(la) LA;
             typedef decltype(s) S;
             typedef decltype(dt) DT;
-            hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT>), flat_grid(g.N), dim3(256), 0, st,
-                               static_cast<const typename S::T *>(gp),
-                               static_cast<const DT *>(desc), g.N, c_ref, k_sink, C);
+            typedef typename S::C CT;
+            const double ref = S::shifted ? c_ref : 0.0;
+            if (out_double)
+                hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, double>), flat_grid(g.N), dim3(256),
+                                   0, st, static_cast<const typename S::T *>(gp),
+                                   static_cast<const DT *>(desc), g.N, ref, k_sink,
+                                   static_cast<double *>(C));
+            else
+                hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, CT>), flat_grid(g.N), dim3(256), 0,
+                                   st, static_cast<const typename S::T *>(gp),
+                                   static_cast<const DT *>(desc), g.N, ref, k_sink,
+                                   static_cast<CT *>(C));
             return hipGetLastError();
         });
     });
@@ -950,9 +1078,7 @@ hipError_t decide(Ctrl *c, hipStream_t st)
 hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st)
 {
     const long long n4 = (long long)(bytes / 16);
-    long long blocks = (n4 + 255) / 256;
-    if (blocks > 256 * 64)
-        blocks = 256 * 64;
+    const long long blocks = (n4 + 1023) / 1024;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st,
                        static_cast<const float4 *>(src), static_cast<float4 *>(dst), n4);
     return hipGetLastError();

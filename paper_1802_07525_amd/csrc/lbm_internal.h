@@ -73,6 +73,9 @@ struct lbm_solver {
     double *d_vals = nullptr;
     int fcur = 0, gcur = 0;
     bool fluid_ready = false, ad_ready = false;
+    // steps taken so far by each solver (seeds the FP16 stochastic rounding;
+    // saved in checkpoints so that a resumed run continues bit-exactly)
+    unsigned long long fsteps = 0, gsteps = 0;
 
     lbmk::Ctrl *h_ctrl = nullptr; // pinned ring of control snapshots
     hipEvent_t ev_ring[8] = {};

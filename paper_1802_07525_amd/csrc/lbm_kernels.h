@@ -12,7 +12,7 @@
 namespace lbmk {
 
 enum { ST_F32 = 0, ST_F32S = 1, ST_F16S = 2, ST_F64 = 3 };
-enum { MODE_PLAIN = 0, MODE_STORE = 1, MODE_CHECK = 2 };
+enum { MODE_PLAIN = 0, MODE_CHECK = 2 };
 enum { STOP_RUN = 0, STOP_OK = 1, STOP_STALLED = 2, STOP_DIVERGED = 3 };
 
 // Per-solve control block in device memory.  The step kernels read `stop`
@@ -33,6 +33,7 @@ struct Ctrl {
     int is_fluid;                 // apply the |u| > 0.3 divergence test
     int K;                        // steps per check
     int pad;
+    double peak;                  // largest residual so far
 };
 
 // Domain geometry as the kernels see it.  Tiles are 64 x 4 nodes (one
@@ -60,12 +61,14 @@ struct FluidArgs {
     const void *src;
     void *dst;
     const void *desc;
-    void *uprev;    // compute-type [dim][N] velocity kept for the residual
+    void *uprev;    // compute-type [dim][N] velocity saved at the previous check
     Ctrl *ctrl;
     Geo g;
     double omega;   // 1 / tau
     double u_in;
-    double inv_uin; // 1 / |u_in|
+    double inv_uin; // 1 / (K |u_in|): residual scale
+    int streaming_stores; // 1: non-temporal population stores (large domains)
+    unsigned int step;    // step counter of this solver (stochastic rounding)
 };
 
 struct AdArgs {
@@ -73,7 +76,7 @@ struct AdArgs {
     void *dst;
     const void *desc;
     const void *u;  // compute-type [dim][N] frozen velocity
-    void *cprev;    // compute-type [N] concentration kept for the residual
+    void *cprev;    // compute-type [N] concentration saved at the previous check
     Ctrl *ctrl;
     Geo g;
     double omega;   // 1 / tau_D
@@ -81,8 +84,10 @@ struct AdArgs {
     double cout_s;  // c_out - shift reference
     double c_ref;   // shift reference (0 when unshifted)
     double k_sink;
-    double inv_cin; // 1 / |c_in|
+    double inv_cin; // 1 / (K |c_in|): residual scale
     int outlet;     // 0 zero-gradient, 1 Dirichlet
+    int streaming_stores; // 1: non-temporal population stores (large domains)
+    unsigned int step;    // step counter of this solver (stochastic rounding)
 };
 
 size_t storage_bytes(int storage);  // bytes per stored population
@@ -103,9 +108,9 @@ hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void 
 // output type (double, else the compute type); RHO may be null.
 hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
                         void *U, void *RHO, int out_double, hipStream_t st);
-// Concentration of a stored substrate state, as double.
+// Concentration of a stored substrate state (double, or the compute type).
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     double c_ref, double k_sink, double *C, hipStream_t st);
+                     double c_ref, double k_sink, void *C, int out_double, hipStream_t st);
 
 // Stored populations <-> unshifted double [Q][N] (0 on inactive nodes).
 hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,

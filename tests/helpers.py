@@ -15,7 +15,8 @@ def masks(w, lib=None):
         st, b, _ = O.geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
                                 w["overlap"], w["seed"])
     assert st == "OK"
-    b = O.biofilm_layer(b)
+    if w.get("layer", True):
+        b = O.biofilm_layer(b)
     if lib is not None:
         if w["nz"] > 1:
             s2, a, _ = lib.lbm_geom_fibres(w["nx"], w["ny"], w["nz"], w["r_min"], w["r_max"],
@@ -24,7 +25,8 @@ def masks(w, lib=None):
             s2, a, _ = lib.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
                                           w["overlap"], w["seed"])
         assert s2 == 0
-        a = lib.lbm_biofilm_layer(a)
+        if w.get("layer", True):
+            a = lib.lbm_biofilm_layer(a)
         assert np.array_equal(a, b)
     return b
 
