@@ -186,12 +186,13 @@ __device__ __forceinline__ NodePos tile_node(const Geo &g)
     return p;
 }
 
-// max over the block of two non-negative FP64 values given as bit patterns
-// (ordering of the bits equals ordering of the values; NaN sorts last),
-// committed with one atomic per block.
+// Max over the block of two non-negative FP64 values given as bit patterns
+// (ordering of the bits equals ordering of the values; NaN sorts last):
+// shuffles within each wave, LDS across the four waves, and one plain store
+// per block into its own slot (part[b], part[nb + b]) -- no contended
+// atomics; the decide kernel reduces the slots.
 __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned long long b,
-                                                 unsigned long long *da,
-                                                 unsigned long long *db)
+                                                 unsigned long long *part)
 {
     __shared__ unsigned long long sa[4], sb[4];
 #pragma unroll
@@ -213,8 +214,8 @@ __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned 
             ma = sa[k] > ma ? sa[k] : ma;
             mb = sb[k] > mb ? sb[k] : mb;
         }
-        atomicMax(da, ma);
-        atomicMax(db, mb);
+        part[blockIdx.x] = ma;
+        part[gridDim.x + blockIdx.x] = mb;
     }
 }
 
@@ -352,7 +353,7 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
             if (L::DIM == 3)
                 up[2 * N + p.n] = uz;
         }
-        block_max_commit(rb, ub, &a.ctrl->res_bits, &a.ctrl->umax_bits);
+        block_max_commit(rb, ub, a.ctrl->part);
     }
 }
 
@@ -443,7 +444,7 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
             rb = dbits(dv * a.inv_cin);
             cp[p.n] = cfull;
         }
-        block_max_commit(rb, 0ull, &a.ctrl->res_bits, &a.ctrl->umax_bits);
+        block_max_commit(rb, 0ull, a.ctrl->part);
     }
 }
 
@@ -691,21 +692,28 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
             part[k * gridDim.x + blockIdx.x] = red[k][0];
 }
 
-__global__ void k_flux_final(const double *part, int nb, double *out5)
+// One wave per component: each lane sums a fixed stride of the partials in
+// index order, then a fixed shuffle tree combines the lanes.
+__global__ void __launch_bounds__(320) k_flux_final(const double *part, int nb, double *out5)
 {
-    const int k = threadIdx.x;
-    if (k < 5) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b)
-            s += part[k * nb + b];
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64)
+        s += part[k * nb + b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_down(s, off);
+    if (lane == 0)
         out5[k] = s;
-    }
 }
 
 // ------------------------------------------------------------- control
-__global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K)
+__global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
+                             unsigned long long *part, int nparts)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->part = part;
+        c->nparts = nparts;
         c->res_bits = 0ull;
         c->umax_bits = 0ull;
         c->tol = tol;
@@ -723,19 +731,40 @@ __global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int 
     }
 }
 
-// After a check step: OK at r <= tol; DIVERGED on NaN/Inf or |u| > 0.3
-// (fluid); STALLED after `window` checks that set neither a new maximum of
-// r nor a new minimum since the last maximum (a flat round-off floor).
-__global__ void k_decide(Ctrl *c)
+// After a check step: reduce the per-block maxima, then OK at r <= tol;
+// DIVERGED on NaN/Inf or |u| > 0.3 (fluid); STALLED after `window` checks
+// that set neither a new maximum of r nor a new minimum since the last
+// maximum (a flat round-off floor).
+__global__ void __launch_bounds__(256) k_decide(Ctrl *c)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || c->stop != STOP_RUN)
+    __shared__ unsigned long long sr[256], su[256];
+    if (c->stop != STOP_RUN)
         return;
+    const int np = c->nparts;
+    unsigned long long mr = 0ull, mu = 0ull;
+    for (int b = threadIdx.x; b < np; b += 256) {
+        const unsigned long long r = c->part[b], u = c->part[np + b];
+        mr = r > mr ? r : mr;
+        mu = u > mu ? u : mu;
+    }
+    sr[threadIdx.x] = mr;
+    su[threadIdx.x] = mu;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sr[threadIdx.x] = sr[threadIdx.x + s] > sr[threadIdx.x] ? sr[threadIdx.x + s] : sr[threadIdx.x];
+            su[threadIdx.x] = su[threadIdx.x + s] > su[threadIdx.x] ? su[threadIdx.x + s] : su[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0)
+        return;
+    c->res_bits = sr[0];
+    c->umax_bits = su[0];
     c->t += c->K;
     c->checks += 1;
-    const double r = __longlong_as_double((long long)c->res_bits);
-    const double um = __longlong_as_double((long long)c->umax_bits);
-    c->res_bits = 0ull; // re-arm the maxima for the next check
-    c->umax_bits = 0ull;
+    const double r = __longlong_as_double((long long)sr[0]);
+    const double um = __longlong_as_double((long long)su[0]);
     c->r_last = r;
     int stop = STOP_RUN;
     if (r != r || isinf(r) || um != um || (c->is_fluid && um > 0.3)) {
@@ -1059,19 +1088,21 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
     });
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_flux_final, dim3(1), dim3(64), 0, st, partials, (int)FLUX_BLOCKS, out5);
+    hipLaunchKernelGGL(k_flux_final, dim3(1), dim3(320), 0, st, partials, (int)FLUX_BLOCKS, out5);
     return hipGetLastError();
 }
 
-hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, hipStream_t st)
+hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
+                      unsigned long long *part, int nparts, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, tol, window, is_fluid, K);
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, tol, window, is_fluid, K, part,
+                       nparts);
     return hipGetLastError();
 }
 
 hipError_t decide(Ctrl *c, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, st, c);
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, st, c);
     return hipGetLastError();
 }
 

@@ -32,8 +32,9 @@ struct Ctrl {
     int window;                   // stall window in checks (<= 0: off)
     int is_fluid;                 // apply the |u| > 0.3 divergence test
     int K;                        // steps per check
-    int pad;
+    int nparts;                   // blocks of the step grid
     double peak;                  // largest residual so far
+    unsigned long long *part;     // per-block maxima [2 * nparts] of a check step
 };
 
 // Domain geometry as the kernels see it.  Tiles are 64 x 4 nodes (one
@@ -131,7 +132,9 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
                   const Geo &g, double u_in, double c_in, double c_ref, double k_sink,
                   int outlet, double c_out, double *partials, double *out5, hipStream_t st);
 
-hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, hipStream_t st);
+// part: device scratch of 2 * nparts words for the per-block check maxima
+hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
+                      unsigned long long *part, int nparts, hipStream_t st);
 hipError_t decide(Ctrl *c, hipStream_t st);
 
 hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st);

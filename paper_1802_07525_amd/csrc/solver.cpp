@@ -241,7 +241,9 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                            : (s->p.stall_checks > 0 ? s->p.stall_checks
                                                     : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
-    HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K, stream), "ctrl reset");
+    HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
+           "ctrl reset");
     int &cur = which == LBM_SOLVER_FLUID ? s->fcur : s->gcur;
     const int cur0 = cur;
     // moments of the starting state: the reference of the first check
@@ -481,6 +483,10 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
         return fail(st);
     s->d_ctrl = static_cast<lbmk::Ctrl *>(tmp);
     tmp = nullptr;
+    if ((st = dev_alloc(s, &tmp, 4 * sizeof(unsigned long long) * (size_t)s->geo.ntiles, "check maxima")))
+        return fail(st);
+    s->d_part = static_cast<unsigned long long *>(tmp);
+    tmp = nullptr;
     if ((st = dev_alloc(s, &tmp, 5 * lbmk::FLUX_BLOCKS * sizeof(double), "flux partials")))
         return fail(st);
     s->d_partials = static_cast<double *>(tmp);
@@ -512,8 +518,9 @@ void lbm_solver_destroy(lbm_solver *s)
         return;
     (void)hipSetDevice(s->ctx->device);
     (void)hipStreamSynchronize(s->ctx->stream);
-    void *bufs[] = {s->d_desc, s->d_f[0], s->d_f[1], s->d_g[0], s->d_g[1], s->d_u, s->d_uprev,
-                    s->d_cprev, s->d_ctrl, s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals};
+    void *bufs[] = {s->d_desc, s->d_f[0],   s->d_f[1],   s->d_g[0], s->d_g[1],
+                    s->d_u,    s->d_uprev,  s->d_cprev,  s->d_ctrl, s->d_part,
+                    s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -558,7 +565,9 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
         if ((st = init_solver(s, which)))
             return st;
     hipStream_t stream = s->ctx->stream;
-    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every, stream), "ctrl");
+    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
+           "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
     for (int64_t t = 0; t < nsteps; ++t) {
@@ -584,7 +593,9 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
     if (!ready)
         return set_err(s->ctx, LBM_EINVAL, "state not initialised");
     hipStream_t stream = s->ctx->stream;
-    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every, stream), "ctrl");
+    HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
+           "ctrl");
     std::vector<hipEvent_t> ev((size_t)2 * nsteps);
     for (auto &e : ev)
         HIPCHK(hipEventCreate(&e), "event");
