@@ -131,6 +131,13 @@ lbm_status lbm_geom_discs(lbm_grid g, const lbm_disc_params *p, uint64_t seed, u
         int64_t x, y, r;
     };
     std::vector<Disc> placed;
+    // Accepted discs are bucketed by centre on a grid of cell size
+    // 2 r_max + 1: a disc can only clash with discs in its own or the eight
+    // neighbouring cells.  "Any clash" does not depend on the order of the
+    // comparisons, so the result equals that of a scan over all discs.
+    const int64_t cell = 2 * (int64_t)p->r_max + 1;
+    const int64_t gx = (xb - xa) / cell + 1, gy = (yb - ya) / cell + 1;
+    std::vector<std::vector<int32_t>> bucket(p->overlap ? 0 : (size_t)(gx * gy));
     SplitMix64 rng{seed};
     int64_t solid = 0, attempts = 0;
     lbm_status st = LBM_OK;
@@ -145,16 +152,24 @@ lbm_status lbm_geom_discs(lbm_grid g, const lbm_disc_params *p, uint64_t seed, u
         d.y = rng.pick(ya, yb - 1);
         d.r = rng.pick(p->r_min, p->r_max);
         if (!p->overlap) {
+            const int64_t cx = (d.x - xa) / cell, cy = (d.y - ya) / cell;
             bool apart = true;
-            for (const Disc &o : placed) {
-                const int64_t dx = d.x - o.x, dy = d.y - o.y, rr = d.r + o.r;
-                if (dx * dx + dy * dy <= rr * rr) {
-                    apart = false;
-                    break;
+            for (int64_t by = cy - 1; by <= cy + 1 && apart; ++by)
+                for (int64_t bx = cx - 1; bx <= cx + 1 && apart; ++bx) {
+                    if (bx < 0 || by < 0 || bx >= gx || by >= gy)
+                        continue;
+                    for (int32_t k : bucket[(size_t)(bx + gx * by)]) {
+                        const Disc &o = placed[(size_t)k];
+                        const int64_t dx = d.x - o.x, dy = d.y - o.y, rr = d.r + o.r;
+                        if (dx * dx + dy * dy <= rr * rr) {
+                            apart = false;
+                            break;
+                        }
+                    }
                 }
-            }
             if (!apart)
                 continue;
+            bucket[(size_t)(cx + gx * cy)].push_back((int32_t)placed.size());
         }
         placed.push_back(d);
         const int64_t y0 = d.y - d.r < ya ? ya : d.y - d.r, y1 = d.y + d.r >= yb ? yb - 1 : d.y + d.r;

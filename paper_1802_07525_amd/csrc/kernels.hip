@@ -109,17 +109,24 @@ __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
 {
     *p = static_cast<typename S::T>(v);
 }
-// Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a
-// node, a direction and a step.
-__device__ __forceinline__ unsigned int sr_hash(unsigned int n, unsigned int i, unsigned int t)
+// Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a node
+// and a step; each direction then advances a 32-bit linear congruential
+// generator (Knuth's MMIX multiplier, increment 1) from it and uses its top
+// 13 bits.
+__device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
 {
-    unsigned int x = n * 0x9E3779B1u ^ i * 0x85EBCA77u ^ t * 0xC2B2AE3Du;
+    unsigned int x = n * 0x9E3779B1u ^ t * 0xC2B2AE3Du;
     x ^= x >> 16;
     x *= 0x7FEB352Du;
     x ^= x >> 15;
     x *= 0x846CA68Bu;
     x ^= x >> 16;
     return x;
+}
+__device__ __forceinline__ unsigned int sr_next(unsigned int &state)
+{
+    state = state * 1664525u + 1013904223u;
+    return state >> 19;
 }
 
 // Stored value of a population.  FP16 storage rounds stochastically: the 13
@@ -128,16 +135,15 @@ __device__ __forceinline__ unsigned int sr_hash(unsigned int n, unsigned int i, 
 // its fraction of an FP16 ulp.  Near a steady state round-to-nearest would
 // repeat the same error every step -- a constant source that slow modes
 // amplify by their relaxation time -- while these errors average to zero.
-// The addend comes from a hash of (node, direction, step): runs are
+// The addends depend only on (node, step, direction): runs are
 // reproducible.  (Values below the FP16 normal range, |v| < 2^-14, get the
 // remaining bits rounded to nearest by the conversion.)
 template <class S>
-__device__ __forceinline__ typename S::T pop_value(typename S::C v, unsigned int n, unsigned int i,
-                                                   unsigned int t)
+__device__ __forceinline__ typename S::T pop_value(typename S::C v, unsigned int &rng)
 {
     if constexpr (sizeof(typename S::T) == 2) {
         unsigned int b = __float_as_uint(v);
-        b = (b + (sr_hash(n, i, t) & 0x1FFFu)) & ~0x1FFFu;
+        b = (b + sr_next(rng)) & ~0x1FFFu;
         return static_cast<typename S::T>(__uint_as_float(b));
     } else {
         return static_cast<typename S::T>(v);
@@ -148,10 +154,9 @@ __device__ __forceinline__ typename S::T pop_value(typename S::C v, unsigned int
 // next step reads these values from HBM anyway, so they need not displace
 // cached data on the way.
 template <class S, bool NT>
-__device__ __forceinline__ void st_pop(typename S::T *p, typename S::C v, unsigned int n,
-                                       unsigned int i, unsigned int t)
+__device__ __forceinline__ void st_pop(typename S::T *p, typename S::C v, unsigned int &rng)
 {
-    const typename S::T h = pop_value<S>(v, n, i, t);
+    const typename S::T h = pop_value<S>(v, rng);
     if constexpr (NT)
         __builtin_nontemporal_store(h, p);
     else
@@ -246,6 +251,7 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
     C ux = C(0), uy = C(0), uz = C(0);
+    C f[L::Q];
     if (act) {
         const long long n = p.n;
         // One unconditional load per direction from a selected address (the
@@ -274,7 +280,6 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
             oz = qz * ir;
         }
         const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
-        C f[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
@@ -327,9 +332,21 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
             // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
             // minus the shift w_i when stored shifted (rs = rho - shift).
             const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
-            st_pop<S, NT>(dst + (long long)i * N + n, f[i] + om * (feq - f[i]), (unsigned int)n, i,
-                          a.step);
+            f[i] = f[i] + om * (feq - f[i]);
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            f[i] = C(0);
+    }
+    // Every lane of the tile stores (blocked nodes store 0, a value nobody
+    // reads): whole-wave stores write whole cache lines, where lanes masked
+    // off by the geometry would turn stores into partial-line writes.
+    if (p.inb) {
+        unsigned int rng = sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, a.step) : 0u;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_pop<S, NT>(dst + (long long)i * N + p.n, f[i], rng);
     }
     if constexpr (MODE == MODE_CHECK) {
         unsigned long long rb = 0ull, ub = 0ull;
@@ -383,11 +400,11 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
     const T *__restrict__ src = static_cast<const T *>(a.src);
     T *__restrict__ dst = static_cast<T *>(a.dst);
     C cfull = C(0);
+    C g[L::Q];
     if (act) {
         const long long n = p.n;
         const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
         const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
-        C g[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
@@ -430,9 +447,20 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
             if (L::cz[i] == 1) cu += uz;
             if (L::cz[i] == -1) cu -= uz;
             const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
-            st_pop<S, NT>(dst + (long long)i * N + n, g[i] + om * (geq - g[i]) - C(L::w[i]) * kc,
-                          (unsigned int)n, 32u + i, a.step);
+            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            g[i] = C(0);
+    }
+    // whole-wave stores (blocked nodes store 0): see the fluid step
+    if (p.inb) {
+        unsigned int rng =
+            sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, a.step ^ 0x5bd1e995u) : 0u;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_pop<S, NT>(dst + (long long)i * N + p.n, g[i], rng);
     }
     if constexpr (MODE == MODE_CHECK) {
         unsigned long long rb = 0ull;
