@@ -312,6 +312,98 @@ lbm_status lbm_coupled_run(lbm_solver *s, int n_updates, const double *xi, doubl
                            int64_t max_iter, int64_t *picked, double *J, double *J_accum,
                            int64_t *iters_fluid, int64_t *iters_ad);
 
+/* ------------------------------------------------------------- serving */
+/* Continuous batching of 2-D steady solves (D2Q9 fluid, then D2Q5
+ * substrate in the exported velocity) -- the model loop's steps 2 and 3
+ * (Sec. 2) for many independent domains at once, e.g. electrode-geometry
+ * or parameter sweeps.  Requests are admitted in ticket order while a slot
+ * is free and their device footprint (lbm_server_footprint) fits the pool;
+ * every admitted request's populations stay resident and all of them are
+ * stepped by the same kernel launches, each in its own phase, in chunks of
+ * check_every steps captured once as a HIP graph.  A request's arithmetic
+ * is that of lbm_solver_fluid followed by lbm_solver_ad (cold, same
+ * storage, same check cadence and stall window): its results are bit-equal
+ * to that single solve and do not depend on what else is in flight.
+ * max_iter is rounded up to a multiple of check_every.  A fluid solve that
+ * ends NOT_CONVERGED or STALLED still proceeds to the substrate solve; one
+ * that diverges ends the request (c is then 0).
+ * All lbm_server_* calls are thread-safe. */
+typedef struct lbm_server lbm_server;
+
+typedef struct {
+    size_t pool_bytes;     /* device memory for request state, one allocation */
+    int32_t max_slots;     /* requests on the device at once, 1..64 (32 if 0) */
+    int32_t storage;       /* LBM_FP32, LBM_FP32_SHIFTED or LBM_FP16_SHIFTED */
+    int32_t check_every;   /* K: steps per chunk and residual cadence, even (100 if 0) */
+    int32_t stall_checks;  /* as lbm_params */
+    int32_t grid_blocks;   /* workgroups of each batched step launch (2048 if 0) */
+    int32_t inflight;      /* chunks enqueued ahead of the decisions, 1..6 (2 if 0) */
+    int32_t prep_threads;  /* host threads that build masks, 1..16 (2 if 0) */
+    int32_t direct_launch; /* 1: launch each chunk's kernels directly instead of the graph */
+} lbm_server_cfg;
+
+typedef struct {
+    int32_t nx, ny;        /* 2-D grid; the mask rules of lbm_solver_create apply */
+    const uint8_t *cls;    /* host uint8 [nx * ny] classes (copied), or NULL to build */
+    lbm_disc_params discs; /* ... discs with lbm_geom_discs(discs, seed) */
+    uint64_t seed;
+    int32_t layer;         /* 1: then add lbm_biofilm_layer */
+    double tau, u_in, D, c_in, k_sink;  /* as lbm_params */
+    int32_t outlet;
+    double c_out;
+    double tol;            /* both solves */
+    int64_t max_iter;      /* per solve */
+    uint64_t user;         /* caller's tag, returned in the result */
+} lbm_request;
+
+typedef struct {
+    uint64_t ticket, user;
+    int32_t status;        /* EINVAL/ENOMEM on a bad request, EDEVICE, else the worse
+                              of the two solves (EDIVERGED > NOT_CONVERGED > STALLED > OK) */
+    int32_t status_fluid, status_ad;
+    int32_t nx, ny;
+    int64_t iters_fluid, iters_ad;
+    double residual_fluid, residual_ad;
+    double flux[5];        /* as lbm_solver_fluxes, on the final states */
+    int64_t active_fluid, active_ad; /* nodes each solve updates */
+    double t_submit, t_admit, t_finish; /* seconds on the server clock */
+    const float *u;        /* [2][N] velocity, owned by the server until released */
+    const float *c;        /* [N] concentration (0 on SOLID/WALL) */
+    char message[96];      /* reason of a rejection */
+} lbm_result;
+
+typedef struct {
+    int64_t submitted, finished, rejected, active, queued, chunks;
+    uint64_t pool_bytes, pool_used, pool_peak;
+    double lattice_updates; /* active-node updates of the finished requests */
+    double busy_seconds;    /* wall time with work on the device */
+    double clock;           /* seconds since creation */
+} lbm_server_stats_t;
+
+/* Device bytes one request of this size takes from the pool. */
+size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage);
+/* Allocates the pool and starts the worker threads on ctx's device (the
+ * server has its own stream).  EINVAL on a bad configuration, ENOMEM. */
+lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server **out);
+/* Queue a request (copied).  EINVAL (see lbm_server_error) for bad
+ * parameters or a request larger than the pool; mask problems found later
+ * (a geometry that cannot be built or does not percolate) come back as a
+ * result with status EINVAL. */
+lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *ticket);
+/* Up to max finished results, waiting up to wait_s seconds for the first.
+ * Each result's arrays stay valid until lbm_result_release. */
+lbm_status lbm_server_poll(lbm_server *s, lbm_result *out, int max, int *n_out, double wait_s);
+void lbm_result_release(lbm_server *s, lbm_result *r);
+/* Wait until every submitted request has finished (timeout_s <= 0: no
+ * limit; EBUSY when it expires). */
+lbm_status lbm_server_drain(lbm_server *s, double timeout_s);
+lbm_status lbm_server_stats(lbm_server *s, lbm_server_stats_t *out);
+/* Text of the last submit error or of a device failure. */
+const char *lbm_server_error(lbm_server *s);
+/* Stops the threads (queued requests are dropped), waits for the device and
+ * frees everything, including unreleased results. */
+void lbm_server_destroy(lbm_server *s);
+
 /* ------------------------------------------------------------ diagnostics */
 /* Device-to-device copy of `bytes` bytes by a plain streaming kernel, reps
  * times, HIP-event timed: *gbps = 2 * bytes / time (read + write),

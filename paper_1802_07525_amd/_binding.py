@@ -61,6 +61,44 @@ class lbm_fibre_params(ct.Structure):
     _fields_ = [("r_min", ct.c_int32), ("r_max", ct.c_int32), ("solid_frac", ct.c_double)]
 
 
+class lbm_server_cfg(ct.Structure):
+    _fields_ = [("pool_bytes", ct.c_size_t), ("max_slots", ct.c_int32), ("storage", ct.c_int32),
+                ("check_every", ct.c_int32), ("stall_checks", ct.c_int32),
+                ("grid_blocks", ct.c_int32), ("inflight", ct.c_int32),
+                ("prep_threads", ct.c_int32), ("direct_launch", ct.c_int32)]
+
+
+class lbm_request(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("cls", ct.c_void_p),
+                ("discs", lbm_disc_params), ("seed", ct.c_uint64), ("layer", ct.c_int32),
+                ("tau", ct.c_double), ("u_in", ct.c_double), ("D", ct.c_double),
+                ("c_in", ct.c_double), ("k_sink", ct.c_double), ("outlet", ct.c_int32),
+                ("c_out", ct.c_double), ("tol", ct.c_double), ("max_iter", ct.c_int64),
+                ("user", ct.c_uint64)]
+
+
+class lbm_result(ct.Structure):
+    _fields_ = [("ticket", ct.c_uint64), ("user", ct.c_uint64), ("status", ct.c_int32),
+                ("status_fluid", ct.c_int32), ("status_ad", ct.c_int32), ("nx", ct.c_int32),
+                ("ny", ct.c_int32), ("iters_fluid", ct.c_int64), ("iters_ad", ct.c_int64),
+                ("residual_fluid", ct.c_double), ("residual_ad", ct.c_double),
+                ("flux", ct.c_double * 5), ("active_fluid", ct.c_int64),
+                ("active_ad", ct.c_int64), ("t_submit", ct.c_double), ("t_admit", ct.c_double),
+                ("t_finish", ct.c_double), ("u", ct.POINTER(ct.c_float)),
+                ("c", ct.POINTER(ct.c_float)), ("message", ct.c_char * 96)]
+
+
+class lbm_server_stats_t(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("finished", ct.c_int64), ("rejected", ct.c_int64),
+                ("active", ct.c_int64), ("queued", ct.c_int64), ("chunks", ct.c_int64),
+                ("pool_bytes", ct.c_uint64), ("pool_used", ct.c_uint64),
+                ("pool_peak", ct.c_uint64), ("lattice_updates", ct.c_double),
+                ("busy_seconds", ct.c_double), ("clock", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 P, I32, I64, U64, D, SZ = (ct.c_void_p, ct.c_int, ct.c_int64, ct.c_uint64, ct.c_double,
                            ct.c_size_t)
 G = lbm_grid
@@ -99,6 +137,15 @@ _SIGS = {
     "lbm_solver_put_state": (I32, [P, P, SZ]),
     "lbm_coupled_run": (I32, [P, I32, P, D, I64, P, P, P, P, P]),
     "lbm_copy_bandwidth": (I32, [P, SZ, I32, P, P]),
+    "lbm_server_footprint": (SZ, [I32, I32, I32]),
+    "lbm_server_create": (I32, [P, P, P]),
+    "lbm_server_submit": (I32, [P, P, P]),
+    "lbm_server_poll": (I32, [P, P, I32, P, D]),
+    "lbm_result_release": (None, [P, P]),
+    "lbm_server_drain": (I32, [P, D]),
+    "lbm_server_stats": (I32, [P, P]),
+    "lbm_server_error": (ct.c_char_p, [P]),
+    "lbm_server_destroy": (None, [P]),
 }
 
 _lib = None
@@ -439,3 +486,89 @@ class Solver:
 
     def error(self):
         return lbm_last_error(self.ctx)
+
+
+# -------------------------------------------------------------- serving
+def lbm_server_footprint(nx, ny, storage):
+    return int(load().lbm_server_footprint(int(nx), int(ny), int(storage)))
+
+
+def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_every=100,
+                    stall_checks=0, grid_blocks=0, inflight=0, prep_threads=0, direct_launch=0):
+    return lbm_server_cfg(int(pool_bytes), int(max_slots), int(storage), int(check_every),
+                          int(stall_checks), int(grid_blocks), int(inflight), int(prep_threads),
+                          int(direct_launch))
+
+
+def make_request(nx, ny, cls=None, r_min=3, r_max=6, solid_frac=0.3, overlap=1, seed=0, layer=0,
+                 tau=0.8, u_in=0.01, D=0.2 / 3, c_in=1.0, k_sink=0.0,
+                 outlet=LBM_OUT_ZERO_GRADIENT, c_out=0.0, tol=1e-6, max_iter=1000000, user=0):
+    """Request struct; a given mask is referenced, not copied, until submit
+    (the returned pair keeps the array alive)."""
+    arr = None if cls is None else _u8(cls)
+    r = lbm_request(int(nx), int(ny), None if arr is None else arr.ctypes.data,
+                    lbm_disc_params(int(r_min), int(r_max), float(solid_frac), int(overlap)),
+                    int(seed), int(layer), float(tau), float(u_in), float(D), float(c_in),
+                    float(k_sink), int(outlet), float(c_out), float(tol), int(max_iter), int(user))
+    return r, arr
+
+
+def lbm_server_create(ctx, cfg):
+    h = ct.c_void_p()
+    st = load().lbm_server_create(ctx, ct.byref(cfg), ct.byref(h))
+    if st:
+        raise LBMError(st, lbm_last_error(ctx))
+    return h
+
+
+def lbm_server_submit(srv, req):
+    """req: (lbm_request, keep-alive) from make_request.  Returns (status, ticket)."""
+    r, _keep = req
+    t = ct.c_uint64()
+    st = load().lbm_server_submit(srv, ct.byref(r), ct.byref(t))
+    return st, t.value
+
+
+def _result_dict(r):
+    N = r.nx * r.ny
+    d = {k: getattr(r, k) for k, _ in r._fields_ if k not in ("u", "c", "flux", "message")}
+    d["flux"] = np.array(r.flux[:])
+    d["message"] = r.message.decode(errors="replace")
+    d["u"] = np.ctypeslib.as_array(r.u, (2, N)).copy() if r.u else None
+    d["c"] = np.ctypeslib.as_array(r.c, (N,)).copy() if r.c else None
+    return d
+
+
+def lbm_server_poll(srv, max_results=64, wait_s=0.0):
+    """Finished results as dicts (arrays copied; the server's copies are
+    released)."""
+    buf = (lbm_result * max_results)()
+    n = ct.c_int()
+    st = load().lbm_server_poll(srv, buf, int(max_results), ct.byref(n), float(wait_s))
+    if st:
+        raise LBMError(st)
+    out = []
+    for k in range(n.value):
+        out.append(_result_dict(buf[k]))
+        load().lbm_result_release(srv, ct.byref(buf[k]))
+    return out
+
+
+def lbm_server_drain(srv, timeout_s=0.0):
+    return load().lbm_server_drain(srv, float(timeout_s))
+
+
+def lbm_server_stats(srv):
+    o = lbm_server_stats_t()
+    st = load().lbm_server_stats(srv, ct.byref(o))
+    if st:
+        raise LBMError(st)
+    return o.as_dict()
+
+
+def lbm_server_error(srv):
+    return load().lbm_server_error(srv).decode()
+
+
+def lbm_server_destroy(srv):
+    load().lbm_server_destroy(srv)

@@ -20,10 +20,13 @@
 //  * Residual checks are fused into the step kernel: on a check step it takes
 //    max |U(t) - U(t-K)| / K in FP64 against the moments saved at the
 //    previous check (and saves the new ones), reduces it across the wave
-//    with shuffles, across the block in LDS, and commits one 64-bit atomic
-//    max per block.
+//    with shuffles, across the block in LDS, and stores one maximum per
+//    block into its own slot; a one-block decide kernel reduces the slots.
 //  * Every step kernel starts by reading the control word and returns when a
 //    stop has been decided, so the host may queue steps ahead of decisions.
+//  * Serving: a grid-stride variant runs the same per-tile code over the
+//    tiles of many 2-D requests at once, each in its own phase (fluid or
+//    substrate), driven by a device slot table.
 #include "lbm_kernels.h"
 
 #include <math.h>
@@ -176,10 +179,9 @@ struct NodePos {
     long long n;
 };
 
-__device__ __forceinline__ NodePos tile_node(const Geo &g)
+__device__ __forceinline__ NodePos tile_node(const Geo &g, int tile)
 {
     NodePos p;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % g.ntx;
     const int r1 = tile / g.ntx;
     const int ty = r1 % g.nty;
@@ -194,10 +196,11 @@ __device__ __forceinline__ NodePos tile_node(const Geo &g)
 // Max over the block of two non-negative FP64 values given as bit patterns
 // (ordering of the bits equals ordering of the values; NaN sorts last):
 // shuffles within each wave, LDS across the four waves, and one plain store
-// per block into its own slot (part[b], part[nb + b]) -- no contended
-// atomics; the decide kernel reduces the slots.
+// per block into its own slots (*pa, *pb) -- no contended atomics; the
+// decide kernel reduces the slots.  Ends with a barrier so that a block may
+// call it again for its next tile.
 __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned long long b,
-                                                 unsigned long long *part)
+                                                 unsigned long long *pa, unsigned long long *pb)
 {
     __shared__ unsigned long long sa[4], sb[4];
 #pragma unroll
@@ -219,9 +222,10 @@ __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned 
             ma = sa[k] > ma ? sa[k] : ma;
             mb = sb[k] > mb ? sb[k] : mb;
         }
-        part[blockIdx.x] = ma;
-        part[gridDim.x + blockIdx.x] = mb;
+        *pa = ma;
+        *pb = mb;
     }
+    __syncthreads();
 }
 
 __device__ __forceinline__ unsigned long long dbits(double v)
@@ -238,13 +242,11 @@ __device__ __forceinline__ unsigned long long dbits(double v)
 //   blocked source (descriptor bit): h_i = h*_opp(n)     (Eq. 11, half-way)
 //   otherwise:                      h_i = h*_i(s)         (streaming)
 template <class L, class S, class DT, int MODE, bool NT>
-__global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
+__device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
+                                           unsigned long long *part_r, unsigned long long *part_u)
 {
     typedef typename S::T T;
     typedef typename S::C C;
-    if (a.ctrl->stop)
-        return;
-    const NodePos p = tile_node(a.g);
     const long long N = a.g.N;
     const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
     const bool act = (d & DT(1)) != 0;
@@ -370,8 +372,18 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
             if (L::DIM == 3)
                 up[2 * N + p.n] = uz;
         }
-        block_max_commit(rb, ub, a.ctrl->part);
+        block_max_commit(rb, ub, part_r, part_u);
     }
+}
+
+template <class L, class S, class DT, int MODE, bool NT>
+__global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
+{
+    if (a.ctrl->stop)
+        return;
+    const NodePos p = tile_node(a.g, xcd_tile(blockIdx.x, gridDim.x));
+    unsigned long long *part = a.ctrl->part;
+    fluid_tile<L, S, DT, MODE, NT>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
 }
 
 // -------------------------------------------------------- substrate step
@@ -384,16 +396,14 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 // Collision (Eq. 12) with the linear equilibrium w_i C (1 + c_i.u / c_s^2)
 // and the biofilm consumption - w_i k C.
 template <class L, int QF, class S, class DT, int MODE, bool NT>
-__global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
+__device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
+                                        unsigned long long *part_r, unsigned long long *part_u)
 {
     typedef typename S::T T;
     typedef typename S::C C;
     constexpr int ACT = QF - 1 + L::Q;
     constexpr int BIO = ACT + 1;
     constexpr int LNK = QF - 1;
-    if (a.ctrl->stop)
-        return;
-    const NodePos p = tile_node(a.g);
     const long long N = a.g.N;
     const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
     const bool act = ((d >> ACT) & DT(1)) != 0;
@@ -472,8 +482,18 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
             rb = dbits(dv * a.inv_cin);
             cp[p.n] = cfull;
         }
-        block_max_commit(rb, 0ull, a.ctrl->part);
+        block_max_commit(rb, 0ull, part_r, part_u);
     }
+}
+
+template <class L, int QF, class S, class DT, int MODE, bool NT>
+__global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
+{
+    if (a.ctrl->stop)
+        return;
+    const NodePos p = tile_node(a.g, xcd_tile(blockIdx.x, gridDim.x));
+    unsigned long long *part = a.ctrl->part;
+    ad_tile<L, QF, S, DT, MODE, NT>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------- init / export
@@ -737,7 +757,7 @@ __global__ void __launch_bounds__(320) k_flux_final(const double *part, int nb, 
 
 // ------------------------------------------------------------- control
 __global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
-                             unsigned long long *part, int nparts)
+                             unsigned long long *part, int nparts, long long t_max)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->part = part;
@@ -756,22 +776,20 @@ __global__ void k_ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int 
         c->window = window;
         c->is_fluid = is_fluid;
         c->K = K;
+        c->t_max = t_max;
     }
 }
 
-// After a check step: reduce the per-block maxima, then OK at r <= tol;
-// DIVERGED on NaN/Inf or |u| > 0.3 (fluid); STALLED after `window` checks
-// that set neither a new maximum of r nor a new minimum since the last
-// maximum (a flat round-off floor).
-__global__ void __launch_bounds__(256) k_decide(Ctrl *c)
+// Block-wide max of the per-tile maxima part_r[0..n), part_u[0..n); the
+// result is valid in thread 0.
+__device__ __forceinline__ void reduce_parts(const unsigned long long *part_r,
+                                             const unsigned long long *part_u, int n,
+                                             unsigned long long &mr_out, unsigned long long &mu_out)
 {
     __shared__ unsigned long long sr[256], su[256];
-    if (c->stop != STOP_RUN)
-        return;
-    const int np = c->nparts;
     unsigned long long mr = 0ull, mu = 0ull;
-    for (int b = threadIdx.x; b < np; b += 256) {
-        const unsigned long long r = c->part[b], u = c->part[np + b];
+    for (int b = threadIdx.x; b < n; b += 256) {
+        const unsigned long long r = part_r[b], u = part_u[b];
         mr = r > mr ? r : mr;
         mu = u > mu ? u : mu;
     }
@@ -785,14 +803,23 @@ __global__ void __launch_bounds__(256) k_decide(Ctrl *c)
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0)
-        return;
-    c->res_bits = sr[0];
-    c->umax_bits = su[0];
+    mr_out = sr[0];
+    mu_out = su[0];
+}
+
+// Stop rule after a check with residual bits rb and max |u| bits ub: OK at
+// r <= tol; DIVERGED on NaN/Inf or |u| > 0.3 (fluid); STALLED after
+// `window` checks that set neither a new maximum of r nor a new minimum
+// since the last maximum (a flat round-off floor); MAXITER once t_max
+// steps are covered.
+__device__ void decide_apply(Ctrl *c, unsigned long long rb, unsigned long long ub)
+{
+    c->res_bits = rb;
+    c->umax_bits = ub;
     c->t += c->K;
     c->checks += 1;
-    const double r = __longlong_as_double((long long)sr[0]);
-    const double um = __longlong_as_double((long long)su[0]);
+    const double r = __longlong_as_double((long long)rb);
+    const double um = __longlong_as_double((long long)ub);
     c->r_last = r;
     int stop = STOP_RUN;
     if (r != r || isinf(r) || um != um || (c->is_fluid && um > 0.3)) {
@@ -811,10 +838,124 @@ __global__ void __launch_bounds__(256) k_decide(Ctrl *c)
         if (c->window > 0 && c->since_best >= c->window)
             stop = STOP_STALLED;
     }
+    if (stop == STOP_RUN && c->t >= c->t_max)
+        stop = STOP_MAXITER;
     if (stop != STOP_RUN) {
         c->t_stop = c->t;
         c->stop = stop;
     }
+}
+
+__global__ void __launch_bounds__(256) k_decide(Ctrl *c)
+{
+    if (c->stop != STOP_RUN)
+        return;
+    const int np = c->nparts;
+    unsigned long long mr, mu;
+    reduce_parts(c->part, c->part + np, np, mr, mu);
+    if (threadIdx.x == 0)
+        decide_apply(c, mr, mu);
+}
+
+// ------------------------------------------------------ batched serving
+// One launch steps every request of the slot table by one step: a block
+// walks the table's tiles with a grid stride (tile v, v + G, ...), finds the
+// owning request by binary search over the tile offsets, and runs the same
+// per-tile code as the single-domain kernels in that request's phase.  All
+// of this is uniform across the block.  Requests are 2-D (D2Q9 + D2Q5).
+// Every phase starts in buffer 0 and a chunk has an even number of steps,
+// so step j of a chunk reads buffer j & 1.
+template <class S, int MODE>
+__global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ slots,
+                                                  const SrvTable *__restrict__ tab, Ctrl *ctrl,
+                                                  unsigned long long *part, int part_cap, int j)
+{
+    const int T = tab->total_tiles;
+    const int na = tab->n_active;
+    const int G = gridDim.x;
+    for (int v = xcd_tile(blockIdx.x, G); v < T; v += G) {
+        int lo = 0, hi = na - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab->begin[mid] <= v)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int sid = tab->slot[lo];
+        const SrvSlot &sl = slots[sid];
+        Ctrl *c = ctrl + sid;
+        if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
+            continue;
+        const NodePos p = tile_node(sl.g, v - tab->begin[lo]);
+        const unsigned int step = (unsigned int)(c->t + j);
+        if (sl.phase == SRV_FLUID) {
+            FluidArgs a;
+            a.src = sl.f[j & 1];
+            a.dst = sl.f[(j & 1) ^ 1];
+            a.desc = sl.desc;
+            a.uprev = sl.prev;
+            a.ctrl = c;
+            a.g = sl.g;
+            a.omega = sl.omega_f;
+            a.u_in = sl.u_in;
+            a.inv_uin = sl.inv_uin;
+            a.streaming_stores = 0;
+            a.step = step;
+            fluid_tile<D2Q9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
+        } else {
+            AdArgs a;
+            a.src = sl.gp[j & 1];
+            a.dst = sl.gp[(j & 1) ^ 1];
+            a.desc = sl.desc;
+            a.u = sl.u;
+            a.cprev = sl.prev;
+            a.ctrl = c;
+            a.g = sl.g;
+            a.omega = sl.omega_a;
+            a.cin_s = sl.cin_s;
+            a.cout_s = sl.cout_s;
+            a.c_ref = sl.c_ref;
+            a.k_sink = sl.k_sink;
+            a.inv_cin = sl.inv_cin;
+            a.outlet = sl.outlet;
+            a.streaming_stores = 0;
+            a.step = step;
+            ad_tile<D2Q5, 9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
+        }
+    }
+}
+
+// One block per table entry: reduce that request's tile maxima of the check
+// step and apply the stop rule to its control block.
+__global__ void __launch_bounds__(256) k_srv_decide(const SrvSlot *__restrict__ slots,
+                                                    const SrvTable *__restrict__ tab, Ctrl *ctrl,
+                                                    const unsigned long long *part, int part_cap)
+{
+    const int e = blockIdx.x;
+    if (e >= tab->n_active)
+        return;
+    const int sid = tab->slot[e];
+    Ctrl *c = ctrl + sid;
+    if (slots[sid].phase == SRV_IDLE || c->stop != STOP_RUN)
+        return;
+    const int b0 = tab->begin[e], n = tab->begin[e + 1] - b0;
+    unsigned long long mr, mu;
+    reduce_parts(part + b0, part + part_cap + b0, n, mr, mu);
+    if (threadIdx.x == 0)
+        decide_apply(c, mr, mu);
+}
+
+__global__ void k_srv_slot_set(SrvSlot *slots, int sid, SrvSlot v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        slots[sid] = v;
+}
+
+__global__ void k_srv_table_set(SrvTable *tab, SrvTable v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *tab = v;
 }
 
 // Plain streaming copy used to calibrate bandwidth and counters: each block
@@ -1121,10 +1262,55 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
 }
 
 hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
-                      unsigned long long *part, int nparts, hipStream_t st)
+                      unsigned long long *part, int nparts, hipStream_t st, long long t_max)
 {
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, tol, window, is_fluid, K, part,
-                       nparts);
+                       nparts, t_max);
+    return hipGetLastError();
+}
+
+hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                    unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st)
+{
+    auto go = [&](auto sp) -> hipError_t {
+        typedef decltype(sp) S;
+        if (mode == MODE_CHECK)
+            hipLaunchKernelGGL((k_srv_step<S, MODE_CHECK>), dim3(blocks), dim3(256), 0, st, slots,
+                               tab, ctrl, part, part_cap, j);
+        else
+            hipLaunchKernelGGL((k_srv_step<S, MODE_PLAIN>), dim3(blocks), dim3(256), 0, st, slots,
+                               tab, ctrl, part, part_cap, j);
+        return hipGetLastError();
+    };
+    switch (storage) {
+    case ST_F32:
+        return go(SF32());
+    case ST_F32S:
+        return go(SF32S());
+    case ST_F16S:
+        return go(SF16S());
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                      const unsigned long long *part, int part_cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_srv_decide, dim3(SRV_MAX_SLOTS), dim3(256), 0, st, slots, tab, ctrl, part,
+                       part_cap);
+    return hipGetLastError();
+}
+
+hipError_t srv_slot_set(SrvSlot *slots, int sid, const SrvSlot &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_srv_slot_set, dim3(1), dim3(64), 0, st, slots, sid, v);
+    return hipGetLastError();
+}
+
+hipError_t srv_table_set(SrvTable *tab, const SrvTable &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_srv_table_set, dim3(1), dim3(64), 0, st, tab, v);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ namespace lbmk {
 
 enum { ST_F32 = 0, ST_F32S = 1, ST_F16S = 2, ST_F64 = 3 };
 enum { MODE_PLAIN = 0, MODE_CHECK = 2 };
-enum { STOP_RUN = 0, STOP_OK = 1, STOP_STALLED = 2, STOP_DIVERGED = 3 };
+enum { STOP_RUN = 0, STOP_OK = 1, STOP_STALLED = 2, STOP_DIVERGED = 3, STOP_MAXITER = 4 };
 
 // Per-solve control block in device memory.  The step kernels read `stop`
 // first and return at once when it is set, so the host may enqueue steps
@@ -35,6 +35,7 @@ struct Ctrl {
     int nparts;                   // blocks of the step grid
     double peak;                  // largest residual so far
     unsigned long long *part;     // per-block maxima [2 * nparts] of a check step
+    long long t_max;              // MAXITER stop once t >= t_max
 };
 
 // Domain geometry as the kernels see it.  Tiles are 64 x 4 nodes (one
@@ -134,9 +135,51 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
 
 // part: device scratch of 2 * nparts words for the per-block check maxima
 hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
-                      unsigned long long *part, int nparts, hipStream_t st);
+                      unsigned long long *part, int nparts, hipStream_t st,
+                      long long t_max = 0x7fffffffffffffffll);
 hipError_t decide(Ctrl *c, hipStream_t st);
 
 hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st);
+
+// ---- batched serving (2-D requests: D2Q9 fluid, D2Q5 substrate) ----------
+enum { SRV_IDLE = 0, SRV_FLUID = 1, SRV_AD = 2 };
+enum { SRV_MAX_SLOTS = 64 };
+
+// One request on the device.  Its substrate buffers g[b] alias the start of
+// the fluid buffers f[b] (the fluid populations are dead once the velocity
+// is exported); prev holds the velocity (fluid phase) or concentration
+// (substrate phase) of the previous check.
+struct SrvSlot {
+    const void *desc; // uint16 descriptor words [N]
+    void *f[2];
+    void *gp[2];      // substrate A/B (aliases of f[0], f[1])
+    void *u;          // compute-type [2][N]
+    void *prev;       // compute-type [2][N]
+    Geo g;
+    double omega_f, u_in, inv_uin;
+    double omega_a, cin_s, cout_s, c_ref, k_sink, inv_cin;
+    int outlet;
+    int phase;        // SRV_*
+};
+
+// Requests being stepped: entry e covers tiles [begin[e], begin[e+1]) of
+// the launch and is request slot[e]; total_tiles = begin[n_active].
+struct SrvTable {
+    int n_active;
+    int total_tiles;
+    int begin[SRV_MAX_SLOTS + 1];
+    int slot[SRV_MAX_SLOTS];
+};
+
+// One step of every request in tab (step j of the current chunk; MODE_CHECK
+// stores per-tile maxima at part[v] and part[part_cap + v]).
+hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                    unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st);
+// Stop rule for every request in tab after a check step.
+hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                      const unsigned long long *part, int part_cap, hipStream_t st);
+// Device-side writes of one slot entry / the whole table, in stream order.
+hipError_t srv_slot_set(SrvSlot *slots, int sid, const SrvSlot &v, hipStream_t st);
+hipError_t srv_table_set(SrvTable *tab, const SrvTable &v, hipStream_t st);
 
 } // namespace lbmk

@@ -1,0 +1,1188 @@
+// server.cpp -- served form: continuous batching of 2-D steady solves.
+//
+// A request is one 2-D steady problem of the paper's model loop (Sec. 2):
+// the fluid solve (Sec. 2.1.1) to its residual tolerance, then the
+// substrate solve (Sec. 2.1.2) in the exported velocity.  The server keeps
+// every admitted request's populations resident in one device pool and
+// steps all of them together:
+//
+//  * Submission copies the request; host preparation threads build its
+//    mask (seeded discs or the caller's classes), check it and turn it into
+//    descriptor words.
+//  * A worker thread admits prepared requests in ticket order while a slot
+//    is free and the request's footprint fits the pool (first fit), uploads
+//    the descriptors through a pinned ring, initialises the request on the
+//    device and adds its tiles to the device slot table.
+//  * Work proceeds in chunks of K steps: K launches of the batched step
+//    kernel (each covers every tile of every admitted request, in that
+//    request's phase) and one batched decide, captured once as a HIP graph
+//    that reads the slot table from device memory, so admissions never
+//    re-capture it.  After each chunk the control blocks are copied to
+//    pinned memory; the host keeps a bounded number of chunks in flight.
+//  * When a snapshot shows a request's fluid solve stopped, the worker
+//    enqueues the velocity export and the substrate start for it; when the
+//    substrate solve stops, the concentration export and the result copy.
+//    The request leaves the table, and its slot and pool range are free for
+//    the next admission at once: all device work is on one stream, so
+//    whatever uses them next is ordered behind the result copy.  The result
+//    is handed out when that copy has completed.
+//
+// A request's arithmetic is that of a single solve with the same storage:
+// the same per-tile code, the same step counters, the same check steps.
+// Its results are therefore the same alone and in any mix, bit for bit.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using namespace lbmh;
+
+namespace {
+
+const size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Per-request device buffers, in pool order.
+struct Layout {
+    size_t desc, f0, f1, u, prev, total;
+};
+
+Layout layout_of(int64_t N, int storage)
+{
+    const size_t sb = lbmk::storage_bytes(storage);
+    Layout L;
+    size_t o = 0;
+    L.desc = o;
+    o += align_up((size_t)N * 2);
+    L.f0 = o;
+    o += align_up((size_t)N * 9 * sb);
+    L.f1 = o;
+    o += align_up((size_t)N * 9 * sb);
+    L.u = o;
+    o += align_up((size_t)N * 2 * 4);
+    L.prev = o;
+    o += align_up((size_t)N * 2 * 4);
+    L.total = o;
+    return L;
+}
+
+// First-fit sub-allocator over the device pool; adjacent free ranges merge.
+class PoolAlloc {
+public:
+    void reset(size_t bytes)
+    {
+        free_.clear();
+        if (bytes)
+            free_[0] = bytes;
+        cap = bytes;
+        used = peak = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes)
+                continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, o = it->first + bytes;
+            free_.erase(it);
+            if (rest)
+                free_[o] = rest;
+            used += bytes;
+            peak = std::max(peak, used);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+        used -= bytes;
+    }
+    size_t cap = 0, used = 0, peak = 0;
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+// Pinned host staging ring for asynchronous copies.  Ranges are taken in
+// FIFO order; a range is reused only after the event recorded behind its
+// copy has completed and its owner (if any) has been handed to `reclaim`,
+// which must read the data out.  Copies complete in stream order, so the
+// ring reclaims from the front.
+class PinnedRing {
+public:
+    std::function<void(void *)> reclaim;
+    ~PinnedRing() { destroy(); }
+    hipError_t init(size_t bytes)
+    {
+        cap_ = bytes;
+        return hipHostMalloc((void **)&base_, bytes, hipHostMallocDefault);
+    }
+    void destroy()
+    {
+        for (auto &u : uses_)
+            (void)hipEventSynchronize(u.ev), spare_.push_back(u.ev);
+        uses_.clear();
+        for (hipEvent_t e : spare_)
+            (void)hipEventDestroy(e);
+        spare_.clear();
+        if (base_)
+            (void)hipHostFree(base_);
+        base_ = nullptr;
+    }
+    bool empty() const { return uses_.empty(); }
+    // Reclaim every range whose copy has completed; with wait, also the
+    // oldest one still in flight.
+    hipError_t reap(bool wait)
+    {
+        while (!uses_.empty()) {
+            hipError_t q = hipEventQuery(uses_.front().ev);
+            if (q == hipErrorNotReady) {
+                if (!wait)
+                    return hipSuccess;
+                wait = false;
+                if ((q = hipEventSynchronize(uses_.front().ev)) != hipSuccess)
+                    return q;
+            } else if (q != hipSuccess) {
+                return q;
+            }
+            pop_front();
+        }
+        return hipSuccess;
+    }
+    // Host pointer to len bytes; waits for older copies when the ring is full.
+    hipError_t acquire(size_t len, char **p, void *owner)
+    {
+        hipError_t e;
+        if (len > cap_) {
+            // grow: drain every outstanding copy, then reallocate
+            while (!uses_.empty())
+                if ((e = reap(true)) != hipSuccess)
+                    return e;
+            (void)hipHostFree(base_);
+            base_ = nullptr;
+            cap_ = align_up(len) * 2;
+            if ((e = hipHostMalloc((void **)&base_, cap_, hipHostMallocDefault)) != hipSuccess)
+                return e;
+            head_ = 0;
+        }
+        if ((e = reap(false)) != hipSuccess)
+            return e;
+        for (;;) {
+            if (uses_.empty())
+                head_ = 0;
+            const size_t x = head_ + len <= cap_ ? head_ : 0;
+            bool clash = false;
+            for (const auto &u : uses_)
+                if (x < u.off + u.len && u.off < x + len) {
+                    clash = true;
+                    break;
+                }
+            if (!clash) {
+                pend_ = {x, len, nullptr, owner};
+                head_ = align_up(x + len);
+                *p = base_ + x;
+                return hipSuccess;
+            }
+            if ((e = reap(true)) != hipSuccess)
+                return e;
+        }
+    }
+    // Record the event behind the copies of the last acquired range.
+    hipError_t commit(hipStream_t st)
+    {
+        hipError_t e;
+        if (!spare_.empty()) {
+            pend_.ev = spare_.back();
+            spare_.pop_back();
+        } else if ((e = hipEventCreateWithFlags(&pend_.ev, hipEventDisableTiming)) != hipSuccess) {
+            return e;
+        }
+        if ((e = hipEventRecord(pend_.ev, st)) != hipSuccess)
+            return e;
+        uses_.push_back(pend_);
+        return hipSuccess;
+    }
+
+private:
+    struct Use {
+        size_t off, len;
+        hipEvent_t ev;
+        void *owner;
+    };
+    void pop_front()
+    {
+        Use u = uses_.front();
+        uses_.pop_front();
+        spare_.push_back(u.ev);
+        if (u.owner && reclaim)
+            reclaim(u.owner);
+    }
+    char *base_ = nullptr;
+    size_t cap_ = 0, head_ = 0;
+    Use pend_{};
+    std::deque<Use> uses_;
+    std::vector<hipEvent_t> spare_;
+};
+
+enum { PH_QUEUED = 0, PH_FLUID = 1, PH_AD = 2, PH_RETIRING = 3, PH_DONE = 4 };
+
+struct Job {
+    uint64_t ticket = 0;
+    lbm_request req{};
+    std::vector<uint8_t> cls;
+    std::vector<uint16_t> desc;
+    lbmk::Geo geo{};
+    int64_t n_fluid = 0, n_ad = 0;
+    Layout lay{};
+    double t_submit = 0, t_admit = 0, t_finish = 0;
+    int status = LBM_OK; // preparation error, if any
+    std::string msg;
+    int sid = -1;
+    size_t off = 0;
+    int phase = PH_QUEUED;
+    long long valid_from = 0; // first chunk whose snapshot shows the current phase
+    long long t_max = 0;
+    int st_fluid = LBM_OK, st_ad = LBM_OK;
+    int64_t it_fluid = 0, it_ad = 0;
+    double r_fluid = NAN, r_ad = NAN;
+    bool ad_ran = false;
+    char *staged = nullptr; // pinned result staging
+    std::vector<float> u, c;
+    double flux[10] = {0};
+};
+
+int stop_status(int stop)
+{
+    switch (stop) {
+    case lbmk::STOP_OK:
+        return LBM_OK;
+    case lbmk::STOP_STALLED:
+        return LBM_STALLED;
+    case lbmk::STOP_DIVERGED:
+        return LBM_EDIVERGED;
+    default:
+        return LBM_NOT_CONVERGED;
+    }
+}
+
+int overall_status(int a, int b)
+{
+    if (a == LBM_EDIVERGED || b == LBM_EDIVERGED)
+        return LBM_EDIVERGED;
+    if (a == LBM_NOT_CONVERGED || b == LBM_NOT_CONVERGED)
+        return LBM_NOT_CONVERGED;
+    if (a == LBM_STALLED || b == LBM_STALLED)
+        return LBM_STALLED;
+    return LBM_OK;
+}
+
+std::string request_problem(const lbm_request &r)
+{
+    if (r.nx < 3 || r.ny < 3)
+        return "grid must be at least 3 x 3 (2-D requests)";
+    if ((int64_t)r.nx * r.ny > ((int64_t)1 << 31) / 9)
+        return "grid too large";
+    if (!(r.tau > 0.5) || !isfinite(r.tau))
+        return "tau must be > 1/2";
+    if (!(fabs(r.u_in) < 0.1) || r.u_in == 0.0)
+        return "u_in must be nonzero with |u_in| < 0.1";
+    if (!(r.D > 0.0) || !isfinite(r.D))
+        return "D must be > 0";
+    if (!(r.c_in != 0.0) || !isfinite(r.c_in))
+        return "c_in must be finite and nonzero";
+    if (!(r.k_sink >= 0.0 && r.k_sink < 1.0))
+        return "k_sink must be in [0, 1)";
+    if (r.outlet != LBM_OUT_ZERO_GRADIENT && r.outlet != LBM_OUT_DIRICHLET)
+        return "unknown outlet mode";
+    if (!isfinite(r.c_out))
+        return "c_out must be finite";
+    if (!(r.tol >= 0.0) || r.max_iter < 1)
+        return "tol must be >= 0 and max_iter >= 1";
+    return std::string();
+}
+
+double now_s(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+} // namespace
+
+struct lbm_server {
+    int device = 0;
+    lbm_server_cfg cfg{};
+    int K = 100, window = 0, blocks = 2048, depth = 2;
+    hipStream_t stream = nullptr;
+    std::chrono::steady_clock::time_point t0;
+
+    // device state
+    char *pool = nullptr;
+    lbmk::SrvSlot *d_slots = nullptr;
+    lbmk::SrvTable *d_tab = nullptr;
+    lbmk::Ctrl *d_ctrl = nullptr;
+    unsigned long long *d_part = nullptr;
+    int part_cap = 0;
+    double *d_partials = nullptr;
+    double *d_out = nullptr; // [SRV_MAX_SLOTS][10] flux results
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    // host state owned by the worker
+    PoolAlloc alloc;
+    PinnedRing up_ring, res_ring;
+    lbmk::Ctrl *h_snap = nullptr; // pinned [RING][SRV_MAX_SLOTS]
+    static const int RING = 8;
+    hipEvent_t ev_snap[RING] = {};
+    long long snap_chunk[RING] = {};
+    long long chunks = 0, head = 0, tail = 0;
+    Job *slot_job[lbmk::SRV_MAX_SLOTS] = {};
+    int tiles_used = 0;
+    bool table_dirty = false;
+    int n_retiring = 0;
+
+    // shared state (mutex)
+    std::mutex mu;
+    std::condition_variable cv_prep, cv_work, cv_done;
+    std::deque<Job *> prep_q;
+    std::map<uint64_t, Job *> ready;     // prepared, by ticket
+    std::deque<Job *> finished;          // not yet polled
+    std::map<uint64_t, Job *> delivered; // polled, not yet released
+    std::map<uint64_t, std::unique_ptr<Job>> all;
+    uint64_t next_ticket = 1;
+    int64_t n_submitted = 0, n_finished = 0, n_rejected = 0, n_active = 0;
+    double updates = 0.0, busy = 0.0;
+    bool stopping = false, failed = false;
+    std::string err;
+    char err_buf[256] = {0};
+    std::vector<std::thread> preps;
+    std::thread worker;
+
+    // ------------------------------------------------------------- prep
+    void prep_loop()
+    {
+        for (;;) {
+            Job *j;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_prep.wait(lk, [&] { return stopping || !prep_q.empty(); });
+                if (stopping)
+                    return;
+                j = prep_q.front();
+                prep_q.pop_front();
+            }
+            prepare(j);
+            std::lock_guard<std::mutex> lk(mu);
+            if (failed || stopping)
+                continue; // already finished by fail(), or abandoned
+            if (j->status != LBM_OK) {
+                finish_locked(j);
+            } else {
+                ready[j->ticket] = j;
+                cv_work.notify_all();
+            }
+        }
+    }
+
+    void prepare(Job *j)
+    {
+        const lbm_request &r = j->req;
+        lbm_grid g{r.nx, r.ny, 1};
+        const int64_t N = (int64_t)r.nx * r.ny;
+        if (j->cls.empty()) {
+            j->cls.assign((size_t)N, 0);
+            double got = 0.0;
+            lbm_status st = lbm_geom_discs(g, &r.discs, r.seed, j->cls.data(), &got);
+            if (st != LBM_OK) {
+                j->status = st;
+                j->msg = "geometry generation failed";
+                return;
+            }
+            if (r.layer)
+                lbm_biofilm_layer(g, j->cls.data());
+        }
+        std::string m = check_mask(g, j->cls.data());
+        if (m.empty() && !percolates(g, j->cls.data()))
+            m = "the fluid domain does not connect inlet to outlet";
+        if (!m.empty()) {
+            j->status = LBM_EINVAL;
+            j->msg = m;
+            return;
+        }
+        std::vector<uint32_t> d((size_t)N);
+        build_desc(g, j->cls.data(), d.data(), 0, N);
+        j->desc.resize((size_t)N);
+        const int aab = lbmk::desc_ad_active_bit(9, 5);
+        for (int64_t n = 0; n < N; ++n) {
+            j->desc[n] = (uint16_t)d[n];
+            j->n_fluid += d[n] & 1u;
+            j->n_ad += (d[n] >> aab) & 1u;
+        }
+        j->geo = lbmk::make_geo(r.nx, r.ny, 1);
+        j->cls.clear();
+        j->cls.shrink_to_fit();
+    }
+
+    // caller holds mu
+    void finish_locked(Job *j)
+    {
+        j->phase = PH_DONE;
+        j->t_finish = now_s(t0);
+        if (j->status == LBM_OK)
+            updates += (double)j->it_fluid * j->n_fluid + (double)j->it_ad * j->n_ad;
+        else
+            ++n_rejected;
+        ++n_finished;
+        finished.push_back(j);
+        cv_done.notify_all();
+    }
+
+    // ----------------------------------------------------------- worker
+    hipError_t admit(Job *j, int sid)
+    {
+        hipError_t e;
+        const int64_t N = j->geo.N;
+        const int storage = cfg.storage;
+        char *base = pool + j->off;
+        void *desc = base + j->lay.desc, *f0 = base + j->lay.f0, *f1 = base + j->lay.f1;
+        void *u = base + j->lay.u, *prev = base + j->lay.prev;
+        char *stage;
+        if ((e = up_ring.acquire((size_t)N * 2, &stage, nullptr)) != hipSuccess)
+            return e;
+        memcpy(stage, j->desc.data(), (size_t)N * 2);
+        if ((e = hipMemcpyAsync(desc, stage, (size_t)N * 2, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return e;
+        if ((e = up_ring.commit(stream)) != hipSuccess)
+            return e;
+        if ((e = hipMemsetAsync(d_out + 10 * sid, 0, 10 * sizeof(double), stream)) != hipSuccess)
+            return e;
+        if ((e = lbmk::fluid_init(2, storage, f0, desc, j->geo, stream)) != hipSuccess)
+            return e;
+        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, prev, nullptr, 0, stream)) != hipSuccess)
+            return e;
+        j->t_max = (j->req.max_iter + K - 1) / K * (long long)K;
+        if ((e = lbmk::ctrl_reset(d_ctrl + sid, j->req.tol, window, 1, K, nullptr, 0, stream, j->t_max)) !=
+            hipSuccess)
+            return e;
+        lbmk::SrvSlot s{};
+        s.desc = desc;
+        s.f[0] = f0;
+        s.f[1] = f1;
+        s.gp[0] = f0;
+        s.gp[1] = f1;
+        s.u = u;
+        s.prev = prev;
+        s.g = j->geo;
+        const lbm_request &r = j->req;
+        s.omega_f = 1.0 / r.tau;
+        s.u_in = r.u_in;
+        s.inv_uin = 1.0 / ((double)K * fabs(r.u_in));
+        s.omega_a = 1.0 / (0.5 + r.D / (1.0 / 3.0)); // as the single solve: D / c_s^2
+        const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
+        s.cin_s = r.c_in - c_ref;
+        s.cout_s = r.c_out - c_ref;
+        s.c_ref = c_ref;
+        s.k_sink = r.k_sink;
+        s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
+        s.outlet = r.outlet;
+        s.phase = lbmk::SRV_FLUID;
+        if ((e = lbmk::srv_slot_set(d_slots, sid, s, stream)) != hipSuccess)
+            return e;
+        j->sid = sid;
+        j->phase = PH_FLUID;
+        j->valid_from = chunks;
+        j->t_admit = now_s(t0);
+        slot_job[sid] = j;
+        tiles_used += j->geo.ntiles;
+        table_dirty = true;
+        return hipSuccess;
+    }
+
+    // Fluid solve of j has stopped: export its velocity and start the
+    // substrate solve (or retire it when the fluid diverged).
+    hipError_t to_substrate(Job *j)
+    {
+        hipError_t e;
+        const int storage = cfg.storage;
+        char *base = pool + j->off;
+        void *desc = base + j->lay.desc, *f0 = base + j->lay.f0;
+        void *u = base + j->lay.u, *prev = base + j->lay.prev;
+        const lbm_request &r = j->req;
+        const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
+        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, u, nullptr, 0, stream)) != hipSuccess)
+            return e;
+        if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, r.u_in, r.c_in, c_ref, r.k_sink,
+                              r.outlet, r.c_out, d_partials, d_out + 10 * j->sid, stream)) != hipSuccess)
+            return e;
+        if (j->st_fluid == LBM_EDIVERGED)
+            return retire(j);
+        // the substrate populations take the place of the fluid ones
+        if ((e = lbmk::ad_init(2, storage, f0, desc, u, j->geo, r.c_in, c_ref, stream)) != hipSuccess)
+            return e;
+        if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, c_ref, r.k_sink, prev, 0, stream)) !=
+            hipSuccess)
+            return e;
+        if ((e = lbmk::ctrl_reset(d_ctrl + j->sid, r.tol, window, 0, K, nullptr, 0, stream, j->t_max)) !=
+            hipSuccess)
+            return e;
+        lbmk::SrvSlot s{};
+        // only the phase changes; rewrite the entry whole
+        s.desc = desc;
+        s.f[0] = f0;
+        s.f[1] = base + j->lay.f1;
+        s.gp[0] = s.f[0];
+        s.gp[1] = s.f[1];
+        s.u = u;
+        s.prev = prev;
+        s.g = j->geo;
+        s.omega_f = 1.0 / r.tau;
+        s.u_in = r.u_in;
+        s.inv_uin = 1.0 / ((double)K * fabs(r.u_in));
+        s.omega_a = 1.0 / (0.5 + r.D / (1.0 / 3.0)); // as the single solve: D / c_s^2
+        s.cin_s = r.c_in - c_ref;
+        s.cout_s = r.c_out - c_ref;
+        s.c_ref = c_ref;
+        s.k_sink = r.k_sink;
+        s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
+        s.outlet = r.outlet;
+        s.phase = lbmk::SRV_AD;
+        if ((e = lbmk::srv_slot_set(d_slots, j->sid, s, stream)) != hipSuccess)
+            return e;
+        j->phase = PH_AD;
+        j->ad_ran = true;
+        j->valid_from = chunks;
+        return hipSuccess;
+    }
+
+    // Export the concentration, copy the results to pinned memory and take
+    // the request out of the table.
+    hipError_t retire(Job *j)
+    {
+        hipError_t e;
+        const int storage = cfg.storage;
+        const int64_t N = j->geo.N;
+        char *base = pool + j->off;
+        void *desc = base + j->lay.desc, *f0 = base + j->lay.f0;
+        void *u = base + j->lay.u, *prev = base + j->lay.prev;
+        const lbm_request &r = j->req;
+        const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
+        double *out = d_out + 10 * j->sid;
+        if (j->ad_ran) {
+            if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, c_ref, r.k_sink, prev, 0, stream)) !=
+                hipSuccess)
+                return e;
+            if ((e = lbmk::fluxes(2, storage, nullptr, f0, desc, j->geo, r.u_in, r.c_in, c_ref, r.k_sink,
+                                  r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
+                return e;
+        } else if ((e = hipMemsetAsync(prev, 0, (size_t)N * 4, stream)) != hipSuccess) {
+            return e;
+        }
+        const size_t bytes = 80 + (size_t)N * 12;
+        if ((e = res_ring.acquire(bytes, &j->staged, j)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(j->staged, out, 80, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(j->staged + 80, u, (size_t)N * 8, hipMemcpyDeviceToHost, stream)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(j->staged + 80 + (size_t)N * 8, prev, (size_t)N * 4, hipMemcpyDeviceToHost,
+                                stream)) != hipSuccess)
+            return e;
+        if ((e = res_ring.commit(stream)) != hipSuccess)
+            return e;
+        // Everything that touches the slot or the pool range is on this
+        // stream: a request admitted into them now is ordered behind the
+        // copies above, so both are free for reuse at once.
+        j->phase = PH_RETIRING;
+        slot_job[j->sid] = nullptr;
+        tiles_used -= j->geo.ntiles;
+        alloc.release(j->off, j->lay.total);
+        table_dirty = true;
+        ++n_retiring;
+        return hipSuccess;
+    }
+
+    // A retired request's copies are done (called by the result ring before
+    // it reuses the staging range): hand out the result.
+    void complete(Job *j)
+    {
+        const int64_t N = j->geo.N;
+        memcpy(j->flux, j->staged, 80);
+        j->u.resize((size_t)N * 2);
+        j->c.resize((size_t)N);
+        memcpy(j->u.data(), j->staged + 80, (size_t)N * 8);
+        memcpy(j->c.data(), j->staged + 80 + (size_t)N * 8, (size_t)N * 4);
+        j->staged = nullptr;
+        j->desc.clear();
+        j->desc.shrink_to_fit();
+        --n_retiring;
+        std::lock_guard<std::mutex> lk(mu);
+        --n_active;
+        finish_locked(j);
+    }
+
+    hipError_t write_table()
+    {
+        lbmk::SrvTable t{};
+        int e = 0, tiles = 0;
+        for (int s = 0; s < lbmk::SRV_MAX_SLOTS; ++s) {
+            Job *j = slot_job[s];
+            if (!j || (j->phase != PH_FLUID && j->phase != PH_AD))
+                continue;
+            t.begin[e] = tiles;
+            t.slot[e] = s;
+            tiles += j->geo.ntiles;
+            ++e;
+        }
+        t.begin[e] = tiles;
+        t.n_active = e;
+        t.total_tiles = tiles;
+        table_dirty = false;
+        return lbmk::srv_table_set(d_tab, t, stream);
+    }
+
+    bool any_running() const
+    {
+        for (int s = 0; s < lbmk::SRV_MAX_SLOTS; ++s)
+            if (slot_job[s] && (slot_job[s]->phase == PH_FLUID || slot_job[s]->phase == PH_AD))
+                return true;
+        return false;
+    }
+
+    hipError_t launch_chunk()
+    {
+        hipError_t e;
+        if (exec) {
+            if ((e = hipGraphLaunch(exec, stream)) != hipSuccess)
+                return e;
+        } else if ((e = enqueue_chunk()) != hipSuccess) {
+            return e;
+        }
+        const int r = (int)(head % RING);
+        if ((e = hipMemcpyAsync(h_snap + (size_t)r * lbmk::SRV_MAX_SLOTS, d_ctrl,
+                                sizeof(lbmk::Ctrl) * lbmk::SRV_MAX_SLOTS, hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipEventRecord(ev_snap[r], stream)) != hipSuccess)
+            return e;
+        snap_chunk[r] = chunks++;
+        ++head;
+        return hipSuccess;
+    }
+
+    hipError_t enqueue_chunk()
+    {
+        hipError_t e;
+        for (int j = 0; j < K; ++j)
+            if ((e = lbmk::srv_step(cfg.storage, j == K - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
+                                    d_tab, d_ctrl, d_part, part_cap, j, blocks, stream)) != hipSuccess)
+                return e;
+        return lbmk::srv_decide(d_slots, d_tab, d_ctrl, d_part, part_cap, stream);
+    }
+
+    hipError_t process_snapshot()
+    {
+        const int r = (int)(tail % RING);
+        const long long c = snap_chunk[r];
+        const lbmk::Ctrl *snap = h_snap + (size_t)r * lbmk::SRV_MAX_SLOTS;
+        ++tail;
+        hipError_t e;
+        for (int s = 0; s < lbmk::SRV_MAX_SLOTS; ++s) {
+            Job *j = slot_job[s];
+            if (!j || c < j->valid_from || snap[s].stop == lbmk::STOP_RUN)
+                continue;
+            const lbmk::Ctrl &k = snap[s];
+            if (j->phase == PH_FLUID) {
+                j->st_fluid = stop_status(k.stop);
+                j->it_fluid = k.t_stop;
+                j->r_fluid = k.checks > 0 ? k.r_last : NAN;
+                if ((e = to_substrate(j)) != hipSuccess)
+                    return e;
+            } else if (j->phase == PH_AD) {
+                j->st_ad = stop_status(k.stop);
+                j->it_ad = k.t_stop;
+                j->r_ad = k.checks > 0 ? k.r_last : NAN;
+                if ((e = retire(j)) != hipSuccess)
+                    return e;
+            }
+        }
+        return hipSuccess;
+    }
+
+    // Admit prepared requests in ticket order while the head one fits.
+    hipError_t admit_ready()
+    {
+        for (;;) {
+            Job *j = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (ready.empty())
+                    return hipSuccess;
+                j = ready.begin()->second;
+            }
+            int sid = -1;
+            for (int s = 0; s < cfg.max_slots; ++s)
+                if (!slot_job[s]) {
+                    sid = s;
+                    break;
+                }
+            if (sid < 0 || tiles_used + j->geo.ntiles > part_cap)
+                return hipSuccess;
+            if (!alloc.alloc(j->lay.total, &j->off))
+                return hipSuccess;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                ready.erase(ready.begin());
+                ++n_active;
+            }
+            hipError_t e = admit(j, sid);
+            if (e != hipSuccess)
+                return e;
+        }
+    }
+
+    hipError_t step_once(bool *idle)
+    {
+        hipError_t e;
+        *idle = false;
+        // finished result copies
+        if ((e = res_ring.reap(false)) != hipSuccess)
+            return e;
+        if ((e = admit_ready()) != hipSuccess)
+            return e;
+        if (table_dirty && (e = write_table()) != hipSuccess)
+            return e;
+        const bool running = any_running();
+        if (running && head - tail < depth) {
+            const auto ta = std::chrono::steady_clock::now();
+            if ((e = launch_chunk()) != hipSuccess)
+                return e;
+            busy_mark(ta);
+            return hipSuccess;
+        }
+        if (head > tail) {
+            const int r = (int)(tail % RING);
+            hipError_t q = hipEventQuery(ev_snap[r]);
+            if (q == hipErrorNotReady) {
+                if (!(head - tail >= depth || !running))
+                    return hipSuccess;
+                if ((e = hipEventSynchronize(ev_snap[r])) != hipSuccess)
+                    return e;
+            } else if (q != hipSuccess) {
+                return q;
+            }
+            return process_snapshot();
+        }
+        if (n_retiring > 0)
+            return res_ring.reap(true);
+        *idle = true;
+        return hipSuccess;
+    }
+
+    std::chrono::steady_clock::time_point busy_since{};
+    bool was_busy = false;
+    void busy_mark(std::chrono::steady_clock::time_point t)
+    {
+        if (!was_busy) {
+            busy_since = t;
+            was_busy = true;
+        }
+    }
+    void busy_end()
+    {
+        if (was_busy) {
+            std::lock_guard<std::mutex> lk(mu);
+            busy += std::chrono::duration<double>(std::chrono::steady_clock::now() - busy_since).count();
+            was_busy = false;
+        }
+    }
+
+    void work_loop()
+    {
+        hipError_t e = hipSetDevice(device);
+        while (e == hipSuccess) {
+            bool idle = false;
+            e = step_once(&idle);
+            if (e != hipSuccess)
+                break;
+            if (idle) {
+                busy_end();
+                std::unique_lock<std::mutex> lk(mu);
+                if (stopping)
+                    return;
+                cv_work.wait_for(lk, std::chrono::milliseconds(20),
+                                 [&] { return stopping || !ready.empty(); });
+                if (stopping)
+                    return;
+            } else {
+                std::lock_guard<std::mutex> lk(mu);
+                if (stopping)
+                    break;
+            }
+        }
+        if (e != hipSuccess)
+            fail(std::string("HIP error in the serving loop: ") + hipGetErrorString(e));
+    }
+
+    // Device failure: every request not yet finished ends with EDEVICE.
+    void fail(const std::string &m)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        failed = true;
+        err = m;
+        for (auto &kv : all) {
+            Job *j = kv.second.get();
+            if (j->phase == PH_DONE)
+                continue;
+            j->status = LBM_EDEVICE;
+            j->msg = m;
+            j->phase = PH_DONE;
+            j->t_finish = now_s(t0);
+            ++n_finished;
+            finished.push_back(j);
+        }
+        prep_q.clear();
+        ready.clear();
+        cv_done.notify_all();
+    }
+
+    void fill_result(Job *j, lbm_result *o)
+    {
+        memset(o, 0, sizeof(*o));
+        o->ticket = j->ticket;
+        o->user = j->req.user;
+        o->nx = j->req.nx;
+        o->ny = j->req.ny;
+        if (j->status != LBM_OK) {
+            o->status = j->status;
+            snprintf(o->message, sizeof(o->message), "%s", j->msg.c_str());
+        } else {
+            o->status_fluid = j->st_fluid;
+            o->status_ad = j->ad_ran ? j->st_ad : j->st_fluid;
+            o->status = overall_status(j->st_fluid, o->status_ad);
+        }
+        o->iters_fluid = j->it_fluid;
+        o->iters_ad = j->it_ad;
+        o->residual_fluid = j->r_fluid;
+        o->residual_ad = j->r_ad;
+        o->flux[0] = j->flux[0];
+        o->flux[1] = j->flux[1];
+        o->flux[2] = j->flux[7];
+        o->flux[3] = j->flux[8];
+        o->flux[4] = j->flux[9];
+        o->active_fluid = j->n_fluid;
+        o->active_ad = j->n_ad;
+        o->t_submit = j->t_submit;
+        o->t_admit = j->t_admit;
+        o->t_finish = j->t_finish;
+        o->u = j->u.empty() ? nullptr : j->u.data();
+        o->c = j->c.empty() ? nullptr : j->c.data();
+    }
+};
+
+extern "C" {
+
+size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage)
+{
+    if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_FP16_SHIFTED)
+        return 0;
+    return layout_of((int64_t)nx * ny, storage).total;
+}
+
+lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server **out)
+{
+    if (!ctx || !cfg || !out)
+        return set_err(ctx, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    lbm_server_cfg c = *cfg;
+    if (c.storage < LBM_FP32 || c.storage > LBM_FP16_SHIFTED)
+        return set_err(ctx, LBM_EINVAL, "server storage must be FP32, FP32_SHIFTED or FP16_SHIFTED");
+    if (c.max_slots == 0)
+        c.max_slots = 32;
+    if (c.max_slots < 1 || c.max_slots > lbmk::SRV_MAX_SLOTS)
+        return set_err(ctx, LBM_EINVAL, "max_slots must be in 1..64");
+    if (c.check_every == 0)
+        c.check_every = 100;
+    if (c.check_every < 2 || (c.check_every & 1) || c.check_every > 1000)
+        return set_err(ctx, LBM_EINVAL, "check_every must be even and in 2..1000");
+    if (c.grid_blocks == 0)
+        c.grid_blocks = 2048;
+    if (c.grid_blocks < 1 || c.grid_blocks > 65536)
+        return set_err(ctx, LBM_EINVAL, "grid_blocks must be in 1..65536");
+    if (c.inflight == 0)
+        c.inflight = 2;
+    if (c.inflight < 1 || c.inflight > 6)
+        return set_err(ctx, LBM_EINVAL, "inflight must be in 1..6");
+    if (c.prep_threads == 0)
+        c.prep_threads = 2;
+    if (c.prep_threads < 1 || c.prep_threads > 16)
+        return set_err(ctx, LBM_EINVAL, "prep_threads must be in 1..16");
+    if (c.pool_bytes < (size_t)1 << 16)
+        return set_err(ctx, LBM_EINVAL, "pool_bytes must be at least 64 KiB");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return hip_err(ctx, e, "set device");
+    std::unique_ptr<lbm_server> s(new lbm_server());
+    s->device = ctx->device;
+    s->cfg = c;
+    s->K = c.check_every;
+    s->window = c.stall_checks < 0 ? 0
+                                   : (c.stall_checks > 0 ? c.stall_checks
+                                                         : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
+    s->blocks = c.grid_blocks;
+    s->depth = c.inflight;
+    s->t0 = std::chrono::steady_clock::now();
+    // tiles: each holds 256 nodes of at least 54 pool bytes; ragged tiles at
+    // the domain edges add at most ntx + nty per request
+    const size_t min_tile = 256 * 54;
+    const size_t pc = c.pool_bytes / min_tile + (size_t)c.max_slots * 1024 + 1024;
+    s->part_cap = (int)std::min<size_t>(pc, (size_t)1 << 30);
+    auto cleanup = [&](lbm_status st) {
+        lbm_server_destroy(s.release());
+        return st;
+    };
+    auto dmalloc = [&](void **p, size_t bytes) -> hipError_t {
+        hipError_t r = hipMalloc(p, bytes);
+        if (r != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+        }
+        return r;
+    };
+    if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
+        return cleanup(hip_err(ctx, e, "server stream"));
+    if (dmalloc((void **)&s->pool, c.pool_bytes) != hipSuccess)
+        return cleanup(set_err(ctx, LBM_ENOMEM, "device pool allocation failed"));
+    if (dmalloc((void **)&s->d_slots, sizeof(lbmk::SrvSlot) * lbmk::SRV_MAX_SLOTS) != hipSuccess ||
+        dmalloc((void **)&s->d_tab, sizeof(lbmk::SrvTable)) != hipSuccess ||
+        dmalloc((void **)&s->d_ctrl, sizeof(lbmk::Ctrl) * lbmk::SRV_MAX_SLOTS) != hipSuccess ||
+        dmalloc((void **)&s->d_part, sizeof(unsigned long long) * 2 * (size_t)s->part_cap) != hipSuccess ||
+        dmalloc((void **)&s->d_partials, sizeof(double) * 5 * lbmk::FLUX_BLOCKS) != hipSuccess ||
+        dmalloc((void **)&s->d_out, sizeof(double) * 10 * lbmk::SRV_MAX_SLOTS) != hipSuccess)
+        return cleanup(set_err(ctx, LBM_ENOMEM, "server device allocation failed"));
+    if ((e = hipMemsetAsync(s->d_slots, 0, sizeof(lbmk::SrvSlot) * lbmk::SRV_MAX_SLOTS, s->stream)) !=
+            hipSuccess ||
+        (e = hipMemsetAsync(s->d_tab, 0, sizeof(lbmk::SrvTable), s->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(s->d_ctrl, 0, sizeof(lbmk::Ctrl) * lbmk::SRV_MAX_SLOTS, s->stream)) !=
+            hipSuccess ||
+        (e = hipMemsetAsync(s->d_out, 0, sizeof(double) * 10 * lbmk::SRV_MAX_SLOTS, s->stream)) != hipSuccess)
+        return cleanup(hip_err(ctx, e, "server init"));
+    s->alloc.reset(c.pool_bytes);
+    if ((e = s->up_ring.init((size_t)32 << 20)) != hipSuccess ||
+        (e = s->res_ring.init((size_t)64 << 20)) != hipSuccess)
+        return cleanup(hip_err(ctx, e, "pinned staging"));
+    if ((e = hipHostMalloc((void **)&s->h_snap, sizeof(lbmk::Ctrl) * lbmk::SRV_MAX_SLOTS * lbm_server::RING,
+                           hipHostMallocDefault)) != hipSuccess) {
+        s->h_snap = nullptr;
+        return cleanup(hip_err(ctx, e, "pinned snapshots"));
+    }
+    for (int k = 0; k < lbm_server::RING; ++k)
+        if ((e = hipEventCreateWithFlags(&s->ev_snap[k], hipEventDisableTiming)) != hipSuccess)
+            return cleanup(hip_err(ctx, e, "event"));
+    if (!c.direct_launch) {
+        // one chunk, captured once: it reads the slot table at run time
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
+            return cleanup(hip_err(ctx, e, "server init"));
+        if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return cleanup(hip_err(ctx, e, "graph capture"));
+        hipError_t le = s->enqueue_chunk();
+        e = hipStreamEndCapture(s->stream, &s->graph);
+        if (le != hipSuccess || e != hipSuccess)
+            return cleanup(hip_err(ctx, le != hipSuccess ? le : e, "graph capture"));
+        if ((e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            s->exec = nullptr;
+            return cleanup(hip_err(ctx, e, "graph instantiate"));
+        }
+    }
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
+        return cleanup(hip_err(ctx, e, "server init"));
+    lbm_server *sp = s.get();
+    s->res_ring.reclaim = [sp](void *o) { sp->complete(static_cast<Job *>(o)); };
+    for (int k = 0; k < c.prep_threads; ++k)
+        s->preps.emplace_back([sp] { sp->prep_loop(); });
+    s->worker = std::thread([sp] { sp->work_loop(); });
+    *out = s.release();
+    return LBM_OK;
+}
+
+lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *ticket)
+{
+    if (!s || !r)
+        return LBM_EINVAL;
+    std::unique_ptr<Job> j(new Job());
+    j->req = *r;
+    j->req.cls = nullptr;
+    const int64_t N = (int64_t)r->nx * r->ny;
+    std::string m = request_problem(*r);
+    if (m.empty()) {
+        j->lay = layout_of(N, s->cfg.storage);
+        if (j->lay.total > s->cfg.pool_bytes ||
+            lbmk::make_geo(r->nx, r->ny, 1).ntiles > s->part_cap)
+            m = "request larger than the server pool";
+        else if (r->cls)
+            j->cls.assign(r->cls, r->cls + N);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed) {
+        snprintf(s->err_buf, sizeof(s->err_buf), "%s", s->err.c_str());
+        return LBM_EDEVICE;
+    }
+    if (s->stopping)
+        return LBM_EBUSY;
+    if (!m.empty()) {
+        snprintf(s->err_buf, sizeof(s->err_buf), "%s", m.c_str());
+        return LBM_EINVAL;
+    }
+    j->ticket = s->next_ticket++;
+    j->t_submit = now_s(s->t0);
+    if (ticket)
+        *ticket = j->ticket;
+    Job *jp = j.get();
+    s->all[jp->ticket] = std::move(j);
+    ++s->n_submitted;
+    s->prep_q.push_back(jp);
+    s->cv_prep.notify_one();
+    return LBM_OK;
+}
+
+lbm_status lbm_server_poll(lbm_server *s, lbm_result *out, int max, int *n_out, double wait_s)
+{
+    if (!s || (!out && max > 0) || !n_out)
+        return LBM_EINVAL;
+    *n_out = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->finished.empty() && wait_s > 0)
+        s->cv_done.wait_for(lk, std::chrono::duration<double>(wait_s), [&] { return !s->finished.empty(); });
+    int n = 0;
+    while (n < max && !s->finished.empty()) {
+        Job *j = s->finished.front();
+        s->finished.pop_front();
+        s->delivered[j->ticket] = j;
+        s->fill_result(j, out + n);
+        ++n;
+    }
+    *n_out = n;
+    return LBM_OK;
+}
+
+void lbm_result_release(lbm_server *s, lbm_result *r)
+{
+    if (!s || !r)
+        return;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->delivered.find(r->ticket);
+    if (it == s->delivered.end())
+        return;
+    s->delivered.erase(it);
+    s->all.erase(r->ticket);
+    r->u = nullptr;
+    r->c = nullptr;
+}
+
+lbm_status lbm_server_drain(lbm_server *s, double timeout_s)
+{
+    if (!s)
+        return LBM_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto done = [&] { return s->n_finished == s->n_submitted; };
+    if (timeout_s > 0) {
+        if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+            return LBM_EBUSY;
+    } else {
+        s->cv_done.wait(lk, done);
+    }
+    return s->failed ? LBM_EDEVICE : LBM_OK;
+}
+
+lbm_status lbm_server_stats(lbm_server *s, lbm_server_stats_t *o)
+{
+    if (!s || !o)
+        return LBM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(o, 0, sizeof(*o));
+    o->submitted = s->n_submitted;
+    o->finished = s->n_finished;
+    o->rejected = s->n_rejected;
+    o->active = s->n_active;
+    o->queued = (int64_t)(s->prep_q.size() + s->ready.size());
+    o->chunks = s->chunks;
+    o->pool_bytes = s->cfg.pool_bytes;
+    o->pool_used = s->alloc.used;
+    o->pool_peak = s->alloc.peak;
+    o->lattice_updates = s->updates;
+    o->busy_seconds = s->busy;
+    o->clock = now_s(s->t0);
+    return LBM_OK;
+}
+
+const char *lbm_server_error(lbm_server *s)
+{
+    if (!s)
+        return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed)
+        snprintf(s->err_buf, sizeof(s->err_buf), "%s", s->err.c_str());
+    return s->err_buf;
+}
+
+void lbm_server_destroy(lbm_server *s)
+{
+    if (!s)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_prep.notify_all();
+    s->cv_work.notify_all();
+    for (auto &t : s->preps)
+        if (t.joinable())
+            t.join();
+    if (s->worker.joinable())
+        s->worker.join();
+    if (s->stream)
+        (void)hipStreamSynchronize(s->stream);
+    s->res_ring.reclaim = nullptr;
+    s->up_ring.destroy();
+    s->res_ring.destroy();
+    if (s->exec)
+        (void)hipGraphExecDestroy(s->exec);
+    if (s->graph)
+        (void)hipGraphDestroy(s->graph);
+    for (int k = 0; k < lbm_server::RING; ++k)
+        if (s->ev_snap[k])
+            (void)hipEventDestroy(s->ev_snap[k]);
+    if (s->h_snap)
+        (void)hipHostFree(s->h_snap);
+    void *bufs[] = {s->pool, s->d_slots, s->d_tab, s->d_ctrl, s->d_part, s->d_partials, s->d_out};
+    for (void *p : bufs)
+        if (p)
+            (void)hipFree(p);
+    if (s->stream)
+        (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+} // extern "C"
