@@ -5,6 +5,7 @@
 // not published; the generators below are seeded stand-ins specified in
 // integer arithmetic so that any two implementations agree byte for byte.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <deque>
@@ -300,12 +301,35 @@ void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, 
     links_impl<false>(g, cls, out, lo, hi);
 }
 
+// The FLUID node of each column x that samples the column's shift reference:
+// the one nearest the middle of the cross-section (|y - ny/2| + |z - nz/2|),
+// the lowest index among equals; -1 for a column without FLUID nodes.
+static std::vector<int64_t> reference_nodes(const lbm_grid &g, const uint8_t *cls)
+{
+    std::vector<int64_t> r((size_t)g.nx, -1);
+    std::vector<int> best((size_t)g.nx, INT32_MAX);
+    const int cy = g.ny / 2, cz = g.nz / 2;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+            const int dist = abs(y - cy) + abs(z - cz);
+            for (int x = 0; x < g.nx; ++x) {
+                const int64_t n = idx3(g, x, y, z);
+                if (cls[n] == LBM_FLUID && dist < best[x]) {
+                    best[x] = dist;
+                    r[x] = n;
+                }
+            }
+        }
+    return r;
+}
+
 void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t lo, int64_t hi)
 {
     const int qf = fluid_dirs(g.nz).q, qa = ad_dirs(g.nz).q;
     std::vector<uint32_t> lf((size_t)(hi - lo)), la((size_t)(hi - lo));
     links_fluid(g, cls, lf.data(), lo, hi);
     links_ad(g, cls, la.data(), lo, hi);
+    const std::vector<int64_t> ref = reference_nodes(g, cls);
     for (int64_t n = lo; n < hi; ++n) {
         const uint8_t k = cls[n];
         uint32_t d = 0;
@@ -319,6 +343,8 @@ void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t l
         }
         if (k == LBM_BIOFILM)
             d |= 1u << lbmk::desc_biofilm_bit(qf, qa);
+        if (n == ref[(size_t)(n % g.nx)])
+            d |= 1u << lbmk::desc_ref_bit(qf, qa);
         desc[n - lo] = d;
     }
 }

@@ -81,24 +81,36 @@ struct D3Q7 {
 };
 
 // ---------------------------------------------------------- storage forms
+// tile_mean: the residual check compares tile means instead of nodes (see
+// check_residual).  colref: the shift reference is a per-column array that
+// moves at checks (see lbm_kernels.h); otherwise it is the constant 1 (fluid)
+// or c_ref (substrate).
 struct SF64 {
     typedef double T;
     typedef double C;
     static constexpr bool shifted = false;
+    static constexpr bool tile_mean = false;
+    static constexpr bool colref = false;
 };
 struct SF32 {
     typedef float T;
     typedef float C;
     static constexpr bool shifted = false;
+    static constexpr bool tile_mean = false;
+    static constexpr bool colref = false;
 };
 struct SF32S {
     typedef float T;
     typedef float C;
     static constexpr bool shifted = true;
+    static constexpr bool tile_mean = false;
+    static constexpr bool colref = false;
 };
 struct SF16S {
-    typedef _Float16 T; // round-to-nearest-even on store
+    typedef _Float16 T; // stores round stochastically (pop_value)
     typedef float C;
+    static constexpr bool tile_mean = true;
+    static constexpr bool colref = true; // column reference moves at checks
     static constexpr bool shifted = true;
 };
 
@@ -233,6 +245,60 @@ __device__ __forceinline__ unsigned long long dbits(double v)
     return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
+// Sums over the block of four doubles (valid in thread 0), in a fixed order.
+__device__ __forceinline__ void block_sum4(double &a, double &b, double &c, double &d)
+{
+    __shared__ double sm[4][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+        d += __shfl_xor(d, off);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sm[wv][0] = a;
+        sm[wv][1] = b;
+        sm[wv][2] = c;
+        sm[wv][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = ((sm[0][0] + sm[1][0]) + sm[2][0]) + sm[3][0];
+        b = ((sm[0][1] + sm[1][1]) + sm[2][1]) + sm[3][1];
+        c = ((sm[0][2] + sm[1][2]) + sm[2][2]) + sm[3][2];
+        d = ((sm[0][3] + sm[1][3]) + sm[2][3]) + sm[3][3];
+    }
+    __syncthreads();
+}
+
+// Residual of one tile at a check step from the per-node changes (dx, dy,
+// dz) of an active node (act; zeros otherwise): the largest change of any
+// node, or -- with FP16 storage, whose stochastic rounding adds zero-mean
+// per-node noise that would set a floor above ordinary tolerances -- the
+// largest change of the tile mean over its active nodes, which averages the
+// noise out and keeps the smooth evolution of the field.
+template <class S>
+__device__ __forceinline__ double check_residual(bool act, double dx, double dy, double dz)
+{
+    if constexpr (S::tile_mean) {
+        double n = act ? 1.0 : 0.0;
+        block_sum4(dx, dy, dz, n);
+        if (threadIdx.x != 0 || n == 0.0)
+            return 0.0;
+        const double r = fmax(fmax(fabs(dx), fabs(dy)), fabs(dz)) / n;
+        return (dx != dx || dy != dy || dz != dz) ? __longlong_as_double(0x7ff8000000000000ll) : r;
+    } else {
+        if (!act)
+            return 0.0;
+        double m = fabs(dx);
+        m = (fabs(dy) > m || dy != dy) ? fabs(dy) : m;
+        m = (fabs(dz) > m || dz != dz) ? fabs(dz) : m;
+        return dx != dx ? __longlong_as_double(0x7ff8000000000000ll) : m;
+    }
+}
+
 // ------------------------------------------------------------ fluid step
 // Pull rules per direction i (source s = n - c_i), first match wins:
 //   inlet  (x == 0, c_ix = +1):   h_i = h*_opp(n) + 6 w_i u_in
@@ -254,12 +320,24 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
     T *__restrict__ dst = static_cast<T *>(a.dst);
     C ux = C(0), uy = C(0), uz = C(0);
     C f[L::Q];
+    // column references: this column (r0), the neighbours' offsets from it
+    // (dm: x - 1, dp: x + 1) and the reference of the written buffer (rd)
+    C r0 = C(1), dm = C(0), dp = C(0), rd = C(1), rho = C(0);
+    if constexpr (S::colref) {
+        if (act) {
+            r0 = a.ref_src[p.x];
+            dm = (p.x > 0 ? a.ref_src[p.x - 1] : r0) - r0;
+            dp = (p.x < a.g.nx - 1 ? a.ref_src[p.x + 1] : r0) - r0;
+            rd = a.ref_dst[p.x];
+        }
+    }
     if (act) {
         const long long n = p.n;
         // One unconditional load per direction from a selected address (the
         // source node, or this node's opposite population when the link is
         // reversed), then the inlet/outlet terms by select: the loads carry no
-        // branches between them and issue back to back.
+        // branches between them and issue back to back.  Values are taken
+        // relative to this column's reference r0.
         const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
         const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
         C ox = C(0), oy = C(0), oz = C(0); // u* of the stored state (outlet column)
@@ -276,7 +354,7 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
                 if (L::cz[i] == 1) qz += v;
                 if (L::cz[i] == -1) qz -= v;
             }
-            const C ir = C(1) / (S::shifted ? C(1) + r : r);
+            const C ir = C(1) / (S::shifted ? r0 + r : r);
             ox = qx * ir;
             oy = qy * ir;
             oz = qz * ir;
@@ -294,12 +372,19 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             const long long off = cx + cy * row + cz * plane;
             const long long idx = rev ? (long long)o * N + n : (long long)i * N + n - off;
             C v = ld<S>(src + idx);
+            if constexpr (S::colref) {
+                // a value streamed from column x - c_ix, re-referenced to r0
+                if (cx == 1)
+                    v = rev ? v : v + C(L::w[i]) * dm;
+                if (cx == -1)
+                    v = rev ? v : v + C(L::w[i]) * dp;
+            }
             if (cx == 1)
                 v = in_i ? v + C(6.0 * L::w[i]) * C(a.u_in) : v;
             if (cx == -1) {
                 const C cu = -ox + C(cy) * oy + C(cz) * oz;
                 const C even = C(4.5) * cu * cu - ousq;
-                v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(0) : C(1)) + even) - v : v;
+                v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - v : v;
             }
             f[i] = v;
         }
@@ -314,7 +399,7 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             if (L::cz[i] == 1) jz += f[i];
             if (L::cz[i] == -1) jz -= f[i];
         }
-        const C rho = S::shifted ? C(1) + rs : rs;
+        rho = S::shifted ? r0 + rs : rs;
         const C inv = C(1) / rho;
         ux = jx * inv;
         uy = jy * inv;
@@ -335,6 +420,8 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             // minus the shift w_i when stored shifted (rs = rho - shift).
             const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
             f[i] = f[i] + om * (feq - f[i]);
+            if constexpr (S::colref)
+                f[i] += C(L::w[i]) * (r0 - rd); // to the written buffer's reference
         }
     } else {
 #pragma unroll
@@ -351,28 +438,32 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             st_pop<S, NT>(dst + (long long)i * N + p.n, f[i], rng);
     }
     if constexpr (MODE == MODE_CHECK) {
-        unsigned long long rb = 0ull, ub = 0ull;
+        unsigned long long ub = 0ull;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
         if (act) {
             C *up = static_cast<C *>(a.uprev);
-            double dm = fabs((double)ux - (double)up[p.n]);
-            double t = fabs((double)uy - (double)up[N + p.n]);
-            dm = (t > dm || t != t) ? t : dm;
+            dx = (double)ux - (double)up[p.n];
+            dy = (double)uy - (double)up[N + p.n];
             double um = fmax(fabs((double)ux), fabs((double)uy));
             if (L::DIM == 3) {
-                t = fabs((double)uz - (double)up[2 * N + p.n]);
-                dm = (t > dm || t != t) ? t : dm;
+                dz = (double)uz - (double)up[2 * N + p.n];
                 um = fmax(um, fabs((double)uz));
             }
             if (ux != ux || uy != uy || uz != uz)
-                dm = um = __longlong_as_double(0x7ff8000000000000ll);
-            rb = dbits(dm * a.inv_uin);
+                um = __longlong_as_double(0x7ff8000000000000ll);
             ub = dbits(um);
             up[p.n] = ux;
             up[N + p.n] = uy;
             if (L::DIM == 3)
                 up[2 * N + p.n] = uz;
+            if constexpr (S::colref) {
+                constexpr int REF = L::Q + (L::DIM == 3 ? 7 : 5) + 1;
+                if ((d >> REF) & DT(1))
+                    a.ref_out[p.x] = rho;
+            }
         }
-        block_max_commit(rb, ub, part_r, part_u);
+        const double r = check_residual<S>(act, dx, dy, dz);
+        block_max_commit(dbits(r * a.inv_uin), ub, part_r, part_u);
     }
 }
 
@@ -411,9 +502,20 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
     T *__restrict__ dst = static_cast<T *>(a.dst);
     C cfull = C(0);
     C g[L::Q];
+    C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0; // column references, as in the fluid
+    if constexpr (S::colref) {
+        if (act) {
+            r0 = a.ref_src[p.x];
+            dm = (p.x > 0 ? a.ref_src[p.x - 1] : r0) - r0;
+            dp = (p.x < a.g.nx - 1 ? a.ref_src[p.x + 1] : r0) - r0;
+            rd = a.ref_dst[p.x];
+        }
+    }
     if (act) {
         const long long n = p.n;
         const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
+        // Dirichlet values relative to this column's reference
+        const C cin_s = C(a.c_in - (double)r0), cout_s = C(a.c_out - (double)r0);
         const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
@@ -431,17 +533,30 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
             const long long idx = rev ? (long long)o * N + n
                                       : (copy_i ? (long long)i * N + n : (long long)i * N + n - off);
             C v = ld<S>(src + idx);
-            if (cx == 1)
-                v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
-            if (cx == -1)
-                v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
+            if constexpr (S::colref) {
+                if (cx == 1)
+                    v = rev ? v : v + C(L::w[i]) * dm;
+                if (cx == -1)
+                    v = (rev || copy_i) ? v : v + C(L::w[i]) * dp;
+            }
+            if constexpr (S::colref) {
+                if (cx == 1)
+                    v = in_i ? C(2.0 * L::w[i]) * cin_s - v : v;
+                if (cx == -1)
+                    v = abb_i ? C(2.0 * L::w[i]) * cout_s - v : v;
+            } else {
+                if (cx == 1)
+                    v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
+                if (cx == -1)
+                    v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
+            }
             g[i] = v;
         }
         C cs = C(0);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             cs += g[i];
-        cfull = S::shifted ? C(a.c_ref) + cs : cs;
+        cfull = S::shifted ? r0 + cs : cs;
         const C *U = static_cast<const C *>(a.u);
         const C ux = U[n], uy = U[N + n];
         const C uz = (L::DIM == 3) ? U[2 * N + n] : C(0);
@@ -458,6 +573,8 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
             if (L::cz[i] == -1) cu -= uz;
             const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
             g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+            if constexpr (S::colref)
+                g[i] += C(L::w[i]) * (r0 - rd);
         }
     } else {
 #pragma unroll
@@ -473,16 +590,18 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
             st_pop<S, NT>(dst + (long long)i * N + p.n, g[i], rng);
     }
     if constexpr (MODE == MODE_CHECK) {
-        unsigned long long rb = 0ull;
+        double dc = 0.0;
         if (act) {
             C *cp = static_cast<C *>(a.cprev);
-            double dv = fabs((double)cfull - (double)cp[p.n]);
-            if (cfull != cfull)
-                dv = __longlong_as_double(0x7ff8000000000000ll);
-            rb = dbits(dv * a.inv_cin);
+            dc = (double)cfull - (double)cp[p.n];
             cp[p.n] = cfull;
+            if constexpr (S::colref) {
+                if ((d >> (BIO + 1)) & DT(1))
+                    a.ref_out[p.x] = cfull;
+            }
         }
-        block_max_commit(rb, 0ull, part_r, part_u);
+        const double r = check_residual<S>(act, dc, 0.0, 0.0);
+        block_max_commit(dbits(r * a.inv_cin), 0ull, part_r, part_u);
     }
 }
 
@@ -540,7 +659,8 @@ __global__ void __launch_bounds__(256) k_ad_init(typename S::T *gp, const DT *de
 
 template <class L, class S, class DT, class O>
 __global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, const DT *desc,
-                                                       long long N, O *U, O *RHO)
+                                                       long long N, const float *ref, int nx, O *U,
+                                                       O *RHO)
 {
     const long long n = blockIdx.x * 256ll + threadIdx.x;
     if (n >= N)
@@ -560,7 +680,7 @@ __global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, co
             if (L::cz[i] == -1) jz -= v;
         }
     }
-    const O rho = act ? (S::shifted ? O(1) + rs : rs) : O(0);
+    const O rho = act ? (S::shifted ? O(ref[n % nx]) + rs : rs) : O(0);
     const O inv = act ? O(1) / rho : O(0);
     if (U) {
         U[n] = jx * inv;
@@ -574,8 +694,8 @@ __global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, co
 
 template <class L, int QF, class S, class DT, class O>
 __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, const DT *desc,
-                                                    long long N, double c_ref, double k_sink,
-                                                    O *Cout)
+                                                    long long N, const float *ref, int nx,
+                                                    double k_sink, O *Cout)
 {
     constexpr int ACT = QF - 1 + L::Q;
     constexpr int BIO = ACT + 1;
@@ -592,45 +712,50 @@ __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, cons
     for (int i = 0; i < L::Q; ++i)
         s += static_cast<O>(gp[(long long)i * N + n]);
     if (S::shifted)
-        s += O(c_ref);
+        s += O(ref[n % nx]);
     const O k = ((d >> BIO) & DT(1)) ? O(k_sink) : O(0);
     Cout[n] = s / (O(1) - k);
 }
 
 template <class L, class S, class DT>
 __global__ void __launch_bounds__(256) k_pops_export(const typename S::T *h, const DT *desc,
-                                                      long long N, int act_bit, double ref,
-                                                      double *out)
+                                                      long long N, int act_bit, const float *ref,
+                                                      int nx, double *out)
 {
     const long long n = blockIdx.x * 256ll + threadIdx.x;
     if (n >= N)
         return;
     const bool act = ((desc[n] >> act_bit) & DT(1)) != 0;
+    const double r = S::shifted ? (double)ref[n % nx] : 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const double v = static_cast<double>(h[(long long)i * N + n]);
-        out[(long long)i * N + n] = act ? (S::shifted ? v + L::w[i] * ref : v) : 0.0;
+        out[(long long)i * N + n] = act ? v + L::w[i] * r : 0.0;
     }
 }
 
 template <class L, class S, class DT>
 __global__ void __launch_bounds__(256) k_pops_import(typename S::T *h, const DT *desc, long long N,
-                                                      int act_bit, double ref, const double *in)
+                                                      int act_bit, const float *ref, int nx,
+                                                      const double *in)
 {
     const long long n = blockIdx.x * 256ll + threadIdx.x;
     if (n >= N)
         return;
     const bool act = ((desc[n] >> act_bit) & DT(1)) != 0;
+    const double r = S::shifted ? (double)ref[n % nx] : 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const double v = in[(long long)i * N + n];
-        const double s = S::shifted ? v - L::w[i] * ref : v;
-        h[(long long)i * N + n] = static_cast<typename S::T>(act ? s : 0.0);
+        const double v = in[(long long)i * N + n] - L::w[i] * r;
+        h[(long long)i * N + n] = static_cast<typename S::T>(act ? v : 0.0);
     }
 }
 
-template <class S>
-__global__ void __launch_bounds__(256) k_pops_set_nodes(typename S::T *h, long long N, int Q,
+// vals: unshifted values [L::Q], stored at the listed nodes (ref may be null
+// when every value is 0)
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_pops_set_nodes(typename S::T *h, long long N,
+                                                        const float *ref, int nx,
                                                         const long long *idx, int count,
                                                         const double *vals)
 {
@@ -638,8 +763,27 @@ __global__ void __launch_bounds__(256) k_pops_set_nodes(typename S::T *h, long l
     if (k >= count)
         return;
     const long long n = idx[k];
-    for (int i = 0; i < Q; ++i)
-        h[(long long)i * N + n] = static_cast<typename S::T>(vals[i]);
+    const double r = (S::shifted && ref) ? (double)ref[n % nx] : 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        h[(long long)i * N + n] = static_cast<typename S::T>(vals[i] - L::w[i] * r);
+}
+
+__global__ void __launch_bounds__(256) k_ref_fill(float *ref, int n, float v)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x < n)
+        ref[x] = v;
+}
+
+__global__ void __launch_bounds__(256) k_ref_roll(const Ctrl *ctrl, float *cur, const float *next,
+                                                  int n)
+{
+    if (ctrl->stop != STOP_RUN)
+        return;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x < n)
+        cur[x] = next[x];
 }
 
 // ---------------------------------------------------------------- fluxes
@@ -652,8 +796,9 @@ __global__ void __launch_bounds__(256) k_pops_set_nodes(typename S::T *h, long l
 template <class LF, class LA, class S, class DT>
 __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                                                         const typename S::T *gp, const DT *desc,
-                                                        Geo g, double u_in, double c_in,
-                                                        double c_ref, double k_sink, int outlet,
+                                                        Geo g, const float *ref_f,
+                                                        const float *ref_g, double u_in,
+                                                        double c_in, double k_sink, int outlet,
                                                         double c_out, double *part)
 {
     constexpr int ACT = LF::Q - 1 + LA::Q;
@@ -663,8 +808,6 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
     const long long lo = blockIdx.x * per;
     const long long hi = lo + per < N ? lo + per : N;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double fs = S::shifted ? 1.0 : 0.0;
-    const double gs = S::shifted ? c_ref : 0.0;
     for (long long n = lo + threadIdx.x; n < hi; n += 256) {
         const int x = (int)(n % g.nx);
         if (x != 0 && x != g.nx - 1) {
@@ -672,6 +815,8 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                 continue;
         }
         const DT d = desc[n];
+        const double fs = (S::shifted && f) ? (double)ref_f[x] : 0.0;
+        const double gs = (S::shifted && gp) ? (double)ref_g[x] : 0.0;
         if (f && (d & DT(1)) && (x == 0 || x == g.nx - 1)) {
             double r = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
 #pragma unroll
@@ -902,6 +1047,9 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
             a.inv_uin = sl.inv_uin;
             a.streaming_stores = 0;
             a.step = step;
+            a.ref_src = sl.ref_cur;
+            a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+            a.ref_out = sl.ref_next;
             fluid_tile<D2Q9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
         } else {
             AdArgs a;
@@ -921,6 +1069,11 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
             a.outlet = sl.outlet;
             a.streaming_stores = 0;
             a.step = step;
+            a.c_in = sl.c_in;
+            a.c_out = sl.c_out;
+            a.ref_src = sl.ref_cur;
+            a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+            a.ref_out = sl.ref_next;
             ad_tile<D2Q5, 9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
         }
     }
@@ -944,6 +1097,22 @@ __global__ void __launch_bounds__(256) k_srv_decide(const SrvSlot *__restrict__ 
     reduce_parts(part + b0, part + part_cap + b0, n, mr, mu);
     if (threadIdx.x == 0)
         decide_apply(c, mr, mu);
+}
+
+// Reference roll of every running request: one block per table entry.
+__global__ void __launch_bounds__(256) k_srv_ref_roll(const SrvSlot *__restrict__ slots,
+                                                      const SrvTable *__restrict__ tab,
+                                                      const Ctrl *ctrl)
+{
+    const int e = blockIdx.x;
+    if (e >= tab->n_active)
+        return;
+    const int sid = tab->slot[e];
+    const SrvSlot &sl = slots[sid];
+    if (sl.phase == SRV_IDLE || ctrl[sid].stop != STOP_RUN)
+        return;
+    for (int x = threadIdx.x; x < sl.g.nx; x += 256)
+        sl.ref_cur[x] = sl.ref_next[x];
 }
 
 __global__ void k_srv_slot_set(SrvSlot *slots, int sid, SrvSlot v)
@@ -1004,6 +1173,10 @@ size_t compute_bytes(int s)
 bool storage_shifted(int s)
 {
     return s == ST_F32S || s == ST_F16S;
+}
+bool storage_moving_ref(int s)
+{
+    return s == ST_F16S;
 }
 
 static inline dim3 flat_grid(long long N)
@@ -1131,7 +1304,7 @@ hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void 
 }
 
 hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
-                        void *U, void *RHO, int out_double, hipStream_t st)
+                        const float *ref, void *U, void *RHO, int out_double, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1142,20 +1315,20 @@ hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, c
             if (out_double)
                 hipLaunchKernelGGL((k_fluid_export<LF, S, DT, double>), flat_grid(g.N), dim3(256), 0,
                                    st, static_cast<const typename S::T *>(f),
-                                   static_cast<const DT *>(desc), g.N, static_cast<double *>(U),
-                                   static_cast<double *>(RHO));
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx,
+                                   static_cast<double *>(U), static_cast<double *>(RHO));
             else
                 hipLaunchKernelGGL((k_fluid_export<LF, S, DT, C>), flat_grid(g.N), dim3(256), 0, st,
                                    static_cast<const typename S::T *>(f),
-                                   static_cast<const DT *>(desc), g.N, static_cast<C *>(U),
-                                   static_cast<C *>(RHO));
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx,
+                                   static_cast<C *>(U), static_cast<C *>(RHO));
             return hipGetLastError();
         });
     });
 }
 
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     double c_ref, double k_sink, void *C, int out_double, hipStream_t st)
+                     const float *ref, double k_sink, void *C, int out_double, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1164,16 +1337,15 @@ hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, con
             typedef decltype(s) S;
             typedef decltype(dt) DT;
             typedef typename S::C CT;
-            const double ref = S::shifted ? c_ref : 0.0;
             if (out_double)
                 hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, double>), flat_grid(g.N), dim3(256),
                                    0, st, static_cast<const typename S::T *>(gp),
-                                   static_cast<const DT *>(desc), g.N, ref, k_sink,
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx, k_sink,
                                    static_cast<double *>(C));
             else
                 hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, CT>), flat_grid(g.N), dim3(256), 0,
                                    st, static_cast<const typename S::T *>(gp),
-                                   static_cast<const DT *>(desc), g.N, ref, k_sink,
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx, k_sink,
                                    static_cast<CT *>(C));
             return hipGetLastError();
         });
@@ -1181,7 +1353,7 @@ hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, con
 }
 
 hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
-                       const Geo &g, double c_ref, double *out, hipStream_t st)
+                       const Geo &g, const float *ref, double *out, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1193,17 +1365,17 @@ hipError_t pops_export(int which, int dim, int storage, const void *h, const voi
             const DT *dp = static_cast<const DT *>(desc);
             if (which == 0)
                 hipLaunchKernelGGL((k_pops_export<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, 0, 1.0, out);
+                                   dp, g.N, 0, ref, g.nx, out);
             else
                 hipLaunchKernelGGL((k_pops_export<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, LF::Q - 1 + LA::Q, c_ref, out);
+                                   dp, g.N, LF::Q - 1 + LA::Q, ref, g.nx, out);
             return hipGetLastError();
         });
     });
 }
 
 hipError_t pops_import(int which, int dim, int storage, void *h, const void *desc,
-                       const Geo &g, double c_ref, const double *in, hipStream_t st)
+                       const Geo &g, const float *ref, const double *in, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1215,32 +1387,54 @@ hipError_t pops_import(int which, int dim, int storage, void *h, const void *des
             const DT *dp = static_cast<const DT *>(desc);
             if (which == 0)
                 hipLaunchKernelGGL((k_pops_import<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, 0, 1.0, in);
+                                   dp, g.N, 0, ref, g.nx, in);
             else
                 hipLaunchKernelGGL((k_pops_import<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, LF::Q - 1 + LA::Q, c_ref, in);
+                                   dp, g.N, LF::Q - 1 + LA::Q, ref, g.nx, in);
             return hipGetLastError();
         });
     });
 }
 
 hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g,
-                          const long long *idx, int count, const double *vals_q, hipStream_t st)
+                          const float *ref, const long long *idx, int count, const double *vals_q,
+                          hipStream_t st)
 {
     if (count <= 0)
         return hipSuccess;
-    const int Q = which == 0 ? (dim == 3 ? 19 : 9) : (dim == 3 ? 7 : 5);
-    return by_storage(storage, [&](auto s) {
-        typedef decltype(s) S;
-        hipLaunchKernelGGL((k_pops_set_nodes<S>), dim3((count + 255) / 256), dim3(256), 0, st,
-                           static_cast<typename S::T *>(h), g.N, Q, idx, count, vals_q);
-        return hipGetLastError();
+    return by_dim(dim, [&](auto lf, auto la, auto) {
+        return by_storage(storage, [&](auto s) {
+            typedef decltype(lf) LF;
+            typedef decltype(la) LA;
+            typedef decltype(s) S;
+            typename S::T *hp = static_cast<typename S::T *>(h);
+            if (which == 0)
+                hipLaunchKernelGGL((k_pops_set_nodes<LF, S>), dim3((count + 255) / 256), dim3(256), 0,
+                                   st, hp, g.N, ref, g.nx, idx, count, vals_q);
+            else
+                hipLaunchKernelGGL((k_pops_set_nodes<LA, S>), dim3((count + 255) / 256), dim3(256), 0,
+                                   st, hp, g.N, ref, g.nx, idx, count, vals_q);
+            return hipGetLastError();
+        });
     });
 }
 
+hipError_t ref_fill(float *ref, int n, float v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ref_fill, dim3((n + 255) / 256), dim3(256), 0, st, ref, n, v);
+    return hipGetLastError();
+}
+
+hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ref_roll, dim3((n + 255) / 256), dim3(256), 0, st, ctrl, cur, next, n);
+    return hipGetLastError();
+}
+
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
-                  const Geo &g, double u_in, double c_in, double c_ref, double k_sink, int outlet,
-                  double c_out, double *partials, double *out5, hipStream_t st)
+                  const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
+                  double k_sink, int outlet, double c_out, double *partials, double *out5,
+                  hipStream_t st)
 {
     hipError_t e = by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1251,7 +1445,7 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
             hipLaunchKernelGGL((k_flux_partials<LF, LA, S, DT>), dim3(FLUX_BLOCKS), dim3(256), 0, st,
                                static_cast<const typename S::T *>(f),
                                static_cast<const typename S::T *>(gp), static_cast<const DT *>(desc),
-                               g, u_in, c_in, c_ref, k_sink, outlet, c_out, partials);
+                               g, ref_f, ref_g, u_in, c_in, k_sink, outlet, c_out, partials);
             return hipGetLastError();
         });
     });
@@ -1299,6 +1493,12 @@ hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
 {
     hipLaunchKernelGGL(k_srv_decide, dim3(SRV_MAX_SLOTS), dim3(256), 0, st, slots, tab, ctrl, part,
                        part_cap);
+    return hipGetLastError();
+}
+
+hipError_t srv_ref_roll(const SrvSlot *slots, const SrvTable *tab, const Ctrl *ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_srv_ref_roll, dim3(SRV_MAX_SLOTS), dim3(256), 0, st, slots, tab, ctrl);
     return hipGetLastError();
 }
 

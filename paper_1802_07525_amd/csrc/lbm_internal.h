@@ -66,6 +66,7 @@ struct lbm_solver {
     void *d_cprev = nullptr;     // compute type [N]
     lbmk::Ctrl *d_ctrl = nullptr; // [2]: fluid, substrate
     unsigned long long *d_part = nullptr; // [2][2 * ntiles] per-block check maxima
+    float *d_ref = nullptr;      // column references [4][nx]: fluid cur, next; substrate cur, next
     double *d_partials = nullptr;
     double *d_out5 = nullptr;
     double *d_stage = nullptr;   // lazily sized double staging buffer

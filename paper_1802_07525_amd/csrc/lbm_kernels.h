@@ -55,9 +55,24 @@ Geo make_geo(int nx, int ny, int nz);
 //   bits QF..QF+QA-2      substrate pull source n - c_i is blocked (i = 1..QA-1)
 //   bit  QF+QA-1          node is FLUID or BIOFILM (substrate solver updates it)
 //   bit  QF+QA            node is BIOFILM (consumption)
+//   bit  QF+QA+1          node samples its column's reference (one FLUID
+//                         node per x, nearest the middle of the cross-section)
 inline int desc_ad_link_bit(int qf, int i) { return qf - 1 + i; }
 inline int desc_ad_active_bit(int qf, int qa) { return qf - 1 + qa; }
 inline int desc_biofilm_bit(int qf, int qa) { return qf + qa; }
+inline int desc_ref_bit(int qf, int qa) { return qf + qa + 1; }
+
+// Shifted storage keeps h_i = f_i - w_i R(x): R is a per-column reference
+// (density for the fluid, concentration for the substrate), one float per
+// x.  FP32 shifted storage keeps R constant (1, or c_ref); FP16 storage
+// moves it at every check to the value at the column's sample node, so that
+// the stored values stay small where the density or concentration drifts
+// along the flow.  Any R is exact: a step un-shifts each pulled value with
+// the reference of its source column and shifts its results with the
+// reference of the buffer it writes.  Protocol per chunk of K steps: step 0
+// reads with R_cur and writes with R_next; then R_cur <- R_next (roll);
+// steps 1..K-1 read and write with R_cur; the check step stores the new
+// sample values into R_next.
 
 struct FluidArgs {
     const void *src;
@@ -71,6 +86,9 @@ struct FluidArgs {
     double inv_uin; // 1 / (K |u_in|): residual scale
     int streaming_stores; // 1: non-temporal population stores (large domains)
     unsigned int step;    // step counter of this solver (stochastic rounding)
+    const float *ref_src; // column reference of src (FP16 storage only)
+    const float *ref_dst; // column reference of dst
+    float *ref_out;       // check steps: sample values for the next reference
 };
 
 struct AdArgs {
@@ -90,11 +108,21 @@ struct AdArgs {
     int outlet;     // 0 zero-gradient, 1 Dirichlet
     int streaming_stores; // 1: non-temporal population stores (large domains)
     unsigned int step;    // step counter of this solver (stochastic rounding)
+    double c_in, c_out;   // unshifted boundary values
+    const float *ref_src; // column references, as in FluidArgs
+    const float *ref_dst;
+    float *ref_out;
 };
 
 size_t storage_bytes(int storage);  // bytes per stored population
 size_t compute_bytes(int storage);  // bytes per compute-type value
 bool storage_shifted(int storage);
+bool storage_moving_ref(int storage); // column reference updated at checks
+
+// ref[0..n) = v
+hipError_t ref_fill(float *ref, int n, float v, hipStream_t st);
+// cur[0..n) = next[0..n) unless the solve has stopped (ctrl->stop)
+hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipStream_t st);
 
 hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStream_t st);
 hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t st);
@@ -106,23 +134,26 @@ hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo
 hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void *u,
                    const Geo &g, double c_init, double c_ref, hipStream_t st);
 
+// In the calls below `ref` is the column reference the stored state is
+// shifted by (float [nx]; ignored, and may be null, for unshifted storage).
+
 // Velocity (and density) of a stored fluid state.  out_double selects the
 // output type (double, else the compute type); RHO may be null.
 hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
-                        void *U, void *RHO, int out_double, hipStream_t st);
+                        const float *ref, void *U, void *RHO, int out_double, hipStream_t st);
 // Concentration of a stored substrate state (double, or the compute type).
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     double c_ref, double k_sink, void *C, int out_double, hipStream_t st);
+                     const float *ref, double k_sink, void *C, int out_double, hipStream_t st);
 
 // Stored populations <-> unshifted double [Q][N] (0 on inactive nodes).
 hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
-                       const Geo &g, double c_ref, double *out, hipStream_t st);
+                       const Geo &g, const float *ref, double *out, hipStream_t st);
 hipError_t pops_import(int which, int dim, int storage, void *h, const void *desc,
-                       const Geo &g, double c_ref, const double *in, hipStream_t st);
+                       const Geo &g, const float *ref, const double *in, hipStream_t st);
 
-// Set the populations of the listed nodes to vals[i] (stored form).
+// Set the populations of the listed nodes to the unshifted values vals[i].
 hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g,
-                          const long long *idx, int count, const double *vals_q,
+                          const float *ref, const long long *idx, int count, const double *vals_q,
                           hipStream_t st);
 
 // Deterministic FP64 fluxes: out[0..4] = fluid in, fluid out, substrate in,
@@ -130,8 +161,9 @@ hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g
 // partials: device double [5 * FLUX_BLOCKS].
 enum { FLUX_BLOCKS = 512 };
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
-                  const Geo &g, double u_in, double c_in, double c_ref, double k_sink,
-                  int outlet, double c_out, double *partials, double *out5, hipStream_t st);
+                  const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
+                  double k_sink, int outlet, double c_out, double *partials, double *out5,
+                  hipStream_t st);
 
 // part: device scratch of 2 * nparts words for the per-block check maxima
 hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,
@@ -155,9 +187,11 @@ struct SrvSlot {
     void *gp[2];      // substrate A/B (aliases of f[0], f[1])
     void *u;          // compute-type [2][N]
     void *prev;       // compute-type [2][N]
+    float *ref_cur, *ref_next; // column references [nx] of the current phase
     Geo g;
     double omega_f, u_in, inv_uin;
     double omega_a, cin_s, cout_s, c_ref, k_sink, inv_cin;
+    double c_in, c_out;
     int outlet;
     int phase;        // SRV_*
 };
@@ -178,6 +212,8 @@ hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable 
 // Stop rule for every request in tab after a check step.
 hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                       const unsigned long long *part, int part_cap, hipStream_t st);
+// Reference roll (ref_cur <- ref_next) of every running request in tab.
+hipError_t srv_ref_roll(const SrvSlot *slots, const SrvTable *tab, const Ctrl *ctrl, hipStream_t st);
 // Device-side writes of one slot entry / the whole table, in stream order.
 hipError_t srv_slot_set(SrvSlot *slots, int sid, const SrvSlot &v, hipStream_t st);
 hipError_t srv_table_set(SrvTable *tab, const SrvTable &v, hipStream_t st);

@@ -56,10 +56,10 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 // Per-request device buffers, in pool order.
 struct Layout {
-    size_t desc, f0, f1, u, prev, total;
+    size_t desc, f0, f1, u, prev, ref, total;
 };
 
-Layout layout_of(int64_t N, int storage)
+Layout layout_of(int32_t nx, int64_t N, int storage)
 {
     const size_t sb = lbmk::storage_bytes(storage);
     Layout L;
@@ -74,6 +74,8 @@ Layout layout_of(int64_t N, int storage)
     o += align_up((size_t)N * 2 * 4);
     L.prev = o;
     o += align_up((size_t)N * 2 * 4);
+    L.ref = o; // column references: current, next
+    o += align_up((size_t)nx * 2 * sizeof(float));
     L.total = o;
     return L;
 }
@@ -462,14 +464,47 @@ struct lbm_server {
     }
 
     // ----------------------------------------------------------- worker
+    // Device slot entry of request j in the given phase.
+    lbmk::SrvSlot slot_entry(const Job *j, int phase) const
+    {
+        char *base = pool + j->off;
+        const lbm_request &r = j->req;
+        const double c_ref = lbmk::storage_shifted(cfg.storage) ? r.c_in : 0.0;
+        lbmk::SrvSlot s{};
+        s.desc = base + j->lay.desc;
+        s.f[0] = base + j->lay.f0;
+        s.f[1] = base + j->lay.f1;
+        s.gp[0] = s.f[0]; // the substrate takes the place of the fluid
+        s.gp[1] = s.f[1];
+        s.u = base + j->lay.u;
+        s.prev = base + j->lay.prev;
+        s.ref_cur = reinterpret_cast<float *>(base + j->lay.ref);
+        s.ref_next = s.ref_cur + r.nx;
+        s.g = j->geo;
+        s.omega_f = 1.0 / r.tau;
+        s.u_in = r.u_in;
+        s.inv_uin = 1.0 / ((double)K * fabs(r.u_in));
+        s.omega_a = 1.0 / (0.5 + r.D / (1.0 / 3.0)); // as the single solve: D / c_s^2
+        s.cin_s = r.c_in - c_ref;
+        s.cout_s = r.c_out - c_ref;
+        s.c_ref = c_ref;
+        s.k_sink = r.k_sink;
+        s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
+        s.c_in = r.c_in;
+        s.c_out = r.c_out;
+        s.outlet = r.outlet;
+        s.phase = phase;
+        return s;
+    }
+
     hipError_t admit(Job *j, int sid)
     {
         hipError_t e;
         const int64_t N = j->geo.N;
         const int storage = cfg.storage;
         char *base = pool + j->off;
-        void *desc = base + j->lay.desc, *f0 = base + j->lay.f0, *f1 = base + j->lay.f1;
-        void *u = base + j->lay.u, *prev = base + j->lay.prev;
+        void *desc = base + j->lay.desc, *f0 = base + j->lay.f0;
+        void *prev = base + j->lay.prev;
         char *stage;
         if ((e = up_ring.acquire((size_t)N * 2, &stage, nullptr)) != hipSuccess)
             return e;
@@ -480,36 +515,19 @@ struct lbm_server {
             return e;
         if ((e = hipMemsetAsync(d_out + 10 * sid, 0, 10 * sizeof(double), stream)) != hipSuccess)
             return e;
+        float *ref = reinterpret_cast<float *>(base + j->lay.ref);
+        if ((e = lbmk::ref_fill(ref, 2 * j->req.nx, 1.0f, stream)) != hipSuccess)
+            return e;
         if ((e = lbmk::fluid_init(2, storage, f0, desc, j->geo, stream)) != hipSuccess)
             return e;
-        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, prev, nullptr, 0, stream)) != hipSuccess)
+        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, ref, prev, nullptr, 0, stream)) !=
+            hipSuccess)
             return e;
         j->t_max = (j->req.max_iter + K - 1) / K * (long long)K;
         if ((e = lbmk::ctrl_reset(d_ctrl + sid, j->req.tol, window, 1, K, nullptr, 0, stream, j->t_max)) !=
             hipSuccess)
             return e;
-        lbmk::SrvSlot s{};
-        s.desc = desc;
-        s.f[0] = f0;
-        s.f[1] = f1;
-        s.gp[0] = f0;
-        s.gp[1] = f1;
-        s.u = u;
-        s.prev = prev;
-        s.g = j->geo;
-        const lbm_request &r = j->req;
-        s.omega_f = 1.0 / r.tau;
-        s.u_in = r.u_in;
-        s.inv_uin = 1.0 / ((double)K * fabs(r.u_in));
-        s.omega_a = 1.0 / (0.5 + r.D / (1.0 / 3.0)); // as the single solve: D / c_s^2
-        const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
-        s.cin_s = r.c_in - c_ref;
-        s.cout_s = r.c_out - c_ref;
-        s.c_ref = c_ref;
-        s.k_sink = r.k_sink;
-        s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
-        s.outlet = r.outlet;
-        s.phase = lbmk::SRV_FLUID;
+        const lbmk::SrvSlot s = slot_entry(j, lbmk::SRV_FLUID);
         if ((e = lbmk::srv_slot_set(d_slots, sid, s, stream)) != hipSuccess)
             return e;
         j->sid = sid;
@@ -533,43 +551,26 @@ struct lbm_server {
         void *u = base + j->lay.u, *prev = base + j->lay.prev;
         const lbm_request &r = j->req;
         const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
-        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, u, nullptr, 0, stream)) != hipSuccess)
+        float *ref = reinterpret_cast<float *>(base + j->lay.ref);
+        if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, ref, u, nullptr, 0, stream)) != hipSuccess)
             return e;
-        if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, r.u_in, r.c_in, c_ref, r.k_sink,
+        if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, ref, nullptr, r.u_in, r.c_in, r.k_sink,
                               r.outlet, r.c_out, d_partials, d_out + 10 * j->sid, stream)) != hipSuccess)
             return e;
         if (j->st_fluid == LBM_EDIVERGED)
             return retire(j);
         // the substrate populations take the place of the fluid ones
+        if ((e = lbmk::ref_fill(ref, 2 * r.nx, (float)c_ref, stream)) != hipSuccess)
+            return e;
         if ((e = lbmk::ad_init(2, storage, f0, desc, u, j->geo, r.c_in, c_ref, stream)) != hipSuccess)
             return e;
-        if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, c_ref, r.k_sink, prev, 0, stream)) !=
+        if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, r.k_sink, prev, 0, stream)) !=
             hipSuccess)
             return e;
         if ((e = lbmk::ctrl_reset(d_ctrl + j->sid, r.tol, window, 0, K, nullptr, 0, stream, j->t_max)) !=
             hipSuccess)
             return e;
-        lbmk::SrvSlot s{};
-        // only the phase changes; rewrite the entry whole
-        s.desc = desc;
-        s.f[0] = f0;
-        s.f[1] = base + j->lay.f1;
-        s.gp[0] = s.f[0];
-        s.gp[1] = s.f[1];
-        s.u = u;
-        s.prev = prev;
-        s.g = j->geo;
-        s.omega_f = 1.0 / r.tau;
-        s.u_in = r.u_in;
-        s.inv_uin = 1.0 / ((double)K * fabs(r.u_in));
-        s.omega_a = 1.0 / (0.5 + r.D / (1.0 / 3.0)); // as the single solve: D / c_s^2
-        s.cin_s = r.c_in - c_ref;
-        s.cout_s = r.c_out - c_ref;
-        s.c_ref = c_ref;
-        s.k_sink = r.k_sink;
-        s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
-        s.outlet = r.outlet;
-        s.phase = lbmk::SRV_AD;
+        const lbmk::SrvSlot s = slot_entry(j, lbmk::SRV_AD);
         if ((e = lbmk::srv_slot_set(d_slots, j->sid, s, stream)) != hipSuccess)
             return e;
         j->phase = PH_AD;
@@ -589,14 +590,14 @@ struct lbm_server {
         void *desc = base + j->lay.desc, *f0 = base + j->lay.f0;
         void *u = base + j->lay.u, *prev = base + j->lay.prev;
         const lbm_request &r = j->req;
-        const double c_ref = lbmk::storage_shifted(storage) ? r.c_in : 0.0;
+        float *ref = reinterpret_cast<float *>(base + j->lay.ref);
         double *out = d_out + 10 * j->sid;
         if (j->ad_ran) {
-            if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, c_ref, r.k_sink, prev, 0, stream)) !=
+            if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, r.k_sink, prev, 0, stream)) !=
                 hipSuccess)
                 return e;
-            if ((e = lbmk::fluxes(2, storage, nullptr, f0, desc, j->geo, r.u_in, r.c_in, c_ref, r.k_sink,
-                                  r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
+            if ((e = lbmk::fluxes(2, storage, nullptr, f0, desc, j->geo, nullptr, ref, r.u_in, r.c_in,
+                                  r.k_sink, r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
                 return e;
         } else if ((e = hipMemsetAsync(prev, 0, (size_t)N * 4, stream)) != hipSuccess) {
             return e;
@@ -695,10 +696,14 @@ struct lbm_server {
     hipError_t enqueue_chunk()
     {
         hipError_t e;
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < K; ++j) {
             if ((e = lbmk::srv_step(cfg.storage, j == K - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
                                     d_tab, d_ctrl, d_part, part_cap, j, blocks, stream)) != hipSuccess)
                 return e;
+            if (j == 0 && lbmk::storage_moving_ref(cfg.storage) &&
+                (e = lbmk::srv_ref_roll(d_slots, d_tab, d_ctrl, stream)) != hipSuccess)
+                return e;
+        }
         return lbmk::srv_decide(d_slots, d_tab, d_ctrl, d_part, part_cap, stream);
     }
 
@@ -908,7 +913,7 @@ size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage)
 {
     if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_FP16_SHIFTED)
         return 0;
-    return layout_of((int64_t)nx * ny, storage).total;
+    return layout_of(nx, (int64_t)nx * ny, storage).total;
 }
 
 lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server **out)
@@ -948,9 +953,7 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     s->device = ctx->device;
     s->cfg = c;
     s->K = c.check_every;
-    s->window = c.stall_checks < 0 ? 0
-                                   : (c.stall_checks > 0 ? c.stall_checks
-                                                         : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
+    s->window = c.stall_checks < 0 ? 0 : (c.stall_checks > 0 ? c.stall_checks : 1000);
     s->blocks = c.grid_blocks;
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();
@@ -1037,7 +1040,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
     const int64_t N = (int64_t)r->nx * r->ny;
     std::string m = request_problem(*r);
     if (m.empty()) {
-        j->lay = layout_of(N, s->cfg.storage);
+        j->lay = layout_of(r->nx, N, s->cfg.storage);
         if (j->lay.total > s->cfg.pool_bytes ||
             lbmk::make_geo(r->nx, r->ny, 1).ntiles > s->part_cap)
             m = "request larger than the server pool";

@@ -38,6 +38,9 @@ const int MAX_INFLIGHT = 3;
 const double STREAMING_BYTES = 192.0 * 1024 * 1024;
 
 inline size_t sbytes(const lbm_solver *s) { return lbmk::storage_bytes(s->p.storage); }
+// column references of the fluid (which = 0) or substrate (1) state
+inline float *ref_cur(const lbm_solver *s, int which) { return s->d_ref + (size_t)(2 * which) * s->grid.nx; }
+inline float *ref_next(const lbm_solver *s, int which) { return s->d_ref + (size_t)(2 * which + 1) * s->grid.nx; }
 inline size_t cbytes(const lbm_solver *s) { return lbmk::compute_bytes(s->p.storage); }
 inline bool shifted(const lbm_solver *s) { return lbmk::storage_shifted(s->p.storage); }
 
@@ -141,7 +144,9 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
     return LBM_OK;
 }
 
-hipError_t launch_step(lbm_solver *s, int which, int mode, int src)
+// first: the first step after a residual check, which moves the stored
+// state to the column reference sampled at that check (see lbm_kernels.h)
+hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first = false)
 {
     if (which == LBM_SOLVER_FLUID) {
         lbmk::FluidArgs a;
@@ -156,6 +161,9 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src)
         a.inv_uin = 1.0 / ((double)s->p.check_every * fabs(s->p.u_in));
         a.streaming_stores = 2.0 * s->qf * (double)s->geo.N * sbytes(s) > STREAMING_BYTES;
         a.step = (unsigned int)(s->fsteps++);
+        a.ref_src = ref_cur(s, 0);
+        a.ref_dst = first ? ref_next(s, 0) : ref_cur(s, 0);
+        a.ref_out = ref_next(s, 0);
         return lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
     }
     const double cs2 = s->dim == 3 ? 0.25 : 1.0 / 3.0;
@@ -176,12 +184,19 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src)
     a.outlet = s->p.outlet;
     a.streaming_stores = 2.0 * s->qa * (double)s->geo.N * sbytes(s) > STREAMING_BYTES;
     a.step = (unsigned int)(s->gsteps++);
+    a.c_in = s->p.c_in;
+    a.c_out = s->p.c_out;
+    a.ref_src = ref_cur(s, 1);
+    a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
+    a.ref_out = ref_next(s, 1);
     return lbmk::ad_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
 }
 
 lbm_status init_solver(lbm_solver *s, int which)
 {
     hipStream_t st = s->ctx->stream;
+    const float r = which == LBM_SOLVER_FLUID ? 1.0f : (float)s->c_ref;
+    HIPCHK(lbmk::ref_fill(ref_cur(s, which), 2 * s->grid.nx, r, st), "reference init");
     if (which == LBM_SOLVER_FLUID) {
         HIPCHK(lbmk::fluid_init(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, st),
                "fluid init");
@@ -207,8 +222,9 @@ double algo_bytes(const lbm_solver *s, int which)
 lbm_status fill_fluxes(lbm_solver *s, double *out5)
 {
     HIPCHK(lbmk::fluxes(s->dim, s->p.storage, s->fluid_ready ? s->d_f[s->fcur] : nullptr,
-                        s->ad_ready ? s->d_g[s->gcur] : nullptr, s->d_desc, s->geo, s->p.u_in,
-                        s->p.c_in, s->c_ref, s->p.k_sink, s->p.outlet, s->p.c_out, s->d_partials,
+                        s->ad_ready ? s->d_g[s->gcur] : nullptr, s->d_desc, s->geo, ref_cur(s, 0),
+                        ref_cur(s, 1), s->p.u_in, s->p.c_in, s->p.k_sink, s->p.outlet, s->p.c_out,
+                        s->d_partials,
                         s->d_out5, s->ctx->stream),
            "fluxes");
     HIPCHK(hipMemcpyAsync(out5, s->d_out5, 5 * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream),
@@ -232,14 +248,10 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
             return stt;
     hipStream_t stream = s->ctx->stream;
     const int K = s->p.check_every;
-    // default stall window: FP16 storage reaches its round-off floor within
-    // ordinary tolerances, so it gets a short window; the FP32/FP64 forms
-    // rarely do, and slow physical transients (a porous medium filling up
-    // behind a fixed inflow) can hold their residual level for >10^4 steps.
-    const int window = s->p.stall_checks < 0
-                           ? 0
-                           : (s->p.stall_checks > 0 ? s->p.stall_checks
-                                                    : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
+    // default stall window: slow physical transients (a long porous medium
+    // filling up behind a fixed inflow) can hold the residual level for
+    // >10^4 steps, so the window is long
+    const int window = s->p.stall_checks < 0 ? 0 : (s->p.stall_checks > 0 ? s->p.stall_checks : 1000);
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
     HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
                             s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
@@ -248,32 +260,32 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     const int cur0 = cur;
     // moments of the starting state: the reference of the first check
     if (which == LBM_SOLVER_FLUID)
-        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[cur0], s->d_desc, s->geo, s->d_uprev,
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[cur0], s->d_desc, s->geo, ref_cur(s, 0),
+                                  s->d_uprev,
                                   nullptr, 0, stream),
                "residual reference");
     else
-        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[cur0], s->d_desc, s->geo, s->c_ref,
+        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[cur0], s->d_desc, s->geo, ref_cur(s, 1),
                                s->p.k_sink, s->d_cprev, 0, stream),
                "residual reference");
     const auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
     int64_t launched = 0, head = 0, tail = 0;
     bool stopped = false;
+    const bool roll = lbmk::storage_moving_ref(s->p.storage);
     while (launched < max_iter && !stopped) {
         const int64_t rem = max_iter - launched;
-        if (rem >= K) {
-            for (int j = 1; j <= K; ++j) {
-                const int mode = j == K ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
-                HIPCHK(launch_step(s, which, mode, (int)((cur0 + launched + j - 1) & 1)), "step launch");
-            }
-            HIPCHK(lbmk::decide(ctrl, stream), "decide");
-            launched += K;
-        } else {
-            for (int64_t j = 1; j <= rem; ++j)
-                HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, (int)((cur0 + launched + j - 1) & 1)),
-                       "step launch");
-            launched += rem;
+        const int64_t n = rem >= K ? K : rem;
+        for (int64_t j = 1; j <= n; ++j) {
+            const int mode = (n == K && j == K) ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
+            HIPCHK(launch_step(s, which, mode, (int)((cur0 + launched + j - 1) & 1), j == 1), "step launch");
+            if (j == 1 && roll)
+                HIPCHK(lbmk::ref_roll(ctrl, ref_cur(s, which), ref_next(s, which), s->grid.nx, stream),
+                       "reference roll");
         }
+        if (n == K)
+            HIPCHK(lbmk::decide(ctrl, stream), "decide");
+        launched += n;
         const int slot = (int)(head % RING);
         HIPCHK(hipMemcpyAsync(&s->h_ctrl[slot], ctrl, sizeof(lbmk::Ctrl), hipMemcpyDeviceToHost, stream),
                "ctrl snapshot");
@@ -309,8 +321,8 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     else if (fin.stop == lbmk::STOP_DIVERGED)
         result = set_err(s->ctx, LBM_EDIVERGED, "solution diverged (NaN/Inf or |u| > 0.3)");
     if (which == LBM_SOLVER_FLUID)
-        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, s->d_u,
-                                  nullptr, 0, stream),
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0),
+                                  s->d_u, nullptr, 0, stream),
                "velocity export");
     if (info) {
         float ms = 0.f;
@@ -357,7 +369,8 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         if ((e = ensure_stage(s, (size_t)(s->dim + 1) * N * 8)))
             return e;
         double *U = s->d_stage, *R = s->d_stage + (size_t)s->dim * N;
-        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, U, R, 1, st),
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0),
+                                  U, R, 1, st),
                "export");
         if (field == LBM_FIELD_U)
             HIPCHK(hipMemcpyAsync(dst, U, (size_t)s->dim * N * 8, hipMemcpyDeviceToHost, st), "copy");
@@ -370,7 +383,7 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
             return set_err(s->ctx, LBM_EINVAL, "substrate state not initialised");
         if ((e = ensure_stage(s, N * 8)))
             return e;
-        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->geo, s->c_ref,
+        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->geo, ref_cur(s, 1),
                                s->p.k_sink, s->d_stage, 1, st),
                "export");
         HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, hipMemcpyDeviceToHost, st), "copy");
@@ -391,7 +404,7 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         if ((e = ensure_stage(s, (size_t)q * N * 8)))
             return e;
         HIPCHK(lbmk::pops_export(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
-                                 s->d_desc, s->geo, s->c_ref, s->d_stage, st),
+                                 s->d_desc, s->geo, ref_cur(s, which), s->d_stage, st),
                "export");
         HIPCHK(hipMemcpyAsync(dst, s->d_stage, (size_t)q * N * 8, hipMemcpyDeviceToHost, st), "copy");
         break;
@@ -410,7 +423,7 @@ struct StateHeader {
     double tau, u_in, D, c_in, k_sink, c_out;
     int32_t outlet, check_every;
     int64_t N;
-    uint64_t f_bytes, g_bytes, u_bytes;
+    uint64_t f_bytes, g_bytes, u_bytes, ref_bytes;
     uint64_t fsteps, gsteps;
 };
 
@@ -418,7 +431,7 @@ size_t state_size(const lbm_solver *s)
 {
     const size_t N = (size_t)s->geo.N;
     return sizeof(StateHeader) + N + (size_t)s->qf * N * sbytes(s) + (size_t)s->qa * N * sbytes(s) +
-           (size_t)s->dim * N * cbytes(s);
+           (size_t)s->dim * N * cbytes(s) + (size_t)4 * s->grid.nx * sizeof(float);
 }
 
 } // namespace
@@ -491,6 +504,14 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
         return fail(st);
     s->d_partials = static_cast<double *>(tmp);
     tmp = nullptr;
+    if ((st = dev_alloc(s, &tmp, 4 * (size_t)g.nx * sizeof(float), "column references")))
+        return fail(st);
+    s->d_ref = static_cast<float *>(tmp);
+    if ((he = lbmk::ref_fill(s->d_ref, 2 * g.nx, 1.0f, ctx->stream)) != hipSuccess ||
+        (he = lbmk::ref_fill(s->d_ref + 2 * (size_t)g.nx, 2 * g.nx, (float)s->c_ref, ctx->stream)) !=
+            hipSuccess)
+        return fail(hip_err(ctx, he, "column references"));
+    tmp = nullptr;
     if ((st = dev_alloc(s, &tmp, 8 * sizeof(double), "flux out")))
         return fail(st);
     s->d_out5 = static_cast<double *>(tmp);
@@ -520,7 +541,7 @@ void lbm_solver_destroy(lbm_solver *s)
     (void)hipStreamSynchronize(s->ctx->stream);
     void *bufs[] = {s->d_desc, s->d_f[0],   s->d_f[1],   s->d_g[0], s->d_g[1],
                     s->d_u,    s->d_uprev,  s->d_cprev,  s->d_ctrl, s->d_part,
-                    s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals};
+                    s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals, s->d_ref};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -630,8 +651,8 @@ lbm_status lbm_solver_export_u(lbm_solver *s)
         return LBM_EINVAL;
     if (!s->fluid_ready)
         return set_err(s->ctx, LBM_EINVAL, "fluid state not initialised");
-    HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, s->d_u, nullptr,
-                              0, s->ctx->stream),
+    HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0),
+                              s->d_u, nullptr, 0, s->ctx->stream),
            "velocity export");
     HIPCHK(hipStreamSynchronize(s->ctx->stream), "sync");
     return LBM_OK;
@@ -677,7 +698,7 @@ lbm_status lbm_solver_put(lbm_solver *s, int field, const double *src)
     hipStream_t stream = s->ctx->stream;
     HIPCHK(hipMemcpyAsync(s->d_stage, src, (size_t)q * N * 8, hipMemcpyHostToDevice, stream), "copy");
     HIPCHK(lbmk::pops_import(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
-                             s->d_desc, s->geo, s->c_ref, s->d_stage, stream),
+                             s->d_desc, s->geo, ref_cur(s, which), s->d_stage, stream),
            "import");
     HIPCHK(hipStreamSynchronize(stream), "sync");
     if (which == 0)
@@ -755,7 +776,6 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
         s->d_vals = static_cast<double *>(p);
     }
     hipStream_t stream = s->ctx->stream;
-    const bool sh = shifted(s);
     static const double wf2[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     static const double wf3[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
@@ -771,14 +791,15 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
             return LBM_OK; // solver never run: nothing stored yet
         const int q = which == 0 ? s->qf : s->qa;
         const double *w = which == 0 ? (s->dim == 3 ? wf3 : wf2) : (s->dim == 3 ? wa3 : wa2);
+        // unshifted values; blocked nodes store 0 whatever the shift
         double vals[19];
         for (int i = 0; i < q; ++i) {
             if (!on)
                 vals[i] = 0.0;
             else if (which == 0)
-                vals[i] = sh ? 0.0 : w[i];                      // rest state
+                vals[i] = w[i];                // rest state
             else
-                vals[i] = w[i] * (s->p.c_in - s->c_ref);         // equilibrium at c_in, u = 0
+                vals[i] = w[i] * s->p.c_in;    // equilibrium at c_in, u = 0
         }
         HIPCHK(hipMemcpyAsync(s->d_vals, vals, q * sizeof(double), hipMemcpyHostToDevice, stream), "vals");
         for (size_t off = 0; off < list.size(); off += 4096) {
@@ -786,7 +807,8 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
             HIPCHK(hipMemcpyAsync(s->d_idx, list.data() + off, cnt * sizeof(long long),
                                   hipMemcpyHostToDevice, stream),
                    "idx");
-            HIPCHK(lbmk::pops_set_nodes(which, s->dim, s->p.storage, buf, s->geo, s->d_idx, cnt, s->d_vals,
+            HIPCHK(lbmk::pops_set_nodes(which, s->dim, s->p.storage, buf, s->geo,
+                                        on ? ref_cur(s, which) : nullptr, s->d_idx, cnt, s->d_vals,
                                         stream),
                    "cell reset");
             HIPCHK(hipStreamSynchronize(stream), "sync");
@@ -816,7 +838,7 @@ lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
     const size_t N = (size_t)s->geo.N;
     StateHeader h;
     memset(&h, 0, sizeof(h));
-    memcpy(h.magic, "LBMSTAT2", 8);
+    memcpy(h.magic, "LBMSTAT3", 8);
     h.nx = s->grid.nx;
     h.ny = s->grid.ny;
     h.nz = s->grid.nz;
@@ -837,6 +859,7 @@ lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
     h.f_bytes = (uint64_t)s->qf * N * sbytes(s);
     h.g_bytes = (uint64_t)s->qa * N * sbytes(s);
     h.u_bytes = (uint64_t)s->dim * N * cbytes(s);
+    h.ref_bytes = (uint64_t)4 * s->grid.nx * sizeof(float);
     h.fsteps = s->fsteps;
     h.gsteps = s->gsteps;
     char *p = static_cast<char *>(dst);
@@ -856,6 +879,8 @@ lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
         memset(p, 0, h.g_bytes);
     p += h.g_bytes;
     HIPCHK(hipMemcpyAsync(p, s->d_u, h.u_bytes, hipMemcpyDeviceToHost, st), "state u");
+    p += h.u_bytes;
+    HIPCHK(hipMemcpyAsync(p, s->d_ref, h.ref_bytes, hipMemcpyDeviceToHost, st), "state references");
     HIPCHK(hipStreamSynchronize(st), "state sync");
     return LBM_OK;
 }
@@ -866,7 +891,7 @@ lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
         return LBM_EINVAL;
     StateHeader h;
     memcpy(&h, src, sizeof(h));
-    if (memcmp(h.magic, "LBMSTAT2", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
+    if (memcmp(h.magic, "LBMSTAT3", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
         h.nz != s->grid.nz || h.storage != s->p.storage || bytes < state_size(s))
         return set_err(s->ctx, LBM_EINVAL, "checkpoint does not match this solver");
     const size_t N = (size_t)s->geo.N;
@@ -889,6 +914,8 @@ lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
     HIPCHK(hipMemcpy(s->d_g[0], p, h.g_bytes, hipMemcpyHostToDevice), "state g");
     p += h.g_bytes;
     HIPCHK(hipMemcpy(s->d_u, p, h.u_bytes, hipMemcpyHostToDevice), "state u");
+    p += h.u_bytes;
+    HIPCHK(hipMemcpy(s->d_ref, p, h.ref_bytes, hipMemcpyHostToDevice), "state references");
     s->fluid_ready = h.fluid_ready != 0;
     s->ad_ready = h.ad_ready != 0;
     s->fsteps = h.fsteps;

@@ -182,7 +182,8 @@ def test_served_fp16_within_5e_3_of_plain_fp32(srv_env):
         nx, ny, solid, tau, u_in, seed = spec
         r = res[i]
         cls = _mask(lbm, nx, ny, solid, seed)
-        p = lbm.make_params(tau=tau, u_in=u_in, D=D_SUB, c_in=1.0, k_sink=K_SINK, storage=FP32)
+        p = lbm.make_params(tau=tau, u_in=u_in, D=D_SUB, c_in=1.0, k_sink=K_SINK, storage=FP32,
+                            stall_checks=-1)
         s = lbm.lbm_solver_create(ctx, cls, p)
         try:
             sf, fi = lbm.lbm_solver_fluid(s, 0.0, r["iters_fluid"])
