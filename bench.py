@@ -12,6 +12,12 @@ Prints one JSON line with a roofline object for the dominant kernel (the
 fluid stream-collide step) and the FP64 CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--workload c2] [--storage fp32s]
+    python bench.py --workload served --storage fp16s [--requests 48] [--rate 50]
+
+The served mode replays the seeded request stream (Poisson arrivals, 2-D
+domains log-uniform in size) into one server in real time and reports the
+p50/p99 solve latency and the aggregate MLUPS beside the plain FP32 single
+solves of the same requests, run one at a time on the same GPU.
 """
 import argparse
 import hashlib
@@ -89,6 +95,141 @@ def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
                       "(%.1f s)" % (steps, asteps, w["name"], tf + ta)}
 
 
+def served_main(args):
+    """Served stream: seeded requests with Poisson arrivals submitted in real
+    time to one server (continuous batching), then the same requests solved
+    one at a time by the plain FP32 single-solve path on the same GPU."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1802_07525_amd as lbm
+    from paper_1802_07525_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    lbm.load()
+    reqs = inputs.serve_requests(args.requests, args.rate)
+    storage = STORAGES[args.storage]
+    max_iter = args.max_iter or 2_000_000
+    ctx = lbm.lbm_ctx_create(0)
+    cfg = lbm.make_server_cfg(int(args.pool_gb * (1 << 30)), max_slots=args.slots, storage=storage,
+                              prep_threads=4, stall_checks=args.stall_checks)
+    srv = lbm.lbm_server_create(ctx, cfg)
+
+    def request(r):
+        return lbm.make_request(r["nx"], r["ny"], r_min=r["r_min"], r_max=r["r_max"],
+                                solid_frac=1.0 - r["porosity"], overlap=r["overlap"],
+                                seed=r["seed"], layer=0, tau=r["tau"], u_in=r["u_in"], D=r["D"],
+                                c_in=r["c_in"], k_sink=r["k"], tol=r["tol"], max_iter=max_iter,
+                                user=r["i"])
+
+    results, refused = {}, []
+    t_start = time.perf_counter()
+
+    def feeder():
+        for r in reqs:
+            dt = r["arrival"] - (time.perf_counter() - t_start)
+            if dt > 0:
+                time.sleep(dt)
+            st, _ = lbm.lbm_server_submit(srv, request(r))
+            if st:
+                refused.append((r["i"], lbm.status_name(st), lbm.lbm_server_error(srv)))
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    last = time.perf_counter()
+    while len(results) + len(refused) < len(reqs):
+        for d in lbm.lbm_server_poll(srv, 64, 0.5):
+            results[d["user"]] = d
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            print("served: %d/%d finished after %.0f s" % (len(results), len(reqs),
+                                                           last - t_start), file=sys.stderr,
+                  flush=True)
+    th.join()
+    stats = lbm.lbm_server_stats(srv)
+    lbm.lbm_server_destroy(srv)
+
+    done = [d for d in results.values() if d["status"] >= 0]
+    lat = np.array([d["t_finish"] - d["t_submit"] for d in done])
+    t0 = min(d["t_submit"] for d in results.values())
+    t1 = max(d["t_finish"] for d in results.values())
+    makespan = t1 - t0
+    upd = sum(d["iters_fluid"] * d["active_fluid"] + d["iters_ad"] * d["active_ad"] for d in done)
+    print("served: all %d finished in %.1f s; plain FP32 single solves next" % (len(results),
+                                                                              makespan),
+          file=sys.stderr, flush=True)
+
+    # plain FP32 single solves of the same requests, one at a time
+    single_s, single_upd, eu, ec, single_fail = 0.0, 0.0, [], [], 0
+    last = time.perf_counter()
+    for d in sorted(done, key=lambda d: d["user"]):
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            print("single FP32: request %d of %d" % (d["user"], len(reqs)), file=sys.stderr,
+                  flush=True)
+        r = reqs[d["user"]]
+        st, cls, _ = lbm.lbm_geom_discs(r["nx"], r["ny"], r["r_min"], r["r_max"],
+                                        1.0 - r["porosity"], r["overlap"], r["seed"])
+        p = lbm.make_params(tau=r["tau"], u_in=r["u_in"], D=r["D"], c_in=r["c_in"],
+                            k_sink=r["k"], storage=STORAGES["fp32"])
+        ts = time.perf_counter()
+        s = lbm.lbm_solver_create(ctx, cls, p)
+        sf, fi = lbm.lbm_solver_fluid(s, r["tol"], max_iter)
+        if sf < 0:
+            lbm.lbm_solver_destroy(s)
+            single_s += time.perf_counter() - ts
+            single_fail += 1
+            continue
+        sa, ai = lbm.lbm_solver_ad(s, r["tol"], max_iter)
+        U = lbm.lbm_solver_get(s, lbm.LBM_FIELD_U, (r["nx"], r["ny"], 1))
+        C = lbm.lbm_solver_get(s, lbm.LBM_FIELD_C, (r["nx"], r["ny"], 1))
+        lbm.lbm_solver_destroy(s)
+        single_s += time.perf_counter() - ts
+        single_upd += fi["iters"] * fi["active_nodes"] + ai["iters"] * ai["active_nodes"]
+        flat = cls.reshape(-1)
+        fl, act = flat == 0, (flat == 0) | (flat == 3)
+        eu.append(float(np.linalg.norm(d["u"][:, fl] - U[:, fl]) / np.linalg.norm(U[:, fl])))
+        ec.append(float(np.linalg.norm(d["c"][act] - C[act]) / np.linalg.norm(C[act])))
+    lbm.lbm_ctx_destroy(ctx)
+    eu, ec = np.array(eu), np.array(ec)
+    sb = {0: 4, 1: 4, 2: 2}[storage]
+    algo = (upd and sum(d["iters_fluid"] * d["active_fluid"] * algo_bytes(9, sb)
+                        + d["iters_ad"] * d["active_ad"] * algo_bytes(5, sb, 8) for d in done))
+    achieved = algo / stats["busy_seconds"] / 1e9 if stats["busy_seconds"] > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": upd / makespan / 1e6, "unit": "MLUPS", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": makespan / len(reqs) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES[args.storage], "data": "synthetic",
+        "config": {"workload": "served stream: %d requests, Poisson %g req/s, 2-D D2Q9+D2Q5, "
+                               "nx log-uniform 64..2048, ny = nx/2" % (len(reqs), args.rate),
+                   "storage": args.storage, "pool_gb": args.pool_gb, "slots": args.slots,
+                   "seed": inputs.SERVE_SEED},
+        "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
+                   "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                   "mean_s": float(lat.mean()), "makespan_s": makespan,
+                   "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
+                   "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
+                   "statuses": {lbm.status_name(k): int(sum(1 for d in results.values()
+                                                            if d["status"] == k))
+                                for k in sorted({d["status"] for d in results.values()})}},
+        "single_fp32": {"seconds": single_s, "mlups": single_upd / single_s / 1e6,
+                        "failed": single_fail,
+                        "req_per_s": len(done) / single_s,
+                        "speedup_served": single_s / makespan,
+                        "u_rel_l2_median": float(np.median(eu)), "u_rel_l2_max": float(eu.max()),
+                        "c_rel_l2_median": float(np.median(ec)), "c_rel_l2_max": float(ec.max()),
+                        "frac_within_5e-3": float(np.mean((eu < 5e-3) & (ec < 5e-3)))},
+        "roofline": {"bound": "hbm", "kernel": "k_srv_step (batched fluid+substrate)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "note": "algorithmic bytes of all served updates / device-busy time"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,12 +239,22 @@ def main():
     ap.add_argument("--storage", default="fp32s", choices=sorted(STORAGES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=0)
+    ap.add_argument("--requests", type=int, default=48, help="served stream length")
+    ap.add_argument("--rate", type=float, default=50.0, help="served arrivals per second")
+    ap.add_argument("--pool-gb", type=float, default=32.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--stall-checks", type=int, default=0,
+                    help="stall window in checks (0: the library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the served stream and slab decomposition would shard across GPUs; "
               "they are not built).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "served":
+        if args.storage == "fp64":
+            sys.exit("the served form stores FP32 or FP16")
+        return served_main(args)
 
     import numpy as np
     import torch
@@ -127,7 +278,7 @@ def main():
     max_iter = args.max_iter or w["max_iter"]
     ctx = lbm.lbm_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
-                        storage=storage)
+                        storage=storage, stall_checks=args.stall_checks)
     s = lbm.lbm_solver_create(ctx, cls, p)
 
     def one_step():

@@ -117,7 +117,8 @@ typedef struct {
     double c_out;         /* outlet value for LBM_OUT_DIRICHLET */
     int32_t storage;      /* lbm_storage */
     int32_t check_every;  /* residual cadence K, even and >= 2 (100 if 0) */
-    int32_t stall_checks; /* stall window in checks (1000 if 0); < 0 disables */
+    int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
+                             1000 otherwise; < 0 disables */
 } lbm_params;
 
 typedef struct {
@@ -219,9 +220,10 @@ void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
  * check interval K = 100, max |U(t) - U(t-K)| / (K |u_in|) over FLUID
  * nodes, evaluated at t = K, 2K, ... -- is <= tol, or max_iter steps.
  * With LBM_FP16_SHIFTED storage the per-node changes are replaced by their
- * means over 64 x 4-node tiles (per z-plane): stochastic rounding makes
- * zero-mean per-node noise that would otherwise set a residual floor above
- * ordinary tolerances; the mean keeps the smooth evolution of the field.
+ * means over 64 x 4-node tiles (per z-plane): stochastic rounding injects
+ * zero-mean momentum noise that would otherwise set a residual floor above
+ * ordinary tolerances; the mean keeps the smooth evolution of the flow.
+ * (The substrate residual below is treated the same way.)
  * Also stops on NaN/Inf or |u| > 0.3 (EDIVERGED) and after stall_checks
  * checks without a new residual minimum (STALLED).  u_out: host double
  * [dim][N] (0 on blocked nodes).  info may be NULL. */

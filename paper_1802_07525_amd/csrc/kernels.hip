@@ -81,7 +81,7 @@ struct D3Q7 {
 };
 
 // ---------------------------------------------------------- storage forms
-// tile_mean: the residual check compares tile means instead of nodes (see
+// tile_mean: the residual compares tile means instead of nodes (see
 // check_residual).  colref: the shift reference is a per-column array that
 // moves at checks (see lbm_kernels.h); otherwise it is the constant 1 (fluid)
 // or c_ref (substrate).
@@ -275,14 +275,15 @@ __device__ __forceinline__ void block_sum4(double &a, double &b, double &c, doub
 
 // Residual of one tile at a check step from the per-node changes (dx, dy,
 // dz) of an active node (act; zeros otherwise): the largest change of any
-// node, or -- with FP16 storage, whose stochastic rounding adds zero-mean
-// per-node noise that would set a floor above ordinary tolerances -- the
-// largest change of the tile mean over its active nodes, which averages the
-// noise out and keeps the smooth evolution of the field.
-template <class S>
+// node, or (MEAN) the largest change of the tile mean over its active
+// nodes.  The mean serves FP16 storage: stochastic rounding injects
+// zero-mean noise into quantities the collisions conserve (momentum, the
+// substrate), so per-node changes carry a noise floor above ordinary
+// tolerances; the mean averages it out and keeps the smooth evolution.
+template <bool MEAN>
 __device__ __forceinline__ double check_residual(bool act, double dx, double dy, double dz)
 {
-    if constexpr (S::tile_mean) {
+    if constexpr (MEAN) {
         double n = act ? 1.0 : 0.0;
         block_sum4(dx, dy, dz, n);
         if (threadIdx.x != 0 || n == 0.0)
@@ -462,7 +463,7 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
                     a.ref_out[p.x] = rho;
             }
         }
-        const double r = check_residual<S>(act, dx, dy, dz);
+        const double r = check_residual<S::tile_mean>(act, dx, dy, dz);
         block_max_commit(dbits(r * a.inv_uin), ub, part_r, part_u);
     }
 }
@@ -600,7 +601,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
                     a.ref_out[p.x] = cfull;
             }
         }
-        const double r = check_residual<S>(act, dc, 0.0, 0.0);
+        const double r = check_residual<S::tile_mean>(act, dc, 0.0, 0.0);
         block_max_commit(dbits(r * a.inv_cin), 0ull, part_r, part_u);
     }
 }

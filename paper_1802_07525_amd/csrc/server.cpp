@@ -953,7 +953,9 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     s->device = ctx->device;
     s->cfg = c;
     s->K = c.check_every;
-    s->window = c.stall_checks < 0 ? 0 : (c.stall_checks > 0 ? c.stall_checks : 1000);
+    s->window = c.stall_checks < 0 ? 0
+                                   : (c.stall_checks > 0 ? c.stall_checks
+                                                         : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     s->blocks = c.grid_blocks;
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();

@@ -250,8 +250,13 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     const int K = s->p.check_every;
     // default stall window: slow physical transients (a long porous medium
     // filling up behind a fixed inflow) can hold the residual level for
-    // >10^4 steps, so the window is long
-    const int window = s->p.stall_checks < 0 ? 0 : (s->p.stall_checks > 0 ? s->p.stall_checks : 1000);
+    // >10^4 steps, so it is long -- except with FP16 storage, whose
+    // residual reaches its round-off floor within ordinary tolerances
+    // (a long window there only repeats steps at the floor)
+    const int window = s->p.stall_checks < 0
+                           ? 0
+                           : (s->p.stall_checks > 0 ? s->p.stall_checks
+                                                    : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
     HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
                             s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
