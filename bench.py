@@ -95,6 +95,29 @@ def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
                       "(%.1f s)" % (steps, asteps, w["name"], tf + ta)}
 
 
+def profile_main(args, lbm, ctx, cls, w, storage):
+    """Short run for profilers: n fluid steps from rest, the velocity export,
+    n substrate steps, then ten 1 GiB device copies by the library's plain
+    copy kernel (the reference for counter calibration).  Per-launch HIP-event
+    times of the step kernels are printed with the launch counts."""
+    n = args.profile_steps
+    p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                        storage=storage)
+    s = lbm.lbm_solver_create(ctx, cls, p)
+    _, f_ms = lbm.lbm_solver_steps(s, 0, n, 1)
+    lbm.lbm_solver_export_u(s)
+    _, a_ms = lbm.lbm_solver_steps(s, 1, n, 1)
+    lbm.lbm_solver_destroy(s)
+    gbs, copy_ms = lbm.lbm_copy_bandwidth(ctx, 1 << 30, 10)
+    lbm.lbm_ctx_destroy(ctx)
+    nf = int((cls == 0).sum())
+    na = int(((cls == 0) | (cls == 3)).sum())
+    print(json.dumps({"profile": w["name"], "storage": args.storage, "steps": n,
+                      "fluid_nodes": nf, "ad_nodes": na, "fluid_ms_per_step": f_ms / n,
+                      "ad_ms_per_step": a_ms / n, "copy_bytes": 1 << 30, "copy_ms": copy_ms,
+                      "copy_gbs": gbs}), flush=True)
+
+
 def served_main(args):
     """Served stream: seeded requests with Poisson arrivals submitted in real
     time to one server (continuous batching), then the same requests solved
@@ -245,6 +268,9 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,
                     help="stall window in checks (0: the library default)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="profiling run: this many fluid and substrate steps of the workload "
+                         "and a 1 GiB copy (counter calibration) instead of the solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -277,6 +303,8 @@ def main():
         cls = lbm.lbm_biofilm_layer(cls)
     max_iter = args.max_iter or w["max_iter"]
     ctx = lbm.lbm_ctx_create(0, torch.cuda.current_stream().cuda_stream)
+    if args.profile_steps:
+        return profile_main(args, lbm, ctx, cls, w, storage)
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
                         storage=storage, stall_checks=args.stall_checks)
     s = lbm.lbm_solver_create(ctx, cls, p)
