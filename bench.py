@@ -336,18 +336,22 @@ def main():
     qf, qa = (19, 7) if dim == 3 else (9, 5)
     sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
     cb = 8 if storage == 3 else 4
-    # dominant kernel: fluid step; HIP-event time over its launches in the timed region
+    # dominant kernel: fluid step; HIP-event time over its launches in the timed
+    # region.  In 2-D one launch advances two steps, so the algorithmic bytes
+    # of a launch are twice the per-step figure.
     f_ms = sum(r[1]["kernel_ms"] for r in recs)
     f_launch = sum(r[1]["launches"] for r in recs)
     a_ms = sum(r[3]["kernel_ms"] for r in recs)
     a_launch = sum(r[3]["launches"] for r in recs)
+    spl = 2 if dim == 2 else 1
     avg_f = f_ms / max(f_launch, 1)
-    bytes_f = algo_bytes(qf, sb) * fi["active_nodes"]
+    bytes_f = spl * algo_bytes(qf, sb) * fi["active_nodes"]
     achieved = bytes_f / (avg_f * 1e-3) / 1e9
     # isolated per-launch HIP-event timing of the same kernel on the same state
     _, iso_ms = lbm.lbm_solver_time_steps(s, 0, 200)
-    bytes_a = algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
-    kernel_name = "k_fluid_step<%s,%s>" % ("D3Q19" if dim == 3 else "D2Q9", args.storage)
+    bytes_a = spl * algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
+    kernel_name = ("k_fluid_step2<%s>" % args.storage if dim == 2
+                   else "k_fluid_step<D3Q19,%s>" % args.storage)
     traffic = traffic_for(kernel_name, args.workload, args.storage)
     out = {
         "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -362,7 +366,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algo_bytes_per_launch": bytes_f,
-                     "avg_launch_ms": avg_f, "avg_launch_ms_isolated": iso_ms,
+                     "steps_per_launch": spl, "avg_launch_ms": avg_f,
+                     "avg_launch_ms_isolated": iso_ms,
                      "ad_kernel_gbs": bytes_a / (a_ms / max(a_launch, 1) * 1e-3) / 1e9,
                      "ad_avg_launch_ms": a_ms / max(a_launch, 1)},
     }

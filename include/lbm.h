@@ -128,7 +128,8 @@ typedef struct {
     int64_t active_nodes; /* nodes the solver updates */
     double seconds;       /* wall time of the solve, device-synchronous */
     double kernel_ms;     /* HIP-event time over the step-kernel launches */
-    int64_t launches;     /* step-kernel launches covered by kernel_ms */
+    int64_t launches;     /* step-kernel launches covered by kernel_ms (a
+                             launch advances two steps in 2-D, one in 3-D) */
     double mlups;         /* active-node updates per second / 1e6 */
     double gbps;          /* algorithmic bytes / kernel_ms: per active-node update,
                              each population read and written once, the 1-byte
@@ -265,10 +266,10 @@ lbm_status lbm_solver_ad(lbm_solver *s, double tol, int64_t max_iter, int warm,
  * lbm_solver_export_u for that. */
 lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold,
                             double *kernel_ms);
-/* Per-launch timing: nsteps single steps of one solver (state must be
- * initialised), each bracketed by its own pair of HIP events on the
- * context's stream; *avg_ms = mean event-to-event time per launch.  The
- * state advances by nsteps steps. */
+/* Per-launch timing: the launches covering nsteps steps of one solver
+ * (state must be initialised; in 2-D a launch advances two steps and nsteps
+ * is rounded up to even), each bracketed by its own pair of HIP events on
+ * the context's stream; *avg_ms = mean event-to-event time per launch. */
 lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *avg_ms);
 /* Recompute the substrate solve's velocity from the stored fluid state. */
 lbm_status lbm_solver_export_u(lbm_solver *s);
@@ -339,7 +340,8 @@ typedef struct {
     size_t pool_bytes;     /* device memory for request state, one allocation */
     int32_t max_slots;     /* requests on the device at once, 1..64 (32 if 0) */
     int32_t storage;       /* LBM_FP32, LBM_FP32_SHIFTED or LBM_FP16_SHIFTED */
-    int32_t check_every;   /* K: steps per chunk and residual cadence, even (100 if 0) */
+    int32_t check_every;   /* K: steps per chunk and residual cadence, a multiple of 4
+                              (100 if 0) */
     int32_t stall_checks;  /* as lbm_params */
     int32_t grid_blocks;   /* workgroups of each batched step launch (2048 if 0) */
     int32_t inflight;      /* chunks enqueued ahead of the decisions, 1..6 (2 if 0) */

@@ -300,6 +300,38 @@ __device__ __forceinline__ double check_residual(bool act, double dx, double dy,
     }
 }
 
+// ------------------------------------------------------ population sources
+// Where a node's incoming populations come from.  get(i, o, off, mode):
+// mode 0 = population i of the source node n - c_i (off = its offset),
+// 1 = this node's population o (the opposite of i: a reversed link),
+// 2 = this node's population i (a copied link).  Values are relative to the
+// column reference of the node they are read from.
+template <class S>
+struct GlobalSrc {
+    typedef typename S::C C;
+    const typename S::T *__restrict__ h;
+    long long N, n;
+    __device__ __forceinline__ C get(int i, int o, long long off, int mode) const
+    {
+        // one load from a selected address: no branches between the loads
+        const long long idx = mode == 1 ? (long long)o * N + n
+                                        : (mode == 2 ? (long long)i * N + n : (long long)i * N + n - off);
+        return ld<S>(h + idx);
+    }
+};
+
+// The block's copy of the first step of a pair in LDS: [q][ly][lx] over the
+// tile and its one-node halo (LX x 6 nodes, lx = x - x0 + 1, ly = y - y0 + 1).
+template <class C, int Q, int LX>
+struct LdsSrc {
+    const C (*v)[6][LX];
+    int lx, ly;
+    __device__ __forceinline__ C get2(int i, int o, int cx, int cy, int mode) const
+    {
+        return mode == 1 ? v[o][ly][lx] : (mode == 2 ? v[i][ly][lx] : v[i][ly - cy][lx - cx]);
+    }
+};
+
 // ------------------------------------------------------------ fluid step
 // Pull rules per direction i (source s = n - c_i), first match wins:
 //   inlet  (x == 0, c_ix = +1):   h_i = h*_opp(n) + 6 w_i u_in
@@ -308,132 +340,130 @@ __device__ __forceinline__ double check_residual(bool act, double dx, double dy,
 //       stored state (twice the even part of the equilibrium, rho_out = 1)
 //   blocked source (descriptor bit): h_i = h*_opp(n)     (Eq. 11, half-way)
 //   otherwise:                      h_i = h*_i(s)         (streaming)
-template <class L, class S, class DT, int MODE, bool NT>
-__device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
-                                           unsigned long long *part_r, unsigned long long *part_u)
+// then the moments (Eqs. 9-10) and the BGK relaxation (Eq. 4) towards the
+// equilibrium of Eq. 5.  Fetch(i, o, cx, cy, cz, mode) returns one incoming
+// value (see the sources above).  f[] comes back relative to this column's
+// reference r0; the caller moves it to the reference it stores with.
+template <class L, class S, class DT, class Fetch>
+__device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, const Fetch &fetch,
+                                              typename S::C r0, typename S::C dm, typename S::C dp,
+                                              typename S::C f[L::Q], typename S::C &ux,
+                                              typename S::C &uy, typename S::C &uz,
+                                              typename S::C &rho)
 {
-    typedef typename S::T T;
+    typedef typename S::C C;
+    const bool xin = x == 0, xout = x == a.g.nx - 1;
+    C ox = C(0), oy = C(0), oz = C(0); // u* of the stored state (outlet column)
+    if (xout) {
+        C r = C(0), qx = C(0), qy = C(0), qz = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const C v = fetch(i, L::op[i], L::cx[i], L::cy[i], L::cz[i], 2);
+            r += v;
+            if (L::cx[i] == 1) qx += v;
+            if (L::cx[i] == -1) qx -= v;
+            if (L::cy[i] == 1) qy += v;
+            if (L::cy[i] == -1) qy -= v;
+            if (L::cz[i] == 1) qz += v;
+            if (L::cz[i] == -1) qz -= v;
+        }
+        const C ir = C(1) / (S::shifted ? r0 + r : r);
+        ox = qx * ir;
+        oy = qy * ir;
+        oz = qz * ir;
+    }
+    const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
+        if (i == 0) {
+            f[0] = fetch(0, 0, 0, 0, 0, 2);
+            continue;
+        }
+        const bool in_i = cx == 1 && xin, out_i = cx == -1 && xout;
+        const bool rev = in_i || out_i || ((d >> i) & DT(1));
+        C v = fetch(i, o, cx, cy, cz, rev ? 1 : 0);
+        if constexpr (S::colref) {
+            // a value streamed from column x - c_ix, re-referenced to r0
+            if (cx == 1)
+                v = rev ? v : v + C(L::w[i]) * dm;
+            if (cx == -1)
+                v = rev ? v : v + C(L::w[i]) * dp;
+        }
+        if (cx == 1)
+            v = in_i ? v + C(6.0 * L::w[i]) * C(a.u_in) : v;
+        if (cx == -1) {
+            const C cu = -ox + C(cy) * oy + C(cz) * oz;
+            const C even = C(4.5) * cu * cu - ousq;
+            v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - v : v;
+        }
+        f[i] = v;
+    }
+    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        rs += f[i];
+        if (L::cx[i] == 1) jx += f[i];
+        if (L::cx[i] == -1) jx -= f[i];
+        if (L::cy[i] == 1) jy += f[i];
+        if (L::cy[i] == -1) jy -= f[i];
+        if (L::cz[i] == 1) jz += f[i];
+        if (L::cz[i] == -1) jz -= f[i];
+    }
+    rho = S::shifted ? r0 + rs : rs;
+    const C inv = C(1) / rho;
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+    const C om = C(a.omega);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        C cu = C(0);
+        if (L::cx[i] == 1) cu += ux;
+        if (L::cx[i] == -1) cu -= ux;
+        if (L::cy[i] == 1) cu += uy;
+        if (L::cy[i] == -1) cu -= uy;
+        if (L::cz[i] == 1) cu += uz;
+        if (L::cz[i] == -1) cu -= uz;
+        cu *= C(3);
+        // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
+        // minus the shift w_i r0 when stored shifted (rs = rho - r0).
+        const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
+        f[i] = f[i] + om * (feq - f[i]);
+    }
+}
+
+// column references of node x: this column (r0), the neighbours' offsets
+// from it (dm: x - 1, dp: x + 1) and the reference of the written buffer (rd)
+template <class S>
+__device__ __forceinline__ void column_refs(const float *src, const float *dst, int x, int nx,
+                                            typename S::C &r0, typename S::C &dm,
+                                            typename S::C &dp, typename S::C &rd)
+{
+    typedef typename S::C C;
+    r0 = src[x];
+    dm = (x > 0 ? src[x - 1] : r0) - r0;
+    dp = (x < nx - 1 ? src[x + 1] : r0) - r0;
+    rd = dst[x];
+}
+
+// Final part of a fluid step at one node: store (every in-grid lane, with
+// zeros on blocked nodes: whole-wave stores write whole cache lines where
+// lanes masked off by the geometry would turn stores into partial-line
+// writes) and, on check steps, the residual and the reference sample.
+template <class L, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void fluid_finish(const FluidArgs &a, const NodePos &p, DT d, bool act,
+                                             typename S::C f[L::Q], typename S::C ux,
+                                             typename S::C uy, typename S::C uz,
+                                             typename S::C rho, unsigned int step,
+                                             unsigned long long *part_r, unsigned long long *part_u)
+{
     typedef typename S::C C;
     const long long N = a.g.N;
-    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
-    const bool act = (d & DT(1)) != 0;
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-    C ux = C(0), uy = C(0), uz = C(0);
-    C f[L::Q];
-    // column references: this column (r0), the neighbours' offsets from it
-    // (dm: x - 1, dp: x + 1) and the reference of the written buffer (rd)
-    C r0 = C(1), dm = C(0), dp = C(0), rd = C(1), rho = C(0);
-    if constexpr (S::colref) {
-        if (act) {
-            r0 = a.ref_src[p.x];
-            dm = (p.x > 0 ? a.ref_src[p.x - 1] : r0) - r0;
-            dp = (p.x < a.g.nx - 1 ? a.ref_src[p.x + 1] : r0) - r0;
-            rd = a.ref_dst[p.x];
-        }
-    }
-    if (act) {
-        const long long n = p.n;
-        // One unconditional load per direction from a selected address (the
-        // source node, or this node's opposite population when the link is
-        // reversed), then the inlet/outlet terms by select: the loads carry no
-        // branches between them and issue back to back.  Values are taken
-        // relative to this column's reference r0.
-        const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
-        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
-        C ox = C(0), oy = C(0), oz = C(0); // u* of the stored state (outlet column)
-        if (xout) {
-            C r = C(0), qx = C(0), qy = C(0), qz = C(0);
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) {
-                const C v = ld<S>(src + (long long)i * N + n);
-                r += v;
-                if (L::cx[i] == 1) qx += v;
-                if (L::cx[i] == -1) qx -= v;
-                if (L::cy[i] == 1) qy += v;
-                if (L::cy[i] == -1) qy -= v;
-                if (L::cz[i] == 1) qz += v;
-                if (L::cz[i] == -1) qz -= v;
-            }
-            const C ir = C(1) / (S::shifted ? r0 + r : r);
-            ox = qx * ir;
-            oy = qy * ir;
-            oz = qz * ir;
-        }
-        const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
-            if (i == 0) {
-                f[0] = ld<S>(src + n);
-                continue;
-            }
-            const bool in_i = cx == 1 && xin, out_i = cx == -1 && xout;
-            const bool rev = in_i || out_i || ((d >> i) & DT(1));
-            const long long off = cx + cy * row + cz * plane;
-            const long long idx = rev ? (long long)o * N + n : (long long)i * N + n - off;
-            C v = ld<S>(src + idx);
-            if constexpr (S::colref) {
-                // a value streamed from column x - c_ix, re-referenced to r0
-                if (cx == 1)
-                    v = rev ? v : v + C(L::w[i]) * dm;
-                if (cx == -1)
-                    v = rev ? v : v + C(L::w[i]) * dp;
-            }
-            if (cx == 1)
-                v = in_i ? v + C(6.0 * L::w[i]) * C(a.u_in) : v;
-            if (cx == -1) {
-                const C cu = -ox + C(cy) * oy + C(cz) * oz;
-                const C even = C(4.5) * cu * cu - ousq;
-                v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - v : v;
-            }
-            f[i] = v;
-        }
-        C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            rs += f[i];
-            if (L::cx[i] == 1) jx += f[i];
-            if (L::cx[i] == -1) jx -= f[i];
-            if (L::cy[i] == 1) jy += f[i];
-            if (L::cy[i] == -1) jy -= f[i];
-            if (L::cz[i] == 1) jz += f[i];
-            if (L::cz[i] == -1) jz -= f[i];
-        }
-        rho = S::shifted ? r0 + rs : rs;
-        const C inv = C(1) / rho;
-        ux = jx * inv;
-        uy = jy * inv;
-        uz = jz * inv;
-        const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
-        const C om = C(a.omega);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            C cu = C(0);
-            if (L::cx[i] == 1) cu += ux;
-            if (L::cx[i] == -1) cu -= ux;
-            if (L::cy[i] == 1) cu += uy;
-            if (L::cy[i] == -1) cu -= uy;
-            if (L::cz[i] == 1) cu += uz;
-            if (L::cz[i] == -1) cu -= uz;
-            cu *= C(3);
-            // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
-            // minus the shift w_i when stored shifted (rs = rho - shift).
-            const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
-            f[i] = f[i] + om * (feq - f[i]);
-            if constexpr (S::colref)
-                f[i] += C(L::w[i]) * (r0 - rd); // to the written buffer's reference
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            f[i] = C(0);
-    }
-    // Every lane of the tile stores (blocked nodes store 0, a value nobody
-    // reads): whole-wave stores write whole cache lines, where lanes masked
-    // off by the geometry would turn stores into partial-line writes.
+    typename S::T *__restrict__ dst = static_cast<typename S::T *>(a.dst);
     if (p.inb) {
-        unsigned int rng = sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, a.step) : 0u;
+        unsigned int rng = sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, step) : 0u;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             st_pop<S, NT>(dst + (long long)i * N + p.n, f[i], rng);
@@ -469,6 +499,122 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
 }
 
 template <class L, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
+                                           unsigned long long *part_r, unsigned long long *part_u)
+{
+    typedef typename S::C C;
+    const long long N = a.g.N;
+    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
+    const bool act = (d & DT(1)) != 0;
+    C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
+    C f[L::Q];
+    C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+    if constexpr (S::colref) {
+        if (act)
+            column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
+    }
+    if (act) {
+        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), N, p.n};
+        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
+        auto fetch = [&](int i, int o, int cx, int cy, int cz, int mode) {
+            return src.get(i, o, cx + cy * row + cz * plane, mode);
+        };
+        fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+        if constexpr (S::colref) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                f[i] += C(L::w[i]) * (r0 - rd); // to the written buffer's reference
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            f[i] = C(0);
+    }
+    fluid_finish<L, S, DT, MODE, NT>(a, p, d, act, f, ux, uy, uz, rho, a.step, part_r, part_u);
+}
+
+// Two fluid steps of one 64 x 4 tile (2-D): the first over the tile and its
+// one-node halo (66 x 6, the halo computed redundantly -- the same code on
+// the same inputs as in its own tile) into LDS in the compute type, the
+// second from LDS; only the second is stored.  With FP64/FP32 storage this
+// equals two single steps (up to multiply-add contraction); FP16 storage
+// skips the intermediate rounding.
+// Step counter: a.step and a.step + 1; check (MODE_CHECK) on the second.
+template <class S, int MODE, bool NT>
+__device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
+                                            unsigned long long *part_r, unsigned long long *part_u)
+{
+    typedef D2Q9 L;
+    typedef uint16_t DT;
+    typedef typename S::C C;
+    constexpr int LX = 66, NR = LX * 6;
+    __shared__ C v[L::Q][6][LX];
+    const long long N = a.g.N;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * 4;
+    const DT *desc = static_cast<const DT *>(a.desc);
+    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
+    for (int r = threadIdx.x; r < NR; r += 256) {
+        const int lx = r % LX, ly = r / LX;
+        const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+        const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
+        const long long n = inb ? x + (long long)nx * y : 0;
+        const DT d = inb ? desc[n] : DT(0);
+        C f[L::Q];
+        if (d & DT(1)) {
+            C r0 = C(1), dm = C(0), dp = C(0), rd = C(1), ux, uy, uz, rho;
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
+            GlobalSrc<S> src = gsrc;
+            src.n = n;
+            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+                return src.get(i, o, cx + cy * (long long)nx, mode);
+            };
+            fluid_collide<L, S, DT>(a, x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                f[i] = C(0);
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            v[i][ly][lx] = f[i];
+    }
+    __syncthreads();
+    NodePos p;
+    p.x = x0 + (threadIdx.x & 63);
+    p.y = y0 + (threadIdx.x >> 6);
+    p.z = 0;
+    p.inb = p.x < nx && p.y < ny;
+    p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+    const DT d = p.inb ? desc[p.n] : DT(0);
+    const bool act = (d & DT(1)) != 0;
+    C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
+    C f[L::Q];
+    if (act) {
+        C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+        if constexpr (S::colref)
+            column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
+        const LdsSrc<C, L::Q, LX> src{v, (int)(threadIdx.x & 63) + 1, (int)(threadIdx.x >> 6) + 1};
+        auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+            return src.get2(i, o, cx, cy, mode);
+        };
+        fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+        if constexpr (S::colref) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                f[i] += C(L::w[i]) * (r0 - rd);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            f[i] = C(0);
+    }
+    fluid_finish<L, S, DT, MODE, NT>(a, p, d, act, f, ux, uy, uz, rho, a.step + 1, part_r, part_u);
+    __syncthreads(); // the block may run another tile: v is reused
+}
+
+template <class L, class S, class DT, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 {
     if (a.ctrl->stop)
@@ -486,106 +632,86 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 //   blocked source (SOLID/WALL):   h_i = h*_opp(n)       (zero flux)
 //   otherwise:                     h_i = h*_i(s)
 // Collision (Eq. 12) with the linear equilibrium w_i C (1 + c_i.u / c_s^2)
-// and the biofilm consumption - w_i k C.
-template <class L, int QF, class S, class DT, int MODE, bool NT>
-__device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
-                                        unsigned long long *part_r, unsigned long long *part_u)
+// and the biofilm consumption - w_i k C.  g[] comes back relative to r0.
+template <class L, int QF, class S, class DT, class Fetch>
+__device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const Fetch &fetch,
+                                           typename S::C ux, typename S::C uy, typename S::C uz,
+                                           typename S::C r0, typename S::C dm, typename S::C dp,
+                                           typename S::C g[L::Q], typename S::C &cfull)
 {
-    typedef typename S::T T;
     typedef typename S::C C;
-    constexpr int ACT = QF - 1 + L::Q;
-    constexpr int BIO = ACT + 1;
+    constexpr int BIO = QF + L::Q;
     constexpr int LNK = QF - 1;
+    const bool xin = x == 0, xout = x == a.g.nx - 1;
+    // Dirichlet values relative to this column's reference
+    const C cin_s = C(a.c_in - (double)r0), cout_s = C(a.c_out - (double)r0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
+        if (i == 0) {
+            g[0] = fetch(0, 0, 0, 0, 0, 2);
+            continue;
+        }
+        const bool in_i = cx == 1 && xin;
+        // zero-gradient outlet copies this node's own population i
+        const bool copy_i = cx == -1 && xout && !a.outlet;
+        const bool abb_i = cx == -1 && xout && a.outlet;
+        const bool rev = in_i || abb_i || ((d >> (LNK + i)) & DT(1));
+        C v = fetch(i, o, cx, cy, cz, rev ? 1 : (copy_i ? 2 : 0));
+        if constexpr (S::colref) {
+            if (cx == 1)
+                v = rev ? v : v + C(L::w[i]) * dm;
+            if (cx == -1)
+                v = (rev || copy_i) ? v : v + C(L::w[i]) * dp;
+        }
+        if constexpr (S::colref) {
+            if (cx == 1)
+                v = in_i ? C(2.0 * L::w[i]) * cin_s - v : v;
+            if (cx == -1)
+                v = abb_i ? C(2.0 * L::w[i]) * cout_s - v : v;
+        } else {
+            if (cx == 1)
+                v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
+            if (cx == -1)
+                v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
+        }
+        g[i] = v;
+    }
+    C cs = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        cs += g[i];
+    cfull = S::shifted ? r0 + cs : cs;
+    const C om = C(a.omega);
+    const C kc = ((d >> BIO) & DT(1)) ? C(a.k_sink) * cfull : C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        C cu = C(0);
+        if (L::cx[i] == 1) cu += ux;
+        if (L::cx[i] == -1) cu -= ux;
+        if (L::cy[i] == 1) cu += uy;
+        if (L::cy[i] == -1) cu -= uy;
+        if (L::cz[i] == 1) cu += uz;
+        if (L::cz[i] == -1) cu -= uz;
+        const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
+        g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+    }
+}
+
+template <class L, int QF, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void ad_finish(const AdArgs &a, const NodePos &p, DT d, bool act,
+                                          typename S::C g[L::Q], typename S::C cfull,
+                                          unsigned int step, unsigned long long *part_r,
+                                          unsigned long long *part_u)
+{
+    typedef typename S::C C;
+    constexpr int BIO = QF + L::Q;
     const long long N = a.g.N;
-    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
-    const bool act = ((d >> ACT) & DT(1)) != 0;
-    const T *__restrict__ src = static_cast<const T *>(a.src);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-    C cfull = C(0);
-    C g[L::Q];
-    C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0; // column references, as in the fluid
-    if constexpr (S::colref) {
-        if (act) {
-            r0 = a.ref_src[p.x];
-            dm = (p.x > 0 ? a.ref_src[p.x - 1] : r0) - r0;
-            dp = (p.x < a.g.nx - 1 ? a.ref_src[p.x + 1] : r0) - r0;
-            rd = a.ref_dst[p.x];
-        }
-    }
-    if (act) {
-        const long long n = p.n;
-        const bool xin = p.x == 0, xout = p.x == a.g.nx - 1;
-        // Dirichlet values relative to this column's reference
-        const C cin_s = C(a.c_in - (double)r0), cout_s = C(a.c_out - (double)r0);
-        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
-            if (i == 0) {
-                g[0] = ld<S>(src + n);
-                continue;
-            }
-            const bool in_i = cx == 1 && xin;
-            // zero-gradient outlet copies this node's own population i
-            const bool copy_i = cx == -1 && xout && !a.outlet;
-            const bool abb_i = cx == -1 && xout && a.outlet;
-            const bool rev = in_i || abb_i || ((d >> (LNK + i)) & DT(1));
-            const long long off = cx + cy * row + cz * plane;
-            const long long idx = rev ? (long long)o * N + n
-                                      : (copy_i ? (long long)i * N + n : (long long)i * N + n - off);
-            C v = ld<S>(src + idx);
-            if constexpr (S::colref) {
-                if (cx == 1)
-                    v = rev ? v : v + C(L::w[i]) * dm;
-                if (cx == -1)
-                    v = (rev || copy_i) ? v : v + C(L::w[i]) * dp;
-            }
-            if constexpr (S::colref) {
-                if (cx == 1)
-                    v = in_i ? C(2.0 * L::w[i]) * cin_s - v : v;
-                if (cx == -1)
-                    v = abb_i ? C(2.0 * L::w[i]) * cout_s - v : v;
-            } else {
-                if (cx == 1)
-                    v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
-                if (cx == -1)
-                    v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
-            }
-            g[i] = v;
-        }
-        C cs = C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            cs += g[i];
-        cfull = S::shifted ? r0 + cs : cs;
-        const C *U = static_cast<const C *>(a.u);
-        const C ux = U[n], uy = U[N + n];
-        const C uz = (L::DIM == 3) ? U[2 * N + n] : C(0);
-        const C om = C(a.omega);
-        const C kc = ((d >> BIO) & DT(1)) ? C(a.k_sink) * cfull : C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            C cu = C(0);
-            if (L::cx[i] == 1) cu += ux;
-            if (L::cx[i] == -1) cu -= ux;
-            if (L::cy[i] == 1) cu += uy;
-            if (L::cy[i] == -1) cu -= uy;
-            if (L::cz[i] == 1) cu += uz;
-            if (L::cz[i] == -1) cu -= uz;
-            const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
-            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
-            if constexpr (S::colref)
-                g[i] += C(L::w[i]) * (r0 - rd);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            g[i] = C(0);
-    }
-    // whole-wave stores (blocked nodes store 0): see the fluid step
+    typename S::T *__restrict__ dst = static_cast<typename S::T *>(a.dst);
+    // whole-wave stores (blocked nodes store 0): see fluid_finish
     if (p.inb) {
         unsigned int rng =
-            sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, a.step ^ 0x5bd1e995u) : 0u;
+            sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, step ^ 0x5bd1e995u) : 0u;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
             st_pop<S, NT>(dst + (long long)i * N + p.n, g[i], rng);
@@ -607,6 +733,122 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
 }
 
 template <class L, int QF, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
+                                        unsigned long long *part_r, unsigned long long *part_u)
+{
+    typedef typename S::C C;
+    constexpr int ACT = QF - 1 + L::Q;
+    const long long N = a.g.N;
+    const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
+    const bool act = ((d >> ACT) & DT(1)) != 0;
+    C cfull = C(0);
+    C g[L::Q];
+    C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+    if constexpr (S::colref) {
+        if (act)
+            column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
+    }
+    if (act) {
+        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), N, p.n};
+        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
+        auto fetch = [&](int i, int o, int cx, int cy, int cz, int mode) {
+            return src.get(i, o, cx + cy * row + cz * plane, mode);
+        };
+        const C *U = static_cast<const C *>(a.u);
+        const C ux = U[p.n], uy = U[N + p.n];
+        const C uz = (L::DIM == 3) ? U[2 * N + p.n] : C(0);
+        ad_collide<L, QF, S, DT>(a, p.x, d, fetch, ux, uy, uz, r0, dm, dp, g, cfull);
+        if constexpr (S::colref) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                g[i] += C(L::w[i]) * (r0 - rd);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            g[i] = C(0);
+    }
+    ad_finish<L, QF, S, DT, MODE, NT>(a, p, d, act, g, cfull, a.step, part_r, part_u);
+}
+
+// Two substrate steps of one 64 x 4 tile (2-D), as fluid_tile2.
+template <class S, int MODE, bool NT>
+__device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned long long *part_r,
+                                         unsigned long long *part_u)
+{
+    typedef D2Q5 L;
+    typedef uint16_t DT;
+    typedef typename S::C C;
+    constexpr int QF = 9, ACT = QF - 1 + L::Q;
+    constexpr int LX = 66, NR = LX * 6;
+    __shared__ C v[L::Q][6][LX];
+    const long long N = a.g.N;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * 4;
+    const DT *desc = static_cast<const DT *>(a.desc);
+    const C *U = static_cast<const C *>(a.u);
+    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
+    for (int r = threadIdx.x; r < NR; r += 256) {
+        const int lx = r % LX, ly = r / LX;
+        const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+        const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
+        const long long n = inb ? x + (long long)nx * y : 0;
+        const DT d = inb ? desc[n] : DT(0);
+        C g[L::Q];
+        if ((d >> ACT) & DT(1)) {
+            C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0, cfull;
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
+            GlobalSrc<S> src = gsrc;
+            src.n = n;
+            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+                return src.get(i, o, cx + cy * (long long)nx, mode);
+            };
+            ad_collide<L, QF, S, DT>(a, x, d, fetch, U[n], U[N + n], C(0), r0, dm, dp, g, cfull);
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                g[i] = C(0);
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            v[i][ly][lx] = g[i];
+    }
+    __syncthreads();
+    NodePos p;
+    p.x = x0 + (threadIdx.x & 63);
+    p.y = y0 + (threadIdx.x >> 6);
+    p.z = 0;
+    p.inb = p.x < nx && p.y < ny;
+    p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+    const DT d = p.inb ? desc[p.n] : DT(0);
+    const bool act = ((d >> ACT) & DT(1)) != 0;
+    C cfull = C(0);
+    C g[L::Q];
+    if (act) {
+        C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+        if constexpr (S::colref)
+            column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
+        const LdsSrc<C, L::Q, LX> src{v, (int)(threadIdx.x & 63) + 1, (int)(threadIdx.x >> 6) + 1};
+        auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+            return src.get2(i, o, cx, cy, mode);
+        };
+        ad_collide<L, QF, S, DT>(a, p.x, d, fetch, U[p.n], U[N + p.n], C(0), r0, dm, dp, g, cfull);
+        if constexpr (S::colref) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                g[i] += C(L::w[i]) * (r0 - rd);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            g[i] = C(0);
+    }
+    ad_finish<L, QF, S, DT, MODE, NT>(a, p, d, act, g, cfull, a.step + 1, part_r, part_u);
+    __syncthreads();
+}
+
+template <class L, int QF, class S, class DT, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
 {
     if (a.ctrl->stop)
@@ -614,6 +856,27 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
     const NodePos p = tile_node(a.g, xcd_tile(blockIdx.x, gridDim.x));
     unsigned long long *part = a.ctrl->part;
     ad_tile<L, QF, S, DT, MODE, NT>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
+}
+
+// Two steps per launch (2-D)
+template <class S, int MODE, bool NT>
+__global__ void __launch_bounds__(256) k_fluid_step2(FluidArgs a)
+{
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    fluid_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                             part + gridDim.x + blockIdx.x);
+}
+
+template <class S, int MODE, bool NT>
+__global__ void __launch_bounds__(256) k_ad_step2(AdArgs a)
+{
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    ad_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                          part + gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------- init / export
@@ -1004,13 +1267,13 @@ __global__ void __launch_bounds__(256) k_decide(Ctrl *c)
 }
 
 // ------------------------------------------------------ batched serving
-// One launch steps every request of the slot table by one step: a block
+// One launch advances every request of the slot table by two steps: a block
 // walks the table's tiles with a grid stride (tile v, v + G, ...), finds the
 // owning request by binary search over the tile offsets, and runs the same
-// per-tile code as the single-domain kernels in that request's phase.  All
-// of this is uniform across the block.  Requests are 2-D (D2Q9 + D2Q5).
-// Every phase starts in buffer 0 and a chunk has an even number of steps,
-// so step j of a chunk reads buffer j & 1.
+// two-step tile code as the single-domain kernels in that request's phase.
+// All of this is uniform across the block.  Requests are 2-D (D2Q9 +
+// D2Q5).  Every phase starts in buffer 0 and a chunk has an even number of
+// launches, so launch j of a chunk (steps 2j, 2j + 1) reads buffer j & 1.
 template <class S, int MODE>
 __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ slots,
                                                   const SrvTable *__restrict__ tab, Ctrl *ctrl,
@@ -1033,8 +1296,8 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
         Ctrl *c = ctrl + sid;
         if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
             continue;
-        const NodePos p = tile_node(sl.g, v - tab->begin[lo]);
-        const unsigned int step = (unsigned int)(c->t + j);
+        const int tile = v - tab->begin[lo];
+        const unsigned int step = (unsigned int)(c->t + 2 * j);
         if (sl.phase == SRV_FLUID) {
             FluidArgs a;
             a.src = sl.f[j & 1];
@@ -1051,7 +1314,7 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
             a.ref_src = sl.ref_cur;
             a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
             a.ref_out = sl.ref_next;
-            fluid_tile<D2Q9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
+            fluid_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v);
         } else {
             AdArgs a;
             a.src = sl.gp[j & 1];
@@ -1075,7 +1338,7 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
             a.ref_src = sl.ref_cur;
             a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
             a.ref_out = sl.ref_next;
-            ad_tile<D2Q5, 9, S, uint16_t, MODE, false>(a, p, part + v, part + part_cap + v);
+            ad_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v);
         }
     }
 }
@@ -1241,6 +1504,46 @@ hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStr
 #undef LBM_FLUID_LAUNCH
             return hipGetLastError();
         });
+    });
+}
+
+hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        const dim3 grid(a.g.ntiles);
+        if (a.streaming_stores) {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, true>), grid, dim3(256), 0, st, a);
+        } else {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, false>), grid, dim3(256), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, false>), grid, dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        const dim3 grid(a.g.ntiles);
+        if (a.streaming_stores) {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, true>), grid, dim3(256), 0, st, a);
+        } else {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, false>), grid, dim3(256), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, false>), grid, dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
     });
 }
 

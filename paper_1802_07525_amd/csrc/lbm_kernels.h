@@ -126,6 +126,13 @@ hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipS
 
 hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStream_t st);
 hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t st);
+// Two steps in one launch (2-D only): steps a.step and a.step + 1, the
+// check (MODE_CHECK) on the second; src -> dst like one step.  The
+// intermediate state stays in LDS in the compute type: FP64 and FP32
+// results equal two single steps (up to how the compiler contracts
+// multiply-adds in the two code paths); FP16 storage skips one rounding.
+hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st);
+hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,
@@ -205,8 +212,9 @@ struct SrvTable {
     int slot[SRV_MAX_SLOTS];
 };
 
-// One step of every request in tab (step j of the current chunk; MODE_CHECK
-// stores per-tile maxima at part[v] and part[part_cap + v]).
+// Two steps of every request in tab (launch j of the current chunk: steps
+// 2j and 2j + 1; MODE_CHECK stores per-tile maxima at part[v] and
+// part[part_cap + v]).
 hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                     unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st);
 // Stop rule for every request in tab after a check step.

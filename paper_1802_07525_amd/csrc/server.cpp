@@ -13,9 +13,10 @@
 //    is free and the request's footprint fits the pool (first fit), uploads
 //    the descriptors through a pinned ring, initialises the request on the
 //    device and adds its tiles to the device slot table.
-//  * Work proceeds in chunks of K steps: K launches of the batched step
-//    kernel (each covers every tile of every admitted request, in that
-//    request's phase) and one batched decide, captured once as a HIP graph
+//  * Work proceeds in chunks of K steps: K/2 launches of the batched step
+//    kernel (each advances every tile of every admitted request by two
+//    steps, in that request's phase) and one batched decide, captured once
+//    as a HIP graph
 //    that reads the slot table from device memory, so admissions never
 //    re-capture it.  After each chunk the control blocks are copied to
 //    pinned memory; the host keeps a bounded number of chunks in flight.
@@ -696,8 +697,9 @@ struct lbm_server {
     hipError_t enqueue_chunk()
     {
         hipError_t e;
-        for (int j = 0; j < K; ++j) {
-            if ((e = lbmk::srv_step(cfg.storage, j == K - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
+        const int nl = K / 2; // each launch advances two steps
+        for (int j = 0; j < nl; ++j) {
+            if ((e = lbmk::srv_step(cfg.storage, j == nl - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
                                     d_tab, d_ctrl, d_part, part_cap, j, blocks, stream)) != hipSuccess)
                 return e;
             if (j == 0 && lbmk::storage_moving_ref(cfg.storage) &&
@@ -930,8 +932,8 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         return set_err(ctx, LBM_EINVAL, "max_slots must be in 1..64");
     if (c.check_every == 0)
         c.check_every = 100;
-    if (c.check_every < 2 || (c.check_every & 1) || c.check_every > 1000)
-        return set_err(ctx, LBM_EINVAL, "check_every must be even and in 2..1000");
+    if (c.check_every < 4 || (c.check_every % 4) || c.check_every > 1000)
+        return set_err(ctx, LBM_EINVAL, "check_every must be a multiple of 4 in 4..1000");
     if (c.grid_blocks == 0)
         c.grid_blocks = 2048;
     if (c.grid_blocks < 1 || c.grid_blocks > 65536)

@@ -144,9 +144,18 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
     return LBM_OK;
 }
 
-// first: the first step after a residual check, which moves the stored
+// 2-D solvers launch two steps at a time (one launch, LDS between them)
+inline bool paired(const lbm_solver *s) { return s->dim == 2; }
+// kernel launches that cover `steps` steps taken from a chunk boundary
+inline int64_t launches_for(const lbm_solver *s, int64_t steps)
+{
+    return paired(s) ? steps / 2 + (steps & 1) : steps;
+}
+
+// One launch of `nsteps` (1, or 2 in 2-D) steps reading buffer src.
+// first: the first launch after a residual check, which moves the stored
 // state to the column reference sampled at that check (see lbm_kernels.h)
-hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first = false)
+hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first = false, int nsteps = 1)
 {
     if (which == LBM_SOLVER_FLUID) {
         lbmk::FluidArgs a;
@@ -160,11 +169,13 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
         a.u_in = s->p.u_in;
         a.inv_uin = 1.0 / ((double)s->p.check_every * fabs(s->p.u_in));
         a.streaming_stores = 2.0 * s->qf * (double)s->geo.N * sbytes(s) > STREAMING_BYTES;
-        a.step = (unsigned int)(s->fsteps++);
+        a.step = (unsigned int)s->fsteps;
+        s->fsteps += nsteps;
         a.ref_src = ref_cur(s, 0);
         a.ref_dst = first ? ref_next(s, 0) : ref_cur(s, 0);
         a.ref_out = ref_next(s, 0);
-        return lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+        return nsteps == 2 ? lbmk::fluid_step2(s->p.storage, mode, a, s->ctx->stream)
+                           : lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
     }
     const double cs2 = s->dim == 3 ? 0.25 : 1.0 / 3.0;
     lbmk::AdArgs a;
@@ -183,13 +194,15 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.inv_cin = 1.0 / ((double)s->p.check_every * fabs(s->p.c_in));
     a.outlet = s->p.outlet;
     a.streaming_stores = 2.0 * s->qa * (double)s->geo.N * sbytes(s) > STREAMING_BYTES;
-    a.step = (unsigned int)(s->gsteps++);
+    a.step = (unsigned int)s->gsteps;
+    s->gsteps += nsteps;
     a.c_in = s->p.c_in;
     a.c_out = s->p.c_out;
     a.ref_src = ref_cur(s, 1);
     a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
     a.ref_out = ref_next(s, 1);
-    return lbmk::ad_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+    return nsteps == 2 ? lbmk::ad_step2(s->p.storage, mode, a, s->ctx->stream)
+                       : lbmk::ad_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
 }
 
 lbm_status init_solver(lbm_solver *s, int which)
@@ -278,15 +291,19 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     int64_t launched = 0, head = 0, tail = 0;
     bool stopped = false;
     const bool roll = lbmk::storage_moving_ref(s->p.storage);
+    int64_t nlaunch = 0;
     while (launched < max_iter && !stopped) {
         const int64_t rem = max_iter - launched;
         const int64_t n = rem >= K ? K : rem;
-        for (int64_t j = 1; j <= n; ++j) {
-            const int mode = (n == K && j == K) ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
-            HIPCHK(launch_step(s, which, mode, (int)((cur0 + launched + j - 1) & 1), j == 1), "step launch");
+        for (int64_t j = 1; j <= n;) {
+            const int k = (paired(s) && j + 1 <= n) ? 2 : 1;
+            const int mode = (n == K && j + k - 1 == K) ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
+            HIPCHK(launch_step(s, which, mode, (int)((cur0 + nlaunch) & 1), j == 1, k), "step launch");
             if (j == 1 && roll)
                 HIPCHK(lbmk::ref_roll(ctrl, ref_cur(s, which), ref_next(s, which), s->grid.nx, stream),
                        "reference roll");
+            ++nlaunch;
+            j += k;
         }
         if (n == K)
             HIPCHK(lbmk::decide(ctrl, stream), "decide");
@@ -317,7 +334,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     HIPCHK(hipMemcpy(&fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
     const auto t1 = std::chrono::steady_clock::now();
     const int64_t t_final = fin.stop != lbmk::STOP_RUN ? fin.t_stop : launched;
-    cur = (int)((cur0 + t_final) & 1);
+    cur = (int)((cur0 + launches_for(s, t_final)) & 1);
     lbm_status result = LBM_NOT_CONVERGED;
     if (fin.stop == lbmk::STOP_OK)
         result = LBM_OK;
@@ -339,7 +356,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         info->active_nodes = which == LBM_SOLVER_FLUID ? s->n_fluid : s->n_ad;
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
         info->kernel_ms = ms;
-        info->launches = t_final;
+        info->launches = launches_for(s, t_final);
         const double upd = (double)t_final * (double)info->active_nodes;
         info->mlups = info->seconds > 0 ? upd / info->seconds / 1e6 : 0.0;
         info->gbps = ms > 0 ? upd * algo_bytes(s, which) / (ms * 1e-3) / 1e9 : 0.0;
@@ -596,9 +613,11 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
            "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
-    for (int64_t t = 0; t < nsteps; ++t) {
-        HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, cur), "step launch");
+    for (int64_t t = 0; t < nsteps;) {
+        const int k = (paired(s) && t + 2 <= nsteps) ? 2 : 1;
+        HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, cur, false, k), "step launch");
         cur ^= 1;
+        t += k;
     }
     HIPCHK(hipEventRecord(s->ev_b, stream), "event");
     HIPCHK(hipStreamSynchronize(stream), "steps sync");
@@ -622,15 +641,17 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
                             s->d_part + (size_t)which * 2 * s->geo.ntiles, s->geo.ntiles, stream),
            "ctrl");
-    std::vector<hipEvent_t> ev((size_t)2 * nsteps);
+    const int k = paired(s) ? 2 : 1; // steps per launch
+    const int nl = (nsteps + k - 1) / k;
+    std::vector<hipEvent_t> ev((size_t)2 * nl);
     for (auto &e : ev)
         HIPCHK(hipEventCreate(&e), "event");
     int &cur = which == 0 ? s->fcur : s->gcur;
     hipError_t err = hipSuccess;
-    for (int t = 0; t < nsteps && err == hipSuccess; ++t) {
+    for (int t = 0; t < nl && err == hipSuccess; ++t) {
         err = hipEventRecord(ev[2 * t], stream);
         if (err == hipSuccess)
-            err = launch_step(s, which, lbmk::MODE_PLAIN, cur);
+            err = launch_step(s, which, lbmk::MODE_PLAIN, cur, false, k);
         if (err == hipSuccess)
             err = hipEventRecord(ev[2 * t + 1], stream);
         cur ^= 1;
@@ -638,7 +659,7 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);
     double sum = 0.0;
-    for (int t = 0; t < nsteps && err == hipSuccess; ++t) {
+    for (int t = 0; t < nl && err == hipSuccess; ++t) {
         float ms = 0.f;
         err = hipEventElapsedTime(&ms, ev[2 * t], ev[2 * t + 1]);
         sum += ms;
@@ -646,7 +667,7 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
     for (auto &e : ev)
         (void)hipEventDestroy(e);
     HIPCHK(err, "per-launch timing");
-    *avg_ms = sum / nsteps;
+    *avg_ms = sum / nl;
     return LBM_OK;
 }
 
