@@ -274,31 +274,48 @@ __device__ __forceinline__ void block_sum4(double &a, double &b, double &c, doub
 }
 
 // Residual of one tile at a check step from the per-node changes (dx, dy,
-// dz) of an active node (act; zeros otherwise): the largest change of any
-// node, or (MEAN) the largest change of the tile mean over its active
-// nodes.  The mean serves FP16 storage: stochastic rounding injects
+// dz) of its active nodes: the largest change of any node, or (MEAN) the
+// largest change of the tile mean over its active nodes.  The mean serves FP16 storage: stochastic rounding injects
 // zero-mean noise into quantities the collisions conserve (momentum, the
 // substrate), so per-node changes carry a noise floor above ordinary
 // tolerances; the mean averages it out and keeps the smooth evolution.
+// A thread adds its nodes' changes; result() is then called by the whole
+// block (valid in thread 0 for MEAN; per thread otherwise, for the block
+// maximum that block_max_commit takes).  NaN is sticky.
 template <bool MEAN>
-__device__ __forceinline__ double check_residual(bool act, double dx, double dy, double dz)
-{
-    if constexpr (MEAN) {
-        double n = act ? 1.0 : 0.0;
-        block_sum4(dx, dy, dz, n);
-        if (threadIdx.x != 0 || n == 0.0)
-            return 0.0;
-        const double r = fmax(fmax(fabs(dx), fabs(dy)), fabs(dz)) / n;
-        return (dx != dx || dy != dy || dz != dz) ? __longlong_as_double(0x7ff8000000000000ll) : r;
-    } else {
+struct CheckAcc {
+    double a = 0.0, b = 0.0, c = 0.0, n = 0.0; // MEAN: sums and count; else a = max
+    unsigned long long ub = 0ull;               // max |u| bits (fluid)
+    __device__ __forceinline__ void add(bool act, double dx, double dy, double dz)
+    {
         if (!act)
-            return 0.0;
-        double m = fabs(dx);
-        m = (fabs(dy) > m || dy != dy) ? fabs(dy) : m;
-        m = (fabs(dz) > m || dz != dz) ? fabs(dz) : m;
-        return dx != dx ? __longlong_as_double(0x7ff8000000000000ll) : m;
+            return;
+        if constexpr (MEAN) {
+            a += dx;
+            b += dy;
+            c += dz;
+            n += 1.0;
+        } else {
+            double m = fabs(dx);
+            m = (fabs(dy) > m || dy != dy) ? fabs(dy) : m;
+            m = (fabs(dz) > m || dz != dz) ? fabs(dz) : m;
+            m = dx != dx ? __longlong_as_double(0x7ff8000000000000ll) : m;
+            a = (m > a || m != m) ? m : a;
+        }
     }
-}
+    __device__ __forceinline__ double result()
+    {
+        if constexpr (MEAN) {
+            block_sum4(a, b, c, n);
+            if (threadIdx.x != 0 || n == 0.0)
+                return 0.0;
+            const double r = fmax(fmax(fabs(a), fabs(b)), fabs(c)) / n;
+            return (a != a || b != b || c != c) ? __longlong_as_double(0x7ff8000000000000ll) : r;
+        } else {
+            return a;
+        }
+    }
+};
 
 // ------------------------------------------------------ population sources
 // Where a node's incoming populations come from.  get(i, o, off, mode):
@@ -321,10 +338,10 @@ struct GlobalSrc {
 };
 
 // The block's copy of the first step of a pair in LDS: [q][ly][lx] over the
-// tile and its one-node halo (LX x 6 nodes, lx = x - x0 + 1, ly = y - y0 + 1).
-template <class C, int Q, int LX>
+// tile and its one-node halo (LX x LY nodes, lx = x - x0 + 1, ly = y - y0 + 1).
+template <class C, int Q, int LY, int LX>
 struct LdsSrc {
-    const C (*v)[6][LX];
+    const C (*v)[LY][LX];
     int lx, ly;
     __device__ __forceinline__ C get2(int i, int o, int cx, int cy, int mode) const
     {
@@ -452,14 +469,10 @@ __device__ __forceinline__ void column_refs(const float *src, const float *dst, 
 // zeros on blocked nodes: whole-wave stores write whole cache lines where
 // lanes masked off by the geometry would turn stores into partial-line
 // writes) and, on check steps, the residual and the reference sample.
-template <class L, class S, class DT, int MODE, bool NT>
-__device__ __forceinline__ void fluid_finish(const FluidArgs &a, const NodePos &p, DT d, bool act,
-                                             typename S::C f[L::Q], typename S::C ux,
-                                             typename S::C uy, typename S::C uz,
-                                             typename S::C rho, unsigned int step,
-                                             unsigned long long *part_r, unsigned long long *part_u)
+template <class L, class S, bool NT>
+__device__ __forceinline__ void fluid_store(const FluidArgs &a, const NodePos &p,
+                                            typename S::C f[L::Q], unsigned int step)
 {
-    typedef typename S::C C;
     const long long N = a.g.N;
     typename S::T *__restrict__ dst = static_cast<typename S::T *>(a.dst);
     if (p.inb) {
@@ -468,33 +481,57 @@ __device__ __forceinline__ void fluid_finish(const FluidArgs &a, const NodePos &
         for (int i = 0; i < L::Q; ++i)
             st_pop<S, NT>(dst + (long long)i * N + p.n, f[i], rng);
     }
+}
+
+// Check-step work of one node: its change since the previous check into
+// acc, the new moments into uprev, and the column reference sample.
+template <class L, class S, class DT>
+__device__ __forceinline__ void fluid_check(const FluidArgs &a, const NodePos &p, DT d, bool act,
+                                            typename S::C ux, typename S::C uy, typename S::C uz,
+                                            typename S::C rho, CheckAcc<S::tile_mean> &acc)
+{
+    typedef typename S::C C;
+    if (!act)
+        return;
+    const long long N = a.g.N;
+    C *up = static_cast<C *>(a.uprev);
+    const double dx = (double)ux - (double)up[p.n];
+    const double dy = (double)uy - (double)up[N + p.n];
+    double dz = 0.0;
+    double um = fmax(fabs((double)ux), fabs((double)uy));
+    if (L::DIM == 3) {
+        dz = (double)uz - (double)up[2 * N + p.n];
+        um = fmax(um, fabs((double)uz));
+    }
+    if (ux != ux || uy != uy || uz != uz)
+        um = __longlong_as_double(0x7ff8000000000000ll);
+    const unsigned long long ubn = dbits(um);
+    acc.ub = ubn > acc.ub ? ubn : acc.ub;
+    up[p.n] = ux;
+    up[N + p.n] = uy;
+    if (L::DIM == 3)
+        up[2 * N + p.n] = uz;
+    if constexpr (S::colref) {
+        constexpr int REF = L::Q + (L::DIM == 3 ? 7 : 5) + 1;
+        if ((d >> REF) & DT(1))
+            a.ref_out[p.x] = rho;
+    }
+    acc.add(true, dx, dy, dz);
+}
+
+template <class L, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void fluid_finish(const FluidArgs &a, const NodePos &p, DT d, bool act,
+                                             typename S::C f[L::Q], typename S::C ux,
+                                             typename S::C uy, typename S::C uz,
+                                             typename S::C rho, unsigned int step,
+                                             unsigned long long *part_r, unsigned long long *part_u)
+{
+    fluid_store<L, S, NT>(a, p, f, step);
     if constexpr (MODE == MODE_CHECK) {
-        unsigned long long ub = 0ull;
-        double dx = 0.0, dy = 0.0, dz = 0.0;
-        if (act) {
-            C *up = static_cast<C *>(a.uprev);
-            dx = (double)ux - (double)up[p.n];
-            dy = (double)uy - (double)up[N + p.n];
-            double um = fmax(fabs((double)ux), fabs((double)uy));
-            if (L::DIM == 3) {
-                dz = (double)uz - (double)up[2 * N + p.n];
-                um = fmax(um, fabs((double)uz));
-            }
-            if (ux != ux || uy != uy || uz != uz)
-                um = __longlong_as_double(0x7ff8000000000000ll);
-            ub = dbits(um);
-            up[p.n] = ux;
-            up[N + p.n] = uy;
-            if (L::DIM == 3)
-                up[2 * N + p.n] = uz;
-            if constexpr (S::colref) {
-                constexpr int REF = L::Q + (L::DIM == 3 ? 7 : 5) + 1;
-                if ((d >> REF) & DT(1))
-                    a.ref_out[p.x] = rho;
-            }
-        }
-        const double r = check_residual<S::tile_mean>(act, dx, dy, dz);
-        block_max_commit(dbits(r * a.inv_uin), ub, part_r, part_u);
+        CheckAcc<S::tile_mean> acc;
+        fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
+        const double r = acc.result();
+        block_max_commit(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
     }
 }
 
@@ -533,25 +570,29 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
     fluid_finish<L, S, DT, MODE, NT>(a, p, d, act, f, ux, uy, uz, rho, a.step, part_r, part_u);
 }
 
-// Two fluid steps of one 64 x 4 tile (2-D): the first over the tile and its
-// one-node halo (66 x 6, the halo computed redundantly -- the same code on
-// the same inputs as in its own tile) into LDS in the compute type, the
-// second from LDS; only the second is stored.  With FP64/FP32 storage this
-// equals two single steps (up to multiply-add contraction); FP16 storage
-// skips the intermediate rounding.
-// Step counter: a.step and a.step + 1; check (MODE_CHECK) on the second.
-template <class S, int MODE, bool NT>
+// Tile height of the two-step kernels (2-D): 64 x PAIR_TY nodes per
+// 256-thread block, PAIR_TY / 4 nodes per thread in the second step.
+constexpr int PAIR_TY = 8;
+
+// Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
+// one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
+// code on the same inputs as in its own tile) into LDS in the compute type,
+// the second from LDS; only the second is stored.  With FP64/FP32 storage
+// this equals two single steps (up to multiply-add contraction); FP16
+// storage skips the intermediate rounding.  Step counter: a.step and
+// a.step + 1; check (MODE_CHECK) on the second.
+template <class S, int MODE, bool NT, int TY = PAIR_TY>
 __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
                                             unsigned long long *part_r, unsigned long long *part_u)
 {
     typedef D2Q9 L;
     typedef uint16_t DT;
     typedef typename S::C C;
-    constexpr int LX = 66, NR = LX * 6;
-    __shared__ C v[L::Q][6][LX];
+    constexpr int LX = 66, LY = TY + 2, NR = LX * LY;
+    __shared__ C v[L::Q][LY][LX];
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
-    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * 4;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const DT *desc = static_cast<const DT *>(a.desc);
     const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
     for (int r = threadIdx.x; r < NR; r += 256) {
@@ -581,36 +622,47 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
             v[i][ly][lx] = f[i];
     }
     __syncthreads();
-    NodePos p;
-    p.x = x0 + (threadIdx.x & 63);
-    p.y = y0 + (threadIdx.x >> 6);
-    p.z = 0;
-    p.inb = p.x < nx && p.y < ny;
-    p.n = p.inb ? p.x + (long long)nx * p.y : 0;
-    const DT d = p.inb ? desc[p.n] : DT(0);
-    const bool act = (d & DT(1)) != 0;
-    C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
-    C f[L::Q];
-    if (act) {
-        C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
-        if constexpr (S::colref)
-            column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
-        const LdsSrc<C, L::Q, LX> src{v, (int)(threadIdx.x & 63) + 1, (int)(threadIdx.x >> 6) + 1};
-        auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-            return src.get2(i, o, cx, cy, mode);
-        };
-        fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
-        if constexpr (S::colref) {
+    CheckAcc<S::tile_mean> acc;
+#pragma unroll
+    for (int k = 0; k < TY / 4; ++k) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * k;
+        NodePos p;
+        p.x = x0 + lx;
+        p.y = y0 + ly;
+        p.z = 0;
+        p.inb = p.x < nx && p.y < ny;
+        p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+        const DT d = p.inb ? desc[p.n] : DT(0);
+        const bool act = (d & DT(1)) != 0;
+        C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
+        C f[L::Q];
+        if (act) {
+            C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
+            const LdsSrc<C, L::Q, LY, LX> src{v, lx + 1, ly + 1};
+            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+                return src.get2(i, o, cx, cy, mode);
+            };
+            fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    f[i] += C(L::w[i]) * (r0 - rd);
+            }
+        } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                f[i] += C(L::w[i]) * (r0 - rd);
+                f[i] = C(0);
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            f[i] = C(0);
+        fluid_store<L, S, NT>(a, p, f, a.step + 1);
+        if constexpr (MODE == MODE_CHECK)
+            fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
     }
-    fluid_finish<L, S, DT, MODE, NT>(a, p, d, act, f, ux, uy, uz, rho, a.step + 1, part_r, part_u);
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
+    }
     __syncthreads(); // the block may run another tile: v is reused
 }
 
@@ -698,17 +750,13 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const F
     }
 }
 
-template <class L, int QF, class S, class DT, int MODE, bool NT>
-__device__ __forceinline__ void ad_finish(const AdArgs &a, const NodePos &p, DT d, bool act,
-                                          typename S::C g[L::Q], typename S::C cfull,
-                                          unsigned int step, unsigned long long *part_r,
-                                          unsigned long long *part_u)
+template <class L, class S, bool NT>
+__device__ __forceinline__ void ad_store(const AdArgs &a, const NodePos &p, typename S::C g[L::Q],
+                                         unsigned int step)
 {
-    typedef typename S::C C;
-    constexpr int BIO = QF + L::Q;
     const long long N = a.g.N;
     typename S::T *__restrict__ dst = static_cast<typename S::T *>(a.dst);
-    // whole-wave stores (blocked nodes store 0): see fluid_finish
+    // whole-wave stores (blocked nodes store 0): see fluid_store
     if (p.inb) {
         unsigned int rng =
             sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, step ^ 0x5bd1e995u) : 0u;
@@ -716,18 +764,37 @@ __device__ __forceinline__ void ad_finish(const AdArgs &a, const NodePos &p, DT 
         for (int i = 0; i < L::Q; ++i)
             st_pop<S, NT>(dst + (long long)i * N + p.n, g[i], rng);
     }
+}
+
+template <class L, int QF, class S, class DT>
+__device__ __forceinline__ void ad_check(const AdArgs &a, const NodePos &p, DT d, bool act,
+                                         typename S::C cfull, CheckAcc<S::tile_mean> &acc)
+{
+    typedef typename S::C C;
+    constexpr int BIO = QF + L::Q;
+    if (!act)
+        return;
+    C *cp = static_cast<C *>(a.cprev);
+    const double dc = (double)cfull - (double)cp[p.n];
+    cp[p.n] = cfull;
+    if constexpr (S::colref) {
+        if ((d >> (BIO + 1)) & DT(1))
+            a.ref_out[p.x] = cfull;
+    }
+    acc.add(true, dc, 0.0, 0.0);
+}
+
+template <class L, int QF, class S, class DT, int MODE, bool NT>
+__device__ __forceinline__ void ad_finish(const AdArgs &a, const NodePos &p, DT d, bool act,
+                                          typename S::C g[L::Q], typename S::C cfull,
+                                          unsigned int step, unsigned long long *part_r,
+                                          unsigned long long *part_u)
+{
+    ad_store<L, S, NT>(a, p, g, step);
     if constexpr (MODE == MODE_CHECK) {
-        double dc = 0.0;
-        if (act) {
-            C *cp = static_cast<C *>(a.cprev);
-            dc = (double)cfull - (double)cp[p.n];
-            cp[p.n] = cfull;
-            if constexpr (S::colref) {
-                if ((d >> (BIO + 1)) & DT(1))
-                    a.ref_out[p.x] = cfull;
-            }
-        }
-        const double r = check_residual<S::tile_mean>(act, dc, 0.0, 0.0);
+        CheckAcc<S::tile_mean> acc;
+        ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
+        const double r = acc.result();
         block_max_commit(dbits(r * a.inv_cin), 0ull, part_r, part_u);
     }
 }
@@ -771,8 +838,8 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
     ad_finish<L, QF, S, DT, MODE, NT>(a, p, d, act, g, cfull, a.step, part_r, part_u);
 }
 
-// Two substrate steps of one 64 x 4 tile (2-D), as fluid_tile2.
-template <class S, int MODE, bool NT>
+// Two substrate steps of one 64 x TY tile (2-D), as fluid_tile2.
+template <class S, int MODE, bool NT, int TY = PAIR_TY>
 __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned long long *part_r,
                                          unsigned long long *part_u)
 {
@@ -780,11 +847,11 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     typedef uint16_t DT;
     typedef typename S::C C;
     constexpr int QF = 9, ACT = QF - 1 + L::Q;
-    constexpr int LX = 66, NR = LX * 6;
-    __shared__ C v[L::Q][6][LX];
+    constexpr int LX = 66, LY = TY + 2, NR = LX * LY;
+    __shared__ C v[L::Q][LY][LX];
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
-    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * 4;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const DT *desc = static_cast<const DT *>(a.desc);
     const C *U = static_cast<const C *>(a.u);
     const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
@@ -815,36 +882,48 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
             v[i][ly][lx] = g[i];
     }
     __syncthreads();
-    NodePos p;
-    p.x = x0 + (threadIdx.x & 63);
-    p.y = y0 + (threadIdx.x >> 6);
-    p.z = 0;
-    p.inb = p.x < nx && p.y < ny;
-    p.n = p.inb ? p.x + (long long)nx * p.y : 0;
-    const DT d = p.inb ? desc[p.n] : DT(0);
-    const bool act = ((d >> ACT) & DT(1)) != 0;
-    C cfull = C(0);
-    C g[L::Q];
-    if (act) {
-        C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
-        if constexpr (S::colref)
-            column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
-        const LdsSrc<C, L::Q, LX> src{v, (int)(threadIdx.x & 63) + 1, (int)(threadIdx.x >> 6) + 1};
-        auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-            return src.get2(i, o, cx, cy, mode);
-        };
-        ad_collide<L, QF, S, DT>(a, p.x, d, fetch, U[p.n], U[N + p.n], C(0), r0, dm, dp, g, cfull);
-        if constexpr (S::colref) {
+    CheckAcc<S::tile_mean> acc;
+#pragma unroll
+    for (int k = 0; k < TY / 4; ++k) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * k;
+        NodePos p;
+        p.x = x0 + lx;
+        p.y = y0 + ly;
+        p.z = 0;
+        p.inb = p.x < nx && p.y < ny;
+        p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+        const DT d = p.inb ? desc[p.n] : DT(0);
+        const bool act = ((d >> ACT) & DT(1)) != 0;
+        C cfull = C(0);
+        C g[L::Q];
+        if (act) {
+            C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
+            const LdsSrc<C, L::Q, LY, LX> src{v, lx + 1, ly + 1};
+            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
+                return src.get2(i, o, cx, cy, mode);
+            };
+            ad_collide<L, QF, S, DT>(a, p.x, d, fetch, U[p.n], U[N + p.n], C(0), r0, dm, dp, g,
+                                     cfull);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    g[i] += C(L::w[i]) * (r0 - rd);
+            }
+        } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                g[i] += C(L::w[i]) * (r0 - rd);
+                g[i] = C(0);
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            g[i] = C(0);
+        ad_store<L, S, NT>(a, p, g, a.step + 1);
+        if constexpr (MODE == MODE_CHECK)
+            ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
     }
-    ad_finish<L, QF, S, DT, MODE, NT>(a, p, d, act, g, cfull, a.step + 1, part_r, part_u);
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit(dbits(r * a.inv_cin), 0ull, part_r, part_u);
+    }
     __syncthreads();
 }
 
@@ -1507,11 +1586,16 @@ hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStr
     });
 }
 
+int pair_tiles(const Geo &g)
+{
+    return g.ntx * ((g.ny + PAIR_TY - 1) / PAIR_TY) * g.nz;
+}
+
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
 {
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        const dim3 grid(a.g.ntiles);
+        const dim3 grid(pair_tiles(a.g));
         if (a.streaming_stores) {
             if (mode == MODE_CHECK)
                 hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);
@@ -1531,7 +1615,7 @@ hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st)
 {
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        const dim3 grid(a.g.ntiles);
+        const dim3 grid(pair_tiles(a.g));
         if (a.streaming_stores) {
             if (mode == MODE_CHECK)
                 hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);

@@ -133,6 +133,9 @@ hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t 
 // multiply-adds in the two code paths); FP16 storage skips one rounding.
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st);
 hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st);
+// Blocks (tiles) of a two-step launch; per-block check maxima need this many
+// slots (never more than g.ntiles).
+int pair_tiles(const Geo &g);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,

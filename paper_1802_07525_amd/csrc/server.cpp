@@ -260,6 +260,7 @@ struct Job {
     std::vector<uint8_t> cls;
     std::vector<uint16_t> desc;
     lbmk::Geo geo{};
+    int tiles = 0; // blocks of the two-step kernels over this request
     int64_t n_fluid = 0, n_ad = 0;
     Layout lay{};
     double t_submit = 0, t_admit = 0, t_finish = 0;
@@ -446,6 +447,7 @@ struct lbm_server {
             j->n_ad += (d[n] >> aab) & 1u;
         }
         j->geo = lbmk::make_geo(r.nx, r.ny, 1);
+        j->tiles = lbmk::pair_tiles(j->geo);
         j->cls.clear();
         j->cls.shrink_to_fit();
     }
@@ -536,7 +538,7 @@ struct lbm_server {
         j->valid_from = chunks;
         j->t_admit = now_s(t0);
         slot_job[sid] = j;
-        tiles_used += j->geo.ntiles;
+        tiles_used += j->tiles;
         table_dirty = true;
         return hipSuccess;
     }
@@ -619,7 +621,7 @@ struct lbm_server {
         // copies above, so both are free for reuse at once.
         j->phase = PH_RETIRING;
         slot_job[j->sid] = nullptr;
-        tiles_used -= j->geo.ntiles;
+        tiles_used -= j->tiles;
         alloc.release(j->off, j->lay.total);
         table_dirty = true;
         ++n_retiring;
@@ -655,7 +657,7 @@ struct lbm_server {
                 continue;
             t.begin[e] = tiles;
             t.slot[e] = s;
-            tiles += j->geo.ntiles;
+            tiles += j->tiles;
             ++e;
         }
         t.begin[e] = tiles;
@@ -755,7 +757,7 @@ struct lbm_server {
                     sid = s;
                     break;
                 }
-            if (sid < 0 || tiles_used + j->geo.ntiles > part_cap)
+            if (sid < 0 || tiles_used + j->tiles > part_cap)
                 return hipSuccess;
             if (!alloc.alloc(j->lay.total, &j->off))
                 return hipSuccess;
@@ -1046,7 +1048,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
     if (m.empty()) {
         j->lay = layout_of(r->nx, N, s->cfg.storage);
         if (j->lay.total > s->cfg.pool_bytes ||
-            lbmk::make_geo(r->nx, r->ny, 1).ntiles > s->part_cap)
+            lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1)) > s->part_cap)
             m = "request larger than the server pool";
         else if (r->cls)
             j->cls.assign(r->cls, r->cls + N);
