@@ -343,7 +343,6 @@ typedef struct {
     int32_t check_every;   /* K: steps per chunk and residual cadence, a multiple of 4
                               (100 if 0) */
     int32_t stall_checks;  /* as lbm_params */
-    int32_t grid_blocks;   /* workgroups of each batched step launch (2048 if 0) */
     int32_t inflight;      /* chunks enqueued ahead of the decisions, 1..6 (2 if 0) */
     int32_t prep_threads;  /* host threads that build masks, 1..16 (2 if 0) */
     int32_t direct_launch; /* 1: launch each chunk's kernels directly instead of the graph */

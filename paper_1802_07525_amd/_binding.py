@@ -64,7 +64,7 @@ class lbm_fibre_params(ct.Structure):
 class lbm_server_cfg(ct.Structure):
     _fields_ = [("pool_bytes", ct.c_size_t), ("max_slots", ct.c_int32), ("storage", ct.c_int32),
                 ("check_every", ct.c_int32), ("stall_checks", ct.c_int32),
-                ("grid_blocks", ct.c_int32), ("inflight", ct.c_int32),
+                ("inflight", ct.c_int32),
                 ("prep_threads", ct.c_int32), ("direct_launch", ct.c_int32)]
 
 
@@ -494,9 +494,9 @@ def lbm_server_footprint(nx, ny, storage):
 
 
 def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_every=100,
-                    stall_checks=0, grid_blocks=0, inflight=0, prep_threads=0, direct_launch=0):
+                    stall_checks=0, inflight=0, prep_threads=0, direct_launch=0):
     return lbm_server_cfg(int(pool_bytes), int(max_slots), int(storage), int(check_every),
-                          int(stall_checks), int(grid_blocks), int(inflight), int(prep_threads),
+                          int(stall_checks), int(inflight), int(prep_threads),
                           int(direct_launch))
 
 

@@ -114,10 +114,26 @@ struct SF16S {
     static constexpr bool shifted = true;
 };
 
+// Global-memory view of a pointer.  The batched kernels take their buffer
+// pointers from the slot table in memory, where the compiler cannot see that
+// they address global memory; generic (flat) accesses would then need a
+// 64-bit address register per access.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ LBM_GLOBAL T *gmem(T *p)
+{
+    return (LBM_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ const LBM_GLOBAL T *gmem(const T *p)
+{
+    return (const LBM_GLOBAL T *)p;
+}
+
 template <class S>
 __device__ __forceinline__ typename S::C ld(const typename S::T *p)
 {
-    return static_cast<typename S::C>(*p);
+    return static_cast<typename S::C>(*gmem(p));
 }
 template <class S>
 __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
@@ -173,9 +189,9 @@ __device__ __forceinline__ void st_pop(typename S::T *p, typename S::C v, unsign
 {
     const typename S::T h = pop_value<S>(v, rng);
     if constexpr (NT)
-        __builtin_nontemporal_store(h, p);
+        __builtin_nontemporal_store(h, gmem(p));
     else
-        *p = h;
+        *gmem(p) = h;
 }
 
 // Contiguous band of tiles per XCD: hardware block b runs on XCD b mod 8.
@@ -459,10 +475,10 @@ __device__ __forceinline__ void column_refs(const float *src, const float *dst, 
                                             typename S::C &dp, typename S::C &rd)
 {
     typedef typename S::C C;
-    r0 = src[x];
-    dm = (x > 0 ? src[x - 1] : r0) - r0;
-    dp = (x < nx - 1 ? src[x + 1] : r0) - r0;
-    rd = dst[x];
+    r0 = gmem(src)[x];
+    dm = (x > 0 ? gmem(src)[x - 1] : r0) - r0;
+    dp = (x < nx - 1 ? gmem(src)[x + 1] : r0) - r0;
+    rd = gmem(dst)[x];
 }
 
 // Final part of a fluid step at one node: store (every in-grid lane, with
@@ -494,7 +510,7 @@ __device__ __forceinline__ void fluid_check(const FluidArgs &a, const NodePos &p
     if (!act)
         return;
     const long long N = a.g.N;
-    C *up = static_cast<C *>(a.uprev);
+    LBM_GLOBAL C *up = gmem(static_cast<C *>(a.uprev));
     const double dx = (double)ux - (double)up[p.n];
     const double dy = (double)uy - (double)up[N + p.n];
     double dz = 0.0;
@@ -514,7 +530,7 @@ __device__ __forceinline__ void fluid_check(const FluidArgs &a, const NodePos &p
     if constexpr (S::colref) {
         constexpr int REF = L::Q + (L::DIM == 3 ? 7 : 5) + 1;
         if ((d >> REF) & DT(1))
-            a.ref_out[p.x] = rho;
+            gmem(a.ref_out)[p.x] = rho;
     }
     acc.add(true, dx, dy, dz);
 }
@@ -581,19 +597,27 @@ constexpr int PAIR_TY = 8;
 // this equals two single steps (up to multiply-add contraction); FP16
 // storage skips the intermediate rounding.  Step counter: a.step and
 // a.step + 1; check (MODE_CHECK) on the second.
+// LDS bytes of the two-step tile functions (their first-step copies)
+template <class C, int Q, int TY = PAIR_TY>
+constexpr int pair_lds_bytes()
+{
+    return Q * (TY + 2) * 66 * (int)sizeof(C);
+}
+
 template <class S, int MODE, bool NT, int TY = PAIR_TY>
 __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
-                                            unsigned long long *part_r, unsigned long long *part_u)
+                                            unsigned long long *part_r, unsigned long long *part_u,
+                                            void *smem)
 {
     typedef D2Q9 L;
     typedef uint16_t DT;
     typedef typename S::C C;
     constexpr int LX = 66, LY = TY + 2, NR = LX * LY;
-    __shared__ C v[L::Q][LY][LX];
+    C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
-    const DT *desc = static_cast<const DT *>(a.desc);
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
@@ -774,12 +798,12 @@ __device__ __forceinline__ void ad_check(const AdArgs &a, const NodePos &p, DT d
     constexpr int BIO = QF + L::Q;
     if (!act)
         return;
-    C *cp = static_cast<C *>(a.cprev);
+    LBM_GLOBAL C *cp = gmem(static_cast<C *>(a.cprev));
     const double dc = (double)cfull - (double)cp[p.n];
     cp[p.n] = cfull;
     if constexpr (S::colref) {
         if ((d >> (BIO + 1)) & DT(1))
-            a.ref_out[p.x] = cfull;
+            gmem(a.ref_out)[p.x] = cfull;
     }
     acc.add(true, dc, 0.0, 0.0);
 }
@@ -841,19 +865,19 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
 // Two substrate steps of one 64 x TY tile (2-D), as fluid_tile2.
 template <class S, int MODE, bool NT, int TY = PAIR_TY>
 __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned long long *part_r,
-                                         unsigned long long *part_u)
+                                         unsigned long long *part_u, void *smem)
 {
     typedef D2Q5 L;
     typedef uint16_t DT;
     typedef typename S::C C;
     constexpr int QF = 9, ACT = QF - 1 + L::Q;
     constexpr int LX = 66, LY = TY + 2, NR = LX * LY;
-    __shared__ C v[L::Q][LY][LX];
+    C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
-    const DT *desc = static_cast<const DT *>(a.desc);
-    const C *U = static_cast<const C *>(a.u);
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
     const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
@@ -941,21 +965,23 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
 template <class S, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_fluid_step2(FluidArgs a)
 {
+    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, 9>()];
     if (a.ctrl->stop)
         return;
     unsigned long long *part = a.ctrl->part;
     fluid_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
-                             part + gridDim.x + blockIdx.x);
+                             part + gridDim.x + blockIdx.x, smem);
 }
 
 template <class S, int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_ad_step2(AdArgs a)
 {
+    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, 5>()];
     if (a.ctrl->stop)
         return;
     unsigned long long *part = a.ctrl->part;
     ad_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
-                          part + gridDim.x + blockIdx.x);
+                          part + gridDim.x + blockIdx.x, smem);
 }
 
 // ------------------------------------------------------- init / export
@@ -1346,79 +1372,82 @@ __global__ void __launch_bounds__(256) k_decide(Ctrl *c)
 }
 
 // ------------------------------------------------------ batched serving
-// One launch advances every request of the slot table by two steps: a block
-// walks the table's tiles with a grid stride (tile v, v + G, ...), finds the
-// owning request by binary search over the tile offsets, and runs the same
-// two-step tile code as the single-domain kernels in that request's phase.
-// All of this is uniform across the block.  Requests are 2-D (D2Q9 +
-// D2Q5).  Every phase starts in buffer 0 and a chunk has an even number of
-// launches, so launch j of a chunk (steps 2j, 2j + 1) reads buffer j & 1.
+// One launch advances every request of the slot table by two steps: block b
+// takes tile v of the table (XCD-banded numbering), finds the owning request
+// by binary search over the tile offsets and runs the same two-step tile code
+// as the single-domain kernels in that request's phase; blocks past the
+// table's tiles exit.  The grid is a power of two at least the table's tile
+// count (one captured graph per size).  All of this is uniform across the
+// block.  Requests are 2-D (D2Q9 + D2Q5).  Every phase starts in buffer 0
+// and a chunk has an even number of launches, so launch j of a chunk (steps
+// 2j, 2j + 1) reads buffer j & 1.
 template <class S, int MODE>
 __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ slots,
                                                   const SrvTable *__restrict__ tab, Ctrl *ctrl,
                                                   unsigned long long *part, int part_cap, int j)
 {
-    const int T = tab->total_tiles;
-    const int na = tab->n_active;
-    const int G = gridDim.x;
-    for (int v = xcd_tile(blockIdx.x, G); v < T; v += G) {
-        int lo = 0, hi = na - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab->begin[mid] <= v)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const int sid = tab->slot[lo];
-        const SrvSlot &sl = slots[sid];
-        Ctrl *c = ctrl + sid;
-        if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
-            continue;
-        const int tile = v - tab->begin[lo];
-        const unsigned int step = (unsigned int)(c->t + 2 * j);
-        if (sl.phase == SRV_FLUID) {
-            FluidArgs a;
-            a.src = sl.f[j & 1];
-            a.dst = sl.f[(j & 1) ^ 1];
-            a.desc = sl.desc;
-            a.uprev = sl.prev;
-            a.ctrl = c;
-            a.g = sl.g;
-            a.omega = sl.omega_f;
-            a.u_in = sl.u_in;
-            a.inv_uin = sl.inv_uin;
-            a.streaming_stores = 0;
-            a.step = step;
-            a.ref_src = sl.ref_cur;
-            a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
-            a.ref_out = sl.ref_next;
-            fluid_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v);
-        } else {
-            AdArgs a;
-            a.src = sl.gp[j & 1];
-            a.dst = sl.gp[(j & 1) ^ 1];
-            a.desc = sl.desc;
-            a.u = sl.u;
-            a.cprev = sl.prev;
-            a.ctrl = c;
-            a.g = sl.g;
-            a.omega = sl.omega_a;
-            a.cin_s = sl.cin_s;
-            a.cout_s = sl.cout_s;
-            a.c_ref = sl.c_ref;
-            a.k_sink = sl.k_sink;
-            a.inv_cin = sl.inv_cin;
-            a.outlet = sl.outlet;
-            a.streaming_stores = 0;
-            a.step = step;
-            a.c_in = sl.c_in;
-            a.c_out = sl.c_out;
-            a.ref_src = sl.ref_cur;
-            a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
-            a.ref_out = sl.ref_next;
-            ad_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v);
-        }
+    typedef typename S::C C;
+    constexpr int LF = pair_lds_bytes<C, 9>(), LA = pair_lds_bytes<C, 5>();
+    __shared__ __align__(16) char smem[LF > LA ? LF : LA];
+    const int v = xcd_tile(blockIdx.x, gridDim.x);
+    if (v >= tab->total_tiles)
+        return;
+    int lo = 0, hi = tab->n_active - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->begin[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int sid = tab->slot[lo];
+    const SrvSlot &sl = slots[sid];
+    Ctrl *c = ctrl + sid;
+    if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
+        return;
+    const int tile = v - tab->begin[lo];
+    const unsigned int step = (unsigned int)(c->t + 2 * j);
+    if (sl.phase == SRV_FLUID) {
+        FluidArgs a;
+        a.src = sl.f[j & 1];
+        a.dst = sl.f[(j & 1) ^ 1];
+        a.desc = sl.desc;
+        a.uprev = sl.prev;
+        a.ctrl = c;
+        a.g = sl.g;
+        a.omega = sl.omega_f;
+        a.u_in = sl.u_in;
+        a.inv_uin = sl.inv_uin;
+        a.streaming_stores = 0;
+        a.step = step;
+        a.ref_src = sl.ref_cur;
+        a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+        a.ref_out = sl.ref_next;
+        fluid_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v, smem);
+    } else {
+        AdArgs a;
+        a.src = sl.gp[j & 1];
+        a.dst = sl.gp[(j & 1) ^ 1];
+        a.desc = sl.desc;
+        a.u = sl.u;
+        a.cprev = sl.prev;
+        a.ctrl = c;
+        a.g = sl.g;
+        a.omega = sl.omega_a;
+        a.cin_s = sl.cin_s;
+        a.cout_s = sl.cout_s;
+        a.c_ref = sl.c_ref;
+        a.k_sink = sl.k_sink;
+        a.inv_cin = sl.inv_cin;
+        a.outlet = sl.outlet;
+        a.streaming_stores = 0;
+        a.step = step;
+        a.c_in = sl.c_in;
+        a.c_out = sl.c_out;
+        a.ref_src = sl.ref_cur;
+        a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+        a.ref_out = sl.ref_next;
+        ad_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v, smem);
     }
 }
 

@@ -217,7 +217,8 @@ struct SrvTable {
 
 // Two steps of every request in tab (launch j of the current chunk: steps
 // 2j and 2j + 1; MODE_CHECK stores per-tile maxima at part[v] and
-// part[part_cap + v]).
+// part[part_cap + v]).  One block per tile: blocks must be at least
+// tab->total_tiles (the extra blocks exit).
 hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                     unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st);
 // Stop rule for every request in tab after a check step.

@@ -340,7 +340,7 @@ double now_s(std::chrono::steady_clock::time_point t0)
 struct lbm_server {
     int device = 0;
     lbm_server_cfg cfg{};
-    int K = 100, window = 0, blocks = 2048, depth = 2;
+    int K = 100, window = 0, depth = 2;
     hipStream_t stream = nullptr;
     std::chrono::steady_clock::time_point t0;
 
@@ -353,8 +353,12 @@ struct lbm_server {
     int part_cap = 0;
     double *d_partials = nullptr;
     double *d_out = nullptr; // [SRV_MAX_SLOTS][10] flux results
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one captured chunk per grid size: blocks = MIN_GRID << k, the smallest
+    // one covering the table's tiles is launched (extra blocks exit at once)
+    static const int MIN_GRID = 64;
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
+    int table_tiles = 0;
 
     // host state owned by the worker
     PoolAlloc alloc;
@@ -663,6 +667,7 @@ struct lbm_server {
         t.begin[e] = tiles;
         t.n_active = e;
         t.total_tiles = tiles;
+        table_tiles = tiles;
         table_dirty = false;
         return lbmk::srv_table_set(d_tab, t, stream);
     }
@@ -678,10 +683,13 @@ struct lbm_server {
     hipError_t launch_chunk()
     {
         hipError_t e;
-        if (exec) {
-            if ((e = hipGraphLaunch(exec, stream)) != hipSuccess)
+        if (!execs.empty()) {
+            size_t k = 0;
+            while ((MIN_GRID << k) < table_tiles && k + 1 < execs.size())
+                ++k;
+            if ((e = hipGraphLaunch(execs[k], stream)) != hipSuccess)
                 return e;
-        } else if ((e = enqueue_chunk()) != hipSuccess) {
+        } else if ((e = enqueue_chunk(std::max(table_tiles, 1))) != hipSuccess) {
             return e;
         }
         const int r = (int)(head % RING);
@@ -696,13 +704,13 @@ struct lbm_server {
         return hipSuccess;
     }
 
-    hipError_t enqueue_chunk()
+    hipError_t enqueue_chunk(int grid)
     {
         hipError_t e;
         const int nl = K / 2; // each launch advances two steps
         for (int j = 0; j < nl; ++j) {
             if ((e = lbmk::srv_step(cfg.storage, j == nl - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
-                                    d_tab, d_ctrl, d_part, part_cap, j, blocks, stream)) != hipSuccess)
+                                    d_tab, d_ctrl, d_part, part_cap, j, grid, stream)) != hipSuccess)
                 return e;
             if (j == 0 && lbmk::storage_moving_ref(cfg.storage) &&
                 (e = lbmk::srv_ref_roll(d_slots, d_tab, d_ctrl, stream)) != hipSuccess)
@@ -936,10 +944,6 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         c.check_every = 100;
     if (c.check_every < 4 || (c.check_every % 4) || c.check_every > 1000)
         return set_err(ctx, LBM_EINVAL, "check_every must be a multiple of 4 in 4..1000");
-    if (c.grid_blocks == 0)
-        c.grid_blocks = 2048;
-    if (c.grid_blocks < 1 || c.grid_blocks > 65536)
-        return set_err(ctx, LBM_EINVAL, "grid_blocks must be in 1..65536");
     if (c.inflight == 0)
         c.inflight = 2;
     if (c.inflight < 1 || c.inflight > 6)
@@ -960,7 +964,6 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     s->window = c.stall_checks < 0 ? 0
                                    : (c.stall_checks > 0 ? c.stall_checks
                                                          : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
-    s->blocks = c.grid_blocks;
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();
     // tiles: each holds 256 nodes of at least 54 pool bytes; ragged tiles at
@@ -1011,18 +1014,26 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         if ((e = hipEventCreateWithFlags(&s->ev_snap[k], hipEventDisableTiming)) != hipSuccess)
             return cleanup(hip_err(ctx, e, "event"));
     if (!c.direct_launch) {
-        // one chunk, captured once: it reads the slot table at run time
+        // the chunk, captured once per grid size: it reads the slot table at
+        // run time, so admissions and retirements never re-capture
         if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
             return cleanup(hip_err(ctx, e, "server init"));
-        if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return cleanup(hip_err(ctx, e, "graph capture"));
-        hipError_t le = s->enqueue_chunk();
-        e = hipStreamEndCapture(s->stream, &s->graph);
-        if (le != hipSuccess || e != hipSuccess)
-            return cleanup(hip_err(ctx, le != hipSuccess ? le : e, "graph capture"));
-        if ((e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0)) != hipSuccess) {
-            s->exec = nullptr;
-            return cleanup(hip_err(ctx, e, "graph instantiate"));
+        for (int64_t grid = lbm_server::MIN_GRID;; grid *= 2) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t x = nullptr;
+            if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return cleanup(hip_err(ctx, e, "graph capture"));
+            hipError_t le = s->enqueue_chunk((int)grid);
+            e = hipStreamEndCapture(s->stream, &g);
+            if (g)
+                s->graphs.push_back(g);
+            if (le != hipSuccess || e != hipSuccess)
+                return cleanup(hip_err(ctx, le != hipSuccess ? le : e, "graph capture"));
+            if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
+                return cleanup(hip_err(ctx, e, "graph instantiate"));
+            s->execs.push_back(x);
+            if (grid >= s->part_cap)
+                break;
         }
     }
     if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
@@ -1176,10 +1187,10 @@ void lbm_server_destroy(lbm_server *s)
     s->res_ring.reclaim = nullptr;
     s->up_ring.destroy();
     s->res_ring.destroy();
-    if (s->exec)
-        (void)hipGraphExecDestroy(s->exec);
-    if (s->graph)
-        (void)hipGraphDestroy(s->graph);
+    for (hipGraphExec_t x : s->execs)
+        (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : s->graphs)
+        (void)hipGraphDestroy(g);
     for (int k = 0; k < lbm_server::RING; ++k)
         if (s->ev_snap[k])
             (void)hipEventDestroy(s->ev_snap[k]);

@@ -137,7 +137,7 @@ def test_server_graph_equals_direct_launch(srv_env):
     lbm, ctx = srv_env
     specs = [MIX[0], MIX[2]]
     g, _, _ = _serve(lbm, ctx, specs, FP32S)
-    d, _, _ = _serve(lbm, ctx, specs, FP32S, direct_launch=1, grid_blocks=96, inflight=1)
+    d, _, _ = _serve(lbm, ctx, specs, FP32S, direct_launch=1, inflight=1)
     for i in range(len(specs)):
         assert g[i]["iters_fluid"] == d[i]["iters_fluid"] and g[i]["iters_ad"] == d[i]["iters_ad"]
         assert np.array_equal(g[i]["u"], d[i]["u"]) and np.array_equal(g[i]["c"], d[i]["c"])
