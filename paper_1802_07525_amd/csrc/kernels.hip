@@ -130,6 +130,16 @@ __device__ __forceinline__ const LBM_GLOBAL T *gmem(const T *p)
     return (const LBM_GLOBAL T *)p;
 }
 
+// 1 / x: the hardware reciprocal (1 ulp) in FP32, a division in FP64
+__device__ __forceinline__ float recip(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+__device__ __forceinline__ double recip(double x)
+{
+    return 1.0 / x;
+}
+
 template <class S>
 __device__ __forceinline__ typename S::C ld(const typename S::T *p)
 {
@@ -386,26 +396,6 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
 {
     typedef typename S::C C;
     const bool xin = x == 0, xout = x == a.g.nx - 1;
-    C ox = C(0), oy = C(0), oz = C(0); // u* of the stored state (outlet column)
-    if (xout) {
-        C r = C(0), qx = C(0), qy = C(0), qz = C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const C v = fetch(i, L::op[i], L::cx[i], L::cy[i], L::cz[i], 2);
-            r += v;
-            if (L::cx[i] == 1) qx += v;
-            if (L::cx[i] == -1) qx -= v;
-            if (L::cy[i] == 1) qy += v;
-            if (L::cy[i] == -1) qy -= v;
-            if (L::cz[i] == 1) qz += v;
-            if (L::cz[i] == -1) qz -= v;
-        }
-        const C ir = C(1) / (S::shifted ? r0 + r : r);
-        ox = qx * ir;
-        oy = qy * ir;
-        oz = qz * ir;
-    }
-    const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
@@ -423,14 +413,40 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
             if (cx == -1)
                 v = rev ? v : v + C(L::w[i]) * dp;
         }
-        if (cx == 1)
-            v = in_i ? v + C(6.0 * L::w[i]) * C(a.u_in) : v;
-        if (cx == -1) {
-            const C cu = -ox + C(cy) * oy + C(cz) * oz;
-            const C even = C(4.5) * cu * cu - ousq;
-            v = out_i ? C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - v : v;
-        }
         f[i] = v;
+    }
+    // boundary columns (branches: waves without such a node skip them)
+    if (xin) {
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i)
+            if (L::cx[i] == 1)
+                f[i] = f[i] + C(6.0 * L::w[i]) * C(a.u_in);
+    }
+    if (xout) {
+        // u* of this node's stored state
+        C r = C(0), qx = C(0), qy = C(0), qz = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const C v = fetch(i, L::op[i], L::cx[i], L::cy[i], L::cz[i], 2);
+            r += v;
+            if (L::cx[i] == 1) qx += v;
+            if (L::cx[i] == -1) qx -= v;
+            if (L::cy[i] == 1) qy += v;
+            if (L::cy[i] == -1) qy -= v;
+            if (L::cz[i] == 1) qz += v;
+            if (L::cz[i] == -1) qz -= v;
+        }
+        const C ir = recip(S::shifted ? r0 + r : r);
+        const C ox = qx * ir, oy = qy * ir, oz = qz * ir;
+        const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            if (L::cx[i] != -1)
+                continue;
+            const C cu = -ox + C(L::cy[i]) * oy + C(L::cz[i]) * oz;
+            const C even = C(4.5) * cu * cu - ousq;
+            f[i] = C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - f[i];
+        }
     }
     C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -444,7 +460,7 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
         if (L::cz[i] == -1) jz -= f[i];
     }
     rho = S::shifted ? r0 + rs : rs;
-    const C inv = C(1) / rho;
+    const C inv = recip(rho);
     ux = jx * inv;
     uy = jy * inv;
     uz = jz * inv;
@@ -740,18 +756,21 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const F
             if (cx == -1)
                 v = (rev || copy_i) ? v : v + C(L::w[i]) * dp;
         }
-        if constexpr (S::colref) {
-            if (cx == 1)
-                v = in_i ? C(2.0 * L::w[i]) * cin_s - v : v;
-            if (cx == -1)
-                v = abb_i ? C(2.0 * L::w[i]) * cout_s - v : v;
-        } else {
-            if (cx == 1)
-                v = in_i ? C(2.0 * L::w[i] * a.cin_s) - v : v;
-            if (cx == -1)
-                v = abb_i ? C(2.0 * L::w[i] * a.cout_s) - v : v;
-        }
         g[i] = v;
+    }
+    // Dirichlet links of the boundary columns (branches: waves without such
+    // a node skip them)
+    if (xin) {
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i)
+            if (L::cx[i] == 1)
+                g[i] = (S::colref ? C(2.0 * L::w[i]) * cin_s : C(2.0 * L::w[i] * a.cin_s)) - g[i];
+    }
+    if (xout && a.outlet) {
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i)
+            if (L::cx[i] == -1)
+                g[i] = (S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s)) - g[i];
     }
     C cs = C(0);
 #pragma unroll
