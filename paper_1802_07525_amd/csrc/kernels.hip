@@ -356,9 +356,12 @@ struct GlobalSrc {
     long long N, n;
     __device__ __forceinline__ C get(int i, int o, long long off, int mode) const
     {
-        // one load from a selected address: no branches between the loads
-        const long long idx = mode == 1 ? (long long)o * N + n
-                                        : (mode == 2 ? (long long)i * N + n : (long long)i * N + n - off);
+        // one load from a selected address: no branches between the loads.
+        // Element indices fit 32 bits (grids hold fewer than 2^31 / 19
+        // nodes); unsigned wrap-around keeps n - off exact.
+        const unsigned int NN = (unsigned int)N, nn = (unsigned int)n;
+        const unsigned int idx = mode == 1 ? (unsigned int)o * NN + nn
+                                           : (unsigned int)i * NN + nn - (mode == 2 ? 0u : (unsigned int)off);
         return ld<S>(h + idx);
     }
 };
@@ -466,8 +469,20 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
     uz = jz * inv;
     const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
     const C om = C(a.omega);
+    // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2), minus
+    // the shift w_i r0 when stored shifted (rs = rho - r0).  Opposite
+    // directions share the even part E = rs + rho (9/2 (c.u)^2 - 3/2 u^2)
+    // and flip the odd part O = 3 rho c.u: one pair at a time.
+    const C base = rs - rho * usq;
+    {
+        const C feq = C(L::w[0]) * base;
+        f[0] = f[0] + om * (feq - f[0]);
+    }
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
+    for (int i = 1; i < L::Q; ++i) {
+        const int o = L::op[i];
+        if (o < i)
+            continue;
         C cu = C(0);
         if (L::cx[i] == 1) cu += ux;
         if (L::cx[i] == -1) cu -= ux;
@@ -475,11 +490,11 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
         if (L::cy[i] == -1) cu -= uy;
         if (L::cz[i] == 1) cu += uz;
         if (L::cz[i] == -1) cu -= uz;
-        cu *= C(3);
-        // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2),
-        // minus the shift w_i r0 when stored shifted (rs = rho - r0).
-        const C feq = C(L::w[i]) * (rs + rho * (cu + C(0.5) * cu * cu - usq));
-        f[i] = f[i] + om * (feq - f[i]);
+        const C rcu = rho * cu;
+        const C even = C(L::w[i]) * (base + C(4.5) * rcu * cu);
+        const C odd = C(3.0 * L::w[i]) * rcu;
+        f[i] = f[i] + om * ((even + odd) - f[i]);
+        f[o] = f[o] + om * ((even - odd) - f[o]);
     }
 }
 
@@ -511,7 +526,7 @@ __device__ __forceinline__ void fluid_store(const FluidArgs &a, const NodePos &p
         unsigned int rng = sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, step) : 0u;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            st_pop<S, NT>(dst + (long long)i * N + p.n, f[i], rng);
+            st_pop<S, NT>(dst + ((unsigned int)i * (unsigned int)N + (unsigned int)p.n), f[i], rng);
     }
 }
 
@@ -805,7 +820,7 @@ __device__ __forceinline__ void ad_store(const AdArgs &a, const NodePos &p, type
             sizeof(typename S::T) == 2 ? sr_seed((unsigned int)p.n, step ^ 0x5bd1e995u) : 0u;
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            st_pop<S, NT>(dst + (long long)i * N + p.n, g[i], rng);
+            st_pop<S, NT>(dst + ((unsigned int)i * (unsigned int)N + (unsigned int)p.n), g[i], rng);
     }
 }
 
