@@ -13,6 +13,7 @@ fluid stream-collide step) and the FP64 CPU oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--workload c2] [--storage fp32s]
     python bench.py --workload served --storage fp16s [--requests 48] [--rate 50]
+    python bench.py --workload c5 [--updates 200] [--compare-storage fp16s]
 
 The served mode replays the seeded request stream (Poisson arrivals, 2-D
 domains log-uniform in size) into one server in real time and reports the
@@ -66,7 +67,7 @@ def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
     import oracle as O
     f = O.fluid_init(cls)
     nz = w["nz"]
-    n_f = int((cls == O.FLUID).sum())
+    n_f = int(O.flow_domain(cls).sum())
     n_a = int(np.isin(cls, [O.FLUID, O.BIOFILM]).sum())
     t0 = time.perf_counter()
     steps = 0
@@ -110,12 +111,111 @@ def profile_main(args, lbm, ctx, cls, w, storage):
     lbm.lbm_solver_destroy(s)
     gbs, copy_ms = lbm.lbm_copy_bandwidth(ctx, 1 << 30, 10)
     lbm.lbm_ctx_destroy(ctx)
-    nf = int((cls == 0).sum())
+    nf = int(lbm.lbm_flow_domain(cls).sum())
     na = int(((cls == 0) | (cls == 3)).sum())
     print(json.dumps({"profile": w["name"], "storage": args.storage, "steps": n,
                       "fluid_nodes": nf, "ad_nodes": na, "fluid_ms_per_step": f_ms / n,
                       "ad_ms_per_step": a_ms / n, "copy_bytes": 1 << 30, "copy_ms": copy_ms,
                       "copy_gbs": gbs}), flush=True)
+
+
+def coupled_main(args):
+    """Coupled biofilm loop on the 512 x 256 anode: cold fluid and substrate
+    solves, then `updates` growth steps, each followed by warm re-solves of
+    both solvers to the tolerance; the consumed flux J is accumulated in
+    FP64.  With --compare-storage the same biofilm history is re-solved in
+    that storage and the J series are compared."""
+    import numpy as np
+    import torch
+
+    import paper_1802_07525_amd as lbm
+    from paper_1802_07525_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    lbm.load()
+    w = inputs.WORKLOADS["c5"]
+    st, cls, _ = lbm.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
+                                    w["overlap"], w["seed"])
+    assert st == 0
+    cls = lbm.lbm_biofilm_layer(cls)
+    updates = args.updates or w["updates"]
+    xi = inputs.growth_draws(updates, seed=w["seed"])
+    ctx = lbm.lbm_ctx_create(0)
+
+    def run(storage):
+        p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                            storage=storage, stall_checks=args.stall_checks)
+        s = lbm.lbm_solver_create(ctx, cls, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stc, out = lbm.lbm_coupled_run(s, xi, w["tol"], args.max_iter or w["max_iter"])
+        el = time.perf_counter() - t0
+        lbm.lbm_solver_destroy(s)
+        # updates completed: the loop stops at the first failing solve
+        done = int(np.count_nonzero(out["iters_ad"])) - 1
+        return stc, out, el, done
+
+    storage = STORAGES[args.storage]
+    stc, out, el, done = run(storage)
+    # nodes updated per solve: the flow domain after each growth step (a
+    # step can close a pore), and the substrate nodes (growth keeps them)
+    flat = cls.reshape(-1).copy()
+    nfs = [int(lbm.lbm_flow_domain(cls).sum())]
+    for q in out["picked"][:done]:
+        flat[q] = 3
+        nfs.append(int(lbm.lbm_flow_domain(flat.reshape(cls.shape)).sum()))
+    nfs += [0] * (updates + 1 - len(nfs))
+    na = int(((cls == 0) | (cls == 3)).sum())
+    upd = float(np.sum(out["iters_fluid"] * np.asarray(nfs)) + np.sum(out["iters_ad"] * na))
+    res = {
+        "metric": METRIC, "value": upd / el / 1e6, "unit": "MLUPS", "n_gpus": 1, "steps": updates,
+        "warmup": 0, "ms_per_step": el / max(updates, 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.storage], "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [w["nx"], w["ny"], 1], "storage": args.storage,
+                   "updates": updates, "tol": w["tol"], "seed": w["seed"],
+                   "status": lbm.status_name(stc), "updates_done": done},
+        "coupled": {"seconds": el, "J_accum": out["J_accum"], "J0": float(out["J"][0]),
+                    "J_last": float(out["J"][-1]),
+                    "fluid_iters_cold": int(out["iters_fluid"][0]),
+                    "ad_iters_cold": int(out["iters_ad"][0]),
+                    "fluid_iters_warm_mean": float(np.mean(out["iters_fluid"][1:])) if updates else 0.0,
+                    "ad_iters_warm_mean": float(np.mean(out["iters_ad"][1:])) if updates else 0.0},
+    }
+    if args.compare_storage:
+        # the same biofilm history (the first run's picks) in the other
+        # storage: an independent loop would part at its first pick, a
+        # discontinuous function of C
+        p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                            storage=STORAGES[args.compare_storage], stall_checks=args.stall_checks)
+        s = lbm.lbm_solver_create(ctx, cls, p)
+        mi = args.max_iter or w["max_iter"]
+        J2, fail = [], None
+        t0 = time.perf_counter()
+        for m in range(done + 1):
+            if m > 0:
+                assert lbm.lbm_solver_update_cells(s, [out["picked"][m - 1]], [3]) == 0
+            sf, _ = lbm.lbm_solver_fluid(s, w["tol"], mi, int(m > 0))
+            sa, ai = lbm.lbm_solver_ad(s, w["tol"], mi, int(m > 0)) if sf >= 0 else (0, None)
+            if sf < 0 or sa < 0:
+                fail = {"update": m, "solver": "fluid" if sf < 0 else "substrate",
+                        "status": lbm.status_name(sf if sf < 0 else sa)}
+                break
+            J2.append(ai["sink_total"])
+        el2 = time.perf_counter() - t0
+        lbm.lbm_solver_destroy(s)
+        k = len(J2)
+        J1 = np.asarray(out["J"][:k])
+        J2 = np.asarray(J2)
+        rel = np.abs(J2 - J1) / np.abs(J1)
+        res["compare"] = {"storage": args.compare_storage, "seconds": el2, "updates": k - 1,
+                          "first_failure": fail,
+                          "J_accum": float(J2[1:].sum()),
+                          "J_accum_rel_diff": float(abs(J2[1:].sum() - J1[1:].sum()) / abs(J1[1:].sum()))
+                          if k > 1 else None,
+                          "J_rel_diff_max": float(rel.max()) if k else None,
+                          "J_rel_diff_median": float(np.median(rel)) if k else None}
+    lbm.lbm_ctx_destroy(ctx)
+    print(json.dumps(res), flush=True)
 
 
 def served_main(args):
@@ -268,6 +368,9 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,
                     help="stall window in checks (0: the library default)")
+    ap.add_argument("--updates", type=int, default=0, help="coupled loop: growth updates")
+    ap.add_argument("--compare-storage", default="", choices=[""] + sorted(STORAGES),
+                    help="coupled loop: repeat in this storage and compare")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling run: this many fluid and substrate steps of the workload "
                          "and a 1 GiB copy (counter calibration) instead of the solves")
@@ -281,6 +384,8 @@ def main():
         if args.storage == "fp64":
             sys.exit("the served form stores FP32 or FP16")
         return served_main(args)
+    if args.workload == "c5":
+        return coupled_main(args)
 
     import numpy as np
     import torch

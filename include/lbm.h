@@ -205,6 +205,16 @@ int64_t lbm_link_list(lbm_grid g, const uint8_t *cls, int which, int64_t *out, i
  * links (breadth-first search); 0 otherwise; negative on bad arguments. */
 int lbm_percolates(lbm_grid g, const uint8_t *cls);
 
+/* Flow domain (Sec. 2.1.1 boundary conditions on the Sec. 3 pore space):
+ * out[n] = 1 iff node n is FLUID and a chain of fluid-lattice links between
+ * FLUID nodes joins it to a FLUID node of the outlet column x = nx-1, else 0.
+ * The fluid solver updates exactly these nodes.  FLUID nodes outside it (a
+ * closed pore, or a pocket open to the inlet alone) carry no steady flow:
+ * they report u = 0 and rho = 0, and the substrate solver treats them as
+ * still fluid.  cls and out are host arrays of nx*ny*nz bytes; LBM_EINVAL on
+ * null pointers or an empty grid. */
+lbm_status lbm_flow_domain(lbm_grid g, const uint8_t *cls, uint8_t *out);
+
 /* Biofilm growth pick of the coupled loop: among FLUID nodes with
  * 1 <= x <= nx-2 and a BIOFILM lattice neighbour (ascending n), weight
  * max(C, 0), pick the first whose running weight exceeds xi * W (W the

@@ -51,6 +51,7 @@ def lib():
             "orc_biofilm_layer": (I, [I, I, I, P]),
             "orc_links": (I, [I, I, I, P, I, P]),
             "orc_percolates": (I, [I, I, I, P]),
+            "orc_flow_domain": (I, [I, I, I, P, P]),
             "orc_growth_pick": (I64, [I, I, I, P, P, D]),
             "orc_fluid_run": (I, [I, I, I, I, P, D, D, P, P, I64, P, P, P]),
             "orc_ad_run": (I, [I, I, I, I, P, D, D, D, I, D, P, P, I64, P, P]),
@@ -325,6 +326,17 @@ def percolates(cls):
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     return bool(lib().orc_percolates(nx, ny, nz, _p(cls)))
+
+
+def flow_domain(cls):
+    """FLUID nodes linked to the outlet column (bool mask, shape of cls): the
+    nodes the fluid solver updates; closed pores and inlet-only pockets carry
+    no steady flow (reading of Sec. 2.1.1 on the Sec. 3 pore space)."""
+    cls = _u8(cls)
+    nx, ny, nz = _shape(cls.shape)
+    out = np.zeros(cls.shape, np.uint8)
+    lib().orc_flow_domain(nx, ny, nz, _p(cls), _p(out))
+    return out.astype(bool)
 
 
 def growth_pick(cls, C, xi):

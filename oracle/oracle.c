@@ -19,6 +19,9 @@
  *   - advection-diffusion BGK step [Sec. 2.1.2, Eqs. 12-13] with the frozen
  *     fluid velocity, zero-flux solids, Dirichlet inlet, zero-gradient or
  *     Dirichlet outlet and a first-order sink on biofilm nodes;
+ *   - the flow domain: FLUID nodes linked to the outlet column (closed
+ *     pores carry no steady flow; reading of Sec. 2.1.1 on the Sec. 3 pore
+ *     space);
  *   - steady-state loops (run "until an equilibrium is reached", Sec. 3);
  *   - seeded geometry (random porous electrode, Sec. 3), biofilm layer,
  *     link masks, percolation and the simplified biofilm growth of the
@@ -194,6 +197,7 @@ static int ad_blocked(uint8_t k) /* substrate: zero flux only at electrode/chass
 {
     return k == ORC_SOLID || k == ORC_WALL;
 }
+static uint8_t *flow_domain(int nx, int ny, int nz, const uint8_t *cls);
 
 /* Equilibrium of Eq. 5 with c = dx/dt = 1 and W_i/rho0 = w_i (reading: the
  * printed c = dx/(dt*sqrt(3)) is the sound speed; with it the coefficients
@@ -241,16 +245,21 @@ int orc_fluid_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     if (make_lattice(lat_id, &L))
         return ORC_EINVAL;
     int64_t N = (int64_t)nx * ny * nz;
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!dom)
+        return ORC_EINVAL;
     for (int i = 0; i < L.q; i++)
         for (int64_t n = 0; n < N; n++)
-            f[i * N + n] = (cls[n] == ORC_FLUID) ? L.w[i] : 0.0;
+            f[i * N + n] = dom[n] ? L.w[i] : 0.0;
+    free(dom);
     return ORC_OK;
 }
 
 /* One time step of the fluid BGK LBM, pull form.
  *
  * f_src holds the stored post-collision populations f*(t) (layout [q][N]);
- * f_dst receives f*(t+1).  For every FLUID node n and direction i, with
+ * f_dst receives f*(t+1).  For every node n of the flow domain (FLUID
+ * nodes linked to the outlet column, see flow_domain) and direction i, with
  * s = n - c_i the node the population comes from:
  *   (a) s left of column 0 (inlet): f_i = f*_opp(n) + 6 w_i c_ix u_in --
  *       bounce-back from a wall moving at the plug inflow speed; each inlet
@@ -273,12 +282,14 @@ int orc_fluid_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  * the Poiseuille pin and is never used by the method.
  * Then rho = sum f_i (Eq. 9), j = sum c_i f_i (Eq. 10), u = (j + F/2)/rho,
  * and f*_i = f_i - (f_i - f_eq_i)/tau (Eq. 4) [+ Guo source].
- * If U is not NULL it receives u ([dim][N], 0 on blocked nodes); if RHO is
- * not NULL it receives rho (0 on blocked nodes). */
-int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                   double tau, double u_in, const int *periodic,
-                   const double *force, const double *f_src, double *f_dst,
-                   double *U, double *RHO)
+ * If U is not NULL it receives u ([dim][N], 0 off the domain); if RHO is
+ * not NULL it receives rho (0 off the domain).  Nodes off the domain store
+ * 0.  (A domain node's FLUID neighbours are in the domain, so rule (c) on
+ * the class is rule (c) on the domain.) */
+static int fluid_step_dom(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
+                          const uint8_t *dom, double tau, double u_in, const int *periodic,
+                          const double *force, const double *f_src, double *f_dst,
+                          double *U, double *RHO)
 {
     orc_lattice L;
     if (make_lattice(lat_id, &L))
@@ -297,7 +308,7 @@ int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         int y = row % ny, z = row / ny;
         for (int x = 0; x < nx; x++) {
             int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
-            if (cls[n] != ORC_FLUID) {
+            if (!dom[n]) {
                 for (int i = 0; i < L.q; i++)
                     f_dst[i * N + n] = 0.0;
                 if (U)
@@ -385,12 +396,26 @@ int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     return ORC_OK;
 }
 
+int orc_fluid_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
+                   double tau, double u_in, const int *periodic,
+                   const double *force, const double *f_src, double *f_dst,
+                   double *U, double *RHO)
+{
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!dom)
+        return ORC_EINVAL;
+    int st = fluid_step_dom(lat_id, nx, ny, nz, cls, dom, tau, u_in, periodic, force,
+                            f_src, f_dst, U, RHO);
+    free(dom);
+    return st;
+}
+
 /* Moments of a stored fluid state: rho = sum f*, u = (sum c f* + F/2)/rho.
  * BGK conserves rho and j, so these equal the pre-collision moments of the
- * step that produced the state.  Blocked nodes get 0. */
-int orc_fluid_moments(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                      const double *force, const double *f, double *U,
-                      double *RHO)
+ * step that produced the state.  Nodes off the flow domain get 0. */
+static int fluid_moments_dom(int lat_id, int nx, int ny, int nz, const uint8_t *dom,
+                             const double *force, const double *f, double *U,
+                             double *RHO)
 {
     orc_lattice L;
     if (make_lattice(lat_id, &L))
@@ -399,7 +424,7 @@ int orc_fluid_moments(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     const double g[3] = {force ? force[0] : 0.0, force ? force[1] : 0.0,
                          force ? force[2] : 0.0};
     for (int64_t n = 0; n < N; n++) {
-        if (cls[n] != ORC_FLUID) {
+        if (!dom[n]) {
             if (U)
                 for (int d = 0; d < L.dim; d++)
                     U[d * N + n] = 0.0;
@@ -422,6 +447,18 @@ int orc_fluid_moments(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     return ORC_OK;
 }
 
+int orc_fluid_moments(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
+                      const double *force, const double *f, double *U,
+                      double *RHO)
+{
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!dom)
+        return ORC_EINVAL;
+    int st = fluid_moments_dom(lat_id, nx, ny, nz, dom, force, f, U, RHO);
+    free(dom);
+    return st;
+}
+
 /* Mass crossing the inlet and outlet per step, evaluated on a stored state.
  * Inlet: sum over inlet links of (incoming - outgoing) populations.
  * Outlet: sum over outlet links of (outgoing - incoming).  Ascending n. */
@@ -434,8 +471,11 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         return ORC_EINVAL;
     const int64_t N = (int64_t)nx * ny * nz;
     double fin = 0.0, fout = 0.0;
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!dom)
+        return ORC_EINVAL;
     for (int64_t n = 0; n < N; n++) {
-        if (cls[n] != ORC_FLUID)
+        if (!dom[n])
             continue;
         int x = (int)(n % nx);
         double us[3] = {0.0, 0.0, 0.0};
@@ -463,6 +503,7 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             }
         }
     }
+    free(dom);
     *flux_in = fin;
     *flux_out = fout;
     return ORC_OK;
@@ -525,10 +566,12 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     double *fb = malloc(sizeof(double) * L.q * N);
     double *Ucur = malloc(sizeof(double) * L.dim * N);
     double *Uprev = malloc(sizeof(double) * L.dim * N);
-    if (!fb || !Ucur || !Uprev) {
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!fb || !Ucur || !Uprev || !dom) {
         free(fb);
         free(Ucur);
         free(Uprev);
+        free(dom);
         return ORC_EINVAL;
     }
     double *a = f, *b = fb;
@@ -536,10 +579,10 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
-    orc_fluid_moments(lat_id, nx, ny, nz, cls, NULL, f, Uprev, NULL);
+    fluid_moments_dom(lat_id, nx, ny, nz, dom, NULL, f, Uprev, NULL);
     for (;;) {
         int need_u = (t + 1) % K == 0;
-        orc_fluid_step(lat_id, nx, ny, nz, cls, tau, u_in, NULL, NULL, a, b,
+        fluid_step_dom(lat_id, nx, ny, nz, cls, dom, tau, u_in, NULL, NULL, a, b,
                        need_u ? Ucur : NULL, NULL);
         double *tmp = a;
         a = b;
@@ -549,7 +592,7 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             double rmax = 0.0, umax = 0.0;
             int bad = 0;
             for (int64_t n = 0; n < N; n++) {
-                if (cls[n] != ORC_FLUID)
+                if (!dom[n])
                     continue;
                 for (int d = 0; d < L.dim; d++) {
                     double v = Ucur[d * N + n];
@@ -577,12 +620,13 @@ int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     }
     if (a != f)
         memcpy(f, a, sizeof(double) * L.q * N);
-    orc_fluid_moments(lat_id, nx, ny, nz, cls, NULL, f, U, NULL);
+    fluid_moments_dom(lat_id, nx, ny, nz, dom, NULL, f, U, NULL);
     *iters = t;
     *residual = r;
     free(fb);
     free(Ucur);
     free(Uprev);
+    free(dom);
     return status;
 }
 
@@ -1133,6 +1177,61 @@ int orc_percolates(int nx, int ny, int nz, const uint8_t *cls)
     return found;
 }
 
+/* Flow domain (reading: the boundary conditions of Sec. 2.1.1 set the flow
+ * in the part of the Sec. 3 pore space that reaches the outlet).  dom[n] = 1
+ * iff n is FLUID and a chain of fluid-lattice links between FLUID nodes
+ * joins it to a FLUID node of column nx-1; breadth-first from that column.
+ * A closed pore has no steady flow and no boundary fixes its pressure; a
+ * pocket open only to the inlet would take in u_in per inlet link forever.
+ * Such nodes hold no fluid populations (u = 0, rho reported 0); the
+ * substrate solver still treats them as fluid.  Returns a malloc'd mask of
+ * N bytes (NULL when out of memory). */
+static uint8_t *flow_domain(int nx, int ny, int nz, const uint8_t *cls)
+{
+    orc_lattice Lb;
+    const orc_lattice *L = nbr_lattice(nz, &Lb);
+    const int64_t N = (int64_t)nx * ny * nz;
+    uint8_t *dom = calloc(N, 1);
+    int64_t *queue = malloc(sizeof(int64_t) * N);
+    if (!dom || !queue) {
+        free(dom);
+        free(queue);
+        return NULL;
+    }
+    int64_t head = 0, tail = 0;
+    for (int64_t n = 0; n < N; n++)
+        if (n % nx == nx - 1 && cls[n] == ORC_FLUID) {
+            dom[n] = 1;
+            queue[tail++] = n;
+        }
+    while (head < tail) {
+        int64_t n = queue[head++];
+        int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+        for (int i = 1; i < L->q; i++) {
+            int sx = x + L->c[i][0], sy = y + L->c[i][1], sz = z + L->c[i][2];
+            if (sx < 0 || sx >= nx || sy < 0 || sy >= ny || sz < 0 || sz >= nz)
+                continue;
+            int64_t m = sx + (int64_t)nx * (sy + (int64_t)ny * sz);
+            if (!dom[m] && cls[m] == ORC_FLUID) {
+                dom[m] = 1;
+                queue[tail++] = m;
+            }
+        }
+    }
+    free(queue);
+    return dom;
+}
+
+int orc_flow_domain(int nx, int ny, int nz, const uint8_t *cls, uint8_t *out)
+{
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!dom)
+        return ORC_EINVAL;
+    memcpy(out, dom, (size_t)nx * ny * nz);
+    free(dom);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Simplified biofilm growth (the coupled loop's stand-in for Sec. 2.3).    */
 
@@ -1290,12 +1389,16 @@ int orc_fluid_run(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         return ORC_EINVAL;
     const int64_t N = (int64_t)nx * ny * nz;
     double *b = malloc(sizeof(double) * L.q * N);
-    if (!b)
+    uint8_t *dom = flow_domain(nx, ny, nz, cls);
+    if (!b || !dom) {
+        free(b);
+        free(dom);
         return ORC_EINVAL;
+    }
     double *a = f;
     for (int64_t t = 0; t < nsteps; t++) {
         int last = (t == nsteps - 1);
-        orc_fluid_step(lat_id, nx, ny, nz, cls, tau, u_in, periodic, force, a, b,
+        fluid_step_dom(lat_id, nx, ny, nz, cls, dom, tau, u_in, periodic, force, a, b,
                        last ? U : NULL, last ? RHO : NULL);
         double *tmp = a;
         a = b;
@@ -1306,6 +1409,7 @@ int orc_fluid_run(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         b = a;
     }
     free(b);
+    free(dom);
     return ORC_OK;
 }
 

@@ -115,6 +115,7 @@ _SIGS = {
     "lbm_links": (I32, [G, P, I32, P]),
     "lbm_link_list": (I64, [G, P, I32, P, I64]),
     "lbm_percolates": (I32, [G, P]),
+    "lbm_flow_domain": (I32, [G, P, P]),
     "lbm_growth_pick": (I64, [G, P, P, D]),
     "lbm_splitmix64": (None, [U64, I64, P]),
     "lbm_fluid_steady": (I32, [P, G, P, D, D, D, I64, I32, P, P]),
@@ -251,6 +252,17 @@ def lbm_percolates(cls):
     if r < 0:
         raise LBMError(r)
     return bool(r)
+
+
+def lbm_flow_domain(cls):
+    """Nodes the fluid solver updates: FLUID nodes linked to the outlet
+    column.  Returns a bool array of the shape of cls."""
+    cls = _u8(cls)
+    out = np.zeros(cls.shape, np.uint8)
+    st = load().lbm_flow_domain(_grid(cls), _p(cls), _p(out))
+    if st:
+        raise LBMError(st)
+    return out.astype(bool)
 
 
 def lbm_growth_pick(cls, C, xi):

@@ -301,10 +301,51 @@ void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, 
     links_impl<false>(g, cls, out, lo, hi);
 }
 
-// The FLUID node of each column x that samples the column's shift reference:
-// the one nearest the middle of the cross-section (|y - ny/2| + |z - nz/2|),
-// the lowest index among equals; -1 for a column without FLUID nodes.
-static std::vector<int64_t> reference_nodes(const lbm_grid &g, const uint8_t *cls)
+// Flow domain: the FLUID nodes joined to a FLUID node of the outlet column
+// x = nx-1 by a chain of fluid-lattice links between FLUID nodes.  A closed
+// pore (no such chain) holds no steady flow and its pressure is set by no
+// boundary condition; a pocket reached from the inlet alone would gain the
+// inflow forever.  Both stay out of the flow solve (Sec. 2.1.1 boundary
+// conditions on the Sec. 3 pore space); the substrate solve keeps them.
+std::vector<uint8_t> flow_domain(const lbm_grid &g, const uint8_t *cls)
+{
+    const Dirs &D = fluid_dirs(g.nz);
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    std::vector<uint8_t> in((size_t)N, 0);
+    std::vector<int64_t> todo;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y) {
+            const int64_t n = idx3(g, g.nx - 1, y, z);
+            if (cls[n] == LBM_FLUID) {
+                in[n] = 1;
+                todo.push_back(n);
+            }
+        }
+    while (!todo.empty()) {
+        const int64_t n = todo.back();
+        todo.pop_back();
+        const int x = (int)(n % g.nx);
+        const int y = (int)((n / g.nx) % g.ny);
+        const int z = (int)(n / ((int64_t)g.nx * g.ny));
+        for (int i = 1; i < D.q; ++i) {
+            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
+            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+                continue;
+            const int64_t m = idx3(g, sx, sy, sz);
+            if (!in[m] && cls[m] == LBM_FLUID) {
+                in[m] = 1;
+                todo.push_back(m);
+            }
+        }
+    }
+    return in;
+}
+
+// The flow-domain node of each column x that samples the column's shift
+// reference: the one nearest the middle of the cross-section
+// (|y - ny/2| + |z - nz/2|), the lowest index among equals; -1 for a column
+// without flow-domain nodes.
+static std::vector<int64_t> reference_nodes(const lbm_grid &g, const std::vector<uint8_t> &dom)
 {
     std::vector<int64_t> r((size_t)g.nx, -1);
     std::vector<int> best((size_t)g.nx, INT32_MAX);
@@ -314,7 +355,7 @@ static std::vector<int64_t> reference_nodes(const lbm_grid &g, const uint8_t *cl
             const int dist = abs(y - cy) + abs(z - cz);
             for (int x = 0; x < g.nx; ++x) {
                 const int64_t n = idx3(g, x, y, z);
-                if (cls[n] == LBM_FLUID && dist < best[x]) {
+                if (dom[(size_t)n] && dist < best[x]) {
                     best[x] = dist;
                     r[x] = n;
                 }
@@ -329,11 +370,12 @@ void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t l
     std::vector<uint32_t> lf((size_t)(hi - lo)), la((size_t)(hi - lo));
     links_fluid(g, cls, lf.data(), lo, hi);
     links_ad(g, cls, la.data(), lo, hi);
-    const std::vector<int64_t> ref = reference_nodes(g, cls);
+    const std::vector<uint8_t> dom = flow_domain(g, cls);
+    const std::vector<int64_t> ref = reference_nodes(g, dom);
     for (int64_t n = lo; n < hi; ++n) {
         const uint8_t k = cls[n];
         uint32_t d = 0;
-        if (k == LBM_FLUID)
+        if (dom[(size_t)n])
             d |= 1u | (lf[n - lo] & ((1u << qf) - 2u));
         if (k == LBM_FLUID || k == LBM_BIOFILM) {
             for (int i = 1; i < qa; ++i)
@@ -504,6 +546,15 @@ int lbm_percolates(lbm_grid g, const uint8_t *cls)
     if (!cls || g.nx < 1 || g.ny < 1 || g.nz < 1)
         return LBM_EINVAL;
     return percolates(g, cls) ? 1 : 0;
+}
+
+lbm_status lbm_flow_domain(lbm_grid g, const uint8_t *cls, uint8_t *out)
+{
+    if (!cls || !out || g.nx < 1 || g.ny < 1 || g.nz < 1)
+        return LBM_EINVAL;
+    const std::vector<uint8_t> d = flow_domain(g, cls);
+    memcpy(out, d.data(), d.size());
+    return LBM_OK;
 }
 
 int64_t lbm_growth_pick(lbm_grid g, const uint8_t *cls, const double *C, double xi)

@@ -35,6 +35,8 @@ bool ad_blocked(uint8_t k);
 // columns free of SOLID/BIOFILM.  Returns empty string if fine.
 std::string check_mask(const lbm_grid &g, const uint8_t *cls);
 bool percolates(const lbm_grid &g, const uint8_t *cls);
+// 1 for FLUID nodes linked to the outlet column, else 0 (one byte per node)
+std::vector<uint8_t> flow_domain(const lbm_grid &g, const uint8_t *cls);
 void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
 void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
 // descriptor words (lbm_kernels.h layout) for nodes [lo, hi)

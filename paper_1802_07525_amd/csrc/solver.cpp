@@ -281,6 +281,8 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
            "ctrl reset");
     int &cur = which == LBM_SOLVER_FLUID ? s->fcur : s->gcur;
     const int cur0 = cur;
+    unsigned long long &steps = which == LBM_SOLVER_FLUID ? s->fsteps : s->gsteps;
+    const unsigned long long steps0 = steps;
     // moments of the starting state: the reference of the first check
     if (which == LBM_SOLVER_FLUID)
         HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[cur0], s->d_desc, s->geo, ref_cur(s, 0),
@@ -340,6 +342,10 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     const auto t1 = std::chrono::steady_clock::now();
     const int64_t t_final = fin.stop != lbmk::STOP_RUN ? fin.t_stop : launched;
     cur = (int)((cur0 + launches_for(s, t_final)) & 1);
+    // launches queued behind the stop returned at once: the step counter
+    // (the stochastic-rounding seed) counts the steps actually taken, so
+    // that later solves do not depend on how many were in flight
+    steps = steps0 + (unsigned long long)t_final;
     lbm_status result = LBM_NOT_CONVERGED;
     if (fin.stop == lbmk::STOP_OK)
         result = LBM_OK;
@@ -776,17 +782,22 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
     if (!percolates(s->grid, trial.data()))
         return set_err(s->ctx, LBM_EINVAL, "update would disconnect inlet from outlet");
     HIPCHK(hipSetDevice(s->ctx->device), "set device");
-    // populations of nodes whose activity changes: four lists
+    // populations of nodes whose activity changes: four lists.  Fluid
+    // activity is membership of the flow domain, which an update can change
+    // far from the updated cells (closing or opening a pore).
     std::vector<long long> f_off, f_on, g_off, g_on;
+    const std::vector<uint8_t> dom0 = flow_domain(s->grid, s->cls.data());
+    const std::vector<uint8_t> dom1 = flow_domain(s->grid, trial.data());
+    for (int64_t j = 0; j < N; ++j) {
+        if (dom0[(size_t)j] && !dom1[(size_t)j])
+            f_off.push_back(j);
+        if (!dom0[(size_t)j] && dom1[(size_t)j])
+            f_on.push_back(j);
+    }
     for (int64_t k = 0; k < n; ++k) {
         const int64_t j = idx[k];
         const uint8_t a = s->cls[(size_t)j], b = trial[(size_t)j];
-        const bool fa = a == LBM_FLUID, fb = b == LBM_FLUID;
         const bool ga = a == LBM_FLUID || a == LBM_BIOFILM, gb = b == LBM_FLUID || b == LBM_BIOFILM;
-        if (fa && !fb)
-            f_off.push_back(j);
-        if (!fa && fb)
-            f_on.push_back(j);
         if (ga && !gb)
             g_off.push_back(j);
         if (!ga && gb)

@@ -269,3 +269,57 @@ def test_update_cells_matches_oracle(gpu_lib):
         assert s.steps(0, 50)[0] == 0
         f_or, _, _ = O.fluid_run(cls2, f_or, w["tau"], w["u_in"], 50)
         assert max_abs(s.get(lbm.LBM_FIELD_F), f_or) < 1e-12
+
+
+def _sealing_pick(cls):
+    """First FLUID node (ascending index, 1 <= x <= nx-2) whose growth keeps
+    the medium percolating and cuts more than itself out of the flow
+    domain, with the nodes it cuts off."""
+    ny, nx = cls.shape
+    dom = O.flow_domain(cls).ravel()
+    flat = cls.ravel()
+    for p in np.flatnonzero(dom):
+        if not 1 <= p % nx <= nx - 2:
+            continue
+        c2 = flat.copy()
+        c2[p] = O.BIOFILM
+        c2 = c2.reshape(cls.shape)
+        d2 = O.flow_domain(c2).ravel()
+        if dom.sum() - d2.sum() > 1 and O.percolates(c2):
+            return int(p), c2, dom & ~d2
+    raise AssertionError("no sealing pick in this medium")
+
+
+@pytest.mark.parametrize("storage", [FP64, FP16S], ids=["fp64", "fp16s"])
+def test_update_sealing_a_pore(gpu_lib, storage):
+    """A growth step that closes a pore takes the pore out of the flow
+    solve: its populations are dropped and it reports u = 0, rho = 0.  In
+    FP64 the warm re-solve matches the oracle's (which drops the pore on its
+    first step) in status, iterations and velocity."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    p, cls2, cut = _sealing_pick(cls)
+    print("sealing pick", p, "cuts", int(cut.sum()) - 1, "nodes", flush=True)
+    tol, mi = 1e-7, 200000
+    # FP16 storage stalls above this tolerance (its round-off floor)
+    ok = (0,) if storage == FP64 else (0, 2)
+    with _solver(lbm, cls, w, storage) as s:
+        st, _ = s.fluid(tol, mi)
+        assert st in ok, lbm.status_name(st)
+        assert lbm.lbm_solver_update_cells(s.h, [p], [O.BIOFILM]) == 0
+        st, info = s.fluid(tol, mi, warm=1)
+        assert st in ok, lbm.status_name(st)
+        U = s.get(lbm.LBM_FIELD_U).reshape(2, -1)
+        rho = s.get(lbm.LBM_FIELD_RHO)
+    dom2 = O.flow_domain(cls2).ravel()
+    assert np.array_equal(lbm.lbm_flow_domain(cls2).ravel(), dom2)
+    assert np.all(U[:, ~dom2] == 0.0) and np.all(rho[~dom2] == 0.0)
+    assert np.all(rho[dom2] > 0.5)
+    if storage == FP64:
+        r1 = O.fluid_solve(cls, w["tau"], w["u_in"], tol, mi)
+        f = r1["f"].copy()
+        f[:, p] = 0.0
+        r2 = O.fluid_solve(cls2, w["tau"], w["u_in"], tol, mi, f=f)
+        assert r2["status"] == "OK" and info["iters"] == r2["iters"]
+        assert np.abs(U - r2["U"]).max() < 1e-9 * np.abs(r2["U"]).max()

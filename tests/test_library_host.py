@@ -95,6 +95,15 @@ def test_percolation_and_growth_pick_match_oracle():
             assert L.lbm_growth_pick(a, C, xi) == O.growth_pick(a, C, xi)
 
 
+def test_flow_domain_matches_oracle():
+    for seed in range(1, 10):
+        _, a, _ = L.lbm_geom_discs(96, 48, 2, 5, 0.35, 0, seed)
+        a = L.lbm_biofilm_layer(a)
+        assert np.array_equal(L.lbm_flow_domain(a), O.flow_domain(a))
+    st, a, _ = L.lbm_geom_fibres(24, 12, 12, 1, 2, 0.35, 3)
+    assert np.array_equal(L.lbm_flow_domain(a), O.flow_domain(a))
+
+
 def test_splitmix64_matches_oracle():
     for seed in (0, 1, 1234567, 2 ** 63 + 11):
         assert np.array_equal(L.lbm_splitmix64(seed, 64), O.splitmix64(seed, 64))

@@ -1,7 +1,8 @@
 """Pins of the oracle's integer side: the SplitMix64 stream against its
 published vectors, the seeded electrode generators against a naive pure-
 Python generator written from the same specification, and the biofilm
-layer, link masks, percolation and growth pick against brute force.
+layer, link masks, percolation, the flow domain and growth pick against
+brute force or an independent library (scipy's connected-component labels).
 """
 import math
 import os
@@ -209,6 +210,62 @@ def test_percolation_random_vs_bfs():
         cls[0] = O.WALL
         cls[-1] = O.WALL
         assert O.percolates(cls) == _bfs(cls)
+
+
+def _domain_scipy(cls):
+    """Flow domain from scipy's connected components: FLUID nodes in a
+    component (8-connected in 2-D, 18-connected in 3-D -- the fluid
+    lattice's neighbours) that holds a FLUID node of the last column."""
+    from scipy import ndimage
+    fl = cls == O.FLUID
+    st = ndimage.generate_binary_structure(cls.ndim, cls.ndim if cls.ndim == 2 else 2)
+    lab, _ = ndimage.label(fl, structure=st)
+    keep = np.unique(lab[..., -1][fl[..., -1]])
+    return np.isin(lab, keep) & fl
+
+
+def test_flow_domain_handmade():
+    cls = np.zeros((8, 12), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    # a closed pore: a solid ring around two fluid nodes
+    cls[2:6, 3:7] = O.SOLID
+    cls[3:5, 4:6] = O.FLUID
+    # an inlet-only pocket: a biofilm fence from the inlet column
+    cls[1:4, 0] = O.FLUID
+    cls[4, 0:3] = O.BIOFILM
+    cls[1:4, 2] = O.BIOFILM
+    # a dead end open to the main channel (stays in the domain)
+    cls[6, 9] = O.FLUID
+    cls[5, 8:11] = O.SOLID
+    cls[5, 9] = O.FLUID
+    dom = O.flow_domain(cls)
+    assert not dom[3:5, 4:6].any()
+    assert not dom[1:4, 0:2].any()
+    assert dom[5, 9] and dom[6, 9]
+    assert dom[6, 0] and dom[3, 11]
+    assert np.array_equal(dom, _domain_scipy(cls))
+    # a diagonal gap is a lattice link: the ring with one corner swapped
+    # for a diagonal opening joins the pore to the channel
+    cls2 = cls.copy()
+    cls2[2, 3] = O.FLUID
+    cls2[1, 2] = O.FLUID
+    assert O.flow_domain(cls2)[3, 4]
+    assert np.array_equal(O.flow_domain(cls2), _domain_scipy(cls2))
+
+
+@pytest.mark.parametrize("nz", [1, 5])
+def test_flow_domain_random_vs_scipy(nz):
+    rng = np.random.default_rng(10 + nz)
+    for _ in range(30):
+        shape = (nz, 9, 14) if nz > 1 else (11, 16)
+        cls = (rng.random(shape) < 0.45).astype(np.uint8) * rng.integers(1, 4, size=shape).astype(np.uint8)
+        got = O.flow_domain(cls)
+        assert np.array_equal(got, _domain_scipy(cls))
+    for seed in range(1, 6):
+        st, cls, _ = O.geom_discs(96, 48, 2, 5, 0.3, 0, seed)
+        cls = O.biofilm_layer(cls)
+        assert np.array_equal(O.flow_domain(cls), _domain_scipy(cls))
 
 
 def _naive_pick(cls, C, xi):
