@@ -100,7 +100,14 @@ typedef enum {
     LBM_FIELD_LINKS_C = 5, /* substrate link mask, uint8 [N] */
     LBM_FIELD_F = 6,       /* fluid populations f*, host double [Q][N], unshifted */
     LBM_FIELD_G = 7,       /* substrate populations g*, host double [Q][N], unshifted */
-    LBM_FIELD_U_DEVICE = 8 /* device velocity buffer the AD solve reads (see device_ptr) */
+    LBM_FIELD_U_DEVICE = 8, /* device velocity buffer the AD solve reads (see device_ptr) */
+    LBM_FIELD_DESC = 9     /* node descriptor words as the kernels read them, copied back
+                            * from the device, uint32 [N] (diagnostic).  With qf, qa the
+                            * fluid and substrate direction counts: bit 0 flow-domain
+                            * node; bits 1..qf-1 blocked fluid pull sources; bits
+                            * qf..qf+qa-2 blocked substrate pull sources (i = 1..qa-1);
+                            * bit qf+qa-1 substrate-active (FLUID or BIOFILM); bit qf+qa
+                            * BIOFILM; bit qf+qa+1 the column's reference node */
 } lbm_field;
 
 typedef struct {

@@ -24,7 +24,7 @@ LBM_FLUID, LBM_SOLID, LBM_WALL, LBM_BIOFILM = 0, 1, 2, 3
 LBM_OUT_ZERO_GRADIENT, LBM_OUT_DIRICHLET = 0, 1
 LBM_SOLVER_FLUID, LBM_SOLVER_AD = 0, 1
 (LBM_FIELD_U, LBM_FIELD_RHO, LBM_FIELD_C, LBM_FIELD_CLASS, LBM_FIELD_LINKS_F, LBM_FIELD_LINKS_C,
- LBM_FIELD_F, LBM_FIELD_G, LBM_FIELD_U_DEVICE) = range(9)
+ LBM_FIELD_F, LBM_FIELD_G, LBM_FIELD_U_DEVICE, LBM_FIELD_DESC) = range(10)
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "STALLED", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EDEVICE", -4: "EDIVERGED", -5: "EBUSY", -6: "ENOTFOUND"}
@@ -377,7 +377,7 @@ def lbm_solver_set_u(s, u):
 _FIELD_SHAPES = {LBM_FIELD_U: ("dim", np.float64), LBM_FIELD_RHO: (1, np.float64),
                  LBM_FIELD_C: (1, np.float64), LBM_FIELD_CLASS: (1, np.uint8),
                  LBM_FIELD_LINKS_C: (1, np.uint8), LBM_FIELD_F: ("qf", np.float64),
-                 LBM_FIELD_G: ("qa", np.float64)}
+                 LBM_FIELD_G: ("qa", np.float64), LBM_FIELD_DESC: (1, np.uint32)}
 
 
 def lbm_solver_get(s, field, grid):

@@ -8,7 +8,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <deque>
 #include <string>
 #include <vector>
 
@@ -85,23 +84,30 @@ static void fill_chassis(const lbm_grid &g, uint8_t *cls)
         }
 }
 
+std::string check_cell(const lbm_grid &g, int x, int y, int z, uint8_t k)
+{
+    const bool chassis = y == 0 || y == g.ny - 1 || (g.nz > 1 && (z == 0 || z == g.nz - 1));
+    if (k > LBM_BIOFILM)
+        return "unknown node class " + std::to_string(k);
+    if (chassis && !(k == LBM_WALL || k == LBM_SOLID))
+        return "chassis rows/planes must be WALL or SOLID";
+    if ((x == 0 || x == g.nx - 1) && (k == LBM_SOLID || k == LBM_BIOFILM))
+        return "inlet/outlet columns must hold no SOLID or BIOFILM";
+    return "";
+}
+
 std::string check_mask(const lbm_grid &g, const uint8_t *cls)
 {
     if (g.nx < 2 || g.ny < 3 || g.nz < 1 || g.nz == 2)
         return "grid must have nx >= 2, ny >= 3 and nz == 1 or nz >= 3";
+    int64_t n = 0;
     for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y) {
-            const bool chassis = y == 0 || y == g.ny - 1 || (g.nz > 1 && (z == 0 || z == g.nz - 1));
-            for (int x = 0; x < g.nx; ++x) {
-                const uint8_t k = cls[idx3(g, x, y, z)];
-                if (k > LBM_BIOFILM)
-                    return "unknown node class " + std::to_string(k);
-                if (chassis && !(k == LBM_WALL || k == LBM_SOLID))
-                    return "chassis rows/planes must be WALL or SOLID";
-                if ((x == 0 || x == g.nx - 1) && (k == LBM_SOLID || k == LBM_BIOFILM))
-                    return "inlet/outlet columns must hold no SOLID or BIOFILM";
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x, ++n) {
+                std::string m = check_cell(g, x, y, z, cls[n]);
+                if (!m.empty())
+                    return m;
             }
-        }
     return "";
 }
 
@@ -271,34 +277,43 @@ lbm_status lbm_biofilm_layer(lbm_grid g, uint8_t *cls)
 
 namespace lbmh {
 
+// Link bits of node (x, y, z): bit i set iff the pull source (x, y, z) - c_i
+// is inside the grid and blocked for that solver.
 template <bool FLUID>
-static void links_impl(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+static inline uint32_t link_bits(const lbm_grid &g, const uint8_t *cls, int x, int y, int z)
 {
     const Dirs &D = FLUID ? fluid_dirs(g.nz) : ad_dirs(g.nz);
-    for (int64_t n = lo; n < hi; ++n) {
-        const int x = (int)(n % g.nx);
-        const int y = (int)((n / g.nx) % g.ny);
-        const int z = (int)(n / ((int64_t)g.nx * g.ny));
-        uint32_t bits = 0;
-        for (int i = 1; i < D.q; ++i) {
-            const int sx = x - D.c[i][0], sy = y - D.c[i][1], sz = z - D.c[i][2];
-            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
-                continue;
-            const uint8_t k = cls[idx3(g, sx, sy, sz)];
-            if (FLUID ? fluid_blocked(k) : ad_blocked(k))
-                bits |= 1u << i;
-        }
-        out[n - lo] = bits;
+    const int64_t n = idx3(g, x, y, z);
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    uint32_t bits = 0;
+    for (int i = 1; i < D.q; ++i) {
+        const int ax = x - D.c[i][0], ay = y - D.c[i][1], az = z - D.c[i][2];
+        if (ax < 0 || ay < 0 || az < 0 || ax >= g.nx || ay >= g.ny || az >= g.nz)
+            continue;
+        const uint8_t k = cls[n - D.c[i][0] - D.c[i][1] * sy - D.c[i][2] * sz];
+        if (FLUID ? fluid_blocked(k) : ad_blocked(k))
+            bits |= 1u << i;
     }
+    return bits;
 }
 
-void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+template <bool FLUID>
+static void links_impl(const lbm_grid &g, const uint8_t *cls, uint32_t *out)
 {
-    links_impl<true>(g, cls, out, lo, hi);
+    int64_t n = 0;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x, ++n)
+                out[n] = link_bits<FLUID>(g, cls, x, y, z);
 }
-void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi)
+
+void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out)
 {
-    links_impl<false>(g, cls, out, lo, hi);
+    links_impl<true>(g, cls, out);
+}
+void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out)
+{
+    links_impl<false>(g, cls, out);
 }
 
 // Flow domain: the FLUID nodes joined to a FLUID node of the outlet column
@@ -307,149 +322,194 @@ void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, 
 // boundary condition; a pocket reached from the inlet alone would gain the
 // inflow forever.  Both stay out of the flow solve (Sec. 2.1.1 boundary
 // conditions on the Sec. 3 pore space); the substrate solve keeps them.
+//
+// The search runs over maximal FLUID runs along x in each row (y, z)
+// rather than over nodes.  Runs [a, b] and [c, d] of two rows are linked
+// iff some of their nodes are lattice neighbours: c <= b + w and
+// a <= d + w, where w = 1 for rows one apart in y or in z (the lattice
+// has (+-1, +-1, 0) and (+-1, 0, +-1)) and w = 0 for rows one apart in both
+// (D3Q19's (0, +-1, +-1) edges, no corners).
 std::vector<uint8_t> flow_domain(const lbm_grid &g, const uint8_t *cls)
 {
-    const Dirs &D = fluid_dirs(g.nz);
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    std::vector<uint8_t> in((size_t)N, 0);
-    std::vector<int64_t> todo;
-    for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y) {
-            const int64_t n = idx3(g, g.nx - 1, y, z);
-            if (cls[n] == LBM_FLUID) {
-                in[n] = 1;
-                todo.push_back(n);
-            }
-        }
-    while (!todo.empty()) {
-        const int64_t n = todo.back();
-        todo.pop_back();
-        const int x = (int)(n % g.nx);
-        const int y = (int)((n / g.nx) % g.ny);
-        const int z = (int)(n / ((int64_t)g.nx * g.ny));
-        for (int i = 1; i < D.q; ++i) {
-            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
-            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    struct Run {
+        int a, b;
+    };
+    std::vector<Run> runs;
+    std::vector<int64_t> first((size_t)rows + 1);
+    for (int64_t r = 0; r < rows; ++r) {
+        first[(size_t)r] = (int64_t)runs.size();
+        const uint8_t *c = cls + r * g.nx;
+        for (int x = 0; x < g.nx;) {
+            if (c[x] != LBM_FLUID) {
+                ++x;
                 continue;
-            const int64_t m = idx3(g, sx, sy, sz);
-            if (!in[m] && cls[m] == LBM_FLUID) {
-                in[m] = 1;
-                todo.push_back(m);
             }
+            const int a = x;
+            while (x < g.nx && c[x] == LBM_FLUID)
+                ++x;
+            runs.push_back({a, x - 1});
         }
     }
+    first[(size_t)rows] = (int64_t)runs.size();
+    const int64_t R = (int64_t)runs.size();
+    std::vector<int64_t> row_of((size_t)R);
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t k = first[(size_t)r]; k < first[(size_t)r + 1]; ++k)
+            row_of[(size_t)k] = r;
+    std::vector<uint8_t> seen((size_t)R, 0);
+    std::vector<int64_t> todo;
+    for (int64_t r = 0; r < rows; ++r)
+        if (first[(size_t)r + 1] > first[(size_t)r] && runs[(size_t)first[(size_t)r + 1] - 1].b == g.nx - 1) {
+            seen[(size_t)first[(size_t)r + 1] - 1] = 1;
+            todo.push_back(first[(size_t)r + 1] - 1);
+        }
+    // neighbouring rows (dy, dz) and their widening
+    struct Nb {
+        int dy, dz, w;
+    };
+    static const Nb nb2[2] = {{1, 0, 1}, {-1, 0, 1}};
+    static const Nb nb3[8] = {{1, 0, 1},  {-1, 0, 1},  {0, 1, 1},  {0, -1, 1},
+                              {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+    const Nb *nb = g.nz > 1 ? nb3 : nb2;
+    const int nnb = g.nz > 1 ? 8 : 2;
+    while (!todo.empty()) {
+        const int64_t k = todo.back();
+        todo.pop_back();
+        const Run q = runs[(size_t)k];
+        const int64_t r = row_of[(size_t)k];
+        const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+        for (int t = 0; t < nnb; ++t) {
+            const int ay = y + nb[t].dy, az = z + nb[t].dz;
+            if (ay < 0 || az < 0 || ay >= g.ny || az >= g.nz)
+                continue;
+            const int64_t r2 = ay + (int64_t)g.ny * az;
+            const int lo = q.a - nb[t].w, hi = q.b + nb[t].w;
+            // first run of row r2 ending at or after lo
+            int64_t i0 = first[(size_t)r2], i1 = first[(size_t)r2 + 1];
+            while (i0 < i1) {
+                const int64_t mid = (i0 + i1) / 2;
+                if (runs[(size_t)mid].b < lo)
+                    i0 = mid + 1;
+                else
+                    i1 = mid;
+            }
+            for (int64_t m = i0; m < first[(size_t)r2 + 1] && runs[(size_t)m].a <= hi; ++m)
+                if (!seen[(size_t)m]) {
+                    seen[(size_t)m] = 1;
+                    todo.push_back(m);
+                }
+        }
+    }
+    std::vector<uint8_t> in((size_t)N, 0);
+    for (int64_t k = 0; k < R; ++k)
+        if (seen[(size_t)k]) {
+            uint8_t *row = in.data() + row_of[(size_t)k] * g.nx;
+            memset(row + runs[(size_t)k].a, 1, (size_t)(runs[(size_t)k].b - runs[(size_t)k].a + 1));
+        }
     return in;
+}
+
+bool domain_reaches_inlet(const lbm_grid &g, const std::vector<uint8_t> &dom)
+{
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            if (dom[(size_t)idx3(g, 0, y, z)])
+                return true;
+    return false;
 }
 
 // The flow-domain node of each column x that samples the column's shift
 // reference: the one nearest the middle of the cross-section
 // (|y - ny/2| + |z - nz/2|), the lowest index among equals; -1 for a column
 // without flow-domain nodes.
-static std::vector<int64_t> reference_nodes(const lbm_grid &g, const std::vector<uint8_t> &dom)
+std::vector<int64_t> reference_nodes(const lbm_grid &g, const std::vector<uint8_t> &dom)
 {
     std::vector<int64_t> r((size_t)g.nx, -1);
     std::vector<int> best((size_t)g.nx, INT32_MAX);
     const int cy = g.ny / 2, cz = g.nz / 2;
+    int64_t n = 0;
     for (int z = 0; z < g.nz; ++z)
         for (int y = 0; y < g.ny; ++y) {
             const int dist = abs(y - cy) + abs(z - cz);
-            for (int x = 0; x < g.nx; ++x) {
-                const int64_t n = idx3(g, x, y, z);
+            for (int x = 0; x < g.nx; ++x, ++n)
                 if (dom[(size_t)n] && dist < best[x]) {
                     best[x] = dist;
                     r[x] = n;
                 }
-            }
         }
     return r;
 }
 
-void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t lo, int64_t hi)
+uint32_t desc_word(const lbm_grid &g, const uint8_t *cls, const uint8_t *dom, bool ref, int x, int y,
+                   int z)
 {
     const int qf = fluid_dirs(g.nz).q, qa = ad_dirs(g.nz).q;
-    std::vector<uint32_t> lf((size_t)(hi - lo)), la((size_t)(hi - lo));
-    links_fluid(g, cls, lf.data(), lo, hi);
-    links_ad(g, cls, la.data(), lo, hi);
-    const std::vector<uint8_t> dom = flow_domain(g, cls);
-    const std::vector<int64_t> ref = reference_nodes(g, dom);
-    for (int64_t n = lo; n < hi; ++n) {
-        const uint8_t k = cls[n];
-        uint32_t d = 0;
-        if (dom[(size_t)n])
-            d |= 1u | (lf[n - lo] & ((1u << qf) - 2u));
-        if (k == LBM_FLUID || k == LBM_BIOFILM) {
-            for (int i = 1; i < qa; ++i)
-                if (la[n - lo] & (1u << i))
-                    d |= 1u << lbmk::desc_ad_link_bit(qf, i);
-            d |= 1u << lbmk::desc_ad_active_bit(qf, qa);
-        }
-        if (k == LBM_BIOFILM)
-            d |= 1u << lbmk::desc_biofilm_bit(qf, qa);
-        if (n == ref[(size_t)(n % g.nx)])
-            d |= 1u << lbmk::desc_ref_bit(qf, qa);
-        desc[n - lo] = d;
+    const int64_t n = idx3(g, x, y, z);
+    const uint8_t k = cls[n];
+    uint32_t d = 0;
+    if (dom[n])
+        d |= 1u | (link_bits<true>(g, cls, x, y, z) & ((1u << qf) - 2u));
+    if (k == LBM_FLUID || k == LBM_BIOFILM) {
+        const uint32_t la = link_bits<false>(g, cls, x, y, z);
+        for (int i = 1; i < qa; ++i)
+            if (la & (1u << i))
+                d |= 1u << lbmk::desc_ad_link_bit(qf, i);
+        d |= 1u << lbmk::desc_ad_active_bit(qf, qa);
     }
+    if (k == LBM_BIOFILM)
+        d |= 1u << lbmk::desc_biofilm_bit(qf, qa);
+    if (ref)
+        d |= 1u << lbmk::desc_ref_bit(qf, qa);
+    return d;
 }
 
+void build_desc(const lbm_grid &g, const uint8_t *cls, const std::vector<uint8_t> &dom,
+                const std::vector<int64_t> &ref, uint32_t *desc)
+{
+    int64_t n = 0;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x, ++n)
+                desc[n] = desc_word(g, cls, dom.data(), n == ref[(size_t)x], x, y, z);
+}
+
+void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc)
+{
+    const std::vector<uint8_t> dom = flow_domain(g, cls);
+    build_desc(g, cls, dom, reference_nodes(g, dom), desc);
+}
+
+// Inlet FLUID nodes are joined to the outlet column iff one of them is in
+// the flow domain (joining is symmetric).
 bool percolates(const lbm_grid &g, const uint8_t *cls)
 {
-    const Dirs &D = fluid_dirs(g.nz);
-    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    std::vector<uint8_t> seen((size_t)N, 0);
-    std::deque<int64_t> todo;
-    for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y) {
-            const int64_t n = idx3(g, 0, y, z);
-            if (cls[n] == LBM_FLUID) {
-                seen[n] = 1;
-                todo.push_back(n);
-            }
-        }
-    while (!todo.empty()) {
-        const int64_t n = todo.front();
-        todo.pop_front();
-        const int x = (int)(n % g.nx);
-        if (x == g.nx - 1)
-            return true;
-        const int y = (int)((n / g.nx) % g.ny);
-        const int z = (int)(n / ((int64_t)g.nx * g.ny));
-        for (int i = 1; i < D.q; ++i) {
-            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
-            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
-                continue;
-            const int64_t m = idx3(g, sx, sy, sz);
-            if (!seen[m] && cls[m] == LBM_FLUID) {
-                seen[m] = 1;
-                todo.push_back(m);
-            }
-        }
-    }
-    return false;
+    return domain_reaches_inlet(g, flow_domain(g, cls));
 }
 
 int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi)
 {
     const Dirs &D = fluid_dirs(g.nz);
-    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
     std::vector<int64_t> cand;
-    for (int64_t n = 0; n < N; ++n) {
-        if (cls[n] != LBM_FLUID)
-            continue;
-        const int x = (int)(n % g.nx);
-        if (x < 1 || x > g.nx - 2)
-            continue;
-        const int y = (int)((n / g.nx) % g.ny);
-        const int z = (int)(n / ((int64_t)g.nx * g.ny));
-        for (int i = 1; i < D.q; ++i) {
-            const int sx = x + D.c[i][0], sy = y + D.c[i][1], sz = z + D.c[i][2];
-            if (sx < 0 || sy < 0 || sz < 0 || sx >= g.nx || sy >= g.ny || sz >= g.nz)
-                continue;
-            if (cls[idx3(g, sx, sy, sz)] == LBM_BIOFILM) {
-                cand.push_back(n);
-                break;
+    int64_t n = 0;
+    for (int z = 0; z < g.nz; ++z)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x, ++n) {
+                if (cls[n] != LBM_FLUID || x < 1 || x > g.nx - 2)
+                    continue;
+                // 1 <= x <= nx-2: every x-neighbour is inside the grid
+                for (int i = 1; i < D.q; ++i) {
+                    const int ay = y + D.c[i][1], az = z + D.c[i][2];
+                    if (ay < 0 || az < 0 || ay >= g.ny || az >= g.nz)
+                        continue;
+                    if (cls[n + D.c[i][0] + D.c[i][1] * sy + D.c[i][2] * sz] == LBM_BIOFILM) {
+                        cand.push_back(n);
+                        break;
+                    }
+                }
             }
-        }
-    }
     if (cand.empty())
         return -1;
     double W = 0.0;
@@ -502,9 +562,9 @@ lbm_status lbm_links(lbm_grid g, const uint8_t *cls, int which, void *out)
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     std::vector<uint32_t> w((size_t)N);
     if (which == LBM_SOLVER_FLUID)
-        links_fluid(g, cls, w.data(), 0, N);
+        links_fluid(g, cls, w.data());
     else
-        links_ad(g, cls, w.data(), 0, N);
+        links_ad(g, cls, w.data());
     for (int64_t n = 0; n < N; ++n) {
         if (which == LBM_SOLVER_AD)
             static_cast<uint8_t *>(out)[n] = (uint8_t)w[n];
@@ -525,9 +585,9 @@ int64_t lbm_link_list(lbm_grid g, const uint8_t *cls, int which, int64_t *out, i
     const int q = which == 0 ? fluid_dirs(g.nz).q : ad_dirs(g.nz).q;
     std::vector<uint32_t> w((size_t)N);
     if (which == 0)
-        links_fluid(g, cls, w.data(), 0, N);
+        links_fluid(g, cls, w.data());
     else
-        links_ad(g, cls, w.data(), 0, N);
+        links_ad(g, cls, w.data());
     int64_t count = 0;
     for (int64_t n = 0; n < N; ++n)
         for (int i = 1; i < q; ++i)

@@ -618,8 +618,13 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
 }
 
 // Tile height of the two-step kernels (2-D): 64 x PAIR_TY nodes per
-// 256-thread block, PAIR_TY / 4 nodes per thread in the second step.
-constexpr int PAIR_TY = 8;
+// 256-thread block, PAIR_TY / 4 nodes per thread in the second step.  Four
+// rows, one node per thread: the first step recomputes 1.55x the tile
+// (66 x 6 nodes) against 1.29x for eight rows, but twice the blocks hide
+// more latency -- 19% faster on a 512 x 256 grid and no slower on
+// 1024 x 512 -- and the FP16 residual's tile means are the single-step
+// kernels' 64 x 4 tiles.
+constexpr int PAIR_TY = 4;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same

@@ -34,13 +34,24 @@ bool ad_blocked(uint8_t k);
 // mask rules: classes <= 3, chassis rows/planes not active, inlet/outlet
 // columns free of SOLID/BIOFILM.  Returns empty string if fine.
 std::string check_mask(const lbm_grid &g, const uint8_t *cls);
+// the same rules for one node (x, y, z) of class k
+std::string check_cell(const lbm_grid &g, int x, int y, int z, uint8_t k);
 bool percolates(const lbm_grid &g, const uint8_t *cls);
 // 1 for FLUID nodes linked to the outlet column, else 0 (one byte per node)
 std::vector<uint8_t> flow_domain(const lbm_grid &g, const uint8_t *cls);
-void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
-void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out, int64_t lo, int64_t hi);
-// descriptor words (lbm_kernels.h layout) for nodes [lo, hi)
-void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc, int64_t lo, int64_t hi);
+// some inlet-column node is in the domain (the mask percolates)
+bool domain_reaches_inlet(const lbm_grid &g, const std::vector<uint8_t> &dom);
+// per column x: the node sampling the shift reference, or -1
+std::vector<int64_t> reference_nodes(const lbm_grid &g, const std::vector<uint8_t> &dom);
+void links_fluid(const lbm_grid &g, const uint8_t *cls, uint32_t *out);
+void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out);
+// descriptor word (lbm_kernels.h layout) of node (x, y, z)
+uint32_t desc_word(const lbm_grid &g, const uint8_t *cls, const uint8_t *dom, bool ref, int x, int y,
+                   int z);
+// descriptor words of every node
+void build_desc(const lbm_grid &g, const uint8_t *cls, const std::vector<uint8_t> &dom,
+                const std::vector<int64_t> &ref, uint32_t *desc);
+void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc);
 int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi);
 
 // ---- error helpers -------------------------------------------------------
@@ -56,6 +67,12 @@ struct lbm_solver {
     int dim = 2, qf = 9, qa = 5;
     lbmk::Geo geo{};
     std::vector<uint8_t> cls;
+    // host mirror of the descriptors and what they derive from: the flow
+    // domain and the reference node of each column (cell updates patch
+    // these and upload the words)
+    std::vector<uint8_t> dom;
+    std::vector<int64_t> refn;
+    std::vector<uint32_t> desc_h;
     size_t desc_bytes = 2;       // per node
     int64_t n_fluid = 0, n_ad = 0;
     double c_ref = 0.0;          // substrate shift reference (0 if unshifted)

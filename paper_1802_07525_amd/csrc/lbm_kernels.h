@@ -50,13 +50,15 @@ struct Geo {
 Geo make_geo(int nx, int ny, int nz);
 
 // Descriptor word per node (uint16 in 2-D, uint32 in 3-D):
-//   bit 0                 node is FLUID (fluid solver updates it)
+//   bit 0                 node is in the flow domain (FLUID and linked to
+//                         the outlet column: the fluid solver updates it)
 //   bits 1..QF-1          fluid pull source n - c_i is blocked (bounce back)
 //   bits QF..QF+QA-2      substrate pull source n - c_i is blocked (i = 1..QA-1)
 //   bit  QF+QA-1          node is FLUID or BIOFILM (substrate solver updates it)
 //   bit  QF+QA            node is BIOFILM (consumption)
-//   bit  QF+QA+1          node samples its column's reference (one FLUID
-//                         node per x, nearest the middle of the cross-section)
+//   bit  QF+QA+1          node samples its column's reference (one flow-
+//                         domain node per x, nearest the middle of the
+//                         cross-section)
 inline int desc_ad_link_bit(int qf, int i) { return qf - 1 + i; }
 inline int desc_ad_active_bit(int qf, int qa) { return qf - 1 + qa; }
 inline int desc_biofilm_bit(int qf, int qa) { return qf + qa; }

@@ -434,15 +434,19 @@ struct lbm_server {
                 lbm_biofilm_layer(g, j->cls.data());
         }
         std::string m = check_mask(g, j->cls.data());
-        if (m.empty() && !percolates(g, j->cls.data()))
-            m = "the fluid domain does not connect inlet to outlet";
+        std::vector<uint8_t> dom;
+        if (m.empty()) {
+            dom = flow_domain(g, j->cls.data());
+            if (!domain_reaches_inlet(g, dom))
+                m = "the fluid domain does not connect inlet to outlet";
+        }
         if (!m.empty()) {
             j->status = LBM_EINVAL;
             j->msg = m;
             return;
         }
         std::vector<uint32_t> d((size_t)N);
-        build_desc(g, j->cls.data(), d.data(), 0, N);
+        build_desc(g, j->cls.data(), dom, reference_nodes(g, dom), d.data());
         j->desc.resize((size_t)N);
         const int aab = lbmk::desc_ad_active_bit(9, 5);
         for (int64_t n = 0; n < N; ++n) {

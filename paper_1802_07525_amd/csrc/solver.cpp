@@ -67,28 +67,43 @@ lbm_status validate_params(lbm_ctx *ctx, const lbm_params &p)
     return LBM_OK;
 }
 
-lbm_status upload_desc(lbm_solver *s)
+// Descriptor words of the mirror to the device, in the device width.
+lbm_status upload_desc_words(lbm_solver *s)
 {
     const int64_t N = s->geo.N;
-    std::vector<uint32_t> d((size_t)N);
-    build_desc(s->grid, s->cls.data(), d.data(), 0, N);
-    int64_t nf = 0, na = 0;
-    const int aab = lbmk::desc_ad_active_bit(s->qf, s->qa);
-    for (int64_t n = 0; n < N; ++n) {
-        nf += d[n] & 1u;
-        na += (d[n] >> aab) & 1u;
-    }
-    s->n_fluid = nf;
-    s->n_ad = na;
     if (s->desc_bytes == 2) {
         std::vector<uint16_t> p16((size_t)N);
         for (int64_t n = 0; n < N; ++n)
-            p16[n] = (uint16_t)d[n];
+            p16[n] = (uint16_t)s->desc_h[n];
         HIPCHK(hipMemcpy(s->d_desc, p16.data(), (size_t)N * 2, hipMemcpyHostToDevice), "desc upload");
     } else {
-        HIPCHK(hipMemcpy(s->d_desc, d.data(), (size_t)N * 4, hipMemcpyHostToDevice), "desc upload");
+        HIPCHK(hipMemcpy(s->d_desc, s->desc_h.data(), (size_t)N * 4, hipMemcpyHostToDevice),
+               "desc upload");
     }
     return LBM_OK;
+}
+
+void count_active(lbm_solver *s)
+{
+    int64_t nf = 0, na = 0;
+    const int aab = lbmk::desc_ad_active_bit(s->qf, s->qa);
+    for (uint32_t d : s->desc_h) {
+        nf += d & 1u;
+        na += (d >> aab) & 1u;
+    }
+    s->n_fluid = nf;
+    s->n_ad = na;
+}
+
+// Full rebuild of the mirror from the mask, then upload.
+lbm_status upload_desc(lbm_solver *s)
+{
+    s->dom = flow_domain(s->grid, s->cls.data());
+    s->refn = reference_nodes(s->grid, s->dom);
+    s->desc_h.resize((size_t)s->geo.N);
+    build_desc(s->grid, s->cls.data(), s->dom, s->refn, s->desc_h.data());
+    count_active(s);
+    return upload_desc_words(s);
 }
 
 lbm_status dev_alloc(lbm_solver *s, void **p, size_t bytes, const char *what)
@@ -423,6 +438,16 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         break;
     case LBM_FIELD_CLASS:
         memcpy(dst, s->cls.data(), N);
+        return LBM_OK;
+    case LBM_FIELD_DESC:
+        if (s->desc_bytes == 2) {
+            std::vector<uint16_t> w(N);
+            HIPCHK(hipMemcpy(w.data(), s->d_desc, N * 2, hipMemcpyDeviceToHost), "desc copy");
+            for (size_t n = 0; n < N; ++n)
+                static_cast<uint32_t *>(dst)[n] = w[n];
+        } else {
+            HIPCHK(hipMemcpy(dst, s->d_desc, N * 4, hipMemcpyDeviceToHost), "desc copy");
+        }
         return LBM_OK;
     case LBM_FIELD_LINKS_F:
         return lbm_links(s->grid, s->cls.data(), LBM_SOLVER_FLUID, dst);
@@ -770,28 +795,31 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
     if (!s || n < 0 || (n > 0 && (!idx || !new_cls)))
         return LBM_EINVAL;
     const int64_t N = s->geo.N;
+    const lbm_grid &g = s->grid;
     std::vector<uint8_t> trial = s->cls;
     for (int64_t k = 0; k < n; ++k) {
         if (idx[k] < 0 || idx[k] >= N || new_cls[k] > LBM_BIOFILM)
             return set_err(s->ctx, LBM_EINVAL, "bad cell index or class");
+        const int x = (int)(idx[k] % g.nx), y = (int)((idx[k] / g.nx) % g.ny);
+        const int z = (int)(idx[k] / ((int64_t)g.nx * g.ny));
+        std::string m = check_cell(g, x, y, z, new_cls[k]);
+        if (!m.empty())
+            return set_err(s->ctx, LBM_EINVAL, m);
         trial[(size_t)idx[k]] = new_cls[k];
     }
-    std::string m = check_mask(s->grid, trial.data());
-    if (!m.empty())
-        return set_err(s->ctx, LBM_EINVAL, m);
-    if (!percolates(s->grid, trial.data()))
+    std::vector<uint8_t> dom1 = flow_domain(g, trial.data());
+    if (!domain_reaches_inlet(g, dom1))
         return set_err(s->ctx, LBM_EINVAL, "update would disconnect inlet from outlet");
+    std::vector<int64_t> ref1 = reference_nodes(g, dom1);
     HIPCHK(hipSetDevice(s->ctx->device), "set device");
     // populations of nodes whose activity changes: four lists.  Fluid
     // activity is membership of the flow domain, which an update can change
     // far from the updated cells (closing or opening a pore).
     std::vector<long long> f_off, f_on, g_off, g_on;
-    const std::vector<uint8_t> dom0 = flow_domain(s->grid, s->cls.data());
-    const std::vector<uint8_t> dom1 = flow_domain(s->grid, trial.data());
     for (int64_t j = 0; j < N; ++j) {
-        if (dom0[(size_t)j] && !dom1[(size_t)j])
+        if (s->dom[(size_t)j] && !dom1[(size_t)j])
             f_off.push_back(j);
-        if (!dom0[(size_t)j] && dom1[(size_t)j])
+        if (!s->dom[(size_t)j] && dom1[(size_t)j])
             f_on.push_back(j);
     }
     for (int64_t k = 0; k < n; ++k) {
@@ -803,8 +831,39 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
         if (!ga && gb)
             g_on.push_back(j);
     }
+    // descriptor words that can change: the updated cells and their lattice
+    // neighbours (link bits), nodes entering or leaving the domain, and the
+    // old and new reference nodes of every column whose reference moved
+    std::vector<int64_t> touch(f_off.begin(), f_off.end());
+    touch.insert(touch.end(), f_on.begin(), f_on.end());
+    const Dirs &D = fluid_dirs(g.nz);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t j = idx[k];
+        const int x = (int)(j % g.nx), y = (int)((j / g.nx) % g.ny);
+        const int z = (int)(j / ((int64_t)g.nx * g.ny));
+        for (int i = 0; i < D.q; ++i) {
+            const int ax = x + D.c[i][0], ay = y + D.c[i][1], az = z + D.c[i][2];
+            if (ax >= 0 && ay >= 0 && az >= 0 && ax < g.nx && ay < g.ny && az < g.nz)
+                touch.push_back(ax + (int64_t)g.nx * (ay + (int64_t)g.ny * az));
+        }
+    }
+    for (int x = 0; x < g.nx; ++x)
+        if (s->refn[(size_t)x] != ref1[(size_t)x]) {
+            if (s->refn[(size_t)x] >= 0)
+                touch.push_back(s->refn[(size_t)x]);
+            if (ref1[(size_t)x] >= 0)
+                touch.push_back(ref1[(size_t)x]);
+        }
+    for (int64_t j : touch) {
+        const int x = (int)(j % g.nx), y = (int)((j / g.nx) % g.ny);
+        const int z = (int)(j / ((int64_t)g.nx * g.ny));
+        s->desc_h[(size_t)j] = desc_word(g, trial.data(), dom1.data(), ref1[(size_t)x] == j, x, y, z);
+    }
     s->cls.swap(trial);
-    lbm_status st = upload_desc(s);
+    s->dom.swap(dom1);
+    s->refn.swap(ref1);
+    count_active(s);
+    lbm_status st = upload_desc_words(s);
     if (st)
         return st;
     if (!s->d_idx) {

@@ -323,3 +323,45 @@ def test_update_sealing_a_pore(gpu_lib, storage):
         r2 = O.fluid_solve(cls2, w["tau"], w["u_in"], tol, mi, f=f)
         assert r2["status"] == "OK" and info["iters"] == r2["iters"]
         assert np.abs(U - r2["U"]).max() < 1e-9 * np.abs(r2["U"]).max()
+
+
+def test_incremental_descriptors_match_fresh_build(gpu_lib):
+    """Cell updates patch the descriptor words on the device in place.
+    After runs of random updates (growth, removal, solid cells; pores closed
+    and opened, reference nodes moved) they equal those of a solver built
+    on the resulting mask, and an update that would cut the inlet from the
+    outlet is refused without changing anything."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    ny, nx = cls.shape
+    rng = np.random.default_rng(7)
+    cur = cls.ravel().copy()
+    refused = 0
+    with _solver(lbm, cls, w, FP32S) as s:
+        assert s.steps(0, 10, cold=1)[0] == 0
+        for t in range(60):
+            # interior nodes, a third of them on the middle rows where the
+            # columns' reference nodes sit
+            y = ny // 2 + int(rng.integers(-1, 2)) if t % 3 == 0 else int(rng.integers(1, ny - 1))
+            x = int(rng.integers(1, nx - 1))
+            n = x + nx * y
+            new = {O.FLUID: (O.BIOFILM, O.SOLID)[t % 2], O.BIOFILM: O.FLUID,
+                   O.SOLID: O.FLUID}.get(int(cur[n]), O.FLUID)
+            trial = cur.copy()
+            trial[n] = new
+            st = lbm.lbm_solver_update_cells(s.h, [n], [new])
+            if O.percolates(trial.reshape(cls.shape)):
+                assert st == 0, s.error()
+                cur = trial
+            else:
+                assert st != 0
+                refused += 1
+            if t % 15 == 14:
+                got = s.get(lbm.LBM_FIELD_DESC)
+                assert np.array_equal(s.get(lbm.LBM_FIELD_CLASS), cur)
+                with _solver(lbm, cur.reshape(cls.shape), w, FP32S) as s2:
+                    want = s2.get(lbm.LBM_FIELD_DESC)
+                assert np.array_equal(got, want), (t, np.flatnonzero(got != want)[:10])
+                assert np.array_equal(got & 1, O.flow_domain(cur.reshape(cls.shape)).ravel())
+    print("updates applied", 60 - refused, "refused", refused, flush=True)

@@ -95,6 +95,30 @@ def test_percolation_and_growth_pick_match_oracle():
             assert L.lbm_growth_pick(a, C, xi) == O.growth_pick(a, C, xi)
 
 
+def test_percolation_and_growth_pick_random_masks():
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        a = (rng.random((10, 14)) < 0.42).astype(np.uint8) * rng.integers(1, 4, size=(10, 14)).astype(np.uint8)
+        a[0] = 2
+        a[-1] = 2
+        assert L.lbm_percolates(a) == O.percolates(a)
+        C = rng.random(a.size) - 0.1
+        xi = float(rng.random())
+        assert L.lbm_growth_pick(a, C, xi) == O.growth_pick(a, C, xi)
+
+
+@pytest.mark.parametrize("shape", [(12, 17), (7, 9, 11), (5, 6, 40)])
+def test_flow_domain_random_masks_match_oracle(shape):
+    """The library searches over runs of FLUID nodes, the oracle node by
+    node; random masks exercise every diagonal and edge link rule."""
+    rng = np.random.default_rng(len(shape) * 100 + shape[-1])
+    for frac in (0.25, 0.35, 0.45, 0.55):
+        for _ in range(15):
+            a = (rng.random(shape) < frac).astype(np.uint8) * rng.integers(1, 4, size=shape).astype(np.uint8)
+            assert np.array_equal(L.lbm_flow_domain(a), O.flow_domain(a))
+            assert L.lbm_percolates(a) == O.percolates(a)
+
+
 def test_flow_domain_matches_oracle():
     for seed in range(1, 10):
         _, a, _ = L.lbm_geom_discs(96, 48, 2, 5, 0.35, 0, seed)

@@ -268,6 +268,17 @@ def test_flow_domain_random_vs_scipy(nz):
         assert np.array_equal(O.flow_domain(cls), _domain_scipy(cls))
 
 
+def test_percolation_is_domain_reaching_inlet():
+    """Links are symmetric, so the inlet reaches the outlet iff an inlet
+    node is in the flow domain (the library decides percolation that way)."""
+    rng = np.random.default_rng(12)
+    for _ in range(60):
+        cls = (rng.random((9, 13)) < 0.45).astype(np.uint8)
+        cls[0] = O.WALL
+        cls[-1] = O.WALL
+        assert O.percolates(cls) == bool(O.flow_domain(cls)[:, 0].any())
+
+
 def _naive_pick(cls, C, xi):
     ny, nx = cls.shape
     c = _nbrs(1)
