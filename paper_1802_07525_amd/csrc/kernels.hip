@@ -214,7 +214,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 struct NodePos {
     int x, y, z;
     bool inb;
-    long long n;
+    unsigned int n; // element indices fit 32 bits: grids hold fewer than 2^31 / 19 nodes
 };
 
 __device__ __forceinline__ NodePos tile_node(const Geo &g, int tile)
@@ -227,7 +227,7 @@ __device__ __forceinline__ NodePos tile_node(const Geo &g, int tile)
     p.x = tx * 64 + (threadIdx.x & 63);
     p.y = ty * 4 + (threadIdx.x >> 6);
     p.inb = (p.x < g.nx) && (p.y < g.ny);
-    p.n = p.inb ? (p.x + (long long)g.nx * (p.y + (long long)g.ny * p.z)) : 0;
+    p.n = p.inb ? (unsigned int)(p.x + g.nx * (p.y + g.ny * p.z)) : 0u;
     return p;
 }
 
@@ -344,39 +344,109 @@ struct CheckAcc {
 };
 
 // ------------------------------------------------------ population sources
-// Where a node's incoming populations come from.  get(i, o, off, mode):
-// mode 0 = population i of the source node n - c_i (off = its offset),
-// 1 = this node's population o (the opposite of i: a reversed link),
-// 2 = this node's population i (a copied link).  Values are relative to the
-// column reference of the node they are read from.
+// Where a node's incoming populations come from.  own(i) is this node's
+// population i; pull(i, o, cx, cy, cz, m) is population i of the pull source
+// n - c_i, or this node's opposite population o on lanes whose mask m is all
+// ones (a reversed link).  Values are relative to the column reference of
+// the node they are read from.
+
+// 0, or all ones when bit i of m is set
+__device__ __forceinline__ unsigned int bit_mask(unsigned int m, int i)
+{
+    return (unsigned int)__builtin_amdgcn_sbfe((int)m, (unsigned int)i, 1u);
+}
+
+// Populations in global memory (the node's own step).  Element indices fit
+// 32 bits (grids hold fewer than 2^31 / 19 nodes), so a reversed link only
+// moves the index: i N + n - off becomes o N + n by adding the uniform
+// (o - i) N + off under the mask -- one load, no branches.
 template <class S>
 struct GlobalSrc {
     typedef typename S::C C;
     const typename S::T *__restrict__ h;
-    long long N, n;
-    __device__ __forceinline__ C get(int i, int o, long long off, int mode) const
+    unsigned int N, n;
+    int row, plane; // node offsets of y + 1 and z + 1
+    __device__ __forceinline__ C own(int i) const { return ld<S>(h + ((unsigned int)i * N + n)); }
+    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int cz, unsigned int m) const
     {
-        // one load from a selected address: no branches between the loads.
-        // Element indices fit 32 bits (grids hold fewer than 2^31 / 19
-        // nodes); unsigned wrap-around keeps n - off exact.
-        const unsigned int NN = (unsigned int)N, nn = (unsigned int)n;
-        const unsigned int idx = mode == 1 ? (unsigned int)o * NN + nn
-                                           : (unsigned int)i * NN + nn - (mode == 2 ? 0u : (unsigned int)off);
-        return ld<S>(h + idx);
+        const unsigned int off = (unsigned int)(cx + cy * row + cz * plane);
+        const unsigned int a = (unsigned int)i * N - off;
+        const unsigned int delta = (unsigned int)(o - i) * N + off;
+        return ld<S>(h + (n + a + (m & delta)));
     }
 };
 
 // The block's copy of the first step of a pair in LDS: [q][ly][lx] over the
 // tile and its one-node halo (LX x LY nodes, lx = x - x0 + 1, ly = y - y0 + 1).
+// Both candidates of a link sit at fixed offsets from the node's slot, so
+// both are read and the value is selected.
 template <class C, int Q, int LY, int LX>
 struct LdsSrc {
     const C (*v)[LY][LX];
     int lx, ly;
-    __device__ __forceinline__ C get2(int i, int o, int cx, int cy, int mode) const
+    __device__ __forceinline__ C own(int i) const { return v[i][ly][lx]; }
+    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int, unsigned int m) const
     {
-        return mode == 1 ? v[o][ly][lx] : (mode == 2 ? v[i][ly][lx] : v[i][ly - cy][lx - cx]);
+        const C a = v[i][ly - cy][lx - cx], b = v[o][ly][lx];
+        return m ? b : a;
     }
 };
+
+// Directions with c_ix = s as a bit mask.
+template <class L>
+__host__ __device__ constexpr unsigned int xdirs(int s)
+{
+    unsigned int m = 0;
+    for (int i = 1; i < L::Q; ++i)
+        if (L::cx[i] == s)
+            m |= 1u << i;
+    return m;
+}
+
+template <class L, int AX>
+__device__ __forceinline__ constexpr int cdir(int i)
+{
+    return AX == 0 ? L::cx[i] : (AX == 1 ? L::cy[i] : L::cz[i]);
+}
+
+// sum_i c_i[AX] f_i in direction order, started from its first nonzero
+// term (0 + x is not x for a compiler that keeps the sign of zero).  The
+// order keeps the partial sums small -- the + and - terms alternate -- which
+// matters where the stored values are whole populations.
+template <class L, int AX, class C>
+__device__ __forceinline__ C axis_sum(const C *f)
+{
+    C r = C(0);
+    bool h = false;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int c = cdir<L, AX>(i);
+        if (c == 0)
+            continue;
+        r = h ? (c > 0 ? r + f[i] : r - f[i]) : (c > 0 ? f[i] : -f[i]);
+        h = true;
+    }
+    return r;
+}
+
+// c_i . u from the nonzero components of c_i only
+template <class L, class C>
+__device__ __forceinline__ C cdot(int i, C ux, C uy, C uz)
+{
+    C r = C(0);
+    bool h = false;
+    const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+    const C u[3] = {ux, uy, uz};
+#pragma unroll
+    for (int k = 0; k < L::DIM; ++k) {
+        if (c[k] == 0)
+            continue;
+        const C t = c[k] > 0 ? u[k] : -u[k];
+        r = h ? r + t : t;
+        h = true;
+    }
+    return r;
+}
 
 // ------------------------------------------------------------ fluid step
 // Pull rules per direction i (source s = n - c_i), first match wins:
@@ -390,8 +460,8 @@ struct LdsSrc {
 // equilibrium of Eq. 5.  Fetch(i, o, cx, cy, cz, mode) returns one incoming
 // value (see the sources above).  f[] comes back relative to this column's
 // reference r0; the caller moves it to the reference it stores with.
-template <class L, class S, class DT, class Fetch>
-__device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, const Fetch &fetch,
+template <class L, class S, class DT, class Src>
+__device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, const Src &src,
                                               typename S::C r0, typename S::C dm, typename S::C dp,
                                               typename S::C f[L::Q], typename S::C &ux,
                                               typename S::C &uy, typename S::C &uz,
@@ -399,22 +469,21 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
 {
     typedef typename S::C C;
     const bool xin = x == 0, xout = x == a.g.nx - 1;
+    // reversed links: blocked sources, and the links through the inlet and
+    // outlet faces (their rules below start from the reversed value)
+    unsigned int rev = (unsigned int)d & ((1u << L::Q) - 2u);
+    rev |= xin ? xdirs<L>(1) : 0u;
+    rev |= xout ? xdirs<L>(-1) : 0u;
+    f[0] = src.own(0);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
-        if (i == 0) {
-            f[0] = fetch(0, 0, 0, 0, 0, 2);
-            continue;
-        }
-        const bool in_i = cx == 1 && xin, out_i = cx == -1 && xout;
-        const bool rev = in_i || out_i || ((d >> i) & DT(1));
-        C v = fetch(i, o, cx, cy, cz, rev ? 1 : 0);
+    for (int i = 1; i < L::Q; ++i) {
+        const int cx = L::cx[i];
+        const unsigned int m = bit_mask(rev, i);
+        C v = src.pull(i, L::op[i], cx, L::cy[i], L::cz[i], m);
         if constexpr (S::colref) {
             // a value streamed from column x - c_ix, re-referenced to r0
-            if (cx == 1)
-                v = rev ? v : v + C(L::w[i]) * dm;
-            if (cx == -1)
-                v = rev ? v : v + C(L::w[i]) * dp;
+            if (cx != 0)
+                v = m ? v : v + C(L::w[i]) * (cx == 1 ? dm : dp);
         }
         f[i] = v;
     }
@@ -427,47 +496,43 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
     }
     if (xout) {
         // u* of this node's stored state
-        C r = C(0), qx = C(0), qy = C(0), qz = C(0);
+        C h[L::Q];
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const C v = fetch(i, L::op[i], L::cx[i], L::cy[i], L::cz[i], 2);
-            r += v;
-            if (L::cx[i] == 1) qx += v;
-            if (L::cx[i] == -1) qx -= v;
-            if (L::cy[i] == 1) qy += v;
-            if (L::cy[i] == -1) qy -= v;
-            if (L::cz[i] == 1) qz += v;
-            if (L::cz[i] == -1) qz -= v;
-        }
+        for (int i = 0; i < L::Q; ++i)
+            h[i] = src.own(i);
+        C r = h[0];
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i)
+            r += h[i];
         const C ir = recip(S::shifted ? r0 + r : r);
-        const C ox = qx * ir, oy = qy * ir, oz = qz * ir;
-        const C ousq = C(1.5) * (ox * ox + oy * oy + oz * oz);
+        const C ox = axis_sum<L, 0>(h) * ir, oy = axis_sum<L, 1>(h) * ir;
+        const C oz = L::DIM == 3 ? axis_sum<L, 2>(h) * ir : C(0);
+        const C ousq = C(1.5) * (L::DIM == 3 ? ox * ox + oy * oy + oz * oz : ox * ox + oy * oy);
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             if (L::cx[i] != -1)
                 continue;
-            const C cu = -ox + C(L::cy[i]) * oy + C(L::cz[i]) * oz;
+            const C cu = cdot<L>(i, ox, oy, oz);
             const C even = C(4.5) * cu * cu - ousq;
             f[i] = C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - f[i];
         }
     }
-    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+    C rs = f[0];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
+    for (int i = 1; i < L::Q; ++i)
         rs += f[i];
-        if (L::cx[i] == 1) jx += f[i];
-        if (L::cx[i] == -1) jx -= f[i];
-        if (L::cy[i] == 1) jy += f[i];
-        if (L::cy[i] == -1) jy -= f[i];
-        if (L::cz[i] == 1) jz += f[i];
-        if (L::cz[i] == -1) jz -= f[i];
-    }
     rho = S::shifted ? r0 + rs : rs;
     const C inv = recip(rho);
-    ux = jx * inv;
-    uy = jy * inv;
-    uz = jz * inv;
-    const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+    ux = axis_sum<L, 0>(f) * inv;
+    uy = axis_sum<L, 1>(f) * inv;
+    C usq = ux * ux + uy * uy;
+    if constexpr (L::DIM == 3) {
+        uz = axis_sum<L, 2>(f) * inv;
+        usq += uz * uz;
+    } else {
+        uz = C(0);
+    }
+    usq *= C(1.5);
     const C om = C(a.omega);
     // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2), minus
     // the shift w_i r0 when stored shifted (rs = rho - r0).  Opposite
@@ -483,13 +548,7 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
         const int o = L::op[i];
         if (o < i)
             continue;
-        C cu = C(0);
-        if (L::cx[i] == 1) cu += ux;
-        if (L::cx[i] == -1) cu -= ux;
-        if (L::cy[i] == 1) cu += uy;
-        if (L::cy[i] == -1) cu -= uy;
-        if (L::cz[i] == 1) cu += uz;
-        if (L::cz[i] == -1) cu -= uz;
+        const C cu = cdot<L>(i, ux, uy, uz);
         const C rcu = rho * cu;
         const C even = C(L::w[i]) * (base + C(4.5) * rcu * cu);
         const C odd = C(3.0 * L::w[i]) * rcu;
@@ -598,12 +657,9 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
     }
     if (act) {
-        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), N, p.n};
-        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
-        auto fetch = [&](int i, int o, int cx, int cy, int cz, int mode) {
-            return src.get(i, o, cx + cy * row + cz * plane, mode);
-        };
-        fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), (unsigned int)N, p.n, a.g.nx,
+                               a.g.nx * a.g.ny};
+        fluid_collide<L, S, DT>(a, p.x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
         if constexpr (S::colref) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -654,12 +710,12 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     const int nx = a.g.nx, ny = a.g.ny;
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
-    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
+    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), (unsigned int)N, 0u, nx, 0};
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
         const int x = x0 - 1 + lx, y = y0 - 1 + ly;
         const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
-        const long long n = inb ? x + (long long)nx * y : 0;
+        const unsigned int n = inb ? (unsigned int)(x + nx * y) : 0u;
         const DT d = inb ? desc[n] : DT(0);
         C f[L::Q];
         if (d & DT(1)) {
@@ -668,10 +724,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
                 column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
             GlobalSrc<S> src = gsrc;
             src.n = n;
-            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-                return src.get(i, o, cx + cy * (long long)nx, mode);
-            };
-            fluid_collide<L, S, DT>(a, x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+            fluid_collide<L, S, DT>(a, x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
         } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -691,7 +744,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
         p.y = y0 + ly;
         p.z = 0;
         p.inb = p.x < nx && p.y < ny;
-        p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+        p.n = p.inb ? (unsigned int)(p.x + nx * p.y) : 0u;
         const DT d = p.inb ? desc[p.n] : DT(0);
         const bool act = (d & DT(1)) != 0;
         C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
@@ -701,10 +754,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
             if constexpr (S::colref)
                 column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
             const LdsSrc<C, L::Q, LY, LX> src{v, lx + 1, ly + 1};
-            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-                return src.get2(i, o, cx, cy, mode);
-            };
-            fluid_collide<L, S, DT>(a, p.x, d, fetch, r0, dm, dp, f, ux, uy, uz, rho);
+            fluid_collide<L, S, DT>(a, p.x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
             if constexpr (S::colref) {
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i)
@@ -745,8 +795,8 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 //   otherwise:                     h_i = h*_i(s)
 // Collision (Eq. 12) with the linear equilibrium w_i C (1 + c_i.u / c_s^2)
 // and the biofilm consumption - w_i k C.  g[] comes back relative to r0.
-template <class L, int QF, class S, class DT, class Fetch>
-__device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const Fetch &fetch,
+template <class L, int QF, class S, class DT, class Src>
+__device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const Src &src,
                                            typename S::C ux, typename S::C uy, typename S::C uz,
                                            typename S::C r0, typename S::C dm, typename S::C dp,
                                            typename S::C g[L::Q], typename S::C &cfull)
@@ -757,24 +807,20 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const F
     const bool xin = x == 0, xout = x == a.g.nx - 1;
     // Dirichlet values relative to this column's reference
     const C cin_s = C(a.c_in - (double)r0), cout_s = C(a.c_out - (double)r0);
+    // reversed links: blocked sources and the inlet and outlet faces (the
+    // zero-gradient outlet replaces its value below)
+    unsigned int rev = ((unsigned int)d >> LNK) & ((1u << L::Q) - 2u);
+    rev |= xin ? xdirs<L>(1) : 0u;
+    rev |= xout ? xdirs<L>(-1) : 0u;
+    g[0] = src.own(0);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i], o = L::op[i];
-        if (i == 0) {
-            g[0] = fetch(0, 0, 0, 0, 0, 2);
-            continue;
-        }
-        const bool in_i = cx == 1 && xin;
-        // zero-gradient outlet copies this node's own population i
-        const bool copy_i = cx == -1 && xout && !a.outlet;
-        const bool abb_i = cx == -1 && xout && a.outlet;
-        const bool rev = in_i || abb_i || ((d >> (LNK + i)) & DT(1));
-        C v = fetch(i, o, cx, cy, cz, rev ? 1 : (copy_i ? 2 : 0));
+    for (int i = 1; i < L::Q; ++i) {
+        const int cx = L::cx[i];
+        const unsigned int m = bit_mask(rev, i);
+        C v = src.pull(i, L::op[i], cx, L::cy[i], L::cz[i], m);
         if constexpr (S::colref) {
-            if (cx == 1)
-                v = rev ? v : v + C(L::w[i]) * dm;
-            if (cx == -1)
-                v = (rev || copy_i) ? v : v + C(L::w[i]) * dp;
+            if (cx != 0)
+                v = m ? v : v + C(L::w[i]) * (cx == 1 ? dm : dp);
         }
         g[i] = v;
     }
@@ -786,28 +832,30 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const F
             if (L::cx[i] == 1)
                 g[i] = (S::colref ? C(2.0 * L::w[i]) * cin_s : C(2.0 * L::w[i] * a.cin_s)) - g[i];
     }
-    if (xout && a.outlet) {
+    if (xout) {
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
-            if (L::cx[i] == -1)
-                g[i] = (S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s)) - g[i];
+            if (L::cx[i] == -1) {
+                if (a.outlet)
+                    g[i] = (S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s)) - g[i];
+                else
+                    g[i] = src.own(i); // zero gradient: copy this node's population i
+            }
     }
-    C cs = C(0);
+    C cs = g[0];
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
+    for (int i = 1; i < L::Q; ++i)
         cs += g[i];
     cfull = S::shifted ? r0 + cs : cs;
     const C om = C(a.omega);
     const C kc = ((d >> BIO) & DT(1)) ? C(a.k_sink) * cfull : C(0);
+    {
+        const C geq = C(L::w[0]) * cs;
+        g[0] = g[0] + om * (geq - g[0]) - C(L::w[0]) * kc;
+    }
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        C cu = C(0);
-        if (L::cx[i] == 1) cu += ux;
-        if (L::cx[i] == -1) cu -= ux;
-        if (L::cy[i] == 1) cu += uy;
-        if (L::cy[i] == -1) cu -= uy;
-        if (L::cz[i] == 1) cu += uz;
-        if (L::cz[i] == -1) cu -= uz;
+    for (int i = 1; i < L::Q; ++i) {
+        const C cu = cdot<L>(i, ux, uy, uz);
         const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
         g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
     }
@@ -879,15 +927,13 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
             column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
     }
     if (act) {
-        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), N, p.n};
-        const long long row = a.g.nx, plane = (long long)a.g.nx * a.g.ny;
-        auto fetch = [&](int i, int o, int cx, int cy, int cz, int mode) {
-            return src.get(i, o, cx + cy * row + cz * plane, mode);
-        };
+        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), (unsigned int)N, p.n, a.g.nx,
+                               a.g.nx * a.g.ny};
         const C *U = static_cast<const C *>(a.u);
-        const C ux = U[p.n], uy = U[N + p.n];
-        const C uz = (L::DIM == 3) ? U[2 * N + p.n] : C(0);
-        ad_collide<L, QF, S, DT>(a, p.x, d, fetch, ux, uy, uz, r0, dm, dp, g, cfull);
+        const unsigned int NN = (unsigned int)N;
+        const C ux = U[p.n], uy = U[NN + p.n];
+        const C uz = (L::DIM == 3) ? U[2u * NN + p.n] : C(0);
+        ad_collide<L, QF, S, DT>(a, p.x, d, src, ux, uy, uz, r0, dm, dp, g, cfull);
         if constexpr (S::colref) {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -917,12 +963,13 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
-    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), N, 0};
+    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), (unsigned int)N, 0u, nx, 0};
+    const unsigned int NN = (unsigned int)N;
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
         const int x = x0 - 1 + lx, y = y0 - 1 + ly;
         const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
-        const long long n = inb ? x + (long long)nx * y : 0;
+        const unsigned int n = inb ? (unsigned int)(x + nx * y) : 0u;
         const DT d = inb ? desc[n] : DT(0);
         C g[L::Q];
         if ((d >> ACT) & DT(1)) {
@@ -931,10 +978,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
                 column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
             GlobalSrc<S> src = gsrc;
             src.n = n;
-            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-                return src.get(i, o, cx + cy * (long long)nx, mode);
-            };
-            ad_collide<L, QF, S, DT>(a, x, d, fetch, U[n], U[N + n], C(0), r0, dm, dp, g, cfull);
+            ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, dm, dp, g, cfull);
         } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -954,7 +998,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
         p.y = y0 + ly;
         p.z = 0;
         p.inb = p.x < nx && p.y < ny;
-        p.n = p.inb ? p.x + (long long)nx * p.y : 0;
+        p.n = p.inb ? (unsigned int)(p.x + nx * p.y) : 0u;
         const DT d = p.inb ? desc[p.n] : DT(0);
         const bool act = ((d >> ACT) & DT(1)) != 0;
         C cfull = C(0);
@@ -964,11 +1008,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
             if constexpr (S::colref)
                 column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
             const LdsSrc<C, L::Q, LY, LX> src{v, lx + 1, ly + 1};
-            auto fetch = [&](int i, int o, int cx, int cy, int, int mode) {
-                return src.get2(i, o, cx, cy, mode);
-            };
-            ad_collide<L, QF, S, DT>(a, p.x, d, fetch, U[p.n], U[N + p.n], C(0), r0, dm, dp, g,
-                                     cfull);
+            ad_collide<L, QF, S, DT>(a, p.x, d, src, U[p.n], U[NN + p.n], C(0), r0, dm, dp, g, cfull);
             if constexpr (S::colref) {
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i)
