@@ -366,6 +366,7 @@ struct GlobalSrc {
     const typename S::T *__restrict__ h;
     unsigned int N, n;
     int row, plane; // node offsets of y + 1 and z + 1
+    __device__ __forceinline__ void set(unsigned int node) { n = node; }
     __device__ __forceinline__ C own(int i) const { return ld<S>(h + ((unsigned int)i * N + n)); }
     __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int cz, unsigned int m) const
     {
@@ -375,6 +376,59 @@ struct GlobalSrc {
         return ld<S>(h + (n + a + (m & delta)));
     }
 };
+
+// Populations through a buffer resource (storage of at most 4 bytes, 2-D:
+// 9 N elements of the largest grid fit 32-bit byte offsets).  The offset is
+// the load's only per-lane address: no 64-bit address arithmetic, and the
+// hardware range check returns 0 rather than reading past the array.
+template <class S>
+struct BufSrc {
+    typedef typename S::C C;
+    typedef typename S::T T;
+    static_assert(sizeof(T) <= 4, "byte offsets of wider storage may exceed 32 bits");
+    __amdgpu_buffer_rsrc_t r;
+    unsigned int N4, n4; // N and n in bytes
+    int row4;            // a y step in bytes
+    __device__ __forceinline__ void set(unsigned int node) { n4 = node * (unsigned int)sizeof(T); }
+    __device__ __forceinline__ C at(unsigned int b) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            return static_cast<C>(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, b, 0, 0)));
+        } else {
+            return static_cast<C>(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, b, 0, 0)));
+        }
+    }
+    __device__ __forceinline__ C own(int i) const { return at((unsigned int)i * N4 + n4); }
+    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int, unsigned int m) const
+    {
+        const unsigned int off = (unsigned int)(cx * (int)sizeof(T) + cy * row4);
+        const unsigned int a = (unsigned int)i * N4 - off;
+        const unsigned int delta = (unsigned int)(o - i) * N4 + off;
+        return at(n4 + a + (m & delta));
+    }
+};
+
+// Buffer resource over q N elements of storage type T (raw, 32-bit format:
+// the gfx9 word-3 value)
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const T *p, unsigned int q, unsigned int N)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), (short)0,
+                                             (int)(q * N * (unsigned int)sizeof(T)), 0x00020000);
+}
+
+// Source of the first step of a 2-D pair (global memory): through a buffer
+// resource where the storage allows it
+template <class S, int Q>
+__device__ __forceinline__ auto pair_src(const void *src, long long N, int nx)
+{
+    typedef typename S::T T;
+    if constexpr (sizeof(T) <= 4)
+        return BufSrc<S>{pop_rsrc(static_cast<const T *>(src), (unsigned int)Q, (unsigned int)N),
+                         (unsigned int)N * (unsigned int)sizeof(T), 0u, nx * (int)sizeof(T)};
+    else
+        return GlobalSrc<S>{static_cast<const T *>(src), (unsigned int)N, 0u, nx, 0};
+}
 
 // The block's copy of the first step of a pair in LDS: [q][ly][lx] over the
 // tile and its one-node halo (LX x LY nodes, lx = x - x0 + 1, ly = y - y0 + 1).
@@ -710,7 +764,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     const int nx = a.g.nx, ny = a.g.ny;
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
-    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), (unsigned int)N, 0u, nx, 0};
+    const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
         const int x = x0 - 1 + lx, y = y0 - 1 + ly;
@@ -722,17 +776,16 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
             C r0 = C(1), dm = C(0), dp = C(0), rd = C(1), ux, uy, uz, rho;
             if constexpr (S::colref)
                 column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
-            GlobalSrc<S> src = gsrc;
-            src.n = n;
+            auto src = gsrc;
+            src.set(n);
             fluid_collide<L, S, DT>(a, x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
-        } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                f[i] = C(0);
+                v[i][ly][lx] = f[i];
         }
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            v[i][ly][lx] = f[i];
+        // inactive nodes leave their slots unwritten: the second step reads
+        // a slot only as one of a link's two candidates, and selects the
+        // other one whenever the slot's node is blocked
     }
     __syncthreads();
     CheckAcc<S::tile_mean> acc;
@@ -963,7 +1016,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
-    const GlobalSrc<S> gsrc{static_cast<const typename S::T *>(a.src), (unsigned int)N, 0u, nx, 0};
+    const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
     const unsigned int NN = (unsigned int)N;
     for (int r = threadIdx.x; r < NR; r += 256) {
         const int lx = r % LX, ly = r / LX;
@@ -976,17 +1029,14 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
             C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0, cfull;
             if constexpr (S::colref)
                 column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
-            GlobalSrc<S> src = gsrc;
-            src.n = n;
+            auto src = gsrc;
+            src.set(n);
             ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, dm, dp, g, cfull);
-        } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                g[i] = C(0);
+                v[i][ly][lx] = g[i];
         }
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            v[i][ly][lx] = g[i];
+        // inactive nodes leave their slots unwritten (see fluid_tile2)
     }
     __syncthreads();
     CheckAcc<S::tile_mean> acc;
