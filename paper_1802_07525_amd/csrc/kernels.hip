@@ -152,8 +152,8 @@ __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
 }
 // Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a node
 // and a step; each direction then advances a 32-bit linear congruential
-// generator (Knuth's MMIX multiplier, increment 1) from it and uses its top
-// 13 bits.
+// generator from it (a = 1664525, c = 1013904223: the quick generator of
+// Press et al., Numerical Recipes) and uses its top 13 bits.
 __device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
 {
     unsigned int x = n * 0x9E3779B1u ^ t * 0xC2B2AE3Du;
