@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -491,25 +492,30 @@ bool percolates(const lbm_grid &g, const uint8_t *cls)
 int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi)
 {
     const Dirs &D = fluid_dirs(g.nz);
-    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
     std::vector<int64_t> cand;
-    int64_t n = 0;
+    // per row: near[x] = some lattice neighbour of (x, y, z) is BIOFILM, from
+    // the neighbouring rows' BIOFILM flags shifted by c_x (byte loops)
+    std::vector<uint8_t> near((size_t)g.nx), bio((size_t)g.nx);
     for (int z = 0; z < g.nz; ++z)
-        for (int y = 0; y < g.ny; ++y)
-            for (int x = 0; x < g.nx; ++x, ++n) {
-                if (cls[n] != LBM_FLUID || x < 1 || x > g.nx - 2)
+        for (int y = 0; y < g.ny; ++y) {
+            std::fill(near.begin(), near.end(), 0);
+            for (int i = 1; i < D.q; ++i) {
+                const int ay = y + D.c[i][1], az = z + D.c[i][2], cx = D.c[i][0];
+                if (ay < 0 || az < 0 || ay >= g.ny || az >= g.nz)
                     continue;
-                // 1 <= x <= nx-2: every x-neighbour is inside the grid
-                for (int i = 1; i < D.q; ++i) {
-                    const int ay = y + D.c[i][1], az = z + D.c[i][2];
-                    if (ay < 0 || az < 0 || ay >= g.ny || az >= g.nz)
-                        continue;
-                    if (cls[n + D.c[i][0] + D.c[i][1] * sy + D.c[i][2] * sz] == LBM_BIOFILM) {
-                        cand.push_back(n);
-                        break;
-                    }
-                }
+                const uint8_t *row = cls + idx3(g, 0, ay, az);
+                for (int x = 0; x < g.nx; ++x)
+                    bio[x] = row[x] == LBM_BIOFILM;
+                // near[x] |= bio[x + cx] for x + cx inside the row
+                const int lo = cx < 0 ? -cx : 0, hi = cx > 0 ? g.nx - cx : g.nx;
+                for (int x = lo; x < hi; ++x)
+                    near[x] |= bio[x + cx];
             }
+            const int64_t n0 = idx3(g, 0, y, z);
+            for (int x = 1; x < g.nx - 1; ++x)
+                if (cls[n0 + x] == LBM_FLUID && near[x])
+                    cand.push_back(n0 + x);
+        }
     if (cand.empty())
         return -1;
     double W = 0.0;

@@ -377,9 +377,10 @@ struct GlobalSrc {
     }
 };
 
-// Populations through a buffer resource (storage of at most 4 bytes, 2-D:
-// 9 N elements of the largest grid fit 32-bit byte offsets).  The offset is
-// the load's only per-lane address: no 64-bit address arithmetic, and the
+// Populations through a buffer resource, where the whole array fits 32-bit
+// byte offsets (storage of at most 4 bytes: always in 2-D, in 3-D below
+// 2^32 / (19 * 4) nodes).  The offset is the load's only per-lane address --
+// no 64-bit address arithmetic and one register per address -- and the
 // hardware range check returns 0 rather than reading past the array.
 template <class S>
 struct BufSrc {
@@ -388,7 +389,7 @@ struct BufSrc {
     static_assert(sizeof(T) <= 4, "byte offsets of wider storage may exceed 32 bits");
     __amdgpu_buffer_rsrc_t r;
     unsigned int N4, n4; // N and n in bytes
-    int row4;            // a y step in bytes
+    int row4, plane4;    // a y step and a z step in bytes
     __device__ __forceinline__ void set(unsigned int node) { n4 = node * (unsigned int)sizeof(T); }
     __device__ __forceinline__ C at(unsigned int b) const
     {
@@ -399,9 +400,9 @@ struct BufSrc {
         }
     }
     __device__ __forceinline__ C own(int i) const { return at((unsigned int)i * N4 + n4); }
-    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int, unsigned int m) const
+    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int cz, unsigned int m) const
     {
-        const unsigned int off = (unsigned int)(cx * (int)sizeof(T) + cy * row4);
+        const unsigned int off = (unsigned int)(cx * (int)sizeof(T) + cy * row4 + cz * plane4);
         const unsigned int a = (unsigned int)i * N4 - off;
         const unsigned int delta = (unsigned int)(o - i) * N4 + off;
         return at(n4 + a + (m & delta));
@@ -417,6 +418,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(const T *p, unsigned 
                                              (int)(q * N * (unsigned int)sizeof(T)), 0x00020000);
 }
 
+// Source of a single-step tile: a buffer resource where the host found the
+// array within 32-bit byte offsets (BUF), else plain global pointers
+template <class L, class S, bool BUF>
+__device__ __forceinline__ auto node_src(const void *src, const Geo &g, unsigned int n)
+{
+    typedef typename S::T T;
+    if constexpr (BUF)
+        return BufSrc<S>{pop_rsrc(static_cast<const T *>(src), (unsigned int)L::Q, (unsigned int)g.N),
+                         (unsigned int)g.N * (unsigned int)sizeof(T), n * (unsigned int)sizeof(T),
+                         g.nx * (int)sizeof(T), g.nx * g.ny * (int)sizeof(T)};
+    else
+        return GlobalSrc<S>{static_cast<const T *>(src), (unsigned int)g.N, n, g.nx, g.nx * g.ny};
+}
+
 // Source of the first step of a 2-D pair (global memory): through a buffer
 // resource where the storage allows it
 template <class S, int Q>
@@ -425,7 +440,7 @@ __device__ __forceinline__ auto pair_src(const void *src, long long N, int nx)
     typedef typename S::T T;
     if constexpr (sizeof(T) <= 4)
         return BufSrc<S>{pop_rsrc(static_cast<const T *>(src), (unsigned int)Q, (unsigned int)N),
-                         (unsigned int)N * (unsigned int)sizeof(T), 0u, nx * (int)sizeof(T)};
+                         (unsigned int)N * (unsigned int)sizeof(T), 0u, nx * (int)sizeof(T), 0};
     else
         return GlobalSrc<S>{static_cast<const T *>(src), (unsigned int)N, 0u, nx, 0};
 }
@@ -695,7 +710,7 @@ __device__ __forceinline__ void fluid_finish(const FluidArgs &a, const NodePos &
     }
 }
 
-template <class L, class S, class DT, int MODE, bool NT>
+template <class L, class S, class DT, int MODE, bool NT, bool BUF>
 __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
                                            unsigned long long *part_r, unsigned long long *part_u)
 {
@@ -711,8 +726,7 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
             column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
     }
     if (act) {
-        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), (unsigned int)N, p.n, a.g.nx,
-                               a.g.nx * a.g.ny};
+        const auto src = node_src<L, S, BUF>(a.src, a.g, p.n);
         fluid_collide<L, S, DT>(a, p.x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
         if constexpr (S::colref) {
 #pragma unroll
@@ -829,14 +843,14 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     __syncthreads(); // the block may run another tile: v is reused
 }
 
-template <class L, class S, class DT, int MODE, bool NT>
+template <class L, class S, class DT, int MODE, bool NT, bool BUF>
 __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 {
     if (a.ctrl->stop)
         return;
     const NodePos p = tile_node(a.g, xcd_tile(blockIdx.x, gridDim.x));
     unsigned long long *part = a.ctrl->part;
-    fluid_tile<L, S, DT, MODE, NT>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
+    fluid_tile<L, S, DT, MODE, NT, BUF>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
 }
 
 // -------------------------------------------------------- substrate step
@@ -963,7 +977,7 @@ __device__ __forceinline__ void ad_finish(const AdArgs &a, const NodePos &p, DT 
     }
 }
 
-template <class L, int QF, class S, class DT, int MODE, bool NT>
+template <class L, int QF, class S, class DT, int MODE, bool NT, bool BUF>
 __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
                                         unsigned long long *part_r, unsigned long long *part_u)
 {
@@ -980,8 +994,7 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
             column_refs<S>(a.ref_src, a.ref_dst, p.x, a.g.nx, r0, dm, dp, rd);
     }
     if (act) {
-        const GlobalSrc<S> src{static_cast<const typename S::T *>(a.src), (unsigned int)N, p.n, a.g.nx,
-                               a.g.nx * a.g.ny};
+        const auto src = node_src<L, S, BUF>(a.src, a.g, p.n);
         const C *U = static_cast<const C *>(a.u);
         const unsigned int NN = (unsigned int)N;
         const C ux = U[p.n], uy = U[NN + p.n];
@@ -1080,14 +1093,14 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     __syncthreads();
 }
 
-template <class L, int QF, class S, class DT, int MODE, bool NT>
+template <class L, int QF, class S, class DT, int MODE, bool NT, bool BUF>
 __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
 {
     if (a.ctrl->stop)
         return;
     const NodePos p = tile_node(a.g, xcd_tile(blockIdx.x, gridDim.x));
     unsigned long long *part = a.ctrl->part;
-    ad_tile<L, QF, S, DT, MODE, NT>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
+    ad_tile<L, QF, S, DT, MODE, NT, BUF>(a, p, part + blockIdx.x, part + gridDim.x + blockIdx.x);
 }
 
 // Two steps per launch (2-D)
@@ -1727,17 +1740,27 @@ hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStr
             typedef decltype(dt) DT;
             dim3 grid(a.g.ntiles), block(256);
             const bool nt = a.streaming_stores != 0;
-#define LBM_FLUID_LAUNCH(M)                                                                       \
+            constexpr bool B = sizeof(typename S::T) <= 4;
+            const bool buf = B && (unsigned long long)LF::Q * (unsigned long long)a.g.N *
+                                          sizeof(typename S::T) <= 0xFFFFFFFFull;
+#define LBM_FLUID_LAUNCH(M, NTV)                                                                  \
     do {                                                                                          \
-        if (nt)                                                                                   \
-            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, true>), grid, block, 0, st, a);      \
+        if (buf)                                                                                  \
+            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, NTV, B>), grid, block, 0, st, a);    \
         else                                                                                      \
-            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, false>), grid, block, 0, st, a);     \
+            hipLaunchKernelGGL((k_fluid_step<LF, S, DT, M, NTV, false>), grid, block, 0, st, a);\
     } while (0)
-            if (mode == MODE_CHECK)
-                LBM_FLUID_LAUNCH(MODE_CHECK);
-            else
-                LBM_FLUID_LAUNCH(MODE_PLAIN);
+            if (mode == MODE_CHECK) {
+                if (nt)
+                    LBM_FLUID_LAUNCH(MODE_CHECK, true);
+                else
+                    LBM_FLUID_LAUNCH(MODE_CHECK, false);
+            } else {
+                if (nt)
+                    LBM_FLUID_LAUNCH(MODE_PLAIN, true);
+                else
+                    LBM_FLUID_LAUNCH(MODE_PLAIN, false);
+            }
 #undef LBM_FLUID_LAUNCH
             return hipGetLastError();
         });
@@ -1799,17 +1822,28 @@ hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t 
             typedef decltype(dt) DT;
             dim3 grid(a.g.ntiles), block(256);
             const bool nt = a.streaming_stores != 0;
-#define LBM_AD_LAUNCH(M)                                                                          \
+            constexpr bool B = sizeof(typename S::T) <= 4;
+            const bool buf = B && (unsigned long long)LA::Q * (unsigned long long)a.g.N *
+                                          sizeof(typename S::T) <= 0xFFFFFFFFull;
+#define LBM_AD_LAUNCH(M, NTV)                                                                     \
     do {                                                                                          \
-        if (nt)                                                                                   \
-            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, true>), grid, block, 0, st, a);  \
+        if (buf)                                                                                  \
+            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, NTV, B>), grid, block, 0, st, a);\
         else                                                                                      \
-            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, false>), grid, block, 0, st, a); \
+            hipLaunchKernelGGL((k_ad_step<LA, LF::Q, S, DT, M, NTV, false>), grid, block, 0, st,  \
+                               a);                                                                \
     } while (0)
-            if (mode == MODE_CHECK)
-                LBM_AD_LAUNCH(MODE_CHECK);
-            else
-                LBM_AD_LAUNCH(MODE_PLAIN);
+            if (mode == MODE_CHECK) {
+                if (nt)
+                    LBM_AD_LAUNCH(MODE_CHECK, true);
+                else
+                    LBM_AD_LAUNCH(MODE_CHECK, false);
+            } else {
+                if (nt)
+                    LBM_AD_LAUNCH(MODE_PLAIN, true);
+                else
+                    LBM_AD_LAUNCH(MODE_PLAIN, false);
+            }
 #undef LBM_AD_LAUNCH
             return hipGetLastError();
         });
