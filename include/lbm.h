@@ -126,6 +126,12 @@ typedef struct {
     int32_t check_every;  /* residual cadence K, even and >= 2 (100 if 0) */
     int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
                              1000 otherwise; < 0 disables */
+    double k_half;        /* 0: first-order sink k_sink C per step on BIOFILM nodes.
+                             > 0: the Monod form of the consumption rate (Eq. 13,
+                             its mediator factor folded into k_sink), k_sink C /
+                             (C + k_half), C the concentration a step collides with;
+                             needs k_sink < k_half.  Zero-initialised parameters keep
+                             the first-order sink. */
 } lbm_params;
 
 typedef struct {
@@ -377,6 +383,7 @@ typedef struct {
     double tol;            /* both solves */
     int64_t max_iter;      /* per solve */
     uint64_t user;         /* caller's tag, returned in the result */
+    double k_half;         /* as lbm_params */
 } lbm_request;
 
 typedef struct {

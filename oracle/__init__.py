@@ -41,10 +41,10 @@ def lib():
             "orc_fluid_fluxes": (I, [I, I, I, I, P, D, P, P, P]),
             "orc_fluid_solve": (I, [I, I, I, I, P, D, D, D, I64, I, I, P, P, P, P]),
             "orc_ad_init": (I, [I, I, I, I, P, D, P, P]),
-            "orc_ad_step": (I, [I, I, I, I, P, D, D, D, I, D, P, P, P, P, P]),
-            "orc_ad_moment": (I, [I, I, I, I, P, D, P, P]),
-            "orc_ad_fluxes": (I, [I, I, I, I, P, D, D, I, D, P, P, P, P]),
-            "orc_ad_solve": (I, [I, I, I, I, P, P, D, D, D, I, D, D, I64, I, I, P, P, P, P]),
+            "orc_ad_step": (I, [I, I, I, I, P, D, D, D, D, I, D, P, P, P, P, P]),
+            "orc_ad_moment": (I, [I, I, I, I, P, D, D, P, P]),
+            "orc_ad_fluxes": (I, [I, I, I, I, P, D, D, D, I, D, P, P, P, P]),
+            "orc_ad_solve": (I, [I, I, I, I, P, P, D, D, D, D, I, D, D, I64, I, I, P, P, P, P]),
             "orc_splitmix64": (None, [U64, I64, P]),
             "orc_geom_discs": (I, [I, I, I, I, D, I, U64, P, P]),
             "orc_geom_fibres": (I, [I, I, I, I, I, D, U64, P, P]),
@@ -54,8 +54,8 @@ def lib():
             "orc_flow_domain": (I, [I, I, I, P, P]),
             "orc_growth_pick": (I64, [I, I, I, P, P, D]),
             "orc_fluid_run": (I, [I, I, I, I, P, D, D, P, P, I64, P, P, P]),
-            "orc_ad_run": (I, [I, I, I, I, P, D, D, D, I, D, P, P, I64, P, P]),
-            "orc_coupled_run": (I, [I, I, I, P, D, D, D, D, D, D, I64, I, I, I, P,
+            "orc_ad_run": (I, [I, I, I, I, P, D, D, D, D, I, D, P, P, I64, P, P]),
+            "orc_coupled_run": (I, [I, I, I, P, D, D, D, D, D, D, D, I64, I, I, I, P,
                                     P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -220,8 +220,10 @@ def ad_init(cls, u, c_init, lat=None):
     return g
 
 
-def ad_step(cls, g, u, D, c_in, k_sink, outlet=0, c_out=0.0, periodic=(0, 0, 0), lat=None):
-    """One step; returns (g_next, C of this step)."""
+def ad_step(cls, g, u, D, c_in, k_sink, outlet=0, c_out=0.0, periodic=(0, 0, 0), lat=None,
+            k_half=0.0):
+    """One step; returns (g_next, C of this step).  k_half > 0 selects the
+    Monod sink k C / (C + k_half) in place of k C."""
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     lat = ad_lattice(nz) if lat is None else lat
@@ -230,11 +232,12 @@ def ad_step(cls, g, u, D, c_in, k_sink, outlet=0, c_out=0.0, periodic=(0, 0, 0),
     C = np.empty(cls.size)
     per = np.asarray(periodic, np.int32)
     lib().orc_ad_step(lat, nx, ny, nz, _p(cls), float(D), float(c_in), float(k_sink),
-                      int(outlet), float(c_out), _p(per), _p(_f64(u)), _p(g), _p(out), _p(C))
+                      float(k_half), int(outlet), float(c_out), _p(per), _p(_f64(u)), _p(g), _p(out), _p(C))
     return out, C
 
 
-def ad_run(cls, g, u, D, c_in, k_sink, nsteps, outlet=0, c_out=0.0, periodic=(0, 0, 0), lat=None):
+def ad_run(cls, g, u, D, c_in, k_sink, nsteps, outlet=0, c_out=0.0, periodic=(0, 0, 0), lat=None,
+           k_half=0.0):
     """nsteps fixed steps from state g (not modified); returns (g, C of the
     last step)."""
     cls = _u8(cls)
@@ -244,31 +247,31 @@ def ad_run(cls, g, u, D, c_in, k_sink, nsteps, outlet=0, c_out=0.0, periodic=(0,
     C = np.zeros(cls.size)
     per = np.asarray(periodic, np.int32)
     lib().orc_ad_run(lat, nx, ny, nz, _p(cls), float(D), float(c_in), float(k_sink),
-                     int(outlet), float(c_out), _p(per), _p(_f64(u)), int(nsteps), _p(g), _p(C))
+                     float(k_half), int(outlet), float(c_out), _p(per), _p(_f64(u)), int(nsteps), _p(g), _p(C))
     return g, C
 
 
-def ad_moment(cls, g, k_sink, lat=None):
+def ad_moment(cls, g, k_sink, lat=None, k_half=0.0):
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     lat = ad_lattice(nz) if lat is None else lat
     C = np.empty(cls.size)
-    lib().orc_ad_moment(lat, nx, ny, nz, _p(cls), float(k_sink), _p(_f64(g)), _p(C))
+    lib().orc_ad_moment(lat, nx, ny, nz, _p(cls), float(k_sink), float(k_half), _p(_f64(g)), _p(C))
     return C
 
 
-def ad_fluxes(cls, g, c_in, k_sink, outlet=0, c_out=0.0, lat=None):
+def ad_fluxes(cls, g, c_in, k_sink, outlet=0, c_out=0.0, lat=None, k_half=0.0):
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     lat = ad_lattice(nz) if lat is None else lat
     a, b, s = ct.c_double(), ct.c_double(), ct.c_double()
-    lib().orc_ad_fluxes(lat, nx, ny, nz, _p(cls), float(c_in), float(k_sink), int(outlet),
+    lib().orc_ad_fluxes(lat, nx, ny, nz, _p(cls), float(c_in), float(k_sink), float(k_half), int(outlet),
                         float(c_out), _p(_f64(g)), ct.byref(a), ct.byref(b), ct.byref(s))
     return a.value, b.value, s.value
 
 
 def ad_solve(cls, u, D, c_in, k_sink, tol, max_iter, outlet=0, c_out=0.0, check_every=100,
-             g=None, lat=None, stall_checks=STALL_CHECKS):
+             g=None, lat=None, stall_checks=STALL_CHECKS, k_half=0.0):
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     lat = ad_lattice(nz) if lat is None else lat
@@ -277,7 +280,8 @@ def ad_solve(cls, u, D, c_in, k_sink, tol, max_iter, outlet=0, c_out=0.0, check_
     C = np.empty(cls.size)
     it, res = ct.c_int64(), ct.c_double()
     st = lib().orc_ad_solve(lat, nx, ny, nz, _p(cls), _p(u), float(D), float(c_in),
-                            float(k_sink), int(outlet), float(c_out), float(tol), int(max_iter),
+                            float(k_sink), float(k_half), int(outlet), float(c_out), float(tol),
+                            int(max_iter),
                             int(check_every), int(stall_checks), _p(g), _p(C), ct.byref(it),
                             ct.byref(res))
     return dict(status=STATUS.get(st, st), iters=it.value, residual=res.value, g=g, C=C)
@@ -346,7 +350,7 @@ def growth_pick(cls, C, xi):
 
 
 def coupled_run(cls, tau, u_in, D, c_in, k_sink, tol, max_iter, xi, check_every=100,
-                stall_checks=STALL_CHECKS):
+                stall_checks=STALL_CHECKS, k_half=0.0):
     cls = _u8(cls).copy()
     nx, ny, nz = _shape(cls.shape)
     xi = _f64(xi)
@@ -359,7 +363,7 @@ def coupled_run(cls, tau, u_in, D, c_in, k_sink, tol, max_iter, xi, check_every=
     U = np.zeros((3 if nz > 1 else 2, cls.size))
     C = np.zeros(cls.size)
     st = lib().orc_coupled_run(nx, ny, nz, _p(cls), float(tau), float(u_in), float(D),
-                               float(c_in), float(k_sink), float(tol), int(max_iter),
+                               float(c_in), float(k_sink), float(k_half), float(tol), int(max_iter),
                                int(check_every), int(stall_checks), M, _p(xi), _p(picked), _p(J), ct.byref(acc),
                                _p(itf), _p(ita), _p(U), _p(C))
     return dict(status=STATUS.get(st, st), cls=cls, picked=picked, J=J, J_accum=acc.value,

@@ -18,7 +18,8 @@
  *     moments [Eqs. 9-10], equilibrium [Eq. 5], BGK relaxation [Eq. 4];
  *   - advection-diffusion BGK step [Sec. 2.1.2, Eqs. 12-13] with the frozen
  *     fluid velocity, zero-flux solids, Dirichlet inlet, zero-gradient or
- *     Dirichlet outlet and a first-order sink on biofilm nodes;
+ *     Dirichlet outlet and a sink on biofilm nodes, first order or of the
+ *     Monod form of the consumption rate (Eq. 13);
  *   - the flow domain: FLUID nodes linked to the outlet column (closed
  *     pores carry no steady flow; reading of Sec. 2.1.1 on the Sec. 3 pore
  *     space);
@@ -198,6 +199,29 @@ static int ad_blocked(uint8_t k) /* substrate: zero flux only at electrode/chass
     return k == ORC_SOLID || k == ORC_WALL;
 }
 static uint8_t *flow_domain(int nx, int ny, int nz, const uint8_t *cls);
+
+/* Substrate consumed in one step by a biofilm node at concentration C.
+ * First order, k C, when k_half <= 0; otherwise the Monod form of the
+ * consumption rate (Eq. 13 with the mediator factor folded into k),
+ * k C / (C + k_half): k is the rate at saturation, k_half the half-
+ * saturation concentration. */
+static double consumed(double C, double k, double k_half)
+{
+    return k_half > 0.0 ? k * C / (C + k_half) : k * C;
+}
+
+/* Concentration C >= 0 before the sink, from the sum s of a biofilm node's
+ * stored populations, s = C - consumed(C).  First order: C = s / (1 - k).
+ * Monod: the positive root of C^2 + b C - s k_half = 0, b = k_half - k - s,
+ * taken in the form that avoids cancellation for either sign of b. */
+static double before_sink(double s, double k, double k_half)
+{
+    if (!(k_half > 0.0))
+        return s / (1.0 - k);
+    double b = k_half - k - s;
+    double disc = sqrt(fmax(b * b + 4.0 * s * k_half, 0.0));
+    return b >= 0.0 ? 2.0 * s * k_half / (b + disc) : (disc - b) / 2.0;
+}
 
 /* Equilibrium of Eq. 5 with c = dx/dt = 1 and W_i/rho0 = w_i (reading: the
  * printed c = dx/(dt*sqrt(3)) is the sound speed; with it the coefficients
@@ -668,13 +692,13 @@ int orc_ad_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  *       Neumann solids (Sec. 2.1.2); biofilm is not blocked for substrate;
  *   (d) otherwise g_i = g*_i(s).
  * Then C = sum g_i (Eq. 13), g_eq = w_i C (1 + c_i.u/c_s^2), and
- * g*_i = g_i - (g_i - g_eq_i)/tau_D - w_i k C, with k = k_sink on BIOFILM
- * nodes and 0 elsewhere: a first-order consumption that removes exactly kC
- * per step at a biofilm node.  tau_D = 1/2 + D/c_s^2 (Table 1's tau_D and D
+ * g*_i = g_i - (g_i - g_eq_i)/tau_D - w_i q, with q = consumed(C) on
+ * BIOFILM nodes (k C, or k C / (C + k_half) for the Monod form) and 0
+ * elsewhere: a biofilm node removes exactly q per step.  tau_D = 1/2 + D/c_s^2 (Table 1's tau_D and D
  * obey this with c_s^2 = 1/3).  If C_out is not NULL it receives C (0 on
  * inactive nodes). */
 int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                double D, double c_in, double k_sink, int outlet_mode,
+                double D, double c_in, double k_sink, double k_half, int outlet_mode,
                 double c_out, const int *periodic, const double *u,
                 const double *g_src, double *g_dst, double *C_out)
 {
@@ -737,13 +761,13 @@ int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             double C = 0.0;
             for (int i = 0; i < L.q; i++)
                 C += g[i];
-            double k = (cls[n] == ORC_BIOFILM) ? k_sink : 0.0;
+            double q = (cls[n] == ORC_BIOFILM) ? consumed(C, k_sink, k_half) : 0.0;
             for (int i = 0; i < L.q; i++) {
                 double cu = 0.0;
                 for (int d = 0; d < L.dim; d++)
                     cu += L.c[i][d] * u[d * N + n];
                 double geq = L.w[i] * C * (1.0 + cu / L.cs2);
-                g_dst[i * N + n] = g[i] - (g[i] - geq) / tau_d - L.w[i] * k * C;
+                g_dst[i * N + n] = g[i] - (g[i] - geq) / tau_d - L.w[i] * q;
             }
             if (C_out)
                 C_out[n] = C;
@@ -755,7 +779,7 @@ int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 /* Concentration of a stored AD state: C = sum g* / (1 - k[biofilm]), which
  * is the pre-collision C of the step that produced the state. */
 int orc_ad_moment(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                  double k_sink, const double *g, double *C)
+                  double k_sink, double k_half, const double *g, double *C)
 {
     orc_lattice L;
     if (make_lattice(lat_id, &L))
@@ -769,8 +793,7 @@ int orc_ad_moment(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         double s = 0.0;
         for (int i = 0; i < L.q; i++)
             s += g[i * N + n];
-        double k = (cls[n] == ORC_BIOFILM) ? k_sink : 0.0;
-        C[n] = s / (1.0 - k);
+        C[n] = (cls[n] == ORC_BIOFILM) ? before_sink(s, k_sink, k_half) : s;
     }
     return ORC_OK;
 }
@@ -778,7 +801,7 @@ int orc_ad_moment(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 /* Substrate crossing inlet and outlet per step and the total consumed by
  * the biofilm sink, on a stored state (ascending n). */
 int orc_ad_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                  double c_in, double k_sink, int outlet_mode, double c_out,
+                  double c_in, double k_sink, double k_half, int outlet_mode, double c_out,
                   const double *g, double *flux_in, double *flux_out,
                   double *sink_total)
 {
@@ -808,7 +831,8 @@ int orc_ad_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             double s = 0.0;
             for (int i = 0; i < L.q; i++)
                 s += g[i * N + n];
-            sink += k_sink * s / (1.0 - k_sink);
+            sink += k_half > 0.0 ? consumed(before_sink(s, k_sink, k_half), k_sink, k_half)
+                                 : k_sink * s / (1.0 - k_sink);
         }
     }
     *flux_in = fin;
@@ -820,7 +844,7 @@ int orc_ad_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 /* AD steady solve from the state in g (cold or warm), in place; residual
  * r = max over active nodes of |C(t) - C(t-1)| / c_in. */
 int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-                 const double *u, double D, double c_in, double k_sink,
+                 const double *u, double D, double c_in, double k_sink, double k_half,
                  int outlet_mode, double c_out, double tol, int64_t max_iter,
                  int check_every, int stall_checks, double *g, double *C,
                  int64_t *iters, double *residual)
@@ -844,10 +868,10 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     int status = ORC_NOT_CONVERGED;
     double r = INFINITY;
     int64_t t = 0;
-    orc_ad_moment(lat_id, nx, ny, nz, cls, k_sink, g, Cprev);
+    orc_ad_moment(lat_id, nx, ny, nz, cls, k_sink, k_half, g, Cprev);
     for (;;) {
         int need_c = (t + 1) % K == 0;
-        orc_ad_step(lat_id, nx, ny, nz, cls, D, c_in, k_sink, outlet_mode,
+        orc_ad_step(lat_id, nx, ny, nz, cls, D, c_in, k_sink, k_half, outlet_mode,
                     c_out, NULL, u, a, b, need_c ? Ccur : NULL);
         double *tmp = a;
         a = b;
@@ -881,7 +905,7 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     }
     if (a != g)
         memcpy(g, a, sizeof(double) * L.q * N);
-    orc_ad_moment(lat_id, nx, ny, nz, cls, k_sink, g, C);
+    orc_ad_moment(lat_id, nx, ny, nz, cls, k_sink, k_half, g, C);
     *iters = t;
     *residual = r;
     free(gb);
@@ -1305,7 +1329,7 @@ int64_t orc_growth_pick(int nx, int ny, int nz, const uint8_t *cls,
  * Per-update picks, sink totals and iteration counts are returned.  cls is
  * updated in place.  2-D (D2Q9 + D2Q5) and 3-D (D3Q19 + D3Q7). */
 int orc_coupled_run(int nx, int ny, int nz, uint8_t *cls, double tau,
-                    double u_in, double D, double c_in, double k_sink,
+                    double u_in, double D, double c_in, double k_sink, double k_half,
                     double tol, int64_t max_iter, int check_every,
                     int stall_checks, int n_updates, const double *xi, int64_t *picked,
                     double *J, double *J_accum, int64_t *iters_fluid,
@@ -1350,7 +1374,7 @@ int orc_coupled_run(int nx, int ny, int nz, uint8_t *cls, double tau,
         }
         if (m == 0)
             orc_ad_init(ad, nx, ny, nz, cls, c_in, U, g);
-        int s2 = orc_ad_solve(ad, nx, ny, nz, cls, U, D, c_in, k_sink, 0, 0.0, tol,
+        int s2 = orc_ad_solve(ad, nx, ny, nz, cls, U, D, c_in, k_sink, k_half, 0, 0.0, tol,
                               max_iter, check_every, stall_checks, g, C, &it, &res);
         iters_ad[m] = it;
         if (s2 < 0) {
@@ -1358,7 +1382,7 @@ int orc_coupled_run(int nx, int ny, int nz, uint8_t *cls, double tau,
             break;
         }
         double fin, fout, sink;
-        orc_ad_fluxes(ad, nx, ny, nz, cls, c_in, k_sink, 0, 0.0, g, &fin, &fout, &sink);
+        orc_ad_fluxes(ad, nx, ny, nz, cls, c_in, k_sink, k_half, 0, 0.0, g, &fin, &fout, &sink);
         J[m] = sink;
         if (m > 0)
             acc += sink;
@@ -1414,7 +1438,7 @@ int orc_fluid_run(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 }
 
 int orc_ad_run(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
-               double D, double c_in, double k_sink, int outlet_mode,
+               double D, double c_in, double k_sink, double k_half, int outlet_mode,
                double c_out, const int *periodic, const double *u,
                int64_t nsteps, double *g, double *C)
 {
@@ -1428,7 +1452,7 @@ int orc_ad_run(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     double *a = g;
     for (int64_t t = 0; t < nsteps; t++) {
         int last = (t == nsteps - 1);
-        orc_ad_step(lat_id, nx, ny, nz, cls, D, c_in, k_sink, outlet_mode, c_out,
+        orc_ad_step(lat_id, nx, ny, nz, cls, D, c_in, k_sink, k_half, outlet_mode, c_out,
                     periodic, u, a, b, last ? C : NULL);
         double *tmp = a;
         a = b;

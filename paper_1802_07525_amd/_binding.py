@@ -38,7 +38,7 @@ class lbm_params(ct.Structure):
     _fields_ = [("tau", ct.c_double), ("u_in", ct.c_double), ("D", ct.c_double),
                 ("c_in", ct.c_double), ("k_sink", ct.c_double), ("outlet", ct.c_int32),
                 ("c_out", ct.c_double), ("storage", ct.c_int32), ("check_every", ct.c_int32),
-                ("stall_checks", ct.c_int32)]
+                ("stall_checks", ct.c_int32), ("k_half", ct.c_double)]
 
 
 class lbm_info(ct.Structure):
@@ -74,7 +74,7 @@ class lbm_request(ct.Structure):
                 ("tau", ct.c_double), ("u_in", ct.c_double), ("D", ct.c_double),
                 ("c_in", ct.c_double), ("k_sink", ct.c_double), ("outlet", ct.c_int32),
                 ("c_out", ct.c_double), ("tol", ct.c_double), ("max_iter", ct.c_int64),
-                ("user", ct.c_uint64)]
+                ("user", ct.c_uint64), ("k_half", ct.c_double)]
 
 
 class lbm_result(ct.Structure):
@@ -324,9 +324,9 @@ def lbm_copy_bandwidth(ctx, nbytes, reps=20):
 
 # --------------------------------------------------------------- solver
 def make_params(tau=0.8, u_in=0.01, D=0.1, c_in=1.0, k_sink=0.0, outlet=LBM_OUT_ZERO_GRADIENT,
-                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=100, stall_checks=0):
+                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=100, stall_checks=0, k_half=0.0):
     return lbm_params(float(tau), float(u_in), float(D), float(c_in), float(k_sink), int(outlet),
-                      float(c_out), int(storage), int(check_every), int(stall_checks))
+                      float(c_out), int(storage), int(check_every), int(stall_checks), float(k_half))
 
 
 def lbm_solver_create(ctx, cls, params):
@@ -514,14 +514,16 @@ def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_ev
 
 def make_request(nx, ny, cls=None, r_min=3, r_max=6, solid_frac=0.3, overlap=1, seed=0, layer=0,
                  tau=0.8, u_in=0.01, D=0.2 / 3, c_in=1.0, k_sink=0.0,
-                 outlet=LBM_OUT_ZERO_GRADIENT, c_out=0.0, tol=1e-6, max_iter=1000000, user=0):
+                 outlet=LBM_OUT_ZERO_GRADIENT, c_out=0.0, tol=1e-6, max_iter=1000000, user=0,
+                 k_half=0.0):
     """Request struct; a given mask is referenced, not copied, until submit
     (the returned pair keeps the array alive)."""
     arr = None if cls is None else _u8(cls)
     r = lbm_request(int(nx), int(ny), None if arr is None else arr.ctypes.data,
                     lbm_disc_params(int(r_min), int(r_max), float(solid_frac), int(overlap)),
                     int(seed), int(layer), float(tau), float(u_in), float(D), float(c_in),
-                    float(k_sink), int(outlet), float(c_out), float(tol), int(max_iter), int(user))
+                    float(k_sink), int(outlet), float(c_out), float(tol), int(max_iter), int(user),
+                    float(k_half))
     return r, arr
 
 

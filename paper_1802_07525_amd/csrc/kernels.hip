@@ -343,6 +343,34 @@ struct CheckAcc {
     }
 };
 
+// ------------------------------------------------------------- the sink
+// Consumption of one step on a BIOFILM node that collides with C: first
+// order k C, or (kh > 0) the Monod form of the consumption rate
+// k C / (C + kh) -- k the rate at saturation, kh the half-saturation
+// concentration (the mediator factor of the double Monod rate is in k).
+template <class T>
+__device__ __forceinline__ T consumption(T c, double k, double kh)
+{
+    return kh > 0.0 ? T(k) * c * recip(c + T(kh)) : T(k) * c;
+}
+__device__ __forceinline__ double consumption(double c, double k, double kh)
+{
+    return kh > 0.0 ? k * c / (c + kh) : k * c;
+}
+
+// The C a BIOFILM node collided with, from the sum s of the populations it
+// stored, s = C - consumption(C): s / (1 - k) for first order; for the Monod
+// form the root C >= 0 of C^2 + b C - s kh = 0, b = kh - k - s, in the form
+// free of cancellation for either sign of b.
+__device__ __forceinline__ double collided_c(double s, double k, double kh)
+{
+    if (!(kh > 0.0))
+        return s / (1.0 - k);
+    const double b = kh - k - s;
+    const double disc = sqrt(fmax(b * b + 4.0 * s * kh, 0.0));
+    return b >= 0.0 ? 2.0 * s * kh / (b + disc) : 0.5 * (disc - b);
+}
+
 // ------------------------------------------------------ population sources
 // Where a node's incoming populations come from.  own(i) is this node's
 // population i; pull(i, o, cx, cy, cz, m) is population i of the pull source
@@ -915,7 +943,7 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
         cs += g[i];
     cfull = S::shifted ? r0 + cs : cs;
     const C om = C(a.omega);
-    const C kc = ((d >> BIO) & DT(1)) ? C(a.k_sink) * cfull : C(0);
+    const C kc = ((d >> BIO) & DT(1)) ? consumption(cfull, a.k_sink, a.k_half) : C(0);
     {
         const C geq = C(L::w[0]) * cs;
         g[0] = g[0] + om * (geq - g[0]) - C(L::w[0]) * kc;
@@ -1206,7 +1234,7 @@ __global__ void __launch_bounds__(256) k_fluid_export(const typename S::T *f, co
 template <class L, int QF, class S, class DT, class O>
 __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, const DT *desc,
                                                     long long N, const float *ref, int nx,
-                                                    double k_sink, O *Cout)
+                                                    Sink sink, O *Cout)
 {
     constexpr int ACT = QF - 1 + L::Q;
     constexpr int BIO = ACT + 1;
@@ -1224,8 +1252,7 @@ __global__ void __launch_bounds__(256) k_ad_export(const typename S::T *gp, cons
         s += static_cast<O>(gp[(long long)i * N + n]);
     if (S::shifted)
         s += O(ref[n % nx]);
-    const O k = ((d >> BIO) & DT(1)) ? O(k_sink) : O(0);
-    Cout[n] = s / (O(1) - k);
+    Cout[n] = ((d >> BIO) & DT(1)) ? O(collided_c((double)s, sink.k, sink.kh)) : s;
 }
 
 template <class L, class S, class DT>
@@ -1309,7 +1336,7 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                                                         const typename S::T *gp, const DT *desc,
                                                         Geo g, const float *ref_f,
                                                         const float *ref_g, double u_in,
-                                                        double c_in, double k_sink, int outlet,
+                                                        double c_in, Sink sink, int outlet,
                                                         double c_out, double *part)
 {
     constexpr int ACT = LF::Q - 1 + LA::Q;
@@ -1377,7 +1404,7 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
 #pragma unroll
                 for (int i = 0; i < LA::Q; ++i)
                     s += static_cast<double>(gp[(long long)i * N + n]) + gs * LA::w[i];
-                acc[4] += k_sink * s / (1.0 - k_sink);
+                acc[4] += sink.kh > 0.0 ? collided_c(s, sink.k, sink.kh) - s : sink.k * s / (1.0 - sink.k);
             }
         }
     }
@@ -1580,6 +1607,7 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
         a.cout_s = sl.cout_s;
         a.c_ref = sl.c_ref;
         a.k_sink = sl.k_sink;
+        a.k_half = sl.k_half;
         a.inv_cin = sl.inv_cin;
         a.outlet = sl.outlet;
         a.streaming_stores = 0;
@@ -1908,7 +1936,7 @@ hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, c
 }
 
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     const float *ref, double k_sink, void *C, int out_double, hipStream_t st)
+                     const float *ref, Sink sink, void *C, int out_double, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
@@ -1920,12 +1948,12 @@ hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, con
             if (out_double)
                 hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, double>), flat_grid(g.N), dim3(256),
                                    0, st, static_cast<const typename S::T *>(gp),
-                                   static_cast<const DT *>(desc), g.N, ref, g.nx, k_sink,
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx, sink,
                                    static_cast<double *>(C));
             else
                 hipLaunchKernelGGL((k_ad_export<LA, LF::Q, S, DT, CT>), flat_grid(g.N), dim3(256), 0,
                                    st, static_cast<const typename S::T *>(gp),
-                                   static_cast<const DT *>(desc), g.N, ref, g.nx, k_sink,
+                                   static_cast<const DT *>(desc), g.N, ref, g.nx, sink,
                                    static_cast<CT *>(C));
             return hipGetLastError();
         });
@@ -2013,7 +2041,7 @@ hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipS
 
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
                   const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
-                  double k_sink, int outlet, double c_out, double *partials, double *out5,
+                  Sink sink, int outlet, double c_out, double *partials, double *out5,
                   hipStream_t st)
 {
     hipError_t e = by_dim(dim, [&](auto lf, auto la, auto dt) {
@@ -2025,7 +2053,7 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
             hipLaunchKernelGGL((k_flux_partials<LF, LA, S, DT>), dim3(FLUX_BLOCKS), dim3(256), 0, st,
                                static_cast<const typename S::T *>(f),
                                static_cast<const typename S::T *>(gp), static_cast<const DT *>(desc),
-                               g, ref_f, ref_g, u_in, c_in, k_sink, outlet, c_out, partials);
+                               g, ref_f, ref_g, u_in, c_in, sink, outlet, c_out, partials);
             return hipGetLastError();
         });
     });

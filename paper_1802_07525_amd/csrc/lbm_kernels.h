@@ -105,7 +105,8 @@ struct AdArgs {
     double cin_s;   // c_in - shift reference (0 reference when unshifted)
     double cout_s;  // c_out - shift reference
     double c_ref;   // shift reference (0 when unshifted)
-    double k_sink;
+    double k_sink;  // consumption on BIOFILM: k_sink C, or k_sink C / (C + k_half)
+    double k_half;  // Monod half-saturation concentration (0: first order)
     double inv_cin; // 1 / (K |c_in|): residual scale
     int outlet;     // 0 zero-gradient, 1 Dirichlet
     int streaming_stores; // 1: non-temporal population stores (large domains)
@@ -153,9 +154,16 @@ hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void 
 // output type (double, else the compute type); RHO may be null.
 hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, const Geo &g,
                         const float *ref, void *U, void *RHO, int out_double, hipStream_t st);
-// Concentration of a stored substrate state (double, or the compute type).
+// Consumption on BIOFILM nodes per step: k C (first order, kh = 0) or the
+// Monod form k C / (C + kh), C the concentration the step collides with.
+struct Sink {
+    double k, kh;
+};
+
+// Concentration of a stored substrate state (double, or the compute type):
+// the concentration of the step that produced it (the sink inverted).
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
-                     const float *ref, double k_sink, void *C, int out_double, hipStream_t st);
+                     const float *ref, Sink sink, void *C, int out_double, hipStream_t st);
 
 // Stored populations <-> unshifted double [Q][N] (0 on inactive nodes).
 hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
@@ -174,7 +182,7 @@ hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g
 enum { FLUX_BLOCKS = 512 };
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
                   const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
-                  double k_sink, int outlet, double c_out, double *partials, double *out5,
+                  Sink sink, int outlet, double c_out, double *partials, double *out5,
                   hipStream_t st);
 
 // part: device scratch of 2 * nparts words for the per-block check maxima
@@ -202,7 +210,7 @@ struct SrvSlot {
     float *ref_cur, *ref_next; // column references [nx] of the current phase
     Geo g;
     double omega_f, u_in, inv_uin;
-    double omega_a, cin_s, cout_s, c_ref, k_sink, inv_cin;
+    double omega_a, cin_s, cout_s, c_ref, k_sink, k_half, inv_cin;
     double c_in, c_out;
     int outlet;
     int phase;        // SRV_*

@@ -321,6 +321,10 @@ std::string request_problem(const lbm_request &r)
         return "c_in must be finite and nonzero";
     if (!(r.k_sink >= 0.0 && r.k_sink < 1.0))
         return "k_sink must be in [0, 1)";
+    if (!(r.k_half >= 0.0) || !isfinite(r.k_half))
+        return "k_half must be finite and >= 0";
+    if (r.k_half > 0.0 && !(r.k_sink < r.k_half))
+        return "the Monod sink needs k_sink < k_half";
     if (r.outlet != LBM_OUT_ZERO_GRADIENT && r.outlet != LBM_OUT_DIRICHLET)
         return "unknown outlet mode";
     if (!isfinite(r.c_out))
@@ -500,6 +504,7 @@ struct lbm_server {
         s.cout_s = r.c_out - c_ref;
         s.c_ref = c_ref;
         s.k_sink = r.k_sink;
+        s.k_half = r.k_half;
         s.inv_cin = 1.0 / ((double)K * fabs(r.c_in));
         s.c_in = r.c_in;
         s.c_out = r.c_out;
@@ -565,7 +570,7 @@ struct lbm_server {
         float *ref = reinterpret_cast<float *>(base + j->lay.ref);
         if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, ref, u, nullptr, 0, stream)) != hipSuccess)
             return e;
-        if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, ref, nullptr, r.u_in, r.c_in, r.k_sink,
+        if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, ref, nullptr, r.u_in, r.c_in, lbmk::Sink{r.k_sink, r.k_half},
                               r.outlet, r.c_out, d_partials, d_out + 10 * j->sid, stream)) != hipSuccess)
             return e;
         if (j->st_fluid == LBM_EDIVERGED)
@@ -575,7 +580,7 @@ struct lbm_server {
             return e;
         if ((e = lbmk::ad_init(2, storage, f0, desc, u, j->geo, r.c_in, c_ref, stream)) != hipSuccess)
             return e;
-        if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, r.k_sink, prev, 0, stream)) !=
+        if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, lbmk::Sink{r.k_sink, r.k_half}, prev, 0, stream)) !=
             hipSuccess)
             return e;
         if ((e = lbmk::ctrl_reset(d_ctrl + j->sid, r.tol, window, 0, K, nullptr, 0, stream, j->t_max)) !=
@@ -604,11 +609,11 @@ struct lbm_server {
         float *ref = reinterpret_cast<float *>(base + j->lay.ref);
         double *out = d_out + 10 * j->sid;
         if (j->ad_ran) {
-            if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, r.k_sink, prev, 0, stream)) !=
+            if ((e = lbmk::ad_export(2, storage, f0, desc, j->geo, ref, lbmk::Sink{r.k_sink, r.k_half}, prev, 0, stream)) !=
                 hipSuccess)
                 return e;
             if ((e = lbmk::fluxes(2, storage, nullptr, f0, desc, j->geo, nullptr, ref, r.u_in, r.c_in,
-                                  r.k_sink, r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
+                                  lbmk::Sink{r.k_sink, r.k_half}, r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
                 return e;
         } else if ((e = hipMemsetAsync(prev, 0, (size_t)N * 4, stream)) != hipSuccess) {
             return e;

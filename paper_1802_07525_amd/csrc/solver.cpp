@@ -56,6 +56,10 @@ lbm_status validate_params(lbm_ctx *ctx, const lbm_params &p)
         return set_err(ctx, LBM_EINVAL, "c_in must be finite and nonzero");
     if (!(p.k_sink >= 0.0 && p.k_sink < 1.0))
         return set_err(ctx, LBM_EINVAL, "k_sink must be in [0, 1)");
+    if (!(p.k_half >= 0.0) || !isfinite(p.k_half))
+        return set_err(ctx, LBM_EINVAL, "k_half must be finite and >= 0");
+    if (p.k_half > 0.0 && !(p.k_sink < p.k_half))
+        return set_err(ctx, LBM_EINVAL, "the Monod sink needs k_sink < k_half (a node never loses all it holds)");
     if (p.outlet != LBM_OUT_ZERO_GRADIENT && p.outlet != LBM_OUT_DIRICHLET)
         return set_err(ctx, LBM_EINVAL, "unknown outlet mode");
     if (!isfinite(p.c_out))
@@ -211,6 +215,7 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.cout_s = s->p.c_out - s->c_ref;
     a.c_ref = s->c_ref;
     a.k_sink = s->p.k_sink;
+    a.k_half = s->p.k_half;
     a.inv_cin = 1.0 / ((double)s->p.check_every * fabs(s->p.c_in));
     a.outlet = s->p.outlet;
     a.streaming_stores = 2.0 * s->qa * (double)s->geo.N * sbytes(s) > STREAMING_BYTES;
@@ -256,7 +261,7 @@ lbm_status fill_fluxes(lbm_solver *s, double *out5)
 {
     HIPCHK(lbmk::fluxes(s->dim, s->p.storage, s->fluid_ready ? s->d_f[s->fcur] : nullptr,
                         s->ad_ready ? s->d_g[s->gcur] : nullptr, s->d_desc, s->geo, ref_cur(s, 0),
-                        ref_cur(s, 1), s->p.u_in, s->p.c_in, s->p.k_sink, s->p.outlet, s->p.c_out,
+                        ref_cur(s, 1), s->p.u_in, s->p.c_in, lbmk::Sink{s->p.k_sink, s->p.k_half}, s->p.outlet, s->p.c_out,
                         s->d_partials,
                         s->d_out5, s->ctx->stream),
            "fluxes");
@@ -306,7 +311,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                "residual reference");
     else
         HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[cur0], s->d_desc, s->geo, ref_cur(s, 1),
-                               s->p.k_sink, s->d_cprev, 0, stream),
+                               lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_cprev, 0, stream),
                "residual reference");
     const auto t0 = std::chrono::steady_clock::now();
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
@@ -432,7 +437,7 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         if ((e = ensure_stage(s, N * 8)))
             return e;
         HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->geo, ref_cur(s, 1),
-                               s->p.k_sink, s->d_stage, 1, st),
+                               lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_stage, 1, st),
                "export");
         HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, hipMemcpyDeviceToHost, st), "copy");
         break;
@@ -478,7 +483,7 @@ struct StateHeader {
     char magic[8];
     int32_t nx, ny, nz, storage;
     int32_t qf, qa, fluid_ready, ad_ready;
-    double tau, u_in, D, c_in, k_sink, c_out;
+    double tau, u_in, D, c_in, k_sink, c_out, k_half;
     int32_t outlet, check_every;
     int64_t N;
     uint64_t f_bytes, g_bytes, u_bytes, ref_bytes;
@@ -939,7 +944,7 @@ lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
     const size_t N = (size_t)s->geo.N;
     StateHeader h;
     memset(&h, 0, sizeof(h));
-    memcpy(h.magic, "LBMSTAT3", 8);
+    memcpy(h.magic, "LBMSTAT4", 8);
     h.nx = s->grid.nx;
     h.ny = s->grid.ny;
     h.nz = s->grid.nz;
@@ -953,6 +958,7 @@ lbm_status lbm_solver_get_state(lbm_solver *s, void *dst, size_t bytes)
     h.D = s->p.D;
     h.c_in = s->p.c_in;
     h.k_sink = s->p.k_sink;
+    h.k_half = s->p.k_half;
     h.c_out = s->p.c_out;
     h.outlet = s->p.outlet;
     h.check_every = s->p.check_every;
@@ -992,7 +998,7 @@ lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
         return LBM_EINVAL;
     StateHeader h;
     memcpy(&h, src, sizeof(h));
-    if (memcmp(h.magic, "LBMSTAT3", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
+    if (memcmp(h.magic, "LBMSTAT4", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
         h.nz != s->grid.nz || h.storage != s->p.storage || bytes < state_size(s))
         return set_err(s->ctx, LBM_EINVAL, "checkpoint does not match this solver");
     const size_t N = (size_t)s->geo.N;

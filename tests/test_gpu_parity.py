@@ -365,3 +365,54 @@ def test_incremental_descriptors_match_fresh_build(gpu_lib):
                 assert np.array_equal(got, want), (t, np.flatnonzero(got != want)[:10])
                 assert np.array_equal(got & 1, O.flow_domain(cur.reshape(cls.shape)).ravel())
     print("updates applied", 60 - refused, "refused", refused, flush=True)
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32S, FP16S], ids=NAMES.get)
+def test_ad_fixed_steps_monod(gpu_lib, storage):
+    """Monod form of the consumption rate (k C / (C + K) on biofilm): fixed
+    steps against the oracle, populations and the concentration recovered
+    from the stored state (the sink inverted)."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    k, K = 5e-3, 0.5
+    _, U, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], 400)
+    with _solver(lbm, cls, w, storage, k_sink=k, k_half=K) as s:
+        assert s and lbm.lbm_solver_set_u(s.h, U) == 0
+        g_or = O.ad_init(cls, U, w["c_in"])
+        done = 0
+        for n in (1, 10, 200):
+            st, _ = s.steps(lbm.LBM_SOLVER_AD, n - done, cold=(done == 0))
+            assert st == 0, s.error()
+            g_or, _ = O.ad_run(cls, g_or, U, w["D"], w["c_in"], k, n - done, k_half=K)
+            done = n
+            G = s.get(lbm.LBM_FIELD_G)
+            C = s.get(lbm.LBM_FIELD_C)
+            C_or = O.ad_moment(cls, g_or, k, k_half=K)
+            assert _pop_ok(storage, G, g_or, act, n), (n, rel_l2(G, g_or, act))
+            assert rel_l2(C, C_or, act) < FIELD_TOL[storage], (n, rel_l2(C, C_or, act))
+
+
+def test_monod_steady_sink_matches_oracle(gpu_lib):
+    """FP64 steady substrate solve with the Monod sink: iteration count,
+    consumed flux and the balance inflow - outflow = consumption."""
+    lbm = gpu_lib
+    w = inputs.scaled(C1, 96, 40, r_min=2, r_max=4, solid=0.2, seed=5, tau=0.8, u_in=0.02,
+                      D=0.1, k=5e-3)
+    cls = masks(w, lbm)
+    K = 0.3
+    with _solver(lbm, cls, w, FP64, k_half=K) as s:
+        st, fi = s.fluid(1e-9, 100000)
+        assert st == 0, s.error()
+        st, ai = s.ad(1e-11, 200000)
+        assert st == 0, s.error()
+        assert abs(ai["flux_in"] - ai["flux_out"] - ai["sink_total"]) / ai["sink_total"] < 1e-6
+        C = s.get(lbm.LBM_FIELD_C)
+    fo = O.fluid_solve(cls, w["tau"], w["u_in"], 1e-9, 100000)
+    ao = O.ad_solve(cls, fo["U"], w["D"], w["c_in"], w["k"], 1e-11, 200000, k_half=K)
+    _, _, sink = O.ad_fluxes(cls, ao["g"], w["c_in"], w["k"], k_half=K)
+    assert ao["iters"] == ai["iters"]
+    assert abs(ai["sink_total"] - sink) / sink < 1e-8
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    assert np.abs(C - ao["C"])[act].max() < 1e-9

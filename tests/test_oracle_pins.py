@@ -195,6 +195,65 @@ def test_ad_closed_box_sink_removes_exactly_kC():
         g = g2
 
 
+def test_ad_closed_box_monod_sink_removes_exactly_q():
+    """The Monod form of the consumption rate (Eq. 13, mediator factor in
+    k): in a periodic box each step removes sum over biofilm nodes of
+    k C / (C + K), C the concentration the step collides with."""
+    cls = O.biofilm_layer(_porous(48, 24, 3))
+    nx, ny = 48, 24
+    rng = np.random.default_rng(2)
+    u = np.zeros((2, nx * ny))
+    u[0] = 0.02 * (cls.ravel() == O.FLUID)
+    g = O.ad_init(cls, u, 1.0) * (1.0 + 0.1 * rng.random((5, nx * ny)))
+    k, K = 3e-3, 0.4
+    bf = cls.ravel() == O.BIOFILM
+    for _ in range(5):
+        g2, C = O.ad_step(cls, g, u, 0.05, 1.0, k, periodic=(1, 0, 0), k_half=K)
+        dM = g2.sum() - g.sum()
+        q = k * C[bf] / (C[bf] + K)
+        assert abs(dM - (-q.sum())) < 1e-13 * g.sum()
+        g = g2
+
+
+def test_monod_uniform_biofilm_decay_recurrence():
+    """A closed, uniform biofilm-filled box at rest: C follows
+    C <- C - k C / (C + K) exactly, and each stored state gives back the
+    concentration of the step that produced it (the sink is inverted)."""
+    nx, ny = 12, 8
+    cls = np.full((ny, nx), O.BIOFILM, np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    u = np.zeros((2, nx * ny))
+    g = O.ad_init(cls, u, 2.0)
+    k, K = 0.02, 0.7
+    act = cls.ravel() == O.BIOFILM
+    c = 2.0
+    for _ in range(60):
+        g, C = O.ad_step(cls, g, u, 0.1, 2.0, k, periodic=(1, 0, 0), k_half=K)
+        assert np.abs(C[act] - c).max() < 1e-13 * c
+        Cm = O.ad_moment(cls, g, k, k_half=K)
+        assert np.abs(Cm[act] - c).max() < 1e-13 * c
+        c = c - k * c / (c + K)
+    assert c < 1.2    # the decay did happen
+
+
+def test_monod_tends_to_first_order():
+    """K -> infinity with k / K fixed: the Monod sink tends to the first-
+    order sink with rate k / K, the gap shrinking like C / K."""
+    cls = O.biofilm_layer(_porous(40, 20, 5))
+    nx, ny = 40, 20
+    u = np.zeros((2, nx * ny))
+    u[0] = 0.01 * (cls.ravel() == O.FLUID)
+    r = 2e-3
+    g1, _ = O.ad_run(cls, O.ad_init(cls, u, 1.0), u, 0.05, 1.0, r, 300)
+    gaps = []
+    for K in (10.0, 100.0, 1000.0):
+        gm, _ = O.ad_run(cls, O.ad_init(cls, u, 1.0), u, 0.05, 1.0, r * K, 300, k_half=K)
+        gaps.append(np.abs(gm - g1).max())
+    assert gaps[0] > gaps[1] > gaps[2]
+    assert gaps[1] / gaps[0] < 0.15 and gaps[2] / gaps[1] < 0.15
+
+
 def _gauss_setup(nx, ny, tau, ux, s0, x0, y0):
     X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
     C0 = np.exp(-((X - x0) ** 2 + (Y - y0) ** 2) / (2 * s0 ** 2)).ravel()
