@@ -43,7 +43,7 @@ def lib():
             "orc_ad_init": (I, [I, I, I, I, P, D, P, P]),
             "orc_ad_step": (I, [I, I, I, I, P, D, D, D, D, I, D, P, P, P, P, P]),
             "orc_ad_moment": (I, [I, I, I, I, P, D, D, P, P]),
-            "orc_ad_fluxes": (I, [I, I, I, I, P, D, D, D, I, D, P, P, P, P]),
+            "orc_ad_fluxes": (I, [I, I, I, I, P, D, D, D, I, D, P, P, P, P, P]),
             "orc_ad_solve": (I, [I, I, I, I, P, P, D, D, D, D, I, D, D, I64, I, I, P, P, P, P]),
             "orc_splitmix64": (None, [U64, I64, P]),
             "orc_geom_discs": (I, [I, I, I, I, D, I, U64, P, P]),
@@ -55,7 +55,7 @@ def lib():
             "orc_growth_pick": (I64, [I, I, I, P, P, D]),
             "orc_fluid_run": (I, [I, I, I, I, P, D, D, P, P, I64, P, P, P]),
             "orc_ad_run": (I, [I, I, I, I, P, D, D, D, D, I, D, P, P, I64, P, P]),
-            "orc_coupled_run": (I, [I, I, I, P, D, D, D, D, D, D, D, I64, I, I, I, P,
+            "orc_coupled_run": (I, [I, I, I, P, D, D, D, D, D, D, I, D, I64, I, I, I, P,
                                     P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -260,13 +260,17 @@ def ad_moment(cls, g, k_sink, lat=None, k_half=0.0):
     return C
 
 
-def ad_fluxes(cls, g, c_in, k_sink, outlet=0, c_out=0.0, lat=None, k_half=0.0):
+def ad_fluxes(cls, g, c_in, k_sink, outlet=0, c_out=0.0, lat=None, k_half=0.0, u=None):
+    """Inflow, outflow and consumption per step of a stored substrate state.
+    u (the frozen velocity) enters the Dirichlet faces of the second-order
+    form; None is u = 0."""
     cls = _u8(cls)
     nx, ny, nz = _shape(cls.shape)
     lat = ad_lattice(nz) if lat is None else lat
     a, b, s = ct.c_double(), ct.c_double(), ct.c_double()
     lib().orc_ad_fluxes(lat, nx, ny, nz, _p(cls), float(c_in), float(k_sink), float(k_half), int(outlet),
-                        float(c_out), _p(_f64(g)), ct.byref(a), ct.byref(b), ct.byref(s))
+                        float(c_out), None if u is None else _p(_f64(u)), _p(_f64(g)), ct.byref(a),
+                        ct.byref(b), ct.byref(s))
     return a.value, b.value, s.value
 
 
@@ -350,7 +354,7 @@ def growth_pick(cls, C, xi):
 
 
 def coupled_run(cls, tau, u_in, D, c_in, k_sink, tol, max_iter, xi, check_every=100,
-                stall_checks=STALL_CHECKS, k_half=0.0):
+                stall_checks=STALL_CHECKS, k_half=0.0, lat_ad=None):
     cls = _u8(cls).copy()
     nx, ny, nz = _shape(cls.shape)
     xi = _f64(xi)
@@ -363,7 +367,8 @@ def coupled_run(cls, tau, u_in, D, c_in, k_sink, tol, max_iter, xi, check_every=
     U = np.zeros((3 if nz > 1 else 2, cls.size))
     C = np.zeros(cls.size)
     st = lib().orc_coupled_run(nx, ny, nz, _p(cls), float(tau), float(u_in), float(D),
-                               float(c_in), float(k_sink), float(k_half), float(tol), int(max_iter),
+                               float(c_in), float(k_sink), float(k_half),
+                               -1 if lat_ad is None else int(lat_ad), float(tol), int(max_iter),
                                int(check_every), int(stall_checks), M, _p(xi), _p(picked), _p(J), ct.byref(acc),
                                _p(itf), _p(ita), _p(U), _p(C))
     return dict(status=STATUS.get(st, st), cls=cls, picked=picked, J=J, J_accum=acc.value,

@@ -246,16 +246,47 @@ void orc_feq(int lat_id, double rho, const double *u, double *feq)
  * Reading: the paper's AD equilibrium is "as Eq. 5"; on the D2Q5/D3Q7
  * lattices the second-order terms have no isotropic closure, so the
  * standard linear form is used. */
+/* Substrate equilibrium of direction i at concentration C and velocity u
+ * (u[3]).  On the lattices with diagonal directions (D2Q9, D3Q19) it is
+ * Eq. 5 with the concentration in place of the density -- the paper's
+ * substrate LBM on D2Q9 (Sec. 2.1.2 computes G^(0) "as in Eq. 5"):
+ * w_i C (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2).  On D2Q5 and D3Q7 it is the
+ * linear w_i C (1 + c.u / c_s^2): their weights are not isotropic enough for
+ * the second-order terms. */
+static double ad_eq(const orc_lattice *L, int i, double C, const double *u)
+{
+    double cu = 0.0, uu = 0.0;
+    for (int d = 0; d < 3; d++) {
+        cu += L->c[i][d] * u[d];
+        uu += u[d] * u[d];
+    }
+    if (L->q == 9 || L->q == 19)
+        return L->w[i] * C * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    return L->w[i] * C * (1.0 + cu / L->cs2);
+}
+
+/* Even part of that equilibrium, (g_eq_i + g_eq_opp(i)) / 2, written out:
+ * w_i C (1 + 9/2 (c.u)^2 - 3/2 u^2), or w_i C for the linear form.  Anti-
+ * bounce-back imposes twice it at a Dirichlet face. */
+static double ad_eq_even(const orc_lattice *L, int i, double C, const double *u)
+{
+    if (L->q == 9 || L->q == 19) {
+        double cu = 0.0, uu = 0.0;
+        for (int d = 0; d < 3; d++) {
+            cu += L->c[i][d] * u[d];
+            uu += u[d] * u[d];
+        }
+        return L->w[i] * C * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+    }
+    return L->w[i] * C;
+}
+
 void orc_geq(int lat_id, double C, const double *u, double *geq)
 {
     orc_lattice L;
     make_lattice(lat_id, &L);
-    for (int i = 0; i < L.q; i++) {
-        double cu = 0.0;
-        for (int d = 0; d < 3; d++)
-            cu += L.c[i][d] * u[d];
-        geq[i] = L.w[i] * C * (1.0 + cu / L.cs2);
-    }
+    for (int i = 0; i < L.q; i++)
+        geq[i] = ad_eq(&L, i, C, u);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -668,12 +699,11 @@ int orc_ad_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
     const int64_t N = (int64_t)nx * ny * nz;
     for (int64_t n = 0; n < N; n++) {
         int active = !ad_blocked(cls[n]);
-        for (int i = 0; i < L.q; i++) {
-            double cu = 0.0;
-            for (int d = 0; d < L.dim; d++)
-                cu += L.c[i][d] * u[d * N + n];
-            g[i * N + n] = active ? L.w[i] * c_init * (1.0 + cu / L.cs2) : 0.0;
-        }
+        double un[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < L.dim; d++)
+            un[d] = u[d * N + n];
+        for (int i = 0; i < L.q; i++)
+            g[i * N + n] = active ? ad_eq(&L, i, c_init, un) : 0.0;
     }
     return ORC_OK;
 }
@@ -682,16 +712,17 @@ int orc_ad_init(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  * u is the frozen fluid velocity [dim][N] (Sec. 2.1.2: constant during the
  * AD solve, taken from the fluid LBM).  For every active node n (FLUID or
  * BIOFILM) and direction i, s = n - c_i:
- *   (a) s left of column 0: g_i = -g*_opp(n) + 2 w_i c_in -- anti-bounce-
- *       back, i.e. concentration c_in imposed half a cell before the first
- *       column (the Dirichlet input of Sec. 2.1.2);
+ *   (a) s left of column 0: g_i = -g*_opp(n) + 2 E_i(c_in, u(n)) -- anti-
+ *       bounce-back, i.e. concentration c_in imposed half a cell before the
+ *       first column (the Dirichlet input of Sec. 2.1.2); E_i is the even
+ *       part of the equilibrium (w_i c_in on D2Q5/D3Q7);
  *   (b) s right of column nx-1: zero-gradient outlet g_i = g*_i(n)
  *       (outlet_mode 0; the paper gives no output value), or Dirichlet
- *       g_i = -g*_opp(n) + 2 w_i c_out (outlet_mode 1);
+ *       g_i = -g*_opp(n) + 2 E_i(c_out, u(n)) (outlet_mode 1);
  *   (c) s electrode/chassis or outside in y/z: g_i = g*_opp(n) -- zero-flux
  *       Neumann solids (Sec. 2.1.2); biofilm is not blocked for substrate;
  *   (d) otherwise g_i = g*_i(s).
- * Then C = sum g_i (Eq. 13), g_eq = w_i C (1 + c_i.u/c_s^2), and
+ * Then C = sum g_i (Eq. 13), g_eq_i = ad_eq(i, C, u) (above), and
  * g*_i = g_i - (g_i - g_eq_i)/tau_D - w_i q, with q = consumed(C) on
  * BIOFILM nodes (k C, or k C / (C + k_half) for the Monod form) and 0
  * elsewhere: a biofilm node removes exactly q per step.  tau_D = 1/2 + D/c_s^2 (Table 1's tau_D and D
@@ -726,6 +757,9 @@ int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
             }
             double g[ORC_MAXQ];
             int pos[3] = {x, y, z};
+            double un[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < L.dim; d++)
+                un[d] = u[d * N + n];
             for (int i = 0; i < L.q; i++) {
                 int s[3];
                 int outside = 0;
@@ -742,10 +776,10 @@ int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                 }
                 int o = L.opp[i];
                 if (outside == 1) {
-                    g[i] = -g_src[o * N + n] + 2.0 * L.w[i] * c_in;
+                    g[i] = -g_src[o * N + n] + 2.0 * ad_eq_even(&L, i, c_in, un);
                 } else if (outside == 2) {
                     if (outlet_mode == 1)
-                        g[i] = -g_src[o * N + n] + 2.0 * L.w[i] * c_out;
+                        g[i] = -g_src[o * N + n] + 2.0 * ad_eq_even(&L, i, c_out, un);
                     else
                         g[i] = g_src[i * N + n];
                 } else if (outside == 3) {
@@ -763,10 +797,7 @@ int orc_ad_step(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                 C += g[i];
             double q = (cls[n] == ORC_BIOFILM) ? consumed(C, k_sink, k_half) : 0.0;
             for (int i = 0; i < L.q; i++) {
-                double cu = 0.0;
-                for (int d = 0; d < L.dim; d++)
-                    cu += L.c[i][d] * u[d * N + n];
-                double geq = L.w[i] * C * (1.0 + cu / L.cs2);
+                double geq = ad_eq(&L, i, C, un);
                 g_dst[i * N + n] = g[i] - (g[i] - geq) / tau_d - L.w[i] * q;
             }
             if (C_out)
@@ -802,7 +833,7 @@ int orc_ad_moment(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
  * the biofilm sink, on a stored state (ascending n). */
 int orc_ad_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
                   double c_in, double k_sink, double k_half, int outlet_mode, double c_out,
-                  const double *g, double *flux_in, double *flux_out,
+                  const double *u, const double *g, double *flux_in, double *flux_out,
                   double *sink_total)
 {
     orc_lattice L;
@@ -814,15 +845,18 @@ int orc_ad_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
         if (ad_blocked(cls[n]))
             continue;
         int x = (int)(n % nx);
+        double un[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; u && d < L.dim; d++)
+            un[d] = u[d * N + n];
         for (int i = 0; i < L.q; i++) {
             int o = L.opp[i];
             if (x == 0 && L.c[i][0] == 1) {
-                double incoming = -g[o * N + n] + 2.0 * L.w[i] * c_in;
+                double incoming = -g[o * N + n] + 2.0 * ad_eq_even(&L, i, c_in, un);
                 fin += incoming - g[o * N + n];
             }
             if (x == nx - 1 && L.c[i][0] == -1) {
                 double incoming = (outlet_mode == 1)
-                                      ? -g[o * N + n] + 2.0 * L.w[i] * c_out
+                                      ? -g[o * N + n] + 2.0 * ad_eq_even(&L, i, c_out, un)
                                       : g[i * N + n];
                 fout += g[o * N + n] - incoming;
             }
@@ -1330,12 +1364,13 @@ int64_t orc_growth_pick(int nx, int ny, int nz, const uint8_t *cls,
  * updated in place.  2-D (D2Q9 + D2Q5) and 3-D (D3Q19 + D3Q7). */
 int orc_coupled_run(int nx, int ny, int nz, uint8_t *cls, double tau,
                     double u_in, double D, double c_in, double k_sink, double k_half,
-                    double tol, int64_t max_iter, int check_every,
+                    int ad_lat, double tol, int64_t max_iter, int check_every,
                     int stall_checks, int n_updates, const double *xi, int64_t *picked,
                     double *J, double *J_accum, int64_t *iters_fluid,
                     int64_t *iters_ad, double *U_out, double *C_out)
 {
-    int fl = nz > 1 ? ORC_D3Q19 : ORC_D2Q9, ad = nz > 1 ? ORC_D3Q7 : ORC_D2Q5;
+    int fl = nz > 1 ? ORC_D3Q19 : ORC_D2Q9;
+    int ad = ad_lat >= 0 ? ad_lat : (nz > 1 ? ORC_D3Q7 : ORC_D2Q5);
     orc_lattice Lf, La;
     make_lattice(fl, &Lf);
     make_lattice(ad, &La);
@@ -1382,7 +1417,7 @@ int orc_coupled_run(int nx, int ny, int nz, uint8_t *cls, double tau,
             break;
         }
         double fin, fout, sink;
-        orc_ad_fluxes(ad, nx, ny, nz, cls, c_in, k_sink, k_half, 0, 0.0, g, &fin, &fout, &sink);
+        orc_ad_fluxes(ad, nx, ny, nz, cls, c_in, k_sink, k_half, 0, 0.0, U, g, &fin, &fout, &sink);
         J[m] = sink;
         if (m > 0)
             acc += sink;

@@ -81,6 +81,20 @@ def test_ad_equilibrium_moments(lat):
     assert np.abs((c * g[:, None]).sum(0) - 0.7 * u).max() < 1e-16
 
 
+def test_ad_second_order_equilibrium_moments():
+    """D2Q9 substrate equilibrium (Eq. 5 with C for rho): zeroth, first and
+    second moments C, C u and C (c_s^2 I + u u)."""
+    c, w, opp, cs2 = O.lattice_tables(O.D2Q9)
+    u = np.array([0.04, -0.025, 0.0])
+    C = 0.7
+    g = O.geq(O.D2Q9, C, u)
+    assert abs(g.sum() - C) < 1e-15
+    assert np.abs((c * g[:, None]).sum(0) - C * u).max() < 1e-16
+    Pi = np.einsum("ia,ib,i->ab", c[:, :2].astype(float), c[:, :2].astype(float), g)
+    want = C * (cs2 * np.eye(2) + np.outer(u[:2], u[:2]))
+    assert np.abs(Pi - want).max() < 1e-15
+
+
 def test_table1_tau_d_and_diffusivity_consistent():
     """Table 1: tau_D = 0.5036 and D = 0.0012 mm^2/s satisfy
     D = c_s^2 (tau_D - 1/2) dx^2/dt with the oracle's D2Q5 c_s^2 = 1/3,
@@ -284,6 +298,51 @@ def test_gaussian_pulse_exact_moment_recurrences():
                     + (cs2 - ux ** 2) * M0 for t in range(T))
     V = (X * X * C).sum() - (X * C).sum() ** 2 / M
     assert abs(V - pred) / pred < 1e-11
+
+
+def test_gaussian_pulse_second_order_exact_recurrences():
+    """D2Q9 substrate with the Eq. 5 equilibrium, uniform u, started at
+    equilibrium.  Totals over the box obey a closed linear map: the
+    centroid moves exactly u per step, and with d = Q - u M1 (Q = sum x
+    c_x g) the central second moment V obeys
+        V(t+1) - V(t) = 2 (1-w) d_t + P_eq - M u^2,
+        d_(t+1) = (1-w) d_t + P_eq - M u^2,  d_0 = 0,
+    where P_eq = sum c_x^2 g_eq = M (c_s^2 + u^2) for this equilibrium
+    (M c_s^2 for the linear form).  So the variance grows by exactly
+    2 M D per step in the long run: no -u^2 numerical diffusion."""
+    # a box large enough that the periodic images stay below round-off
+    nx, ny, tau, ux, T = 300, 160, 0.8, 0.05, 300
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    X, Y = X.ravel(), Y.ravel()
+    C0 = np.exp(-((X - 80.0) ** 2 + (Y - 80.0) ** 2) / (2 * 6.0 ** 2))
+    c, w, opp, cs2 = O.lattice_tables(O.D2Q9)
+    cu = c[:, 0] * ux
+    g = np.array([w[i] * C0 * (1 + 3 * cu[i] + 4.5 * cu[i] ** 2 - 1.5 * ux ** 2) for i in range(9)])
+    u = np.zeros((2, nx * ny))
+    u[0] = ux
+    D = (tau - 0.5) * cs2
+    _, C = O.ad_run(np.zeros((ny, nx), np.uint8), g, u, D, 1.0, 0.0, T, periodic=(1, 1, 0),
+                    lat=O.D2Q9)
+    M0, M = C0.sum(), C.sum()
+    assert abs(M - M0) / M0 < 1e-13
+    X0 = (X * C0).sum() / M0
+    assert abs((X * C).sum() / M - X0 - ux * T) < 1e-10
+    om = 1.0 / tau
+    V = (X * X * C0).sum() - (X * C0).sum() ** 2 / M0
+    d = 0.0
+    for _ in range(T):
+        V += 2 * (1 - om) * d + M0 * cs2
+        d = (1 - om) * d + M0 * cs2
+    Vg = (X * X * C).sum() - (X * C).sum() ** 2 / M
+    assert abs(Vg - V) / V < 1e-11
+    # across the flow (u_y = 0) the same recurrence holds with u = 0
+    Vy = (Y * Y * C0).sum() - (Y * C0).sum() ** 2 / M0
+    d = 0.0
+    for _ in range(T):
+        Vy += 2 * (1 - om) * d + M0 * cs2
+        d = (1 - om) * d + M0 * cs2
+    Vyg = (Y * Y * C).sum() - (Y * C).sum() ** 2 / M
+    assert abs(Vyg - Vy) / Vy < 1e-11
 
 
 def test_gaussian_pulse_continuum():
@@ -537,6 +596,71 @@ def _push_ad(cls, g, u, tau_d, c_in, k, c, w, opp):
             ge = w[i] * C * (1 + 3 * cu)
             out[i, n] = gi[i] - (gi[i] - ge) / tau_d - w[i] * kk * C
     return out
+
+
+def _push_ad9(cls, g, u, tau_d, c_in, k, K, outlet, c_out):
+    """Push form of one D2Q9 substrate step with the Eq. 5 equilibrium:
+    every stored population is sent along c_i; one that would enter a solid
+    comes back reversed; one leaving through x < 0 is replaced, in the node
+    it left, by -itself + 2 w_i c_in (1 + 9/2 (c.u)^2 - 3/2 u^2) of the
+    reversed direction (u the node's velocity); one leaving through x >= nx
+    by the node's own value (zero gradient) or the same Dirichlet form with
+    c_out.  Then collide, with the Monod sink k C / (C + K) on biofilm."""
+    ny, nx = cls.shape
+    c, w, opp, cs2 = O.lattice_tables(O.D2Q9)
+    N = nx * ny
+    arr = np.full((9, N), np.nan)
+    blocked = lambda t: t in (O.SOLID, O.WALL)
+    for y in range(ny):
+        for x in range(nx):
+            n = x + nx * y
+            if blocked(cls[y, x]):
+                continue
+            ux, uy = u[0, n], u[1, n]
+            for i in range(9):
+                p = g[i, n]
+                tx, ty = x + c[i, 0], y + c[i, 1]
+                j = opp[i]
+                cuj = c[j, 0] * ux + c[j, 1] * uy
+                even = w[j] * (1 + 4.5 * cuj * cuj - 1.5 * (ux * ux + uy * uy))
+                if tx < 0:
+                    arr[j, n] = -p + 2 * even * c_in
+                elif tx >= nx:
+                    arr[j, n] = -p + 2 * even * c_out if outlet == 1 else g[j, n]
+                elif ty < 0 or ty >= ny or blocked(cls[ty, tx]):
+                    arr[j, n] = p
+                else:
+                    arr[i, tx + nx * ty] = p
+    out = np.zeros((9, N))
+    for n in range(N):
+        if blocked(cls.ravel()[n]):
+            continue
+        gi = arr[:, n]
+        assert not np.isnan(gi).any()
+        C = sum(gi)
+        q = k * C / (C + K) if cls.ravel()[n] == O.BIOFILM else 0.0
+        ux, uy = u[0, n], u[1, n]
+        for i in range(9):
+            cu = c[i, 0] * ux + c[i, 1] * uy
+            ge = w[i] * C * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy))
+            out[i, n] = gi[i] - (gi[i] - ge) / tau_d - w[i] * q
+    return out
+
+
+@pytest.mark.parametrize("outlet", [0, 1])
+def test_bruteforce_push_ad_d2q9(outlet):
+    cls = _tiny_mask()
+    rng = np.random.default_rng(7 + outlet)
+    u = 0.05 * (rng.random((2, cls.size)) - 0.5)
+    act = ~np.isin(cls.ravel(), [O.SOLID, O.WALL])
+    g = rng.random((9, cls.size)) * act
+    D = 0.08
+    tau_d = 0.5 + D * 3
+    for _ in range(4):
+        want = _push_ad9(cls, g, u, tau_d, 0.9, 0.01, 0.3, outlet, 0.2)
+        got, _ = O.ad_step(cls, g, u, D, 0.9, 0.01, outlet=outlet, c_out=0.2, lat=O.D2Q9, k_half=0.3)
+        assert np.abs(got - want).max() < 1e-15
+        g = got
 
 
 def _tiny_mask():
