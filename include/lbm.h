@@ -132,6 +132,12 @@ typedef struct {
                              (C + k_half), C the concentration a step collides with;
                              needs k_sink < k_half.  Zero-initialised parameters keep
                              the first-order sink. */
+    int32_t ad_lattice;   /* 0: D2Q5 (2-D) / D3Q7 (3-D) substrate with the linear
+                             equilibrium.  1 (2-D only): the paper's substrate LBM,
+                             D2Q9 with the equilibrium of Eq. 5 (C for rho); its
+                             Dirichlet faces impose twice the even part of that
+                             equilibrium, w_i c (1 + 9/2 (c.u)^2 - 3/2 u^2).  Not
+                             offered by the server. */
 } lbm_params;
 
 typedef struct {

@@ -38,7 +38,7 @@ class lbm_params(ct.Structure):
     _fields_ = [("tau", ct.c_double), ("u_in", ct.c_double), ("D", ct.c_double),
                 ("c_in", ct.c_double), ("k_sink", ct.c_double), ("outlet", ct.c_int32),
                 ("c_out", ct.c_double), ("storage", ct.c_int32), ("check_every", ct.c_int32),
-                ("stall_checks", ct.c_int32), ("k_half", ct.c_double)]
+                ("stall_checks", ct.c_int32), ("k_half", ct.c_double), ("ad_lattice", ct.c_int32)]
 
 
 class lbm_info(ct.Structure):
@@ -324,9 +324,11 @@ def lbm_copy_bandwidth(ctx, nbytes, reps=20):
 
 # --------------------------------------------------------------- solver
 def make_params(tau=0.8, u_in=0.01, D=0.1, c_in=1.0, k_sink=0.0, outlet=LBM_OUT_ZERO_GRADIENT,
-                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=100, stall_checks=0, k_half=0.0):
+                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=100, stall_checks=0, k_half=0.0,
+                ad_lattice=0):
     return lbm_params(float(tau), float(u_in), float(D), float(c_in), float(k_sink), int(outlet),
-                      float(c_out), int(storage), int(check_every), int(stall_checks), float(k_half))
+                      float(c_out), int(storage), int(check_every), int(stall_checks), float(k_half),
+                      int(ad_lattice))
 
 
 def lbm_solver_create(ctx, cls, params):
@@ -380,8 +382,10 @@ _FIELD_SHAPES = {LBM_FIELD_U: ("dim", np.float64), LBM_FIELD_RHO: (1, np.float64
                  LBM_FIELD_G: ("qa", np.float64), LBM_FIELD_DESC: (1, np.uint32)}
 
 
-def lbm_solver_get(s, field, grid):
-    """grid = (nx, ny, nz).  Returns the field as a numpy array."""
+def lbm_solver_get(s, field, grid, qa=None):
+    """grid = (nx, ny, nz).  Returns the field as a numpy array.  qa: the
+    substrate lattice's direction count where it is not the default (9 for
+    the D2Q9 substrate)."""
     nx, ny, nz = grid
     N = nx * ny * nz
     dim = 3 if nz > 1 else 2
@@ -389,7 +393,8 @@ def lbm_solver_get(s, field, grid):
         out = np.zeros(N, np.uint32 if nz > 1 else np.uint16)
     else:
         rows, dt = _FIELD_SHAPES[field]
-        rows = {"dim": dim, "qf": 19 if nz > 1 else 9, "qa": 7 if nz > 1 else 5}.get(rows, rows)
+        rows = {"dim": dim, "qf": 19 if nz > 1 else 9,
+                "qa": qa or (7 if nz > 1 else 5)}.get(rows, rows)
         out = np.zeros((rows, N) if rows != 1 else N, dt)
     st = load().lbm_solver_get(s, int(field), _p(out))
     if st:
@@ -494,7 +499,7 @@ class Solver:
         return lbm_solver_steps(self.h, which, nsteps, cold)
 
     def get(self, field):
-        return lbm_solver_get(self.h, field, self.grid)
+        return lbm_solver_get(self.h, field, self.grid, qa=9 if self.params.ad_lattice == 1 else None)
 
     def error(self):
         return lbm_last_error(self.ctx)

@@ -466,6 +466,32 @@ uint32_t desc_word(const lbm_grid &g, const uint8_t *cls, const uint8_t *dom, bo
     return d;
 }
 
+uint16_t ad9_desc_word(const lbm_grid &g, const uint8_t *cls, bool ref, int x, int y)
+{
+    // the D2Q9 substrate's own word: bits 1..8 blocked pull sources (D2Q9
+    // directions, substrate rule), then active, BIOFILM, reference node --
+    // the substrate layout with no fluid bits below it (fluid Q taken as 1)
+    const Dirs &D = fluid_dirs(1);
+    const int64_t n = idx3(g, x, y, 0);
+    const uint8_t k = cls[n];
+    uint32_t d = 0;
+    if (k == LBM_FLUID || k == LBM_BIOFILM) {
+        for (int i = 1; i < D.q; ++i) {
+            const int ax = x - D.c[i][0], ay = y - D.c[i][1];
+            if (ax < 0 || ay < 0 || ax >= g.nx || ay >= g.ny)
+                continue;
+            if (ad_blocked(cls[idx3(g, ax, ay, 0)]))
+                d |= 1u << lbmk::desc_ad_link_bit(1, i);
+        }
+        d |= 1u << lbmk::desc_ad_active_bit(1, D.q);
+    }
+    if (k == LBM_BIOFILM)
+        d |= 1u << lbmk::desc_biofilm_bit(1, D.q);
+    if (ref)
+        d |= 1u << lbmk::desc_ref_bit(1, D.q);
+    return (uint16_t)d;
+}
+
 void build_desc(const lbm_grid &g, const uint8_t *cls, const std::vector<uint8_t> &dom,
                 const std::vector<int64_t> &ref, uint32_t *desc)
 {

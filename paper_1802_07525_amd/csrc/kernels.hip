@@ -79,6 +79,16 @@ struct D3Q7 {
     static constexpr double w[7] = {1.0 / 4, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8};
     static constexpr double inv_cs2 = 4.0;
 };
+// Stand-in for the fluid lattice where a substrate descriptor holds no fluid
+// bits (the D2Q9 substrate's own words): its Q = 1 puts the substrate bits
+// at the bottom of the word.
+struct NoFluid {
+    static constexpr int Q = 1;
+};
+// Substrate equilibrium: on a lattice with diagonal directions (D2Q9) the
+// second-order form of Eq. 5 with C for rho, else the linear form.
+template <class L>
+constexpr bool ad_second_order = L::Q == 9 || L::Q == 19;
 
 // ---------------------------------------------------------- storage forms
 // tile_mean: the residual compares tile means instead of nodes (see
@@ -919,22 +929,40 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
         }
         g[i] = v;
     }
+    // second-order form: 9/2 (c.u)^2 - 3/2 u^2 of direction i
+    C usq = C(0);
+    if constexpr (ad_second_order<L>)
+        usq = C(1.5) * (L::DIM == 3 ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
+    auto quad = [&](int i) {
+        const C cu = cdot<L>(i, ux, uy, uz);
+        return C(4.5) * cu * cu - usq;
+    };
     // Dirichlet links of the boundary columns (branches: waves without such
-    // a node skip them)
+    // a node skip them): twice the even part of the equilibrium at the
+    // boundary value, w_i c (1 + 9/2 (c.u)^2 - 3/2 u^2) in the second-order
+    // form, minus the reversed population
     if (xin) {
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
-            if (L::cx[i] == 1)
-                g[i] = (S::colref ? C(2.0 * L::w[i]) * cin_s : C(2.0 * L::w[i] * a.cin_s)) - g[i];
+            if (L::cx[i] == 1) {
+                C e = S::colref ? C(2.0 * L::w[i]) * cin_s : C(2.0 * L::w[i] * a.cin_s);
+                if constexpr (ad_second_order<L>)
+                    e += C(2.0 * L::w[i] * a.c_in) * quad(i);
+                g[i] = e - g[i];
+            }
     }
     if (xout) {
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
             if (L::cx[i] == -1) {
-                if (a.outlet)
-                    g[i] = (S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s)) - g[i];
-                else
+                if (a.outlet) {
+                    C e = S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s);
+                    if constexpr (ad_second_order<L>)
+                        e += C(2.0 * L::w[i] * a.c_out) * quad(i);
+                    g[i] = e - g[i];
+                } else {
                     g[i] = src.own(i); // zero gradient: copy this node's population i
+                }
             }
     }
     C cs = g[0];
@@ -948,11 +976,23 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
         const C geq = C(L::w[0]) * cs;
         g[0] = g[0] + om * (geq - g[0]) - C(L::w[0]) * kc;
     }
+    if constexpr (ad_second_order<L>) {
+        // Eq. 5 with C for rho, minus the shift: w_i (cs + C (3 c.u +
+        // 9/2 (c.u)^2 - 3/2 u^2)); the rest direction carries -3/2 u^2
+        g[0] = g[0] - om * C(L::w[0]) * cfull * usq;
 #pragma unroll
-    for (int i = 1; i < L::Q; ++i) {
-        const C cu = cdot<L>(i, ux, uy, uz);
-        const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
-        g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+        for (int i = 1; i < L::Q; ++i) {
+            const C cu = cdot<L>(i, ux, uy, uz);
+            const C geq = C(L::w[i]) * (cs + cfull * (C(3) * cu + (C(4.5) * cu * cu - usq)));
+            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+        }
+    } else {
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const C cu = cdot<L>(i, ux, uy, uz);
+            const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
+            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+        }
     }
 }
 
@@ -1042,14 +1082,13 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
 }
 
 // Two substrate steps of one 64 x TY tile (2-D), as fluid_tile2.
-template <class S, int MODE, bool NT, int TY = PAIR_TY>
+template <class S, int MODE, bool NT, class L = D2Q5, int QF = 9, int TY = PAIR_TY>
 __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned long long *part_r,
                                          unsigned long long *part_u, void *smem)
 {
-    typedef D2Q5 L;
     typedef uint16_t DT;
     typedef typename S::C C;
-    constexpr int QF = 9, ACT = QF - 1 + L::Q;
+    constexpr int ACT = QF - 1 + L::Q;
     constexpr int LX = 66, LY = TY + 2, NR = LX * LY;
     C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
     const long long N = a.g.N;
@@ -1143,15 +1182,15 @@ __global__ void __launch_bounds__(256) k_fluid_step2(FluidArgs a)
                              part + gridDim.x + blockIdx.x, smem);
 }
 
-template <class S, int MODE, bool NT>
+template <class S, int MODE, bool NT, class L, int QF>
 __global__ void __launch_bounds__(256) k_ad_step2(AdArgs a)
 {
-    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, 5>()];
+    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, L::Q>()];
     if (a.ctrl->stop)
         return;
     unsigned long long *part = a.ctrl->part;
-    ad_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
-                          part + gridDim.x + blockIdx.x, smem);
+    ad_tile2<S, MODE, NT, L, QF>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                 part + gridDim.x + blockIdx.x, smem);
 }
 
 // ------------------------------------------------------- init / export
@@ -1182,16 +1221,12 @@ __global__ void __launch_bounds__(256) k_ad_init(typename S::T *gp, const DT *de
     const C ux = act ? U[n] : C(0), uy = act ? U[N + n] : C(0);
     const C uz = (act && L::DIM == 3) ? U[2 * N + n] : C(0);
     const C cs = S::shifted ? C(c_init - c_ref) : C(c_init);
+    const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        C cu = C(0);
-        if (L::cx[i] == 1) cu += ux;
-        if (L::cx[i] == -1) cu -= ux;
-        if (L::cy[i] == 1) cu += uy;
-        if (L::cy[i] == -1) cu -= uy;
-        if (L::cz[i] == 1) cu += uz;
-        if (L::cz[i] == -1) cu -= uz;
-        const C v = C(L::w[i]) * (cs + C(c_init) * (C(L::inv_cs2) * cu));
+        const C cu = i == 0 ? C(0) : cdot<L>(i, ux, uy, uz);
+        const C t = ad_second_order<L> ? C(3) * cu + (C(4.5) * cu * cu - usq) : C(L::inv_cs2) * cu;
+        const C v = C(L::w[i]) * (cs + C(c_init) * t);
         st<S>(gp + (long long)i * N + n, act ? v : C(0));
     }
 }
@@ -1337,7 +1372,8 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                                                         Geo g, const float *ref_f,
                                                         const float *ref_g, double u_in,
                                                         double c_in, Sink sink, int outlet,
-                                                        double c_out, double *part)
+                                                        double c_out, const typename S::C *U,
+                                                        double *part)
 {
     constexpr int ACT = LF::Q - 1 + LA::Q;
     constexpr int BIO = ACT + 1;
@@ -1355,6 +1391,7 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
         const DT d = desc[n];
         const double fs = (S::shifted && f) ? (double)ref_f[x] : 0.0;
         const double gs = (S::shifted && gp) ? (double)ref_g[x] : 0.0;
+        if constexpr (LF::Q > 1) {
         if (f && (d & DT(1)) && (x == 0 || x == g.nx - 1)) {
             double r = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
 #pragma unroll
@@ -1382,19 +1419,31 @@ __global__ void __launch_bounds__(256) k_flux_partials(const typename S::T *f,
                 }
             }
         }
+        }
         if (gp && ((d >> ACT) & DT(1))) {
             if (x == 0 || x == g.nx - 1) {
+                // even part of the equilibrium per unit concentration: 1, or
+                // 1 + 9/2 (c.u)^2 - 3/2 u^2 in the second-order form
+                double ux = 0.0, uy = 0.0, uz = 0.0;
+                if (ad_second_order<LA> && U) {
+                    ux = (double)U[n];
+                    uy = (double)U[N + n];
+                    uz = LA::DIM == 3 ? (double)U[2 * N + n] : 0.0;
+                }
+                const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
                 for (int i = 1; i < LA::Q; ++i) {
                     const int o = LA::op[i];
                     const double go = static_cast<double>(gp[(long long)o * N + n]) + gs * LA::w[o];
+                    const double cu = LA::cx[i] * ux + LA::cy[i] * uy + LA::cz[i] * uz;
+                    const double ev = ad_second_order<LA> ? 1.0 + 4.5 * cu * cu - 1.5 * uu : 1.0;
                     if (x == 0 && LA::cx[i] == 1) {
-                        const double incoming = -go + 2.0 * LA::w[i] * c_in;
+                        const double incoming = -go + 2.0 * LA::w[i] * c_in * ev;
                         acc[2] += incoming - go;
                     }
                     if (x == g.nx - 1 && LA::cx[i] == -1) {
                         const double gi = static_cast<double>(gp[(long long)i * N + n]) + gs * LA::w[i];
-                        const double incoming = outlet ? -go + 2.0 * LA::w[i] * c_out : gi;
+                        const double incoming = outlet ? -go + 2.0 * LA::w[i] * c_out * ev : gi;
                         acc[3] += go - incoming;
                     }
                 }
@@ -1759,6 +1808,16 @@ static hipError_t by_dim(int dim, F &&fn)
     return hipErrorInvalidValue;
 }
 
+// Lattices of a layout code for substrate calls: 2 and 3 as by_dim, or
+// LAY_2D_AD9, the D2Q9 substrate with its own 16-bit words (no fluid bits)
+template <class F>
+static hipError_t by_lay(int lay, F &&fn)
+{
+    if (lay == LAY_2D_AD9)
+        return fn(NoFluid{}, D2Q9{}, uint16_t{});
+    return by_dim(lay, fn);
+}
+
 hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStream_t st)
 {
     return by_dim(dim, [&](auto lf, auto, auto dt) {
@@ -1820,29 +1879,37 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
     });
 }
 
-hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st)
+hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t st)
 {
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         const dim3 grid(pair_tiles(a.g));
-        if (a.streaming_stores) {
-            if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, true>), grid, dim3(256), 0, st, a);
-        } else {
-            if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, false>), grid, dim3(256), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, false>), grid, dim3(256), 0, st, a);
-        }
+        auto go = [&](auto la, auto qf) {
+            typedef decltype(la) L;
+            constexpr int QF = decltype(qf)::value;
+            if (a.streaming_stores) {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true, L, QF>), grid, dim3(256), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, true, L, QF>), grid, dim3(256), 0, st, a);
+            } else {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, false, L, QF>), grid, dim3(256), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, false, L, QF>), grid, dim3(256), 0, st, a);
+            }
+        };
+        if (lay == LAY_2D_AD9)
+            go(D2Q9{}, std::integral_constant<int, 1>{});
+        else
+            go(D2Q5{}, std::integral_constant<int, 9>{});
         return hipGetLastError();
     });
 }
 
 hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t st)
 {
-    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+    return by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -1896,7 +1963,7 @@ hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo
 hipError_t ad_init(int dim, int storage, void *gp, const void *desc, const void *u,
                    const Geo &g, double c_init, double c_ref, hipStream_t st)
 {
-    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+    return by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -1938,7 +2005,7 @@ hipError_t fluid_export(int dim, int storage, const void *f, const void *desc, c
 hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, const Geo &g,
                      const float *ref, Sink sink, void *C, int out_double, hipStream_t st)
 {
-    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+    return by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -1963,7 +2030,7 @@ hipError_t ad_export(int dim, int storage, const void *gp, const void *desc, con
 hipError_t pops_export(int which, int dim, int storage, const void *h, const void *desc,
                        const Geo &g, const float *ref, double *out, hipStream_t st)
 {
-    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+    return by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -1971,10 +2038,15 @@ hipError_t pops_export(int which, int dim, int storage, const void *h, const voi
             typedef decltype(dt) DT;
             const typename S::T *hp = static_cast<const typename S::T *>(h);
             const DT *dp = static_cast<const DT *>(desc);
+            if constexpr (LF::Q > 1) {
+                if (which == 0) {
+                    hipLaunchKernelGGL((k_pops_export<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                       dp, g.N, 0, ref, g.nx, out);
+                    return hipGetLastError();
+                }
+            }
             if (which == 0)
-                hipLaunchKernelGGL((k_pops_export<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, 0, ref, g.nx, out);
-            else
+                return hipErrorInvalidValue;
                 hipLaunchKernelGGL((k_pops_export<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
                                    dp, g.N, LF::Q - 1 + LA::Q, ref, g.nx, out);
             return hipGetLastError();
@@ -1985,7 +2057,7 @@ hipError_t pops_export(int which, int dim, int storage, const void *h, const voi
 hipError_t pops_import(int which, int dim, int storage, void *h, const void *desc,
                        const Geo &g, const float *ref, const double *in, hipStream_t st)
 {
-    return by_dim(dim, [&](auto lf, auto la, auto dt) {
+    return by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -1993,10 +2065,15 @@ hipError_t pops_import(int which, int dim, int storage, void *h, const void *des
             typedef decltype(dt) DT;
             typename S::T *hp = static_cast<typename S::T *>(h);
             const DT *dp = static_cast<const DT *>(desc);
+            if constexpr (LF::Q > 1) {
+                if (which == 0) {
+                    hipLaunchKernelGGL((k_pops_import<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
+                                       dp, g.N, 0, ref, g.nx, in);
+                    return hipGetLastError();
+                }
+            }
             if (which == 0)
-                hipLaunchKernelGGL((k_pops_import<LF, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
-                                   dp, g.N, 0, ref, g.nx, in);
-            else
+                return hipErrorInvalidValue;
                 hipLaunchKernelGGL((k_pops_import<LA, S, DT>), flat_grid(g.N), dim3(256), 0, st, hp,
                                    dp, g.N, LF::Q - 1 + LA::Q, ref, g.nx, in);
             return hipGetLastError();
@@ -2010,16 +2087,21 @@ hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g
 {
     if (count <= 0)
         return hipSuccess;
-    return by_dim(dim, [&](auto lf, auto la, auto) {
+    return by_lay(dim, [&](auto lf, auto la, auto) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
             typedef decltype(s) S;
             typename S::T *hp = static_cast<typename S::T *>(h);
+            if constexpr (LF::Q > 1) {
+                if (which == 0) {
+                    hipLaunchKernelGGL((k_pops_set_nodes<LF, S>), dim3((count + 255) / 256), dim3(256), 0,
+                                       st, hp, g.N, ref, g.nx, idx, count, vals_q);
+                    return hipGetLastError();
+                }
+            }
             if (which == 0)
-                hipLaunchKernelGGL((k_pops_set_nodes<LF, S>), dim3((count + 255) / 256), dim3(256), 0,
-                                   st, hp, g.N, ref, g.nx, idx, count, vals_q);
-            else
+                return hipErrorInvalidValue;
                 hipLaunchKernelGGL((k_pops_set_nodes<LA, S>), dim3((count + 255) / 256), dim3(256), 0,
                                    st, hp, g.N, ref, g.nx, idx, count, vals_q);
             return hipGetLastError();
@@ -2041,10 +2123,10 @@ hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipS
 
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
                   const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
-                  Sink sink, int outlet, double c_out, double *partials, double *out5,
-                  hipStream_t st)
+                  Sink sink, int outlet, double c_out, const void *u, double *partials,
+                  double *out5, hipStream_t st)
 {
-    hipError_t e = by_dim(dim, [&](auto lf, auto la, auto dt) {
+    hipError_t e = by_lay(dim, [&](auto lf, auto la, auto dt) {
         return by_storage(storage, [&](auto s) {
             typedef decltype(lf) LF;
             typedef decltype(la) LA;
@@ -2053,7 +2135,8 @@ hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const voi
             hipLaunchKernelGGL((k_flux_partials<LF, LA, S, DT>), dim3(FLUX_BLOCKS), dim3(256), 0, st,
                                static_cast<const typename S::T *>(f),
                                static_cast<const typename S::T *>(gp), static_cast<const DT *>(desc),
-                               g, ref_f, ref_g, u_in, c_in, sink, outlet, c_out, partials);
+                               g, ref_f, ref_g, u_in, c_in, sink, outlet, c_out,
+                               static_cast<const typename S::C *>(u), partials);
             return hipGetLastError();
         });
     });

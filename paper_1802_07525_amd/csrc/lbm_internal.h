@@ -48,6 +48,8 @@ void links_ad(const lbm_grid &g, const uint8_t *cls, uint32_t *out);
 // descriptor word (lbm_kernels.h layout) of node (x, y, z)
 uint32_t desc_word(const lbm_grid &g, const uint8_t *cls, const uint8_t *dom, bool ref, int x, int y,
                    int z);
+// word of node (x, y) for the D2Q9 substrate (2-D), its own layout
+uint16_t ad9_desc_word(const lbm_grid &g, const uint8_t *cls, bool ref, int x, int y);
 // descriptor words of every node
 void build_desc(const lbm_grid &g, const uint8_t *cls, const std::vector<uint8_t> &dom,
                 const std::vector<int64_t> &ref, uint32_t *desc);
@@ -74,6 +76,10 @@ struct lbm_solver {
     std::vector<int64_t> refn;
     std::vector<uint32_t> desc_h;
     size_t desc_bytes = 2;       // per node
+    // D2Q9 substrate (lbm_params.ad_lattice): its own 16-bit words
+    bool ad9 = false;
+    void *d_desc_ad = nullptr;
+    std::vector<uint16_t> desc_ad_h;
     int64_t n_fluid = 0, n_ad = 0;
     double c_ref = 0.0;          // substrate shift reference (0 if unshifted)
 

@@ -49,6 +49,11 @@ struct Geo {
 
 Geo make_geo(int nx, int ny, int nz);
 
+// Layout code of substrate calls whose descriptor words are the D2Q9
+// substrate's own (16-bit, no fluid bits; the "dim" argument of substrate
+// functions is 2, 3 or this)
+enum { LAY_2D_AD9 = 4 };
+
 // Descriptor word per node (uint16 in 2-D, uint32 in 3-D):
 //   bit 0                 node is in the flow domain (FLUID and linked to
 //                         the outlet column: the fluid solver updates it)
@@ -135,7 +140,8 @@ hipError_t ad_step(int dim, int storage, int mode, const AdArgs &a, hipStream_t 
 // results equal two single steps (up to how the compiler contracts
 // multiply-adds in the two code paths); FP16 storage skips one rounding.
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st);
-hipError_t ad_step2(int storage, int mode, const AdArgs &a, hipStream_t st);
+// lay: 2 (D2Q5 substrate) or LAY_2D_AD9 (D2Q9 substrate, its own words)
+hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t st);
 // Blocks (tiles) of a two-step launch; per-block check maxima need this many
 // slots (never more than g.ntiles).
 int pair_tiles(const Geo &g);
@@ -177,13 +183,16 @@ hipError_t pops_set_nodes(int which, int dim, int storage, void *h, const Geo &g
                           hipStream_t st);
 
 // Deterministic FP64 fluxes: out[0..4] = fluid in, fluid out, substrate in,
-// substrate out, substrate consumed.  f or gp may be null (then 0).
+// substrate out, substrate consumed.  f or gp may be null (then 0).  u: the
+// compute-type velocity [dim][N] the substrate's second-order Dirichlet
+// faces need (may be null otherwise).  With dim = LAY_2D_AD9 the words are
+// the D2Q9 substrate's own and only the substrate terms are computed.
 // partials: device double [5 * FLUX_BLOCKS].
 enum { FLUX_BLOCKS = 512 };
 hipError_t fluxes(int dim, int storage, const void *f, const void *gp, const void *desc,
                   const Geo &g, const float *ref_f, const float *ref_g, double u_in, double c_in,
-                  Sink sink, int outlet, double c_out, double *partials, double *out5,
-                  hipStream_t st);
+                  Sink sink, int outlet, double c_out, const void *u, double *partials,
+                  double *out5, hipStream_t st);
 
 // part: device scratch of 2 * nparts words for the per-block check maxima
 hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K,

@@ -571,7 +571,7 @@ struct lbm_server {
         if ((e = lbmk::fluid_export(2, storage, f0, desc, j->geo, ref, u, nullptr, 0, stream)) != hipSuccess)
             return e;
         if ((e = lbmk::fluxes(2, storage, f0, nullptr, desc, j->geo, ref, nullptr, r.u_in, r.c_in, lbmk::Sink{r.k_sink, r.k_half},
-                              r.outlet, r.c_out, d_partials, d_out + 10 * j->sid, stream)) != hipSuccess)
+                              r.outlet, r.c_out, nullptr, d_partials, d_out + 10 * j->sid, stream)) != hipSuccess)
             return e;
         if (j->st_fluid == LBM_EDIVERGED)
             return retire(j);
@@ -613,7 +613,7 @@ struct lbm_server {
                 hipSuccess)
                 return e;
             if ((e = lbmk::fluxes(2, storage, nullptr, f0, desc, j->geo, nullptr, ref, r.u_in, r.c_in,
-                                  lbmk::Sink{r.k_sink, r.k_half}, r.outlet, r.c_out, d_partials, out + 5, stream)) != hipSuccess)
+                                  lbmk::Sink{r.k_sink, r.k_half}, r.outlet, r.c_out, nullptr, d_partials, out + 5, stream)) != hipSuccess)
                 return e;
         } else if ((e = hipMemsetAsync(prev, 0, (size_t)N * 4, stream)) != hipSuccess) {
             return e;

@@ -99,6 +99,24 @@ void count_active(lbm_solver *s)
     s->n_ad = na;
 }
 
+// Substrate layout code and descriptor words: the D2Q9 substrate's own, or
+// the shared words
+int ad_lay(const lbm_solver *s)
+{
+    return s->ad9 ? (int)lbmk::LAY_2D_AD9 : s->dim;
+}
+const void *ad_desc(const lbm_solver *s)
+{
+    return s->ad9 ? s->d_desc_ad : s->d_desc;
+}
+
+lbm_status upload_ad9_words(lbm_solver *s)
+{
+    HIPCHK(hipMemcpy(s->d_desc_ad, s->desc_ad_h.data(), s->desc_ad_h.size() * 2, hipMemcpyHostToDevice),
+           "substrate desc upload");
+    return LBM_OK;
+}
+
 // Full rebuild of the mirror from the mask, then upload.
 lbm_status upload_desc(lbm_solver *s)
 {
@@ -107,6 +125,16 @@ lbm_status upload_desc(lbm_solver *s)
     s->desc_h.resize((size_t)s->geo.N);
     build_desc(s->grid, s->cls.data(), s->dom, s->refn, s->desc_h.data());
     count_active(s);
+    if (s->ad9) {
+        s->desc_ad_h.resize((size_t)s->geo.N);
+        for (int y = 0; y < s->grid.ny; ++y)
+            for (int x = 0; x < s->grid.nx; ++x)
+                s->desc_ad_h[(size_t)x + (size_t)s->grid.nx * y] =
+                    ad9_desc_word(s->grid, s->cls.data(), s->refn[(size_t)x] == x + (int64_t)s->grid.nx * y, x, y);
+        lbm_status st = upload_ad9_words(s);
+        if (st)
+            return st;
+    }
     return upload_desc_words(s);
 }
 
@@ -205,7 +233,7 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     lbmk::AdArgs a;
     a.src = s->d_g[src];
     a.dst = s->d_g[src ^ 1];
-    a.desc = s->d_desc;
+    a.desc = ad_desc(s);
     a.u = s->d_u;
     a.cprev = s->d_cprev;
     a.ctrl = s->d_ctrl + 1;
@@ -226,8 +254,8 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.ref_src = ref_cur(s, 1);
     a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
     a.ref_out = ref_next(s, 1);
-    return nsteps == 2 ? lbmk::ad_step2(s->p.storage, mode, a, s->ctx->stream)
-                       : lbmk::ad_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+    return nsteps == 2 ? lbmk::ad_step2(ad_lay(s), s->p.storage, mode, a, s->ctx->stream)
+                       : lbmk::ad_step(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
 }
 
 lbm_status init_solver(lbm_solver *s, int which)
@@ -240,7 +268,7 @@ lbm_status init_solver(lbm_solver *s, int which)
                "fluid init");
         s->fluid_ready = true;
     } else {
-        HIPCHK(lbmk::ad_init(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->d_u, s->geo,
+        HIPCHK(lbmk::ad_init(ad_lay(s), s->p.storage, s->d_g[s->gcur], ad_desc(s), s->d_u, s->geo,
                              s->p.c_in, s->c_ref, st),
                "substrate init");
         s->ad_ready = true;
@@ -259,15 +287,27 @@ double algo_bytes(const lbm_solver *s, int which)
 
 lbm_status fill_fluxes(lbm_solver *s, double *out5)
 {
-    HIPCHK(lbmk::fluxes(s->dim, s->p.storage, s->fluid_ready ? s->d_f[s->fcur] : nullptr,
-                        s->ad_ready ? s->d_g[s->gcur] : nullptr, s->d_desc, s->geo, ref_cur(s, 0),
-                        ref_cur(s, 1), s->p.u_in, s->p.c_in, lbmk::Sink{s->p.k_sink, s->p.k_half}, s->p.outlet, s->p.c_out,
-                        s->d_partials,
-                        s->d_out5, s->ctx->stream),
+    const lbmk::Sink sink{s->p.k_sink, s->p.k_half};
+    const void *f = s->fluid_ready ? s->d_f[s->fcur] : nullptr;
+    const void *gp = s->ad_ready ? s->d_g[s->gcur] : nullptr;
+    // the D2Q9 substrate has words of its own: fluid and substrate terms
+    // in two passes, the second into out5 + 5
+    HIPCHK(lbmk::fluxes(s->dim, s->p.storage, f, s->ad9 ? nullptr : gp, s->d_desc, s->geo, ref_cur(s, 0),
+                        ref_cur(s, 1), s->p.u_in, s->p.c_in, sink, s->p.outlet, s->p.c_out, s->d_u,
+                        s->d_partials, s->d_out5, s->ctx->stream),
            "fluxes");
-    HIPCHK(hipMemcpyAsync(out5, s->d_out5, 5 * sizeof(double), hipMemcpyDeviceToHost, s->ctx->stream),
+    if (s->ad9)
+        HIPCHK(lbmk::fluxes(lbmk::LAY_2D_AD9, s->p.storage, nullptr, gp, s->d_desc_ad, s->geo, ref_cur(s, 0),
+                            ref_cur(s, 1), s->p.u_in, s->p.c_in, sink, s->p.outlet, s->p.c_out, s->d_u,
+                            s->d_partials, s->d_out5 + 5, s->ctx->stream),
+               "substrate fluxes");
+    double o[10];
+    HIPCHK(hipMemcpyAsync(o, s->d_out5, (s->ad9 ? 10 : 5) * sizeof(double), hipMemcpyDeviceToHost,
+                          s->ctx->stream),
            "flux copy");
     HIPCHK(hipStreamSynchronize(s->ctx->stream), "flux sync");
+    for (int k = 0; k < 5; ++k)
+        out5[k] = s->ad9 && k >= 2 ? o[5 + k] : o[k];
     return LBM_OK;
 }
 
@@ -310,7 +350,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                                   nullptr, 0, stream),
                "residual reference");
     else
-        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[cur0], s->d_desc, s->geo, ref_cur(s, 1),
+        HIPCHK(lbmk::ad_export(ad_lay(s), s->p.storage, s->d_g[cur0], ad_desc(s), s->geo, ref_cur(s, 1),
                                lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_cprev, 0, stream),
                "residual reference");
     const auto t0 = std::chrono::steady_clock::now();
@@ -436,7 +476,7 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
             return set_err(s->ctx, LBM_EINVAL, "substrate state not initialised");
         if ((e = ensure_stage(s, N * 8)))
             return e;
-        HIPCHK(lbmk::ad_export(s->dim, s->p.storage, s->d_g[s->gcur], s->d_desc, s->geo, ref_cur(s, 1),
+        HIPCHK(lbmk::ad_export(ad_lay(s), s->p.storage, s->d_g[s->gcur], ad_desc(s), s->geo, ref_cur(s, 1),
                                lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_stage, 1, st),
                "export");
         HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, hipMemcpyDeviceToHost, st), "copy");
@@ -466,8 +506,10 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         const int q = which == 0 ? s->qf : s->qa;
         if ((e = ensure_stage(s, (size_t)q * N * 8)))
             return e;
-        HIPCHK(lbmk::pops_export(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
-                                 s->d_desc, s->geo, ref_cur(s, which), s->d_stage, st),
+        HIPCHK(lbmk::pops_export(which, which == 0 ? s->dim : ad_lay(s), s->p.storage,
+                                 which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
+                                 which == 0 ? s->d_desc : ad_desc(s), s->geo, ref_cur(s, which), s->d_stage,
+                                 st),
                "export");
         HIPCHK(hipMemcpyAsync(dst, s->d_stage, (size_t)q * N * 8, hipMemcpyDeviceToHost, st), "copy");
         break;
@@ -529,6 +571,8 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
     lbm_status st = validate_params(ctx, p);
     if (st)
         return st;
+    if (p.ad_lattice != 0 && !(p.ad_lattice == 1 && g.nz == 1))
+        return set_err(ctx, LBM_EINVAL, "ad_lattice: 0, or 1 (D2Q9 substrate) on a 2-D grid");
     if (require_percolation && !percolates(g, cls))
         return set_err(ctx, LBM_EINVAL, "the fluid domain does not connect inlet to outlet");
     hipError_t he = hipSetDevice(ctx->device);
@@ -540,7 +584,8 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
     s->p = p;
     s->dim = g.nz > 1 ? 3 : 2;
     s->qf = s->dim == 3 ? 19 : 9;
-    s->qa = s->dim == 3 ? 7 : 5;
+    s->ad9 = p.ad_lattice == 1;
+    s->qa = s->dim == 3 ? 7 : (s->ad9 ? 9 : 5);
     s->geo = lbmk::make_geo(g.nx, g.ny, g.nz);
     s->cls.assign(cls, cls + N64);
     s->desc_bytes = s->dim == 3 ? 4 : 2;
@@ -551,6 +596,8 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
         return e;
     };
     if ((st = dev_alloc(s, &s->d_desc, N * s->desc_bytes, "descriptors")))
+        return fail(st);
+    if (s->ad9 && (st = dev_alloc(s, &s->d_desc_ad, N * 2, "substrate descriptors")))
         return fail(st);
     if ((st = dev_alloc(s, &s->d_u, (size_t)s->dim * N * cbytes(s), "velocity")))
         return fail(st);
@@ -575,7 +622,7 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
             hipSuccess)
         return fail(hip_err(ctx, he, "column references"));
     tmp = nullptr;
-    if ((st = dev_alloc(s, &tmp, 8 * sizeof(double), "flux out")))
+    if ((st = dev_alloc(s, &tmp, 16 * sizeof(double), "flux out")))
         return fail(st);
     s->d_out5 = static_cast<double *>(tmp);
     if ((st = upload_desc(s)))
@@ -604,7 +651,8 @@ void lbm_solver_destroy(lbm_solver *s)
     (void)hipStreamSynchronize(s->ctx->stream);
     void *bufs[] = {s->d_desc, s->d_f[0],   s->d_f[1],   s->d_g[0], s->d_g[1],
                     s->d_u,    s->d_uprev,  s->d_cprev,  s->d_ctrl, s->d_part,
-                    s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals, s->d_ref};
+                    s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals, s->d_ref,
+                    s->d_desc_ad};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -764,8 +812,10 @@ lbm_status lbm_solver_put(lbm_solver *s, int field, const double *src)
         return st;
     hipStream_t stream = s->ctx->stream;
     HIPCHK(hipMemcpyAsync(s->d_stage, src, (size_t)q * N * 8, hipMemcpyHostToDevice, stream), "copy");
-    HIPCHK(lbmk::pops_import(which, s->dim, s->p.storage, which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
-                             s->d_desc, s->geo, ref_cur(s, which), s->d_stage, stream),
+    HIPCHK(lbmk::pops_import(which, which == 0 ? s->dim : ad_lay(s), s->p.storage,
+                             which == 0 ? s->d_f[s->fcur] : s->d_g[s->gcur],
+                             which == 0 ? s->d_desc : ad_desc(s), s->geo, ref_cur(s, which), s->d_stage,
+                             stream),
            "import");
     HIPCHK(hipStreamSynchronize(stream), "sync");
     if (which == 0)
@@ -863,6 +913,8 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
         const int x = (int)(j % g.nx), y = (int)((j / g.nx) % g.ny);
         const int z = (int)(j / ((int64_t)g.nx * g.ny));
         s->desc_h[(size_t)j] = desc_word(g, trial.data(), dom1.data(), ref1[(size_t)x] == j, x, y, z);
+        if (s->ad9)
+            s->desc_ad_h[(size_t)j] = ad9_desc_word(g, trial.data(), ref1[(size_t)x] == j, x, y);
     }
     s->cls.swap(trial);
     s->dom.swap(dom1);
@@ -870,6 +922,8 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
     count_active(s);
     lbm_status st = upload_desc_words(s);
     if (st)
+        return st;
+    if (s->ad9 && (st = upload_ad9_words(s)))
         return st;
     if (!s->d_idx) {
         void *p = nullptr;
@@ -896,7 +950,8 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
         if (!buf)
             return LBM_OK; // solver never run: nothing stored yet
         const int q = which == 0 ? s->qf : s->qa;
-        const double *w = which == 0 ? (s->dim == 3 ? wf3 : wf2) : (s->dim == 3 ? wa3 : wa2);
+        const double *w = which == 0 ? (s->dim == 3 ? wf3 : wf2)
+                                     : (s->dim == 3 ? wa3 : (s->ad9 ? wf2 : wa2));
         // unshifted values; blocked nodes store 0 whatever the shift
         double vals[19];
         for (int i = 0; i < q; ++i) {
@@ -913,7 +968,7 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
             HIPCHK(hipMemcpyAsync(s->d_idx, list.data() + off, cnt * sizeof(long long),
                                   hipMemcpyHostToDevice, stream),
                    "idx");
-            HIPCHK(lbmk::pops_set_nodes(which, s->dim, s->p.storage, buf, s->geo,
+            HIPCHK(lbmk::pops_set_nodes(which, which == 0 ? s->dim : ad_lay(s), s->p.storage, buf, s->geo,
                                         on ? ref_cur(s, which) : nullptr, s->d_idx, cnt, s->d_vals,
                                         stream),
                    "cell reset");
@@ -999,7 +1054,7 @@ lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
     StateHeader h;
     memcpy(&h, src, sizeof(h));
     if (memcmp(h.magic, "LBMSTAT4", 8) != 0 || h.nx != s->grid.nx || h.ny != s->grid.ny ||
-        h.nz != s->grid.nz || h.storage != s->p.storage || bytes < state_size(s))
+        h.nz != s->grid.nz || h.storage != s->p.storage || h.qa != s->qa || bytes < state_size(s))
         return set_err(s->ctx, LBM_EINVAL, "checkpoint does not match this solver");
     const size_t N = (size_t)s->geo.N;
     const char *p = static_cast<const char *>(src) + sizeof(h);

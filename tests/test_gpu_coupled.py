@@ -67,3 +67,26 @@ def test_coupled_loop_fp16_reproducible(gpu_lib):
     assert np.array_equal(a["iters_ad"], b["iters_ad"])
     assert np.array_equal(a["J"], b["J"])
     assert np.array_equal(ca, cb)
+
+
+def test_coupled_loop_d2q9_substrate_fp64(gpu_lib):
+    """The coupled loop with the paper's D2Q9 substrate LBM: picks,
+    iteration counts and J against the oracle's loop on the same lattice
+    (growth updates patch the substrate's own descriptor words)."""
+    lbm = gpu_lib
+    cls = masks(W, lbm)
+    xi = inputs.growth_draws(4, seed=57)
+    tol, max_iter = 1e-7, 200000
+    o = O.coupled_run(cls, W["tau"], W["u_in"], W["D"], W["c_in"], W["k"], tol, max_iter, xi,
+                      lat_ad=O.D2Q9)
+    assert o["status"] == "OK", o["status"]
+    with lbm.Solver(cls, tau=W["tau"], u_in=W["u_in"], D=W["D"], c_in=W["c_in"], k_sink=W["k"],
+                    storage=FP64, ad_lattice=1) as s:
+        st, g = lbm.lbm_coupled_run(s.h, xi, tol, max_iter)
+        assert st == 0, (lbm.status_name(st), s.error())
+        C = s.get(lbm.LBM_FIELD_C)
+    assert np.array_equal(g["picked"], o["picked"])
+    assert np.array_equal(g["iters_fluid"], o["iters_fluid"])
+    assert np.array_equal(g["iters_ad"], o["iters_ad"])
+    assert np.allclose(g["J"], o["J"], rtol=1e-9, atol=0)
+    assert np.abs(C - o["C"]).max() < 1e-9

@@ -416,3 +416,59 @@ def test_monod_steady_sink_matches_oracle(gpu_lib):
     assert abs(ai["sink_total"] - sink) / sink < 1e-8
     act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
     assert np.abs(C - ao["C"])[act].max() < 1e-9
+
+
+@pytest.mark.parametrize("storage,outlet,K", [(FP64, 0, 0.0), (FP64, 1, 0.4), (FP32S, 0, 0.0),
+                                              (FP16S, 1, 0.0)],
+                         ids=["fp64-zg", "fp64-dirichlet-monod", "fp32s-zg", "fp16s-dirichlet"])
+def test_ad_d2q9_fixed_steps(gpu_lib, storage, outlet, K):
+    """The paper's substrate LBM: D2Q9 with the Eq. 5 equilibrium, against
+    the oracle's, from identical starting states (populations and C)."""
+    lbm = gpu_lib
+    w = C1
+    cls = masks(w, lbm)
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    _, U, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], 400)
+    k = 5e-3
+    with _solver(lbm, cls, w, storage, outlet=outlet, c_out=0.25, k_sink=k, k_half=K,
+                 ad_lattice=1) as s:
+        assert s and lbm.lbm_solver_set_u(s.h, U) == 0
+        g_or = O.ad_init(cls, U, w["c_in"], lat=O.D2Q9)
+        done = 0
+        for n in (1, 10, 200):
+            st, _ = s.steps(lbm.LBM_SOLVER_AD, n - done, cold=(done == 0))
+            assert st == 0, s.error()
+            g_or, _ = O.ad_run(cls, g_or, U, w["D"], w["c_in"], k, n - done, outlet, 0.25,
+                               lat=O.D2Q9, k_half=K)
+            done = n
+            G = s.get(lbm.LBM_FIELD_G)
+            C = s.get(lbm.LBM_FIELD_C)
+            C_or = O.ad_moment(cls, g_or, k, lat=O.D2Q9, k_half=K)
+            assert G.shape[0] == 9
+            assert _pop_ok(storage, G, g_or, act, n), (n, rel_l2(G, g_or, act))
+            assert rel_l2(C, C_or, act) < FIELD_TOL[storage], (n, rel_l2(C, C_or, act))
+
+
+def test_ad_d2q9_steady_matches_oracle(gpu_lib):
+    """FP64 steady D2Q9 substrate solve: iterations, inflow, outflow and
+    consumption (the Dirichlet faces carry the second-order terms) and the
+    field, against the oracle; and the balance in - out = consumed."""
+    lbm = gpu_lib
+    w = inputs.scaled(C1, 96, 40, r_min=2, r_max=4, solid=0.2, seed=5, tau=0.8, u_in=0.02,
+                      D=0.1, k=5e-3)
+    cls = masks(w, lbm)
+    with _solver(lbm, cls, w, FP64, ad_lattice=1) as s:
+        st, fi = s.fluid(1e-9, 100000)
+        assert st == 0, s.error()
+        st, ai = s.ad(1e-11, 200000)
+        assert st == 0, s.error()
+        C = s.get(lbm.LBM_FIELD_C)
+    assert abs(ai["flux_in"] - ai["flux_out"] - ai["sink_total"]) / ai["sink_total"] < 1e-6
+    fo = O.fluid_solve(cls, w["tau"], w["u_in"], 1e-9, 100000)
+    ao = O.ad_solve(cls, fo["U"], w["D"], w["c_in"], w["k"], 1e-11, 200000, lat=O.D2Q9)
+    fin, fout, sink = O.ad_fluxes(cls, ao["g"], w["c_in"], w["k"], lat=O.D2Q9, u=fo["U"])
+    assert ao["status"] == "OK" and ao["iters"] == ai["iters"]
+    for got, want in ((ai["flux_in"], fin), (ai["flux_out"], fout), (ai["sink_total"], sink)):
+        assert abs(got - want) <= 1e-8 * abs(want), (got, want)
+    act = np.isin(cls.ravel(), [O.FLUID, O.BIOFILM])
+    assert np.abs(C - ao["C"])[act].max() < 1e-9
