@@ -371,6 +371,11 @@ def main():
     ap.add_argument("--updates", type=int, default=0, help="coupled loop: growth updates")
     ap.add_argument("--compare-storage", default="", choices=[""] + sorted(STORAGES),
                     help="coupled loop: repeat in this storage and compare")
+    ap.add_argument("--ad-lattice", default="d2q5", choices=["d2q5", "d2q9"],
+                    help="2-D substrate lattice: D2Q5 with the linear equilibrium, or the "
+                         "paper's D2Q9 with the Eq. 5 equilibrium")
+    ap.add_argument("--k-half", type=float, default=0.0,
+                    help="Monod half-saturation of the biofilm sink (0: first order)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling run: this many fluid and substrate steps of the workload "
                          "and a 1 GiB copy (counter calibration) instead of the solves")
@@ -410,8 +415,12 @@ def main():
     ctx = lbm.lbm_ctx_create(0, torch.cuda.current_stream().cuda_stream)
     if args.profile_steps:
         return profile_main(args, lbm, ctx, cls, w, storage)
+    ad9 = args.ad_lattice == "d2q9"
+    if ad9 and w["nz"] > 1:
+        sys.exit("--ad-lattice d2q9 is a 2-D option")
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
-                        storage=storage, stall_checks=args.stall_checks)
+                        storage=storage, stall_checks=args.stall_checks, k_half=args.k_half,
+                        ad_lattice=int(ad9))
     s = lbm.lbm_solver_create(ctx, cls, p)
 
     def one_step():
@@ -438,7 +447,7 @@ def main():
     value = upd / el / 1e6
     sf, fi, sa, ai = recs[-1]
     dim = 3 if w["nz"] > 1 else 2
-    qf, qa = (19, 7) if dim == 3 else (9, 5)
+    qf, qa = (19, 7) if dim == 3 else (9, 9 if ad9 else 5)
     sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
     cb = 8 if storage == 3 else 4
     # dominant kernel: fluid step; HIP-event time over its launches in the timed
@@ -464,7 +473,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.storage], "data": "synthetic",
         "config": {"workload": w["name"], "grid": [w["nx"], w["ny"], w["nz"]],
                    "storage": args.storage, "tau": w["tau"], "u_in": w["u_in"], "D": w["D"],
-                   "k_sink": w["k"], "tol": w["tol"], "seed": w["seed"],
+                   "k_sink": w["k"], "k_half": args.k_half,
+                   "substrate_lattice": "d3q7" if dim == 3 else args.ad_lattice,
+                   "tol": w["tol"], "seed": w["seed"],
                    "fluid_status": lbm.status_name(sf), "fluid_iters": fi["iters"],
                    "ad_status": lbm.status_name(sa), "ad_iters": ai["iters"],
                    "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"]},

@@ -90,7 +90,9 @@ lbm_status upload_desc_words(lbm_solver *s)
 void count_active(lbm_solver *s)
 {
     int64_t nf = 0, na = 0;
-    const int aab = lbmk::desc_ad_active_bit(s->qf, s->qa);
+    // the shared words carry the D2Q5 / D3Q7 substrate bits whatever the
+    // substrate lattice: the same active nodes
+    const int aab = lbmk::desc_ad_active_bit(s->qf, s->dim == 3 ? 7 : 5);
     for (uint32_t d : s->desc_h) {
         nf += d & 1u;
         na += (d >> aab) & 1u;
