@@ -127,7 +127,7 @@ typedef struct {
     int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
                              1000 otherwise; < 0 disables */
     double k_half;        /* 0: first-order sink k_sink C per step on BIOFILM nodes.
-                             > 0: the Monod form of the consumption rate (Eq. 13,
+                             > 0: the Monod form of the consumption rate (Eq. 16,
                              its mediator factor folded into k_sink), k_sink C /
                              (C + k_half), C the concentration a step collides with;
                              needs k_sink < k_half.  Zero-initialised parameters keep

@@ -19,7 +19,7 @@
  *   - advection-diffusion BGK step [Sec. 2.1.2, Eqs. 12-13] with the frozen
  *     fluid velocity, zero-flux solids, Dirichlet inlet, zero-gradient or
  *     Dirichlet outlet and a sink on biofilm nodes, first order or of the
- *     Monod form of the consumption rate (Eq. 13);
+ *     Monod form of the consumption rate (Eq. 16);
  *   - the flow domain: FLUID nodes linked to the outlet column (closed
  *     pores carry no steady flow; reading of Sec. 2.1.1 on the Sec. 3 pore
  *     space);
@@ -202,7 +202,7 @@ static uint8_t *flow_domain(int nx, int ny, int nz, const uint8_t *cls);
 
 /* Substrate consumed in one step by a biofilm node at concentration C.
  * First order, k C, when k_half <= 0; otherwise the Monod form of the
- * consumption rate (Eq. 13 with the mediator factor folded into k),
+ * consumption rate (Eq. 16 with the mediator factor folded into k),
  * k C / (C + k_half): k is the rate at saturation, k_half the half-
  * saturation concentration. */
 static double consumed(double C, double k, double k_half)

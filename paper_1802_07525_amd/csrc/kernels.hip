@@ -355,7 +355,7 @@ struct CheckAcc {
 
 // ------------------------------------------------------------- the sink
 // Consumption of one step on a BIOFILM node that collides with C: first
-// order k C, or (kh > 0) the Monod form of the consumption rate
+// order k C, or (kh > 0) the Monod form of the consumption rate (Eq. 16)
 // k C / (C + kh) -- k the rate at saturation, kh the half-saturation
 // concentration (the mediator factor of the double Monod rate is in k).
 template <class T>

@@ -210,7 +210,7 @@ def test_ad_closed_box_sink_removes_exactly_kC():
 
 
 def test_ad_closed_box_monod_sink_removes_exactly_q():
-    """The Monod form of the consumption rate (Eq. 13, mediator factor in
+    """The Monod form of the consumption rate (Eq. 16, mediator factor in
     k): in a periodic box each step removes sum over biofilm nodes of
     k C / (C + K), C the concentration the step collides with."""
     cls = O.biofilm_layer(_porous(48, 24, 3))
