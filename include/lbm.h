@@ -347,6 +347,83 @@ lbm_status lbm_coupled_run(lbm_solver *s, int n_updates, const double *xi, doubl
                            int64_t max_iter, int64_t *picked, double *J, double *J_accum,
                            int64_t *iters_fluid, int64_t *iters_ad);
 
+/* ------------------------------------------------- bio-electrochemistry */
+/* The MFC outputs of Sec. 2.2 (Eqs. 14-21), computed once per model
+ * interval (one hour, Sec. 3) after the two steady solves (model loop of
+ * Sec. 2, step 4).  Every cell holding biomass carries its biomass
+ * concentration C_bio and its oxidised intracellular mediator M_ox (per unit
+ * biomass; M_red = M_total - M_ox, Eq. 14).  One interval, from the
+ * solver's current substrate field C:
+ *   - double-Monod consumption (Eq. 16) q_a = q_max S/(S + K_s) *
+ *     M_ox/(M_ox + K_Mox), with S = c_scale * max(C, 0) in mg/L;
+ *   - the mediator balance of Eq. 15 over the interval with q_a and the
+ *     current taken at the new state: per cell M = M0 - Y q_a(M) dt +
+ *     gamma I dt / (m F B), B = sum of C_bio * V_a / N over the cells (the
+ *     total biomass, N the lattice cells), capped at M_total;
+ *   - the cell current of Eq. 20 with the overpotentials of Eqs. 18-19 at
+ *     the biomass-weighted mean mediator: the unique root of I = max(0,
+ *     I_20(I)) on [0, E0 / (R_int + R_ext)], by bisection (at most 80
+ *     halvings, to adjacent doubles).
+ * Units: mg, L, day (q_max), hour (dt_hours), A, V, ohm, m^2, K. */
+typedef struct {
+    double q_max;     /* maximum consumption rate, mg substrate / (mg biomass day) */
+    double K_s;       /* substrate half-saturation, mg/L, > 0 */
+    double M_total;   /* total intracellular mediator, mg mediator / mg biomass, > 0 */
+    double K_Mox;     /* oxidised-mediator half-saturation, same unit, > 0 */
+    double Y;         /* mediator yield, mg mediator / mg substrate */
+    double gamma;     /* mediator molar mass, mg / mol */
+    double m;         /* electrons per mediator reduction */
+    double I0;        /* exchange current density, A / m^2 */
+    double E0;        /* open-circuit voltage, V */
+    double R_ext;     /* external load, ohm */
+    double R_int;     /* internal resistance, ohm */
+    double A_a;       /* anode surface area, m^2 */
+    double V_a;       /* anode compartment volume, L */
+    double T;         /* temperature, K */
+    double eps;       /* current bound at low M_red (Eq. 20), mg mediator / mg biomass, >= 0 */
+    double C0_bio;    /* biomass given to BIOFILM cells when none is passed, mg/L */
+    double c_scale;   /* mg/L per lattice concentration unit */
+    double dt_hours;  /* model interval, h */
+} lbm_bio_params;
+
+typedef struct {
+    double I_cell;    /* A */
+    double V_cell;    /* load voltage I R_ext, V (the left side of Eq. 17) */
+    double V_total;   /* I (R_int + R_ext), V (Eq. 21) */
+    double n_conc;    /* Eq. 18, V (+inf when no mediator is reduced) */
+    double n_act;     /* Eq. 19, V */
+    double M_ox;      /* biomass-weighted mean after the interval */
+    double M_red;     /* M_total - M_ox */
+    double biomass;   /* B, mg */
+    double q_total;   /* substrate consumed at the new state, mg / h */
+    int32_t n_cells;  /* cells holding biomass */
+    int32_t root_iters; /* bisection halvings taken */
+} lbm_bio_out;
+
+typedef struct lbm_bio lbm_bio;
+enum { LBM_BIO_CBIO = 0, LBM_BIO_MOX = 1 };
+
+/* Attach a bio-electrochemical state to solver s (which must outlive it).
+ * c_bio: host double [N] biomass in mg/L, >= 0, nonzero only on BIOFILM
+ * nodes, or NULL for C0_bio on every BIOFILM node.  m_ox: host double [N]
+ * in [0, M_total] where c_bio > 0, or NULL for M_total (fully oxidised).
+ * EINVAL for invalid parameters or fields; ENOMEM if device memory is
+ * short.  Device memory: 28 bytes per biomass cell plus 8 per node. */
+lbm_status lbm_bio_create(lbm_solver *s, const lbm_bio_params *p, const double *c_bio,
+                          const double *m_ox, lbm_bio **out);
+/* One interval on the solver's current substrate state (EINVAL before any
+ * substrate solve).  Updates M_ox of every biomass cell; *out may be NULL.
+ * Synchronises the solver's stream. */
+lbm_status lbm_bio_step(lbm_bio *b, lbm_bio_out *out);
+/* Field LBM_BIO_CBIO or LBM_BIO_MOX as host double [N] (0 where no biomass). */
+lbm_status lbm_bio_get(lbm_bio *b, int field, double *dst);
+/* Set C_bio and M_ox of n nodes (host arrays; the same rules as create, and
+ * c_bio = 0 removes a cell's biomass).  Call after growth has changed the
+ * solver's cells. */
+lbm_status lbm_bio_set(lbm_bio *b, const int64_t *nodes, const double *c_bio, const double *m_ox,
+                       int64_t n);
+void lbm_bio_destroy(lbm_bio *b);
+
 /* ------------------------------------------------------------- serving */
 /* Continuous batching of 2-D steady solves (D2Q9 fluid, then D2Q5
  * substrate in the exported velocity) -- the model loop's steps 2 and 3

@@ -99,6 +99,23 @@ class lbm_server_stats_t(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lbm_bio_params(ct.Structure):
+    _fields_ = [(k, ct.c_double) for k in (
+        "q_max", "K_s", "M_total", "K_Mox", "Y", "gamma", "m", "I0", "E0", "R_ext", "R_int",
+        "A_a", "V_a", "T", "eps", "C0_bio", "c_scale", "dt_hours")]
+
+
+class lbm_bio_out(ct.Structure):
+    _fields_ = [(k, ct.c_double) for k in (
+        "I_cell", "V_cell", "V_total", "n_conc", "n_act", "M_ox", "M_red", "biomass",
+        "q_total")] + [("n_cells", ct.c_int32), ("root_iters", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+LBM_BIO_CBIO, LBM_BIO_MOX = 0, 1
+
 P, I32, I64, U64, D, SZ = (ct.c_void_p, ct.c_int, ct.c_int64, ct.c_uint64, ct.c_double,
                            ct.c_size_t)
 G = lbm_grid
@@ -137,6 +154,11 @@ _SIGS = {
     "lbm_solver_get_state": (I32, [P, P, SZ]),
     "lbm_solver_put_state": (I32, [P, P, SZ]),
     "lbm_coupled_run": (I32, [P, I32, P, D, I64, P, P, P, P, P]),
+    "lbm_bio_create": (I32, [P, P, P, P, P]),
+    "lbm_bio_step": (I32, [P, P]),
+    "lbm_bio_get": (I32, [P, I32, P]),
+    "lbm_bio_set": (I32, [P, P, P, P, I64]),
+    "lbm_bio_destroy": (None, [P]),
     "lbm_copy_bandwidth": (I32, [P, SZ, I32, P, P]),
     "lbm_server_footprint": (SZ, [I32, I32, I32]),
     "lbm_server_create": (I32, [P, P, P]),
@@ -454,6 +476,57 @@ def lbm_coupled_run(s, xi, tol, max_iter):
     st = load().lbm_coupled_run(s, M, _p(xi), float(tol), int(max_iter), _p(picked), _p(J),
                                 ct.byref(acc), _p(itf), _p(ita))
     return st, dict(picked=picked, J=J, J_accum=acc.value, iters_fluid=itf, iters_ad=ita)
+
+
+# ------------------------------------------------- bio-electrochemistry
+def make_bio_params(c_scale, **kw):
+    """Parameters of the bio-electrochemical model (Sec. 2.2).  Defaults:
+    Table 1, with T = 298.15 K, eps = 0.01 M_total, A_a = 48 x 65 mm^2 and
+    V_a = 17 x 60 x 65 mm^3; c_scale is mg/L per lattice concentration unit."""
+    M_total = kw.pop("M_total", 0.05)
+    v = dict(q_max=8.48, K_s=20.0, M_total=M_total, K_Mox=0.02 * M_total, Y=0.5687,
+             gamma=663400.0, m=2.0, I0=1e-3, E0=0.7, R_ext=360.0, R_int=360.0,
+             A_a=48e-3 * 65e-3, V_a=17 * 60 * 65 * 1e-6, T=298.15, eps=0.01 * M_total,
+             C0_bio=450.0, c_scale=float(c_scale), dt_hours=1.0)
+    for k, x in kw.items():
+        if k not in v:
+            raise KeyError(k)
+        v[k] = float(x)
+    return lbm_bio_params(**v)
+
+
+def lbm_bio_create(s, params, c_bio=None, m_ox=None, ctx=None):
+    h = ct.c_void_p()
+    cb = None if c_bio is None else _f64(np.asarray(c_bio).reshape(-1))
+    mo = None if m_ox is None else _f64(np.asarray(m_ox).reshape(-1))
+    st = load().lbm_bio_create(s, ct.byref(params), _p(cb), _p(mo), ct.byref(h))
+    if st:
+        raise LBMError(st, lbm_last_error(ctx) if ctx else "")
+    return h
+
+
+def lbm_bio_step(b):
+    o = lbm_bio_out()
+    st = load().lbm_bio_step(b, ct.byref(o))
+    return st, o.as_dict()
+
+
+def lbm_bio_get(b, field, n_nodes):
+    out = np.zeros(int(n_nodes))
+    st = load().lbm_bio_get(b, int(field), _p(out))
+    if st:
+        raise LBMError(st)
+    return out
+
+
+def lbm_bio_set(b, nodes, c_bio, m_ox):
+    nodes = np.ascontiguousarray(nodes, np.int64)
+    c_bio, m_ox = _f64(c_bio), _f64(m_ox)
+    return load().lbm_bio_set(b, _p(nodes), _p(c_bio), _p(m_ox), len(nodes))
+
+
+def lbm_bio_destroy(b):
+    load().lbm_bio_destroy(b)
 
 
 class Solver:

@@ -56,6 +56,11 @@ void build_desc(const lbm_grid &g, const uint8_t *cls, const std::vector<uint8_t
 void build_desc(const lbm_grid &g, const uint8_t *cls, uint32_t *desc);
 int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, double xi);
 
+// ---- solver services (solver.cpp) ---------------------------------------
+// enqueue the substrate concentration of every node (FP64, the value each
+// node collides with) into device memory dst [N] on the solver's stream
+lbm_status export_c_device(lbm_solver *s, double *dst);
+
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
 lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);

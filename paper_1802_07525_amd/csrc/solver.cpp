@@ -543,6 +543,16 @@ size_t state_size(const lbm_solver *s)
 
 } // namespace
 
+lbm_status lbmh::export_c_device(lbm_solver *s, double *dst)
+{
+    if (!s->ad_ready)
+        return set_err(s->ctx, LBM_EINVAL, "substrate state not initialised");
+    HIPCHK(lbmk::ad_export(ad_lay(s), s->p.storage, s->d_g[s->gcur], ad_desc(s), s->geo, ref_cur(s, 1),
+                           lbmk::Sink{s->p.k_sink, s->p.k_half}, dst, 1, s->ctx->stream),
+           "export");
+    return LBM_OK;
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 

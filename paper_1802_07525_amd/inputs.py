@@ -4,8 +4,9 @@ This module holds no lattice arithmetic.  It names the workloads (grid,
 electrode generator settings, relaxation times, inflow, sink, tolerance and
 seed) and draws the random inputs both the HIP path and the oracle receive:
 random population states for fixed-step comparisons, the uniform numbers of
-the biofilm growth draws, and the parameters and arrival times of a served
-request stream.  Each side builds its electrode mask itself from the
+the biofilm growth draws, the parameters and arrival times of a served
+request stream, and the biomass and mediator fields and Table 1 values of
+the bio-electrochemical model.  Each side builds its electrode mask itself from the
 generator settings and seed here.
 
 Substrate diffusivities are given directly as D = c_s^2 (tau_D - 1/2)
@@ -78,6 +79,42 @@ def random_velocity(dim, n, seed, amp=0.02):
 def growth_draws(count, seed):
     """Uniform numbers in [0, 1) for the biofilm growth picks."""
     return np.random.default_rng(seed).random(count)
+
+
+# Bio-electrochemical model (Sec. 2.2): Table 1's values (mg, L, day, A, V,
+# ohm) and the values Table 1 does not give -- temperature 298.15 K,
+# eps = 0.01 M_total, the electrode's projected face 48 x 65 mm as A_a and
+# the compartment 17 x 60 x 65 mm as V_a.  The lattice concentration c_in
+# stands for Table 1's inflow of 410 mg/L.
+BIO_TABLE1 = dict(q_max=8.48, K_s=20.0, M_total=0.05, K_Mox=0.02 * 0.05, Y=0.5687,
+                  gamma=663400.0, m=2.0, I0=1e-3, E0=0.7, R_ext=360.0, R_int=360.0,
+                  A_a=48e-3 * 65e-3, V_a=17 * 60 * 65 * 1e-6, T=298.15, eps=0.01 * 0.05,
+                  C0_bio=450.0, dt_hours=1.0)
+BIO_CIN_MG_L = 410.0
+
+
+def bio_params(c_in, **over):
+    """BIO_TABLE1 with c_scale = 410 mg/L / c_in, plus overrides."""
+    d = dict(BIO_TABLE1)
+    d["c_scale"] = BIO_CIN_MG_L / c_in
+    d.update(over)
+    return d
+
+
+def biomass_field(cls, seed, c0=450.0, spread=0.5, biofilm=3):
+    """C_bio per node: c0 * U[1 - spread, 1 + spread) on BIOFILM nodes, 0
+    elsewhere."""
+    flat = np.asarray(cls).reshape(-1)
+    rng = np.random.default_rng(seed)
+    r = c0 * (1.0 - spread + 2.0 * spread * rng.random(flat.size))
+    return np.where(flat == biofilm, r, 0.0)
+
+
+def mediator_field(cls, seed, m_total=0.05, biofilm=3):
+    """M_ox per node: U[0, m_total) on BIOFILM nodes, 0 elsewhere."""
+    flat = np.asarray(cls).reshape(-1)
+    r = m_total * np.random.default_rng(seed).random(flat.size)
+    return np.where(flat == biofilm, r, 0.0)
 
 
 def serve_requests(n, rate, seed=SERVE_SEED):
