@@ -424,6 +424,72 @@ lbm_status lbm_bio_set(lbm_bio *b, const int64_t *nodes, const double *c_bio, co
                        int64_t n);
 void lbm_bio_destroy(lbm_bio *b);
 
+/* ------------------------------------------------------ biofilm formation */
+/* The agent-based biofilm of Sec. 2.3, once per model interval after the
+ * bio-electrochemical update (model loop of Sec. 2, step 5), on the
+ * solver's current substrate field and the bio state's biomass C_bio and
+ * mediator M_ox:
+ *   1. attachment: min(k_ata, front size) cells drawn without replacement
+ *      (partial Fisher-Yates shuffle of the front in ascending node order)
+ *      get C_bio = C0_bio and M_ox = M_total.  The front is the FLUID nodes
+ *      with a SOLID neighbour among the fluid lattice's directions, outside
+ *      the inlet and outlet columns;
+ *   2. growth: C_bio += C_bio Y_bio q_a dt (q_a of Eq. 16, per day, at the
+ *      current substrate and mediator; M_ox per unit biomass unchanged);
+ *   3. spreading, one ascending pass over the nodes: a node whose C_bio
+ *      exceeds C_max when visited passes fr_spr C_bio, with its M_ox, to a
+ *      free neighbour drawn uniformly (free: FLUID outside the inlet and
+ *      outlet columns).  With none free, a loop-erased random walk through
+ *      BIOFILM nodes (uniform direction per step; a step into SOLID, WALL or
+ *      off the grid is spent in place) finds a free node within max_walk
+ *      steps, the biomass and mediator along its path move one node outward,
+ *      and the initial node's neighbour on the path receives the share;
+ *      otherwise nothing spreads.
+ * Every node that gains biomass becomes BIOFILM (lbm_solver_update_cells).
+ * Random numbers: the SplitMix64 stream of `seed` in the order above,
+ * u = (x >> 11) 2^-53, an index in [0, m) is floor(u m). */
+typedef struct {
+    int32_t k_ata;     /* front cells attached per interval (Table 1: 200) */
+    double C_max;      /* spreading threshold, mg/L (512.5) */
+    double fr_spr;     /* fraction of the biomass a spreading moves (0.4) */
+    int32_t max_walk;  /* random-walk steps before a spreading is given up */
+    double Y_bio;      /* biomass per consumed substrate, mg/mg (not in Table 1;
+                          1: the growth rate per unit biomass is q_a) */
+} lbm_biofilm_params;
+
+typedef struct {
+    int32_t attached;    /* cells attached */
+    int32_t spread;      /* spreading events */
+    int32_t walks;       /* spreading attempts that needed a random walk */
+    int32_t abandoned;   /* walks that found no free node */
+    int32_t new_biofilm; /* nodes turned BIOFILM */
+    int32_t cells;       /* nodes holding biomass afterwards */
+    double biomass;      /* mg, afterwards */
+} lbm_biofilm_stats;
+
+/* One interval of attachment, growth and spreading.  EINVAL for bad
+ * parameters, before any substrate solve, or when the new BIOFILM nodes
+ * would stop the mask from percolating (nothing is changed then).
+ * *st may be NULL. */
+lbm_status lbm_biofilm_step(lbm_bio *b, const lbm_biofilm_params *p, uint64_t seed,
+                            lbm_biofilm_stats *st);
+
+typedef struct {
+    int32_t status_fluid, status_ad;  /* lbm_status of the two solves */
+    int64_t iters_fluid, iters_ad;
+    lbm_bio_out bio;
+    lbm_biofilm_stats film;
+} lbm_mfc_interval;
+
+/* The model loop of Sec. 2 for n_hours intervals (one hour each, Sec. 3):
+ * fluid and substrate solves to tol (cold in the first interval, warm
+ * after), lbm_bio_step, then lbm_biofilm_step with the interval's seed,
+ * output h of the SplitMix64 stream of `seed`.  series: n_hours records.
+ * Stops at the first error (a diverged solve, or growth that would close
+ * the flow path: EINVAL), returning it; earlier records stay valid. */
+lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *p, int n_hours, uint64_t seed,
+                       double tol, int64_t max_iter, lbm_mfc_interval *series);
+
 /* ------------------------------------------------------------- serving */
 /* Continuous batching of 2-D steady solves (D2Q9 fluid, then D2Q5
  * substrate in the exported velocity) -- the model loop's steps 2 and 3

@@ -29,9 +29,11 @@ Readings (the paper is silent or ambiguous):
   - Attachment draws min(k_ata, front size) cells without replacement (a
     partial Fisher-Yates shuffle of the front in ascending node order).  An
     attached cell starts with C0_bio and fully oxidised mediator (M_total).
-  - Growth: C_bio += C_bio q_a dt, q_a of Eq. 16 (per day) from the current
-    substrate field and mediator; no biomass yield is given, so the growth
-    rate per unit biomass is q_a.  Attached cells grow in the same interval.
+  - Growth: C_bio += C_bio Y_bio q_a dt, q_a of Eq. 16 (per day) from the
+    current substrate field and mediator.  The paper gives no biomass yield;
+    Y_bio = 1 (growth rate per unit biomass = q_a) reads the text literally,
+    and with Table 1's q_max it grows a cell by up to ~35% an hour.  Attached
+    cells grow in the same interval.
   - Spreading visits nodes once in ascending order and acts on a node whose
     biomass exceeds C_max when it is visited.  A free neighbour is drawn
     uniformly among the free neighbours.  The walk steps in a uniformly drawn
@@ -90,7 +92,7 @@ def biofilm_step(cls, C, cbio, mox, bp, fp, seed):
     cls: class mask (shape (ny, nx) or (nz, ny, nx)); C: substrate field
     (lattice units, every node, before this step's changes); cbio, mox:
     biomass and M_ox per node; bp: bio-electrochemical parameters (Table 1);
-    fp: dict(k_ata, C_max, fr_spr, max_walk); seed: the interval's seed.
+    fp: dict(k_ata, C_max, fr_spr, max_walk, Y_bio); seed: the interval's seed.
     Returns (cls, cbio, mox, stats) as new arrays."""
     shape = cls.shape
     nz, ny, nx = (1,) + shape if len(shape) == 2 else shape
@@ -134,7 +136,7 @@ def biofilm_step(cls, C, cbio, mox, bp, fp, seed):
     has = cb > 0.0
     S = bp["c_scale"] * np.maximum(C[has], 0.0)
     q = OB.consumption_rate(S, mo[has], bp)
-    cb[has] = cb[has] + dt_day * q * cb[has]
+    cb[has] = cb[has] + dt_day * (fp["Y_bio"] * q) * cb[has]
     # spreading
     spread = walks = abandoned = 0
     for n in range(N):

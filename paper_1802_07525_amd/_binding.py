@@ -116,6 +116,31 @@ class lbm_bio_out(ct.Structure):
 
 LBM_BIO_CBIO, LBM_BIO_MOX = 0, 1
 
+
+class lbm_biofilm_params(ct.Structure):
+    _fields_ = [("k_ata", ct.c_int32), ("C_max", ct.c_double), ("fr_spr", ct.c_double),
+                ("max_walk", ct.c_int32), ("Y_bio", ct.c_double)]
+
+
+class lbm_biofilm_stats(ct.Structure):
+    _fields_ = [("attached", ct.c_int32), ("spread", ct.c_int32), ("walks", ct.c_int32),
+                ("abandoned", ct.c_int32), ("new_biofilm", ct.c_int32), ("cells", ct.c_int32),
+                ("biomass", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lbm_mfc_interval(ct.Structure):
+    _fields_ = [("status_fluid", ct.c_int32), ("status_ad", ct.c_int32),
+                ("iters_fluid", ct.c_int64), ("iters_ad", ct.c_int64),
+                ("bio", lbm_bio_out), ("film", lbm_biofilm_stats)]
+
+    def as_dict(self):
+        return dict(status_fluid=self.status_fluid, status_ad=self.status_ad,
+                    iters_fluid=self.iters_fluid, iters_ad=self.iters_ad,
+                    bio=self.bio.as_dict(), film=self.film.as_dict())
+
 P, I32, I64, U64, D, SZ = (ct.c_void_p, ct.c_int, ct.c_int64, ct.c_uint64, ct.c_double,
                            ct.c_size_t)
 G = lbm_grid
@@ -159,6 +184,8 @@ _SIGS = {
     "lbm_bio_get": (I32, [P, I32, P]),
     "lbm_bio_set": (I32, [P, P, P, P, I64]),
     "lbm_bio_destroy": (None, [P]),
+    "lbm_biofilm_step": (I32, [P, P, U64, P]),
+    "lbm_mfc_run": (I32, [P, P, I32, U64, D, I64, P]),
     "lbm_copy_bandwidth": (I32, [P, SZ, I32, P, P]),
     "lbm_server_footprint": (SZ, [I32, I32, I32]),
     "lbm_server_create": (I32, [P, P, P]),
@@ -527,6 +554,27 @@ def lbm_bio_set(b, nodes, c_bio, m_ox):
 
 def lbm_bio_destroy(b):
     load().lbm_bio_destroy(b)
+
+
+def make_biofilm_params(k_ata=200, C_max=512.5, fr_spr=0.4, max_walk=10000, Y_bio=1.0):
+    """Biofilm formation parameters (Sec. 2.3); defaults from Table 1, and
+    Y_bio = 1 (not in Table 1: growth rate per unit biomass = q_a)."""
+    return lbm_biofilm_params(int(k_ata), float(C_max), float(fr_spr), int(max_walk),
+                              float(Y_bio))
+
+
+def lbm_biofilm_step(b, params, seed):
+    o = lbm_biofilm_stats()
+    st = load().lbm_biofilm_step(b, ct.byref(params), ct.c_uint64(int(seed)), ct.byref(o))
+    return st, o.as_dict()
+
+
+def lbm_mfc_run(b, params, n_hours, seed, tol, max_iter):
+    """The model loop; returns (status, list of per-interval dicts)."""
+    arr = (lbm_mfc_interval * max(int(n_hours), 1))()
+    st = load().lbm_mfc_run(b, ct.byref(params), int(n_hours), ct.c_uint64(int(seed)),
+                            float(tol), int(max_iter), arr)
+    return st, [arr[h].as_dict() for h in range(int(n_hours))]
 
 
 class Solver:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lbm.so")
-SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

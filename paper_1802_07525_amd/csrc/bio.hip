@@ -23,22 +23,6 @@
 
 using namespace lbmh;
 
-struct lbm_bio {
-    lbm_solver *s = nullptr;
-    lbm_bio_params p{};
-    std::vector<double> cb;      // biomass per node, mg/L (host, N)
-    std::vector<double> mox;     // M_ox per node (host mirror, N)
-    std::vector<int32_t> cells;  // nodes holding biomass, ascending
-    bool mox_stale = false;      // the device copy is newer than `mox`
-    size_t cap = 0;              // cells the device arrays hold
-    int32_t *d_idx = nullptr;
-    double *d_cb = nullptr, *d_mox = nullptr, *d_fs = nullptr;
-    double *d_c = nullptr;       // substrate field [N]
-    lbm_bio_out *d_out = nullptr;
-    lbm_bio_out *h_out = nullptr; // pinned
-    double sum_cb = 0.0, biomass = 0.0;
-};
-
 namespace {
 
 constexpr int BIO_THREADS = 1024;
@@ -204,8 +188,10 @@ void free_dev(lbm_bio *b)
     b->cap = 0;
 }
 
+} // namespace
+
 // device M_ox -> host mirror
-lbm_status pull_mox(lbm_bio *b)
+lbm_status lbmh::bio_pull_mox(lbm_bio *b)
 {
     if (!b->mox_stale)
         return LBM_OK;
@@ -223,7 +209,7 @@ lbm_status pull_mox(lbm_bio *b)
 }
 
 // host fields -> compact cell list, totals and device arrays
-lbm_status push_cells(lbm_bio *b)
+lbm_status lbmh::bio_push_cells(lbm_bio *b)
 {
     const size_t N = b->cb.size();
     b->cells.clear();
@@ -265,8 +251,6 @@ lbm_status push_cells(lbm_bio *b)
     }
     return LBM_OK;
 }
-
-} // namespace
 
 extern "C" {
 
@@ -323,7 +307,7 @@ lbm_status lbm_bio_create(lbm_solver *s, const lbm_bio_params *p, const double *
         lbm_bio_destroy(b);
         return set_err(s->ctx, LBM_ENOMEM, "bio state");
     }
-    lbm_status st = push_cells(b);
+    lbm_status st = bio_push_cells(b);
     if (st) {
         lbm_bio_destroy(b);
         return st;
@@ -391,7 +375,7 @@ lbm_status lbm_bio_get(lbm_bio *b, int field, double *dst)
         memcpy(dst, b->cb.data(), b->cb.size() * 8);
         return LBM_OK;
     }
-    lbm_status st = pull_mox(b);
+    lbm_status st = bio_pull_mox(b);
     if (st)
         return st;
     memcpy(dst, b->mox.data(), b->mox.size() * 8);
@@ -411,14 +395,14 @@ lbm_status lbm_bio_set(lbm_bio *b, const int64_t *nodes, const double *c_bio, co
         if (!msg.empty())
             return set_err(b->s->ctx, LBM_EINVAL, msg);
     }
-    lbm_status st = pull_mox(b);
+    lbm_status st = bio_pull_mox(b);
     if (st)
         return st;
     for (int64_t i = 0; i < n; ++i) {
         b->cb[(size_t)nodes[i]] = c_bio[i];
         b->mox[(size_t)nodes[i]] = c_bio[i] > 0.0 ? m_ox[i] : 0.0;
     }
-    return push_cells(b);
+    return bio_push_cells(b);
 }
 
 } // extern "C"

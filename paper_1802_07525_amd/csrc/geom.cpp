@@ -54,23 +54,6 @@ bool ad_blocked(uint8_t k)
     return k == LBM_SOLID || k == LBM_WALL;
 }
 
-// ---- SplitMix64 (Steele, Lea & Flood 2014) ------------------------------
-struct SplitMix64 {
-    uint64_t state;
-    uint64_t next()
-    {
-        state += 0x9E3779B97F4A7C15ULL;
-        uint64_t z = state;
-        z ^= z >> 30;
-        z *= 0xBF58476D1CE4E5B9ULL;
-        z ^= z >> 27;
-        z *= 0x94D049BB133111EBULL;
-        return z ^ (z >> 31);
-    }
-    // integer in [lo, hi] by modulo of one draw
-    int64_t pick(int64_t lo, int64_t hi) { return lo + (int64_t)(next() % (uint64_t)(hi - lo + 1)); }
-};
-
 static inline int64_t idx3(const lbm_grid &g, int64_t x, int64_t y, int64_t z)
 {
     return x + (int64_t)g.nx * (y + (int64_t)g.ny * z);

@@ -19,6 +19,23 @@ struct lbm_ctx {
 
 namespace lbmh {
 
+// ---- SplitMix64 (Steele, Lea & Flood 2014) ------------------------------
+struct SplitMix64 {
+    uint64_t state;
+    uint64_t next()
+    {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z ^= z >> 30;
+        z *= 0xBF58476D1CE4E5B9ULL;
+        z ^= z >> 27;
+        z *= 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    // integer in [lo, hi] by modulo of one draw
+    int64_t pick(int64_t lo, int64_t hi) { return lo + (int64_t)(next() % (uint64_t)(hi - lo + 1)); }
+};
+
 // ---- host geometry (geom.cpp) -------------------------------------------
 struct Dirs {
     int q;
@@ -113,3 +130,27 @@ struct lbm_solver {
     hipEvent_t ev_ring[8] = {};
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };
+
+// bio-electrochemical state beside a solver (bio.hip; biofilm.cpp changes it)
+struct lbm_bio {
+    lbm_solver *s = nullptr;
+    lbm_bio_params p{};
+    std::vector<double> cb;      // biomass per node, mg/L (host, N)
+    std::vector<double> mox;     // M_ox per node (host mirror, N)
+    std::vector<int32_t> cells;  // nodes holding biomass, ascending
+    bool mox_stale = false;      // the device copy is newer than `mox`
+    size_t cap = 0;              // cells the device arrays hold
+    int32_t *d_idx = nullptr;
+    double *d_cb = nullptr, *d_mox = nullptr, *d_fs = nullptr;
+    double *d_c = nullptr;       // substrate field [N]
+    lbm_bio_out *d_out = nullptr;
+    lbm_bio_out *h_out = nullptr; // pinned
+    double sum_cb = 0.0, biomass = 0.0;
+};
+
+
+namespace lbmh {
+// device M_ox -> host mirror; host fields -> cell list, totals, device (bio.hip)
+lbm_status bio_pull_mox(lbm_bio *b);
+lbm_status bio_push_cells(lbm_bio *b);
+} // namespace lbmh

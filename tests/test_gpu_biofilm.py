@@ -1,0 +1,145 @@
+"""Agent-based biofilm (Sec. 2.3) and the model loop (Sec. 2) through the
+C ABI against the FP64 oracle.
+
+Classes, attachment and spreading decisions, walk counts and iteration
+counts must agree exactly: they are integer outcomes of the same draws and
+of FP64 comparisons whose operands agree to ~1e-12 on both sides (no value
+lies that close to C_max here).  Biomass and mediator fields agree to
+1e-10 relative (growth at rates computed from fields that agree to
+~1e-12), the electrical outputs as in the interval tests.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.bioelec as OB
+import oracle.biofilm as BF
+from helpers import masks
+from paper_1802_07525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64 = 3
+C1 = inputs.WORKLOADS["c1"]
+FILM = dict(k_ata=25, C_max=512.5, fr_spr=0.4, max_walk=10000, Y_bio=1.0)
+# a milder yield keeps this medium open for three intervals of spreading
+FILM_STEPS = dict(FILM, Y_bio=0.2)
+COUNTS = ("attached", "spread", "walks", "abandoned", "new_biofilm", "cells")
+
+
+def _solver(lbm, cls, w):
+    return lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                      storage=FP64)
+
+
+def _fields_close(a, b, rtol):
+    return np.all(np.abs(a - b) <= rtol * np.maximum(np.abs(b), 1e-300))
+
+
+def test_biofilm_steps_match_oracle(gpu_lib):
+    """Three intervals of bio update + attachment, growth and spreading on a
+    fixed-step substrate field, from biomass partly above C_max."""
+    lbm = gpu_lib
+    w = inputs.scaled(C1, 128, 64, seed=21)
+    cls = masks(w, lbm)
+    N = cls.size
+    bp = inputs.bio_params(w["c_in"])
+    cb = inputs.biomass_field(cls, seed=81, c0=450.0, spread=0.3)
+    mo = inputs.mediator_field(cls, seed=82, m_total=bp["M_total"])
+    assert (cb > FILM["C_max"]).sum() > 10
+    seeds = [901, 902, 903]
+    nf, na = 1000, 1000
+    print("biofilm steps 128x64", flush=True)
+    got = []
+    with _solver(lbm, cls, w) as s:
+        assert s.steps(0, nf, 1)[0] == 0
+        assert lbm.lbm_solver_export_u(s.h) == 0
+        assert s.steps(1, na, 1)[0] == 0
+        b = lbm.lbm_bio_create(s.h, lbm.make_bio_params(**bp), cb, mo, s.ctx)
+        try:
+            fp = lbm.make_biofilm_params(**FILM_STEPS)
+            for sd in seeds:
+                st, bo = lbm.lbm_bio_step(b)
+                assert st == 0, s.error()
+                st, fo = lbm.lbm_biofilm_step(b, fp, sd)
+                assert st == 0, s.error()
+                got.append((bo, fo, s.get(lbm.LBM_FIELD_CLASS).copy(),
+                            lbm.lbm_bio_get(b, lbm.LBM_BIO_CBIO, N),
+                            lbm.lbm_bio_get(b, lbm.LBM_BIO_MOX, N)))
+        finally:
+            lbm.lbm_bio_destroy(b)
+    # oracle: its own substrate field; classes change only through the
+    # biofilm, the substrate state stays (the GPU reads the grown nodes'
+    # concentration with their new classes)
+    f, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], nf)
+    U, _ = O.fluid_moments(cls, f)
+    g, _ = O.ad_run(cls, O.ad_init(cls, U, w["c_in"]), U, w["D"], w["c_in"], w["k"], na)
+    ocls, ocb, omo = cls.copy(), cb.copy(), mo.copy()
+    for h, sd in enumerate(seeds):
+        C = O.ad_moment(ocls, g, w["k"])
+        omo, bo = OB.bio_step(C, ocb, omo, bp, N)
+        ocls, ocb, omo, st = BF.biofilm_step(ocls, C, ocb, omo, bp, FILM_STEPS, sd)
+        assert O.percolates(ocls)
+        gb, gf, gcls, gcb, gmo = got[h]
+        assert abs(gb["I_cell"] - bo["I_cell"]) <= 1e-9 * bo["I_cell"]
+        for k in COUNTS:
+            assert gf[k] == (len(st["new_biofilm"]) if k == "new_biofilm" else st[k]), (h, k)
+        assert np.array_equal(gcls, ocls.reshape(-1)), h
+        assert _fields_close(gcb, ocb, 1e-10), h
+        assert np.abs(gmo - omo).max() < 1e-11, h
+        assert abs(gf["biomass"] - st["biomass"]) <= 1e-12 * st["biomass"]
+    assert sum(x[1]["spread"] for x in got) > 0 and sum(x[1]["walks"] for x in got) > 0
+
+
+@pytest.mark.parametrize("layer,hours", [(False, 6), (True, 3)], ids=["bare-6h", "layered-clogs"])
+def test_model_loop_matches_oracle(gpu_lib, layer, hours):
+    """The model loop: fluid and substrate to 1e-7 (cold, then warm),
+    bio-electrochemistry, biofilm formation.  Per interval: solve statuses
+    and iteration counts, attachment/spreading counts, current and voltage;
+    at the end the classes, biomass and mediator.  From a bare electrode
+    the biofilm attaches and spreads for six hours; from the one-cell layer
+    every cell spreads at once and growth closes the flow path in the third
+    interval, which both sides refuse at the same point."""
+    lbm = gpu_lib
+    w = inputs.scaled(C1, 96, 48, seed=22, layer=layer)
+    cls = masks(w, lbm)
+    N = cls.size
+    bp = inputs.bio_params(w["c_in"])
+    seed, tol, max_iter = 4242, 1e-7, 200000
+    print("model loop 96x48 layer=%s, %d hours" % (layer, hours), flush=True)
+    with _solver(lbm, cls, w) as s:
+        b = lbm.lbm_bio_create(s.h, lbm.make_bio_params(**bp), None, None, s.ctx)
+        try:
+            st, series = lbm.lbm_mfc_run(b, lbm.make_biofilm_params(**FILM), hours, seed, tol,
+                                         max_iter)
+            gcls = s.get(lbm.LBM_FIELD_CLASS).copy()
+            gcb = lbm.lbm_bio_get(b, lbm.LBM_BIO_CBIO, N)
+            gmo = lbm.lbm_bio_get(b, lbm.LBM_BIO_MOX, N)
+        finally:
+            lbm.lbm_bio_destroy(b)
+    recs, ocls, ocb, omo = BF.mfc_run(cls, w, bp, FILM, hours, seed, tol, max_iter)
+    if layer:
+        # growth closed the flow path: the oracle stops at the same interval
+        assert st == lbm.LBM_EINVAL and recs[-1]["status"] == "EINVAL"
+        assert len(recs) == 3
+    else:
+        assert st == 0 and len(recs) == hours and all(r["status"] == "OK" for r in recs)
+        assert series[-1]["film"]["walks"] > 0 and series[-1]["film"]["attached"] > 0
+    for h, r in enumerate(recs):
+        gr = series[h]
+        assert gr["iters_fluid"] == r["iters_fluid"] and gr["iters_ad"] == r["iters_ad"], h
+        assert gr["status_fluid"] == 0 and r["fluid"] == "OK"
+        assert abs(gr["bio"]["I_cell"] - r["bio"]["I_cell"]) <= 1e-9 * r["bio"]["I_cell"], h
+        assert abs(gr["bio"]["V_cell"] - r["bio"]["V_cell"]) <= 1e-9 * r["bio"]["V_cell"], h
+        if r["status"] == "OK":
+            for k in COUNTS:
+                want = len(r["film"]["new_biofilm"]) if k == "new_biofilm" else r["film"][k]
+                assert gr["film"][k] == want, (h, k)
+    if st == 0:
+        assert np.array_equal(gcls, ocls.reshape(-1))
+        assert _fields_close(gcb, ocb, 1e-10)
+        assert np.abs(gmo - omo).max() < 1e-11
+    # the biofilm grew and the current followed
+    if not layer:
+        assert series[0]["film"]["cells"] < series[-1]["film"]["cells"]
+        assert 0.0 == series[0]["bio"]["I_cell"] < series[-1]["bio"]["I_cell"]

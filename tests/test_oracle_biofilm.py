@@ -14,7 +14,7 @@ import oracle as O
 import oracle.bioelec as OB
 import oracle.biofilm as BF
 
-FP = dict(k_ata=200, C_max=512.5, fr_spr=0.4, max_walk=10000)
+FP = dict(k_ata=200, C_max=512.5, fr_spr=0.4, max_walk=10000, Y_bio=1.0)
 
 
 def _bp(**over):
@@ -62,17 +62,18 @@ def test_front_is_the_dilated_electrode_and_attachment_picks_from_it():
 
 def test_growth_multiplies_by_one_plus_rate_times_interval():
     """No attachment, nothing above C_max: each cell's biomass is multiplied
-    by 1 + q dt, q at half saturation of both factors = q_max / 4."""
+    by 1 + Y_bio q dt, q at half saturation of both factors = q_max / 4."""
     cls = _channel(12, 8)
     cls[3:5, 4:7] = O.BIOFILM
     bp = _bp()
     C = np.full(cls.size, bp["K_s"] / bp["c_scale"])
     cb = np.where(cls.reshape(-1) == O.BIOFILM, 300.0, 0.0)
     mo = np.where(cb > 0, bp["K_Mox"], 0.0)
-    _, cb2, mo2, s = BF.biofilm_step(cls, C, cb, mo, bp, dict(FP, k_ata=0), 5)
-    grow = 1.0 + (bp["q_max"] / 4.0) / 24.0
-    assert np.allclose(cb2[cb > 0], 300.0 * grow, rtol=1e-15)
-    assert np.array_equal(mo2, mo) and s["spread"] == 0
+    for Y in (1.0, 0.3):
+        _, cb2, mo2, s = BF.biofilm_step(cls, C, cb, mo, bp, dict(FP, k_ata=0, Y_bio=Y), 5)
+        grow = 1.0 + Y * (bp["q_max"] / 4.0) / 24.0
+        assert np.allclose(cb2[cb > 0], 300.0 * grow, rtol=1e-15)
+        assert np.array_equal(mo2, mo) and s["spread"] == 0
 
 
 def _totals(cb, mo):
