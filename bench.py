@@ -218,6 +218,67 @@ def coupled_main(args):
     print(json.dumps(res), flush=True)
 
 
+def mfc_main(args):
+    """The model loop of Sec. 2 on the 512 x 256 electrode, one hour per
+    interval: fluid and substrate solves to 1e-6 (cold, then warm), the
+    bio-electrochemical update (one work-group kernel) and the agent-based
+    biofilm (host), Table 1's parameters.  Reports lattice updates per
+    second over the loop, the time per stage and the V, I series' ends."""
+    import numpy as np
+    import torch
+
+    import paper_1802_07525_amd as lbm
+    from paper_1802_07525_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    lbm.load()
+    w = inputs.WORKLOADS["mfc"]
+    st, cls, _ = lbm.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
+                                    w["overlap"], w["seed"])
+    assert st == 0
+    hours = args.hours or w["hours"]
+    ctx = lbm.lbm_ctx_create(0)
+    p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                        storage=STORAGES[args.storage], stall_checks=args.stall_checks)
+    s = lbm.lbm_solver_create(ctx, cls, p)
+    b = lbm.lbm_bio_create(s, lbm.make_bio_params(**inputs.bio_params(w["c_in"])), None, None, ctx)
+    fp = lbm.make_biofilm_params(Y_bio=args.y_bio)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stc, series = lbm.lbm_mfc_run(b, fp, hours, w["seed"], w["tol"], args.max_iter or w["max_iter"])
+    el = time.perf_counter() - t0
+    lbm.lbm_bio_destroy(b)
+    lbm.lbm_solver_destroy(s)
+    lbm.lbm_ctx_destroy(ctx)
+    done = [r for r in series if r["iters_ad"] > 0 and r["film"]["cells"] > 0]
+    upd = float(sum(r["iters_fluid"] * r["nodes_fluid"] + r["iters_ad"] * r["nodes_ad"]
+                    for r in series))
+    I = [r["bio"]["I_cell"] for r in done]
+    V = [r["bio"]["V_cell"] for r in done]
+    res = {
+        "metric": METRIC, "value": upd / el / 1e6, "unit": "MLUPS", "n_gpus": 1, "steps": hours,
+        "warmup": 0, "ms_per_step": el / max(len(done), 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.storage], "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [w["nx"], w["ny"], 1], "storage": args.storage,
+                   "hours": hours, "hours_done": len(done), "tol": w["tol"], "seed": w["seed"],
+                   "Y_bio": args.y_bio, "status": lbm.status_name(stc)},
+        "mfc": {"seconds": el,
+                "seconds_solves": float(sum(r["seconds_solves"] for r in series)),
+                "seconds_bio": float(sum(r["seconds_bio"] for r in series)),
+                "seconds_film": float(sum(r["seconds_film"] for r in series)),
+                "bio_ms_mean": float(np.mean([r["seconds_bio"] for r in done]) * 1e3) if done else None,
+                "film_ms_mean": float(np.mean([r["seconds_film"] for r in done]) * 1e3) if done else None,
+                "fluid_iters": [int(r["iters_fluid"]) for r in series],
+                "ad_iters": [int(r["iters_ad"]) for r in series],
+                "I_mA": [round(x * 1e3, 6) for x in I],
+                "V_mV": [round(x * 1e3, 4) for x in V],
+                "biofilm_cells": [int(r["film"]["cells"]) for r in done],
+                "spread": int(sum(r["film"]["spread"] for r in done)),
+                "walks": int(sum(r["film"]["walks"] for r in done))},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def served_main(args):
     """Served stream: seeded requests with Poisson arrivals submitted in real
     time to one server (continuous batching), then the same requests solved
@@ -369,6 +430,9 @@ def main():
     ap.add_argument("--stall-checks", type=int, default=0,
                     help="stall window in checks (0: the library default)")
     ap.add_argument("--updates", type=int, default=0, help="coupled loop: growth updates")
+    ap.add_argument("--hours", type=int, default=0, help="model loop: intervals (0: 72)")
+    ap.add_argument("--y-bio", type=float, default=1.0,
+                    help="model loop: biomass yield on the consumed substrate")
     ap.add_argument("--compare-storage", default="", choices=[""] + sorted(STORAGES),
                     help="coupled loop: repeat in this storage and compare")
     ap.add_argument("--ad-lattice", default="d2q5", choices=["d2q5", "d2q9"],
@@ -391,6 +455,8 @@ def main():
         return served_main(args)
     if args.workload == "c5":
         return coupled_main(args)
+    if args.workload == "mfc":
+        return mfc_main(args)
 
     import numpy as np
     import torch

@@ -477,6 +477,10 @@ lbm_status lbm_biofilm_step(lbm_bio *b, const lbm_biofilm_params *p, uint64_t se
 typedef struct {
     int32_t status_fluid, status_ad;  /* lbm_status of the two solves */
     int64_t iters_fluid, iters_ad;
+    int64_t nodes_fluid, nodes_ad;    /* nodes each solve updated per step */
+    double seconds_solves;            /* wall time of the two solves */
+    double seconds_bio;               /* of lbm_bio_step */
+    double seconds_film;              /* of lbm_biofilm_step */
     lbm_bio_out bio;
     lbm_biofilm_stats film;
 } lbm_mfc_interval;

@@ -134,12 +134,15 @@ class lbm_biofilm_stats(ct.Structure):
 class lbm_mfc_interval(ct.Structure):
     _fields_ = [("status_fluid", ct.c_int32), ("status_ad", ct.c_int32),
                 ("iters_fluid", ct.c_int64), ("iters_ad", ct.c_int64),
+                ("nodes_fluid", ct.c_int64), ("nodes_ad", ct.c_int64),
+                ("seconds_solves", ct.c_double), ("seconds_bio", ct.c_double),
+                ("seconds_film", ct.c_double),
                 ("bio", lbm_bio_out), ("film", lbm_biofilm_stats)]
 
     def as_dict(self):
-        return dict(status_fluid=self.status_fluid, status_ad=self.status_ad,
-                    iters_fluid=self.iters_fluid, iters_ad=self.iters_ad,
-                    bio=self.bio.as_dict(), film=self.film.as_dict())
+        d = {k: getattr(self, k) for k, _ in self._fields_[:9]}
+        d.update(bio=self.bio.as_dict(), film=self.film.as_dict())
+        return d
 
 P, I32, I64, U64, D, SZ = (ct.c_void_p, ct.c_int, ct.c_int64, ct.c_uint64, ct.c_double,
                            ct.c_size_t)

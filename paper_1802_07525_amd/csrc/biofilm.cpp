@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -203,10 +204,15 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *fp, int n_hours, ui
         return LBM_EINVAL;
     lbm_solver *s = b->s;
     SplitMix64 seeds{seed};
+    using clk = std::chrono::steady_clock;
+    auto secs = [](clk::time_point a, clk::time_point z) { return std::chrono::duration<double>(z - a).count(); };
     for (int h = 0; h < n_hours; ++h) {
         lbm_mfc_interval &r = series[h];
         r = lbm_mfc_interval{};
         lbm_info fi{}, ai{};
+        const auto t0 = clk::now();
+        r.nodes_fluid = s->n_fluid;
+        r.nodes_ad = s->n_ad;
         const lbm_status sf = lbm_solver_fluid(s, tol, max_iter, h > 0, &fi);
         r.status_fluid = sf;
         r.iters_fluid = fi.iters;
@@ -217,10 +223,16 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *fp, int n_hours, ui
         r.iters_ad = ai.iters;
         if (sa < 0)
             return sa;
+        const auto t1 = clk::now();
+        r.seconds_solves = secs(t0, t1);
         lbm_status st = lbm_bio_step(b, &r.bio);
+        const auto t2 = clk::now();
+        r.seconds_bio = secs(t1, t2);
         if (st)
             return st;
-        if ((st = lbm_biofilm_step(b, fp, seeds.next(), &r.film)))
+        st = lbm_biofilm_step(b, fp, seeds.next(), &r.film);
+        r.seconds_film = secs(t2, clk::now());
+        if (st)
             return st;
     }
     return LBM_OK;

@@ -41,6 +41,14 @@ WORKLOADS = {
                geom="discs", r_min=3, r_max=6, solid=0.3, overlap=0, seed=5, layer=True,
                tau=0.8, u_in=0.01, D=0.2 / 3.0, c_in=1.0, k=1e-3, tol=1e-6, max_iter=1_000_000,
                updates=200),
+    # the model loop of Sec. 2 (fluid, substrate, bio-electrochemistry,
+    # biofilm), one hour per interval, over the 72 hours the paper simulates:
+    # the coupled workload's 512 x 256 electrode, bare (the biofilm attaches
+    # and grows), Table 1's bio parameters
+    "mfc": dict(name="d2q9+d2q5 512x256 discs r3-6 porosity0.7 model loop 72h", nx=512, ny=256,
+                nz=1, geom="discs", r_min=3, r_max=6, solid=0.3, overlap=0, seed=5, layer=False,
+                tau=0.8, u_in=0.01, D=0.2 / 3.0, c_in=1.0, k=1e-3, tol=1e-6,
+                max_iter=1_000_000, hours=72),
     # large 2-D bandwidth point (well beyond the 256 MB last-level cache)
     "c2_hbm": dict(name="d2q9+d2q5 8192x4096 discs r4-10 porosity0.6", nx=8192, ny=4096, nz=1,
                    geom="discs", r_min=4, r_max=10, solid=0.4, overlap=0, seed=2, layer=False,
