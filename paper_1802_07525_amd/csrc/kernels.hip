@@ -671,7 +671,6 @@ __device__ __forceinline__ void column_refs(const float *src, const float *dst, 
                                             typename S::C &r0, typename S::C &dm,
                                             typename S::C &dp, typename S::C &rd)
 {
-    typedef typename S::C C;
     r0 = gmem(src)[x];
     dm = (x > 0 ? gmem(src)[x - 1] : r0) - r0;
     dp = (x < nx - 1 ? gmem(src)[x + 1] : r0) - r0;
@@ -753,7 +752,6 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
                                            unsigned long long *part_r, unsigned long long *part_u)
 {
     typedef typename S::C C;
-    const long long N = a.g.N;
     const DT d = p.inb ? static_cast<const DT *>(a.desc)[p.n] : DT(0);
     const bool act = (d & DT(1)) != 0;
     C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
