@@ -143,3 +143,41 @@ def test_model_loop_matches_oracle(gpu_lib, layer, hours):
     if not layer:
         assert series[0]["film"]["cells"] < series[-1]["film"]["cells"]
         assert 0.0 == series[0]["bio"]["I_cell"] < series[-1]["bio"]["I_cell"]
+
+
+def test_model_loop_3d_matches_oracle(gpu_lib):
+    """The model loop on a 3-D fibre electrode (D3Q19 fluid, D3Q7 substrate;
+    the biofilm front and spreading use the 18 D3Q19 neighbours): four
+    hours, the same per-interval and final checks as in 2-D."""
+    lbm = gpu_lib
+    w = inputs.scaled(inputs.WORKLOADS["c3"], 48, 24, 24, seed=31, layer=False)
+    cls = masks(w, lbm)
+    N = cls.size
+    bp = inputs.bio_params(w["c_in"])
+    film = dict(FILM, k_ata=40)
+    hours, seed, tol, max_iter = 4, 777, 1e-7, 200000
+    print("model loop 48x24x24, %d hours" % hours, flush=True)
+    with _solver(lbm, cls, w) as s:
+        b = lbm.lbm_bio_create(s.h, lbm.make_bio_params(**bp), None, None, s.ctx)
+        try:
+            st, series = lbm.lbm_mfc_run(b, lbm.make_biofilm_params(**film), hours, seed, tol,
+                                         max_iter)
+            assert st == 0, s.error()
+            gcls = s.get(lbm.LBM_FIELD_CLASS).copy()
+            gcb = lbm.lbm_bio_get(b, lbm.LBM_BIO_CBIO, N)
+            gmo = lbm.lbm_bio_get(b, lbm.LBM_BIO_MOX, N)
+        finally:
+            lbm.lbm_bio_destroy(b)
+    recs, ocls, ocb, omo = BF.mfc_run(cls, w, bp, film, hours, seed, tol, max_iter)
+    assert len(recs) == hours and all(r["status"] == "OK" for r in recs)
+    for h, r in enumerate(recs):
+        gr = series[h]
+        assert gr["iters_fluid"] == r["iters_fluid"] and gr["iters_ad"] == r["iters_ad"], h
+        assert abs(gr["bio"]["I_cell"] - r["bio"]["I_cell"]) <= 1e-9 * r["bio"]["I_cell"], h
+        for k in COUNTS:
+            want = len(r["film"]["new_biofilm"]) if k == "new_biofilm" else r["film"][k]
+            assert gr["film"][k] == want, (h, k)
+    assert np.array_equal(gcls, ocls.reshape(-1))
+    assert _fields_close(gcb, ocb, 1e-10)
+    assert np.abs(gmo - omo).max() < 1e-11
+    assert series[-1]["film"]["spread"] > 0

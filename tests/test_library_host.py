@@ -141,3 +141,13 @@ def test_geometry_rejects_bad_arguments():
     # unreachable target with non-overlapping discs -> EINVAL after 10^6 attempts
     st, _, _ = L.lbm_geom_discs(16, 10, 5, 5, 0.9, 0, 1)
     assert st == L.LBM_EINVAL
+
+
+def test_smoke_mask_percolates():
+    """The smoke check's mask must be one the solver accepts."""
+    import __graft_entry__ as G
+    w = inputs.scaled(inputs.WORKLOADS["c1"], 96, 48, **G.SMOKE_MASK)
+    st, cls, _ = L.lbm_geom_discs(w["nx"], w["ny"], w["r_min"], w["r_max"], w["solid"],
+                                    w["overlap"], w["seed"])
+    assert st == 0
+    assert L.lbm_percolates(L.lbm_biofilm_layer(cls))
