@@ -31,6 +31,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace lbmk {
 
 // ---------------------------------------------------------------- lattices
@@ -247,10 +249,11 @@ __device__ __forceinline__ NodePos tile_node(const Geo &g, int tile)
 // per block into its own slots (*pa, *pb) -- no contended atomics; the
 // decide kernel reduces the slots.  Ends with a barrier so that a block may
 // call it again for its next tile.
+template <int NW = 4>
 __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned long long b,
                                                  unsigned long long *pa, unsigned long long *pb)
 {
-    __shared__ unsigned long long sa[4], sb[4];
+    __shared__ unsigned long long sa[NW], sb[NW];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long oa = __shfl_xor(a, off);
@@ -266,7 +269,7 @@ __device__ __forceinline__ void block_max_commit(unsigned long long a, unsigned 
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long ma = sa[0], mb = sb[0];
-        for (int k = 1; k < 4; ++k) {
+        for (int k = 1; k < NW; ++k) {
             ma = sa[k] > ma ? sa[k] : ma;
             mb = sb[k] > mb ? sb[k] : mb;
         }
@@ -778,13 +781,19 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
 }
 
 // Tile height of the two-step kernels (2-D): 64 x PAIR_TY nodes per
-// 256-thread block, PAIR_TY / 4 nodes per thread in the second step.  Four
-// rows, one node per thread: the first step recomputes 1.55x the tile
-// (66 x 6 nodes) against 1.29x for eight rows, but twice the blocks hide
-// more latency -- 19% faster on a 512 x 256 grid and no slower on
+// 256-thread block, one node per thread in the second step.  Four rows: the
+// first step recomputes 1.55x the tile (66 x 6 nodes) against 1.29x for
+// eight rows, but 256-thread blocks of eight rows (two nodes per thread)
+// leave a CU half the waves -- 19% slower on a 512 x 256 grid, 2% on
 // 1024 x 512 -- and the FP16 residual's tile means are the single-step
-// kernels' 64 x 4 tiles.
+// kernels' 64 x 4 tiles.  Large grids without tile means take the wide
+// form: 64 x 8 tiles on 512-thread blocks, still one node per thread and
+// full occupancy, and 14% fewer first-step wave-collisions than 64 x 4
+// (19 against 22 per 512 nodes, counting the partly filled last wave).
 constexpr int PAIR_TY = 4;
+constexpr int WIDE_TY = 8, WIDE_NTH = 512;
+// blocks of 64 x 8 needed for the wide form: four per CU
+constexpr int WIDE_MIN_TILES = 1024;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
@@ -800,11 +809,13 @@ constexpr int pair_lds_bytes()
     return Q * (TY + 2) * 66 * (int)sizeof(C);
 }
 
-template <class S, int MODE, bool NT, int TY = PAIR_TY>
+template <class S, int MODE, bool NT, int TY = PAIR_TY, int NTH = 256>
 __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
                                             unsigned long long *part_r, unsigned long long *part_u,
                                             void *smem)
 {
+    static_assert(NTH % 64 == 0 && (64 * TY) % NTH == 0, "whole rows per thread pass");
+    static_assert(!S::tile_mean || (TY == 4 && NTH == 256), "tile means are over 64 x 4 tiles");
     typedef D2Q9 L;
     typedef uint16_t DT;
     typedef typename S::C C;
@@ -815,7 +826,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
-    for (int r = threadIdx.x; r < NR; r += 256) {
+    for (int r = threadIdx.x; r < NR; r += NTH) {
         const int lx = r % LX, ly = r / LX;
         const int x = x0 - 1 + lx, y = y0 - 1 + ly;
         const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
@@ -840,8 +851,8 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     __syncthreads();
     CheckAcc<S::tile_mean> acc;
 #pragma unroll
-    for (int k = 0; k < TY / 4; ++k) {
-        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * k;
+    for (int k = 0; k < 64 * TY / NTH; ++k) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + (NTH / 64) * k;
         NodePos p;
         p.x = x0 + lx;
         p.y = y0 + ly;
@@ -874,7 +885,7 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
     }
     if constexpr (MODE == MODE_CHECK) {
         const double r = acc.result();
-        block_max_commit(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
+        block_max_commit<NTH / 64>(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
     }
     __syncthreads(); // the block may run another tile: v is reused
 }
@@ -1169,15 +1180,15 @@ __global__ void __launch_bounds__(256) k_ad_step(AdArgs a)
 }
 
 // Two steps per launch (2-D)
-template <class S, int MODE, bool NT>
-__global__ void __launch_bounds__(256) k_fluid_step2(FluidArgs a)
+template <class S, int MODE, bool NT, int TY = PAIR_TY, int NTH = 256>
+__global__ void __launch_bounds__(NTH) k_fluid_step2(FluidArgs a)
 {
-    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, 9>()];
+    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, 9, TY>()];
     if (a.ctrl->stop)
         return;
     unsigned long long *part = a.ctrl->part;
-    fluid_tile2<S, MODE, NT>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
-                             part + gridDim.x + blockIdx.x, smem);
+    fluid_tile2<S, MODE, NT, TY, NTH>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                      part + gridDim.x + blockIdx.x, smem);
 }
 
 template <class S, int MODE, bool NT, class L, int QF>
@@ -1852,26 +1863,51 @@ hipError_t fluid_step(int dim, int storage, int mode, const FluidArgs &a, hipStr
     });
 }
 
+int pair_tiles(const Geo &g, int ty)
+{
+    return g.ntx * ((g.ny + ty - 1) / ty) * g.nz;
+}
 int pair_tiles(const Geo &g)
 {
-    return g.ntx * ((g.ny + PAIR_TY - 1) / PAIR_TY) * g.nz;
+    return pair_tiles(g, PAIR_TY);
+}
+
+int fluid_pair_ty(int storage, const Geo &g)
+{
+    // FP16 storage (the only one with tile means) keeps 64 x 4
+    const bool means = storage == ST_F16S;
+    static_assert(SF16S::tile_mean && !SF32S::tile_mean && !SF32::tile_mean && !SF64::tile_mean,
+                  "tile means are FP16 storage's alone");
+    return !means && pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES ? WIDE_TY : PAIR_TY;
 }
 
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
 {
+    const bool wide = fluid_pair_ty(storage, a.g) == WIDE_TY;
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        const dim3 grid(pair_tiles(a.g));
-        if (a.streaming_stores) {
-            if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, true>), grid, dim3(256), 0, st, a);
-            else
-                hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, true>), grid, dim3(256), 0, st, a);
+        auto go = [&](auto ty, auto nth) {
+            constexpr int TY = decltype(ty)::value, NTH = decltype(nth)::value;
+            const dim3 grid(pair_tiles(a.g, TY));
+            if (a.streaming_stores) {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, true, TY, NTH>), grid, dim3(NTH), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, true, TY, NTH>), grid, dim3(NTH), 0, st, a);
+            } else {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, false, TY, NTH>), grid, dim3(NTH), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, false, TY, NTH>), grid, dim3(NTH), 0, st, a);
+            }
+        };
+        if constexpr (S::tile_mean) {
+            go(std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
         } else {
-            if (mode == MODE_CHECK)
-                hipLaunchKernelGGL((k_fluid_step2<S, MODE_CHECK, false>), grid, dim3(256), 0, st, a);
+            if (wide)
+                go(std::integral_constant<int, WIDE_TY>{}, std::integral_constant<int, WIDE_NTH>{});
             else
-                hipLaunchKernelGGL((k_fluid_step2<S, MODE_PLAIN, false>), grid, dim3(256), 0, st, a);
+                go(std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
         }
         return hipGetLastError();
     });

@@ -143,8 +143,14 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
 // lay: 2 (D2Q5 substrate) or LAY_2D_AD9 (D2Q9 substrate, its own words)
 hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t st);
 // Blocks (tiles) of a two-step launch; per-block check maxima need this many
-// slots (never more than g.ntiles).
+// slots (never more than g.ntiles).  pair_tiles(g): 64 x 4 tiles;
+// pair_tiles(g, ty): 64 x ty tiles.
 int pair_tiles(const Geo &g);
+int pair_tiles(const Geo &g, int ty);
+// Tile height fluid_step2 uses for this storage and grid: 8 (512-thread
+// blocks) on grids with at least 1024 such tiles and no FP16 tile means,
+// else 4.
+int fluid_pair_ty(int storage, const Geo &g);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,

@@ -201,9 +201,12 @@ inline int64_t launches_for(const lbm_solver *s, int64_t steps)
     return paired(s) ? steps / 2 + (steps & 1) : steps;
 }
 // blocks of the check-step launches (the per-block maxima the decide reads)
-inline int check_blocks(const lbm_solver *s)
+inline int check_blocks(const lbm_solver *s, int which)
 {
-    return paired(s) ? lbmk::pair_tiles(s->geo) : s->geo.ntiles;
+    if (!paired(s))
+        return s->geo.ntiles;
+    return which == LBM_SOLVER_FLUID ? lbmk::pair_tiles(s->geo, lbmk::fluid_pair_ty(s->p.storage, s->geo))
+                                     : lbmk::pair_tiles(s->geo);
 }
 
 // One launch of `nsteps` (1, or 2 in 2-D) steps reading buffer src.
@@ -339,7 +342,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                                                     : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
     HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s), stream),
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
            "ctrl reset");
     int &cur = which == LBM_SOLVER_FLUID ? s->fcur : s->gcur;
     const int cur0 = cur;
@@ -710,7 +713,7 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
             return st;
     hipStream_t stream = s->ctx->stream;
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s), stream),
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
            "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
@@ -740,7 +743,7 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
         return set_err(s->ctx, LBM_EINVAL, "state not initialised");
     hipStream_t stream = s->ctx->stream;
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s), stream),
+                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
            "ctrl");
     const int k = paired(s) ? 2 : 1; // steps per launch
     const int nl = (nsteps + k - 1) / k;

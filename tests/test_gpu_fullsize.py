@@ -1,0 +1,80 @@
+"""Parity at the benchmark's full sizes and launch configuration.
+
+The 1024 x 512 electrode (the single-solve benchmark) and the 256 x 128 x
+128 fibre electrode, compared with the FP64 oracle element by element after
+fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
+(the residual checks, the stop decision and the iteration count).  On the
+2-D grid FP64 and FP32 storage run the wide two-step kernel (64 x 8 tiles,
+512-thread blocks), FP16 the 64 x 4 one -- the forms the benchmark times.
+Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
+and FP16 5e-3 relative L2 on the fields.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import masks, rel_l2
+from paper_1802_07525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP32S, FP16S, FP64 = 1, 2, 3
+TOL = {FP64: 1e-12, FP32S: 1e-4, FP16S: 5e-3}
+C2 = inputs.WORKLOADS["c2"]
+C3 = inputs.WORKLOADS["c3"]
+
+
+def _solver(lbm, cls, w, storage):
+    return lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                      storage=storage)
+
+
+def _fixed(lbm, w, storage, nf, na):
+    cls = masks(w, lbm)
+    print("full size %s storage %d: %d + %d steps" % (w["name"], storage, nf, na), flush=True)
+    with _solver(lbm, cls, w, storage) as s:
+        assert s.steps(0, nf, 1)[0] == 0, s.error()
+        assert lbm.lbm_solver_export_u(s.h) == 0
+        assert s.steps(1, na, 1)[0] == 0, s.error()
+        U = s.get(lbm.LBM_FIELD_U)
+        C = s.get(lbm.LBM_FIELD_C)
+    f, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], nf)
+    Uo, _ = O.fluid_moments(cls, f)
+    g, _ = O.ad_run(cls, O.ad_init(cls, Uo, w["c_in"]), Uo, w["D"], w["c_in"], w["k"], na)
+    Co = O.ad_moment(cls, g, w["k"])
+    return cls, U, C, Uo.reshape(U.shape), Co
+
+
+def _check(storage, cls, U, C, Uo, Co):
+    act = np.isin(cls.reshape(-1), [O.FLUID, O.BIOFILM])
+    if storage == FP64:
+        assert np.abs(U - Uo).max() < TOL[FP64]
+        assert np.abs(C - Co)[act].max() < TOL[FP64]
+    else:
+        assert rel_l2(U, Uo) < TOL[storage]
+        assert rel_l2(C, Co, act) < TOL[storage]
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32S, FP16S], ids=["fp64", "fp32s", "fp16s"])
+def test_c2_full_size_fixed_steps(gpu_lib, storage):
+    cls, U, C, Uo, Co = _fixed(gpu_lib, C2, storage, 40, 40)
+    _check(storage, cls, U, C, Uo, Co)
+
+
+def test_c2_full_size_fp64_steady(gpu_lib):
+    """The checks of the wide kernel (its 512-thread block maxima) decide
+    the stop at the oracle's step."""
+    lbm = gpu_lib
+    cls = masks(C2, lbm)
+    with _solver(lbm, cls, C2, FP64) as s:
+        st, fi = s.fluid(1e-2, 20000)
+        assert st == 0, s.error()
+        U = s.get(lbm.LBM_FIELD_U)
+    fo = O.fluid_solve(cls, C2["tau"], C2["u_in"], 1e-2, 20000)
+    assert fo["status"] == "OK" and fi["iters"] == fo["iters"]
+    assert np.abs(U - fo["U"].reshape(U.shape)).max() < 1e-9
+
+
+def test_c3_full_size_fixed_steps(gpu_lib):
+    cls, U, C, Uo, Co = _fixed(gpu_lib, C3, FP32S, 10, 10)
+    _check(FP32S, cls, U, C, Uo, Co)
