@@ -787,13 +787,15 @@ __device__ __forceinline__ void fluid_tile(const FluidArgs &a, const NodePos &p,
 // leave a CU half the waves -- 19% slower on a 512 x 256 grid, 2% on
 // 1024 x 512 -- and the FP16 residual's tile means are the single-step
 // kernels' 64 x 4 tiles.  Large grids without tile means take the wide
-// form: 64 x 8 tiles on 512-thread blocks, still one node per thread and
-// full occupancy, and 14% fewer first-step wave-collisions than 64 x 4
-// (19 against 22 per 512 nodes, counting the partly filled last wave).
+// form: 64 x 16 tiles on 1024-thread blocks, still one node per thread and
+// full occupancy (two blocks, 32 waves per CU), and a first step of 19
+// waves for 16 rows instead of 4 x 7 = 28 (the last wave of each pass is
+// partly filled).  On 1024 x 512 the paired fluid launch went 10.23 ->
+// 9.90 us with 64 x 8 on 512 threads, and to 9.57 us with 64 x 16.
 constexpr int PAIR_TY = 4;
-constexpr int WIDE_TY = 8, WIDE_NTH = 512;
-// blocks of 64 x 8 needed for the wide form: four per CU
-constexpr int WIDE_MIN_TILES = 1024;
+constexpr int WIDE_TY = 16, WIDE_NTH = 1024;
+// blocks of the wide form needed to use it: two per CU
+constexpr int WIDE_MIN_TILES = 512;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
@@ -1091,10 +1093,12 @@ __device__ __forceinline__ void ad_tile(const AdArgs &a, const NodePos &p,
 }
 
 // Two substrate steps of one 64 x TY tile (2-D), as fluid_tile2.
-template <class S, int MODE, bool NT, class L = D2Q5, int QF = 9, int TY = PAIR_TY>
+template <class S, int MODE, bool NT, class L = D2Q5, int QF = 9, int TY = PAIR_TY, int NTH = 256>
 __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned long long *part_r,
                                          unsigned long long *part_u, void *smem)
 {
+    static_assert(NTH % 64 == 0 && (64 * TY) % NTH == 0, "whole rows per thread pass");
+    static_assert(!S::tile_mean || (TY == 4 && NTH == 256), "tile means are over 64 x 4 tiles");
     typedef uint16_t DT;
     typedef typename S::C C;
     constexpr int ACT = QF - 1 + L::Q;
@@ -1107,7 +1111,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
     const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
     const unsigned int NN = (unsigned int)N;
-    for (int r = threadIdx.x; r < NR; r += 256) {
+    for (int r = threadIdx.x; r < NR; r += NTH) {
         const int lx = r % LX, ly = r / LX;
         const int x = x0 - 1 + lx, y = y0 - 1 + ly;
         const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
@@ -1130,8 +1134,8 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     __syncthreads();
     CheckAcc<S::tile_mean> acc;
 #pragma unroll
-    for (int k = 0; k < TY / 4; ++k) {
-        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * k;
+    for (int k = 0; k < 64 * TY / NTH; ++k) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + (NTH / 64) * k;
         NodePos p;
         p.x = x0 + lx;
         p.y = y0 + ly;
@@ -1164,7 +1168,7 @@ __device__ __forceinline__ void ad_tile2(const AdArgs &a, int tile, unsigned lon
     }
     if constexpr (MODE == MODE_CHECK) {
         const double r = acc.result();
-        block_max_commit(dbits(r * a.inv_cin), 0ull, part_r, part_u);
+        block_max_commit<NTH / 64>(dbits(r * a.inv_cin), 0ull, part_r, part_u);
     }
     __syncthreads();
 }
@@ -1191,15 +1195,15 @@ __global__ void __launch_bounds__(NTH) k_fluid_step2(FluidArgs a)
                                       part + gridDim.x + blockIdx.x, smem);
 }
 
-template <class S, int MODE, bool NT, class L, int QF>
-__global__ void __launch_bounds__(256) k_ad_step2(AdArgs a)
+template <class S, int MODE, bool NT, class L, int QF, int TY = PAIR_TY, int NTH = 256>
+__global__ void __launch_bounds__(NTH) k_ad_step2(AdArgs a)
 {
-    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, L::Q>()];
+    __shared__ __align__(16) char smem[pair_lds_bytes<typename S::C, L::Q, TY>()];
     if (a.ctrl->stop)
         return;
     unsigned long long *part = a.ctrl->part;
-    ad_tile2<S, MODE, NT, L, QF>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
-                                 part + gridDim.x + blockIdx.x, smem);
+    ad_tile2<S, MODE, NT, L, QF, TY, NTH>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                          part + gridDim.x + blockIdx.x, smem);
 }
 
 // ------------------------------------------------------- init / export
@@ -1872,7 +1876,7 @@ int pair_tiles(const Geo &g)
     return pair_tiles(g, PAIR_TY);
 }
 
-int fluid_pair_ty(int storage, const Geo &g)
+int pair_ty(int storage, const Geo &g)
 {
     // FP16 storage (the only one with tile means) keeps 64 x 4
     const bool means = storage == ST_F16S;
@@ -1883,7 +1887,7 @@ int fluid_pair_ty(int storage, const Geo &g)
 
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
 {
-    const bool wide = fluid_pair_ty(storage, a.g) == WIDE_TY;
+    const bool wide = pair_ty(storage, a.g) == WIDE_TY;
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         auto go = [&](auto ty, auto nth) {
@@ -1915,28 +1919,40 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
 
 hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t st)
 {
+    const bool wide = pair_ty(storage, a.g) == WIDE_TY;
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        const dim3 grid(pair_tiles(a.g));
-        auto go = [&](auto la, auto qf) {
+        auto go = [&](auto la, auto qf, auto ty, auto nth) {
             typedef decltype(la) L;
             constexpr int QF = decltype(qf)::value;
+            constexpr int TY = decltype(ty)::value, NTH = decltype(nth)::value;
+            const dim3 grid(pair_tiles(a.g, TY));
             if (a.streaming_stores) {
                 if (mode == MODE_CHECK)
-                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true, L, QF>), grid, dim3(256), 0, st, a);
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, true, L, QF, TY, NTH>), grid, dim3(NTH), 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, true, L, QF>), grid, dim3(256), 0, st, a);
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, true, L, QF, TY, NTH>), grid, dim3(NTH), 0, st, a);
             } else {
                 if (mode == MODE_CHECK)
-                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, false, L, QF>), grid, dim3(256), 0, st, a);
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_CHECK, false, L, QF, TY, NTH>), grid, dim3(NTH), 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, false, L, QF>), grid, dim3(256), 0, st, a);
+                    hipLaunchKernelGGL((k_ad_step2<S, MODE_PLAIN, false, L, QF, TY, NTH>), grid, dim3(NTH), 0, st, a);
+            }
+        };
+        auto shape = [&](auto la, auto qf) {
+            if constexpr (S::tile_mean) {
+                go(la, qf, std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
+            } else {
+                if (wide)
+                    go(la, qf, std::integral_constant<int, WIDE_TY>{}, std::integral_constant<int, WIDE_NTH>{});
+                else
+                    go(la, qf, std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
             }
         };
         if (lay == LAY_2D_AD9)
-            go(D2Q9{}, std::integral_constant<int, 1>{});
+            shape(D2Q9{}, std::integral_constant<int, 1>{});
         else
-            go(D2Q5{}, std::integral_constant<int, 9>{});
+            shape(D2Q5{}, std::integral_constant<int, 9>{});
         return hipGetLastError();
     });
 }

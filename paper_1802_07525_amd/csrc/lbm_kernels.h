@@ -147,10 +147,10 @@ hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t
 // pair_tiles(g, ty): 64 x ty tiles.
 int pair_tiles(const Geo &g);
 int pair_tiles(const Geo &g, int ty);
-// Tile height fluid_step2 uses for this storage and grid: 8 (512-thread
-// blocks) on grids with at least 1024 such tiles and no FP16 tile means,
-// else 4.
-int fluid_pair_ty(int storage, const Geo &g);
+// Tile height fluid_step2 and ad_step2 use for this storage and grid: 16
+// (1024-thread blocks) on grids with at least 512 such tiles and no FP16
+// tile means, else 4 (256-thread blocks).
+int pair_ty(int storage, const Geo &g);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,

@@ -205,8 +205,8 @@ inline int check_blocks(const lbm_solver *s, int which)
 {
     if (!paired(s))
         return s->geo.ntiles;
-    return which == LBM_SOLVER_FLUID ? lbmk::pair_tiles(s->geo, lbmk::fluid_pair_ty(s->p.storage, s->geo))
-                                     : lbmk::pair_tiles(s->geo);
+    (void)which; // both solvers pick the same tile shape
+    return lbmk::pair_tiles(s->geo, lbmk::pair_ty(s->p.storage, s->geo));
 }
 
 // One launch of `nsteps` (1, or 2 in 2-D) steps reading buffer src.

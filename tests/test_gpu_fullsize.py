@@ -4,8 +4,9 @@ The 1024 x 512 electrode (the single-solve benchmark) and the 256 x 128 x
 128 fibre electrode, compared with the FP64 oracle element by element after
 fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
 (the residual checks, the stop decision and the iteration count).  On the
-2-D grid FP64 and FP32 storage run the wide two-step kernel (64 x 8 tiles,
-512-thread blocks), FP16 the 64 x 4 one -- the forms the benchmark times.
+2-D grid FP64 and FP32 storage run the wide two-step kernels (64 x 16
+tiles, 1024-thread blocks), FP16 the 64 x 4 ones -- the forms the
+benchmark times.
 Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
 and FP16 5e-3 relative L2 on the fields.
 """
@@ -24,15 +25,17 @@ C2 = inputs.WORKLOADS["c2"]
 C3 = inputs.WORKLOADS["c3"]
 
 
-def _solver(lbm, cls, w, storage):
+def _solver(lbm, cls, w, storage, ad9=False):
     return lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
-                      storage=storage)
+                      storage=storage, ad_lattice=1 if ad9 else 0)
 
 
-def _fixed(lbm, w, storage, nf, na):
+def _fixed(lbm, w, storage, nf, na, ad9=False):
     cls = masks(w, lbm)
-    print("full size %s storage %d: %d + %d steps" % (w["name"], storage, nf, na), flush=True)
-    with _solver(lbm, cls, w, storage) as s:
+    print("full size %s storage %d ad9 %s: %d + %d steps" % (w["name"], storage, ad9, nf, na),
+          flush=True)
+    lat = O.D2Q9 if ad9 else None
+    with _solver(lbm, cls, w, storage, ad9) as s:
         assert s.steps(0, nf, 1)[0] == 0, s.error()
         assert lbm.lbm_solver_export_u(s.h) == 0
         assert s.steps(1, na, 1)[0] == 0, s.error()
@@ -40,8 +43,9 @@ def _fixed(lbm, w, storage, nf, na):
         C = s.get(lbm.LBM_FIELD_C)
     f, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], nf)
     Uo, _ = O.fluid_moments(cls, f)
-    g, _ = O.ad_run(cls, O.ad_init(cls, Uo, w["c_in"]), Uo, w["D"], w["c_in"], w["k"], na)
-    Co = O.ad_moment(cls, g, w["k"])
+    g, _ = O.ad_run(cls, O.ad_init(cls, Uo, w["c_in"], lat=lat), Uo, w["D"], w["c_in"], w["k"], na,
+                    lat=lat)
+    Co = O.ad_moment(cls, g, w["k"], lat=lat)
     return cls, U, C, Uo.reshape(U.shape), Co
 
 
@@ -61,18 +65,32 @@ def test_c2_full_size_fixed_steps(gpu_lib, storage):
     _check(storage, cls, U, C, Uo, Co)
 
 
+def test_c2_full_size_d2q9_substrate(gpu_lib):
+    """The paper's D2Q9 substrate (its own words, the wide two-step kernel)."""
+    cls, U, C, Uo, Co = _fixed(gpu_lib, C2, FP32S, 40, 40, ad9=True)
+    _check(FP32S, cls, U, C, Uo, Co)
+
+
 def test_c2_full_size_fp64_steady(gpu_lib):
-    """The checks of the wide kernel (its 512-thread block maxima) decide
-    the stop at the oracle's step."""
+    """The checks of the wide kernels (their 1024-thread block maxima)
+    decide each stop at the oracle's step: fluid to 1e-2 (3 checks),
+    substrate to 1e-3 (32 checks)."""
     lbm = gpu_lib
     cls = masks(C2, lbm)
     with _solver(lbm, cls, C2, FP64) as s:
         st, fi = s.fluid(1e-2, 20000)
         assert st == 0, s.error()
         U = s.get(lbm.LBM_FIELD_U)
+        st, ai = s.ad(1e-3, 20000)
+        assert st == 0, s.error()
+        C = s.get(lbm.LBM_FIELD_C)
     fo = O.fluid_solve(cls, C2["tau"], C2["u_in"], 1e-2, 20000)
     assert fo["status"] == "OK" and fi["iters"] == fo["iters"]
     assert np.abs(U - fo["U"].reshape(U.shape)).max() < 1e-9
+    ao = O.ad_solve(cls, fo["U"], C2["D"], C2["c_in"], C2["k"], 1e-3, 20000)
+    assert ao["status"] == "OK" and ai["iters"] == ao["iters"]
+    act = np.isin(cls.reshape(-1), [O.FLUID, O.BIOFILM])
+    assert np.abs(C - ao["C"])[act].max() < 1e-9
 
 
 def test_c3_full_size_fixed_steps(gpu_lib):
