@@ -151,3 +151,22 @@ def test_smoke_mask_percolates():
                                     w["overlap"], w["seed"])
     assert st == 0
     assert L.lbm_percolates(L.lbm_biofilm_layer(cls))
+
+
+def test_oracle_and_product_are_independent():
+    """The oracle imports nothing of the product package and the product
+    imports nothing of the oracle; the library's sources include nothing
+    from oracle/ and the oracle's C includes nothing from the library."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_1802_07525_amd")
+    orc = os.path.join(root, "oracle")
+    for d, banned in ((orc, r"paper_1802_07525_amd|_lbm"), (pkg, r"\boracle\b")):
+        for dirpath, _, files in os.walk(d):
+            for fn in files:
+                if not fn.endswith((".py", ".c", ".h", ".cpp", ".hip")):
+                    continue
+                text = open(os.path.join(dirpath, fn)).read()
+                for line in text.splitlines():
+                    s = line.strip()
+                    if s.startswith(("import ", "from ", "#include")):
+                        assert not re.search(banned, s), (fn, s)
