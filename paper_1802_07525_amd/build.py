@@ -17,7 +17,10 @@ LIB = os.path.join(PKG, "_lbm.so")
 SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+# -ffp-contract=on: multiply-adds are fused per source expression, not
+# after inlining, so every instance of a tile function (the single-domain
+# kernels' tile shapes, the server's) rounds the same way
+COMMON = ["-O3", "-std=c++17", "-ffp-contract=on", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

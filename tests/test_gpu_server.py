@@ -246,3 +246,30 @@ def test_server_max_iter_and_rejections(srv_env):
     assert r["status"] == r["status_fluid"] == s["sf"] == lbm.LBM_EDIVERGED
     assert r["iters_fluid"] == s["fi"]["iters"] and r["iters_ad"] == 0
     assert not np.any(r["c"]) and r["flux"][0] == s["fi"]["flux_in"]
+
+
+def test_server_matches_wide_single_solve(srv_env):
+    """A 1024 x 512 request: the server steps it with 64 x 4 tiles, the
+    single solve with the wide two-step kernel (64 x 16 tiles, 1024-thread
+    blocks).  Both make the same multiply-add choices (fused per source
+    expression), so the states stay equal bit for bit: 400 steps of each
+    solver, then statuses, counts and the FP64 fluxes of the final states."""
+    lbm, ctx = srv_env
+    spec = (1024, 512, 0.3, 0.8, 0.01, 21)
+    need = lbm.lbm_server_footprint(spec[0], spec[1], FP32S)
+    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=FP32S)
+    srv = lbm.lbm_server_create(ctx, cfg)
+    print("server vs wide single solve 1024x512", flush=True)
+    try:
+        st, t = lbm.lbm_server_submit(srv, _request(lbm, spec, max_iter=400))
+        assert st == 0, lbm.lbm_server_error(srv)
+        assert lbm.lbm_server_drain(srv, 120.0) == 0
+        r = lbm.lbm_server_poll(srv, 1, 1.0)[0]
+    finally:
+        lbm.lbm_server_destroy(srv)
+    s = _single(lbm, ctx, spec, FP32S, max_iter=400)
+    assert r["status_fluid"] == s["sf"] == lbm.LBM_NOT_CONVERGED
+    assert r["iters_fluid"] == s["fi"]["iters"] == 400 and r["iters_ad"] == s["ai"]["iters"] == 400
+    assert r["flux"][0] == s["fi"]["flux_in"] and r["flux"][1] == s["fi"]["flux_out"]
+    assert r["flux"][2] == s["ai"]["flux_in"] and r["flux"][3] == s["ai"]["flux_out"]
+    assert r["flux"][4] == s["ai"]["sink_total"]
