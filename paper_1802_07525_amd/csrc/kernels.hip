@@ -796,6 +796,10 @@ constexpr int PAIR_TY = 4;
 constexpr int WIDE_TY = 16, WIDE_NTH = 1024;
 // blocks of the wide form needed to use it: two per CU
 constexpr int WIDE_MIN_TILES = 512;
+// middle form for grids of 256-511 tiles of 64 x 8 (e.g. 512 x 256): 64 x 8
+// tiles on 512-thread blocks, the same 8 waves per CU as 64 x 4 there
+constexpr int MID_TY = 8, MID_NTH = 512;
+constexpr int MID_MIN_TILES = 256;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
@@ -1882,12 +1886,16 @@ int pair_ty(int storage, const Geo &g)
     const bool means = storage == ST_F16S;
     static_assert(SF16S::tile_mean && !SF32S::tile_mean && !SF32::tile_mean && !SF64::tile_mean,
                   "tile means are FP16 storage's alone");
-    return !means && pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES ? WIDE_TY : PAIR_TY;
+    if (means)
+        return PAIR_TY;
+    if (pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES)
+        return WIDE_TY;
+    return pair_tiles(g, MID_TY) >= MID_MIN_TILES ? MID_TY : PAIR_TY;
 }
 
 hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
 {
-    const bool wide = pair_ty(storage, a.g) == WIDE_TY;
+    const int ty = pair_ty(storage, a.g);
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         auto go = [&](auto ty, auto nth) {
@@ -1908,8 +1916,10 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
         if constexpr (S::tile_mean) {
             go(std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
         } else {
-            if (wide)
+            if (ty == WIDE_TY)
                 go(std::integral_constant<int, WIDE_TY>{}, std::integral_constant<int, WIDE_NTH>{});
+            else if (ty == MID_TY)
+                go(std::integral_constant<int, MID_TY>{}, std::integral_constant<int, MID_NTH>{});
             else
                 go(std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
         }
@@ -1919,7 +1929,7 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
 
 hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t st)
 {
-    const bool wide = pair_ty(storage, a.g) == WIDE_TY;
+    const int ty = pair_ty(storage, a.g);
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         auto go = [&](auto la, auto qf, auto ty, auto nth) {
@@ -1943,8 +1953,10 @@ hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t
             if constexpr (S::tile_mean) {
                 go(la, qf, std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
             } else {
-                if (wide)
+                if (ty == WIDE_TY)
                     go(la, qf, std::integral_constant<int, WIDE_TY>{}, std::integral_constant<int, WIDE_NTH>{});
+                else if (ty == MID_TY)
+                    go(la, qf, std::integral_constant<int, MID_TY>{}, std::integral_constant<int, MID_NTH>{});
                 else
                     go(la, qf, std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
             }

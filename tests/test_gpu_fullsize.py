@@ -6,7 +6,8 @@ fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
 (the residual checks, the stop decision and the iteration count).  On the
 2-D grid FP64 and FP32 storage run the wide two-step kernels (64 x 16
 tiles, 1024-thread blocks), FP16 the 64 x 4 ones -- the forms the
-benchmark times.
+benchmark times; the 512 x 256 coupled-loop grid runs the middle form
+(64 x 8 tiles, 512-thread blocks).
 Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
 and FP16 5e-3 relative L2 on the fields.
 """
@@ -91,6 +92,14 @@ def test_c2_full_size_fp64_steady(gpu_lib):
     assert ao["status"] == "OK" and ai["iters"] == ao["iters"]
     act = np.isin(cls.reshape(-1), [O.FLUID, O.BIOFILM])
     assert np.abs(C - ao["C"])[act].max() < 1e-9
+
+
+@pytest.mark.parametrize("storage", [FP64, FP32S], ids=["fp64", "fp32s"])
+def test_c5_full_size_fixed_steps(gpu_lib, storage):
+    """512 x 256, the coupled loop's grid: the middle two-step form (64 x 8
+    tiles, 512-thread blocks)."""
+    cls, U, C, Uo, Co = _fixed(gpu_lib, inputs.WORKLOADS["c5"], storage, 60, 60)
+    _check(storage, cls, U, C, Uo, Co)
 
 
 def test_c3_full_size_fixed_steps(gpu_lib):

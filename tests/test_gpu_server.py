@@ -248,18 +248,20 @@ def test_server_max_iter_and_rejections(srv_env):
     assert not np.any(r["c"]) and r["flux"][0] == s["fi"]["flux_in"]
 
 
-def test_server_matches_wide_single_solve(srv_env):
-    """A 1024 x 512 request: the server steps it with 64 x 4 tiles, the
-    single solve with the wide two-step kernel (64 x 16 tiles, 1024-thread
-    blocks).  Both make the same multiply-add choices (fused per source
-    expression), so the states stay equal bit for bit: 400 steps of each
-    solver, then statuses, counts and the FP64 fluxes of the final states."""
+@pytest.mark.parametrize("spec", [(1024, 512, 0.3, 0.8, 0.01, 21), (512, 256, 0.3, 0.8, 0.01, 22)],
+                         ids=["1024x512-wide", "512x256-middle"])
+def test_server_matches_wide_single_solve(srv_env, spec):
+    """Large requests: the server steps them with 64 x 4 tiles, the single
+    solve with the wide (64 x 16 tiles, 1024-thread blocks) or middle (64 x
+    8, 512 threads) two-step kernel.  All make the same multiply-add
+    choices (fused per source expression), so the states stay equal bit
+    for bit: 400 steps of each solver, then statuses, counts and the FP64
+    fluxes of the final states."""
     lbm, ctx = srv_env
-    spec = (1024, 512, 0.3, 0.8, 0.01, 21)
     need = lbm.lbm_server_footprint(spec[0], spec[1], FP32S)
     cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=FP32S)
     srv = lbm.lbm_server_create(ctx, cfg)
-    print("server vs wide single solve 1024x512", flush=True)
+    print("server vs single solve %dx%d" % spec[:2], flush=True)
     try:
         st, t = lbm.lbm_server_submit(srv, _request(lbm, spec, max_iter=400))
         assert st == 0, lbm.lbm_server_error(srv)
