@@ -270,6 +270,21 @@ lbm_status lbm_ad_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const dou
                          double tol, int64_t max_iter, int storage, double *c_field,
                          lbm_info *info);
 
+/* Device-pointer forms of the two one-shot solves, for callers that hold
+ * the mask and the fields in device memory (e.g. torch tensors): the same
+ * arguments and results, but cls (uint8 [N]), u (double [dim][N]), u_out
+ * and c_field are device pointers on the context's device.  The mask and
+ * the input velocity are read back to the host once (geometry and link
+ * words are built on the host); the outputs are written device to device
+ * on the context's stream, which is synchronised before return. */
+lbm_status lbm_fluid_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
+                                double u_in, double tol, int64_t max_iter, int storage,
+                                double *u_out, lbm_info *info);
+lbm_status lbm_ad_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const double *u,
+                             double D, double c_in, double k_sink, int outlet, double c_out,
+                             double tol, int64_t max_iter, int storage, double *c_field,
+                             lbm_info *info);
+
 /* ----------------------------------------------------- stateful solver */
 /* A solver owns the device state of one domain: both solvers' populations
  * (A/B pull buffers), the velocity the substrate solve reads, the node

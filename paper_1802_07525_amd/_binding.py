@@ -165,6 +165,8 @@ _SIGS = {
     "lbm_splitmix64": (None, [U64, I64, P]),
     "lbm_fluid_steady": (I32, [P, G, P, D, D, D, I64, I32, P, P]),
     "lbm_ad_steady": (I32, [P, G, P, P, D, D, D, I32, D, D, I64, I32, P, P]),
+    "lbm_fluid_steady_dev": (I32, [P, G, P, D, D, D, I64, I32, P, P]),
+    "lbm_ad_steady_dev": (I32, [P, G, P, P, D, D, D, I32, D, D, I64, I32, P, P]),
     "lbm_solver_create": (I32, [P, G, P, P, P]),
     "lbm_solver_destroy": (None, [P]),
     "lbm_solver_fluid": (I32, [P, D, I64, I32, P]),
@@ -364,6 +366,29 @@ def lbm_ad_steady(ctx, cls, u, D, c_in, k_sink, tol, max_iter, outlet=LBM_OUT_ZE
                               float(k_sink), int(outlet), float(c_out), float(tol), int(max_iter),
                               int(storage), _p(C), ct.byref(info))
     return st, C, info.as_dict()
+
+
+def lbm_fluid_steady_dev(ctx, grid, cls_ptr, tau, u_in, tol, max_iter, u_ptr,
+                         storage=LBM_FP32_SHIFTED):
+    """Device-pointer form: grid (nx, ny, nz); cls_ptr and u_ptr are device
+    addresses (e.g. tensor.data_ptr()) of uint8 [N] and float64 [dim][N]."""
+    info = lbm_info()
+    st = load().lbm_fluid_steady_dev(ctx, lbm_grid(*grid), ct.c_void_p(cls_ptr), float(tau),
+                                     float(u_in), float(tol), int(max_iter), int(storage),
+                                     ct.c_void_p(u_ptr), ct.byref(info))
+    return st, info.as_dict()
+
+
+def lbm_ad_steady_dev(ctx, grid, cls_ptr, u_ptr, D, c_in, k_sink, tol, max_iter, c_ptr,
+                      outlet=LBM_OUT_ZERO_GRADIENT, c_out=0.0, storage=LBM_FP32_SHIFTED):
+    """Device-pointer form of lbm_ad_steady (device addresses as above;
+    c_ptr: float64 [N])."""
+    info = lbm_info()
+    st = load().lbm_ad_steady_dev(ctx, lbm_grid(*grid), ct.c_void_p(cls_ptr), ct.c_void_p(u_ptr),
+                                  float(D), float(c_in), float(k_sink), int(outlet), float(c_out),
+                                  float(tol), int(max_iter), int(storage), ct.c_void_p(c_ptr),
+                                  ct.byref(info))
+    return st, info.as_dict()
 
 
 def lbm_copy_bandwidth(ctx, nbytes, reps=20):

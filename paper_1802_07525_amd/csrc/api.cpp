@@ -156,6 +156,86 @@ lbm_status lbm_ad_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const dou
     return r;
 }
 
+// the mask of a device-pointer call, staged to the host (geometry is host work)
+static lbm_status mask_from_device(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, std::vector<uint8_t> &out)
+{
+    if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0)
+        return set_err(ctx, LBM_EINVAL, "bad grid");
+    out.resize((size_t)g.nx * g.ny * g.nz);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = hipMemcpy(out.data(), cls, out.size(), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? LBM_OK : hip_err(ctx, e, "mask copy");
+}
+
+lbm_status lbm_fluid_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
+                                double u_in, double tol, int64_t max_iter, int storage,
+                                double *u_out, lbm_info *info)
+{
+    if (!ctx || !cls || !u_out)
+        return set_err(ctx, LBM_EINVAL, "null argument");
+    std::vector<uint8_t> mask;
+    lbm_status st = mask_from_device(ctx, g, cls, mask);
+    if (st)
+        return st;
+    lbm_params p;
+    memset(&p, 0, sizeof(p));
+    p.tau = tau;
+    p.u_in = u_in;
+    p.D = 1.0 / 6.0; // unused by a fluid solve
+    p.c_in = 1.0;
+    p.storage = storage;
+    p.check_every = 100;
+    lbm_solver *s = nullptr;
+    if ((st = lbm_solver_create(ctx, g, mask.data(), &p, &s)))
+        return st;
+    lbm_status r = lbm_solver_fluid(s, tol, max_iter, 0, info);
+    if (r >= 0) {
+        lbm_status e = get_field_device(s, LBM_FIELD_U, u_out);
+        if (e)
+            r = e;
+    }
+    lbm_solver_destroy(s);
+    return r;
+}
+
+lbm_status lbm_ad_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const double *u,
+                             double D, double c_in, double k_sink, int outlet, double c_out,
+                             double tol, int64_t max_iter, int storage, double *c_field,
+                             lbm_info *info)
+{
+    if (!ctx || !cls || !u || !c_field)
+        return set_err(ctx, LBM_EINVAL, "null argument");
+    std::vector<uint8_t> mask;
+    lbm_status st = mask_from_device(ctx, g, cls, mask);
+    if (st)
+        return st;
+    lbm_params p;
+    memset(&p, 0, sizeof(p));
+    p.tau = 1.0;   // unused by a substrate solve
+    p.u_in = 0.01; // unused by a substrate solve
+    p.D = D;
+    p.c_in = c_in;
+    p.k_sink = k_sink;
+    p.outlet = outlet;
+    p.c_out = c_out;
+    p.storage = storage;
+    p.check_every = 100;
+    lbm_solver *s = nullptr;
+    if ((st = lbm_solver_create_ex(ctx, g, mask.data(), &p, 0, &s)))
+        return st;
+    lbm_status r = set_u_device(s, u);
+    if (r == LBM_OK)
+        r = lbm_solver_ad(s, tol, max_iter, 0, info);
+    if (r >= 0) {
+        lbm_status e = get_field_device(s, LBM_FIELD_C, c_field);
+        if (e)
+            r = e;
+    }
+    lbm_solver_destroy(s);
+    return r;
+}
+
 lbm_status lbm_copy_bandwidth(lbm_ctx *ctx, size_t bytes, int reps, double *gbps, double *ms_per_copy)
 {
     if (!ctx || bytes < 16 || reps < 1)

@@ -77,6 +77,10 @@ int64_t growth_pick(const lbm_grid &g, const uint8_t *cls, const double *C, doub
 // enqueue the substrate concentration of every node (FP64, the value each
 // node collides with) into device memory dst [N] on the solver's stream
 lbm_status export_c_device(lbm_solver *s, double *dst);
+// field U, RHO or C (FP64) into device memory dst; synchronises the stream
+lbm_status get_field_device(lbm_solver *s, int field, void *dst);
+// the frozen velocity from device double [dim][N] (staged through the host)
+lbm_status set_u_device(lbm_solver *s, const double *u);
 
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);

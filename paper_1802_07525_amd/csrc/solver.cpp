@@ -454,7 +454,9 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     return result;
 }
 
-lbm_status get_field(lbm_solver *s, int field, void *dst)
+// kind: where dst lives for the exported fields (U, RHO, C): host
+// (DeviceToHost) or device (DeviceToDevice); the other fields are host only
+lbm_status get_field(lbm_solver *s, int field, void *dst, hipMemcpyKind kind = hipMemcpyDeviceToHost)
 {
     const size_t N = (size_t)s->geo.N;
     hipStream_t st = s->ctx->stream;
@@ -471,9 +473,9 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
                                   U, R, 1, st),
                "export");
         if (field == LBM_FIELD_U)
-            HIPCHK(hipMemcpyAsync(dst, U, (size_t)s->dim * N * 8, hipMemcpyDeviceToHost, st), "copy");
+            HIPCHK(hipMemcpyAsync(dst, U, (size_t)s->dim * N * 8, kind, st), "copy");
         else
-            HIPCHK(hipMemcpyAsync(dst, R, N * 8, hipMemcpyDeviceToHost, st), "copy");
+            HIPCHK(hipMemcpyAsync(dst, R, N * 8, kind, st), "copy");
         break;
     }
     case LBM_FIELD_C:
@@ -484,7 +486,7 @@ lbm_status get_field(lbm_solver *s, int field, void *dst)
         HIPCHK(lbmk::ad_export(ad_lay(s), s->p.storage, s->d_g[s->gcur], ad_desc(s), s->geo, ref_cur(s, 1),
                                lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_stage, 1, st),
                "export");
-        HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, hipMemcpyDeviceToHost, st), "copy");
+        HIPCHK(hipMemcpyAsync(dst, s->d_stage, N * 8, kind, st), "copy");
         break;
     case LBM_FIELD_CLASS:
         memcpy(dst, s->cls.data(), N);
@@ -545,6 +547,23 @@ size_t state_size(const lbm_solver *s)
 }
 
 } // namespace
+
+lbm_status lbmh::get_field_device(lbm_solver *s, int field, void *dst)
+{
+    if (field != LBM_FIELD_U && field != LBM_FIELD_RHO && field != LBM_FIELD_C)
+        return set_err(s->ctx, LBM_EINVAL, "only U, RHO and C export to device memory");
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    return get_field(s, field, dst, hipMemcpyDeviceToDevice);
+}
+
+lbm_status lbmh::set_u_device(lbm_solver *s, const double *u)
+{
+    const size_t n = (size_t)s->dim * (size_t)s->geo.N;
+    std::vector<double> h(n);
+    HIPCHK(hipSetDevice(s->ctx->device), "set device");
+    HIPCHK(hipMemcpy(h.data(), u, n * 8, hipMemcpyDeviceToHost), "velocity copy");
+    return lbm_solver_set_u(s, h.data());
+}
 
 lbm_status lbmh::export_c_device(lbm_solver *s, double *dst)
 {
