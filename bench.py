@@ -99,7 +99,19 @@ def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     return {"value": upd / (tf + ta) / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": "%d fluid + %d substrate FP64 steps from rest on the same %s mask "
-                      "(%.1f s)" % (steps, asteps, w["name"], tf + ta)}
+                      "(%.1f s)" % (steps, asteps, w["name"], tf + ta),
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def profile_main(args, lbm, ctx, cls, w, storage):
@@ -539,6 +551,11 @@ def main():
     kernel_name = ("k_fluid_step2<%s>" % args.storage if dim == 2
                    else "k_fluid_step<D3Q19,%s>" % args.storage)
     traffic = traffic_for(kernel_name, args.workload, args.storage)
+    # achievable streaming rate on this GPU: a 1 GiB device copy (outside the
+    # timed region), to read the kernel's rate against besides the datasheet
+    copy_gbs, _ = lbm.lbm_copy_bandwidth(ctx, 1 << 30, 10)
+    n_all = w["nx"] * w["ny"] * w["nz"]
+    upd_all = sum((fi_["iters"] + ai_["iters"]) * n_all for _, fi_, _, ai_ in recs)
     out = {
         "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
@@ -550,14 +567,17 @@ def main():
                    "tol": w["tol"], "seed": w["seed"],
                    "fluid_status": lbm.status_name(sf), "fluid_iters": fi["iters"],
                    "ad_status": lbm.status_name(sa), "ad_iters": ai["iters"],
-                   "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"]},
+                   "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"],
+                   "fluid_seconds": fi["seconds"], "ad_seconds": ai["seconds"],
+                   "mlups_all_nodes": upd_all / el / 1e6},
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algo_bytes_per_launch": bytes_f,
                      "steps_per_launch": spl, "avg_launch_ms": avg_f,
                      "avg_launch_ms_isolated": iso_ms,
                      "ad_kernel_gbs": bytes_a / (a_ms / max(a_launch, 1) * 1e-3) / 1e9,
-                     "ad_avg_launch_ms": a_ms / max(a_launch, 1)},
+                     "ad_avg_launch_ms": a_ms / max(a_launch, 1),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
     lbm.lbm_solver_destroy(s)
     lbm.lbm_ctx_destroy(ctx)
