@@ -428,7 +428,8 @@ struct GlobalSrc {
 // FP32 storage: 3% faster on 256 x 128 x 128); otherwise one load from an
 // address selected by the descriptor bit (the 2-D kernels and FP16 storage,
 // where the extra branches cost more than the latency they hide: 11% slower
-// for the 3-D FP16 step).
+// for the 3-D FP16 step; loading both values and selecting without branches
+// did not help the 2-D kernels either).
 template <class S, bool EARLY = false>
 struct BufSrc {
     typedef typename S::C C;
