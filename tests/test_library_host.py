@@ -170,3 +170,15 @@ def test_oracle_and_product_are_independent():
                     s = line.strip()
                     if s.startswith(("import ", "from ", "#include")):
                         assert not re.search(banned, s), (fn, s)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message (and
+    before touching a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
