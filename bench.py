@@ -63,7 +63,8 @@ def traffic_for(kernel, workload, storage):
     rec = t.get("%s|%s|%s" % (kernel, workload, storage))
     if not rec or rec.get("kernel_sha") != kernel_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    # HBM-side bytes per lattice step of the kernel's launches
+    return rec.get("hbm_bytes_per_launch") / rec.get("steps_per_launch", 1)
 
 
 def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
@@ -534,23 +535,31 @@ def main():
     qf, qa = (19, 7) if dim == 3 else (9, 9 if ad9 else 5)
     sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
     cb = 8 if storage == 3 else 4
-    # dominant kernel: fluid step; HIP-event time over its launches in the timed
-    # region.  In 2-D one launch advances two steps, so the algorithmic bytes
-    # of a launch are twice the per-step figure.
+    # dominant kernel: the fluid step; HIP-event time over its launches in the
+    # timed region.  In 2-D a launch advances several steps -- two, or three
+    # with the multi-step form, where each 100-step chunk is 32 three-step
+    # launches and two two-step ones closing it -- so the algorithmic bytes of
+    # a launch are the per-step figure times the solve's steps per launch.
     f_ms = sum(r[1]["kernel_ms"] for r in recs)
     f_launch = sum(r[1]["launches"] for r in recs)
     a_ms = sum(r[3]["kernel_ms"] for r in recs)
     a_launch = sum(r[3]["launches"] for r in recs)
-    spl = 2 if dim == 2 else 1
+    spl_f = sum(r[1]["iters"] for r in recs) / max(f_launch, 1)
+    spl_a = sum(r[3]["iters"] for r in recs) / max(a_launch, 1)
     avg_f = f_ms / max(f_launch, 1)
-    bytes_f = spl * algo_bytes(qf, sb) * fi["active_nodes"]
+    bytes_f = spl_f * algo_bytes(qf, sb) * fi["active_nodes"]
     achieved = bytes_f / (avg_f * 1e-3) / 1e9
-    # isolated per-launch HIP-event timing of the same kernel on the same state
-    _, iso_ms = lbm.lbm_solver_time_steps(s, 0, 200)
-    bytes_a = spl * algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
-    kernel_name = ("k_fluid_step2<%s>" % args.storage if dim == 2
-                   else "k_fluid_step<D3Q19,%s>" % args.storage)
-    traffic = traffic_for(kernel_name, args.workload, args.storage)
+    # isolated per-launch HIP-event timing of the dominant kernel on the same state
+    _, iso_ms = lbm.lbm_solver_time_steps(s, 0, 300)
+    bytes_a = spl_a * algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
+    if dim == 3:
+        kernel_name = "k_fluid_step<D3Q19,%s>" % args.storage
+    elif spl_f > 2.5:
+        kernel_name = "k_fluid_stepN<%s>" % args.storage
+    else:
+        kernel_name = "k_fluid_step2<%s>" % args.storage
+    per_step = traffic_for(kernel_name, args.workload, args.storage)
+    traffic = None if per_step is None else per_step * spl_f
     # achievable streaming rate on this GPU: a 1 GiB device copy (outside the
     # timed region), to read the kernel's rate against besides the datasheet
     copy_gbs, _ = lbm.lbm_copy_bandwidth(ctx, 1 << 30, 10)
@@ -573,7 +582,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algo_bytes_per_launch": bytes_f,
-                     "steps_per_launch": spl, "avg_launch_ms": avg_f,
+                     "steps_per_launch": spl_f, "avg_launch_ms": avg_f,
                      "avg_launch_ms_isolated": iso_ms,
                      "ad_kernel_gbs": bytes_a / (a_ms / max(a_launch, 1) * 1e-3) / 1e9,
                      "ad_avg_launch_ms": a_ms / max(a_launch, 1),

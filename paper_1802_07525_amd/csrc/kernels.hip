@@ -818,6 +818,8 @@ constexpr int WIDE_MIN_TILES = 512;
 // tiles on 512-thread blocks, the same 8 waves per CU as 64 x 4 there
 constexpr int MID_TY = 8, MID_NTH = 512;
 constexpr int MID_MIN_TILES = 256;
+// steps per launch of the fluid's multi-step form (wide tiles, FP32 forms)
+constexpr int MULTI_NS = 3;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
@@ -912,6 +914,157 @@ __device__ __forceinline__ void fluid_tile2(const FluidArgs &a, int tile,
         block_max_commit<NTH / 64>(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
     }
     __syncthreads(); // the block may run another tile: v is reused
+}
+
+// Source of an intermediate step updated in place in LDS: the values a node
+// streams from its neighbours were read into registers (nb[i - 1]) before
+// the block's barrier, since the neighbours overwrite their slots after it;
+// the node's own slot is written only by its own thread, so its own values
+// are read when needed.
+template <class C, int LY, int LX>
+struct StagedSrc {
+    const C (*v)[LY][LX];
+    int lx, ly;
+    const C *nb;
+    __device__ __forceinline__ C own(int i) const { return v[i][ly][lx]; }
+    __device__ __forceinline__ C pull(int i, int o, int, int, int, unsigned int m) const
+    {
+        const C b = v[o][ly][lx];
+        return m ? b : nb[i - 1];
+    }
+};
+
+// LDS bytes of the NS-step tile: one population buffer over the tile and an
+// (NS - 1)-node halo, updated in place, and the region's descriptor words
+template <class C, int TY, int NS>
+constexpr int multi_lds_bytes()
+{
+    return 9 * (TY + 2 * (NS - 1)) * (64 + 2 * (NS - 1)) * (int)sizeof(C) +
+           (TY + 2 * (NS - 1)) * (64 + 2 * (NS - 1)) * 2;
+}
+
+// NS fluid steps of one 64 x TY tile (2-D), NS >= 3: the first over the
+// tile and an (NS - 1)-node halo from global memory into LDS, the
+// intermediate ones in place in LDS over a region one node narrower each
+// step (the streamed values staged in registers across a barrier), the last
+// over the tile from LDS, stored.  The same per-node code as the paired
+// kernel, so the states equal NS single steps up to rounding order; a check
+// (MODE_CHECK) is taken on the last step.  Compute types of 4 bytes: the
+// staged values of two nodes per thread stay within the register budget of
+// full occupancy.
+template <class S, int MODE, bool NT, int TY, int NTH, int NS>
+__device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsigned long long *part_r,
+                                            unsigned long long *part_u, void *smem)
+{
+    typedef D2Q9 L;
+    typedef uint16_t DT;
+    typedef typename S::C C;
+    static_assert(NS >= 3 && sizeof(C) == 4 && !S::tile_mean && !S::colref, "FP32 forms only");
+    constexpr int H = NS - 1, LX = 64 + 2 * H, LY = TY + 2 * H, NR = LX * LY;
+    static_assert(NTH == 64 * TY && (LX - 2) * (LY - 2) <= 2 * NTH, "two staged nodes per thread");
+    C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
+    DT(*dl)[LX] = reinterpret_cast<DT(*)[LX]>(static_cast<char *>(smem) + 9 * NR * sizeof(C));
+    const long long N = a.g.N;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
+    // step 1: the whole region from global memory
+    for (int r = threadIdx.x; r < NR; r += NTH) {
+        const int lx = r % LX, ly = r / LX;
+        const int x = x0 - H + lx, y = y0 - H + ly;
+        const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
+        const unsigned int n = inb ? (unsigned int)(x + nx * y) : 0u;
+        const DT d = inb ? desc[n] : DT(0);
+        dl[ly][lx] = d;
+        if (d & DT(1)) {
+            C f[L::Q], ux, uy, uz, rho;
+            auto src = gsrc;
+            src.set(n);
+            fluid_collide<L, S, DT>(a, x, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                v[i][ly][lx] = f[i];
+        }
+    }
+    __syncthreads();
+    // intermediate steps: region [k - 1, LX - k] x [k - 1, LY - k], in place
+#pragma unroll
+    for (int k = 2; k < NS; ++k) {
+        const int lo = k - 1, RW = LX - 2 * lo, RN = RW * (LY - 2 * lo);
+        C nb[2][L::Q - 1];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = threadIdx.x + q * NTH;
+            if (r < RN) {
+                const int lx = lo + r % RW, ly = lo + r / RW;
+                if (dl[ly][lx] & DT(1)) {
+#pragma unroll
+                    for (int i = 1; i < L::Q; ++i)
+                        nb[q][i - 1] = v[i][ly - L::cy[i]][lx - L::cx[i]];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = threadIdx.x + q * NTH;
+            if (r < RN) {
+                const int lx = lo + r % RW, ly = lo + r / RW;
+                const DT d = dl[ly][lx];
+                if (d & DT(1)) {
+                    C f[L::Q], ux, uy, uz, rho;
+                    const StagedSrc<C, LY, LX> src{v, lx, ly, nb[q]};
+                    fluid_collide<L, S, DT>(a, x0 - H + lx, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+#pragma unroll
+                    for (int i = 0; i < L::Q; ++i)
+                        v[i][ly][lx] = f[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // last step: the tile, one node per thread, stored
+    CheckAcc<false> acc;
+    {
+        const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+        NodePos p;
+        p.x = x0 + lx;
+        p.y = y0 + ly;
+        p.z = 0;
+        p.inb = p.x < nx && p.y < ny;
+        p.n = p.inb ? (unsigned int)(p.x + nx * p.y) : 0u;
+        const DT d = p.inb ? dl[ly + H][lx + H] : DT(0);
+        const bool act = (d & DT(1)) != 0;
+        C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
+        C f[L::Q];
+        if (act) {
+            const LdsSrc<C, L::Q, LY, LX> src{v, lx + H, ly + H};
+            fluid_collide<L, S, DT>(a, p.x, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                f[i] = C(0);
+        }
+        fluid_store<L, S, NT>(a, p, f, a.step + NS - 1);
+        if constexpr (MODE == MODE_CHECK)
+            fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit<NTH / 64>(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
+    }
+}
+
+template <class S, int MODE, bool NT, int TY, int NTH, int NS>
+__global__ void __launch_bounds__(NTH) k_fluid_stepN(FluidArgs a)
+{
+    __shared__ __align__(16) char smem[multi_lds_bytes<typename S::C, TY, NS>()];
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    fluid_tileN<S, MODE, NT, TY, NTH, NS>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                          part + gridDim.x + blockIdx.x, smem);
 }
 
 template <class L, class S, class DT, int MODE, bool NT, bool BUF>
@@ -1226,6 +1379,131 @@ __global__ void __launch_bounds__(NTH) k_ad_step2(AdArgs a)
     unsigned long long *part = a.ctrl->part;
     ad_tile2<S, MODE, NT, L, QF, TY, NTH>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
                                           part + gridDim.x + blockIdx.x, smem);
+}
+
+// NS substrate steps of one 64 x TY tile (2-D), as fluid_tileN: the first
+// from global memory over the tile and an (NS - 1)-node halo, the
+// intermediate ones in place in LDS with the streamed values staged in
+// registers, the last stored; the frozen velocity is read from global memory
+// (cache-resident) at each step.
+template <class S, int MODE, bool NT, class L, int QF, int TY, int NTH, int NS>
+__device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned long long *part_r,
+                                         unsigned long long *part_u, void *smem)
+{
+    typedef uint16_t DT;
+    typedef typename S::C C;
+    static_assert(NS >= 3 && sizeof(C) == 4 && !S::tile_mean && !S::colref, "FP32 forms only");
+    constexpr int ACT = QF - 1 + L::Q;
+    constexpr int H = NS - 1, LX = 64 + 2 * H, LY = TY + 2 * H, NR = LX * LY;
+    static_assert(NTH == 64 * TY && (LX - 2) * (LY - 2) <= 2 * NTH, "two staged nodes per thread");
+    C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
+    DT(*dl)[LX] = reinterpret_cast<DT(*)[LX]>(static_cast<char *>(smem) + L::Q * NR * sizeof(C));
+    const long long N = a.g.N;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
+    const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
+    const unsigned int NN = (unsigned int)N;
+    const C r0 = C(a.c_ref);
+    // node index of region slot (lx, ly) (only read for active slots)
+    auto node = [&](int lx, int ly) { return (unsigned int)(x0 - H + lx + nx * (y0 - H + ly)); };
+    for (int r = threadIdx.x; r < NR; r += NTH) {
+        const int lx = r % LX, ly = r / LX;
+        const int x = x0 - H + lx, y = y0 - H + ly;
+        const bool inb = x >= 0 && x < nx && y >= 0 && y < ny;
+        const unsigned int n = inb ? (unsigned int)(x + nx * y) : 0u;
+        const DT d = inb ? desc[n] : DT(0);
+        dl[ly][lx] = d;
+        if ((d >> ACT) & DT(1)) {
+            C g[L::Q], cfull;
+            auto src = gsrc;
+            src.set(n);
+            ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, C(0), C(0), g, cfull);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                v[i][ly][lx] = g[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 2; k < NS; ++k) {
+        const int lo = k - 1, RW = LX - 2 * lo, RN = RW * (LY - 2 * lo);
+        C nb[2][L::Q - 1];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = threadIdx.x + q * NTH;
+            if (r < RN) {
+                const int lx = lo + r % RW, ly = lo + r / RW;
+                if ((dl[ly][lx] >> ACT) & DT(1)) {
+#pragma unroll
+                    for (int i = 1; i < L::Q; ++i)
+                        nb[q][i - 1] = v[i][ly - L::cy[i]][lx - L::cx[i]];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = threadIdx.x + q * NTH;
+            if (r < RN) {
+                const int lx = lo + r % RW, ly = lo + r / RW;
+                const DT d = dl[ly][lx];
+                if ((d >> ACT) & DT(1)) {
+                    const unsigned int n = node(lx, ly);
+                    C g[L::Q], cfull;
+                    const StagedSrc<C, LY, LX> src{v, lx, ly, nb[q]};
+                    ad_collide<L, QF, S, DT>(a, x0 - H + lx, d, src, U[n], U[NN + n], C(0), r0, C(0), C(0),
+                                             g, cfull);
+#pragma unroll
+                    for (int i = 0; i < L::Q; ++i)
+                        v[i][ly][lx] = g[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    CheckAcc<false> acc;
+    {
+        const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+        NodePos p;
+        p.x = x0 + lx;
+        p.y = y0 + ly;
+        p.z = 0;
+        p.inb = p.x < nx && p.y < ny;
+        p.n = p.inb ? (unsigned int)(p.x + nx * p.y) : 0u;
+        const DT d = p.inb ? dl[ly + H][lx + H] : DT(0);
+        const bool act = ((d >> ACT) & DT(1)) != 0;
+        C cfull = C(0);
+        C g[L::Q];
+        if (act) {
+            const LdsSrc<C, L::Q, LY, LX> src{v, lx + H, ly + H};
+            ad_collide<L, QF, S, DT>(a, p.x, d, src, U[p.n], U[NN + p.n], C(0), r0, C(0), C(0), g, cfull);
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                g[i] = C(0);
+        }
+        ad_store<L, S, NT>(a, p, g, a.step + NS - 1);
+        if constexpr (MODE == MODE_CHECK)
+            ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit<NTH / 64>(dbits(r * a.inv_cin), 0ull, part_r, part_u);
+    }
+}
+
+template <class S, int MODE, bool NT, class L, int QF, int TY, int NTH, int NS>
+__global__ void __launch_bounds__(NTH) k_ad_stepN(AdArgs a)
+{
+    __shared__ __align__(16) char smem[L::Q * (TY + 2 * (NS - 1)) * (64 + 2 * (NS - 1)) * sizeof(typename S::C) +
+                                       (TY + 2 * (NS - 1)) * (64 + 2 * (NS - 1)) * 2];
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    ad_tileN<S, MODE, NT, L, QF, TY, NTH, NS>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                              part + gridDim.x + blockIdx.x, smem);
 }
 
 // ------------------------------------------------------- init / export
@@ -1942,6 +2220,79 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
                 go(std::integral_constant<int, PAIR_TY>{}, std::integral_constant<int, 256>{});
         }
         return hipGetLastError();
+    });
+}
+
+int fluid_launch_steps(int storage, const Geo &g)
+{
+    return (storage == ST_F32 || storage == ST_F32S) && pair_ty(storage, g) == WIDE_TY ? MULTI_NS : 2;
+}
+
+hipError_t fluid_stepN(int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    if (fluid_launch_steps(storage, a.g) != MULTI_NS)
+        return hipErrorInvalidValue;
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
+            const dim3 grid(pair_tiles(a.g, WIDE_TY));
+            if (a.streaming_stores) {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, true, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
+                                       dim3(WIDE_NTH), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, true, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
+                                       dim3(WIDE_NTH), 0, st, a);
+            } else {
+                if (mode == MODE_CHECK)
+                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, false, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
+                                       dim3(WIDE_NTH), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, false, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
+                                       dim3(WIDE_NTH), 0, st, a);
+            }
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
+hipError_t ad_stepN(int lay, int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    if (fluid_launch_steps(storage, a.g) != MULTI_NS)
+        return hipErrorInvalidValue;
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
+            const dim3 grid(pair_tiles(a.g, WIDE_TY));
+            auto go = [&](auto la, auto qf) {
+                typedef decltype(la) L;
+                constexpr int QF = decltype(qf)::value;
+                if (a.streaming_stores) {
+                    if (mode == MODE_CHECK)
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, true, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                                           grid, dim3(WIDE_NTH), 0, st, a);
+                    else
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, true, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                                           grid, dim3(WIDE_NTH), 0, st, a);
+                } else {
+                    if (mode == MODE_CHECK)
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, false, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                                           grid, dim3(WIDE_NTH), 0, st, a);
+                    else
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, false, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                                           grid, dim3(WIDE_NTH), 0, st, a);
+                }
+            };
+            if (lay == LAY_2D_AD9)
+                go(D2Q9{}, std::integral_constant<int, 1>{});
+            else
+                go(D2Q5{}, std::integral_constant<int, 9>{});
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
     });
 }
 

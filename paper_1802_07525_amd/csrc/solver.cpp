@@ -193,12 +193,43 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
     return LBM_OK;
 }
 
-// 2-D solvers launch two steps at a time (one launch, LDS between them)
+// 2-D solvers launch several steps at a time (one launch, LDS between them)
 inline bool paired(const lbm_solver *s) { return s->dim == 2; }
-// kernel launches that cover `steps` steps taken from a chunk boundary
-inline int64_t launches_for(const lbm_solver *s, int64_t steps)
+// most steps one launch of this solver takes: 1 in 3-D; in 2-D 2, or 3 for
+// the multi-step form
+inline int launch_steps(const lbm_solver *s, int which)
 {
-    return paired(s) ? steps / 2 + (steps & 1) : steps;
+    (void)which; // both solvers take the same form
+    if (!paired(s))
+        return 1;
+    return lbmk::fluid_launch_steps(s->p.storage, s->geo);
+}
+// steps of the next launch with `rem` steps left: threes while more than
+// four or exactly three remain, then twos, and a one only to finish an odd
+// count -- a chunk of K (even) steps thus ends on a two- or three-step
+// launch, whose per-block check maxima are the ones the decide reads
+inline int next_launch(int spl, int64_t rem)
+{
+    if (spl >= 3 && (rem > 4 || rem == 3))
+        return 3;
+    if (spl >= 2 && rem >= 2)
+        return 2;
+    return 1;
+}
+inline int64_t chunk_launches(int spl, int64_t n)
+{
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; j += next_launch(spl, n - j))
+        ++c;
+    return c;
+}
+// kernel launches that cover `steps` steps taken from a chunk boundary in
+// chunks of check_every steps
+inline int64_t launches_for(const lbm_solver *s, int which, int64_t steps)
+{
+    const int spl = launch_steps(s, which);
+    const int64_t K = s->p.check_every;
+    return (steps / K) * chunk_launches(spl, K) + chunk_launches(spl, steps % K);
 }
 // blocks of the check-step launches (the per-block maxima the decide reads)
 inline int check_blocks(const lbm_solver *s, int which)
@@ -209,7 +240,7 @@ inline int check_blocks(const lbm_solver *s, int which)
     return lbmk::pair_tiles(s->geo, lbmk::pair_ty(s->p.storage, s->geo));
 }
 
-// One launch of `nsteps` (1, or 2 in 2-D) steps reading buffer src.
+// One launch of `nsteps` (1; 2 or 3 in 2-D) steps reading buffer src.
 // first: the first launch after a residual check, which moves the stored
 // state to the column reference sampled at that check (see lbm_kernels.h)
 hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first = false, int nsteps = 1)
@@ -231,6 +262,8 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
         a.ref_src = ref_cur(s, 0);
         a.ref_dst = first ? ref_next(s, 0) : ref_cur(s, 0);
         a.ref_out = ref_next(s, 0);
+        if (nsteps == 3)
+            return lbmk::fluid_stepN(s->p.storage, mode, a, s->ctx->stream);
         return nsteps == 2 ? lbmk::fluid_step2(s->p.storage, mode, a, s->ctx->stream)
                            : lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
     }
@@ -259,6 +292,8 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.ref_src = ref_cur(s, 1);
     a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
     a.ref_out = ref_next(s, 1);
+    if (nsteps == 3)
+        return lbmk::ad_stepN(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
     return nsteps == 2 ? lbmk::ad_step2(ad_lay(s), s->p.storage, mode, a, s->ctx->stream)
                        : lbmk::ad_step(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
 }
@@ -331,6 +366,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
             return stt;
     hipStream_t stream = s->ctx->stream;
     const int K = s->p.check_every;
+    const int spl = launch_steps(s, which);
     // default stall window: slow physical transients (a long porous medium
     // filling up behind a fixed inflow) can hold the residual level for
     // >10^4 steps, so it is long -- except with FP16 storage, whose
@@ -368,7 +404,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         const int64_t rem = max_iter - launched;
         const int64_t n = rem >= K ? K : rem;
         for (int64_t j = 1; j <= n;) {
-            const int k = (paired(s) && j + 1 <= n) ? 2 : 1;
+            const int k = next_launch(spl, n - j + 1);
             const int mode = (n == K && j + k - 1 == K) ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
             HIPCHK(launch_step(s, which, mode, (int)((cur0 + nlaunch) & 1), j == 1, k), "step launch");
             if (j == 1 && roll)
@@ -406,7 +442,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     HIPCHK(hipMemcpy(&fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
     const auto t1 = std::chrono::steady_clock::now();
     const int64_t t_final = fin.stop != lbmk::STOP_RUN ? fin.t_stop : launched;
-    cur = (int)((cur0 + launches_for(s, t_final)) & 1);
+    cur = (int)((cur0 + launches_for(s, which, t_final)) & 1);
     // launches queued behind the stop returned at once: the step counter
     // (the stochastic-rounding seed) counts the steps actually taken, so
     // that later solves do not depend on how many were in flight
@@ -432,7 +468,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         info->active_nodes = which == LBM_SOLVER_FLUID ? s->n_fluid : s->n_ad;
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
         info->kernel_ms = ms;
-        info->launches = launches_for(s, t_final);
+        info->launches = launches_for(s, which, t_final);
         const double upd = (double)t_final * (double)info->active_nodes;
         info->mlups = info->seconds > 0 ? upd / info->seconds / 1e6 : 0.0;
         info->gbps = ms > 0 ? upd * algo_bytes(s, which) / (ms * 1e-3) / 1e9 : 0.0;
@@ -736,8 +772,9 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
            "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
+    const int spl = launch_steps(s, which);
     for (int64_t t = 0; t < nsteps;) {
-        const int k = (paired(s) && t + 2 <= nsteps) ? 2 : 1;
+        const int k = next_launch(spl, nsteps - t);
         HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, cur, false, k), "step launch");
         cur ^= 1;
         t += k;
@@ -764,7 +801,7 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
                             s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
            "ctrl");
-    const int k = paired(s) ? 2 : 1; // steps per launch
+    const int k = launch_steps(s, which); // steps per launch
     const int nl = (nsteps + k - 1) / k;
     std::vector<hipEvent_t> ev((size_t)2 * nl);
     for (auto &e : ev)

@@ -94,6 +94,38 @@ def test_c2_full_size_fp64_steady(gpu_lib):
     assert np.abs(C - ao["C"])[act].max() < 1e-9
 
 
+def test_c2_full_size_fp32s_steady_iteration_matched(gpu_lib):
+    """FP32 shifted storage takes the three-step kernels on this grid
+    (chunks of 100 steps: 32 three-step launches, then two two-step ones
+    carrying the check).  Fluid to 1e-2, substrate to 1e-3; the oracle then
+    runs exactly the GPU's step counts and the fields agree to the FP32
+    bound."""
+    lbm = gpu_lib
+    cls = masks(C2, lbm)
+    with _solver(lbm, cls, C2, FP32S) as s:
+        st, fi = s.fluid(1e-2, 20000)
+        assert st == 0, s.error()
+        U = s.get(lbm.LBM_FIELD_U)
+        st, ai = s.ad(1e-3, 20000)
+        assert st == 0, s.error()
+        C = s.get(lbm.LBM_FIELD_C)
+    f, _, _ = O.fluid_run(cls, O.fluid_init(cls), C2["tau"], C2["u_in"], fi["iters"])
+    Uo, _ = O.fluid_moments(cls, f)
+    assert fi["iters"] % 100 == 0 and fi["iters"] >= 200
+    assert rel_l2(U, Uo.reshape(U.shape)) < TOL[FP32S]
+    g, _ = O.ad_run(cls, O.ad_init(cls, Uo, C2["c_in"]), Uo, C2["D"], C2["c_in"], C2["k"], ai["iters"])
+    act = np.isin(cls.reshape(-1), [O.FLUID, O.BIOFILM])
+    assert ai["iters"] % 100 == 0 and ai["iters"] >= 200
+    assert rel_l2(C, O.ad_moment(cls, g, C2["k"]), act) < TOL[FP32S]
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 4, 5, 7, 41])
+def test_c2_three_step_planning_fixed_steps(gpu_lib, steps):
+    """Step counts that end on each launch form (threes, twos, a one)."""
+    cls, U, C, Uo, Co = _fixed(gpu_lib, C2, FP32S, steps, 2)
+    _check(FP32S, cls, U, C, Uo, Co)
+
+
 @pytest.mark.parametrize("storage", [FP64, FP32S], ids=["fp64", "fp32s"])
 def test_c5_full_size_fixed_steps(gpu_lib, storage):
     """512 x 256, the coupled loop's grid: the middle two-step form (64 x 8
