@@ -818,8 +818,8 @@ constexpr int WIDE_MIN_TILES = 512;
 // tiles on 512-thread blocks, the same 8 waves per CU as 64 x 4 there
 constexpr int MID_TY = 8, MID_NTH = 512;
 constexpr int MID_MIN_TILES = 256;
-// steps per launch of the fluid's multi-step form (wide tiles, FP32 forms)
-constexpr int MULTI_NS = 3;
+// most steps per launch of the multi-step form (wide tiles, FP32 forms)
+constexpr int MULTI_NS = 4;
 
 // Two fluid steps of one 64 x TY tile (2-D): the first over the tile and its
 // one-node halo (66 x (TY + 2), the halo computed redundantly -- the same
@@ -2228,29 +2228,36 @@ int fluid_launch_steps(int storage, const Geo &g)
     return (storage == ST_F32 || storage == ST_F32S) && pair_ty(storage, g) == WIDE_TY ? MULTI_NS : 2;
 }
 
-hipError_t fluid_stepN(int storage, int mode, const FluidArgs &a, hipStream_t st)
+hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStream_t st)
 {
-    if (fluid_launch_steps(storage, a.g) != MULTI_NS)
+    if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
             const dim3 grid(pair_tiles(a.g, WIDE_TY));
-            if (a.streaming_stores) {
-                if (mode == MODE_CHECK)
-                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, true, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
-                                       dim3(WIDE_NTH), 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, true, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
-                                       dim3(WIDE_NTH), 0, st, a);
-            } else {
-                if (mode == MODE_CHECK)
-                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, false, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
-                                       dim3(WIDE_NTH), 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, false, WIDE_TY, WIDE_NTH, MULTI_NS>), grid,
-                                       dim3(WIDE_NTH), 0, st, a);
-            }
+            auto go = [&](auto nsc) {
+                constexpr int NS = decltype(nsc)::value;
+                if (a.streaming_stores) {
+                    if (mode == MODE_CHECK)
+                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, true, WIDE_TY, WIDE_NTH, NS>), grid,
+                                           dim3(WIDE_NTH), 0, st, a);
+                    else
+                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, true, WIDE_TY, WIDE_NTH, NS>), grid,
+                                           dim3(WIDE_NTH), 0, st, a);
+                } else {
+                    if (mode == MODE_CHECK)
+                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, false, WIDE_TY, WIDE_NTH, NS>), grid,
+                                           dim3(WIDE_NTH), 0, st, a);
+                    else
+                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, false, WIDE_TY, WIDE_NTH, NS>), grid,
+                                           dim3(WIDE_NTH), 0, st, a);
+                }
+            };
+            if (ns == 4)
+                go(std::integral_constant<int, 4>{});
+            else
+                go(std::integral_constant<int, 3>{});
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
@@ -2258,37 +2265,43 @@ hipError_t fluid_stepN(int storage, int mode, const FluidArgs &a, hipStream_t st
     });
 }
 
-hipError_t ad_stepN(int lay, int storage, int mode, const AdArgs &a, hipStream_t st)
+hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hipStream_t st)
 {
-    if (fluid_launch_steps(storage, a.g) != MULTI_NS)
+    if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
             const dim3 grid(pair_tiles(a.g, WIDE_TY));
-            auto go = [&](auto la, auto qf) {
+            auto go = [&](auto la, auto qf, auto nsc) {
                 typedef decltype(la) L;
-                constexpr int QF = decltype(qf)::value;
+                constexpr int QF = decltype(qf)::value, NS = decltype(nsc)::value;
                 if (a.streaming_stores) {
                     if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, true, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, true, L, QF, WIDE_TY, WIDE_NTH, NS>),
                                            grid, dim3(WIDE_NTH), 0, st, a);
                     else
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, true, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, true, L, QF, WIDE_TY, WIDE_NTH, NS>),
                                            grid, dim3(WIDE_NTH), 0, st, a);
                 } else {
                     if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, false, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, false, L, QF, WIDE_TY, WIDE_NTH, NS>),
                                            grid, dim3(WIDE_NTH), 0, st, a);
                     else
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, false, L, QF, WIDE_TY, WIDE_NTH, MULTI_NS>),
+                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, false, L, QF, WIDE_TY, WIDE_NTH, NS>),
                                            grid, dim3(WIDE_NTH), 0, st, a);
                 }
             };
-            if (lay == LAY_2D_AD9)
-                go(D2Q9{}, std::integral_constant<int, 1>{});
+            auto lat = [&](auto nsc) {
+                if (lay == LAY_2D_AD9)
+                    go(D2Q9{}, std::integral_constant<int, 1>{}, nsc);
+                else
+                    go(D2Q5{}, std::integral_constant<int, 9>{}, nsc);
+            };
+            if (ns == 4)
+                lat(std::integral_constant<int, 4>{});
             else
-                go(D2Q5{}, std::integral_constant<int, 9>{});
+                lat(std::integral_constant<int, 3>{});
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;

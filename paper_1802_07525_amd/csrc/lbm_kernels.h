@@ -151,15 +151,15 @@ int pair_tiles(const Geo &g, int ty);
 // (1024-thread blocks) on grids with at least 512 such tiles and no FP16
 // tile means, else 4 (256-thread blocks).
 int pair_ty(int storage, const Geo &g);
-// Steps per launch of either solver in 2-D: 3 (fluid_stepN / ad_stepN) for
-// FP32 and FP32 shifted storage on the wide tiles, else 2.
+// Most steps per launch of either solver in 2-D: 4 (fluid_stepN / ad_stepN)
+// for FP32 and FP32 shifted storage on the wide tiles, else 2.
 int fluid_launch_steps(int storage, const Geo &g);
-// Three fluid steps per launch (2-D; the wide tiles and an in-place LDS
-// region, as fluid_launch_steps allows); the check, if any, on the last.
-hipError_t fluid_stepN(int storage, int mode, const FluidArgs &a, hipStream_t st);
-// Three substrate steps per launch, under the same conditions (lay as
+// ns = 3 or 4 fluid steps per launch (2-D; the wide tiles and an in-place
+// LDS region, as fluid_launch_steps allows); the check, if any, on the last.
+hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStream_t st);
+// ns = 3 or 4 substrate steps per launch, under the same conditions (lay as
 // ad_step2).
-hipError_t ad_stepN(int lay, int storage, int mode, const AdArgs &a, hipStream_t st);
+hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hipStream_t st);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,

@@ -195,7 +195,7 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
 
 // 2-D solvers launch several steps at a time (one launch, LDS between them)
 inline bool paired(const lbm_solver *s) { return s->dim == 2; }
-// most steps one launch of this solver takes: 1 in 3-D; in 2-D 2, or 3 for
+// most steps one launch of this solver takes: 1 in 3-D; in 2-D 2, or 4 for
 // the multi-step form
 inline int launch_steps(const lbm_solver *s, int which)
 {
@@ -204,16 +204,16 @@ inline int launch_steps(const lbm_solver *s, int which)
         return 1;
     return lbmk::fluid_launch_steps(s->p.storage, s->geo);
 }
-// steps of the next launch with `rem` steps left: threes while more than
-// four or exactly three remain, then twos, and a one only to finish an odd
-// count -- a chunk of K (even) steps thus ends on a two- or three-step
-// launch, whose per-block check maxima are the ones the decide reads
+// steps of the next launch with `rem` steps left: the largest launch size
+// that does not leave a single step behind, a one only to finish an odd
+// count -- a chunk of K (even) steps thus ends on a multi-step launch, whose
+// per-block check maxima are the ones the decide reads (K = 100 with four
+// steps per launch: 25 launches of four)
 inline int next_launch(int spl, int64_t rem)
 {
-    if (spl >= 3 && (rem > 4 || rem == 3))
-        return 3;
-    if (spl >= 2 && rem >= 2)
-        return 2;
+    for (int k = spl; k >= 2; --k)
+        if (k <= rem && rem - k != 1)
+            return k;
     return 1;
 }
 inline int64_t chunk_launches(int spl, int64_t n)
@@ -240,7 +240,7 @@ inline int check_blocks(const lbm_solver *s, int which)
     return lbmk::pair_tiles(s->geo, lbmk::pair_ty(s->p.storage, s->geo));
 }
 
-// One launch of `nsteps` (1; 2 or 3 in 2-D) steps reading buffer src.
+// One launch of `nsteps` (1; 2 to 4 in 2-D) steps reading buffer src.
 // first: the first launch after a residual check, which moves the stored
 // state to the column reference sampled at that check (see lbm_kernels.h)
 hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first = false, int nsteps = 1)
@@ -262,8 +262,8 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
         a.ref_src = ref_cur(s, 0);
         a.ref_dst = first ? ref_next(s, 0) : ref_cur(s, 0);
         a.ref_out = ref_next(s, 0);
-        if (nsteps == 3)
-            return lbmk::fluid_stepN(s->p.storage, mode, a, s->ctx->stream);
+        if (nsteps >= 3)
+            return lbmk::fluid_stepN(s->p.storage, mode, nsteps, a, s->ctx->stream);
         return nsteps == 2 ? lbmk::fluid_step2(s->p.storage, mode, a, s->ctx->stream)
                            : lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
     }
@@ -292,8 +292,8 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.ref_src = ref_cur(s, 1);
     a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
     a.ref_out = ref_next(s, 1);
-    if (nsteps == 3)
-        return lbmk::ad_stepN(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
+    if (nsteps >= 3)
+        return lbmk::ad_stepN(ad_lay(s), s->p.storage, mode, nsteps, a, s->ctx->stream);
     return nsteps == 2 ? lbmk::ad_step2(ad_lay(s), s->p.storage, mode, a, s->ctx->stream)
                        : lbmk::ad_step(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
 }

@@ -95,9 +95,9 @@ def test_c2_full_size_fp64_steady(gpu_lib):
 
 
 def test_c2_full_size_fp32s_steady_iteration_matched(gpu_lib):
-    """FP32 shifted storage takes the three-step kernels on this grid
-    (chunks of 100 steps: 32 three-step launches, then two two-step ones
-    carrying the check).  Fluid to 1e-2, substrate to 1e-3; the oracle then
+    """FP32 shifted storage takes the multi-step kernels on this grid
+    (chunks of 100 steps: 25 four-step launches, the last carrying the
+    check).  Fluid to 1e-2, substrate to 1e-3; the oracle then
     runs exactly the GPU's step counts and the fields agree to the FP32
     bound."""
     lbm = gpu_lib
@@ -119,9 +119,9 @@ def test_c2_full_size_fp32s_steady_iteration_matched(gpu_lib):
     assert rel_l2(C, O.ad_moment(cls, g, C2["k"]), act) < TOL[FP32S]
 
 
-@pytest.mark.parametrize("steps", [1, 2, 3, 4, 5, 7, 41])
+@pytest.mark.parametrize("steps", [1, 2, 3, 4, 5, 6, 7, 8, 41])
 def test_c2_three_step_planning_fixed_steps(gpu_lib, steps):
-    """Step counts that end on each launch form (threes, twos, a one)."""
+    """Step counts that end on each launch form (fours, threes, twos, a one)."""
     cls, U, C, Uo, Co = _fixed(gpu_lib, C2, FP32S, steps, 2)
     _check(FP32S, cls, U, C, Uo, Co)
 
