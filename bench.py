@@ -536,9 +536,9 @@ def main():
     sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
     cb = 8 if storage == 3 else 4
     # dominant kernel: the fluid step; HIP-event time over its launches in the
-    # timed region.  In 2-D a launch advances several steps -- two, or three
-    # with the multi-step form, where each 100-step chunk is 32 three-step
-    # launches and two two-step ones closing it -- so the algorithmic bytes of
+    # timed region.  In 2-D a launch advances several steps -- two, or four
+    # with the multi-step form (a 100-step chunk is 25 four-step launches) --
+    # so the algorithmic bytes of
     # a launch are the per-step figure times the solve's steps per launch.
     f_ms = sum(r[1]["kernel_ms"] for r in recs)
     f_launch = sum(r[1]["launches"] for r in recs)

@@ -4,8 +4,8 @@ The 1024 x 512 electrode (the single-solve benchmark) and the 256 x 128 x
 128 fibre electrode, compared with the FP64 oracle element by element after
 fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
 (the residual checks, the stop decision and the iteration count).  On the
-2-D grid FP64 and FP32 storage run the wide two-step kernels (64 x 16
-tiles, 1024-thread blocks), FP16 the 64 x 4 ones -- the forms the
+2-D grid FP32 storage runs the wide four-step kernels and FP64 the wide
+two-step ones (64 x 16 tiles, 1024-thread blocks), FP16 the 64 x 4 ones -- the forms the
 benchmark times; the 512 x 256 coupled-loop grid runs the middle form
 (64 x 8 tiles, 512-thread blocks).
 Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
@@ -67,7 +67,7 @@ def test_c2_full_size_fixed_steps(gpu_lib, storage):
 
 
 def test_c2_full_size_d2q9_substrate(gpu_lib):
-    """The paper's D2Q9 substrate (its own words, the wide two-step kernel)."""
+    """The paper's D2Q9 substrate (its own words, the wide four-step kernel)."""
     cls, U, C, Uo, Co = _fixed(gpu_lib, C2, FP32S, 40, 40, ad9=True)
     _check(FP32S, cls, U, C, Uo, Co)
 

@@ -253,7 +253,7 @@ def test_server_max_iter_and_rejections(srv_env):
 def test_server_matches_wide_single_solve(srv_env, spec):
     """Large requests: the server steps them with 64 x 4 tiles, the single
     solve with the wide (64 x 16 tiles, 1024-thread blocks) or middle (64 x
-    8, 512 threads) two-step kernel.  All make the same multiply-add
+    8, 512 threads) multi-step kernels.  All make the same multiply-add
     choices (fused per source expression), so the states stay equal bit
     for bit: 400 steps of each solver, then statuses, counts and the FP64
     fluxes of the final states."""
