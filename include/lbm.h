@@ -148,7 +148,9 @@ typedef struct {
     double seconds;       /* wall time of the solve, device-synchronous */
     double kernel_ms;     /* HIP-event time over the step-kernel launches */
     int64_t launches;     /* step-kernel launches covered by kernel_ms (a
-                             launch advances two steps in 2-D, one in 3-D) */
+                             launch advances one step in 3-D; in 2-D two,
+                             or up to four with FP32 storage on grids of at
+                             least 512 tiles of 64 x 16 nodes) */
     double mlups;         /* active-node updates per second / 1e6 */
     double gbps;          /* algorithmic bytes / kernel_ms: per active-node update,
                              each population read and written once, the 1-byte
@@ -311,8 +313,10 @@ lbm_status lbm_solver_ad(lbm_solver *s, double tol, int64_t max_iter, int warm,
 lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold,
                             double *kernel_ms);
 /* Per-launch timing: the launches covering nsteps steps of one solver
- * (state must be initialised; in 2-D a launch advances two steps and nsteps
- * is rounded up to even), each bracketed by its own pair of HIP events on
+ * (state must be initialised; in 2-D a launch advances two steps, four
+ * with FP32 storage on grids of at least 512 tiles of 64 x 16 nodes, and
+ * nsteps is rounded up to whole launches), each bracketed by its own pair
+ * of HIP events on
  * the context's stream; *avg_ms = mean event-to-event time per launch. */
 lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *avg_ms);
 /* Recompute the substrate solve's velocity from the stored fluid state. */

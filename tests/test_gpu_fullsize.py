@@ -20,8 +20,8 @@ from paper_1802_07525_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-FP32S, FP16S, FP64 = 1, 2, 3
-TOL = {FP64: 1e-12, FP32S: 1e-4, FP16S: 5e-3}
+FP32, FP32S, FP16S, FP64 = 0, 1, 2, 3
+TOL = {FP64: 1e-12, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3}
 C2 = inputs.WORKLOADS["c2"]
 C3 = inputs.WORKLOADS["c3"]
 
@@ -124,6 +124,53 @@ def test_c2_three_step_planning_fixed_steps(gpu_lib, steps):
     """Step counts that end on each launch form (fours, threes, twos, a one)."""
     cls, U, C, Uo, Co = _fixed(gpu_lib, C2, FP32S, steps, 2)
     _check(FP32S, cls, U, C, Uo, Co)
+
+
+# Wide grids whose sides are no multiples of the 64 x 16 tile (1000 = 15 *
+# 64 + 40, 530 = 33 * 16 + 2; 1090 = 17 * 64 + 2, 483 = 30 * 16 + 3), with
+# over 512 tiles, so the FP32 forms take the multi-step kernels: partial
+# tiles whose halos leave the grid on the right and top edges.
+RAGGED = [inputs.scaled(C2, 1000, 530, seed=23), inputs.scaled(C2, 1090, 483, seed=25)]
+
+
+@pytest.mark.parametrize("steps", [4, 41])
+@pytest.mark.parametrize("storage,ad9", [(FP32, False), (FP32S, False), (FP32S, True)],
+                         ids=["fp32", "fp32s", "fp32s-d2q9"])
+@pytest.mark.parametrize("w", RAGGED, ids=["1000x530", "1090x483"])
+def test_ragged_wide_grid_multi_step(gpu_lib, w, storage, ad9, steps):
+    """One four-step launch, and 41 steps (nine four-step launches, a three
+    and a two), on each solver."""
+    lbm = gpu_lib
+    cls, U, C, Uo, Co = _fixed(lbm, w, storage, steps, steps, ad9)
+    _check(storage, cls, U, C, Uo, Co)
+
+
+def test_ragged_wide_grid_fp32s_steady(gpu_lib):
+    """Steady solves on a ragged wide grid: the checks' per-block maxima
+    cover partial tiles (fluid to 1e-2, substrate to 1e-3); the oracle then
+    runs the GPU's step counts and the fields agree to the FP32 bound."""
+    lbm = gpu_lib
+    w = RAGGED[1]
+    cls = masks(w, lbm)
+    with _solver(lbm, cls, w, FP32S) as s:
+        st, fi = s.fluid(1e-2, 20000)
+        assert st == 0, s.error()
+        U = s.get(lbm.LBM_FIELD_U)
+        st, ai = s.ad(1e-3, 20000)
+        assert st == 0, s.error()
+        C = s.get(lbm.LBM_FIELD_C)
+    fo = O.fluid_solve(cls, w["tau"], w["u_in"], 1e-2, 20000)
+    # FP32 and FP64 residuals take the same stop decision unless one lies
+    # within rounding of the tolerance
+    assert abs(fi["iters"] - fo["iters"]) <= 100
+    # 100-step chunks of four-step launches
+    assert fi["iters"] == 4 * fi["launches"] and ai["iters"] == 4 * ai["launches"]
+    f, _, _ = O.fluid_run(cls, O.fluid_init(cls), w["tau"], w["u_in"], fi["iters"])
+    Uo, _ = O.fluid_moments(cls, f)
+    assert rel_l2(U, Uo.reshape(U.shape)) < TOL[FP32S]
+    g, _ = O.ad_run(cls, O.ad_init(cls, Uo, w["c_in"]), Uo, w["D"], w["c_in"], w["k"], ai["iters"])
+    act = np.isin(cls.reshape(-1), [O.FLUID, O.BIOFILM])
+    assert rel_l2(C, O.ad_moment(cls, g, w["k"]), act) < TOL[FP32S]
 
 
 @pytest.mark.parametrize("storage", [FP64, FP32S], ids=["fp64", "fp32s"])
