@@ -1903,15 +1903,80 @@ __global__ void __launch_bounds__(256) k_decide(Ctrl *c)
 }
 
 // ------------------------------------------------------ batched serving
-// One launch advances every request of the slot table by two steps: block b
-// takes tile v of the table (XCD-banded numbering), finds the owning request
-// by binary search over the tile offsets and runs the same two-step tile code
-// as the single-domain kernels in that request's phase; blocks past the
+// One launch advances every request of the slot table by the same number of
+// steps: block b takes tile v of the table (XCD-banded numbering), finds the
+// owning request by binary search over the tile offsets and runs the tile
+// code of the single-domain kernels in that request's phase; blocks past the
 // table's tiles exit.  The grid is a power of two at least the table's tile
 // count (one captured graph per size).  All of this is uniform across the
 // block.  Requests are 2-D (D2Q9 + D2Q5).  Every phase starts in buffer 0
-// and a chunk has an even number of launches, so launch j of a chunk (steps
-// 2j, 2j + 1) reads buffer j & 1.
+// and a chunk has an even number of launches, so launch j of a chunk reads
+// buffer j & 1.
+
+// Table entry owning tile v (entries are in tile order)
+__device__ __forceinline__ int srv_entry(const SrvTable *tab, int v)
+{
+    int lo = 0, hi = tab->n_active - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->begin[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Step arguments of a slot in launch j of a chunk whose first step is step
+__device__ __forceinline__ FluidArgs srv_fluid_args(const SrvSlot &sl, Ctrl *c, int j, unsigned int step)
+{
+    FluidArgs a;
+    a.src = sl.f[j & 1];
+    a.dst = sl.f[(j & 1) ^ 1];
+    a.desc = sl.desc;
+    a.uprev = sl.prev;
+    a.ctrl = c;
+    a.g = sl.g;
+    a.omega = sl.omega_f;
+    a.u_in = sl.u_in;
+    a.inv_uin = sl.inv_uin;
+    a.streaming_stores = 0;
+    a.step = step;
+    a.ref_src = sl.ref_cur;
+    a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+    a.ref_out = sl.ref_next;
+    return a;
+}
+__device__ __forceinline__ AdArgs srv_ad_args(const SrvSlot &sl, Ctrl *c, int j, unsigned int step)
+{
+    AdArgs a;
+    a.src = sl.gp[j & 1];
+    a.dst = sl.gp[(j & 1) ^ 1];
+    a.desc = sl.desc;
+    a.u = sl.u;
+    a.cprev = sl.prev;
+    a.ctrl = c;
+    a.g = sl.g;
+    a.omega = sl.omega_a;
+    a.cin_s = sl.cin_s;
+    a.cout_s = sl.cout_s;
+    a.c_ref = sl.c_ref;
+    a.k_sink = sl.k_sink;
+    a.k_half = sl.k_half;
+    a.inv_cin = sl.inv_cin;
+    a.outlet = sl.outlet;
+    a.streaming_stores = 0;
+    a.step = step;
+    a.c_in = sl.c_in;
+    a.c_out = sl.c_out;
+    a.ref_src = sl.ref_cur;
+    a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
+    a.ref_out = sl.ref_next;
+    return a;
+}
+
+// Two steps (2j, 2j + 1 of the chunk) over 64 x 4 tiles, 256-thread blocks:
+// every storage form.
 template <class S, int MODE>
 __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ slots,
                                                   const SrvTable *__restrict__ tab, Ctrl *ctrl,
@@ -1923,63 +1988,58 @@ __global__ void __launch_bounds__(256) k_srv_step(const SrvSlot *__restrict__ sl
     const int v = xcd_tile(blockIdx.x, gridDim.x);
     if (v >= tab->total_tiles)
         return;
-    int lo = 0, hi = tab->n_active - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab->begin[mid] <= v)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const int sid = tab->slot[lo];
+    const int e = srv_entry(tab, v);
+    const int sid = tab->slot[e];
     const SrvSlot &sl = slots[sid];
     Ctrl *c = ctrl + sid;
     if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
         return;
-    const int tile = v - tab->begin[lo];
+    const int tile = v - tab->begin[e];
     const unsigned int step = (unsigned int)(c->t + 2 * j);
+    if (sl.phase == SRV_FLUID)
+        fluid_tile2<S, MODE, false>(srv_fluid_args(sl, c, j, step), tile, part + v, part + part_cap + v, smem);
+    else
+        ad_tile2<S, MODE, false>(srv_ad_args(sl, c, j, step), tile, part + v, part + part_cap + v, smem);
+}
+
+// NS steps (2 or 4) over 64 x 16 tiles, 1024-thread blocks: the FP32
+// storage forms, with the wide paired or multi-step tile code of the single
+// solves.  t_off is the launch's first step within the chunk.
+template <class S, int MODE, int NS>
+__global__ void __launch_bounds__(WIDE_NTH) k_srv_stepN(const SrvSlot *__restrict__ slots,
+                                                        const SrvTable *__restrict__ tab, Ctrl *ctrl,
+                                                        unsigned long long *part, int part_cap, int j,
+                                                        int t_off)
+{
+    typedef typename S::C C;
+    constexpr int H = NS - 1, NR = (WIDE_TY + 2 * H) * (64 + 2 * H);
+    constexpr int LF = NS == 2 ? pair_lds_bytes<C, 9, WIDE_TY>() : multi_lds_bytes<C, WIDE_TY, NS>();
+    constexpr int LA = NS == 2 ? pair_lds_bytes<C, 5, WIDE_TY>() : 5 * NR * (int)sizeof(C) + NR * 2;
+    __shared__ __align__(16) char smem[LF > LA ? LF : LA];
+    const int v = xcd_tile(blockIdx.x, gridDim.x);
+    if (v >= tab->total_tiles)
+        return;
+    const int e = srv_entry(tab, v);
+    const int sid = tab->slot[e];
+    const SrvSlot &sl = slots[sid];
+    Ctrl *c = ctrl + sid;
+    if (sl.phase == SRV_IDLE || c->stop != STOP_RUN)
+        return;
+    const int tile = v - tab->begin[e];
+    const unsigned int step = (unsigned int)(c->t + t_off);
+    unsigned long long *pr = part + v, *pu = part + part_cap + v;
     if (sl.phase == SRV_FLUID) {
-        FluidArgs a;
-        a.src = sl.f[j & 1];
-        a.dst = sl.f[(j & 1) ^ 1];
-        a.desc = sl.desc;
-        a.uprev = sl.prev;
-        a.ctrl = c;
-        a.g = sl.g;
-        a.omega = sl.omega_f;
-        a.u_in = sl.u_in;
-        a.inv_uin = sl.inv_uin;
-        a.streaming_stores = 0;
-        a.step = step;
-        a.ref_src = sl.ref_cur;
-        a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
-        a.ref_out = sl.ref_next;
-        fluid_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v, smem);
+        const FluidArgs a = srv_fluid_args(sl, c, j, step);
+        if constexpr (NS == 2)
+            fluid_tile2<S, MODE, false, WIDE_TY, WIDE_NTH>(a, tile, pr, pu, smem);
+        else
+            fluid_tileN<S, MODE, false, WIDE_TY, WIDE_NTH, NS>(a, tile, pr, pu, smem);
     } else {
-        AdArgs a;
-        a.src = sl.gp[j & 1];
-        a.dst = sl.gp[(j & 1) ^ 1];
-        a.desc = sl.desc;
-        a.u = sl.u;
-        a.cprev = sl.prev;
-        a.ctrl = c;
-        a.g = sl.g;
-        a.omega = sl.omega_a;
-        a.cin_s = sl.cin_s;
-        a.cout_s = sl.cout_s;
-        a.c_ref = sl.c_ref;
-        a.k_sink = sl.k_sink;
-        a.k_half = sl.k_half;
-        a.inv_cin = sl.inv_cin;
-        a.outlet = sl.outlet;
-        a.streaming_stores = 0;
-        a.step = step;
-        a.c_in = sl.c_in;
-        a.c_out = sl.c_out;
-        a.ref_src = sl.ref_cur;
-        a.ref_dst = j == 0 ? sl.ref_next : sl.ref_cur;
-        a.ref_out = sl.ref_next;
-        ad_tile2<S, MODE, false>(a, tile, part + v, part + part_cap + v, smem);
+        const AdArgs a = srv_ad_args(sl, c, j, step);
+        if constexpr (NS == 2)
+            ad_tile2<S, MODE, false, D2Q5, 9, WIDE_TY, WIDE_NTH>(a, tile, pr, pu, smem);
+        else
+            ad_tileN<S, MODE, false, D2Q5, 9, WIDE_TY, WIDE_NTH, NS>(a, tile, pr, pu, smem);
     }
 }
 
@@ -2621,6 +2681,38 @@ hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable 
     default:
         return hipErrorInvalidValue;
     }
+}
+
+int srv_tile_ty(int storage)
+{
+    return storage == ST_F32 || storage == ST_F32S ? WIDE_TY : PAIR_TY;
+}
+
+hipError_t srv_stepN(int storage, int mode, int ns, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                     unsigned long long *part, int part_cap, int j, int t_off, int blocks, hipStream_t st)
+{
+    if (srv_tile_ty(storage) != WIDE_TY || (ns != 2 && ns != MULTI_NS))
+        return hipErrorInvalidValue;
+    auto go = [&](auto sp) -> hipError_t {
+        typedef decltype(sp) S;
+        if (ns == 2) {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_srv_stepN<S, MODE_CHECK, 2>), dim3(blocks), dim3(WIDE_NTH), 0, st, slots,
+                                   tab, ctrl, part, part_cap, j, t_off);
+            else
+                hipLaunchKernelGGL((k_srv_stepN<S, MODE_PLAIN, 2>), dim3(blocks), dim3(WIDE_NTH), 0, st, slots,
+                                   tab, ctrl, part, part_cap, j, t_off);
+        } else {
+            if (mode == MODE_CHECK)
+                hipLaunchKernelGGL((k_srv_stepN<S, MODE_CHECK, MULTI_NS>), dim3(blocks), dim3(WIDE_NTH), 0, st,
+                                   slots, tab, ctrl, part, part_cap, j, t_off);
+            else
+                hipLaunchKernelGGL((k_srv_stepN<S, MODE_PLAIN, MULTI_NS>), dim3(blocks), dim3(WIDE_NTH), 0, st,
+                                   slots, tab, ctrl, part, part_cap, j, t_off);
+        }
+        return hipGetLastError();
+    };
+    return storage == ST_F32 ? go(SF32()) : go(SF32S());
 }
 
 hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,

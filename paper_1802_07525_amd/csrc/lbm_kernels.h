@@ -255,6 +255,14 @@ struct SrvTable {
 // tab->total_tiles (the extra blocks exit).
 hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                     unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st);
+// Tile height of the served launches: 16 (64 x 16 tiles, 1024-thread
+// blocks, srv_stepN) for the FP32 storage forms, 4 (srv_step) for FP16.
+int srv_tile_ty(int storage);
+// ns steps (2 or 4) of every request in tab over 64 x 16 tiles: launch j of
+// the current chunk, whose first step is t_off within the chunk.  FP32
+// storage forms only; otherwise as srv_step.
+hipError_t srv_stepN(int storage, int mode, int ns, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
+                     unsigned long long *part, int part_cap, int j, int t_off, int blocks, hipStream_t st);
 // Stop rule for every request in tab after a check step.
 hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                       const unsigned long long *part, int part_cap, hipStream_t st);

@@ -459,7 +459,7 @@ struct lbm_server {
             j->n_ad += (d[n] >> aab) & 1u;
         }
         j->geo = lbmk::make_geo(r.nx, r.ny, 1);
-        j->tiles = lbmk::pair_tiles(j->geo);
+        j->tiles = lbmk::pair_tiles(j->geo, lbmk::srv_tile_ty(cfg.storage));
         j->cls.clear();
         j->cls.shrink_to_fit();
     }
@@ -716,14 +716,33 @@ struct lbm_server {
     hipError_t enqueue_chunk(int grid)
     {
         hipError_t e;
-        const int nl = K / 2; // each launch advances two steps
+        // Steps per launch: FP16 two (64 x 4 tiles); the FP32 forms four
+        // (64 x 16 tiles), the first two launches taking two when K / 4 is
+        // odd, so that a chunk has an even number of launches.  The check
+        // is taken on the last launch.
+        std::vector<int> plan;
+        const bool wide = lbmk::srv_tile_ty(cfg.storage) == 16;
+        if (wide) {
+            const int m = K / 4;
+            plan.assign((size_t)(m & 1 ? 2 : 0), 2);
+            plan.insert(plan.end(), (size_t)(m & 1 ? m - 1 : m), 4);
+        } else {
+            plan.assign((size_t)(K / 2), 2);
+        }
+        const int nl = (int)plan.size();
+        int t_off = 0;
         for (int j = 0; j < nl; ++j) {
-            if ((e = lbmk::srv_step(cfg.storage, j == nl - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN, d_slots,
-                                    d_tab, d_ctrl, d_part, part_cap, j, grid, stream)) != hipSuccess)
+            const int mode = j == nl - 1 ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
+            e = wide ? lbmk::srv_stepN(cfg.storage, mode, plan[(size_t)j], d_slots, d_tab, d_ctrl, d_part,
+                                       part_cap, j, t_off, grid, stream)
+                     : lbmk::srv_step(cfg.storage, mode, d_slots, d_tab, d_ctrl, d_part, part_cap, j, grid,
+                                      stream);
+            if (e != hipSuccess)
                 return e;
             if (j == 0 && lbmk::storage_moving_ref(cfg.storage) &&
                 (e = lbmk::srv_ref_roll(d_slots, d_tab, d_ctrl, stream)) != hipSuccess)
                 return e;
+            t_off += plan[(size_t)j];
         }
         return lbmk::srv_decide(d_slots, d_tab, d_ctrl, d_part, part_cap, stream);
     }
@@ -975,11 +994,13 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
                                                          : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();
-    // tiles: each holds 256 nodes of at least 54 pool bytes; ragged tiles at
-    // the domain edges add at most ntx + nty per request
-    const size_t min_tile = 256 * 54;
-    const size_t pc = c.pool_bytes / min_tile + (size_t)c.max_slots * 1024 + 1024;
-    s->part_cap = (int)std::min<size_t>(pc, (size_t)1 << 30);
+    // tiles: each holds 64 x ty nodes (one per thread of a block) of at
+    // least 54 pool bytes; ragged tiles at the domain edges add at most
+    // ntx + nty per request.  The largest captured grid (the power of two
+    // at or above part_cap) times the block size stays within 2^31 threads.
+    const size_t tile_nodes = (size_t)64 * lbmk::srv_tile_ty(c.storage);
+    const size_t pc = c.pool_bytes / (tile_nodes * 54) + (size_t)c.max_slots * 1024 + 1024;
+    s->part_cap = (int)std::min<size_t>(pc, ((size_t)1 << 31) / tile_nodes);
     auto cleanup = [&](lbm_status st) {
         lbm_server_destroy(s.release());
         return st;
@@ -1068,7 +1089,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
     if (m.empty()) {
         j->lay = layout_of(r->nx, N, s->cfg.storage);
         if (j->lay.total > s->cfg.pool_bytes ||
-            lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1)) > s->part_cap)
+            lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), lbmk::srv_tile_ty(s->cfg.storage)) > s->part_cap)
             m = "request larger than the server pool";
         else if (r->cls)
             j->cls.assign(r->cls, r->cls + N);

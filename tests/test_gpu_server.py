@@ -80,10 +80,11 @@ def _serve(lbm, ctx, specs, storage, pool=None, slots=8, order=None, **cfgkw):
     return res, stats, need
 
 
-def _single(lbm, ctx, spec, storage, tol=1e-6, max_iter=400000):
+def _single(lbm, ctx, spec, storage, tol=1e-6, max_iter=400000, check_every=100):
     nx, ny, solid, tau, u_in, seed = spec
     cls = _mask(lbm, nx, ny, solid, seed)
-    p = lbm.make_params(tau=tau, u_in=u_in, D=D_SUB, c_in=1.0, k_sink=K_SINK, storage=storage)
+    p = lbm.make_params(tau=tau, u_in=u_in, D=D_SUB, c_in=1.0, k_sink=K_SINK, storage=storage,
+                        check_every=check_every)
     s = lbm.lbm_solver_create(ctx, cls, p)
     try:
         sf, fi = lbm.lbm_solver_fluid(s, tol, max_iter)
@@ -95,18 +96,23 @@ def _single(lbm, ctx, spec, storage, tol=1e-6, max_iter=400000):
     return dict(cls=cls, sf=sf, sa=sa, fi=fi, ai=ai, U=U, C=C)
 
 
-@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=["fp32s", "fp16s"])
-def test_server_matches_single_solve(srv_env, storage):
+@pytest.mark.parametrize("storage,K", [(FP32, 100), (FP32S, 100), (FP32S, 40), (FP16S, 100)],
+                         ids=["fp32", "fp32s", "fp32s-K40", "fp16s"])
+def test_server_matches_single_solve(srv_env, storage, K):
+    """FP32 forms are served over 64 x 16 tiles, four steps per launch (a
+    chunk of K = 100 opens with two two-step launches, K = 40 has four-step
+    launches only); FP16 over 64 x 4 tiles, two steps per launch.  The
+    single solves of these small domains take 64 x 4 tiles and two steps."""
     lbm, ctx = srv_env
     specs = MIX[:4]
     need = [lbm.lbm_server_footprint(s[0], s[1], storage) for s in specs]
     pool = max(need) + sorted(need)[-2] + 4096  # at most two largest at once
-    print("server vs single solve, storage", storage, "pool", pool, flush=True)
-    res, stats, _ = _serve(lbm, ctx, specs, storage, pool=pool, slots=3)
+    print("server vs single solve, storage", storage, "K", K, "pool", pool, flush=True)
+    res, stats, _ = _serve(lbm, ctx, specs, storage, pool=pool, slots=3, check_every=K)
     assert sum(need) > pool and stats["pool_peak"] <= pool
     assert stats["finished"] == len(specs) and stats["rejected"] == 0
     for i, spec in enumerate(specs):
-        r, s = res[i], _single(lbm, ctx, spec, storage)
+        r, s = res[i], _single(lbm, ctx, spec, storage, check_every=K)
         assert r["status_fluid"] == s["sf"] and r["status_ad"] == s["sa"], (i, r, s["sf"], s["sa"])
         assert r["iters_fluid"] == s["fi"]["iters"] and r["iters_ad"] == s["ai"]["iters"]
         assert r["active_fluid"] == s["fi"]["active_nodes"] and r["active_ad"] == s["ai"]["active_nodes"]
@@ -120,13 +126,14 @@ def test_server_matches_single_solve(srv_env, storage):
         assert r["t_submit"] <= r["t_admit"] <= r["t_finish"]
 
 
-def test_server_alone_equals_in_mix(srv_env):
+@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=["fp32s", "fp16s"])
+def test_server_alone_equals_in_mix(srv_env, storage):
     lbm, ctx = srv_env
     x = MIX[2]
-    alone, _, _ = _serve(lbm, ctx, [x], FP16S)
+    alone, _, _ = _serve(lbm, ctx, [x], storage)
     mix = [MIX[0], MIX[1], x, MIX[3], MIX[4]]
-    print("alone vs mix", flush=True)
-    inmix, _, _ = _serve(lbm, ctx, mix, FP16S, slots=4, order=[3, 0, 2, 4, 1])
+    print("alone vs mix, storage", storage, flush=True)
+    inmix, _, _ = _serve(lbm, ctx, mix, storage, slots=4, order=[3, 0, 2, 4, 1])
     a, b = alone[0], inmix[2]
     assert a["iters_fluid"] == b["iters_fluid"] and a["iters_ad"] == b["iters_ad"]
     assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["c"], b["c"])
