@@ -952,6 +952,21 @@ constexpr int multi_lds_bytes()
 // (MODE_CHECK) is taken on the last step.  Compute types of 4 bytes: the
 // staged values of two nodes per thread stay within the register budget of
 // full occupancy.
+//
+// Storage that rounds on store (FP16: stochastic rounding, moving column
+// references) takes NS = 4 as two paired launches fused: the second step
+// ends as the paired kernel's store would -- the move to the written
+// buffer's references and the rounding with that store's (node, step)
+// draws -- in LDS, so the states equal those of the paired kernel bit for
+// bit.  Such a launch is never the first after a check (source and
+// destination references are the same) and never a check (tile means are
+// taken over 64 x 4 tiles by the paired kernel).
+template <class S>
+constexpr bool rounds_on_store()
+{
+    return sizeof(typename S::T) != sizeof(typename S::C) || S::colref;
+}
+
 template <class S, int MODE, bool NT, int TY, int NTH, int NS>
 __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsigned long long *part_r,
                                             unsigned long long *part_u, void *smem)
@@ -959,7 +974,9 @@ __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsign
     typedef D2Q9 L;
     typedef uint16_t DT;
     typedef typename S::C C;
-    static_assert(NS >= 3 && sizeof(C) == 4 && !S::tile_mean && !S::colref, "FP32 forms only");
+    constexpr bool EMU = rounds_on_store<S>();
+    static_assert(NS >= 3 && sizeof(C) == 4 && (MODE == MODE_PLAIN || !S::tile_mean), "4-byte compute, no tile means");
+    static_assert(!EMU || NS % 2 == 0, "rounding storage: whole paired launches");
     constexpr int H = NS - 1, LX = 64 + 2 * H, LY = TY + 2 * H, NR = LX * LY;
     static_assert(NTH == 64 * TY && (LX - 2) * (LY - 2) <= 2 * NTH, "two staged nodes per thread");
     C(*v)[LY][LX] = reinterpret_cast<C(*)[LY][LX]>(smem);
@@ -979,9 +996,12 @@ __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsign
         dl[ly][lx] = d;
         if (d & DT(1)) {
             C f[L::Q], ux, uy, uz, rho;
+            C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
             auto src = gsrc;
             src.set(n);
-            fluid_collide<L, S, DT>(a, x, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+            fluid_collide<L, S, DT>(a, x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 v[i][ly][lx] = f[i];
@@ -1014,8 +1034,27 @@ __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsign
                 const DT d = dl[ly][lx];
                 if (d & DT(1)) {
                     C f[L::Q], ux, uy, uz, rho;
+                    const int x = x0 - H + lx;
+                    // step k ends a paired launch when k is even
+                    const bool st_pt = EMU && (k % 2 == 0);
+                    C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+                    if constexpr (S::colref)
+                        column_refs<S>(a.ref_src, st_pt ? a.ref_dst : a.ref_src, x, nx, r0, dm, dp, rd);
                     const StagedSrc<C, LY, LX> src{v, lx, ly, nb[q]};
-                    fluid_collide<L, S, DT>(a, x0 - H + lx, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+                    fluid_collide<L, S, DT>(a, x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
+                    if constexpr (EMU) {
+                        if (st_pt) {
+                            if constexpr (S::colref) {
+#pragma unroll
+                                for (int i = 0; i < L::Q; ++i)
+                                    f[i] += C(L::w[i]) * (r0 - rd);
+                            }
+                            unsigned int rng = sr_seed((unsigned int)(x + nx * (y0 - H + ly)), a.step + k - 1);
+#pragma unroll
+                            for (int i = 0; i < L::Q; ++i)
+                                f[i] = static_cast<C>(pop_value<S>(f[i], rng));
+                        }
+                    }
 #pragma unroll
                     for (int i = 0; i < L::Q; ++i)
                         v[i][ly][lx] = f[i];
@@ -1039,8 +1078,16 @@ __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsign
         C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
         C f[L::Q];
         if (act) {
+            C r0 = C(1), dm = C(0), dp = C(0), rd = C(1);
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
             const LdsSrc<C, L::Q, LY, LX> src{v, lx + H, ly + H};
-            fluid_collide<L, S, DT>(a, p.x, d, src, C(1), C(0), C(0), f, ux, uy, uz, rho);
+            fluid_collide<L, S, DT>(a, p.x, d, src, r0, dm, dp, f, ux, uy, uz, rho);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    f[i] += C(L::w[i]) * (r0 - rd);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -1392,7 +1439,10 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
 {
     typedef uint16_t DT;
     typedef typename S::C C;
-    static_assert(NS >= 3 && sizeof(C) == 4 && !S::tile_mean && !S::colref, "FP32 forms only");
+    // storage that rounds on store: as in fluid_tileN
+    constexpr bool EMU = rounds_on_store<S>();
+    static_assert(NS >= 3 && sizeof(C) == 4 && (MODE == MODE_PLAIN || !S::tile_mean), "4-byte compute, no tile means");
+    static_assert(!EMU || NS % 2 == 0, "rounding storage: whole paired launches");
     constexpr int ACT = QF - 1 + L::Q;
     constexpr int H = NS - 1, LX = 64 + 2 * H, LY = TY + 2 * H, NR = LX * LY;
     static_assert(NTH == 64 * TY && (LX - 2) * (LY - 2) <= 2 * NTH, "two staged nodes per thread");
@@ -1405,7 +1455,6 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
     const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
     const unsigned int NN = (unsigned int)N;
-    const C r0 = C(a.c_ref);
     // node index of region slot (lx, ly) (only read for active slots)
     auto node = [&](int lx, int ly) { return (unsigned int)(x0 - H + lx + nx * (y0 - H + ly)); };
     for (int r = threadIdx.x; r < NR; r += NTH) {
@@ -1417,9 +1466,12 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
         dl[ly][lx] = d;
         if ((d >> ACT) & DT(1)) {
             C g[L::Q], cfull;
+            C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_src, x, nx, r0, dm, dp, rd);
             auto src = gsrc;
             src.set(n);
-            ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, C(0), C(0), g, cfull);
+            ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, dm, dp, g, cfull);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 v[i][ly][lx] = g[i];
@@ -1451,10 +1503,28 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
                 const DT d = dl[ly][lx];
                 if ((d >> ACT) & DT(1)) {
                     const unsigned int n = node(lx, ly);
+                    const int x = x0 - H + lx;
                     C g[L::Q], cfull;
+                    // step k ends a paired launch when k is even
+                    const bool st_pt = EMU && (k % 2 == 0);
+                    C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+                    if constexpr (S::colref)
+                        column_refs<S>(a.ref_src, st_pt ? a.ref_dst : a.ref_src, x, nx, r0, dm, dp, rd);
                     const StagedSrc<C, LY, LX> src{v, lx, ly, nb[q]};
-                    ad_collide<L, QF, S, DT>(a, x0 - H + lx, d, src, U[n], U[NN + n], C(0), r0, C(0), C(0),
-                                             g, cfull);
+                    ad_collide<L, QF, S, DT>(a, x, d, src, U[n], U[NN + n], C(0), r0, dm, dp, g, cfull);
+                    if constexpr (EMU) {
+                        if (st_pt) {
+                            if constexpr (S::colref) {
+#pragma unroll
+                                for (int i = 0; i < L::Q; ++i)
+                                    g[i] += C(L::w[i]) * (r0 - rd);
+                            }
+                            unsigned int rng = sr_seed(n, (a.step + k - 1) ^ 0x5bd1e995u);
+#pragma unroll
+                            for (int i = 0; i < L::Q; ++i)
+                                g[i] = static_cast<C>(pop_value<S>(g[i], rng));
+                        }
+                    }
 #pragma unroll
                     for (int i = 0; i < L::Q; ++i)
                         v[i][ly][lx] = g[i];
@@ -1477,8 +1547,16 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
         C cfull = C(0);
         C g[L::Q];
         if (act) {
+            C r0 = C(a.c_ref), dm = C(0), dp = C(0), rd = r0;
+            if constexpr (S::colref)
+                column_refs<S>(a.ref_src, a.ref_dst, p.x, nx, r0, dm, dp, rd);
             const LdsSrc<C, L::Q, LY, LX> src{v, lx + H, ly + H};
-            ad_collide<L, QF, S, DT>(a, p.x, d, src, U[p.n], U[NN + p.n], C(0), r0, C(0), C(0), g, cfull);
+            ad_collide<L, QF, S, DT>(a, p.x, d, src, U[p.n], U[NN + p.n], C(0), r0, dm, dp, g, cfull);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    g[i] += C(L::w[i]) * (r0 - rd);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
@@ -2285,43 +2363,55 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
 
 int fluid_launch_steps(int storage, const Geo &g)
 {
-    return (storage == ST_F32 || storage == ST_F32S) && pair_ty(storage, g) == WIDE_TY ? MULTI_NS : 2;
+    // FP64 keeps paired launches (its staged values would exceed the
+    // register budget of full occupancy)
+    return storage != ST_F64 && pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES ? MULTI_NS : 2;
+}
+
+// Multi-step launch of one solver: FP32 forms take three or four steps,
+// either mode; storage that rounds on store takes four, plain, with equal
+// source and destination references (see fluid_tileN).  K(NS, MODE, NT)
+// launches the kernel instance.
+template <class S, class K>
+hipError_t launch_multi(int mode, int ns, bool nt, const void *ref_src, const void *ref_dst, K k)
+{
+    if constexpr (sizeof(typename S::C) != 4) {
+        return hipErrorInvalidValue;
+    } else {
+        if (rounds_on_store<S>() && (ns != 4 || mode != MODE_PLAIN || ref_src != ref_dst))
+            return hipErrorInvalidValue;
+        auto go = [&](auto nsc, auto mc, auto ntc) -> hipError_t {
+            constexpr int NS = decltype(nsc)::value, M = decltype(mc)::value;
+            if constexpr ((rounds_on_store<S>() && NS % 2) || (S::tile_mean && M != MODE_PLAIN)) {
+                return hipErrorInvalidValue;
+            } else {
+                k(nsc, mc, ntc);
+                return hipGetLastError();
+            }
+        };
+        auto by_nt = [&](auto nsc, auto mc) {
+            return nt ? go(nsc, mc, std::true_type{}) : go(nsc, mc, std::false_type{});
+        };
+        auto by_mode = [&](auto nsc) {
+            return mode == MODE_CHECK ? by_nt(nsc, std::integral_constant<int, MODE_CHECK>{})
+                                      : by_nt(nsc, std::integral_constant<int, MODE_PLAIN>{});
+        };
+        return ns == 4 ? by_mode(std::integral_constant<int, 4>{}) : by_mode(std::integral_constant<int, 3>{});
+    }
 }
 
 hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStream_t st)
 {
     if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
+    const dim3 grid(pair_tiles(a.g, WIDE_TY));
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
-            const dim3 grid(pair_tiles(a.g, WIDE_TY));
-            auto go = [&](auto nsc) {
-                constexpr int NS = decltype(nsc)::value;
-                if (a.streaming_stores) {
-                    if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, true, WIDE_TY, WIDE_NTH, NS>), grid,
-                                           dim3(WIDE_NTH), 0, st, a);
-                    else
-                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, true, WIDE_TY, WIDE_NTH, NS>), grid,
-                                           dim3(WIDE_NTH), 0, st, a);
-                } else {
-                    if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_CHECK, false, WIDE_TY, WIDE_NTH, NS>), grid,
-                                           dim3(WIDE_NTH), 0, st, a);
-                    else
-                        hipLaunchKernelGGL((k_fluid_stepN<S, MODE_PLAIN, false, WIDE_TY, WIDE_NTH, NS>), grid,
-                                           dim3(WIDE_NTH), 0, st, a);
-                }
-            };
-            if (ns == 4)
-                go(std::integral_constant<int, 4>{});
-            else
-                go(std::integral_constant<int, 3>{});
-            return hipGetLastError();
-        } else {
-            return hipErrorInvalidValue;
-        }
+        return launch_multi<S>(mode, ns, a.streaming_stores, a.ref_src, a.ref_dst, [&](auto nsc, auto mc, auto ntc) {
+            constexpr int NS = decltype(nsc)::value, M = decltype(mc)::value;
+            constexpr bool NT = decltype(ntc)::value;
+            hipLaunchKernelGGL((k_fluid_stepN<S, M, NT, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0, st, a);
+        });
     });
 }
 
@@ -2329,43 +2419,19 @@ hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hip
 {
     if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
+    const dim3 grid(pair_tiles(a.g, WIDE_TY));
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
-        if constexpr (sizeof(typename S::C) == 4 && !S::tile_mean && !S::colref) {
-            const dim3 grid(pair_tiles(a.g, WIDE_TY));
-            auto go = [&](auto la, auto qf, auto nsc) {
-                typedef decltype(la) L;
-                constexpr int QF = decltype(qf)::value, NS = decltype(nsc)::value;
-                if (a.streaming_stores) {
-                    if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, true, L, QF, WIDE_TY, WIDE_NTH, NS>),
-                                           grid, dim3(WIDE_NTH), 0, st, a);
-                    else
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, true, L, QF, WIDE_TY, WIDE_NTH, NS>),
-                                           grid, dim3(WIDE_NTH), 0, st, a);
-                } else {
-                    if (mode == MODE_CHECK)
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_CHECK, false, L, QF, WIDE_TY, WIDE_NTH, NS>),
-                                           grid, dim3(WIDE_NTH), 0, st, a);
-                    else
-                        hipLaunchKernelGGL((k_ad_stepN<S, MODE_PLAIN, false, L, QF, WIDE_TY, WIDE_NTH, NS>),
-                                           grid, dim3(WIDE_NTH), 0, st, a);
-                }
-            };
-            auto lat = [&](auto nsc) {
-                if (lay == LAY_2D_AD9)
-                    go(D2Q9{}, std::integral_constant<int, 1>{}, nsc);
-                else
-                    go(D2Q5{}, std::integral_constant<int, 9>{}, nsc);
-            };
-            if (ns == 4)
-                lat(std::integral_constant<int, 4>{});
+        return launch_multi<S>(mode, ns, a.streaming_stores, a.ref_src, a.ref_dst, [&](auto nsc, auto mc, auto ntc) {
+            constexpr int NS = decltype(nsc)::value, M = decltype(mc)::value;
+            constexpr bool NT = decltype(ntc)::value;
+            if (lay == LAY_2D_AD9)
+                hipLaunchKernelGGL((k_ad_stepN<S, M, NT, D2Q9, 1, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0,
+                                   st, a);
             else
-                lat(std::integral_constant<int, 3>{});
-            return hipGetLastError();
-        } else {
-            return hipErrorInvalidValue;
-        }
+                hipLaunchKernelGGL((k_ad_stepN<S, M, NT, D2Q5, 9, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0,
+                                   st, a);
+        });
     });
 }
 

@@ -216,10 +216,27 @@ inline int next_launch(int spl, int64_t rem)
             return k;
     return 1;
 }
-inline int64_t chunk_launches(int spl, int64_t n)
+// Steps of the next launch of a solver with `rem` steps left in the chunk;
+// first: the chunk's first launch.  Storage that rounds on store (FP16)
+// follows the paired launches (next_launch with two) and fuses two of them
+// into one four-step launch wherever neither is the chunk's first (which
+// moves the column references) and neither ends the chunk (the check, whose
+// tile means the paired kernel takes): the stored states stay those of the
+// paired launches bit for bit.  K = 100: 2, 24 x 4, 2.
+inline int plan_next(const lbm_solver *s, int which, int64_t rem, bool first)
+{
+    const int spl = launch_steps(s, which);
+    if (spl < 4 || !lbmk::storage_moving_ref(s->p.storage))
+        return next_launch(spl, rem);
+    const int k = next_launch(2, rem);
+    if (first || k != 2 || rem < 6 || next_launch(2, rem - 2) != 2)
+        return k;
+    return 4;
+}
+inline int64_t chunk_launches(const lbm_solver *s, int which, int64_t n)
 {
     int64_t c = 0;
-    for (int64_t j = 0; j < n; j += next_launch(spl, n - j))
+    for (int64_t j = 0; j < n; j += plan_next(s, which, n - j, j == 0))
         ++c;
     return c;
 }
@@ -227,9 +244,8 @@ inline int64_t chunk_launches(int spl, int64_t n)
 // chunks of check_every steps
 inline int64_t launches_for(const lbm_solver *s, int which, int64_t steps)
 {
-    const int spl = launch_steps(s, which);
     const int64_t K = s->p.check_every;
-    return (steps / K) * chunk_launches(spl, K) + chunk_launches(spl, steps % K);
+    return (steps / K) * chunk_launches(s, which, K) + chunk_launches(s, which, steps % K);
 }
 // blocks of the check-step launches (the per-block maxima the decide reads)
 inline int check_blocks(const lbm_solver *s, int which)
@@ -366,7 +382,6 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
             return stt;
     hipStream_t stream = s->ctx->stream;
     const int K = s->p.check_every;
-    const int spl = launch_steps(s, which);
     // default stall window: slow physical transients (a long porous medium
     // filling up behind a fixed inflow) can hold the residual level for
     // >10^4 steps, so it is long -- except with FP16 storage, whose
@@ -404,7 +419,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         const int64_t rem = max_iter - launched;
         const int64_t n = rem >= K ? K : rem;
         for (int64_t j = 1; j <= n;) {
-            const int k = next_launch(spl, n - j + 1);
+            const int k = plan_next(s, which, n - j + 1, j == 1);
             const int mode = (n == K && j + k - 1 == K) ? lbmk::MODE_CHECK : lbmk::MODE_PLAIN;
             HIPCHK(launch_step(s, which, mode, (int)((cur0 + nlaunch) & 1), j == 1, k), "step launch");
             if (j == 1 && roll)
@@ -772,9 +787,8 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
            "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
-    const int spl = launch_steps(s, which);
     for (int64_t t = 0; t < nsteps;) {
-        const int k = next_launch(spl, nsteps - t);
+        const int k = plan_next(s, which, nsteps - t, false);
         HIPCHK(launch_step(s, which, lbmk::MODE_PLAIN, cur, false, k), "step launch");
         cur ^= 1;
         t += k;

@@ -126,6 +126,39 @@ def test_c2_three_step_planning_fixed_steps(gpu_lib, steps):
     _check(FP32S, cls, U, C, Uo, Co)
 
 
+def _paired_plan(n):
+    """Launch sizes of the paired form for n steps: twos, a one only where
+    two would leave a single step behind."""
+    out = []
+    while n:
+        k = 2 if n >= 2 and n - 2 != 1 else 1
+        out.append(k)
+        n -= k
+    return out
+
+
+@pytest.mark.parametrize("steps", [8, 41])
+def test_c2_fp16_fused_launches_equal_paired(gpu_lib, steps):
+    """FP16 storage on the wide grid fuses paired launches into four-step
+    ones, rounding in LDS as the paired store would.  Taking the same steps
+    one paired launch per call (each call of one or two steps is a single
+    launch) must give the same stored state bit for bit, for both solvers."""
+    lbm = gpu_lib
+    cls = masks(C2, lbm)
+    states = []
+    for split in (False, True):
+        print("fp16 fused vs paired, %d steps, split %s" % (steps, split), flush=True)
+        with _solver(lbm, cls, C2, FP16S) as s:
+            for which in (0, 1):
+                if which == 1:
+                    assert lbm.lbm_solver_export_u(s.h) == 0
+                plan = _paired_plan(steps) if split else [steps]
+                for i, k in enumerate(plan):
+                    assert s.steps(which, k, 1 if i == 0 else 0)[0] == 0, s.error()
+            states.append(lbm.lbm_solver_get_state(s.h))
+    assert np.array_equal(states[0], states[1])
+
+
 # Wide grids whose sides are no multiples of the 64 x 16 tile (1000 = 15 *
 # 64 + 40, 530 = 33 * 16 + 2; 1090 = 17 * 64 + 2, 483 = 30 * 16 + 3), with
 # over 512 tiles, so the FP32 forms take the multi-step kernels: partial

@@ -255,20 +255,25 @@ def test_server_max_iter_and_rejections(srv_env):
     assert not np.any(r["c"]) and r["flux"][0] == s["fi"]["flux_in"]
 
 
+@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=["fp32s", "fp16s"])
 @pytest.mark.parametrize("spec", [(1024, 512, 0.3, 0.8, 0.01, 21), (512, 256, 0.3, 0.8, 0.01, 22)],
                          ids=["1024x512-wide", "512x256-middle"])
-def test_server_matches_wide_single_solve(srv_env, spec):
-    """Large requests: the server steps them with 64 x 4 tiles, the single
-    solve with the wide (64 x 16 tiles, 1024-thread blocks) or middle (64 x
-    8, 512 threads) multi-step kernels.  All make the same multiply-add
-    choices (fused per source expression), so the states stay equal bit
-    for bit: 400 steps of each solver, then statuses, counts and the FP64
-    fluxes of the final states."""
+def test_server_matches_wide_single_solve(srv_env, spec, storage):
+    """Large requests, whose single solves take other launch forms than the
+    server.  Shifted FP32: served four steps per launch over 64 x 16 tiles;
+    the single solve takes the same on 1024 x 512 and paired launches over
+    64 x 8 tiles on 512 x 256.  FP16: served by paired launches over 64 x 4
+    tiles; the single solve on 1024 x 512 fuses pairs of them into
+    four-step launches over 64 x 16 tiles, rounding in LDS as the paired
+    store would.  All make the same multiply-add choices (fused per source
+    expression), so the states stay equal bit for bit: 400 steps of each
+    solver (checks, and FP16's reference moves, every 100), then statuses,
+    counts and the FP64 fluxes of the final states."""
     lbm, ctx = srv_env
-    need = lbm.lbm_server_footprint(spec[0], spec[1], FP32S)
-    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=FP32S)
+    need = lbm.lbm_server_footprint(spec[0], spec[1], storage)
+    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=storage)
     srv = lbm.lbm_server_create(ctx, cfg)
-    print("server vs single solve %dx%d" % spec[:2], flush=True)
+    print("server vs single solve %dx%d storage %d" % (spec[0], spec[1], storage), flush=True)
     try:
         st, t = lbm.lbm_server_submit(srv, _request(lbm, spec, max_iter=400))
         assert st == 0, lbm.lbm_server_error(srv)
@@ -276,7 +281,7 @@ def test_server_matches_wide_single_solve(srv_env, spec):
         r = lbm.lbm_server_poll(srv, 1, 1.0)[0]
     finally:
         lbm.lbm_server_destroy(srv)
-    s = _single(lbm, ctx, spec, FP32S, max_iter=400)
+    s = _single(lbm, ctx, spec, storage, max_iter=400)
     assert r["status_fluid"] == s["sf"] == lbm.LBM_NOT_CONVERGED
     assert r["iters_fluid"] == s["fi"]["iters"] == 400 and r["iters_ad"] == s["ai"]["iters"] == 400
     assert r["flux"][0] == s["fi"]["flux_in"] and r["flux"][1] == s["fi"]["flux_out"]
