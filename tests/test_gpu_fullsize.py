@@ -5,7 +5,8 @@ The 1024 x 512 electrode (the single-solve benchmark) and the 256 x 128 x
 fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
 (the residual checks, the stop decision and the iteration count).  On the
 2-D grid FP32 storage runs the wide four-step kernels and FP64 the wide
-two-step ones (64 x 16 tiles, 1024-thread blocks), FP16 the 64 x 4 ones -- the forms the
+two-step ones (64 x 16 tiles, 1024-thread blocks), FP16 four-step launches fused from
+paired ones with its checks over 64 x 4 tiles -- the forms the
 benchmark times; the 512 x 256 coupled-loop grid runs the middle form
 (64 x 8 tiles, 512-thread blocks).
 Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
