@@ -2361,11 +2361,22 @@ hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st
     });
 }
 
+// Tile height of the multi-step launches on grid g: 16 (1024-thread
+// blocks) or 8 (512), as the FP32 forms' paired launches take; 0 where the
+// grid is too small for them.  Storage with tile means runs its checks as
+// 64 x 4 paired launches and its plain launches at this height.
+int multi_ty(const Geo &g)
+{
+    if (pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES)
+        return WIDE_TY;
+    return pair_tiles(g, MID_TY) >= MID_MIN_TILES ? MID_TY : 0;
+}
+
 int fluid_launch_steps(int storage, const Geo &g)
 {
     // FP64 keeps paired launches (its staged values would exceed the
     // register budget of full occupancy)
-    return storage != ST_F64 && pair_tiles(g, WIDE_TY) >= WIDE_MIN_TILES ? MULTI_NS : 2;
+    return storage != ST_F64 && multi_ty(g) ? MULTI_NS : 2;
 }
 
 // Multi-step launch of one solver: FP32 forms take three or four steps,
@@ -2404,13 +2415,17 @@ hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStr
 {
     if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
-    const dim3 grid(pair_tiles(a.g, WIDE_TY));
+    const bool wide = multi_ty(a.g) == WIDE_TY;
+    const dim3 grid(pair_tiles(a.g, wide ? WIDE_TY : MID_TY));
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         return launch_multi<S>(mode, ns, a.streaming_stores, a.ref_src, a.ref_dst, [&](auto nsc, auto mc, auto ntc) {
             constexpr int NS = decltype(nsc)::value, M = decltype(mc)::value;
             constexpr bool NT = decltype(ntc)::value;
-            hipLaunchKernelGGL((k_fluid_stepN<S, M, NT, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0, st, a);
+            if (wide)
+                hipLaunchKernelGGL((k_fluid_stepN<S, M, NT, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_fluid_stepN<S, M, NT, MID_TY, MID_NTH, NS>), grid, dim3(MID_NTH), 0, st, a);
         });
     });
 }
@@ -2419,18 +2434,27 @@ hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hip
 {
     if (fluid_launch_steps(storage, a.g) < 3 || ns < 3 || ns > MULTI_NS)
         return hipErrorInvalidValue;
-    const dim3 grid(pair_tiles(a.g, WIDE_TY));
+    const bool wide = multi_ty(a.g) == WIDE_TY;
+    const dim3 grid(pair_tiles(a.g, wide ? WIDE_TY : MID_TY));
     return by_storage(storage, [&](auto s) -> hipError_t {
         typedef decltype(s) S;
         return launch_multi<S>(mode, ns, a.streaming_stores, a.ref_src, a.ref_dst, [&](auto nsc, auto mc, auto ntc) {
             constexpr int NS = decltype(nsc)::value, M = decltype(mc)::value;
             constexpr bool NT = decltype(ntc)::value;
+            auto go = [&](auto la, auto qf) {
+                typedef decltype(la) L;
+                constexpr int QF = decltype(qf)::value;
+                if (wide)
+                    hipLaunchKernelGGL((k_ad_stepN<S, M, NT, L, QF, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0,
+                                       st, a);
+                else
+                    hipLaunchKernelGGL((k_ad_stepN<S, M, NT, L, QF, MID_TY, MID_NTH, NS>), grid, dim3(MID_NTH), 0,
+                                       st, a);
+            };
             if (lay == LAY_2D_AD9)
-                hipLaunchKernelGGL((k_ad_stepN<S, M, NT, D2Q9, 1, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0,
-                                   st, a);
+                go(D2Q9{}, std::integral_constant<int, 1>{});
             else
-                hipLaunchKernelGGL((k_ad_stepN<S, M, NT, D2Q5, 9, WIDE_TY, WIDE_NTH, NS>), grid, dim3(WIDE_NTH), 0,
-                                   st, a);
+                go(D2Q5{}, std::integral_constant<int, 9>{});
         });
     });
 }

@@ -148,14 +148,20 @@ hipError_t ad_step2(int lay, int storage, int mode, const AdArgs &a, hipStream_t
 int pair_tiles(const Geo &g);
 int pair_tiles(const Geo &g, int ty);
 // Tile height fluid_step2 and ad_step2 use for this storage and grid: 16
-// (1024-thread blocks) on grids with at least 512 such tiles and no FP16
-// tile means, else 4 (256-thread blocks).
+// (1024-thread blocks) on grids with at least 512 such tiles, 8 (512
+// threads) on grids with at least 256 such tiles, else 4 (256 threads);
+// always 4 with FP16 storage (tile means).
 int pair_ty(int storage, const Geo &g);
+// Tile height of the multi-step launches: 16 or 8 by the same tile counts,
+// 0 on smaller grids.
+int multi_ty(const Geo &g);
 // Most steps per launch of either solver in 2-D: 4 (fluid_stepN / ad_stepN)
-// for FP32 and FP32 shifted storage on the wide tiles, else 2.
+// on grids that take the wide or middle tiles, except FP64; else 2.
 int fluid_launch_steps(int storage, const Geo &g);
-// ns = 3 or 4 fluid steps per launch (2-D; the wide tiles and an in-place
-// LDS region, as fluid_launch_steps allows); the check, if any, on the last.
+// ns = 3 or 4 fluid steps per launch (2-D; 64 x multi_ty tiles and an
+// in-place LDS region, as fluid_launch_steps allows); the check, if any, on
+// the last.  FP16 storage: ns = 4, plain, equal source and destination
+// references only (two paired launches fused; see kernels.hip).
 hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStream_t st);
 // ns = 3 or 4 substrate steps per launch, under the same conditions (lay as
 // ad_step2).

@@ -7,8 +7,8 @@ fixed steps, and the 1024 x 512 FP64 steady solve with a loose tolerance
 2-D grid FP32 storage runs the wide four-step kernels and FP64 the wide
 two-step ones (64 x 16 tiles, 1024-thread blocks), FP16 four-step launches fused from
 paired ones with its checks over 64 x 4 tiles -- the forms the
-benchmark times; the 512 x 256 coupled-loop grid runs the middle form
-(64 x 8 tiles, 512-thread blocks).
+benchmark times; the 512 x 256 coupled-loop grid runs the same forms over
+middle tiles (64 x 8, 512-thread blocks).
 Tolerances as in the smaller parity tests: FP64 1e-12 absolute; FP32 1e-4
 and FP16 5e-3 relative L2 on the fields.
 """
@@ -139,17 +139,19 @@ def _paired_plan(n):
 
 
 @pytest.mark.parametrize("steps", [8, 41])
-def test_c2_fp16_fused_launches_equal_paired(gpu_lib, steps):
+@pytest.mark.parametrize("w", ["c2", "c5"], ids=["1024x512-wide", "512x256-middle"])
+def test_fp16_fused_launches_equal_paired(gpu_lib, w, steps):
     """FP16 storage on the wide grid fuses paired launches into four-step
     ones, rounding in LDS as the paired store would.  Taking the same steps
     one paired launch per call (each call of one or two steps is a single
     launch) must give the same stored state bit for bit, for both solvers."""
     lbm = gpu_lib
-    cls = masks(C2, lbm)
+    w = inputs.WORKLOADS[w]
+    cls = masks(w, lbm)
     states = []
     for split in (False, True):
-        print("fp16 fused vs paired, %d steps, split %s" % (steps, split), flush=True)
-        with _solver(lbm, cls, C2, FP16S) as s:
+        print("fp16 fused vs paired, %s, %d steps, split %s" % (w["name"], steps, split), flush=True)
+        with _solver(lbm, cls, w, FP16S) as s:
             for which in (0, 1):
                 if which == 1:
                     assert lbm.lbm_solver_export_u(s.h) == 0
@@ -160,17 +162,19 @@ def test_c2_fp16_fused_launches_equal_paired(gpu_lib, steps):
     assert np.array_equal(states[0], states[1])
 
 
-# Wide grids whose sides are no multiples of the 64 x 16 tile (1000 = 15 *
-# 64 + 40, 530 = 33 * 16 + 2; 1090 = 17 * 64 + 2, 483 = 30 * 16 + 3), with
-# over 512 tiles, so the FP32 forms take the multi-step kernels: partial
+# Grids whose sides are no multiples of the tile (1000 = 15 * 64 + 40, 530
+# = 33 * 16 + 2; 1090 = 17 * 64 + 2, 483 = 30 * 16 + 3: over 512 tiles of
+# 64 x 16; 530 x 250, 250 = 31 * 8 + 2: 288 tiles of 64 x 8), so the FP32
+# forms take the multi-step kernels over wide or middle tiles: partial
 # tiles whose halos leave the grid on the right and top edges.
-RAGGED = [inputs.scaled(C2, 1000, 530, seed=23), inputs.scaled(C2, 1090, 483, seed=25)]
+RAGGED = [inputs.scaled(C2, 1000, 530, seed=23), inputs.scaled(C2, 1090, 483, seed=25),
+          inputs.scaled(C2, 530, 250, seed=27)]
 
 
 @pytest.mark.parametrize("steps", [4, 41])
 @pytest.mark.parametrize("storage,ad9", [(FP32, False), (FP32S, False), (FP32S, True)],
                          ids=["fp32", "fp32s", "fp32s-d2q9"])
-@pytest.mark.parametrize("w", RAGGED, ids=["1000x530", "1090x483"])
+@pytest.mark.parametrize("w", RAGGED, ids=["1000x530", "1090x483", "530x250-middle"])
 def test_ragged_wide_grid_multi_step(gpu_lib, w, storage, ad9, steps):
     """One four-step launch, and 41 steps (nine four-step launches, a three
     and a two), on each solver."""
@@ -209,8 +213,8 @@ def test_ragged_wide_grid_fp32s_steady(gpu_lib):
 
 @pytest.mark.parametrize("storage", [FP64, FP32S], ids=["fp64", "fp32s"])
 def test_c5_full_size_fixed_steps(gpu_lib, storage):
-    """512 x 256, the coupled loop's grid: the middle two-step form (64 x 8
-    tiles, 512-thread blocks)."""
+    """512 x 256, the coupled loop's grid: middle tiles (64 x 8, 512-thread
+    blocks), four steps per launch in FP32, two in FP64."""
     cls, U, C, Uo, Co = _fixed(gpu_lib, inputs.WORKLOADS["c5"], storage, 60, 60)
     _check(storage, cls, U, C, Uo, Co)
 

@@ -261,11 +261,11 @@ def test_server_max_iter_and_rejections(srv_env):
 def test_server_matches_wide_single_solve(srv_env, spec, storage):
     """Large requests, whose single solves take other launch forms than the
     server.  Shifted FP32: served four steps per launch over 64 x 16 tiles;
-    the single solve takes the same on 1024 x 512 and paired launches over
-    64 x 8 tiles on 512 x 256.  FP16: served by paired launches over 64 x 4
-    tiles; the single solve on 1024 x 512 fuses pairs of them into
-    four-step launches over 64 x 16 tiles, rounding in LDS as the paired
-    store would.  All make the same multiply-add choices (fused per source
+    the single solve takes four-step launches over 64 x 16 tiles on 1024 x
+    512 and over 64 x 8 tiles on 512 x 256.  FP16: served by paired
+    launches over 64 x 4 tiles; the single solve fuses pairs of them into
+    four-step launches over 64 x 16 or 64 x 8 tiles, rounding in LDS as the
+    paired store would.  All make the same multiply-add choices (fused per source
     expression), so the states stay equal bit for bit: 400 steps of each
     solver (checks, and FP16's reference moves, every 100), then statuses,
     counts and the FP64 fluxes of the final states."""
