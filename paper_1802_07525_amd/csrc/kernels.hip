@@ -2773,9 +2773,13 @@ hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable 
     }
 }
 
+// The 64 x 16 served form (srv_stepN) is switched off: served FP32 requests
+// stalled twice in tests with it (requests never finishing) and no cause
+// has been shown.  Every storage is served by paired 64 x 4 launches.
 int srv_tile_ty(int storage)
 {
-    return storage == ST_F32 || storage == ST_F32S ? WIDE_TY : PAIR_TY;
+    (void)storage;
+    return PAIR_TY;
 }
 
 hipError_t srv_stepN(int storage, int mode, int ns, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
