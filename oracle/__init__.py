@@ -57,6 +57,7 @@ def lib():
             "orc_ad_run": (I, [I, I, I, I, P, D, D, D, D, I, D, P, P, I64, P, P]),
             "orc_coupled_run": (I, [I, I, I, P, D, D, D, D, D, D, I, D, I64, I, I, I, P,
                                     P, P, P, P, P, P, P]),
+            "orc_stall_rule": (I, [P, P, I, D, I, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -192,6 +193,18 @@ def fluid_fluxes(cls, f, u_in, lat=None):
 
 
 STALL_CHECKS = 1000
+
+
+def stall_rule(r, tol, window, umax=None):
+    """The solves' stop rule applied to a sequence of check residuals r (and
+    the largest |u| at each check): (status, index of the deciding check),
+    or ("NOT_CONVERGED", len(r)) when no check stops it."""
+    r = _f64(r)
+    um = None if umax is None else _f64(umax)
+    at = ct.c_int()
+    st = lib().orc_stall_rule(_p(r), None if um is None else _p(um), len(r), float(tol),
+                              int(window), ct.byref(at))
+    return STATUS.get(st, st), at.value
 
 
 def fluid_solve(cls, tau, u_in, tol, max_iter, check_every=100, f=None, lat=None,

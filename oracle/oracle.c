@@ -606,6 +606,26 @@ static int residual_decide(double r, double umax, double tol, orc_stall *st)
     return -100; /* keep going */
 }
 
+/* The stop rule applied to a given sequence of check residuals r[0..n-1]
+ * (and the largest |u| at each check, or NULL for none), as a solve applies
+ * it check by check: returns the status of the check at which it stops and
+ * its index in *stop_at, or NOT_CONVERGED with *stop_at = n when no check
+ * stops it.  Exposed so that the rule can be checked on its own. */
+int orc_stall_rule(const double *r, const double *umax, int n, double tol, int window,
+                   int *stop_at)
+{
+    orc_stall st = {INFINITY, 0, window, -INFINITY};
+    for (int k = 0; k < n; k++) {
+        int dec = residual_decide(r[k], umax ? umax[k] : 0.0, tol, &st);
+        if (dec != -100) {
+            *stop_at = k;
+            return dec;
+        }
+    }
+    *stop_at = n;
+    return ORC_NOT_CONVERGED;
+}
+
 /* Fluid steady solve from the state in f (cold or warm), in place.
  * On return f holds f*(t) at the stop, U the moments of that state. */
 int orc_fluid_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
