@@ -67,41 +67,66 @@ def traffic_for(kernel, workload, storage):
     return rec.get("hbm_bytes_per_launch") / rec.get("steps_per_launch", 1)
 
 
-def cpu_baseline(cls, w, min_seconds=10.0, max_seconds=30.0):
-    """FP64 oracle on a bounded sample of the same workload: repeated
-    100-step fluid and substrate segments until ~10 s of CPU time."""
+def _omp():
+    """OpenMP runtime the oracle library runs on (same process)."""
+    import ctypes
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def _oracle_rate(cls, w, seconds):
+    """FP64 oracle MLUPS on the mask: fluid segments from rest, then
+    substrate segments from equilibrium in the last velocity, each for about
+    seconds / 2.  Segments are 100 steps (2-D) or 10 (3-D)."""
     import numpy as np
     import oracle as O
+    seg = 10 if w["nz"] > 1 else 100
     f = O.fluid_init(cls)
-    nz = w["nz"]
     n_f = int(O.flow_domain(cls).sum())
     n_a = int(np.isin(cls, [O.FLUID, O.BIOFILM]).sum())
     t0 = time.perf_counter()
     steps = 0
     U = None
     while True:
-        f, U, _ = O.fluid_run(cls, f, w["tau"], w["u_in"], 100)
-        steps += 100
-        el = time.perf_counter() - t0
-        if el >= min_seconds / 2 or el >= max_seconds / 2:
+        f, U, _ = O.fluid_run(cls, f, w["tau"], w["u_in"], seg)
+        steps += seg
+        if time.perf_counter() - t0 >= seconds / 2:
             break
     tf = time.perf_counter() - t0
     g = O.ad_init(cls, U, w["c_in"])
     t1 = time.perf_counter()
     asteps = 0
     while True:
-        g, _ = O.ad_run(cls, g, U, w["D"], w["c_in"], w["k"], 100)
-        asteps += 100
-        el = time.perf_counter() - t1
-        if el >= min_seconds / 2 or el >= max_seconds / 2:
+        g, _ = O.ad_run(cls, g, U, w["D"], w["c_in"], w["k"], seg)
+        asteps += seg
+        if time.perf_counter() - t1 >= seconds / 2:
             break
     ta = time.perf_counter() - t1
-    upd = steps * n_f + asteps * n_a
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": upd / (tf + ta) / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%d fluid + %d substrate FP64 steps from rest on the same %s mask "
-                      "(%.1f s)" % (steps, asteps, w["name"], tf + ta),
-            "cpu_model": cpu_model()}
+    return (steps * n_f + asteps * n_a) / (tf + ta) / 1e6, steps, asteps, tf + ta
+
+
+def cpu_baseline(cls, w, seconds=10.0):
+    """FP64 oracle on a bounded sample of the same workload, with all the
+    host's OpenMP threads and with one: fluid segments from rest, then
+    substrate segments, about `seconds` per thread count."""
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else os.cpu_count()
+    rate, fs, as_, el = _oracle_rate(cls, w, seconds)
+    out = {"value": rate, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": "%d fluid + %d substrate FP64 steps from rest on the same %s mask "
+                     "(%.1f s, %d threads)" % (fs, as_, w["name"], el, cores),
+           "cpu_model": cpu_model()}
+    if omp:
+        omp.omp_set_num_threads(1)
+        try:
+            r1, fs1, as1, el1 = _oracle_rate(cls, w, seconds)
+        finally:
+            omp.omp_set_num_threads(cores)
+        out["one_thread"] = {"value": r1, "unit": "MLUPS", "cores": 1,
+                             "sample": "%d fluid + %d substrate FP64 steps (%.1f s)" % (fs1, as1, el1)}
+    return out
 
 
 def cpu_model():
@@ -438,7 +463,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--storage", default="fp32s", choices=sorted(STORAGES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=0)
@@ -535,43 +560,56 @@ def main():
     qf, qa = (19, 7) if dim == 3 else (9, 9 if ad9 else 5)
     sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
     cb = 8 if storage == 3 else 4
-    # dominant kernel: the fluid step; HIP-event time over its launches in the
-    # timed region.  In 2-D a launch advances several steps -- two, or four
-    # with the multi-step form (a 100-step chunk is 25 four-step launches) --
-    # so the algorithmic bytes of
+    # Per solver: HIP-event time over its launches in the timed region (on
+    # the library's stream).  A launch advances several steps -- two in 3-D
+    # (z-marching blocks), two or four in 2-D -- so the algorithmic bytes of
     # a launch are the per-step figure times the solve's steps per launch.
-    f_ms = sum(r[1]["kernel_ms"] for r in recs)
-    f_launch = sum(r[1]["launches"] for r in recs)
-    a_ms = sum(r[3]["kernel_ms"] for r in recs)
-    a_launch = sum(r[3]["launches"] for r in recs)
-    spl_f = sum(r[1]["iters"] for r in recs) / max(f_launch, 1)
-    spl_a = sum(r[3]["iters"] for r in recs) / max(a_launch, 1)
-    avg_f = f_ms / max(f_launch, 1)
-    bytes_f = spl_f * algo_bytes(qf, sb) * fi["active_nodes"]
-    achieved = bytes_f / (avg_f * 1e-3) / 1e9
-    # isolated per-launch HIP-event timing of the dominant kernel on the same state
-    _, iso_ms = lbm.lbm_solver_time_steps(s, 0, 300)
-    bytes_a = spl_a * algo_bytes(qa, sb, dim * cb) * ai["active_nodes"]
-    if dim == 3:
-        kernel_name = "k_fluid_step<D3Q19,%s>" % args.storage
-    elif spl_f > 2.5:
-        kernel_name = "k_fluid_stepN<%s>" % args.storage
-    else:
-        kernel_name = "k_fluid_step2<%s>" % args.storage
-    per_step = traffic_for(kernel_name, args.workload, args.storage)
-    traffic = None if per_step is None else per_step * spl_f
-    # achievable streaming rate on this GPU: a 1 GiB device copy (outside the
-    # timed region), to read the kernel's rate against besides the datasheet
     copy_gbs, _ = lbm.lbm_copy_bandwidth(ctx, 1 << 30, 10)
+
+    def kernel_figures(which, q, extra, idx, name):
+        ms = sum(r[idx]["kernel_ms"] for r in recs)
+        nl = sum(r[idx]["launches"] for r in recs)
+        spl = sum(r[idx]["iters"] for r in recs) / max(nl, 1)
+        avg = ms / max(nl, 1)
+        nodes = recs[-1][idx]["active_nodes"]
+        algo = spl * algo_bytes(q, sb, extra) * nodes
+        gbs = algo / (avg * 1e-3) / 1e9
+        # isolated per-launch HIP-event timing on the same state
+        _, iso = lbm.lbm_solver_time_steps(s, which, 300)
+        per_step = traffic_for(name, args.workload, args.storage)
+        traffic = None if per_step is None else per_step * spl
+        rec = {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+               "algo_bytes_per_launch": algo, "steps_per_launch": spl, "avg_launch_ms": avg,
+               "avg_launch_ms_isolated": iso, "launches": nl, "kernel_ms_total": ms,
+               "copy_gbs": copy_gbs, "frac_of_copy": gbs / copy_gbs,
+               # HBM bytes actually moved (counters) over the same launch time
+               "hbm_gbs": None if traffic is None else traffic / (avg * 1e-3) / 1e9}
+        rec["hbm_frac"] = None if traffic is None else rec["hbm_gbs"] / HBM_PEAK_GBS
+        return rec
+
+    form = lambda spl: ("3d2" if spl > 1.5 else "") if dim == 3 else ("N" if spl > 2.5 else "2")
+    nl_f = sum(r[1]["launches"] for r in recs)
+    nl_a = sum(r[3]["launches"] for r in recs)
+    spl_f = sum(r[1]["iters"] for r in recs) / max(nl_f, 1)
+    spl_a = sum(r[3]["iters"] for r in recs) / max(nl_a, 1)
+    lat_f = "D3Q19" if dim == 3 else "D2Q9"
+    lat_a = "D3Q7" if dim == 3 else ("D2Q9" if ad9 else "D2Q5")
+    fl = kernel_figures(0, qf, 0, 1, "k_fluid_step%s<%s,%s>" % (form(spl_f), lat_f, args.storage))
+    ad = kernel_figures(1, qa, dim * cb, 3, "k_ad_step%s<%s,%s>" % (form(spl_a), lat_a, args.storage))
+    # the roofline object is the kernel with the larger share of GPU time
+    dom, other = (fl, ad) if fl["kernel_ms_total"] >= ad["kernel_ms_total"] else (ad, fl)
     n_all = w["nx"] * w["ny"] * w["nz"]
     upd_all = sum((fi_["iters"] + ai_["iters"]) * n_all for _, fi_, _, ai_ in recs)
+    layer = w.get("layer", True)
     out = {
         "metric": METRIC, "value": value, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.storage], "data": "synthetic",
         "config": {"workload": w["name"], "grid": [w["nx"], w["ny"], w["nz"]],
                    "storage": args.storage, "tau": w["tau"], "u_in": w["u_in"], "D": w["D"],
-                   "k_sink": w["k"], "k_half": args.k_half,
+                   "biofilm_layer": layer, "k_sink": w["k"] if layer else None,
+                   "k_half": args.k_half if layer else None,
                    "substrate_lattice": "d3q7" if dim == 3 else args.ad_lattice,
                    "tol": w["tol"], "seed": w["seed"],
                    "fluid_status": lbm.status_name(sf), "fluid_iters": fi["iters"],
@@ -579,14 +617,8 @@ def main():
                    "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"],
                    "fluid_seconds": fi["seconds"], "ad_seconds": ai["seconds"],
                    "mlups_all_nodes": upd_all / el / 1e6},
-        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algo_bytes_per_launch": bytes_f,
-                     "steps_per_launch": spl_f, "avg_launch_ms": avg_f,
-                     "avg_launch_ms_isolated": iso_ms,
-                     "ad_kernel_gbs": bytes_a / (a_ms / max(a_launch, 1) * 1e-3) / 1e9,
-                     "ad_avg_launch_ms": a_ms / max(a_launch, 1),
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "roofline": dom,
+        "roofline_other": other,
     }
     lbm.lbm_solver_destroy(s)
     lbm.lbm_ctx_destroy(ctx)

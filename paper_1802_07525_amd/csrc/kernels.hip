@@ -30,6 +30,7 @@
 #include "lbm_kernels.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 #include <type_traits>
 
@@ -1584,6 +1585,596 @@ __global__ void __launch_bounds__(NTH) k_ad_stepN(AdArgs a)
                                               part + gridDim.x + blockIdx.x, smem);
 }
 
+// -------------------------------------------- two steps per launch (3-D)
+// A block owns a 32 x TY column of the grid and marches along z over
+// a segment of planes [z0, z1).  At plane k it takes the first step on the
+// column and a one-node halo in x and y (34 x (TY + 2) nodes, from global
+// memory), then the second step on plane k - 1 from those results.  A
+// population of the first step moves by c_z to the plane where the second
+// step pulls it, so the block keeps three groups of directions in LDS with
+// as many planes as each needs: c_z = -1 (pulled by plane k - 1 at once:
+// one plane), c_z = 0 (pulled one plane later: two) and c_z = +1 (two
+// planes later: three).  A column thread's own values -- every direction,
+// for bounce-back and the outlet's u* -- stay in its registers until the
+// next plane.  Each segment repeats the first step on the planes z0 - 1 and
+// z1 of its neighbours.  The populations cross global memory once per two
+// steps; the intermediate state stays in the compute type, so FP32 results
+// equal two single steps up to rounding order and FP16 storage skips one
+// rounding.  Step counters: a.step and a.step + 1; a check (MODE_CHECK,
+// storage without tile means) is taken on the second step.
+// Column shape: 32 x TY nodes (TY = 8 or 16; 32 x TY threads), the region
+// of the first step 34 x (TY + 2)
+constexpr int Z3_TX = 32, Z3_LX = Z3_TX + 2;
+template <int TY>
+struct Z3T {
+    static constexpr int NTH = Z3_TX * TY, LY = TY + 2, R = Z3_LX * LY, HALO = R - Z3_TX * TY;
+    static_assert(HALO <= NTH, "one halo node per thread at most");
+};
+
+// Position of each moving direction within its c_z group, and group sizes
+// (index c_z + 1)
+template <class L>
+struct ZGroupTable {
+    int pos[L::Q];
+    int n[3];
+};
+template <class L>
+constexpr ZGroupTable<L> make_zgroups()
+{
+    ZGroupTable<L> t{};
+    for (int i = 1; i < L::Q; ++i) {
+        const int g = L::cz[i] + 1;
+        t.pos[i] = t.n[g]++;
+    }
+    return t;
+}
+template <class L>
+struct ZG {
+    static constexpr ZGroupTable<L> t = make_zgroups<L>();
+    static constexpr int NM = t.n[0], NZ = t.n[1], NP = t.n[2];
+};
+// LDS bytes: c_z = +1 over three planes, 0 over two, -1 over one
+template <class L, class C, int TY>
+constexpr int z3_lds_bytes()
+{
+    return (3 * ZG<L>::NP + 2 * ZG<L>::NZ + ZG<L>::NM) * Z3T<TY>::R * (int)sizeof(C);
+}
+
+// LDS plane bases of one step-2 plane z: the c_z = +1 group of plane z - 1,
+// the c_z = 0 group of plane z, the c_z = -1 group of plane z + 1, and the
+// c_z = +1 group of plane z (the node's own values of those directions)
+template <class C>
+struct Z3Planes {
+    const C *p, *z, *m, *po;
+};
+
+// Slot of a direction among the values a thread keeps in registers for its
+// own node: the rest direction and the c_z = -1 group, whose LDS plane is
+// overwritten before the second step reads its own values
+template <class L>
+__device__ __forceinline__ constexpr int keep_pos(int i)
+{
+    return i == 0 ? 0 : 1 + ZG<L>::t.pos[i];
+}
+template <class L>
+constexpr int keep_count()
+{
+    return 1 + ZG<L>::NM;
+}
+
+// The second step's source: streamed values from the LDS groups at the
+// region index r of this node; own values from the groups still holding
+// this node's plane, and from registers (kept) for the rest direction and
+// the c_z = -1 group
+template <class L, class C, int TY>
+struct RingSrc {
+    static constexpr int Z3_R = Z3T<TY>::R;
+    const C *kept;
+    Z3Planes<C> pl;
+    int r;
+    __device__ __forceinline__ C own(int i) const
+    {
+        if (i == 0 || L::cz[i] < 0)
+            return kept[keep_pos<L>(i)];
+        const C *base = L::cz[i] > 0 ? pl.po : pl.z;
+        return base[ZG<L>::t.pos[i] * Z3_R + r];
+    }
+    __device__ __forceinline__ C pull(int i, int o, int cx, int cy, int cz, unsigned int m) const
+    {
+        const C *base = cz > 0 ? pl.p : (cz == 0 ? pl.z : pl.m);
+        const C v = base[ZG<L>::t.pos[i] * Z3_R + r - cx - cy * Z3_LX];
+        return m ? own(o) : v;
+    }
+};
+
+// Block layout of a segment: column tile and planes
+struct Z3Block {
+    int x0, y0, z0, z1;
+};
+template <int TY>
+__device__ __forceinline__ Z3Block z3_block(const Geo &g, int zseg, int tile)
+{
+    const int ntx = (g.nx + Z3_TX - 1) / Z3_TX, nty = (g.ny + TY - 1) / TY;
+    const int col = tile % (ntx * nty), seg = tile / (ntx * nty);
+    Z3Block b;
+    b.x0 = (col % ntx) * Z3_TX;
+    b.y0 = (col / ntx) * TY;
+    b.z0 = seg * zseg;
+    b.z1 = min(b.z0 + zseg, g.nz);
+    return b;
+}
+
+// Region coordinates (lx, ly) of this thread's node in pass 0 (the column)
+// or pass 1 (the halo: top row, bottom row, left column, right column)
+template <int TY>
+__device__ __forceinline__ void z3_region(int pass, int t, int &lx, int &ly)
+{
+    constexpr int Z3_LY = Z3T<TY>::LY;
+    if (pass == 0) {
+        lx = 1 + t % Z3_TX;
+        ly = 1 + t / Z3_TX;
+    } else if (t < Z3_LX) {
+        lx = t;
+        ly = 0;
+    } else if (t < 2 * Z3_LX) {
+        lx = t - Z3_LX;
+        ly = Z3_LY - 1;
+    } else if (t < 2 * Z3_LX + TY) {
+        lx = 0;
+        ly = 1 + t - 2 * Z3_LX;
+    } else {
+        lx = Z3_LX - 1;
+        ly = 1 + t - 2 * Z3_LX - TY;
+    }
+}
+
+// Store the first-step values f of the node at region index r of plane k
+// into the LDS groups (the rest direction is never pulled)
+template <class L, class C, int TY>
+__device__ __forceinline__ void z3_put(C *lds, int k, int r, const C f[L::Q])
+{
+    constexpr int NP = ZG<L>::NP, NZ = ZG<L>::NZ, Z3_R = Z3T<TY>::R;
+    C *gp = lds + ((k % 3 + 3) % 3) * NP * Z3_R;
+    C *gz = lds + 3 * NP * Z3_R + (k & 1) * NZ * Z3_R;
+    C *gm = lds + (3 * NP + 2 * NZ) * Z3_R;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        C *base = L::cz[i] > 0 ? gp : (L::cz[i] == 0 ? gz : gm);
+        base[ZG<L>::t.pos[i] * Z3_R + r] = f[i];
+    }
+}
+
+template <class L, class C, int TY>
+__device__ __forceinline__ Z3Planes<C> z3_planes(const C *lds, int z)
+{
+    constexpr int NP = ZG<L>::NP, NZ = ZG<L>::NZ, Z3_R = Z3T<TY>::R;
+    Z3Planes<C> pl;
+    pl.p = lds + (((z - 1) % 3 + 3) % 3) * NP * Z3_R;
+    pl.z = lds + 3 * NP * Z3_R + (z & 1) * NZ * Z3_R;
+    pl.m = lds + (3 * NP + 2 * NZ) * Z3_R;
+    pl.po = lds + (z % 3) * NP * Z3_R;
+    return pl;
+}
+
+// A node's first-step inputs, loaded one plane ahead of their use: the value
+// each direction pulls, its address already selected by the node's reversed
+// links (v[0] = own(0)), the frozen velocity (substrate), and on the outlet
+// column the node's own values the outlet rule reads that no pull supplies
+// (directions in OWN; HASO, else loaded when used).
+template <class L, class C, int NO>
+struct PreVals {
+    C v[L::Q];
+    C o[NO > 0 ? NO : 1];
+    C u[3];
+};
+
+// Directions whose own value an outlet rule reads besides the pulled ones:
+// the fluid's u* reads every own value -- those with c_x = +1 are the
+// reversed pulls of the outlet's c_x = -1 links -- the substrate's
+// zero-gradient copy reads its c_x = -1 ones.
+template <class L>
+constexpr unsigned int fluid_out_own()
+{
+    unsigned int m = 0;
+    for (int i = 1; i < L::Q; ++i)
+        if (L::cx[i] <= 0)
+            m |= 1u << i;
+    return m;
+}
+template <class L>
+constexpr int own_count(unsigned int m)
+{
+    int n = 0;
+    for (int i = 1; i < L::Q; ++i)
+        n += (m >> i) & 1u;
+    return n;
+}
+__device__ __forceinline__ constexpr int own_pos(unsigned int m, int i)
+{
+    return __builtin_popcount(m & ((1u << i) - 1u));
+}
+
+// Source over prefetched values (see PreVals); g: the node's global source
+template <class L, class C, unsigned int OWN, bool HASO, class G>
+struct PreSrc {
+    const C *v, *o;
+    G g;
+    __device__ __forceinline__ C own(int i) const
+    {
+        if (i == 0)
+            return v[0];
+        if ((OWN >> i) & 1u) {
+            if constexpr (HASO)
+                return o[own_pos(OWN, i)];
+            else
+                return g.own(i);
+        }
+        return v[L::op[i]];
+    }
+    __device__ __forceinline__ C pull(int i, int, int, int, int, unsigned int) const { return v[i]; }
+};
+
+// Global source of a first-step node: one load per direction from the
+// address the reversed links select (buffer resource where the array fits
+// 32-bit byte offsets)
+template <class L, class S, bool BUF>
+__device__ __forceinline__ auto z3_src(const void *src, const Geo &g, unsigned int n)
+{
+    typedef typename S::T T;
+    if constexpr (BUF)
+        return BufSrc<S, false>{pop_rsrc(static_cast<const T *>(src), (unsigned int)L::Q, (unsigned int)g.N),
+                                (unsigned int)g.N * (unsigned int)sizeof(T), n * (unsigned int)sizeof(T),
+                                g.nx * (int)sizeof(T), g.nx * g.ny * (int)sizeof(T)};
+    else
+        return GlobalSrc<S>{static_cast<const T *>(src), (unsigned int)g.N, n, g.nx, g.nx * g.ny};
+}
+
+// Issue the loads of a first-step node with reversed links rev
+template <class L, unsigned int OWN, bool HASO, class G, class C, int NO>
+__device__ __forceinline__ void z3_prefetch(const G &g, unsigned int rev, bool xout, PreVals<L, C, NO> &p)
+{
+    p.v[0] = g.own(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i)
+        p.v[i] = g.pull(i, L::op[i], L::cx[i], L::cy[i], L::cz[i], bit_mask(rev, i));
+    if constexpr (HASO) {
+        if (xout) {
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i)
+                if ((OWN >> i) & 1u)
+                    p.o[own_pos(OWN, i)] = g.own(i);
+        }
+    }
+}
+
+// Reversed links of a node (as the collide functions form them): blocked
+// sources, and the links through the inlet and outlet faces
+template <class L>
+__device__ __forceinline__ unsigned int z3_rev(unsigned int blocked, bool xin, bool xout)
+{
+    unsigned int rev = blocked & ((1u << L::Q) - 2u);
+    rev |= xin ? xdirs<L>(1) : 0u;
+    rev |= xout ? xdirs<L>(-1) : 0u;
+    return rev;
+}
+
+// The two step-1 nodes of a thread: its column node (c) and, for threads
+// below Z3_HALO, one halo node (h); their grid positions do not depend on z
+struct Z3Nodes {
+    int xc, yc, xh, yh, rc, rh;
+    bool inc, inh;
+};
+template <int TY>
+__device__ __forceinline__ Z3Nodes z3_nodes(const Z3Block &b, int nx, int ny)
+{
+    constexpr int Z3_HALO = Z3T<TY>::HALO;
+    Z3Nodes q;
+    const int t = threadIdx.x;
+    int lx, ly;
+    z3_region<TY>(0, t, lx, ly);
+    q.xc = b.x0 + lx - 1;
+    q.yc = b.y0 + ly - 1;
+    q.rc = ly * Z3_LX + lx;
+    q.inc = q.xc < nx && q.yc < ny;
+    z3_region<TY>(1, t < Z3_HALO ? t : 0, lx, ly);
+    q.xh = b.x0 + lx - 1;
+    q.yh = b.y0 + ly - 1;
+    q.rh = ly * Z3_LX + lx;
+    q.inh = t < Z3_HALO && q.xh >= 0 && q.xh < nx && q.yh >= 0 && q.yh < ny;
+    return q;
+}
+
+template <class S, int MODE, bool NT, bool BUF, int TY>
+__device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsigned long long *part_r,
+                                              unsigned long long *part_u, void *smem)
+{
+    typedef D3Q19 L;
+    typedef uint32_t DT;
+    typedef typename S::C C;
+    constexpr unsigned int OWN = fluid_out_own<L>();
+    constexpr int NO = own_count<L>(OWN);
+    static_assert(MODE == MODE_PLAIN || !S::tile_mean, "checks with tile means take single steps");
+    C *lds = static_cast<C *>(smem);
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const Z3Block b = z3_block<TY>(a.g, a.zseg, tile);
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const Z3Nodes q = z3_nodes<TY>(b, nx, ny);
+    const bool xin_c = q.xc == 0, xout_c = q.xc == nx - 1;
+    const bool xin_h = q.xh == 0, xout_h = q.xh == nx - 1;
+    // column references (FP16 storage): constant over the launch
+    C r0c = C(1), dmc = C(0), dpc = C(0), r0h = C(1), dmh = C(0), dph = C(0), rdc = C(1), rd2 = C(1);
+    C s2m = C(0), s2p = C(0), s2r = C(1);
+    if constexpr (S::colref) {
+        if (q.inc) {
+            column_refs<S>(a.ref_src, a.ref_src, q.xc, nx, r0c, dmc, dpc, rdc);
+            column_refs<S>(a.ref_src, a.ref_dst, q.xc, nx, s2r, s2m, s2p, rd2);
+        }
+        if (q.inh)
+            column_refs<S>(a.ref_src, a.ref_src, q.xh, nx, r0h, dmh, dph, rdc);
+    }
+    auto nidx = [&](int x, int y, int k) { return (unsigned int)(x + nx * (y + ny * k)); };
+    auto dload = [&](bool in, int x, int y, int k) {
+        return (in && k >= 0 && k < nz) ? desc[nidx(x, y, k)] : DT(0);
+    };
+    const int kb = b.z0 - 1, ke = b.z1;
+    PreVals<L, C, NO> pc, ph;
+    DT dc = dload(q.inc, q.xc, q.yc, kb), dh = dload(q.inh, q.xh, q.yh, kb);
+    auto issue = [&](int k) {
+        if (dc & DT(1)) {
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xc, q.yc, k));
+            z3_prefetch<L, OWN, true>(g, z3_rev<L>((unsigned int)dc, xin_c, xout_c), xout_c, pc);
+        }
+        if (dh & DT(1)) {
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xh, q.yh, k));
+            z3_prefetch<L, OWN, false>(g, z3_rev<L>((unsigned int)dh, xin_h, xout_h), xout_h, ph);
+        }
+    };
+    issue(kb);
+    DT dcn = dload(q.inc, q.xc, q.yc, kb + 1), dhn = dload(q.inh, q.xh, q.yh, kb + 1);
+    constexpr int NK = keep_count<L>();
+    C own[NK], nxt[NK];
+    DT dnx = DT(0);
+#pragma unroll
+    for (int i = 0; i < NK; ++i)
+        nxt[i] = C(0);
+    CheckAcc<S::tile_mean> acc;
+    for (int k = kb; k <= ke; ++k) {
+        // the kept values of plane k - 1 become this node's own
+        const DT d = dnx;
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+            own[i] = nxt[i];
+        __syncthreads(); // the previous plane's second step has read the LDS
+        // first step at plane k from the prefetched values
+        if (dc & DT(1)) {
+            C f[L::Q], ux, uy, uz, rho;
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xc, q.yc, k));
+            const PreSrc<L, C, OWN, true, decltype(g)> src{pc.v, pc.o, g};
+            fluid_collide<L, S, DT>(a, q.xc, dc, src, r0c, dmc, dpc, f, ux, uy, uz, rho);
+            z3_put<L, C, TY>(lds, k, q.rc, f);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                if (i == 0 || L::cz[i] < 0)
+                    nxt[keep_pos<L>(i)] = f[i];
+        }
+        if (dh & DT(1)) {
+            C f[L::Q], ux, uy, uz, rho;
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xh, q.yh, k));
+            const PreSrc<L, C, OWN, false, decltype(g)> src{ph.v, ph.o, g};
+            fluid_collide<L, S, DT>(a, q.xh, dh, src, r0h, dmh, dph, f, ux, uy, uz, rho);
+            z3_put<L, C, TY>(lds, k, q.rh, f);
+        }
+        // inactive nodes leave their slots unwritten: a second step reads a
+        // slot only as one of a link's two candidates and selects its own
+        // value whenever the slot's node is blocked
+        dnx = dc;
+        // loads of plane k + 1 (in flight during the second step below)
+        dc = dcn;
+        dh = dhn;
+        if (k + 1 <= ke)
+            issue(k + 1);
+        dcn = dload(q.inc, q.xc, q.yc, k + 2);
+        dhn = dload(q.inh, q.xh, q.yh, k + 2);
+        __syncthreads();
+        // second step at plane z = k - 1
+        const int z = k - 1;
+        if (z < b.z0 || z >= b.z1)
+            continue;
+        NodePos p;
+        p.x = q.xc;
+        p.y = q.yc;
+        p.z = z;
+        p.inb = q.inc;
+        p.n = q.inc ? nidx(q.xc, q.yc, z) : 0u;
+        const bool act = (d & DT(1)) != 0;
+        C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
+        C f[L::Q];
+        if (act) {
+            const RingSrc<L, C, TY> src{own, z3_planes<L, C, TY>(lds, z), q.rc};
+            fluid_collide<L, S, DT>(a, q.xc, d, src, s2r, s2m, s2p, f, ux, uy, uz, rho);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    f[i] += C(L::w[i]) * (s2r - rd2);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                f[i] = C(0);
+        }
+        fluid_store<L, S, NT>(a, p, f, a.step + 1);
+        if constexpr (MODE == MODE_CHECK)
+            fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit<Z3T<TY>::NTH / 64>(dbits(r * a.inv_uin), acc.ub, part_r, part_u);
+    }
+}
+
+template <class S, int MODE, bool NT, bool BUF, int TY>
+__global__ void __launch_bounds__(Z3T<TY>::NTH) k_fluid_step3d2(FluidArgs a)
+{
+    __shared__ __align__(16) char smem[z3_lds_bytes<D3Q19, typename S::C, TY>()];
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    fluid_tile3d2<S, MODE, NT, BUF, TY>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                    part + gridDim.x + blockIdx.x, smem);
+}
+
+template <class S, int MODE, bool NT, bool BUF, int TY>
+__device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned long long *part_r,
+                                           unsigned long long *part_u, void *smem)
+{
+    typedef D3Q7 L;
+    typedef uint32_t DT;
+    typedef typename S::C C;
+    constexpr int QF = 19;
+    constexpr int ACT = QF - 1 + L::Q;
+    constexpr int LNK = QF - 1;
+    constexpr unsigned int OWN = xdirs<L>(-1);
+    constexpr int NO = own_count<L>(OWN);
+    static_assert(MODE == MODE_PLAIN || !S::tile_mean, "checks with tile means take single steps");
+    C *lds = static_cast<C *>(smem);
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const Z3Block b = z3_block<TY>(a.g, a.zseg, tile);
+    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
+    const unsigned int NN = (unsigned int)a.g.N;
+    const Z3Nodes q = z3_nodes<TY>(b, nx, ny);
+    const bool xin_c = q.xc == 0, xout_c = q.xc == nx - 1;
+    const bool xin_h = q.xh == 0, xout_h = q.xh == nx - 1;
+    C r0c = C(a.c_ref), dmc = C(0), dpc = C(0), r0h = C(a.c_ref), dmh = C(0), dph = C(0), rdc = r0c;
+    C s2r = C(a.c_ref), s2m = C(0), s2p = C(0), rd2 = s2r;
+    if constexpr (S::colref) {
+        if (q.inc) {
+            column_refs<S>(a.ref_src, a.ref_src, q.xc, nx, r0c, dmc, dpc, rdc);
+            column_refs<S>(a.ref_src, a.ref_dst, q.xc, nx, s2r, s2m, s2p, rd2);
+        }
+        if (q.inh)
+            column_refs<S>(a.ref_src, a.ref_src, q.xh, nx, r0h, dmh, dph, rdc);
+    }
+    auto nidx = [&](int x, int y, int k) { return (unsigned int)(x + nx * (y + ny * k)); };
+    auto dload = [&](bool in, int x, int y, int k) {
+        return (in && k >= 0 && k < nz) ? desc[nidx(x, y, k)] : DT(0);
+    };
+    const int kb = b.z0 - 1, ke = b.z1;
+    PreVals<L, C, NO> pc, ph;
+    DT dc = dload(q.inc, q.xc, q.yc, kb), dh = dload(q.inh, q.xh, q.yh, kb);
+    auto issue = [&](int k) {
+        if ((dc >> ACT) & DT(1)) {
+            const unsigned int n = nidx(q.xc, q.yc, k);
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, n);
+            z3_prefetch<L, OWN, true>(g, z3_rev<L>((unsigned int)dc >> LNK, xin_c, xout_c), xout_c, pc);
+            pc.u[0] = U[n];
+            pc.u[1] = U[NN + n];
+            pc.u[2] = U[2u * NN + n];
+        }
+        if ((dh >> ACT) & DT(1)) {
+            const unsigned int n = nidx(q.xh, q.yh, k);
+            const auto g = z3_src<L, S, BUF>(a.src, a.g, n);
+            z3_prefetch<L, OWN, false>(g, z3_rev<L>((unsigned int)dh >> LNK, xin_h, xout_h), xout_h, ph);
+            ph.u[0] = U[n];
+            ph.u[1] = U[NN + n];
+            ph.u[2] = U[2u * NN + n];
+        }
+    };
+    issue(kb);
+    DT dcn = dload(q.inc, q.xc, q.yc, kb + 1), dhn = dload(q.inh, q.xh, q.yh, kb + 1);
+    constexpr int NK = keep_count<L>();
+    C own[NK], nxt[NK];
+    C ou[3], nu[3];
+    DT dnx = DT(0);
+#pragma unroll
+    for (int i = 0; i < NK; ++i)
+        nxt[i] = C(0);
+    nu[0] = nu[1] = nu[2] = C(0);
+    CheckAcc<S::tile_mean> acc;
+    for (int k = kb; k <= ke; ++k) {
+        const DT d = dnx;
+#pragma unroll
+        for (int i = 0; i < NK; ++i)
+            own[i] = nxt[i];
+        ou[0] = nu[0];
+        ou[1] = nu[1];
+        ou[2] = nu[2];
+        __syncthreads();
+        if ((dc >> ACT) & DT(1)) {
+            C g[L::Q], cfull;
+            const auto gs = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xc, q.yc, k));
+            const PreSrc<L, C, OWN, true, decltype(gs)> src{pc.v, pc.o, gs};
+            ad_collide<L, QF, S, DT>(a, q.xc, dc, src, pc.u[0], pc.u[1], pc.u[2], r0c, dmc, dpc, g, cfull);
+            z3_put<L, C, TY>(lds, k, q.rc, g);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                if (i == 0 || L::cz[i] < 0)
+                    nxt[keep_pos<L>(i)] = g[i];
+            nu[0] = pc.u[0];
+            nu[1] = pc.u[1];
+            nu[2] = pc.u[2];
+        }
+        if ((dh >> ACT) & DT(1)) {
+            C g[L::Q], cfull;
+            const auto gs = z3_src<L, S, BUF>(a.src, a.g, nidx(q.xh, q.yh, k));
+            const PreSrc<L, C, OWN, false, decltype(gs)> src{ph.v, ph.o, gs};
+            ad_collide<L, QF, S, DT>(a, q.xh, dh, src, ph.u[0], ph.u[1], ph.u[2], r0h, dmh, dph, g, cfull);
+            z3_put<L, C, TY>(lds, k, q.rh, g);
+        }
+        dnx = dc;
+        dc = dcn;
+        dh = dhn;
+        if (k + 1 <= ke)
+            issue(k + 1);
+        dcn = dload(q.inc, q.xc, q.yc, k + 2);
+        dhn = dload(q.inh, q.xh, q.yh, k + 2);
+        __syncthreads();
+        const int z = k - 1;
+        if (z < b.z0 || z >= b.z1)
+            continue;
+        NodePos p;
+        p.x = q.xc;
+        p.y = q.yc;
+        p.z = z;
+        p.inb = q.inc;
+        p.n = q.inc ? nidx(q.xc, q.yc, z) : 0u;
+        const bool act = ((d >> ACT) & DT(1)) != 0;
+        C cfull = C(0);
+        C g[L::Q];
+        if (act) {
+            const RingSrc<L, C, TY> src{own, z3_planes<L, C, TY>(lds, z), q.rc};
+            ad_collide<L, QF, S, DT>(a, q.xc, d, src, ou[0], ou[1], ou[2], s2r, s2m, s2p, g, cfull);
+            if constexpr (S::colref) {
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    g[i] += C(L::w[i]) * (s2r - rd2);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                g[i] = C(0);
+        }
+        ad_store<L, S, NT>(a, p, g, a.step + 1);
+        if constexpr (MODE == MODE_CHECK)
+            ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
+    }
+    if constexpr (MODE == MODE_CHECK) {
+        const double r = acc.result();
+        block_max_commit<Z3T<TY>::NTH / 64>(dbits(r * a.inv_cin), 0ull, part_r, part_u);
+    }
+}
+
+template <class S, int MODE, bool NT, bool BUF, int TY>
+__global__ void __launch_bounds__(Z3T<TY>::NTH) k_ad_step3d2(AdArgs a)
+{
+    __shared__ __align__(16) char smem[z3_lds_bytes<D3Q7, typename S::C, TY>()];
+    if (a.ctrl->stop)
+        return;
+    unsigned long long *part = a.ctrl->part;
+    ad_tile3d2<S, MODE, NT, BUF, TY>(a, xcd_tile(blockIdx.x, gridDim.x), part + blockIdx.x,
+                                 part + gridDim.x + blockIdx.x, smem);
+}
+
 // ------------------------------------------------------- init / export
 template <class L, class S, class DT>
 __global__ void __launch_bounds__(256) k_fluid_init(typename S::T *f, const DT *desc, long long N)
@@ -2456,6 +3047,103 @@ hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hip
             else
                 go(D2Q5{}, std::integral_constant<int, 9>{});
         });
+    });
+}
+
+// Two-step 3-D launches: column height, output planes per block, and
+// blocks.  32 x 16 columns (512 threads, 88 KB of LDS for the fluid: one
+// block per CU) recompute 1.2x the column in the first step, 32 x 8 (256
+// threads, 49 KB) 1.3x.  The planes per block are chosen so that the grid is
+// about one round of resident blocks, at least 4 (on 256 x 128 x 128 with
+// 32 x 16 columns: 64 columns x 4 segments of 32 planes).  The environment
+// variable LBM_3D_TILE_Y (8 or 16) overrides the column height (tuning).
+int z3_tile_y(const Geo &g)
+{
+    (void)g;
+    if (const char *e = getenv("LBM_3D_TILE_Y"))
+        if (atoi(e) == 8 || atoi(e) == 16)
+            return atoi(e);
+    return 16;
+}
+int z3_planes_per_block(const Geo &g, int ty, int blocks_per_cu)
+{
+    const int ncol = ((g.nx + Z3_TX - 1) / Z3_TX) * ((g.ny + ty - 1) / ty);
+    const int want = 256 * blocks_per_cu;
+    int nseg = (want + ncol / 2) / ncol;
+    nseg = nseg < 1 ? 1 : nseg;
+    int zs = (g.nz + nseg - 1) / nseg;
+    return zs < 4 ? (g.nz < 4 ? g.nz : 4) : zs;
+}
+int z3_blocks(const Geo &g, int zseg, int ty)
+{
+    const int ncol = ((g.nx + Z3_TX - 1) / Z3_TX) * ((g.ny + ty - 1) / ty);
+    return ncol * ((g.nz + zseg - 1) / zseg);
+}
+
+template <class S, class K>
+static hipError_t launch_z3(int mode, const Geo &g, int zseg, int ty, bool nt, unsigned long long n_elems, K k)
+{
+    if constexpr (sizeof(typename S::C) != 4) {
+        return hipErrorInvalidValue;
+    } else {
+        if (g.nz < 3 || zseg < 1 || (ty != 8 && ty != 16) || (S::tile_mean && mode != MODE_PLAIN))
+            return hipErrorInvalidValue;
+        const dim3 grid(z3_blocks(g, zseg, ty));
+        const bool buf = n_elems * sizeof(typename S::T) <= 0xFFFFFFFFull;
+        auto go = [&](auto mc, auto ntc, auto bc) {
+            constexpr int M = decltype(mc)::value;
+            if constexpr (!(S::tile_mean && M != MODE_PLAIN)) {
+                if (ty == 16)
+                    k(mc, ntc, bc, std::integral_constant<int, 16>{}, grid);
+                else
+                    k(mc, ntc, bc, std::integral_constant<int, 8>{}, grid);
+            }
+        };
+        auto by_buf = [&](auto mc, auto ntc) {
+            if (buf)
+                go(mc, ntc, std::true_type{});
+            else
+                go(mc, ntc, std::false_type{});
+        };
+        auto by_nt = [&](auto mc) {
+            if (nt)
+                by_buf(mc, std::true_type{});
+            else
+                by_buf(mc, std::false_type{});
+        };
+        if (mode == MODE_CHECK)
+            by_nt(std::integral_constant<int, MODE_CHECK>{});
+        else
+            by_nt(std::integral_constant<int, MODE_PLAIN>{});
+        return hipGetLastError();
+    }
+}
+
+hipError_t fluid_step3d2(int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        return launch_z3<S>(mode, a.g, a.zseg, a.ty3, a.streaming_stores != 0, 19ull * (unsigned long long)a.g.N,
+                            [&](auto mc, auto ntc, auto bc, auto tyc, dim3 grid) {
+                                constexpr int M = decltype(mc)::value, TY = decltype(tyc)::value;
+                                constexpr bool NT = decltype(ntc)::value, B = decltype(bc)::value;
+                                hipLaunchKernelGGL((k_fluid_step3d2<S, M, NT, B, TY>), grid, dim3(Z3T<TY>::NTH), 0,
+                                                   st, a);
+                            });
+    });
+}
+
+hipError_t ad_step3d2(int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return by_storage(storage, [&](auto s) -> hipError_t {
+        typedef decltype(s) S;
+        return launch_z3<S>(mode, a.g, a.zseg, a.ty3, a.streaming_stores != 0, 7ull * (unsigned long long)a.g.N,
+                            [&](auto mc, auto ntc, auto bc, auto tyc, dim3 grid) {
+                                constexpr int M = decltype(mc)::value, TY = decltype(tyc)::value;
+                                constexpr bool NT = decltype(ntc)::value, B = decltype(bc)::value;
+                                hipLaunchKernelGGL((k_ad_step3d2<S, M, NT, B, TY>), grid, dim3(Z3T<TY>::NTH), 0, st,
+                                                   a);
+                            });
     });
 }
 

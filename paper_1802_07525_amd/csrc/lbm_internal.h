@@ -107,6 +107,9 @@ struct lbm_solver {
     void *d_desc_ad = nullptr;
     std::vector<uint16_t> desc_ad_h;
     int64_t n_fluid = 0, n_ad = 0;
+    int zseg_f = 0, zseg_a = 0;  // 3-D two-step launches: output planes per block
+    int ty3 = 0;                 // 3-D two-step launches: column height
+    int max_launch_steps = 0;    // cap on steps per launch (0: none)
     double c_ref = 0.0;          // substrate shift reference (0 if unshifted)
 
     void *d_desc = nullptr;
@@ -116,7 +119,8 @@ struct lbm_solver {
     void *d_uprev = nullptr;     // compute type [dim][N]
     void *d_cprev = nullptr;     // compute type [N]
     lbmk::Ctrl *d_ctrl = nullptr; // [2]: fluid, substrate
-    unsigned long long *d_part = nullptr; // [2][2 * ntiles] per-block check maxima
+    unsigned long long *d_part = nullptr; // [2][2 * part_n] per-block check maxima
+    int part_n = 0;              // blocks of the largest check launch
     float *d_ref = nullptr;      // column references [4][nx]: fluid cur, next; substrate cur, next
     double *d_partials = nullptr;
     double *d_out5 = nullptr;

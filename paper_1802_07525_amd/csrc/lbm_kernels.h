@@ -96,6 +96,8 @@ struct FluidArgs {
     const float *ref_src; // column reference of src (FP16 storage only)
     const float *ref_dst; // column reference of dst
     float *ref_out;       // check steps: sample values for the next reference
+    int zseg;             // two-step 3-D launches: output planes per block
+    int ty3;              // two-step 3-D launches: column height (8 or 16)
 };
 
 struct AdArgs {
@@ -120,6 +122,8 @@ struct AdArgs {
     const float *ref_src; // column references, as in FluidArgs
     const float *ref_dst;
     float *ref_out;
+    int zseg;             // two-step 3-D launches: output planes per block
+    int ty3;              // two-step 3-D launches: column height (8 or 16)
 };
 
 size_t storage_bytes(int storage);  // bytes per stored population
@@ -166,6 +170,20 @@ hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStr
 // ns = 3 or 4 substrate steps per launch, under the same conditions (lay as
 // ad_step2).
 hipError_t ad_stepN(int lay, int storage, int mode, int ns, const AdArgs &a, hipStream_t st);
+
+// Two steps in one launch (3-D, compute types of 4 bytes): a block marches
+// along z over a.zseg output planes of a 32 x a.ty3 column, steps a.step and
+// a.step + 1, src -> dst like one step; the check (MODE_CHECK) on the
+// second, not for storage with tile means.  FP32 results equal two single
+// steps up to rounding order; FP16 storage skips one rounding.
+hipError_t fluid_step3d2(int storage, int mode, const FluidArgs &a, hipStream_t st);
+hipError_t ad_step3d2(int storage, int mode, const AdArgs &a, hipStream_t st);
+// column height and output planes per block the grid's two-step 3-D
+// launches take by default, and the blocks (per-block check maxima) of such
+// a launch
+int z3_tile_y(const Geo &g);
+int z3_planes_per_block(const Geo &g, int ty, int blocks_per_cu);
+int z3_blocks(const Geo &g, int zseg, int ty);
 
 // f = rest state on FLUID nodes, 0 elsewhere.
 hipError_t fluid_init(int dim, int storage, void *f, const void *desc, const Geo &g,

@@ -11,6 +11,7 @@
 // chunks in flight, so the GPU never waits on the host for a decision and the
 // state at the stop is exactly the state of the deciding check.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -195,14 +196,15 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
 
 // 2-D solvers launch several steps at a time (one launch, LDS between them)
 inline bool paired(const lbm_solver *s) { return s->dim == 2; }
-// most steps one launch of this solver takes: 1 in 3-D; in 2-D 2, or 4 for
-// the multi-step form
+// most steps one launch of this solver takes: in 3-D 2 (z-marching blocks,
+// compute types of 4 bytes) or 1 (FP64); in 2-D 2, or 4 for the multi-step
+// form
 inline int launch_steps(const lbm_solver *s, int which)
 {
     (void)which; // both solvers take the same form
-    if (!paired(s))
-        return 1;
-    return lbmk::fluid_launch_steps(s->p.storage, s->geo);
+    const int spl = !paired(s) ? (s->p.storage == LBM_FP64 ? 1 : 2)
+                               : lbmk::fluid_launch_steps(s->p.storage, s->geo);
+    return s->max_launch_steps > 0 && s->max_launch_steps < spl ? s->max_launch_steps : spl;
 }
 // steps of the next launch with `rem` steps left: the largest launch size
 // that does not leave a single step behind, a one only to finish an odd
@@ -226,6 +228,11 @@ inline int next_launch(int spl, int64_t rem)
 inline int plan_next(const lbm_solver *s, int which, int64_t rem, bool first)
 {
     const int spl = launch_steps(s, which);
+    // 3-D storage with tile means (FP16) takes its check as a single step
+    // (tile means over 64 x 4 tiles of one plane): a chunk ends on two
+    // single steps (K = 100: 49 x 2, 1, 1)
+    if (!paired(s) && spl == 2 && lbmk::storage_moving_ref(s->p.storage))
+        return rem <= 2 ? 1 : 2;
     if (spl < 4 || !lbmk::storage_moving_ref(s->p.storage))
         return next_launch(spl, rem);
     const int k = next_launch(2, rem);
@@ -250,8 +257,12 @@ inline int64_t launches_for(const lbm_solver *s, int which, int64_t steps)
 // blocks of the check-step launches (the per-block maxima the decide reads)
 inline int check_blocks(const lbm_solver *s, int which)
 {
-    if (!paired(s))
+    if (launch_steps(s, which) == 1)
         return s->geo.ntiles;
+    if (!paired(s))
+        return lbmk::storage_moving_ref(s->p.storage)
+                   ? s->geo.ntiles
+                   : lbmk::z3_blocks(s->geo, which == LBM_SOLVER_FLUID ? s->zseg_f : s->zseg_a, s->ty3);
     (void)which; // both solvers pick the same tile shape
     return lbmk::pair_tiles(s->geo, lbmk::pair_ty(s->p.storage, s->geo));
 }
@@ -278,10 +289,14 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
         a.ref_src = ref_cur(s, 0);
         a.ref_dst = first ? ref_next(s, 0) : ref_cur(s, 0);
         a.ref_out = ref_next(s, 0);
+        a.zseg = s->zseg_f;
+        a.ty3 = s->ty3;
         if (nsteps >= 3)
             return lbmk::fluid_stepN(s->p.storage, mode, nsteps, a, s->ctx->stream);
-        return nsteps == 2 ? lbmk::fluid_step2(s->p.storage, mode, a, s->ctx->stream)
-                           : lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
+        if (nsteps == 2)
+            return paired(s) ? lbmk::fluid_step2(s->p.storage, mode, a, s->ctx->stream)
+                             : lbmk::fluid_step3d2(s->p.storage, mode, a, s->ctx->stream);
+        return lbmk::fluid_step(s->dim, s->p.storage, mode, a, s->ctx->stream);
     }
     const double cs2 = s->dim == 3 ? 0.25 : 1.0 / 3.0;
     lbmk::AdArgs a;
@@ -308,10 +323,14 @@ hipError_t launch_step(lbm_solver *s, int which, int mode, int src, bool first =
     a.ref_src = ref_cur(s, 1);
     a.ref_dst = first ? ref_next(s, 1) : ref_cur(s, 1);
     a.ref_out = ref_next(s, 1);
+    a.zseg = s->zseg_a;
+    a.ty3 = s->ty3;
     if (nsteps >= 3)
         return lbmk::ad_stepN(ad_lay(s), s->p.storage, mode, nsteps, a, s->ctx->stream);
-    return nsteps == 2 ? lbmk::ad_step2(ad_lay(s), s->p.storage, mode, a, s->ctx->stream)
-                       : lbmk::ad_step(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
+    if (nsteps == 2)
+        return paired(s) ? lbmk::ad_step2(ad_lay(s), s->p.storage, mode, a, s->ctx->stream)
+                         : lbmk::ad_step3d2(s->p.storage, mode, a, s->ctx->stream);
+    return lbmk::ad_step(ad_lay(s), s->p.storage, mode, a, s->ctx->stream);
 }
 
 lbm_status init_solver(lbm_solver *s, int which)
@@ -393,7 +412,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                                                     : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
     HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
+                            s->d_part + (size_t)which * 2 * s->part_n, check_blocks(s, which), stream),
            "ctrl reset");
     int &cur = which == LBM_SOLVER_FLUID ? s->fcur : s->gcur;
     const int cur0 = cur;
@@ -672,6 +691,28 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
     s->ad9 = p.ad_lattice == 1;
     s->qa = s->dim == 3 ? 7 : (s->ad9 ? 9 : 5);
     s->geo = lbmk::make_geo(g.nx, g.ny, g.nz);
+    s->ty3 = g.nz > 1 ? lbmk::z3_tile_y(s->geo) : 0;
+    // resident blocks per CU: the fluid kernel is held to two waves per SIMD
+    // by its registers (one 512-thread or two 256-thread blocks), the
+    // substrate kernel to four (32 x 16) or five (32 x 8) blocks
+    s->zseg_f = g.nz > 1 ? lbmk::z3_planes_per_block(s->geo, s->ty3, s->ty3 == 16 ? 1 : 2) : 0;
+    s->zseg_a = g.nz > 1 ? lbmk::z3_planes_per_block(s->geo, s->ty3, s->ty3 == 16 ? 4 : 5) : 0;
+    // LBM_3D_PLANES_PER_BLOCK overrides the planes per block of the
+    // two-step 3-D launches (tuning; tests run several segment lengths)
+    if (const char *e = getenv("LBM_3D_PLANES_PER_BLOCK"))
+        if (g.nz > 1 && atoi(e) > 0)
+            s->zseg_f = s->zseg_a = atoi(e) < g.nz ? atoi(e) : g.nz;
+    // LBM_MAX_LAUNCH_STEPS = 1 or 2 caps the steps per launch (tests compare
+    // the launch forms, which take the same steps)
+    if (const char *e = getenv("LBM_MAX_LAUNCH_STEPS"))
+        if (atoi(e) == 1 || atoi(e) == 2)
+            s->max_launch_steps = atoi(e);
+    // per-block check maxima: one slot pair per block of the largest check
+    // launch (64 x 4 tiles, or the 3-D two-step blocks where there are more)
+    s->part_n = s->geo.ntiles;
+    for (int zs : {s->zseg_f, s->zseg_a})
+        if (g.nz > 1 && lbmk::z3_blocks(s->geo, zs, s->ty3) > s->part_n)
+            s->part_n = lbmk::z3_blocks(s->geo, zs, s->ty3);
     s->cls.assign(cls, cls + N64);
     s->desc_bytes = s->dim == 3 ? 4 : 2;
     s->c_ref = lbmk::storage_shifted(p.storage) ? p.c_in : 0.0;
@@ -691,7 +732,7 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
         return fail(st);
     s->d_ctrl = static_cast<lbmk::Ctrl *>(tmp);
     tmp = nullptr;
-    if ((st = dev_alloc(s, &tmp, 4 * sizeof(unsigned long long) * (size_t)s->geo.ntiles, "check maxima")))
+    if ((st = dev_alloc(s, &tmp, 4 * sizeof(unsigned long long) * (size_t)s->part_n, "check maxima")))
         return fail(st);
     s->d_part = static_cast<unsigned long long *>(tmp);
     tmp = nullptr;
@@ -783,7 +824,7 @@ lbm_status lbm_solver_steps(lbm_solver *s, int which, int64_t nsteps, int cold, 
             return st;
     hipStream_t stream = s->ctx->stream;
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
+                            s->d_part + (size_t)which * 2 * s->part_n, check_blocks(s, which), stream),
            "ctrl");
     int &cur = which == 0 ? s->fcur : s->gcur;
     HIPCHK(hipEventRecord(s->ev_a, stream), "event");
@@ -813,7 +854,7 @@ lbm_status lbm_solver_time_steps(lbm_solver *s, int which, int nsteps, double *a
         return set_err(s->ctx, LBM_EINVAL, "state not initialised");
     hipStream_t stream = s->ctx->stream;
     HIPCHK(lbmk::ctrl_reset(s->d_ctrl + which, 0.0, 0, which == 0, s->p.check_every,
-                            s->d_part + (size_t)which * 2 * s->geo.ntiles, check_blocks(s, which), stream),
+                            s->d_part + (size_t)which * 2 * s->part_n, check_blocks(s, which), stream),
            "ctrl");
     const int k = launch_steps(s, which); // steps per launch
     const int nl = (nsteps + k - 1) / k;
