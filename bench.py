@@ -34,18 +34,20 @@ METRIC = "MLUPS and % HBM peak (fluid+AD LBM); served p50/p99 steady-solve laten
 HBM_PEAK_GBS = 8000.0
 STORAGES = {"fp32": 0, "fp32s": 1, "fp16s": 2, "fp64": 3}
 DTYPES = {"fp32": "f32", "fp32s": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
-# the step kernels' source and the build script holding their compiler
-# flags: counters taken for other code are not reported
+# the step kernels' sources and compiler flags: counters taken for other
+# code are not reported
 KERNEL_SRC = (os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "kernels.hip"),
-              os.path.join(ROOT, "paper_1802_07525_amd", "build.py"))
+              os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "lbm_kernels.h"))
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_sha():
+    from paper_1802_07525_amd import build as libbuild
     h = hashlib.sha256()
     for path in KERNEL_SRC:
         with open(path, "rb") as fh:
             h.update(fh.read())
+    h.update(repr((libbuild.COMMON[:4], libbuild.DEVICE)).encode())
     return h.hexdigest()[:16]
 
 
