@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -41,12 +42,20 @@ KERNEL_SRC = (os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "kernels.hip"),
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+def _code_only(text):
+    """Source text without comments and blank space (comment edits do not
+    change the kernels)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sha():
     from paper_1802_07525_amd import build as libbuild
     h = hashlib.sha256()
     for path in KERNEL_SRC:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path) as fh:
+            h.update(_code_only(fh.read()).encode())
     h.update(repr((libbuild.COMMON[:4], libbuild.DEVICE)).encode())
     return h.hexdigest()[:16]
 
@@ -325,24 +334,11 @@ def mfc_main(args):
     print(json.dumps(res), flush=True)
 
 
-def served_main(args):
-    """Served stream: seeded requests with Poisson arrivals submitted in real
-    time to one server (continuous batching), then the same requests solved
-    one at a time by the plain FP32 single-solve path on the same GPU."""
+def _serve_stream(lbm, ctx, reqs, storage, args, max_iter):
+    """Submit reqs in real time (Poisson arrivals) to a fresh server and
+    collect every result: (results by request index, refusals, stats)."""
     import threading
 
-    import numpy as np
-    import torch
-
-    import paper_1802_07525_amd as lbm
-    from paper_1802_07525_amd import inputs
-
-    assert torch.cuda.is_available(), "no GPU visible"
-    lbm.load()
-    reqs = inputs.serve_requests(args.requests, args.rate)
-    storage = STORAGES[args.storage]
-    max_iter = args.max_iter or 2_000_000
-    ctx = lbm.lbm_ctx_create(0)
     cfg = lbm.make_server_cfg(int(args.pool_gb * (1 << 30)), max_slots=args.slots, storage=storage,
                               prep_threads=4, stall_checks=args.stall_checks)
     srv = lbm.lbm_server_create(ctx, cfg)
@@ -374,90 +370,153 @@ def served_main(args):
             results[d["user"]] = d
         if time.perf_counter() - last > 20:
             last = time.perf_counter()
-            print("served: %d/%d finished after %.0f s" % (len(results), len(reqs),
-                                                           last - t_start), file=sys.stderr,
-                  flush=True)
+            print("served: %d/%d finished after %.0f s" % (len(results), len(reqs), last - t_start),
+                  file=sys.stderr, flush=True)
     th.join()
     stats = lbm.lbm_server_stats(srv)
     lbm.lbm_server_destroy(srv)
+    return results, refused, stats
 
-    done = [d for d in results.values() if d["status"] >= 0]
-    lat = np.array([d["t_finish"] - d["t_submit"] for d in done])
-    t0 = min(d["t_submit"] for d in results.values())
-    t1 = max(d["t_finish"] for d in results.values())
-    makespan = t1 - t0
-    upd = sum(d["iters_fluid"] * d["active_fluid"] + d["iters_ad"] * d["active_ad"] for d in done)
-    print("served: all %d finished in %.1f s; plain FP32 single solves next" % (len(results),
-                                                                              makespan),
-          file=sys.stderr, flush=True)
 
-    # plain FP32 single solves of the same requests, one at a time
-    single_s, single_upd, eu, ec, single_fail = 0.0, 0.0, [], [], 0
-    last = time.perf_counter()
-    for d in sorted(done, key=lambda d: d["user"]):
-        if time.perf_counter() - last > 20:
-            last = time.perf_counter()
-            print("single FP32: request %d of %d" % (d["user"], len(reqs)), file=sys.stderr,
-                  flush=True)
-        r = reqs[d["user"]]
-        st, cls, _ = lbm.lbm_geom_discs(r["nx"], r["ny"], r["r_min"], r["r_max"],
-                                        1.0 - r["porosity"], r["overlap"], r["seed"])
-        p = lbm.make_params(tau=r["tau"], u_in=r["u_in"], D=r["D"], c_in=r["c_in"],
-                            k_sink=r["k"], storage=STORAGES["fp32"])
-        ts = time.perf_counter()
-        s = lbm.lbm_solver_create(ctx, cls, p)
+def _single(lbm, ctx, r, storage, max_iter, fixed=None):
+    """One request as a plain single solve: to its tolerance, or (fixed =
+    (fluid steps, substrate steps)) for exactly those steps.  Returns
+    (seconds, updates, U, C, status pair) or None if the fluid diverged."""
+    st, cls, _ = lbm.lbm_geom_discs(r["nx"], r["ny"], r["r_min"], r["r_max"], 1.0 - r["porosity"],
+                                    r["overlap"], r["seed"])
+    p = lbm.make_params(tau=r["tau"], u_in=r["u_in"], D=r["D"], c_in=r["c_in"], k_sink=r["k"],
+                        storage=storage)
+    ts = time.perf_counter()
+    s = lbm.lbm_solver_create(ctx, cls, p)
+    if fixed is None:
         sf, fi = lbm.lbm_solver_fluid(s, r["tol"], max_iter)
         if sf < 0:
             lbm.lbm_solver_destroy(s)
-            single_s += time.perf_counter() - ts
-            single_fail += 1
-            continue
+            return None
         sa, ai = lbm.lbm_solver_ad(s, r["tol"], max_iter)
-        U = lbm.lbm_solver_get(s, lbm.LBM_FIELD_U, (r["nx"], r["ny"], 1))
-        C = lbm.lbm_solver_get(s, lbm.LBM_FIELD_C, (r["nx"], r["ny"], 1))
-        lbm.lbm_solver_destroy(s)
-        single_s += time.perf_counter() - ts
-        single_upd += fi["iters"] * fi["active_nodes"] + ai["iters"] * ai["active_nodes"]
+        upd = fi["iters"] * fi["active_nodes"] + ai["iters"] * ai["active_nodes"]
+        stat = (sf, sa)
+    else:
+        lbm.lbm_solver_steps(s, 0, fixed[0], 1)
+        lbm.lbm_solver_export_u(s)
+        lbm.lbm_solver_steps(s, 1, fixed[1], 1)
+        nf = int(lbm.lbm_flow_domain(cls).sum())
+        na = int(((cls == 0) | (cls == 3)).sum())
+        upd = fixed[0] * nf + fixed[1] * na
+        stat = (0, 0)
+    grid = (r["nx"], r["ny"], 1)
+    U = lbm.lbm_solver_get(s, lbm.LBM_FIELD_U, grid)
+    C = lbm.lbm_solver_get(s, lbm.LBM_FIELD_C, grid)
+    lbm.lbm_solver_destroy(s)
+    return time.perf_counter() - ts, upd, U, C, stat, cls
+
+
+def served_main(args):
+    """Served stream: the seeded requests with Poisson arrivals, submitted in
+    real time to one server (continuous batching) at each rate of the sweep
+    (one JSON line per rate: p50/p99 latency, throughput).  Then the same
+    requests as plain single solves one at a time on the same GPU in FP32
+    shifted storage: to their tolerance (throughput), and for exactly the
+    served solves' step counts (equal work; field errors of the served
+    results against them)."""
+    import numpy as np
+    import torch
+
+    import paper_1802_07525_amd as lbm
+    from paper_1802_07525_amd import inputs
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    lbm.load()
+    storage = STORAGES[args.storage]
+    max_iter = args.max_iter or 2_000_000
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    ctx = lbm.lbm_ctx_create(0)
+    sb = {0: 4, 1: 4, 2: 2}[storage]
+    last_results = None
+    for rate in rates:
+        reqs = inputs.serve_requests(args.requests, rate)
+        results, refused, stats = _serve_stream(lbm, ctx, reqs, storage, args, max_iter)
+        done = [d for d in results.values() if d["status"] >= 0]
+        lat = np.array([d["t_finish"] - d["t_submit"] for d in done])
+        t0 = min(d["t_submit"] for d in results.values())
+        t1 = max(d["t_finish"] for d in results.values())
+        makespan = t1 - t0
+        upd = sum(d["iters_fluid"] * d["active_fluid"] + d["iters_ad"] * d["active_ad"] for d in done)
+        algo = sum(d["iters_fluid"] * d["active_fluid"] * algo_bytes(9, sb)
+                   + d["iters_ad"] * d["active_ad"] * algo_bytes(5, sb, 8) for d in done)
+        achieved = algo / stats["busy_seconds"] / 1e9 if stats["busy_seconds"] > 0 else 0.0
+        line = {
+            "metric": METRIC, "value": upd / makespan / 1e6, "unit": "MLUPS", "n_gpus": 1,
+            "steps": len(reqs), "warmup": 0, "ms_per_step": makespan / len(reqs) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": DTYPES[args.storage], "data": "synthetic",
+            "config": {"workload": "served stream: first %d requests of the seeded stream, Poisson "
+                                   "%g req/s, 2-D D2Q9+D2Q5, nx log-uniform 64..2048, ny = nx/2"
+                                   % (len(reqs), rate),
+                       "rate": rate, "storage": args.storage, "pool_gb": args.pool_gb,
+                       "slots": args.slots, "seed": inputs.SERVE_SEED},
+            "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
+                       "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                       "mean_s": float(lat.mean()), "makespan_s": makespan,
+                       "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
+                       "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
+                       "statuses": {lbm.status_name(k): int(sum(1 for d in results.values()
+                                                                if d["status"] == k))
+                                    for k in sorted({d["status"] for d in results.values()})}},
+            "roofline": {"bound": "hbm", "kernel": "k_srv_step (batched fluid+substrate)",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "note": "algorithmic bytes of all served updates / device-busy time"},
+        }
+        print(json.dumps(line), flush=True)
+        last_results = (reqs, results, makespan, upd)
+    if args.no_single:
+        lbm.lbm_ctx_destroy(ctx)
+        return
+    reqs, results, makespan, upd = last_results
+    done = sorted((d for d in results.values() if d["status"] >= 0), key=lambda d: d["user"])
+    # single FP32-shifted solves to tolerance (throughput), then at the served
+    # step counts (equal work: field errors)
+    single_s, single_upd, fail = 0.0, 0.0, 0
+    eq_s, eq_upd, eu, ec, n_ok = 0.0, 0.0, [], [], 0
+    last = time.perf_counter()
+    for d in done:
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            print("single FP32S: request %d of %d" % (d["user"], len(reqs)), file=sys.stderr, flush=True)
+        r = reqs[d["user"]]
+        a = _single(lbm, ctx, r, STORAGES["fp32s"], max_iter)
+        if a is None:
+            fail += 1
+        else:
+            single_s += a[0]
+            single_upd += a[1]
+        b = _single(lbm, ctx, r, STORAGES["fp32s"], max_iter, fixed=(d["iters_fluid"], d["iters_ad"]))
+        eq_s += b[0]
+        eq_upd += b[1]
+        U, C, cls = b[2], b[3], b[5]
         flat = cls.reshape(-1)
         fl, act = flat == 0, (flat == 0) | (flat == 3)
         eu.append(float(np.linalg.norm(d["u"][:, fl] - U[:, fl]) / np.linalg.norm(U[:, fl])))
         ec.append(float(np.linalg.norm(d["c"][act] - C[act]) / np.linalg.norm(C[act])))
+        n_ok += d["status"] == 0
     lbm.lbm_ctx_destroy(ctx)
     eu, ec = np.array(eu), np.array(ec)
-    sb = {0: 4, 1: 4, 2: 2}[storage]
-    algo = (upd and sum(d["iters_fluid"] * d["active_fluid"] * algo_bytes(9, sb)
-                        + d["iters_ad"] * d["active_ad"] * algo_bytes(5, sb, 8) for d in done))
-    achieved = algo / stats["busy_seconds"] / 1e9 if stats["busy_seconds"] > 0 else 0.0
-    out = {
-        "metric": METRIC, "value": upd / makespan / 1e6, "unit": "MLUPS", "n_gpus": 1,
-        "steps": len(reqs), "warmup": 0, "ms_per_step": makespan / len(reqs) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPES[args.storage], "data": "synthetic",
-        "config": {"workload": "served stream: %d requests, Poisson %g req/s, 2-D D2Q9+D2Q5, "
-                               "nx log-uniform 64..2048, ny = nx/2" % (len(reqs), args.rate),
-                   "storage": args.storage, "pool_gb": args.pool_gb, "slots": args.slots,
-                   "seed": inputs.SERVE_SEED},
-        "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
-                   "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                   "mean_s": float(lat.mean()), "makespan_s": makespan,
-                   "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
-                   "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
-                   "statuses": {lbm.status_name(k): int(sum(1 for d in results.values()
-                                                            if d["status"] == k))
-                                for k in sorted({d["status"] for d in results.values()})}},
-        "single_fp32": {"seconds": single_s, "mlups": single_upd / single_s / 1e6,
-                        "failed": single_fail,
-                        "req_per_s": len(done) / single_s,
-                        "speedup_served": single_s / makespan,
-                        "u_rel_l2_median": float(np.median(eu)), "u_rel_l2_max": float(eu.max()),
-                        "c_rel_l2_median": float(np.median(ec)), "c_rel_l2_max": float(ec.max()),
-                        "frac_within_5e-3": float(np.mean((eu < 5e-3) & (ec < 5e-3)))},
-        "roofline": {"bound": "hbm", "kernel": "k_srv_step (batched fluid+substrate)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "note": "algorithmic bytes of all served updates / device-busy time"},
-    }
-    print(json.dumps(out), flush=True)
+    within = (eu < 5e-3) & (ec < 5e-3)
+    print(json.dumps({
+        "compare": "served %s (last rate) against single FP32-shifted solves of the same %d requests "
+                   "on the same GPU" % (args.storage, len(done)),
+        "served_makespan_s": makespan, "served_mlups": upd / makespan / 1e6,
+        "served_ok": int(n_ok),
+        "single_fp32s_to_tol": {"seconds": single_s, "mlups": single_upd / single_s / 1e6,
+                                "failed": fail, "req_per_s": (len(done) - fail) / single_s},
+        "single_fp32s_equal_steps": {"seconds": eq_s, "mlups": eq_upd / eq_s / 1e6,
+                                     "speedup_served": eq_s / makespan},
+        "fields_vs_equal_steps": {"u_rel_l2_median": float(np.median(eu)), "u_rel_l2_max": float(eu.max()),
+                                  "c_rel_l2_median": float(np.median(ec)), "c_rel_l2_max": float(ec.max()),
+                                  "frac_within_5e-3": float(within.mean()),
+                                  "outside": [int(d["user"]) for d, ok in zip(done, within) if not ok]}}),
+          flush=True)
 
 
 def main():
@@ -471,6 +530,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--requests", type=int, default=48, help="served stream length")
     ap.add_argument("--rate", type=float, default=50.0, help="served arrivals per second")
+    ap.add_argument("--rates", default="", help="served: comma-separated arrival rates (a sweep)")
+    ap.add_argument("--no-single", action="store_true", help="served: skip the single-solve comparison")
     ap.add_argument("--pool-gb", type=float, default=32.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,

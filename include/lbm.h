@@ -75,6 +75,12 @@ typedef enum {
  * g_i - w_i c_ref (c_ref = c_in) for the substrate, an exact change of
  * variables that keeps the stored values small. */
 typedef enum {
+    /* unshifted FP32 storage: each population at its full magnitude (~w_i
+     * rho), whose round-to-nearest error recurs every step near a steady
+     * state.  Fixed-step results hold the FP32 bounds, but converged fields
+     * can drift past 1e-4 relative L2 (measured 1.4e-4 in velocity and
+     * 5e-4 in concentration after 20,000 + 53,000 steps); it is kept for
+     * comparison only.  LBM_FP32_SHIFTED is the FP32 form held to 1e-4. */
     LBM_FP32 = 0,
     LBM_FP32_SHIFTED = 1,
     LBM_FP16_SHIFTED = 2,
@@ -147,10 +153,12 @@ typedef struct {
     int64_t active_nodes; /* nodes the solver updates */
     double seconds;       /* wall time of the solve, device-synchronous */
     double kernel_ms;     /* HIP-event time over the step-kernel launches */
-    int64_t launches;     /* step-kernel launches covered by kernel_ms (a
-                             launch advances one step in 3-D; in 2-D two,
-                             or up to four with FP32 storage on grids of at
-                             least 512 tiles of 64 x 16 nodes) */
+    int64_t launches;     /* step-kernel launches covered by kernel_ms.  A
+                             launch advances two steps in 3-D (one with FP64
+                             storage; FP16 storage takes its check and the
+                             step before it as single steps); in 2-D two, or
+                             three to four with FP32 storage on grids of at
+                             least 256 tiles of 64 x 8 nodes */
     double mlups;         /* active-node updates per second / 1e6 */
     double gbps;          /* algorithmic bytes / kernel_ms: per active-node update,
                              each population read and written once, the 1-byte
@@ -256,8 +264,11 @@ void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
  * zero-mean momentum noise that would otherwise set a residual floor above
  * ordinary tolerances; the mean keeps the smooth evolution of the flow.
  * (The substrate residual below is treated the same way.)
- * Also stops on NaN/Inf or |u| > 0.3 (EDIVERGED) and after stall_checks
- * checks without a new residual minimum (STALLED).  u_out: host double
+ * Also stops on NaN/Inf or |u| > 0.3 (EDIVERGED), and (STALLED) after
+ * stall_checks consecutive checks that set neither a new maximum of the
+ * residual nor a new minimum since its last maximum -- a residual flat on a
+ * round-off floor above tol; a transient that rises before it decays does
+ * not count as a stall.  u_out: host double
  * [dim][N] (0 on blocked nodes).  info may be NULL. */
 lbm_status lbm_fluid_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
                             double u_in, double tol, int64_t max_iter, int storage,
@@ -286,6 +297,7 @@ lbm_status lbm_ad_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const
                              double D, double c_in, double k_sink, int outlet, double c_out,
                              double tol, int64_t max_iter, int storage, double *c_field,
                              lbm_info *info);
+
 
 /* ----------------------------------------------------- stateful solver */
 /* A solver owns the device state of one domain: both solvers' populations

@@ -24,9 +24,12 @@
 //    block into its own slot; a one-block decide kernel reduces the slots.
 //  * Every step kernel starts by reading the control word and returns when a
 //    stop has been decided, so the host may queue steps ahead of decisions.
-//  * Serving: a grid-stride variant runs the same per-tile code over the
-//    tiles of many 2-D requests at once, each in its own phase (fluid or
-//    substrate), driven by a device slot table.
+//  * Temporal blocking: 2-D launches take two to four steps over a tile and
+//    a halo staged in LDS; 3-D launches take two steps in blocks that march
+//    along z with rings of first-step planes in LDS.
+//  * Serving: one block per tile of the device slot table runs the same
+//    per-tile code over the tiles of many 2-D requests at once, each in its
+//    own phase (fluid or substrate).
 #include "lbm_kernels.h"
 
 #include <math.h>

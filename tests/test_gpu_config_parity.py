@@ -1,0 +1,133 @@
+"""Parity at the workloads' full sizes against stored FP64 oracle results.
+
+The oracle cannot run the full-size workloads within a test: 1024 x 512 to
+1e-6 takes 149,500 + 170,000 steps, 256 x 128 x 128 13,100 + 45,800 steps of
+D3Q19 and D3Q7, and the coupled loop 200 growth updates.  Its results are
+written beforehand by tests/golden/make_oracle_fields.py and
+tests/golden/make_oracle_coupled.py, which call only the oracle (FP64,
+Sec. 2.1.1 fluid, Sec. 2.1.2 substrate, the model loop of Sec. 2), into
+tests/golden/oracle_fields/.  A missing file skips its test with the command
+that writes it.
+
+* Iteration-matched fields: the GPU runs exactly the oracle's step counts
+  (those at which the GPU's FP32-shifted steady solves stop at 1e-6) from
+  the same starting states, and the sampled fields -- u_x, u_y, (u_z),
+  rho - 1 on flow-domain nodes, C on substrate-active nodes -- and the
+  FP64 fluxes (inflow, consumption J) must agree within 1e-4 relative L2
+  with FP32 shifted storage and 5e-3 with FP16 storage.  The steady solves
+  themselves must stop at those counts.
+* The coupled loop: the GPU's FP32-shifted loop and the oracle's FP64 loop
+  take the same seeded growth draws; the growth picks, and so the biofilm
+  masks, must be identical along all updates, and the consumption series
+  J agree within 1e-4.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import masks, rel_l2
+from paper_1802_07525_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FIELDS = os.path.join(HERE, "golden", "oracle_fields")
+FP32S, FP16S = 1, 2
+TOL = {FP32S: 1e-4, FP16S: 5e-3}
+STEPS = {"c2": (149500, 170000), "c3": (13100, 45800)}
+
+
+def _load(name):
+    path = os.path.join(FIELDS, name)
+    if not os.path.exists(path):
+        pytest.skip("%s not written (python tests/golden/make_oracle_*.py)" % path)
+    return np.load(path)
+
+
+def _gpu_fixed(lbm, cls, w, storage, nf, na):
+    with lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                    storage=storage) as s:
+        assert s.steps(lbm.LBM_SOLVER_FLUID, nf, cold=1)[0] == 0, s.error()
+        assert lbm.lbm_solver_export_u(s.h) == 0
+        U = s.get(lbm.LBM_FIELD_U)
+        R = s.get(lbm.LBM_FIELD_RHO)
+        assert s.steps(lbm.LBM_SOLVER_AD, na, cold=1)[0] == 0, s.error()
+        C = s.get(lbm.LBM_FIELD_C)
+        fl = lbm.lbm_solver_fluxes(s.h)
+    return U, R, C, fl
+
+
+@pytest.mark.parametrize("name,storage", [("c2", FP32S), ("c3", FP32S), ("c3", FP16S)],
+                         ids=["c2-fp32s", "c3-fp32s", "c3-fp16s"])
+def test_full_size_fields_iteration_matched(gpu_lib, name, storage):
+    lbm = gpu_lib
+    nf, na = STEPS[name]
+    ref = _load("%s_f%d_a%d.npz" % (name, nf, na))
+    w = inputs.WORKLOADS[name]
+    cls = masks(w, lbm)
+    nodes = ref["nodes"].astype(np.int64)
+    dom = O.flow_domain(cls).ravel()[nodes]
+    act = np.isin(cls.ravel()[nodes], [O.FLUID, O.BIOFILM])
+    print("%s %s: %d + %d steps" % (name, storage, nf, na), flush=True)
+    U, R, C, fl = _gpu_fixed(lbm, cls, w, storage, nf, na)
+    errs = {}
+    for d, ax in enumerate("xyz"[:U.shape[0]]):
+        errs["u_" + ax] = rel_l2(U[d, nodes], ref["U"][d], dom)
+    errs["rho-1"] = rel_l2(R[nodes] - 1.0, ref["rho_m1"], dom)
+    errs["C"] = rel_l2(C[nodes], ref["C"], act)
+    fx = ref["fluxes"]  # fluid in, fluid out, substrate in, substrate out, consumed
+    errs["substrate inflow"] = abs(fl[2] - fx[2]) / abs(fx[2])
+    if fx[4] != 0.0:
+        errs["J"] = abs(fl[4] - fx[4]) / abs(fx[4])
+    print(name, storage, errs, flush=True)
+    bad = {k: v for k, v in errs.items() if not v < TOL[storage]}
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_full_size_steady_solves_stop_at_the_stored_counts(gpu_lib, name):
+    """The FP32-shifted steady solves stop (OK) at the step counts the
+    stored oracle fields were taken at."""
+    lbm = gpu_lib
+    nf, na = STEPS[name]
+    _load("%s_f%d_a%d.npz" % (name, nf, na))
+    w = inputs.WORKLOADS[name]
+    cls = masks(w, lbm)
+    with lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                    storage=FP32S) as s:
+        st, fi = s.fluid(w["tol"], w["max_iter"])
+        assert st == 0 and fi["iters"] == nf, (st, fi["iters"])
+        assert lbm.lbm_solver_export_u(s.h) == 0
+        st, ai = s.ad(w["tol"], w["max_iter"])
+        assert st == 0 and ai["iters"] == na, (st, ai["iters"])
+
+
+def test_coupled_loop_full_size_matches_oracle(gpu_lib):
+    lbm = gpu_lib
+    w = inputs.WORKLOADS["c5"]
+    ref = _load("c5_u%d.npz" % w["updates"])
+    cls = masks(w, lbm)
+    xi = inputs.growth_draws(w["updates"], seed=w["seed"])
+    print("coupled loop 512x256, %d updates" % w["updates"], flush=True)
+    with lbm.Solver(cls, tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
+                    storage=FP32S) as s:
+        st, g = lbm.lbm_coupled_run(s.h, xi, w["tol"], w["max_iter"])
+        assert st == 0, (lbm.status_name(st), s.error())
+        C = s.get(lbm.LBM_FIELD_C)
+        final = s.get(lbm.LBM_FIELD_CLASS)
+    picked = ref["picked"]
+    same = int(np.sum(g["picked"] == picked))
+    print("picks equal: %d of %d" % (same, len(picked)), flush=True)
+    assert np.array_equal(g["picked"], picked)
+    want = cls.copy().ravel()
+    want[picked] = O.BIOFILM
+    assert np.array_equal(final.ravel(), want)
+    relJ = np.abs(g["J"] - ref["J"]) / np.abs(ref["J"])
+    print("J: max rel diff %.3g, J_accum %.3g" % (relJ.max(), abs(g["J_accum"] - ref["J_accum"][0]) /
+                                                   abs(ref["J_accum"][0])), flush=True)
+    assert relJ.max() < 1e-4
+    nodes = ref["nodes"].astype(np.int64)
+    act = np.isin(final.ravel()[nodes], [O.FLUID, O.BIOFILM])
+    assert rel_l2(C[nodes], ref["C"], act) < 1e-4
