@@ -298,6 +298,23 @@ lbm_status lbm_ad_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const
                              double tol, int64_t max_iter, int storage, double *c_field,
                              lbm_info *info);
 
+/* No-allocation form of lbm_fluid_steady_dev, for callers that cannot
+ * allocate device memory (code around stream capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments (device pointers) and
+ * the same results bit for bit: the same kernels in the same order.  Every
+ * device buffer of the solve is carved from a device scratch array of
+ * LBM_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it has run
+ * this call on, until the process ends; the call makes no device or pinned
+ * allocation and creates no events.  The solve needs about 90 bytes per
+ * node in 2-D with FP32 storage (about 700,000 nodes fit; 170 with FP64) and
+ * about 190 in 3-D: EINVAL, with the sizes in lbm_last_error, if the grid
+ * does not fit.  Calls that overlap on one GPU share its array and race:
+ * the caller serialises them.  info->kernel_ms and info->gbps are 0 (no
+ * events).  The context's stream is synchronised before return. */
+#define LBM_NOALLOC_SCRATCH_BYTES (64u << 20)
+lbm_status lbm_fluid_steady_dev_noalloc(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double tau,
+                                        double u_in, double tol, int64_t max_iter, int storage,
+                                        double *u_out, lbm_info *info);
 
 /* ----------------------------------------------------- stateful solver */
 /* A solver owns the device state of one domain: both solvers' populations

@@ -167,6 +167,7 @@ _SIGS = {
     "lbm_ad_steady": (I32, [P, G, P, P, D, D, D, I32, D, D, I64, I32, P, P]),
     "lbm_fluid_steady_dev": (I32, [P, G, P, D, D, D, I64, I32, P, P]),
     "lbm_ad_steady_dev": (I32, [P, G, P, P, D, D, D, I32, D, D, I64, I32, P, P]),
+    "lbm_fluid_steady_dev_noalloc": (I32, [P, G, P, D, D, D, I64, I32, P, P]),
     "lbm_solver_create": (I32, [P, G, P, P, P]),
     "lbm_solver_destroy": (None, [P]),
     "lbm_solver_fluid": (I32, [P, D, I64, I32, P]),
@@ -376,6 +377,16 @@ def lbm_fluid_steady_dev(ctx, grid, cls_ptr, tau, u_in, tol, max_iter, u_ptr,
     st = load().lbm_fluid_steady_dev(ctx, lbm_grid(*grid), ct.c_void_p(cls_ptr), float(tau),
                                      float(u_in), float(tol), int(max_iter), int(storage),
                                      ct.c_void_p(u_ptr), ct.byref(info))
+    return st, info.as_dict()
+
+
+def lbm_fluid_steady_dev_noalloc(ctx, grid, cls_ptr, tau, u_in, tol, max_iter, u_ptr,
+                                 storage=LBM_FP32_SHIFTED):
+    """No-allocation form of lbm_fluid_steady_dev (same arguments)."""
+    info = lbm_info()
+    st = load().lbm_fluid_steady_dev_noalloc(ctx, lbm_grid(*grid), ct.c_void_p(cls_ptr), float(tau),
+                                             float(u_in), float(tol), int(max_iter), int(storage),
+                                             ct.c_void_p(u_ptr), ct.byref(info))
     return st, info.as_dict()
 
 

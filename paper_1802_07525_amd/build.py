@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lbm.so")
-SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # -ffp-contract=on: multiply-adds are fused per source expression, not

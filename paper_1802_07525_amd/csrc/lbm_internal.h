@@ -82,6 +82,16 @@ lbm_status get_field_device(lbm_solver *s, int field, void *dst);
 // the frozen velocity from device double [dim][N] (staged through the host)
 lbm_status set_u_device(lbm_solver *s, const double *u);
 
+// solver whose device buffers are carved from the device region [arena,
+// arena + cap) (256-byte aligned): no device or pinned allocation and no
+// events; its steady solves check the control block synchronously after
+// each chunk (the same launches, stop and state).  EINVAL if the region is
+// too small.  Destroy with lbm_solver_destroy (frees nothing in the region).
+lbm_status solver_create_in(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params &p, void *arena,
+                            size_t cap, lbm_solver **out);
+// velocity (double [dim][N], device) of the fluid state, on the stream
+lbm_status export_u_device(lbm_solver *s, double *dst);
+
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
 lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);
@@ -134,7 +144,12 @@ struct lbm_solver {
     // saved in checkpoints so that a resumed run continues bit-exactly)
     unsigned long long fsteps = 0, gsteps = 0;
 
-    lbmk::Ctrl *h_ctrl = nullptr; // pinned ring of control snapshots
+    // device memory region the buffers are carved from instead of device
+    // allocations (the no-allocation solve); null: each buffer is allocated
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+
+    lbmk::Ctrl *h_ctrl = nullptr; // pinned ring of control snapshots (host heap with an arena)
     hipEvent_t ev_ring[8] = {};
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };

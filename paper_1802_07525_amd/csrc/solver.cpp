@@ -145,6 +145,17 @@ lbm_status dev_alloc(lbm_solver *s, void **p, size_t bytes, const char *what)
 {
     if (*p)
         return LBM_OK;
+    if (s->arena) {
+        const size_t off = (s->arena_used + 255) & ~(size_t)255;
+        if (off > s->arena_cap || bytes > s->arena_cap - off)
+            return set_err(s->ctx, LBM_EINVAL,
+                           std::string("the grid does not fit the scratch region (") + what + ": " +
+                               std::to_string(off + bytes) + " of " + std::to_string(s->arena_cap) + " bytes)");
+        *p = s->arena + off;
+        s->arena_used = off + bytes;
+        HIPCHK(hipMemsetAsync(*p, 0, bytes, s->ctx->stream), what);
+        return LBM_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -179,6 +190,8 @@ lbm_status ensure_stage(lbm_solver *s, size_t bytes)
 {
     if (s->stage_bytes >= bytes)
         return LBM_OK;
+    if (s->d_stage && s->arena)
+        return set_err(s->ctx, LBM_EINVAL, "staging buffer of a solver in a scratch region cannot grow");
     if (s->d_stage) {
         HIPCHK(hipStreamSynchronize(s->ctx->stream), "stage sync");
         HIPCHK(hipFree(s->d_stage), "stage free");
@@ -429,7 +442,11 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                                lbmk::Sink{s->p.k_sink, s->p.k_half}, s->d_cprev, 0, stream),
                "residual reference");
     const auto t0 = std::chrono::steady_clock::now();
-    HIPCHK(hipEventRecord(s->ev_a, stream), "event");
+    // a solver in a scratch region has no events: it reads each chunk's
+    // control snapshot synchronously
+    const bool sync = s->arena != nullptr;
+    if (!sync)
+        HIPCHK(hipEventRecord(s->ev_a, stream), "event");
     int64_t launched = 0, head = 0, tail = 0;
     bool stopped = false;
     const bool roll = lbmk::storage_moving_ref(s->p.storage);
@@ -453,6 +470,12 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         const int slot = (int)(head % RING);
         HIPCHK(hipMemcpyAsync(&s->h_ctrl[slot], ctrl, sizeof(lbmk::Ctrl), hipMemcpyDeviceToHost, stream),
                "ctrl snapshot");
+        if (sync) {
+            HIPCHK(hipStreamSynchronize(stream), "ctrl snapshot sync");
+            if (s->h_ctrl[slot].stop != lbmk::STOP_RUN)
+                stopped = true;
+            continue;
+        }
         HIPCHK(hipEventRecord(s->ev_ring[slot], stream), "event");
         ++head;
         while (tail < head) {
@@ -470,7 +493,8 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
             ++tail;
         }
     }
-    HIPCHK(hipEventRecord(s->ev_b, stream), "event");
+    if (!sync)
+        HIPCHK(hipEventRecord(s->ev_b, stream), "event");
     HIPCHK(hipStreamSynchronize(stream), "solve sync");
     lbmk::Ctrl fin;
     HIPCHK(hipMemcpy(&fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
@@ -493,8 +517,9 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
                                   s->d_u, nullptr, 0, stream),
                "velocity export");
     if (info) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b), "event time");
+        float ms = 0.f; // no kernel time without events
+        if (!sync)
+            HIPCHK(hipEventElapsedTime(&ms, s->ev_a, s->ev_b), "event time");
         memset(info, 0, sizeof(*info));
         info->iters = t_final;
         info->residual = fin.checks > 0 ? fin.r_last : NAN;
@@ -657,8 +682,12 @@ lbm_status lbm_solver_create(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const
     return lbm_solver_create_ex(ctx, g, cls, p, 1, out);
 }
 
-lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *pp,
-                                int require_percolation, lbm_solver **out)
+} // extern "C"
+
+// Creation shared by the allocating solver (arena null) and the solver in a
+// scratch region
+static lbm_status create_solver(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *pp,
+                                int require_percolation, void *arena, size_t cap, lbm_solver **out)
 {
     if (!ctx || !cls || !pp || !out)
         return set_err(ctx, LBM_EINVAL, "null argument");
@@ -684,6 +713,8 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
         return hip_err(ctx, he, "set device");
     lbm_solver *s = new lbm_solver();
     s->ctx = ctx;
+    s->arena = static_cast<char *>(arena);
+    s->arena_cap = arena ? cap : 0;
     s->grid = g;
     s->p = p;
     s->dim = g.nz > 1 ? 3 : 2;
@@ -753,20 +784,52 @@ lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
     s->d_out5 = static_cast<double *>(tmp);
     if ((st = upload_desc(s)))
         return fail(st);
-    he = hipHostMalloc((void **)&s->h_ctrl, RING * sizeof(lbmk::Ctrl), hipHostMallocDefault);
-    if (he != hipSuccess) {
-        s->h_ctrl = nullptr;
-        return fail(hip_err(ctx, he, "pinned control ring"));
-    }
-    for (int k = 0; k < RING; ++k)
-        if ((he = hipEventCreateWithFlags(&s->ev_ring[k], hipEventDisableTiming)) != hipSuccess)
+    if (s->arena) {
+        // no pinned memory and no events: control snapshots go to the host
+        // heap, read after a stream synchronisation
+        s->h_ctrl = new lbmk::Ctrl[RING];
+    } else {
+        he = hipHostMalloc((void **)&s->h_ctrl, RING * sizeof(lbmk::Ctrl), hipHostMallocDefault);
+        if (he != hipSuccess) {
+            s->h_ctrl = nullptr;
+            return fail(hip_err(ctx, he, "pinned control ring"));
+        }
+        for (int k = 0; k < RING; ++k)
+            if ((he = hipEventCreateWithFlags(&s->ev_ring[k], hipEventDisableTiming)) != hipSuccess)
+                return fail(hip_err(ctx, he, "event"));
+        if ((he = hipEventCreate(&s->ev_a)) != hipSuccess || (he = hipEventCreate(&s->ev_b)) != hipSuccess)
             return fail(hip_err(ctx, he, "event"));
-    if ((he = hipEventCreate(&s->ev_a)) != hipSuccess || (he = hipEventCreate(&s->ev_b)) != hipSuccess)
-        return fail(hip_err(ctx, he, "event"));
+    }
     if ((he = hipStreamSynchronize(ctx->stream)) != hipSuccess)
         return fail(hip_err(ctx, he, "create sync"));
     *out = s;
     return LBM_OK;
+}
+
+lbm_status lbmh::solver_create_in(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params &p,
+                                  void *arena, size_t cap, lbm_solver **out)
+{
+    if (!arena)
+        return set_err(ctx, LBM_EINVAL, "null scratch region");
+    return create_solver(ctx, g, cls, &p, 1, arena, cap, out);
+}
+
+lbm_status lbmh::export_u_device(lbm_solver *s, double *dst)
+{
+    if (!s->fluid_ready)
+        return set_err(s->ctx, LBM_EINVAL, "fluid state not initialised");
+    HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0), dst,
+                              nullptr, 1, s->ctx->stream),
+           "export");
+    return LBM_OK;
+}
+
+extern "C" {
+
+lbm_status lbm_solver_create_ex(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *pp,
+                                int require_percolation, lbm_solver **out)
+{
+    return create_solver(ctx, g, cls, pp, require_percolation, nullptr, 0, out);
 }
 
 void lbm_solver_destroy(lbm_solver *s)
@@ -779,11 +842,16 @@ void lbm_solver_destroy(lbm_solver *s)
                     s->d_u,    s->d_uprev,  s->d_cprev,  s->d_ctrl, s->d_part,
                     s->d_partials, s->d_out5, s->d_stage, s->d_idx, s->d_vals, s->d_ref,
                     s->d_desc_ad};
-    for (void *b : bufs)
-        if (b)
-            (void)hipFree(b);
-    if (s->h_ctrl)
-        (void)hipHostFree(s->h_ctrl);
+    if (!s->arena)
+        for (void *b : bufs)
+            if (b)
+                (void)hipFree(b);
+    if (s->h_ctrl) {
+        if (s->arena)
+            delete[] s->h_ctrl;
+        else
+            (void)hipHostFree(s->h_ctrl);
+    }
     for (int k = 0; k < RING; ++k)
         if (s->ev_ring[k])
             (void)hipEventDestroy(s->ev_ring[k]);
