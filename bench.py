@@ -241,7 +241,8 @@ def coupled_main(args):
         # storage: an independent loop would part at its first pick, a
         # discontinuous function of C
         p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
-                            storage=STORAGES[args.compare_storage], stall_checks=args.stall_checks)
+                            storage=STORAGES[args.compare_storage], stall_checks=args.stall_checks,
+                            check_every=args.compare_check_every or 100)
         s = lbm.lbm_solver_create(ctx, cls, p)
         mi = args.max_iter or w["max_iter"]
         J2, fail = [], None
@@ -263,6 +264,7 @@ def coupled_main(args):
         J2 = np.asarray(J2)
         rel = np.abs(J2 - J1) / np.abs(J1)
         res["compare"] = {"storage": args.compare_storage, "seconds": el2, "updates": k - 1,
+                          "check_every": args.compare_check_every or 100,
                           "first_failure": fail,
                           "J_accum": float(J2[1:].sum()),
                           "J_accum_rel_diff": float(abs(J2[1:].sum() - J1[1:].sum()) / abs(J1[1:].sum()))
@@ -340,7 +342,8 @@ def _serve_stream(lbm, ctx, reqs, storage, args, max_iter):
     import threading
 
     cfg = lbm.make_server_cfg(int(args.pool_gb * (1 << 30)), max_slots=args.slots, storage=storage,
-                              prep_threads=4, stall_checks=args.stall_checks)
+                              prep_threads=4, stall_checks=args.stall_checks,
+                              check_every=args.check_every or 100)
     srv = lbm.lbm_server_create(ctx, cfg)
 
     def request(r):
@@ -454,6 +457,7 @@ def served_main(args):
                                    "%g req/s, 2-D D2Q9+D2Q5, nx log-uniform 64..2048, ny = nx/2"
                                    % (len(reqs), rate),
                        "rate": rate, "storage": args.storage, "pool_gb": args.pool_gb,
+                       "check_every": args.check_every or 100,
                        "slots": args.slots, "seed": inputs.SERVE_SEED},
             "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
                        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
@@ -478,7 +482,7 @@ def served_main(args):
     # single FP32-shifted solves to tolerance (throughput), then at the served
     # step counts (equal work: field errors)
     single_s, single_upd, fail = 0.0, 0.0, 0
-    eq_s, eq_upd, eu, ec, n_ok = 0.0, 0.0, [], [], 0
+    eq_s, eq_upd, eu, ec, n_ok, detail = 0.0, 0.0, [], [], 0, []
     last = time.perf_counter()
     for d in done:
         if time.perf_counter() - last > 20:
@@ -500,6 +504,9 @@ def served_main(args):
         eu.append(float(np.linalg.norm(d["u"][:, fl] - U[:, fl]) / np.linalg.norm(U[:, fl])))
         ec.append(float(np.linalg.norm(d["c"][act] - C[act]) / np.linalg.norm(C[act])))
         n_ok += d["status"] == 0
+        detail.append({"user": int(d["user"]), "status": lbm.status_name(d["status"]),
+                       "porosity": round(r["porosity"], 3), "nx": r["nx"],
+                       "u": round(eu[-1], 6), "c": round(ec[-1], 6)})
     lbm.lbm_ctx_destroy(ctx)
     eu, ec = np.array(eu), np.array(ec)
     within = (eu < 5e-3) & (ec < 5e-3)
@@ -515,7 +522,9 @@ def served_main(args):
         "fields_vs_equal_steps": {"u_rel_l2_median": float(np.median(eu)), "u_rel_l2_max": float(eu.max()),
                                   "c_rel_l2_median": float(np.median(ec)), "c_rel_l2_max": float(ec.max()),
                                   "frac_within_5e-3": float(within.mean()),
-                                  "outside": [int(d["user"]) for d, ok in zip(done, within) if not ok]}}),
+                                  "frac_within_5e-3_of_ok": float(within[[d["status"] == 0 for d in done]].mean())
+                                  if n_ok else None,
+                                  "outside": [x for x, ok in zip(detail, within) if not ok]}}),
           flush=True)
 
 
@@ -532,6 +541,8 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="served arrivals per second")
     ap.add_argument("--rates", default="", help="served: comma-separated arrival rates (a sweep)")
     ap.add_argument("--no-single", action="store_true", help="served: skip the single-solve comparison")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="residual check interval of the solves or the server (0: 100)")
     ap.add_argument("--pool-gb", type=float, default=32.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,
@@ -542,6 +553,8 @@ def main():
                     help="model loop: biomass yield on the consumed substrate")
     ap.add_argument("--compare-storage", default="", choices=[""] + sorted(STORAGES),
                     help="coupled loop: repeat in this storage and compare")
+    ap.add_argument("--compare-check-every", type=int, default=0,
+                    help="coupled loop: residual check interval of the compared run (0: 100)")
     ap.add_argument("--ad-lattice", default="d2q5", choices=["d2q5", "d2q9"],
                     help="2-D substrate lattice: D2Q5 with the linear equilibrium, or the "
                          "paper's D2Q9 with the Eq. 5 equilibrium")
@@ -593,7 +606,7 @@ def main():
         sys.exit("--ad-lattice d2q9 is a 2-D option")
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
                         storage=storage, stall_checks=args.stall_checks, k_half=args.k_half,
-                        ad_lattice=int(ad9))
+                        ad_lattice=int(ad9), check_every=args.check_every or 100)
     s = lbm.lbm_solver_create(ctx, cls, p)
 
     def one_step():

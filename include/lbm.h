@@ -129,7 +129,10 @@ typedef struct {
     int32_t outlet;       /* lbm_ad_outlet */
     double c_out;         /* outlet value for LBM_OUT_DIRICHLET */
     int32_t storage;      /* lbm_storage */
-    int32_t check_every;  /* residual cadence K, even and >= 2 (100 if 0) */
+    int32_t check_every;  /* residual cadence K, even and >= 2.  0: 100, or 1000
+                             with FP16 storage, whose tile-mean residual carries
+                             stochastic-rounding noise that falls with K: at
+                             100 its floor sits above 1e-6 on most media */
     int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
                              1000 otherwise; < 0 disables */
     double k_half;        /* 0: first-order sink k_sink C per step on BIOFILM nodes.
@@ -257,8 +260,9 @@ void lbm_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
 /* ---------------------------------------------------- one-shot solves */
 /* Steady fluid flow (Sec. 2.1.1) from rest on the mask cls (host uint8 [N]),
  * run until the residual -- the largest velocity change per step over the
- * check interval K = 100, max |U(t) - U(t-K)| / (K |u_in|) over FLUID
- * nodes, evaluated at t = K, 2K, ... -- is <= tol, or max_iter steps.
+ * check interval K (100; 1000 with FP16 storage), max |U(t) - U(t-K)| /
+ * (K |u_in|) over FLUID nodes, evaluated at t = K, 2K, ... -- is <= tol, or
+ * max_iter steps.
  * With LBM_FP16_SHIFTED storage the per-node changes are replaced by their
  * means over 64 x 4-node tiles (per z-plane): stochastic rounding injects
  * zero-mean momentum noise that would otherwise set a residual floor above
@@ -550,16 +554,27 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *p, int n_hours, uin
  * is free and their device footprint (lbm_server_footprint) fits the pool;
  * every admitted request's populations stay resident and all of them are
  * stepped by the same kernel launches, each in its own phase, in chunks of
- * check_every steps captured once as a HIP graph (FP32 storage forms: four
- * steps per launch over 64 x 16 tiles; FP16: two over 64 x 4 tiles).  The
- * largest request the server takes is bounded by pool_bytes and by
- * 2^31 / (64 * tile height) tiles in flight.  A request's arithmetic
+ * check_every steps captured once as a HIP graph (two steps per launch
+ * over 64 x 4 tiles, every storage form).  The largest request the server
+ * takes is bounded by pool_bytes and by 2^31 / 256 tiles in flight.  A request's arithmetic
  * is that of lbm_solver_fluid followed by lbm_solver_ad (cold, same
  * storage, same check cadence and stall window): its results are bit-equal
  * to that single solve and do not depend on what else is in flight.
  * max_iter is rounded up to a multiple of check_every.  A fluid solve that
  * ends NOT_CONVERGED or STALLED still proceeds to the substrate solve; one
  * that diverges ends the request (c is then 0).
+ * Besides the batch the server runs a solo lane: one host thread that
+ * solves requests one at a time with a single-domain solver
+ * (lbm_solver_fluid, then lbm_solver_ad, cold) on a stream of its own,
+ * concurrently with the batch.  It takes (a) requests of at least
+ * solo_nodes nodes, which fill the GPU on their own and there run the
+ * single solver's wider multi-step launches, in the server's storage and
+ * cadence -- bit-equal to what the batch would return -- and (b) with
+ * escalate set and reduced storage (FP16 or unshifted FP32), every request
+ * whose batched solves did not both end OK: it is solved again from rest
+ * with FP32-shifted storage (cadence and stall window the lbm_params
+ * defaults), and that solve's result is returned, marked in `lane`, with
+ * the first attempt's status and step counts alongside.
  * All lbm_server_* calls are thread-safe. */
 typedef struct lbm_server lbm_server;
 
@@ -568,11 +583,15 @@ typedef struct {
     int32_t max_slots;     /* requests on the device at once, 1..64 (32 if 0) */
     int32_t storage;       /* LBM_FP32, LBM_FP32_SHIFTED or LBM_FP16_SHIFTED */
     int32_t check_every;   /* K: steps per chunk and residual cadence, a multiple of 4
-                              (100 if 0) */
+                              (if 0: 100, or 1000 with FP16 storage, as lbm_params) */
     int32_t stall_checks;  /* as lbm_params */
     int32_t inflight;      /* chunks enqueued ahead of the decisions, 1..6 (2 if 0) */
     int32_t prep_threads;  /* host threads that build masks, 1..16 (2 if 0) */
     int32_t direct_launch; /* 1: launch each chunk's kernels directly instead of the graph */
+    int32_t escalate;      /* 1: re-solve failed reduced-storage requests in FP32-shifted
+                              storage on the solo lane (see above) */
+    int64_t solo_nodes;    /* requests of at least this many nodes go to the solo lane
+                              (0: none); such requests need not fit the pool */
 } lbm_server_cfg;
 
 typedef struct {
@@ -604,14 +623,21 @@ typedef struct {
     const float *u;        /* [2][N] velocity, owned by the server until released */
     const float *c;        /* [N] concentration (0 on SOLID/WALL) */
     char message[96];      /* reason of a rejection */
+    int32_t lane;          /* LBM_LANE_BATCH, LBM_LANE_SOLO or LBM_LANE_ESCALATED */
+    int32_t first_status;  /* escalated: overall status of the batched attempt */
+    int64_t first_iters_fluid, first_iters_ad; /* escalated: its step counts */
 } lbm_result;
+
+enum { LBM_LANE_BATCH = 0, LBM_LANE_SOLO = 1, LBM_LANE_ESCALATED = 2 };
 
 typedef struct {
     int64_t submitted, finished, rejected, active, queued, chunks;
     uint64_t pool_bytes, pool_used, pool_peak;
     double lattice_updates; /* active-node updates of the finished requests */
-    double busy_seconds;    /* wall time with work on the device */
+    double busy_seconds;    /* wall time with work on the device (either lane) */
     double clock;           /* seconds since creation */
+    int64_t solo, escalated; /* finished requests solved on the solo lane, of which
+                                escalated */
 } lbm_server_stats_t;
 
 /* Device bytes one request of this size takes from the pool. */
@@ -620,7 +646,7 @@ size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage);
  * server has its own stream).  EINVAL on a bad configuration, ENOMEM. */
 lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server **out);
 /* Queue a request (copied).  EINVAL (see lbm_server_error) for bad
- * parameters or a request larger than the pool; mask problems found later
+ * parameters or a batch request larger than the pool; mask problems found later
  * (a geometry that cannot be built or does not percolate) come back as a
  * result with status EINVAL. */
 lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *ticket);

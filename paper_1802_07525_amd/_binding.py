@@ -23,6 +23,7 @@ LBM_FP32, LBM_FP32_SHIFTED, LBM_FP16_SHIFTED, LBM_FP64 = 0, 1, 2, 3
 LBM_FLUID, LBM_SOLID, LBM_WALL, LBM_BIOFILM = 0, 1, 2, 3
 LBM_OUT_ZERO_GRADIENT, LBM_OUT_DIRICHLET = 0, 1
 LBM_SOLVER_FLUID, LBM_SOLVER_AD = 0, 1
+LBM_LANE_BATCH, LBM_LANE_SOLO, LBM_LANE_ESCALATED = 0, 1, 2
 (LBM_FIELD_U, LBM_FIELD_RHO, LBM_FIELD_C, LBM_FIELD_CLASS, LBM_FIELD_LINKS_F, LBM_FIELD_LINKS_C,
  LBM_FIELD_F, LBM_FIELD_G, LBM_FIELD_U_DEVICE, LBM_FIELD_DESC) = range(10)
 
@@ -65,7 +66,8 @@ class lbm_server_cfg(ct.Structure):
     _fields_ = [("pool_bytes", ct.c_size_t), ("max_slots", ct.c_int32), ("storage", ct.c_int32),
                 ("check_every", ct.c_int32), ("stall_checks", ct.c_int32),
                 ("inflight", ct.c_int32),
-                ("prep_threads", ct.c_int32), ("direct_launch", ct.c_int32)]
+                ("prep_threads", ct.c_int32), ("direct_launch", ct.c_int32),
+                ("escalate", ct.c_int32), ("solo_nodes", ct.c_int64)]
 
 
 class lbm_request(ct.Structure):
@@ -85,7 +87,9 @@ class lbm_result(ct.Structure):
                 ("flux", ct.c_double * 5), ("active_fluid", ct.c_int64),
                 ("active_ad", ct.c_int64), ("t_submit", ct.c_double), ("t_admit", ct.c_double),
                 ("t_finish", ct.c_double), ("u", ct.POINTER(ct.c_float)),
-                ("c", ct.POINTER(ct.c_float)), ("message", ct.c_char * 96)]
+                ("c", ct.POINTER(ct.c_float)), ("message", ct.c_char * 96),
+                ("lane", ct.c_int32), ("first_status", ct.c_int32),
+                ("first_iters_fluid", ct.c_int64), ("first_iters_ad", ct.c_int64)]
 
 
 class lbm_server_stats_t(ct.Structure):
@@ -93,7 +97,8 @@ class lbm_server_stats_t(ct.Structure):
                 ("active", ct.c_int64), ("queued", ct.c_int64), ("chunks", ct.c_int64),
                 ("pool_bytes", ct.c_uint64), ("pool_used", ct.c_uint64),
                 ("pool_peak", ct.c_uint64), ("lattice_updates", ct.c_double),
-                ("busy_seconds", ct.c_double), ("clock", ct.c_double)]
+                ("busy_seconds", ct.c_double), ("clock", ct.c_double),
+                ("solo", ct.c_int64), ("escalated", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -412,7 +417,7 @@ def lbm_copy_bandwidth(ctx, nbytes, reps=20):
 
 # --------------------------------------------------------------- solver
 def make_params(tau=0.8, u_in=0.01, D=0.1, c_in=1.0, k_sink=0.0, outlet=LBM_OUT_ZERO_GRADIENT,
-                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=100, stall_checks=0, k_half=0.0,
+                c_out=0.0, storage=LBM_FP32_SHIFTED, check_every=0, stall_checks=0, k_half=0.0,
                 ad_lattice=0):
     return lbm_params(float(tau), float(u_in), float(D), float(c_in), float(k_sink), int(outlet),
                       float(c_out), int(storage), int(check_every), int(stall_checks), float(k_half),
@@ -670,11 +675,12 @@ def lbm_server_footprint(nx, ny, storage):
     return int(load().lbm_server_footprint(int(nx), int(ny), int(storage)))
 
 
-def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_every=100,
-                    stall_checks=0, inflight=0, prep_threads=0, direct_launch=0):
+def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_every=0,
+                    stall_checks=0, inflight=0, prep_threads=0, direct_launch=0, escalate=0,
+                    solo_nodes=0):
     return lbm_server_cfg(int(pool_bytes), int(max_slots), int(storage), int(check_every),
                           int(stall_checks), int(inflight), int(prep_threads),
-                          int(direct_launch))
+                          int(direct_launch), int(escalate), int(solo_nodes))
 
 
 def make_request(nx, ny, cls=None, r_min=3, r_max=6, solid_frac=0.3, overlap=1, seed=0, layer=0,

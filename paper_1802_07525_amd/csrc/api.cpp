@@ -108,7 +108,7 @@ lbm_status lbm_fluid_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, double
     p.D = 1.0 / 6.0; // unused by a fluid solve
     p.c_in = 1.0;
     p.storage = storage;
-    p.check_every = 100;
+    p.check_every = 0; // the library default for the storage
     lbm_solver *s = nullptr;
     lbm_status st = lbm_solver_create(ctx, g, cls, &p, &s);
     if (st)
@@ -139,7 +139,7 @@ lbm_status lbm_ad_steady(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const dou
     p.outlet = outlet;
     p.c_out = c_out;
     p.storage = storage;
-    p.check_every = 100;
+    p.check_every = 0; // the library default for the storage
     lbm_solver *s = nullptr;
     lbm_status st = lbm_solver_create_ex(ctx, g, cls, &p, 0, &s);
     if (st)
@@ -185,7 +185,7 @@ lbm_status lbm_fluid_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, do
     p.D = 1.0 / 6.0; // unused by a fluid solve
     p.c_in = 1.0;
     p.storage = storage;
-    p.check_every = 100;
+    p.check_every = 0; // the library default for the storage
     lbm_solver *s = nullptr;
     if ((st = lbm_solver_create(ctx, g, mask.data(), &p, &s)))
         return st;
@@ -220,7 +220,7 @@ lbm_status lbm_ad_steady_dev(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const
     p.outlet = outlet;
     p.c_out = c_out;
     p.storage = storage;
-    p.check_every = 100;
+    p.check_every = 0; // the library default for the storage
     lbm_solver *s = nullptr;
     if ((st = lbm_solver_create_ex(ctx, g, mask.data(), &p, 0, &s)))
         return st;

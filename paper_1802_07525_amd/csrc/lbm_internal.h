@@ -91,6 +91,10 @@ lbm_status solver_create_in(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const 
                             size_t cap, lbm_solver **out);
 // velocity (double [dim][N], device) of the fluid state, on the stream
 lbm_status export_u_device(lbm_solver *s, double *dst);
+// Velocity (which 0, [dim][N]) or concentration (which 1, [N]) exported in
+// FP32 -- the values the served form returns -- into host memory dst.
+// Storage FP32, FP32-shifted or FP16 only; synchronises the stream.
+lbm_status export_f32(lbm_solver *s, int which, float *dst);
 
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);

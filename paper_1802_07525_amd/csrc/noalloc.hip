@@ -86,7 +86,7 @@ lbm_status lbm_fluid_steady_dev_noalloc(lbm_ctx *ctx, lbm_grid g, const uint8_t 
     p.D = 1.0 / 6.0; // unused by a fluid solve
     p.c_in = 1.0;
     p.storage = storage;
-    p.check_every = 100;
+    p.check_every = 0; // the library default for the storage
     lbm_solver *s = nullptr;
     if ((st = solver_create_in(ctx, g, mask.data(), p, arena, LBM_NOALLOC_SCRATCH_BYTES, &s)))
         return st;

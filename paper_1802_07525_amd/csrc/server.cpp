@@ -31,6 +31,13 @@
 // A request's arithmetic is that of a single solve with the same storage:
 // the same per-tile code, the same step counters, the same check steps.
 // Its results are therefore the same alone and in any mix, bit for bit.
+//
+// A solo lane -- one more host thread with a context and stream of its own
+// -- runs whole requests through the single-domain solver next to the
+// batch: requests large enough to fill the GPU alone (the single solver's
+// wider multi-step launches serve them faster than the batch's two-step
+// tiles), and, when escalation is on, reduced-storage requests whose
+// batched solves did not both end OK, solved again in FP32-shifted storage.
 #include <math.h>
 #include <string.h>
 
@@ -278,6 +285,9 @@ struct Job {
     char *staged = nullptr; // pinned result staging
     std::vector<float> u, c;
     double flux[10] = {0};
+    int lane = LBM_LANE_BATCH;
+    int first_status = LBM_OK;
+    int64_t first_it_fluid = 0, first_it_ad = 0;
 };
 
 int stop_status(int stop)
@@ -394,6 +404,16 @@ struct lbm_server {
     std::vector<std::thread> preps;
     std::thread worker;
 
+    // solo lane (mutex for the queue and counters)
+    lbm_ctx *solo_ctx = nullptr;
+    std::deque<Job *> solo_q;
+    std::condition_variable cv_solo;
+    std::thread solo;
+    int64_t n_solo = 0, n_escalated = 0;
+    Job *solo_cur = nullptr; // the request the solo lane is solving
+    int lanes_busy = 0;
+    std::chrono::steady_clock::time_point lanes_since{};
+
     // ------------------------------------------------------------- prep
     void prep_loop()
     {
@@ -413,6 +433,9 @@ struct lbm_server {
                 continue; // already finished by fail(), or abandoned
             if (j->status != LBM_OK) {
                 finish_locked(j);
+            } else if (j->lane == LBM_LANE_SOLO) {
+                solo_q.push_back(j);
+                cv_solo.notify_all();
             } else {
                 ready[j->ticket] = j;
                 cv_work.notify_all();
@@ -449,6 +472,9 @@ struct lbm_server {
             j->msg = m;
             return;
         }
+        j->geo = lbmk::make_geo(r.nx, r.ny, 1);
+        if (j->lane == LBM_LANE_SOLO)
+            return; // the single solver builds its own descriptors
         std::vector<uint32_t> d((size_t)N);
         build_desc(g, j->cls.data(), dom, reference_nodes(g, dom), d.data());
         j->desc.resize((size_t)N);
@@ -458,11 +484,14 @@ struct lbm_server {
             j->n_fluid += d[n] & 1u;
             j->n_ad += (d[n] >> aab) & 1u;
         }
-        j->geo = lbmk::make_geo(r.nx, r.ny, 1);
         j->tiles = lbmk::pair_tiles(j->geo, lbmk::srv_tile_ty(cfg.storage));
-        j->cls.clear();
-        j->cls.shrink_to_fit();
+        if (!may_escalate()) {
+            j->cls.clear();
+            j->cls.shrink_to_fit();
+        }
     }
+
+    bool may_escalate() const { return cfg.escalate && cfg.storage != LBM_FP32_SHIFTED; }
 
     // caller holds mu
     void finish_locked(Job *j)
@@ -473,6 +502,10 @@ struct lbm_server {
             updates += (double)j->it_fluid * j->n_fluid + (double)j->it_ad * j->n_ad;
         else
             ++n_rejected;
+        if (j->lane != LBM_LANE_BATCH && j->status != LBM_EDEVICE) {
+            ++n_solo;
+            n_escalated += j->lane == LBM_LANE_ESCALATED;
+        }
         ++n_finished;
         finished.push_back(j);
         cv_done.notify_all();
@@ -657,6 +690,22 @@ struct lbm_server {
         --n_retiring;
         std::lock_guard<std::mutex> lk(mu);
         --n_active;
+        const int st = overall_status(j->st_fluid, j->ad_ran ? j->st_ad : j->st_fluid);
+        if (may_escalate() && st != LBM_OK && !stopping && !failed) {
+            // the batched attempt's work counts; its fields are dropped
+            updates += (double)j->it_fluid * j->n_fluid + (double)j->it_ad * j->n_ad;
+            j->first_status = st;
+            j->first_it_fluid = j->it_fluid;
+            j->first_it_ad = j->it_ad;
+            j->lane = LBM_LANE_ESCALATED;
+            j->u.clear();
+            j->c.clear();
+            solo_q.push_back(j);
+            cv_solo.notify_all();
+            return;
+        }
+        j->cls.clear();
+        j->cls.shrink_to_fit();
         finish_locked(j);
     }
 
@@ -846,12 +895,23 @@ struct lbm_server {
         return hipSuccess;
     }
 
-    std::chrono::steady_clock::time_point busy_since{};
+    // Busy time is the union of the lanes' busy intervals.
     bool was_busy = false;
+    void lane_enter_locked(std::chrono::steady_clock::time_point t)
+    {
+        if (lanes_busy++ == 0)
+            lanes_since = t;
+    }
+    void lane_leave_locked()
+    {
+        if (--lanes_busy == 0)
+            busy += std::chrono::duration<double>(std::chrono::steady_clock::now() - lanes_since).count();
+    }
     void busy_mark(std::chrono::steady_clock::time_point t)
     {
         if (!was_busy) {
-            busy_since = t;
+            std::lock_guard<std::mutex> lk(mu);
+            lane_enter_locked(t);
             was_busy = true;
         }
     }
@@ -859,9 +919,112 @@ struct lbm_server {
     {
         if (was_busy) {
             std::lock_guard<std::mutex> lk(mu);
-            busy += std::chrono::duration<double>(std::chrono::steady_clock::now() - busy_since).count();
+            lane_leave_locked();
             was_busy = false;
         }
+    }
+
+    // ------------------------------------------------------- solo lane
+    void solo_loop()
+    {
+        for (;;) {
+            Job *j;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_solo.wait(lk, [&] { return stopping || !solo_q.empty(); });
+                if (stopping)
+                    return;
+                j = solo_q.front();
+                solo_q.pop_front();
+                solo_cur = j;
+                lane_enter_locked(std::chrono::steady_clock::now());
+                if (j->t_admit == 0)
+                    j->t_admit = now_s(t0);
+            }
+            solve_alone(j);
+            std::lock_guard<std::mutex> lk(mu);
+            lane_leave_locked();
+            solo_cur = nullptr;
+            finish_locked(j);
+        }
+    }
+
+    // The request's two solves by the single-domain solver: the server's
+    // storage and cadence on the solo lane proper, FP32-shifted storage with
+    // the default cadence and stall window when escalated.
+    void solve_alone(Job *j)
+    {
+        const lbm_request &r = j->req;
+        const bool esc = j->lane == LBM_LANE_ESCALATED;
+        lbm_params p{};
+        p.tau = r.tau;
+        p.u_in = r.u_in;
+        p.D = r.D;
+        p.c_in = r.c_in;
+        p.k_sink = r.k_sink;
+        p.k_half = r.k_half;
+        p.outlet = r.outlet;
+        p.c_out = r.c_out;
+        p.storage = esc ? LBM_FP32_SHIFTED : cfg.storage;
+        p.check_every = esc ? 0 : K;
+        p.stall_checks = esc ? 0 : cfg.stall_checks;
+        const int64_t Ks = esc ? 100 : K;
+        const int64_t max_iter = (r.max_iter + Ks - 1) / Ks * Ks;
+        const lbm_grid g{r.nx, r.ny, 1};
+        const int64_t N = (int64_t)r.nx * r.ny;
+        j->st_fluid = j->st_ad = LBM_OK;
+        j->it_fluid = j->it_ad = 0;
+        j->r_fluid = j->r_ad = NAN;
+        j->ad_ran = false;
+        std::fill(j->flux, j->flux + 10, 0.0);
+        lbm_solver *sv = nullptr;
+        lbm_status st = lbm_solver_create(solo_ctx, g, j->cls.data(), &p, &sv);
+        j->cls.clear();
+        j->cls.shrink_to_fit();
+        auto fail_job = [&](lbm_status e) {
+            j->status = e;
+            j->msg = lbm_last_error(solo_ctx);
+            if (sv)
+                lbm_solver_destroy(sv);
+        };
+        if (st != LBM_OK)
+            return fail_job(st);
+        auto solve_status = [](lbm_status e) {
+            return e == LBM_OK || e == LBM_STALLED || e == LBM_NOT_CONVERGED || e == LBM_EDIVERGED;
+        };
+        lbm_info fi{}, ai{};
+        st = lbm_solver_fluid(sv, r.tol, max_iter, 0, &fi);
+        if (!solve_status(st))
+            return fail_job(st);
+        j->st_fluid = st;
+        j->it_fluid = fi.iters;
+        j->r_fluid = fi.checks > 0 ? fi.residual : NAN;
+        j->n_fluid = fi.active_nodes;
+        // the FP32 exports, as the batch returns them
+        std::vector<double> out5(5, 0.0);
+        j->u.assign((size_t)N * 2, 0.0f);
+        j->c.assign((size_t)N, 0.0f);
+        lbm_status e;
+        if ((e = export_f32(sv, 0, j->u.data())) != LBM_OK || (e = lbm_solver_fluxes(sv, out5.data())) != LBM_OK)
+            return fail_job(e);
+        j->flux[0] = out5[0];
+        j->flux[1] = out5[1];
+        if (st != LBM_EDIVERGED) {
+            st = lbm_solver_ad(sv, r.tol, max_iter, 0, &ai);
+            if (!solve_status(st))
+                return fail_job(st);
+            j->st_ad = st;
+            j->it_ad = ai.iters;
+            j->r_ad = ai.checks > 0 ? ai.residual : NAN;
+            j->n_ad = ai.active_nodes;
+            j->ad_ran = true;
+            if ((e = export_f32(sv, 1, j->c.data())) != LBM_OK || (e = lbm_solver_fluxes(sv, out5.data())) != LBM_OK)
+                return fail_job(e);
+            j->flux[7] = out5[2];
+            j->flux[8] = out5[3];
+            j->flux[9] = out5[4];
+        }
+        lbm_solver_destroy(sv);
     }
 
     void work_loop()
@@ -899,8 +1062,8 @@ struct lbm_server {
         err = m;
         for (auto &kv : all) {
             Job *j = kv.second.get();
-            if (j->phase == PH_DONE)
-                continue;
+            if (j->phase == PH_DONE || j == solo_cur)
+                continue; // the solo lane finishes its current request itself
             j->status = LBM_EDEVICE;
             j->msg = m;
             j->phase = PH_DONE;
@@ -910,6 +1073,7 @@ struct lbm_server {
         }
         prep_q.clear();
         ready.clear();
+        solo_q.clear();
         cv_done.notify_all();
     }
 
@@ -944,6 +1108,10 @@ struct lbm_server {
         o->t_finish = j->t_finish;
         o->u = j->u.empty() ? nullptr : j->u.data();
         o->c = j->c.empty() ? nullptr : j->c.data();
+        o->lane = j->lane;
+        o->first_status = j->first_status;
+        o->first_iters_fluid = j->first_it_fluid;
+        o->first_iters_ad = j->first_it_ad;
     }
 };
 
@@ -969,7 +1137,7 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     if (c.max_slots < 1 || c.max_slots > lbmk::SRV_MAX_SLOTS)
         return set_err(ctx, LBM_EINVAL, "max_slots must be in 1..64");
     if (c.check_every == 0)
-        c.check_every = 100;
+        c.check_every = c.storage == LBM_FP16_SHIFTED ? 1000 : 100; // as lbm_params
     if (c.check_every < 4 || (c.check_every % 4) || c.check_every > 1000)
         return set_err(ctx, LBM_EINVAL, "check_every must be a multiple of 4 in 4..1000");
     if (c.inflight == 0)
@@ -982,6 +1150,10 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         return set_err(ctx, LBM_EINVAL, "prep_threads must be in 1..16");
     if (c.pool_bytes < (size_t)1 << 16)
         return set_err(ctx, LBM_EINVAL, "pool_bytes must be at least 64 KiB");
+    if (c.escalate != 0 && c.escalate != 1)
+        return set_err(ctx, LBM_EINVAL, "escalate must be 0 or 1");
+    if (c.solo_nodes < 0)
+        return set_err(ctx, LBM_EINVAL, "solo_nodes must be >= 0");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return hip_err(ctx, e, "set device");
@@ -1015,6 +1187,8 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     };
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return cleanup(hip_err(ctx, e, "server stream"));
+    if (lbm_ctx_create(ctx->device, nullptr, &s->solo_ctx) != LBM_OK)
+        return cleanup(set_err(ctx, LBM_EDEVICE, "solo lane context"));
     if (dmalloc((void **)&s->pool, c.pool_bytes) != hipSuccess)
         return cleanup(set_err(ctx, LBM_ENOMEM, "device pool allocation failed"));
     if (dmalloc((void **)&s->d_slots, sizeof(lbmk::SrvSlot) * lbmk::SRV_MAX_SLOTS) != hipSuccess ||
@@ -1073,6 +1247,7 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     for (int k = 0; k < c.prep_threads; ++k)
         s->preps.emplace_back([sp] { sp->prep_loop(); });
     s->worker = std::thread([sp] { sp->work_loop(); });
+    s->solo = std::thread([sp] { sp->solo_loop(); });
     *out = s.release();
     return LBM_OK;
 }
@@ -1088,10 +1263,13 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
     std::string m = request_problem(*r);
     if (m.empty()) {
         j->lay = layout_of(r->nx, N, s->cfg.storage);
-        if (j->lay.total > s->cfg.pool_bytes ||
-            lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), lbmk::srv_tile_ty(s->cfg.storage)) > s->part_cap)
+        if (s->cfg.solo_nodes > 0 && N >= s->cfg.solo_nodes)
+            j->lane = LBM_LANE_SOLO;
+        else if (j->lay.total > s->cfg.pool_bytes ||
+                 lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), lbmk::srv_tile_ty(s->cfg.storage)) >
+                     s->part_cap)
             m = "request larger than the server pool";
-        else if (r->cls)
+        if (m.empty() && r->cls)
             j->cls.assign(r->cls, r->cls + N);
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -1176,14 +1354,19 @@ lbm_status lbm_server_stats(lbm_server *s, lbm_server_stats_t *o)
     o->finished = s->n_finished;
     o->rejected = s->n_rejected;
     o->active = s->n_active;
-    o->queued = (int64_t)(s->prep_q.size() + s->ready.size());
+    o->queued = (int64_t)(s->prep_q.size() + s->ready.size() + s->solo_q.size());
     o->chunks = s->chunks;
     o->pool_bytes = s->cfg.pool_bytes;
     o->pool_used = s->alloc.used;
     o->pool_peak = s->alloc.peak;
     o->lattice_updates = s->updates;
     o->busy_seconds = s->busy;
+    if (s->lanes_busy > 0)
+        o->busy_seconds +=
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - s->lanes_since).count();
     o->clock = now_s(s->t0);
+    o->solo = s->n_solo;
+    o->escalated = s->n_escalated;
     return LBM_OK;
 }
 
@@ -1207,11 +1390,16 @@ void lbm_server_destroy(lbm_server *s)
     }
     s->cv_prep.notify_all();
     s->cv_work.notify_all();
+    s->cv_solo.notify_all();
     for (auto &t : s->preps)
         if (t.joinable())
             t.join();
     if (s->worker.joinable())
         s->worker.join();
+    if (s->solo.joinable())
+        s->solo.join();
+    if (s->solo_ctx)
+        lbm_ctx_destroy(s->solo_ctx);
     if (s->stream)
         (void)hipStreamSynchronize(s->stream);
     s->res_ring.reclaim = nullptr;

@@ -699,8 +699,11 @@ static lbm_status create_solver(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, co
     if (N64 > ((int64_t)1 << 31) / 19)
         return set_err(ctx, LBM_EINVAL, "grid too large");
     lbm_params p = *pp;
+    // default check interval: 100 steps, or 1000 with FP16 storage, whose
+    // residual (tile means) carries stochastic-rounding noise that falls
+    // with the interval (see lbm.h)
     if (p.check_every == 0)
-        p.check_every = 100;
+        p.check_every = p.storage == LBM_FP16_SHIFTED ? 1000 : 100;
     lbm_status st = validate_params(ctx, p);
     if (st)
         return st;
@@ -821,6 +824,32 @@ lbm_status lbmh::export_u_device(lbm_solver *s, double *dst)
     HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0), dst,
                               nullptr, 1, s->ctx->stream),
            "export");
+    return LBM_OK;
+}
+
+lbm_status lbmh::export_f32(lbm_solver *s, int which, float *dst)
+{
+    if (s->p.storage == LBM_FP64)
+        return set_err(s->ctx, LBM_EINVAL, "FP32 export of an FP64 solver");
+    if (!(which == 0 ? s->fluid_ready : s->ad_ready))
+        return set_err(s->ctx, LBM_EINVAL, "state not initialised");
+    const size_t N = (size_t)s->geo.N;
+    const size_t bytes = (which == 0 ? (size_t)s->dim : 1) * N * 4;
+    lbm_status e;
+    if ((e = ensure_stage(s, bytes)))
+        return e;
+    hipStream_t st = s->ctx->stream;
+    float *stage = reinterpret_cast<float *>(s->d_stage);
+    if (which == 0)
+        HIPCHK(lbmk::fluid_export(s->dim, s->p.storage, s->d_f[s->fcur], s->d_desc, s->geo, ref_cur(s, 0), stage,
+                                  nullptr, 0, st),
+               "export");
+    else
+        HIPCHK(lbmk::ad_export(ad_lay(s), s->p.storage, s->d_g[s->gcur], ad_desc(s), s->geo, ref_cur(s, 1),
+                               lbmk::Sink{s->p.k_sink, s->p.k_half}, stage, 0, st),
+               "export");
+    HIPCHK(hipMemcpyAsync(dst, stage, bytes, hipMemcpyDeviceToHost, st), "copy");
+    HIPCHK(hipStreamSynchronize(st), "sync");
     return LBM_OK;
 }
 

@@ -12,7 +12,10 @@ What is checked, through the C ABI:
   * FP16-storage served results stay within 5e-3 relative L2 of the plain
     FP32 single solve run for the same numbers of steps;
   * rejections (bad parameters, a pool too small, a medium that does not
-    percolate) and max_iter endings.
+    percolate) and max_iter endings;
+  * the solo lane: a request routed to the single-domain solver returns
+    what the batch returns, bit for bit; an escalated request returns the
+    FP32-shifted single solve, with the batched attempt's status and counts.
 """
 import numpy as np
 import pytest
@@ -80,7 +83,7 @@ def _serve(lbm, ctx, specs, storage, pool=None, slots=8, order=None, **cfgkw):
     return res, stats, need
 
 
-def _single(lbm, ctx, spec, storage, tol=1e-6, max_iter=400000, check_every=100):
+def _single(lbm, ctx, spec, storage, tol=1e-6, max_iter=400000, check_every=0):
     nx, ny, solid, tau, u_in, seed = spec
     cls = _mask(lbm, nx, ny, solid, seed)
     p = lbm.make_params(tau=tau, u_in=u_in, D=D_SUB, c_in=1.0, k_sink=K_SINK, storage=storage,
@@ -273,7 +276,7 @@ def test_server_matches_wide_single_solve(srv_env, spec, storage):
     counts and the FP64 fluxes of the final states."""
     lbm, ctx = srv_env
     need = lbm.lbm_server_footprint(spec[0], spec[1], storage)
-    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=storage)
+    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=storage, check_every=100)
     srv = lbm.lbm_server_create(ctx, cfg)
     print("server vs single solve %dx%d storage %d" % (spec[0], spec[1], storage), flush=True)
     try:
@@ -283,9 +286,74 @@ def test_server_matches_wide_single_solve(srv_env, spec, storage):
         r = lbm.lbm_server_poll(srv, 1, 1.0)[0]
     finally:
         lbm.lbm_server_destroy(srv)
-    s = _single(lbm, ctx, spec, storage, max_iter=400)
+    s = _single(lbm, ctx, spec, storage, max_iter=400, check_every=100)
     assert r["status_fluid"] == s["sf"] == lbm.LBM_NOT_CONVERGED
     assert r["iters_fluid"] == s["fi"]["iters"] == 400 and r["iters_ad"] == s["ai"]["iters"] == 400
     assert r["flux"][0] == s["fi"]["flux_in"] and r["flux"][1] == s["fi"]["flux_out"]
     assert r["flux"][2] == s["ai"]["flux_in"] and r["flux"][3] == s["ai"]["flux_out"]
     assert r["flux"][4] == s["ai"]["sink_total"]
+
+
+@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=["fp32s", "fp16s"])
+def test_solo_lane_equals_batch(srv_env, storage):
+    """A request of at least solo_nodes nodes is solved by the single-domain
+    solver on the solo lane (wider multi-step launches, its own stream, next
+    to the batch): statuses, counts, fluxes and the FP32 fields equal the
+    batch's bit for bit."""
+    lbm, ctx = srv_env
+    specs = [MIX[0], MIX[3]]  # 2,048 and 8,192 nodes
+    print("solo lane vs batch, storage", storage, flush=True)
+    batch, bstats, _ = _serve(lbm, ctx, specs, storage)
+    solo, sstats, _ = _serve(lbm, ctx, specs, storage, solo_nodes=4096)
+    assert bstats["solo"] == 0 and sstats["solo"] == 1 and sstats["escalated"] == 0
+    assert [batch[i]["lane"] for i in (0, 1)] == [lbm.LBM_LANE_BATCH] * 2
+    assert [solo[i]["lane"] for i in (0, 1)] == [lbm.LBM_LANE_BATCH, lbm.LBM_LANE_SOLO]
+    for i in (0, 1):
+        a, b = batch[i], solo[i]
+        for k in ("status", "status_fluid", "status_ad", "iters_fluid", "iters_ad", "active_fluid",
+                  "active_ad"):
+            assert a[k] == b[k], (i, k, a[k], b[k])
+        assert np.array_equal(a["flux"], b["flux"])
+        assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["c"], b["c"])
+        assert b["t_submit"] <= b["t_admit"] <= b["t_finish"]
+
+
+def test_escalation_resolves_in_fp32_shifted(srv_env):
+    """FP16 server with escalation: a request whose batched solves end
+    NOT_CONVERGED (max_iter 200) is solved again from rest in FP32-shifted
+    storage -- the result is that single solve's, marked escalated, with the
+    batched attempt's status and step counts; a request that ends OK stays
+    a batch result."""
+    lbm, ctx = srv_env
+    a_spec, b_spec = MIX[0], MIX[2]
+    need = sum(lbm.lbm_server_footprint(s[0], s[1], FP16S) for s in (a_spec, b_spec))
+    cfg = lbm.make_server_cfg(4 * need, max_slots=4, storage=FP16S, check_every=100, escalate=1)
+    srv = lbm.lbm_server_create(ctx, cfg)
+    print("escalation", flush=True)
+    try:
+        st, ta = lbm.lbm_server_submit(srv, _request(lbm, a_spec, max_iter=200))
+        assert st == 0
+        st, tb = lbm.lbm_server_submit(srv, _request(lbm, b_spec, tol=1e-3))
+        assert st == 0
+        assert lbm.lbm_server_drain(srv, 120.0) == 0
+        got = {r["ticket"]: r for r in lbm.lbm_server_poll(srv, 4, 1.0)}
+        stats = lbm.lbm_server_stats(srv)
+    finally:
+        lbm.lbm_server_destroy(srv)
+    assert stats["finished"] == 2 and stats["solo"] == 1 and stats["escalated"] == 1
+    ra, rb = got[ta], got[tb]
+    assert ra["lane"] == lbm.LBM_LANE_ESCALATED
+    assert ra["first_status"] == lbm.LBM_NOT_CONVERGED
+    assert ra["first_iters_fluid"] == 200 and ra["first_iters_ad"] == 200
+    s = _single(lbm, ctx, a_spec, FP32S, max_iter=200)
+    assert ra["status_fluid"] == s["sf"] == lbm.LBM_NOT_CONVERGED
+    assert ra["iters_fluid"] == s["fi"]["iters"] == 200 and ra["iters_ad"] == s["ai"]["iters"] == 200
+    assert ra["flux"][0] == s["fi"]["flux_in"] and ra["flux"][1] == s["fi"]["flux_out"]
+    assert ra["flux"][2] == s["ai"]["flux_in"] and ra["flux"][4] == s["ai"]["sink_total"]
+    assert np.abs(ra["u"] - s["U"]).max() <= 1e-6 * max(np.abs(s["U"]).max(), 1e-30)
+    assert np.abs(ra["c"] - s["C"]).max() <= 1e-6
+    assert rb["lane"] == lbm.LBM_LANE_BATCH and rb["status"] == lbm.LBM_OK
+    assert rb["first_status"] == 0 and rb["first_iters_fluid"] == 0
+    s = _single(lbm, ctx, b_spec, FP16S, tol=1e-3, check_every=100)
+    assert rb["iters_fluid"] == s["fi"]["iters"] and rb["iters_ad"] == s["ai"]["iters"]
+    assert rb["flux"][0] == s["fi"]["flux_in"] and rb["flux"][4] == s["ai"]["sink_total"]
