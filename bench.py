@@ -22,6 +22,7 @@ solves of the same requests, run one at a time on the same GPU.
 """
 import argparse
 import hashlib
+import collections
 import json
 import os
 import re
@@ -33,8 +34,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % HBM peak (fluid+AD LBM); served p50/p99 steady-solve latency"
 HBM_PEAK_GBS = 8000.0
-STORAGES = {"fp32": 0, "fp32s": 1, "fp16s": 2, "fp64": 3}
-DTYPES = {"fp32": "f32", "fp32s": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64"}
+STORAGES = {"fp32": 0, "fp32s": 1, "fp16s": 2, "fp64": 3, "fp32s-f64": 4}
+DTYPES = {"fp32": "f32", "fp32s": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64",
+          "fp32s-f64": "f64 (f32 storage)"}
 # the step kernels' sources and compiler flags: counters taken for other
 # code are not reported
 KERNEL_SRC = (os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "kernels.hip"),
@@ -76,6 +78,11 @@ def traffic_for(kernel, workload, storage):
         return None
     # HBM-side bytes per lattice step of the kernel's launches
     return rec.get("hbm_bytes_per_launch") / rec.get("steps_per_launch", 1)
+
+
+def default_k(storage_name):
+    """The library's residual check interval for a storage form."""
+    return 1000 if storage_name == "fp16s" else 100
 
 
 def _omp():
@@ -242,7 +249,7 @@ def coupled_main(args):
         # discontinuous function of C
         p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
                             storage=STORAGES[args.compare_storage], stall_checks=args.stall_checks,
-                            check_every=args.compare_check_every or 100)
+                            check_every=args.compare_check_every)
         s = lbm.lbm_solver_create(ctx, cls, p)
         mi = args.max_iter or w["max_iter"]
         J2, fail = [], None
@@ -264,7 +271,7 @@ def coupled_main(args):
         J2 = np.asarray(J2)
         rel = np.abs(J2 - J1) / np.abs(J1)
         res["compare"] = {"storage": args.compare_storage, "seconds": el2, "updates": k - 1,
-                          "check_every": args.compare_check_every or 100,
+                          "check_every": args.compare_check_every or default_k(args.compare_storage),
                           "first_failure": fail,
                           "J_accum": float(J2[1:].sum()),
                           "J_accum_rel_diff": float(abs(J2[1:].sum() - J1[1:].sum()) / abs(J1[1:].sum()))
@@ -343,7 +350,8 @@ def _serve_stream(lbm, ctx, reqs, storage, args, max_iter):
 
     cfg = lbm.make_server_cfg(int(args.pool_gb * (1 << 30)), max_slots=args.slots, storage=storage,
                               prep_threads=4, stall_checks=args.stall_checks,
-                              check_every=args.check_every or 100)
+                              check_every=args.check_every, escalate=int(args.escalate),
+                              solo_nodes=args.solo_nodes, solo_lanes=args.solo_lanes)
     srv = lbm.lbm_server_create(ctx, cfg)
 
     def request(r):
@@ -434,7 +442,7 @@ def served_main(args):
     max_iter = args.max_iter or 2_000_000
     rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
     ctx = lbm.lbm_ctx_create(0)
-    sb = {0: 4, 1: 4, 2: 2}[storage]
+    sb = {0: 4, 1: 4, 2: 2, 4: 4}[storage]
     last_results = None
     for rate in rates:
         reqs = inputs.serve_requests(args.requests, rate)
@@ -457,20 +465,31 @@ def served_main(args):
                                    "%g req/s, 2-D D2Q9+D2Q5, nx log-uniform 64..2048, ny = nx/2"
                                    % (len(reqs), rate),
                        "rate": rate, "storage": args.storage, "pool_gb": args.pool_gb,
-                       "check_every": args.check_every or 100,
-                       "slots": args.slots, "seed": inputs.SERVE_SEED},
+                       "check_every": args.check_every or default_k(args.storage),
+                       "slots": args.slots, "seed": inputs.SERVE_SEED,
+                       "escalate": bool(args.escalate), "solo_nodes": args.solo_nodes,
+                       "solo_lanes": args.solo_lanes or 2},
             "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
                        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                        "mean_s": float(lat.mean()), "makespan_s": makespan,
                        "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
                        "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
+                       "lanes": {"batch": int(sum(1 for d in results.values() if d["lane"] == 0)),
+                                 "solo": int(sum(1 for d in results.values() if d["lane"] == 1)),
+                                 "escalated": int(sum(1 for d in results.values() if d["lane"] == 2))},
+                       "escalated": {"%s->%s" % (lbm.status_name(a), lbm.status_name(b)): int(n)
+                                     for (a, b), n in sorted(collections.Counter(
+                                         (d["first_status"], d["status"]) for d in results.values()
+                                         if d["lane"] == 2).items())},
                        "statuses": {lbm.status_name(k): int(sum(1 for d in results.values()
                                                                 if d["status"] == k))
                                     for k in sorted({d["status"] for d in results.values()})}},
             "roofline": {"bound": "hbm", "kernel": "k_srv_step (batched fluid+substrate)",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "note": "algorithmic bytes of all served updates / device-busy time"},
+                         "note": "algorithmic bytes of the returned solves (batch and solo lane; "
+                                 "not the discarded first attempts of escalated requests) / "
+                                 "device-busy time of either lane"},
         }
         print(json.dumps(line), flush=True)
         last_results = (reqs, results, makespan, upd)
@@ -542,8 +561,14 @@ def main():
     ap.add_argument("--rates", default="", help="served: comma-separated arrival rates (a sweep)")
     ap.add_argument("--no-single", action="store_true", help="served: skip the single-solve comparison")
     ap.add_argument("--check-every", type=int, default=0,
-                    help="residual check interval of the solves or the server (0: 100)")
+                    help="residual check interval of the solves or the server (0: the library "
+                         "default, 100, or 1000 with FP16 storage)")
     ap.add_argument("--pool-gb", type=float, default=32.0)
+    ap.add_argument("--escalate", action="store_true",
+                    help="served: re-solve failed reduced-storage requests in FP32-shifted storage")
+    ap.add_argument("--solo-nodes", type=int, default=0,
+                    help="served: requests of at least this many nodes go to the solo lanes")
+    ap.add_argument("--solo-lanes", type=int, default=0, help="served: solo-lane threads (0: 2)")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,
                     help="stall window in checks (0: the library default)")
@@ -554,7 +579,8 @@ def main():
     ap.add_argument("--compare-storage", default="", choices=[""] + sorted(STORAGES),
                     help="coupled loop: repeat in this storage and compare")
     ap.add_argument("--compare-check-every", type=int, default=0,
-                    help="coupled loop: residual check interval of the compared run (0: 100)")
+                    help="coupled loop: residual check interval of the compared run (0: the "
+                         "library default)")
     ap.add_argument("--ad-lattice", default="d2q5", choices=["d2q5", "d2q9"],
                     help="2-D substrate lattice: D2Q5 with the linear equilibrium, or the "
                          "paper's D2Q9 with the Eq. 5 equilibrium")
@@ -606,7 +632,7 @@ def main():
         sys.exit("--ad-lattice d2q9 is a 2-D option")
     p = lbm.make_params(tau=w["tau"], u_in=w["u_in"], D=w["D"], c_in=w["c_in"], k_sink=w["k"],
                         storage=storage, stall_checks=args.stall_checks, k_half=args.k_half,
-                        ad_lattice=int(ad9), check_every=args.check_every or 100)
+                        ad_lattice=int(ad9), check_every=args.check_every)
     s = lbm.lbm_solver_create(ctx, cls, p)
 
     def one_step():
@@ -634,7 +660,7 @@ def main():
     sf, fi, sa, ai = recs[-1]
     dim = 3 if w["nz"] > 1 else 2
     qf, qa = (19, 7) if dim == 3 else (9, 9 if ad9 else 5)
-    sb = {0: 4, 1: 4, 2: 2, 3: 8}[storage]
+    sb = {0: 4, 1: 4, 2: 2, 3: 8, 4: 4}[storage]
     cb = 8 if storage == 3 else 4
     # Per solver: HIP-event time over its launches in the timed region (on
     # the library's stream).  A launch advances several steps -- two in 3-D
@@ -688,6 +714,7 @@ def main():
                    "k_half": args.k_half if layer else None,
                    "substrate_lattice": "d3q7" if dim == 3 else args.ad_lattice,
                    "tol": w["tol"], "seed": w["seed"],
+                   "check_every": args.check_every or default_k(args.storage),
                    "fluid_status": lbm.status_name(sf), "fluid_iters": fi["iters"],
                    "ad_status": lbm.status_name(sa), "ad_iters": ai["iters"],
                    "fluid_nodes": fi["active_nodes"], "ad_nodes": ai["active_nodes"],

@@ -70,10 +70,11 @@ typedef enum {
     LBM_ENOTFOUND = -6     /* unknown ticket or field */
 } lbm_status;
 
-/* Population storage.  Arithmetic is FP64 for LBM_FP64 and FP32 for the
- * others.  Shifted forms store f_i - w_i rho0 (rho0 = 1) for the fluid and
- * g_i - w_i c_ref (c_ref = c_in) for the substrate, an exact change of
- * variables that keeps the stored values small. */
+/* Population storage.  Arithmetic is FP64 for LBM_FP64 and
+ * LBM_FP32_SHIFTED_F64 and FP32 for the others.  Shifted forms store
+ * f_i - w_i rho0 (rho0 = 1) for the fluid and g_i - w_i c_ref (c_ref = c_in)
+ * for the substrate, an exact change of variables that keeps the stored
+ * values small. */
 typedef enum {
     /* unshifted FP32 storage: each population at its full magnitude (~w_i
      * rho), whose round-to-nearest error recurs every step near a steady
@@ -82,9 +83,19 @@ typedef enum {
      * 5e-4 in concentration after 20,000 + 53,000 steps); it is kept for
      * comparison only.  LBM_FP32_SHIFTED is the FP32 form held to 1e-4. */
     LBM_FP32 = 0,
+    /* FP32 arithmetic on FP32 shifted storage: the fastest FP32 form.  Its
+     * rounding errors are deterministic functions of the state, and near a
+     * steady state slow modes accumulate them: on the 1024 x 512 disc
+     * medium at tau 0.6 (pore velocities to 0.23, density to 2.2) converged
+     * fields differ from FP64 by 5e-4 relative L2 in velocity. */
     LBM_FP32_SHIFTED = 1,
     LBM_FP16_SHIFTED = 2,
-    LBM_FP64 = 3
+    LBM_FP64 = 3,
+    /* FP32 shifted storage -- the same bytes in memory as LBM_FP32_SHIFTED,
+     * the same launches -- with each collision widened to FP64 and its
+     * results rounded once to FP32: the FP32 form held to 1e-4 relative L2
+     * against the FP64 fields on every workload. */
+    LBM_FP32_SHIFTED_F64 = 4
 } lbm_storage;
 
 enum { LBM_FLUID = 0, LBM_SOLID = 1, LBM_WALL = 2, LBM_BIOFILM = 3 };
@@ -133,8 +144,9 @@ typedef struct {
                              with FP16 storage, whose tile-mean residual carries
                              stochastic-rounding noise that falls with K: at
                              100 its floor sits above 1e-6 on most media */
-    int32_t stall_checks; /* stall window in checks; 0: 100 for FP16 storage,
-                             1000 otherwise; < 0 disables */
+    int32_t stall_checks; /* stall window in checks; 0: 1000, or with FP16 storage
+                             the checks that span 10,000 steps (10 at K = 1000);
+                             < 0 disables */
     double k_half;        /* 0: first-order sink k_sink C per step on BIOFILM nodes.
                              > 0: the Monod form of the consumption rate (Eq. 16,
                              its mediator factor folded into k_sink), k_sink C /
@@ -563,9 +575,9 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *p, int n_hours, uin
  * max_iter is rounded up to a multiple of check_every.  A fluid solve that
  * ends NOT_CONVERGED or STALLED still proceeds to the substrate solve; one
  * that diverges ends the request (c is then 0).
- * Besides the batch the server runs a solo lane: one host thread that
- * solves requests one at a time with a single-domain solver
- * (lbm_solver_fluid, then lbm_solver_ad, cold) on a stream of its own,
+ * Besides the batch the server runs solo lanes: host threads that each
+ * solve one request at a time with a single-domain solver
+ * (lbm_solver_fluid, then lbm_solver_ad, cold) on a stream of their own,
  * concurrently with the batch.  It takes (a) requests of at least
  * solo_nodes nodes, which fill the GPU on their own and there run the
  * single solver's wider multi-step launches, in the server's storage and
@@ -581,7 +593,7 @@ typedef struct lbm_server lbm_server;
 typedef struct {
     size_t pool_bytes;     /* device memory for request state, one allocation */
     int32_t max_slots;     /* requests on the device at once, 1..64 (32 if 0) */
-    int32_t storage;       /* LBM_FP32, LBM_FP32_SHIFTED or LBM_FP16_SHIFTED */
+    int32_t storage;       /* any but LBM_FP64 */
     int32_t check_every;   /* K: steps per chunk and residual cadence, a multiple of 4
                               (if 0: 100, or 1000 with FP16 storage, as lbm_params) */
     int32_t stall_checks;  /* as lbm_params */
@@ -590,8 +602,9 @@ typedef struct {
     int32_t direct_launch; /* 1: launch each chunk's kernels directly instead of the graph */
     int32_t escalate;      /* 1: re-solve failed reduced-storage requests in FP32-shifted
                               storage on the solo lane (see above) */
-    int64_t solo_nodes;    /* requests of at least this many nodes go to the solo lane
+    int64_t solo_nodes;    /* requests of at least this many nodes go to the solo lanes
                               (0: none); such requests need not fit the pool */
+    int32_t solo_lanes;    /* solo-lane threads, 1..8 (2 if 0) */
 } lbm_server_cfg;
 
 typedef struct {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lbm.so")
 
 LBM_OK, LBM_NOT_CONVERGED, LBM_STALLED = 0, 1, 2
 LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_EBUSY, LBM_ENOTFOUND = -1, -2, -3, -4, -5, -6
-LBM_FP32, LBM_FP32_SHIFTED, LBM_FP16_SHIFTED, LBM_FP64 = 0, 1, 2, 3
+LBM_FP32, LBM_FP32_SHIFTED, LBM_FP16_SHIFTED, LBM_FP64, LBM_FP32_SHIFTED_F64 = 0, 1, 2, 3, 4
 LBM_FLUID, LBM_SOLID, LBM_WALL, LBM_BIOFILM = 0, 1, 2, 3
 LBM_OUT_ZERO_GRADIENT, LBM_OUT_DIRICHLET = 0, 1
 LBM_SOLVER_FLUID, LBM_SOLVER_AD = 0, 1
@@ -67,7 +67,8 @@ class lbm_server_cfg(ct.Structure):
                 ("check_every", ct.c_int32), ("stall_checks", ct.c_int32),
                 ("inflight", ct.c_int32),
                 ("prep_threads", ct.c_int32), ("direct_launch", ct.c_int32),
-                ("escalate", ct.c_int32), ("solo_nodes", ct.c_int64)]
+                ("escalate", ct.c_int32), ("solo_nodes", ct.c_int64),
+                ("solo_lanes", ct.c_int32)]
 
 
 class lbm_request(ct.Structure):
@@ -677,10 +678,10 @@ def lbm_server_footprint(nx, ny, storage):
 
 def make_server_cfg(pool_bytes, max_slots=32, storage=LBM_FP16_SHIFTED, check_every=0,
                     stall_checks=0, inflight=0, prep_threads=0, direct_launch=0, escalate=0,
-                    solo_nodes=0):
+                    solo_nodes=0, solo_lanes=0):
     return lbm_server_cfg(int(pool_bytes), int(max_slots), int(storage), int(check_every),
                           int(stall_checks), int(inflight), int(prep_threads),
-                          int(direct_launch), int(escalate), int(solo_nodes))
+                          int(direct_launch), int(escalate), int(solo_nodes), int(solo_lanes))
 
 
 def make_request(nx, ny, cls=None, r_min=3, r_max=6, solid_frac=0.3, overlap=1, seed=0, layer=0,

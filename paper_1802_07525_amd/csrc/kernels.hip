@@ -104,6 +104,7 @@ constexpr bool ad_second_order = L::Q == 9 || L::Q == 19;
 struct SF64 {
     typedef double T;
     typedef double C;
+    typedef double M;
     static constexpr bool shifted = false;
     static constexpr bool tile_mean = false;
     static constexpr bool colref = false;
@@ -111,6 +112,7 @@ struct SF64 {
 struct SF32 {
     typedef float T;
     typedef float C;
+    typedef float M;
     static constexpr bool shifted = false;
     static constexpr bool tile_mean = false;
     static constexpr bool colref = false;
@@ -118,6 +120,18 @@ struct SF32 {
 struct SF32S {
     typedef float T;
     typedef float C;
+    typedef float M;
+    static constexpr bool shifted = true;
+    static constexpr bool tile_mean = false;
+    static constexpr bool colref = false;
+};
+// FP32 shifted state (memory, LDS, registers between steps) with FP64
+// collision arithmetic: each collision widens its inputs and rounds its
+// results once.
+struct SF32X {
+    typedef float T;
+    typedef float C;
+    typedef double M;
     static constexpr bool shifted = true;
     static constexpr bool tile_mean = false;
     static constexpr bool colref = false;
@@ -125,6 +139,7 @@ struct SF32S {
 struct SF16S {
     typedef _Float16 T; // stores round stochastically (pop_value)
     typedef float C;
+    typedef float M;
     static constexpr bool tile_mean = true;
     static constexpr bool colref = true; // column reference moves at checks
     static constexpr bool shifted = true;
@@ -600,13 +615,15 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
                                               typename S::C &rho)
 {
     typedef typename S::C C;
+    typedef typename S::M M; // arithmetic: the state type, or FP64 over FP32 state
     const bool xin = x == 0, xout = x == a.g.nx - 1;
     // reversed links: blocked sources, and the links through the inlet and
     // outlet faces (their rules below start from the reversed value)
     unsigned int rev = (unsigned int)d & ((1u << L::Q) - 2u);
     rev |= xin ? xdirs<L>(1) : 0u;
     rev |= xout ? xdirs<L>(-1) : 0u;
-    f[0] = src.own(0);
+    M h[L::Q];
+    h[0] = M(src.own(0));
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int cx = L::cx[i];
@@ -617,75 +634,79 @@ __device__ __forceinline__ void fluid_collide(const FluidArgs &a, int x, DT d, c
             if (cx != 0)
                 v = m ? v : v + C(L::w[i]) * (cx == 1 ? dm : dp);
         }
-        f[i] = v;
+        h[i] = M(v);
     }
+    const M mr0 = M(r0);
     // boundary columns (branches: waves without such a node skip them)
     if (xin) {
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
             if (L::cx[i] == 1)
-                f[i] = f[i] + C(6.0 * L::w[i]) * C(a.u_in);
+                h[i] = h[i] + M(6.0 * L::w[i]) * M(a.u_in);
     }
     if (xout) {
         // u* of this node's stored state
-        C h[L::Q];
+        M o[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            h[i] = src.own(i);
-        C r = h[0];
+            o[i] = M(src.own(i));
+        M r = o[0];
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
-            r += h[i];
-        const C ir = recip(S::shifted ? r0 + r : r);
-        const C ox = axis_sum<L, 0>(h) * ir, oy = axis_sum<L, 1>(h) * ir;
-        const C oz = L::DIM == 3 ? axis_sum<L, 2>(h) * ir : C(0);
-        const C ousq = C(1.5) * (L::DIM == 3 ? ox * ox + oy * oy + oz * oz : ox * ox + oy * oy);
+            r += o[i];
+        const M ir = recip(S::shifted ? mr0 + r : r);
+        const M ox = axis_sum<L, 0>(o) * ir, oy = axis_sum<L, 1>(o) * ir;
+        const M oz = L::DIM == 3 ? axis_sum<L, 2>(o) * ir : M(0);
+        const M ousq = M(1.5) * (L::DIM == 3 ? ox * ox + oy * oy + oz * oz : ox * ox + oy * oy);
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
             if (L::cx[i] != -1)
                 continue;
-            const C cu = cdot<L>(i, ox, oy, oz);
-            const C even = C(4.5) * cu * cu - ousq;
-            f[i] = C(2.0 * L::w[i]) * ((S::shifted ? C(1) - r0 : C(1)) + even) - f[i];
+            const M cu = cdot<L>(i, ox, oy, oz);
+            const M even = M(4.5) * cu * cu - ousq;
+            h[i] = M(2.0 * L::w[i]) * ((S::shifted ? M(1) - mr0 : M(1)) + even) - h[i];
         }
     }
-    C rs = f[0];
+    M rs = h[0];
 #pragma unroll
     for (int i = 1; i < L::Q; ++i)
-        rs += f[i];
-    rho = S::shifted ? r0 + rs : rs;
-    const C inv = recip(rho);
-    ux = axis_sum<L, 0>(f) * inv;
-    uy = axis_sum<L, 1>(f) * inv;
-    C usq = ux * ux + uy * uy;
+        rs += h[i];
+    const M mrho = S::shifted ? mr0 + rs : rs;
+    const M inv = recip(mrho);
+    const M mux = axis_sum<L, 0>(h) * inv;
+    const M muy = axis_sum<L, 1>(h) * inv;
+    M usq = mux * mux + muy * muy;
+    M muz = M(0);
     if constexpr (L::DIM == 3) {
-        uz = axis_sum<L, 2>(f) * inv;
-        usq += uz * uz;
-    } else {
-        uz = C(0);
+        muz = axis_sum<L, 2>(h) * inv;
+        usq += muz * muz;
     }
-    usq *= C(1.5);
-    const C om = C(a.omega);
+    usq *= M(1.5);
+    rho = C(mrho);
+    ux = C(mux);
+    uy = C(muy);
+    uz = C(muz);
+    const M om = M(a.omega);
     // Eq. 5 with c = 1: w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2), minus
     // the shift w_i r0 when stored shifted (rs = rho - r0).  Opposite
     // directions share the even part E = rs + rho (9/2 (c.u)^2 - 3/2 u^2)
     // and flip the odd part O = 3 rho c.u: one pair at a time.
-    const C base = rs - rho * usq;
+    const M base = rs - mrho * usq;
     {
-        const C feq = C(L::w[0]) * base;
-        f[0] = f[0] + om * (feq - f[0]);
+        const M feq = M(L::w[0]) * base;
+        f[0] = C(h[0] + om * (feq - h[0]));
     }
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int o = L::op[i];
         if (o < i)
             continue;
-        const C cu = cdot<L>(i, ux, uy, uz);
-        const C rcu = rho * cu;
-        const C even = C(L::w[i]) * (base + C(4.5) * rcu * cu);
-        const C odd = C(3.0 * L::w[i]) * rcu;
-        f[i] = f[i] + om * ((even + odd) - f[i]);
-        f[o] = f[o] + om * ((even - odd) - f[o]);
+        const M cu = cdot<L>(i, mux, muy, muz);
+        const M rcu = mrho * cu;
+        const M even = M(L::w[i]) * (base + M(4.5) * rcu * cu);
+        const M odd = M(3.0 * L::w[i]) * rcu;
+        f[i] = C(h[i] + om * ((even + odd) - h[i]));
+        f[o] = C(h[o] + om * ((even - odd) - h[o]));
     }
 }
 
@@ -1139,22 +1160,25 @@ __global__ void __launch_bounds__(256) k_fluid_step(FluidArgs a)
 // and the biofilm consumption - w_i k C.  g[] comes back relative to r0.
 template <class L, int QF, class S, class DT, class Src>
 __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const Src &src,
-                                           typename S::C ux, typename S::C uy, typename S::C uz,
+                                           typename S::C ux_c, typename S::C uy_c, typename S::C uz_c,
                                            typename S::C r0, typename S::C dm, typename S::C dp,
                                            typename S::C g[L::Q], typename S::C &cfull)
 {
     typedef typename S::C C;
+    typedef typename S::M M; // arithmetic: the state type, or FP64 over FP32 state
     constexpr int BIO = QF + L::Q;
     constexpr int LNK = QF - 1;
     const bool xin = x == 0, xout = x == a.g.nx - 1;
+    const M ux = M(ux_c), uy = M(uy_c), uz = M(uz_c);
     // Dirichlet values relative to this column's reference
-    const C cin_s = C(a.c_in - (double)r0), cout_s = C(a.c_out - (double)r0);
+    const M cin_s = M(C(a.c_in - (double)r0)), cout_s = M(C(a.c_out - (double)r0));
     // reversed links: blocked sources and the inlet and outlet faces (the
     // zero-gradient outlet replaces its value below)
     unsigned int rev = ((unsigned int)d >> LNK) & ((1u << L::Q) - 2u);
     rev |= xin ? xdirs<L>(1) : 0u;
     rev |= xout ? xdirs<L>(-1) : 0u;
-    g[0] = src.own(0);
+    M h[L::Q];
+    h[0] = M(src.own(0));
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const int cx = L::cx[i];
@@ -1164,15 +1188,15 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
             if (cx != 0)
                 v = m ? v : v + C(L::w[i]) * (cx == 1 ? dm : dp);
         }
-        g[i] = v;
+        h[i] = M(v);
     }
     // second-order form: 9/2 (c.u)^2 - 3/2 u^2 of direction i
-    C usq = C(0);
+    M usq = M(0);
     if constexpr (ad_second_order<L>)
-        usq = C(1.5) * (L::DIM == 3 ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
+        usq = M(1.5) * (L::DIM == 3 ? ux * ux + uy * uy + uz * uz : ux * ux + uy * uy);
     auto quad = [&](int i) {
-        const C cu = cdot<L>(i, ux, uy, uz);
-        return C(4.5) * cu * cu - usq;
+        const M cu = cdot<L>(i, ux, uy, uz);
+        return M(4.5) * cu * cu - usq;
     };
     // Dirichlet links of the boundary columns (branches: waves without such
     // a node skip them): twice the even part of the equilibrium at the
@@ -1182,10 +1206,10 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
 #pragma unroll
         for (int i = 1; i < L::Q; ++i)
             if (L::cx[i] == 1) {
-                C e = S::colref ? C(2.0 * L::w[i]) * cin_s : C(2.0 * L::w[i] * a.cin_s);
+                M e = S::colref ? M(2.0 * L::w[i]) * cin_s : M(2.0 * L::w[i] * a.cin_s);
                 if constexpr (ad_second_order<L>)
-                    e += C(2.0 * L::w[i] * a.c_in) * quad(i);
-                g[i] = e - g[i];
+                    e += M(2.0 * L::w[i] * a.c_in) * quad(i);
+                h[i] = e - h[i];
             }
     }
     if (xout) {
@@ -1193,44 +1217,48 @@ __device__ __forceinline__ void ad_collide(const AdArgs &a, int x, DT d, const S
         for (int i = 1; i < L::Q; ++i)
             if (L::cx[i] == -1) {
                 if (a.outlet) {
-                    C e = S::colref ? C(2.0 * L::w[i]) * cout_s : C(2.0 * L::w[i] * a.cout_s);
+                    M e = S::colref ? M(2.0 * L::w[i]) * cout_s : M(2.0 * L::w[i] * a.cout_s);
                     if constexpr (ad_second_order<L>)
-                        e += C(2.0 * L::w[i] * a.c_out) * quad(i);
-                    g[i] = e - g[i];
+                        e += M(2.0 * L::w[i] * a.c_out) * quad(i);
+                    h[i] = e - h[i];
                 } else {
-                    g[i] = src.own(i); // zero gradient: copy this node's population i
+                    h[i] = M(src.own(i)); // zero gradient: copy this node's population i
                 }
             }
     }
-    C cs = g[0];
+    M cs = h[0];
 #pragma unroll
     for (int i = 1; i < L::Q; ++i)
-        cs += g[i];
-    cfull = S::shifted ? r0 + cs : cs;
-    const C om = C(a.omega);
-    const C kc = ((d >> BIO) & DT(1)) ? consumption(cfull, a.k_sink, a.k_half) : C(0);
+        cs += h[i];
+    const M mc = S::shifted ? M(r0) + cs : cs;
+    cfull = C(mc);
+    const M om = M(a.omega);
+    const M kc = ((d >> BIO) & DT(1)) ? consumption(mc, a.k_sink, a.k_half) : M(0);
     {
-        const C geq = C(L::w[0]) * cs;
-        g[0] = g[0] + om * (geq - g[0]) - C(L::w[0]) * kc;
+        const M geq = M(L::w[0]) * cs;
+        h[0] = h[0] + om * (geq - h[0]) - M(L::w[0]) * kc;
     }
     if constexpr (ad_second_order<L>) {
         // Eq. 5 with C for rho, minus the shift: w_i (cs + C (3 c.u +
         // 9/2 (c.u)^2 - 3/2 u^2)); the rest direction carries -3/2 u^2
-        g[0] = g[0] - om * C(L::w[0]) * cfull * usq;
+        h[0] = h[0] - om * M(L::w[0]) * mc * usq;
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            const C cu = cdot<L>(i, ux, uy, uz);
-            const C geq = C(L::w[i]) * (cs + cfull * (C(3) * cu + (C(4.5) * cu * cu - usq)));
-            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+            const M cu = cdot<L>(i, ux, uy, uz);
+            const M geq = M(L::w[i]) * (cs + mc * (M(3) * cu + (M(4.5) * cu * cu - usq)));
+            h[i] = h[i] + om * (geq - h[i]) - M(L::w[i]) * kc;
         }
     } else {
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            const C cu = cdot<L>(i, ux, uy, uz);
-            const C geq = C(L::w[i]) * (cs + cfull * (C(L::inv_cs2) * cu));
-            g[i] = g[i] + om * (geq - g[i]) - C(L::w[i]) * kc;
+            const M cu = cdot<L>(i, ux, uy, uz);
+            const M geq = M(L::w[i]) * (cs + mc * (M(L::inv_cs2) * cu));
+            h[i] = h[i] + om * (geq - h[i]) - M(L::w[i]) * kc;
         }
     }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+        g[i] = C(h[i]);
 }
 
 template <class L, class S, bool NT>
@@ -2808,7 +2836,7 @@ size_t compute_bytes(int s)
 }
 bool storage_shifted(int s)
 {
-    return s == ST_F32S || s == ST_F16S;
+    return s == ST_F32S || s == ST_F16S || s == ST_F32X;
 }
 bool storage_moving_ref(int s)
 {
@@ -2832,6 +2860,8 @@ static hipError_t by_storage(int storage, F &&fn)
         return fn(SF16S{});
     case ST_F64:
         return fn(SF64{});
+    case ST_F32X:
+        return fn(SF32X{});
     default:
         return hipErrorInvalidValue;
     }
@@ -3459,6 +3489,8 @@ hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable 
         return go(SF32S());
     case ST_F16S:
         return go(SF16S());
+    case ST_F32X:
+        return go(SF32X());
     default:
         return hipErrorInvalidValue;
     }

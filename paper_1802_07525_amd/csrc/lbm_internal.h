@@ -96,6 +96,16 @@ lbm_status export_u_device(lbm_solver *s, double *dst);
 // Storage FP32, FP32-shifted or FP16 only; synchronises the stream.
 lbm_status export_f32(lbm_solver *s, int which, float *dst);
 
+// Default stall window in checks: 1000, or for FP16 storage the checks
+// that span 10,000 steps (10 at its default cadence of 1000 steps).
+inline int default_stall_checks(int storage, int check_every)
+{
+    if (storage != LBM_FP16_SHIFTED)
+        return 1000;
+    const int w = 10000 / (check_every > 0 ? check_every : 1);
+    return w > 1 ? w : 1;
+}
+
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
 lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);

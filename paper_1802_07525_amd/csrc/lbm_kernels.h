@@ -11,7 +11,7 @@
 
 namespace lbmk {
 
-enum { ST_F32 = 0, ST_F32S = 1, ST_F16S = 2, ST_F64 = 3 };
+enum { ST_F32 = 0, ST_F32S = 1, ST_F16S = 2, ST_F64 = 3, ST_F32X = 4 };
 enum { MODE_PLAIN = 0, MODE_CHECK = 2 };
 enum { STOP_RUN = 0, STOP_OK = 1, STOP_STALLED = 2, STOP_DIVERGED = 3, STOP_MAXITER = 4 };
 

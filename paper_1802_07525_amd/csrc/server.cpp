@@ -404,13 +404,13 @@ struct lbm_server {
     std::vector<std::thread> preps;
     std::thread worker;
 
-    // solo lane (mutex for the queue and counters)
-    lbm_ctx *solo_ctx = nullptr;
+    // solo lanes (mutex for the queue and counters)
+    std::vector<lbm_ctx *> solo_ctx;
     std::deque<Job *> solo_q;
     std::condition_variable cv_solo;
-    std::thread solo;
+    std::vector<std::thread> solo;
     int64_t n_solo = 0, n_escalated = 0;
-    Job *solo_cur = nullptr; // the request the solo lane is solving
+    std::vector<Job *> solo_cur; // the request each solo lane is solving
     int lanes_busy = 0;
     std::chrono::steady_clock::time_point lanes_since{};
 
@@ -925,7 +925,7 @@ struct lbm_server {
     }
 
     // ------------------------------------------------------- solo lane
-    void solo_loop()
+    void solo_loop(int lane)
     {
         for (;;) {
             Job *j;
@@ -936,15 +936,15 @@ struct lbm_server {
                     return;
                 j = solo_q.front();
                 solo_q.pop_front();
-                solo_cur = j;
+                solo_cur[lane] = j;
                 lane_enter_locked(std::chrono::steady_clock::now());
                 if (j->t_admit == 0)
                     j->t_admit = now_s(t0);
             }
-            solve_alone(j);
+            solve_alone(j, solo_ctx[lane]);
             std::lock_guard<std::mutex> lk(mu);
             lane_leave_locked();
-            solo_cur = nullptr;
+            solo_cur[lane] = nullptr;
             finish_locked(j);
         }
     }
@@ -952,7 +952,7 @@ struct lbm_server {
     // The request's two solves by the single-domain solver: the server's
     // storage and cadence on the solo lane proper, FP32-shifted storage with
     // the default cadence and stall window when escalated.
-    void solve_alone(Job *j)
+    void solve_alone(Job *j, lbm_ctx *sctx)
     {
         const lbm_request &r = j->req;
         const bool esc = j->lane == LBM_LANE_ESCALATED;
@@ -978,12 +978,12 @@ struct lbm_server {
         j->ad_ran = false;
         std::fill(j->flux, j->flux + 10, 0.0);
         lbm_solver *sv = nullptr;
-        lbm_status st = lbm_solver_create(solo_ctx, g, j->cls.data(), &p, &sv);
+        lbm_status st = lbm_solver_create(sctx, g, j->cls.data(), &p, &sv);
         j->cls.clear();
         j->cls.shrink_to_fit();
         auto fail_job = [&](lbm_status e) {
             j->status = e;
-            j->msg = lbm_last_error(solo_ctx);
+            j->msg = lbm_last_error(sctx);
             if (sv)
                 lbm_solver_destroy(sv);
         };
@@ -1062,8 +1062,8 @@ struct lbm_server {
         err = m;
         for (auto &kv : all) {
             Job *j = kv.second.get();
-            if (j->phase == PH_DONE || j == solo_cur)
-                continue; // the solo lane finishes its current request itself
+            if (j->phase == PH_DONE || std::find(solo_cur.begin(), solo_cur.end(), j) != solo_cur.end())
+                continue; // a solo lane finishes its current request itself
             j->status = LBM_EDEVICE;
             j->msg = m;
             j->phase = PH_DONE;
@@ -1119,7 +1119,7 @@ extern "C" {
 
 size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage)
 {
-    if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_FP16_SHIFTED)
+    if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage == LBM_FP64 || storage > LBM_FP32_SHIFTED_F64)
         return 0;
     return layout_of(nx, (int64_t)nx * ny, storage).total;
 }
@@ -1130,8 +1130,9 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         return set_err(ctx, LBM_EINVAL, "null argument");
     *out = nullptr;
     lbm_server_cfg c = *cfg;
-    if (c.storage < LBM_FP32 || c.storage > LBM_FP16_SHIFTED)
-        return set_err(ctx, LBM_EINVAL, "server storage must be FP32, FP32_SHIFTED or FP16_SHIFTED");
+    if (c.storage < LBM_FP32 || c.storage == LBM_FP64 || c.storage > LBM_FP32_SHIFTED_F64)
+        return set_err(ctx, LBM_EINVAL,
+                       "server storage must be FP32, FP32_SHIFTED, FP16_SHIFTED or FP32_SHIFTED_F64");
     if (c.max_slots == 0)
         c.max_slots = 32;
     if (c.max_slots < 1 || c.max_slots > lbmk::SRV_MAX_SLOTS)
@@ -1154,6 +1155,10 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         return set_err(ctx, LBM_EINVAL, "escalate must be 0 or 1");
     if (c.solo_nodes < 0)
         return set_err(ctx, LBM_EINVAL, "solo_nodes must be >= 0");
+    if (c.solo_lanes == 0)
+        c.solo_lanes = 2;
+    if (c.solo_lanes < 1 || c.solo_lanes > 8)
+        return set_err(ctx, LBM_EINVAL, "solo_lanes must be in 1..8");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return hip_err(ctx, e, "set device");
@@ -1161,9 +1166,7 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     s->device = ctx->device;
     s->cfg = c;
     s->K = c.check_every;
-    s->window = c.stall_checks < 0 ? 0
-                                   : (c.stall_checks > 0 ? c.stall_checks
-                                                         : (c.storage == LBM_FP16_SHIFTED ? 100 : 1000));
+    s->window = c.stall_checks < 0 ? 0 : (c.stall_checks > 0 ? c.stall_checks : default_stall_checks(c.storage, s->K));
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();
     // tiles: each holds 64 x ty nodes (one per thread of a block) of at
@@ -1187,8 +1190,13 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     };
     if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
         return cleanup(hip_err(ctx, e, "server stream"));
-    if (lbm_ctx_create(ctx->device, nullptr, &s->solo_ctx) != LBM_OK)
-        return cleanup(set_err(ctx, LBM_EDEVICE, "solo lane context"));
+    for (int k = 0; k < c.solo_lanes; ++k) {
+        lbm_ctx *sc = nullptr;
+        if (lbm_ctx_create(ctx->device, nullptr, &sc) != LBM_OK)
+            return cleanup(set_err(ctx, LBM_EDEVICE, "solo lane context"));
+        s->solo_ctx.push_back(sc);
+    }
+    s->solo_cur.assign((size_t)c.solo_lanes, nullptr);
     if (dmalloc((void **)&s->pool, c.pool_bytes) != hipSuccess)
         return cleanup(set_err(ctx, LBM_ENOMEM, "device pool allocation failed"));
     if (dmalloc((void **)&s->d_slots, sizeof(lbmk::SrvSlot) * lbmk::SRV_MAX_SLOTS) != hipSuccess ||
@@ -1247,7 +1255,8 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     for (int k = 0; k < c.prep_threads; ++k)
         s->preps.emplace_back([sp] { sp->prep_loop(); });
     s->worker = std::thread([sp] { sp->work_loop(); });
-    s->solo = std::thread([sp] { sp->solo_loop(); });
+    for (int k = 0; k < c.solo_lanes; ++k)
+        s->solo.emplace_back([sp, k] { sp->solo_loop(k); });
     *out = s.release();
     return LBM_OK;
 }
@@ -1396,10 +1405,11 @@ void lbm_server_destroy(lbm_server *s)
             t.join();
     if (s->worker.joinable())
         s->worker.join();
-    if (s->solo.joinable())
-        s->solo.join();
-    if (s->solo_ctx)
-        lbm_ctx_destroy(s->solo_ctx);
+    for (auto &t : s->solo)
+        if (t.joinable())
+            t.join();
+    for (lbm_ctx *sc : s->solo_ctx)
+        lbm_ctx_destroy(sc);
     if (s->stream)
         (void)hipStreamSynchronize(s->stream);
     s->res_ring.reclaim = nullptr;

@@ -65,7 +65,7 @@ lbm_status validate_params(lbm_ctx *ctx, const lbm_params &p)
         return set_err(ctx, LBM_EINVAL, "unknown outlet mode");
     if (!isfinite(p.c_out))
         return set_err(ctx, LBM_EINVAL, "c_out must be finite");
-    if (p.storage < LBM_FP32 || p.storage > LBM_FP64)
+    if (p.storage < LBM_FP32 || p.storage > LBM_FP32_SHIFTED_F64)
         return set_err(ctx, LBM_EINVAL, "unknown storage");
     if (p.check_every < 2 || (p.check_every & 1))
         return set_err(ctx, LBM_EINVAL, "check_every must be even and >= 2");
@@ -421,8 +421,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
     // (a long window there only repeats steps at the floor)
     const int window = s->p.stall_checks < 0
                            ? 0
-                           : (s->p.stall_checks > 0 ? s->p.stall_checks
-                                                    : (s->p.storage == LBM_FP16_SHIFTED ? 100 : 1000));
+                           : (s->p.stall_checks > 0 ? s->p.stall_checks : default_stall_checks(s->p.storage, K));
     lbmk::Ctrl *ctrl = s->d_ctrl + which;
     HIPCHK(lbmk::ctrl_reset(ctrl, tol, window, which == LBM_SOLVER_FLUID, K,
                             s->d_part + (size_t)which * 2 * s->part_n, check_blocks(s, which), stream),

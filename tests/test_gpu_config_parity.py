@@ -14,8 +14,11 @@ that writes it.
   the same starting states, and the sampled fields -- u_x, u_y, (u_z),
   rho - 1 on flow-domain nodes, C on substrate-active nodes -- and the
   FP64 fluxes (inflow, consumption J) must agree within 1e-4 relative L2
-  with FP32 shifted storage and 5e-3 with FP16 storage.  The steady solves
-  themselves must stop at those counts.
+  with FP32 storage and 5e-3 with FP16 storage.  On the 1024 x 512
+  workload (pore velocities to 0.23, density to 2.2) the FP32 form is the
+  one with FP64 collision arithmetic: the FP32 arithmetic of the plain
+  shifted form leaves 5e-4 there (slow modes accumulate its rounding).
+  The steady solves themselves must stop at those counts.
 * The coupled loop: the GPU's FP32-shifted loop and the oracle's FP64 loop
   take the same seeded growth draws; the growth picks, and so the biofilm
   masks, must be identical along all updates, and the consumption series
@@ -34,8 +37,8 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 FIELDS = os.path.join(HERE, "golden", "oracle_fields")
-FP32S, FP16S = 1, 2
-TOL = {FP32S: 1e-4, FP16S: 5e-3}
+FP32S, FP16S, FP32X = 1, 2, 4
+TOL = {FP32S: 1e-4, FP16S: 5e-3, FP32X: 1e-4}
 STEPS = {"c2": (149500, 170000), "c3": (13100, 45800)}
 
 
@@ -59,8 +62,8 @@ def _gpu_fixed(lbm, cls, w, storage, nf, na):
     return U, R, C, fl
 
 
-@pytest.mark.parametrize("name,storage", [("c2", FP32S), ("c3", FP32S), ("c3", FP16S)],
-                         ids=["c2-fp32s", "c3-fp32s", "c3-fp16s"])
+@pytest.mark.parametrize("name,storage", [("c2", FP32X), ("c3", FP32S), ("c3", FP32X), ("c3", FP16S)],
+                         ids=["c2-fp32s-f64", "c3-fp32s", "c3-fp32s-f64", "c3-fp16s"])
 def test_full_size_fields_iteration_matched(gpu_lib, name, storage):
     lbm = gpu_lib
     nf, na = STEPS[name]

@@ -17,10 +17,14 @@ linearly: the bound after n steps is 2 u (|h|/|f|) (n + 1), i.e. per-step
 rates 1.2e-7 (FP32), 1.2e-8 (FP32 shifted) and 1e-5 (FP16 shifted).
 Velocity and concentration must stay within 1e-4 (FP32 forms) and 5e-3
 (FP16 storage) relative L2, the targets of the method's precision forms.
-At convergence only the shifted FP32 form, the library's FP32 form, is held
-to 1e-4: the unshifted form stores ~w_i C with an ulp of ~3e-8 whose
-round-to-nearest bias recurs every step and is amplified by the slow
-advective mode (~1e4 steps), and is kept for comparison only.
+At convergence the unshifted form is not held to 1e-4: it stores ~w_i C
+with an ulp of ~3e-8 whose round-to-nearest bias recurs every step and is
+amplified by the slow advective mode (~1e4 steps), and is kept for
+comparison only.  FP32 shifted storage with FP64 collision arithmetic rounds
+only its stored values (once per step, the same per-step bound as the
+shifted form); the FP32 collision arithmetic of the shifted form adds
+rounding errors of its own, deterministic in the state, that slow modes
+accumulate on strongly driven media (the 1024 x 512 workload).
 """
 import numpy as np
 import pytest
@@ -31,13 +35,13 @@ from paper_1802_07525_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-FP32, FP32S, FP16S, FP64 = 0, 1, 2, 3
-NAMES = {FP32: "fp32", FP32S: "fp32s", FP16S: "fp16s", FP64: "fp64"}
+FP32, FP32S, FP16S, FP64, FP32X = 0, 1, 2, 3, 4
+NAMES = {FP32: "fp32", FP32S: "fp32s", FP16S: "fp16s", FP64: "fp64", FP32X: "fp32s-f64"}
 
 # population error per step (rel L2; FP64: max abs) and field bound (rel L2)
-POP_RATE = {FP64: None, FP32: 1.2e-7, FP32S: 1.2e-8, FP16S: 1e-5}
-FIELD_TOL = {FP64: 1e-12, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3}
-TOL_CONV = {FP64: 1e-9, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3}
+POP_RATE = {FP64: None, FP32: 1.2e-7, FP32S: 1.2e-8, FP16S: 1e-5, FP32X: 1.2e-8}
+FIELD_TOL = {FP64: 1e-12, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3, FP32X: 1e-4}
+TOL_CONV = {FP64: 1e-9, FP32: 1e-4, FP32S: 1e-4, FP16S: 5e-3, FP32X: 1e-4}
 
 
 def _pop_ok(storage, got, want, sel, n):
@@ -56,7 +60,7 @@ def _solver(lbm, cls, w, storage, **over):
     return lbm.Solver(cls, **p)
 
 
-@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S], ids=NAMES.get)
+@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S, FP32X], ids=NAMES.get)
 @pytest.mark.parametrize("w", [C1, RAGGED], ids=["128x64", "100x37"])
 def test_fluid_fixed_steps(gpu_lib, storage, w):
     lbm = gpu_lib
@@ -78,7 +82,7 @@ def test_fluid_fixed_steps(gpu_lib, storage, w):
             assert np.all(F[:, ~fluid] == 0) and np.all(U[:, ~fluid] == 0)
 
 
-@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S], ids=NAMES.get)
+@pytest.mark.parametrize("storage", [FP64, FP32, FP32S, FP16S, FP32X], ids=NAMES.get)
 @pytest.mark.parametrize("outlet", [0, 1])
 def test_ad_fixed_steps(gpu_lib, storage, outlet):
     lbm = gpu_lib
@@ -103,7 +107,7 @@ def test_ad_fixed_steps(gpu_lib, storage, outlet):
             assert rel_l2(C, C_or, act) < FIELD_TOL[storage], (n, rel_l2(C, C_or, act))
 
 
-@pytest.mark.parametrize("storage", [FP64, FP32S], ids=NAMES.get)
+@pytest.mark.parametrize("storage", [FP64, FP32S, FP32X], ids=NAMES.get)
 def test_3d_fixed_steps(gpu_lib, storage):
     lbm = gpu_lib
     w = inputs.scaled(inputs.WORKLOADS["c3"], 70, 22, 18, seed=9)
@@ -153,15 +157,14 @@ def test_c1_converged_fp64_matches_oracle(gpu_lib):
 C2S = inputs.scaled(inputs.WORKLOADS["c2"], 256, 128)
 
 
-@pytest.mark.parametrize("storage", [FP32S, FP16S], ids=NAMES.get)
+@pytest.mark.parametrize("storage", [FP32S, FP32X, FP16S], ids=NAMES.get)
 def test_converged_reduced_precision(gpu_lib, storage):
     """256 x 128 electrode with the 1024 x 512 workload's physics (tau =
     tau_D = 0.6, u_in = 0.02, porosity 0.6), solved to 1e-6.  The oracle
     runs exactly the GPU's step counts (iteration-matched); velocity and
-    concentration must agree within 1e-4 (FP32 shifted storage) / 5e-3
-    (FP16 storage) relative L2.  Unshifted FP32 storage is not held to
-    the FP32 bound at convergence (see its entry in lbm.h): the shifted
-    form is the library's FP32 form."""
+    concentration must agree within 1e-4 (the shifted FP32 storage forms)
+    / 5e-3 (FP16 storage) relative L2.  Unshifted FP32 storage is not held
+    to the FP32 bound at convergence (see its entry in lbm.h)."""
     lbm = gpu_lib
     w = C2S
     cls = masks(w, lbm)
