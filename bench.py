@@ -481,6 +481,9 @@ def served_main(args):
                                      for (a, b), n in sorted(collections.Counter(
                                          (d["first_status"], d["status"]) for d in results.values()
                                          if d["lane"] == 2).items())},
+                       "requests": [[int(d["user"]), int(d["status"]), int(d["lane"]), int(d["iters_fluid"]),
+                                     int(d["iters_ad"])] for d in sorted(results.values(),
+                                                                         key=lambda d: d["user"])],
                        "statuses": {lbm.status_name(k): int(sum(1 for d in results.values()
                                                                 if d["status"] == k))
                                     for k in sorted({d["status"] for d in results.values()})}},

@@ -164,7 +164,7 @@ static lbm_status mask_from_device(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls,
     out.resize((size_t)g.nx * g.ny * g.nz);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = hipMemcpy(out.data(), cls, out.size(), hipMemcpyDeviceToHost);
+        e = stream_copy(ctx, out.data(), cls, out.size(), hipMemcpyDeviceToHost);
     return e == hipSuccess ? LBM_OK : hip_err(ctx, e, "mask copy");
 }
 

@@ -106,6 +106,17 @@ inline int default_stall_checks(int storage, int check_every)
     return w > 1 ? w : 1;
 }
 
+// Copy ordered on the context's stream and complete on return.  A plain
+// hipMemcpy runs on the null stream, which orders nothing against work on
+// a non-blocking stream (the context's own, or several solvers' in one
+// process): an upload could still be landing while the stream's kernels
+// read the buffer.
+inline hipError_t stream_copy(lbm_ctx *ctx, void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, ctx->stream);
+    return e == hipSuccess ? hipStreamSynchronize(ctx->stream) : e;
+}
+
 // ---- error helpers -------------------------------------------------------
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
 lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);

@@ -76,7 +76,7 @@ lbm_status lbm_fluid_steady_dev_noalloc(lbm_ctx *ctx, lbm_grid g, const uint8_t 
     std::vector<uint8_t> mask((size_t)g.nx * g.ny * g.nz);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = hipMemcpy(mask.data(), cls, mask.size(), hipMemcpyDeviceToHost);
+        e = stream_copy(ctx, mask.data(), cls, mask.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_err(ctx, e, "mask copy");
     lbm_params p;

@@ -80,9 +80,9 @@ lbm_status upload_desc_words(lbm_solver *s)
         std::vector<uint16_t> p16((size_t)N);
         for (int64_t n = 0; n < N; ++n)
             p16[n] = (uint16_t)s->desc_h[n];
-        HIPCHK(hipMemcpy(s->d_desc, p16.data(), (size_t)N * 2, hipMemcpyHostToDevice), "desc upload");
+        HIPCHK(stream_copy(s->ctx, s->d_desc, p16.data(), (size_t)N * 2, hipMemcpyHostToDevice), "desc upload");
     } else {
-        HIPCHK(hipMemcpy(s->d_desc, s->desc_h.data(), (size_t)N * 4, hipMemcpyHostToDevice),
+        HIPCHK(stream_copy(s->ctx, s->d_desc, s->desc_h.data(), (size_t)N * 4, hipMemcpyHostToDevice),
                "desc upload");
     }
     return LBM_OK;
@@ -115,7 +115,7 @@ const void *ad_desc(const lbm_solver *s)
 
 lbm_status upload_ad9_words(lbm_solver *s)
 {
-    HIPCHK(hipMemcpy(s->d_desc_ad, s->desc_ad_h.data(), s->desc_ad_h.size() * 2, hipMemcpyHostToDevice),
+    HIPCHK(stream_copy(s->ctx, s->d_desc_ad, s->desc_ad_h.data(), s->desc_ad_h.size() * 2, hipMemcpyHostToDevice),
            "substrate desc upload");
     return LBM_OK;
 }
@@ -496,7 +496,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
         HIPCHK(hipEventRecord(s->ev_b, stream), "event");
     HIPCHK(hipStreamSynchronize(stream), "solve sync");
     lbmk::Ctrl fin;
-    HIPCHK(hipMemcpy(&fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
+    HIPCHK(stream_copy(s->ctx, &fin, ctrl, sizeof(fin), hipMemcpyDeviceToHost), "ctrl read");
     const auto t1 = std::chrono::steady_clock::now();
     const int64_t t_final = fin.stop != lbmk::STOP_RUN ? fin.t_stop : launched;
     cur = (int)((cur0 + launches_for(s, which, t_final)) & 1);
@@ -588,11 +588,11 @@ lbm_status get_field(lbm_solver *s, int field, void *dst, hipMemcpyKind kind = h
     case LBM_FIELD_DESC:
         if (s->desc_bytes == 2) {
             std::vector<uint16_t> w(N);
-            HIPCHK(hipMemcpy(w.data(), s->d_desc, N * 2, hipMemcpyDeviceToHost), "desc copy");
+            HIPCHK(stream_copy(s->ctx, w.data(), s->d_desc, N * 2, hipMemcpyDeviceToHost), "desc copy");
             for (size_t n = 0; n < N; ++n)
                 static_cast<uint32_t *>(dst)[n] = w[n];
         } else {
-            HIPCHK(hipMemcpy(dst, s->d_desc, N * 4, hipMemcpyDeviceToHost), "desc copy");
+            HIPCHK(stream_copy(s->ctx, dst, s->d_desc, N * 4, hipMemcpyDeviceToHost), "desc copy");
         }
         return LBM_OK;
     case LBM_FIELD_LINKS_F:
@@ -655,7 +655,7 @@ lbm_status lbmh::set_u_device(lbm_solver *s, const double *u)
     const size_t n = (size_t)s->dim * (size_t)s->geo.N;
     std::vector<double> h(n);
     HIPCHK(hipSetDevice(s->ctx->device), "set device");
-    HIPCHK(hipMemcpy(h.data(), u, n * 8, hipMemcpyDeviceToHost), "velocity copy");
+    HIPCHK(stream_copy(s->ctx, h.data(), u, n * 8, hipMemcpyDeviceToHost), "velocity copy");
     return lbm_solver_set_u(s, h.data());
 }
 
@@ -1001,12 +1001,12 @@ lbm_status lbm_solver_set_u(lbm_solver *s, const double *u)
         return LBM_EINVAL;
     const size_t n = (size_t)s->dim * (size_t)s->geo.N;
     if (cbytes(s) == 8) {
-        HIPCHK(hipMemcpy(s->d_u, u, n * 8, hipMemcpyHostToDevice), "set u");
+        HIPCHK(stream_copy(s->ctx, s->d_u, u, n * 8, hipMemcpyHostToDevice), "set u");
     } else {
         std::vector<float> f(n);
         for (size_t k = 0; k < n; ++k)
             f[k] = (float)u[k];
-        HIPCHK(hipMemcpy(s->d_u, f.data(), n * 4, hipMemcpyHostToDevice), "set u");
+        HIPCHK(stream_copy(s->ctx, s->d_u, f.data(), n * 4, hipMemcpyHostToDevice), "set u");
     }
     return LBM_OK;
 }
@@ -1293,13 +1293,13 @@ lbm_status lbm_solver_put_state(lbm_solver *s, const void *src, size_t bytes)
     p += N;
     s->fcur = 0;
     s->gcur = 0;
-    HIPCHK(hipMemcpy(s->d_f[0], p, h.f_bytes, hipMemcpyHostToDevice), "state f");
+    HIPCHK(stream_copy(s->ctx, s->d_f[0], p, h.f_bytes, hipMemcpyHostToDevice), "state f");
     p += h.f_bytes;
-    HIPCHK(hipMemcpy(s->d_g[0], p, h.g_bytes, hipMemcpyHostToDevice), "state g");
+    HIPCHK(stream_copy(s->ctx, s->d_g[0], p, h.g_bytes, hipMemcpyHostToDevice), "state g");
     p += h.g_bytes;
-    HIPCHK(hipMemcpy(s->d_u, p, h.u_bytes, hipMemcpyHostToDevice), "state u");
+    HIPCHK(stream_copy(s->ctx, s->d_u, p, h.u_bytes, hipMemcpyHostToDevice), "state u");
     p += h.u_bytes;
-    HIPCHK(hipMemcpy(s->d_ref, p, h.ref_bytes, hipMemcpyHostToDevice), "state references");
+    HIPCHK(stream_copy(s->ctx, s->d_ref, p, h.ref_bytes, hipMemcpyHostToDevice), "state references");
     s->fluid_ready = h.fluid_ready != 0;
     s->ad_ready = h.ad_ready != 0;
     s->fsteps = h.fsteps;

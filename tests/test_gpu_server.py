@@ -357,3 +357,22 @@ def test_escalation_resolves_in_fp32_shifted(srv_env):
     s = _single(lbm, ctx, b_spec, FP16S, tol=1e-3, check_every=100)
     assert rb["iters_fluid"] == s["fi"]["iters"] and rb["iters_ad"] == s["ai"]["iters"]
     assert rb["flux"][0] == s["fi"]["flux_in"] and rb["flux"][4] == s["ai"]["sink_total"]
+
+
+def test_concurrent_solo_lanes_equal_batch(srv_env):
+    """Four solo lanes solving five requests at once, each lane a solver on
+    its own stream and host thread: every result equals the batch's bit for
+    bit.  (Uploads that ran on the null stream were not ordered against a
+    lane's non-blocking stream: under concurrency a solve could start on
+    descriptors still landing.)"""
+    lbm, ctx = srv_env
+    specs = MIX[:5]
+    batch, _, _ = _serve(lbm, ctx, specs, FP32S)
+    solo, stats, _ = _serve(lbm, ctx, specs, FP32S, solo_nodes=1, solo_lanes=4)
+    assert stats["solo"] == len(specs)
+    for i in range(len(specs)):
+        a, b = batch[i], solo[i]
+        assert b["lane"] == lbm.LBM_LANE_SOLO
+        assert (a["status"], a["iters_fluid"], a["iters_ad"]) == (b["status"], b["iters_fluid"], b["iters_ad"]), i
+        assert np.array_equal(a["flux"], b["flux"])
+        assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["c"], b["c"])
