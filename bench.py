@@ -467,7 +467,7 @@ def served_main(args):
                        "rate": rate, "storage": args.storage, "pool_gb": args.pool_gb,
                        "check_every": args.check_every or default_k(args.storage),
                        "slots": args.slots, "seed": inputs.SERVE_SEED,
-                       "escalate": bool(args.escalate), "solo_nodes": args.solo_nodes,
+                       "escalate": bool(args.escalate), "solo_nodes": args.solo_nodes or 262144,
                        "solo_lanes": args.solo_lanes or 2},
             "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
                        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
@@ -570,7 +570,8 @@ def main():
     ap.add_argument("--escalate", action="store_true",
                     help="served: re-solve failed reduced-storage requests in FP32-shifted storage")
     ap.add_argument("--solo-nodes", type=int, default=0,
-                    help="served: requests of at least this many nodes go to the solo lanes")
+                    help="served: requests of at least this many nodes go to the solo lanes "
+                         "(0: the library default, 262,144; -1: none)")
     ap.add_argument("--solo-lanes", type=int, default=0, help="served: solo-lane threads (0: 2)")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--stall-checks", type=int, default=0,

@@ -583,10 +583,11 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *p, int n_hours, uin
  * single solver's wider multi-step launches, in the server's storage and
  * cadence -- bit-equal to what the batch would return -- and (b) with
  * escalate set and reduced storage (FP16 or unshifted FP32), every request
- * whose batched solves did not both end OK: it is solved again from rest
- * with FP32-shifted storage (cadence and stall window the lbm_params
- * defaults), and that solve's result is returned, marked in `lane`, with
- * the first attempt's status and step counts alongside.
+ * whose solves in that storage (batched or solo) did not both end OK: it is
+ * solved again from rest with FP32-shifted storage (cadence and stall
+ * window the lbm_params defaults), and that solve's result is returned,
+ * marked in `lane`, with the first attempt's status and step counts
+ * alongside.
  * All lbm_server_* calls are thread-safe. */
 typedef struct lbm_server lbm_server;
 
@@ -603,7 +604,8 @@ typedef struct {
     int32_t escalate;      /* 1: re-solve failed reduced-storage requests in FP32-shifted
                               storage on the solo lane (see above) */
     int64_t solo_nodes;    /* requests of at least this many nodes go to the solo lanes
-                              (0: none); such requests need not fit the pool */
+                              (0: 262,144, where a request fills the GPU alone;
+                              < 0: none); such requests need not fit the pool */
     int32_t solo_lanes;    /* solo-lane threads, 1..8 (2 if 0) */
 } lbm_server_cfg;
 

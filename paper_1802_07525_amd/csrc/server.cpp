@@ -491,7 +491,10 @@ struct lbm_server {
         }
     }
 
-    bool may_escalate() const { return cfg.escalate && cfg.storage != LBM_FP32_SHIFTED; }
+    bool may_escalate() const
+    {
+        return cfg.escalate && (cfg.storage == LBM_FP16_SHIFTED || cfg.storage == LBM_FP32);
+    }
 
     // caller holds mu
     void finish_locked(Job *j)
@@ -945,6 +948,22 @@ struct lbm_server {
             std::lock_guard<std::mutex> lk(mu);
             lane_leave_locked();
             solo_cur[lane] = nullptr;
+            const int st = overall_status(j->st_fluid, j->ad_ran ? j->st_ad : j->st_fluid);
+            if (j->lane == LBM_LANE_SOLO && j->status == LBM_OK && st != LBM_OK && may_escalate() &&
+                !stopping && !failed) {
+                // a reduced-storage solve on the solo lane: escalated as a
+                // batched one would be
+                updates += (double)j->it_fluid * j->n_fluid + (double)j->it_ad * j->n_ad;
+                j->first_status = st;
+                j->first_it_fluid = j->it_fluid;
+                j->first_it_ad = j->it_ad;
+                j->lane = LBM_LANE_ESCALATED;
+                j->u.clear();
+                j->c.clear();
+                solo_q.push_back(j);
+                cv_solo.notify_all();
+                continue;
+            }
             finish_locked(j);
         }
     }
@@ -979,8 +998,10 @@ struct lbm_server {
         std::fill(j->flux, j->flux + 10, 0.0);
         lbm_solver *sv = nullptr;
         lbm_status st = lbm_solver_create(sctx, g, j->cls.data(), &p, &sv);
-        j->cls.clear();
-        j->cls.shrink_to_fit();
+        if (esc || !may_escalate()) {
+            j->cls.clear(); // no later solve of this request needs the mask
+            j->cls.shrink_to_fit();
+        }
         auto fail_job = [&](lbm_status e) {
             j->status = e;
             j->msg = lbm_last_error(sctx);
@@ -1153,8 +1174,8 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         return set_err(ctx, LBM_EINVAL, "pool_bytes must be at least 64 KiB");
     if (c.escalate != 0 && c.escalate != 1)
         return set_err(ctx, LBM_EINVAL, "escalate must be 0 or 1");
-    if (c.solo_nodes < 0)
-        return set_err(ctx, LBM_EINVAL, "solo_nodes must be >= 0");
+    if (c.solo_nodes == 0)
+        c.solo_nodes = (int64_t)1 << 18;
     if (c.solo_lanes == 0)
         c.solo_lanes = 2;
     if (c.solo_lanes < 1 || c.solo_lanes > 8)
@@ -1272,7 +1293,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
     std::string m = request_problem(*r);
     if (m.empty()) {
         j->lay = layout_of(r->nx, N, s->cfg.storage);
-        if (s->cfg.solo_nodes > 0 && N >= s->cfg.solo_nodes)
+        if (s->cfg.solo_nodes > 0 && N >= s->cfg.solo_nodes) // < 0: no solo lane
             j->lane = LBM_LANE_SOLO;
         else if (j->lay.total > s->cfg.pool_bytes ||
                  lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), lbmk::srv_tile_ty(s->cfg.storage)) >

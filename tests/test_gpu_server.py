@@ -218,7 +218,7 @@ def test_served_fp16_within_5e_3_of_plain_fp32(srv_env):
 def test_server_max_iter_and_rejections(srv_env):
     lbm, ctx = srv_env
     spec = MIX[3]
-    cfg = lbm.make_server_cfg(4 << 20, max_slots=2, storage=FP32S)
+    cfg = lbm.make_server_cfg(4 << 20, max_slots=2, storage=FP32S, solo_nodes=-1)
     srv = lbm.lbm_server_create(ctx, cfg)
     try:
         # parameters checked at submission
@@ -276,7 +276,7 @@ def test_server_matches_wide_single_solve(srv_env, spec, storage):
     counts and the FP64 fluxes of the final states."""
     lbm, ctx = srv_env
     need = lbm.lbm_server_footprint(spec[0], spec[1], storage)
-    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=storage, check_every=100)
+    cfg = lbm.make_server_cfg(need + 4096, max_slots=1, storage=storage, check_every=100, solo_nodes=-1)
     srv = lbm.lbm_server_create(ctx, cfg)
     print("server vs single solve %dx%d storage %d" % (spec[0], spec[1], storage), flush=True)
     try:
@@ -303,7 +303,7 @@ def test_solo_lane_equals_batch(srv_env, storage):
     lbm, ctx = srv_env
     specs = [MIX[0], MIX[3]]  # 2,048 and 8,192 nodes
     print("solo lane vs batch, storage", storage, flush=True)
-    batch, bstats, _ = _serve(lbm, ctx, specs, storage)
+    batch, bstats, _ = _serve(lbm, ctx, specs, storage, solo_nodes=-1)
     solo, sstats, _ = _serve(lbm, ctx, specs, storage, solo_nodes=4096)
     assert bstats["solo"] == 0 and sstats["solo"] == 1 and sstats["escalated"] == 0
     assert [batch[i]["lane"] for i in (0, 1)] == [lbm.LBM_LANE_BATCH] * 2
@@ -318,16 +318,18 @@ def test_solo_lane_equals_batch(srv_env, storage):
         assert b["t_submit"] <= b["t_admit"] <= b["t_finish"]
 
 
-def test_escalation_resolves_in_fp32_shifted(srv_env):
-    """FP16 server with escalation: a request whose batched solves end
-    NOT_CONVERGED (max_iter 200) is solved again from rest in FP32-shifted
-    storage -- the result is that single solve's, marked escalated, with the
-    batched attempt's status and step counts; a request that ends OK stays
-    a batch result."""
+@pytest.mark.parametrize("solo", [0, 1], ids=["batched", "solo"])
+def test_escalation_resolves_in_fp32_shifted(srv_env, solo):
+    """FP16 server with escalation: a request whose FP16 solves (batched, or
+    on a solo lane) end NOT_CONVERGED (max_iter 200) is solved again from
+    rest in FP32-shifted storage -- the result is that single solve's,
+    marked escalated, with the first attempt's status and step counts; a
+    request that ends OK keeps its FP16 result."""
     lbm, ctx = srv_env
     a_spec, b_spec = MIX[0], MIX[2]
     need = sum(lbm.lbm_server_footprint(s[0], s[1], FP16S) for s in (a_spec, b_spec))
-    cfg = lbm.make_server_cfg(4 * need, max_slots=4, storage=FP16S, check_every=100, escalate=1)
+    cfg = lbm.make_server_cfg(4 * need, max_slots=4, storage=FP16S, check_every=100, escalate=1,
+                              solo_nodes=solo or -1)
     srv = lbm.lbm_server_create(ctx, cfg)
     print("escalation", flush=True)
     try:
@@ -340,7 +342,7 @@ def test_escalation_resolves_in_fp32_shifted(srv_env):
         stats = lbm.lbm_server_stats(srv)
     finally:
         lbm.lbm_server_destroy(srv)
-    assert stats["finished"] == 2 and stats["solo"] == 1 and stats["escalated"] == 1
+    assert stats["finished"] == 2 and stats["solo"] == 1 + solo and stats["escalated"] == 1
     ra, rb = got[ta], got[tb]
     assert ra["lane"] == lbm.LBM_LANE_ESCALATED
     assert ra["first_status"] == lbm.LBM_NOT_CONVERGED
@@ -352,7 +354,7 @@ def test_escalation_resolves_in_fp32_shifted(srv_env):
     assert ra["flux"][2] == s["ai"]["flux_in"] and ra["flux"][4] == s["ai"]["sink_total"]
     assert np.abs(ra["u"] - s["U"]).max() <= 1e-6 * max(np.abs(s["U"]).max(), 1e-30)
     assert np.abs(ra["c"] - s["C"]).max() <= 1e-6
-    assert rb["lane"] == lbm.LBM_LANE_BATCH and rb["status"] == lbm.LBM_OK
+    assert rb["lane"] == (lbm.LBM_LANE_SOLO if solo else lbm.LBM_LANE_BATCH) and rb["status"] == lbm.LBM_OK
     assert rb["first_status"] == 0 and rb["first_iters_fluid"] == 0
     s = _single(lbm, ctx, b_spec, FP16S, tol=1e-3, check_every=100)
     assert rb["iters_fluid"] == s["fi"]["iters"] and rb["iters_ad"] == s["ai"]["iters"]
@@ -367,7 +369,7 @@ def test_concurrent_solo_lanes_equal_batch(srv_env):
     descriptors still landing.)"""
     lbm, ctx = srv_env
     specs = MIX[:5]
-    batch, _, _ = _serve(lbm, ctx, specs, FP32S)
+    batch, _, _ = _serve(lbm, ctx, specs, FP32S, solo_nodes=-1)
     solo, stats, _ = _serve(lbm, ctx, specs, FP32S, solo_nodes=1, solo_lanes=4)
     assert stats["solo"] == len(specs)
     for i in range(len(specs)):
