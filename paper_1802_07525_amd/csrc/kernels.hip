@@ -1915,6 +1915,72 @@ __device__ __forceinline__ Z3Nodes z3_nodes(const Z3Block &b, int nx, int ny)
     return q;
 }
 
+// Stores of a z-marching second step.  With a buffer resource (BUF) every
+// lane issues its Q stores: no branch separates them from the loads of the
+// next plane, so the compiler's waits for those loads count the stores
+// issued after them and let the stores drain in the background.  A lane
+// with nothing to write (off the grid, or a plane outside the block's
+// segment) stores at offsets from the resource's end on, which the
+// hardware drops (the host takes this form only where (2Q - 1) N sizeof(T)
+// bytes fit 32-bit offsets).  Values and rounding as fluid_store /
+// ad_store: seed is their stochastic-rounding seed.
+template <class L, class S, bool NT, bool BUF>
+__device__ __forceinline__ void z3_store(void *dst, unsigned int N, unsigned int n, bool ok,
+                                         typename S::C f[L::Q], unsigned int seed)
+{
+    typedef typename S::T T;
+    unsigned int rng = seed;
+    if constexpr (BUF) {
+        const unsigned int stride = N * (unsigned int)sizeof(T);
+        const unsigned int numrec = (unsigned int)L::Q * stride;
+        const auto r = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)numrec, 0x00020000);
+        const unsigned int base = ok ? n * (unsigned int)sizeof(T) : numrec;
+        constexpr int aux = NT ? 2 : 0; // non-temporal
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const T h = pop_value<S>(f[i], rng);
+            if constexpr (sizeof(T) == 4)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, h), r,
+                                                      base + (unsigned int)i * stride, 0, aux);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r,
+                                                      base + (unsigned int)i * stride, 0, aux);
+        }
+    } else if (ok) {
+        T *d = static_cast<T *>(dst);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_pop<S, NT>(d + ((unsigned int)i * N + n), f[i], rng);
+    }
+}
+
+// Q stores that write nothing (offsets past the resource's end), issued
+// once before a z-marching loop right after its first descriptor loads.
+// The loop's entry then has as many stores in flight behind those loads as
+// its back edge has behind the next plane's, and the compiler's wait for
+// the loaded values at the loop head -- the smaller count over both edges --
+// lets the previous plane's stores drain instead of waiting for them.
+template <class L, class S, bool NT, bool BUF>
+__device__ __forceinline__ void z3_entry_stores(void *dst, unsigned int N)
+{
+    if constexpr (BUF) {
+        typename S::C zero[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            zero[i] = typename S::C(0);
+        z3_store<L, S, NT, BUF>(dst, N, 0u, false, zero, 0u);
+    }
+}
+
+// Node descriptor of a z-marching block (0 off the grid and outside the
+// planes 0..nz-1): a buffer load, so that no branch guards it
+template <class DT>
+__device__ __forceinline__ DT z3_desc(__amdgpu_buffer_rsrc_t r, bool ok, unsigned int n)
+{
+    static_assert(sizeof(DT) == 4, "3-D descriptor words are 32-bit");
+    return __builtin_amdgcn_raw_buffer_load_b32(r, ok ? n * 4u : 0xFFFFFFFFu, 0, 0);
+}
+
 template <class S, int MODE, bool NT, bool BUF, int TY>
 __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsigned long long *part_r,
                                               unsigned long long *part_u, void *smem)
@@ -1928,7 +1994,8 @@ __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsi
     C *lds = static_cast<C *>(smem);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const Z3Block b = z3_block<TY>(a.g, a.zseg, tile);
-    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const auto drs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.desc), (short)0,
+                                                       (int)((unsigned int)a.g.N * 4u), 0x00020000);
     const Z3Nodes q = z3_nodes<TY>(b, nx, ny);
     const bool xin_c = q.xc == 0, xout_c = q.xc == nx - 1;
     const bool xin_h = q.xh == 0, xout_h = q.xh == nx - 1;
@@ -1945,7 +2012,7 @@ __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsi
     }
     auto nidx = [&](int x, int y, int k) { return (unsigned int)(x + nx * (y + ny * k)); };
     auto dload = [&](bool in, int x, int y, int k) {
-        return (in && k >= 0 && k < nz) ? desc[nidx(x, y, k)] : DT(0);
+        return z3_desc<DT>(drs, in && k >= 0 && k < nz, nidx(x, y, k));
     };
     const int kb = b.z0 - 1, ke = b.z1;
     PreVals<L, C, NO> pc, ph;
@@ -1962,6 +2029,7 @@ __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsi
     };
     issue(kb);
     DT dcn = dload(q.inc, q.xc, q.yc, kb + 1), dhn = dload(q.inh, q.xh, q.yh, kb + 1);
+    z3_entry_stores<L, S, NT, BUF>(a.dst, (unsigned int)a.g.N);
     constexpr int NK = keep_count<L>();
     C own[NK], nxt[NK];
     DT dnx = DT(0);
@@ -2007,17 +2075,17 @@ __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsi
         dcn = dload(q.inc, q.xc, q.yc, k + 2);
         dhn = dload(q.inh, q.xh, q.yh, k + 2);
         __syncthreads();
-        // second step at plane z = k - 1
+        // second step at plane z = k - 1 (the first two passes have none:
+        // their results are not stored)
         const int z = k - 1;
-        if (z < b.z0 || z >= b.z1)
-            continue;
+        const bool zok = z >= b.z0 && z < b.z1;
         NodePos p;
         p.x = q.xc;
         p.y = q.yc;
         p.z = z;
-        p.inb = q.inc;
-        p.n = q.inc ? nidx(q.xc, q.yc, z) : 0u;
-        const bool act = (d & DT(1)) != 0;
+        p.inb = q.inc && zok;
+        p.n = p.inb ? nidx(q.xc, q.yc, z) : 0u;
+        const bool act = zok && (d & DT(1)) != 0;
         C ux = C(0), uy = C(0), uz = C(0), rho = C(0);
         C f[L::Q];
         if (act) {
@@ -2033,9 +2101,11 @@ __device__ __forceinline__ void fluid_tile3d2(const FluidArgs &a, int tile, unsi
             for (int i = 0; i < L::Q; ++i)
                 f[i] = C(0);
         }
-        fluid_store<L, S, NT>(a, p, f, a.step + 1);
+        z3_store<L, S, NT, BUF>(a.dst, (unsigned int)a.g.N, p.n, p.inb, f,
+                                sizeof(typename S::T) == 2 ? sr_seed(p.n, a.step + 1) : 0u);
         if constexpr (MODE == MODE_CHECK)
-            fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
+            if (p.inb)
+                fluid_check<L, S, DT>(a, p, d, act, ux, uy, uz, rho, acc);
     }
     if constexpr (MODE == MODE_CHECK) {
         const double r = acc.result();
@@ -2070,7 +2140,8 @@ __device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned l
     C *lds = static_cast<C *>(smem);
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const Z3Block b = z3_block<TY>(a.g, a.zseg, tile);
-    const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
+    const auto drs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(a.desc), (short)0,
+                                                       (int)((unsigned int)a.g.N * 4u), 0x00020000);
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
     const unsigned int NN = (unsigned int)a.g.N;
     const Z3Nodes q = z3_nodes<TY>(b, nx, ny);
@@ -2088,7 +2159,7 @@ __device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned l
     }
     auto nidx = [&](int x, int y, int k) { return (unsigned int)(x + nx * (y + ny * k)); };
     auto dload = [&](bool in, int x, int y, int k) {
-        return (in && k >= 0 && k < nz) ? desc[nidx(x, y, k)] : DT(0);
+        return z3_desc<DT>(drs, in && k >= 0 && k < nz, nidx(x, y, k));
     };
     const int kb = b.z0 - 1, ke = b.z1;
     PreVals<L, C, NO> pc, ph;
@@ -2113,6 +2184,7 @@ __device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned l
     };
     issue(kb);
     DT dcn = dload(q.inc, q.xc, q.yc, kb + 1), dhn = dload(q.inh, q.xh, q.yh, kb + 1);
+    z3_entry_stores<L, S, NT, BUF>(a.dst, (unsigned int)a.g.N);
     constexpr int NK = keep_count<L>();
     C own[NK], nxt[NK];
     C ou[3], nu[3];
@@ -2160,16 +2232,16 @@ __device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned l
         dcn = dload(q.inc, q.xc, q.yc, k + 2);
         dhn = dload(q.inh, q.xh, q.yh, k + 2);
         __syncthreads();
+        // second step at plane z = k - 1 (none in the first two passes)
         const int z = k - 1;
-        if (z < b.z0 || z >= b.z1)
-            continue;
+        const bool zok = z >= b.z0 && z < b.z1;
         NodePos p;
         p.x = q.xc;
         p.y = q.yc;
         p.z = z;
-        p.inb = q.inc;
-        p.n = q.inc ? nidx(q.xc, q.yc, z) : 0u;
-        const bool act = ((d >> ACT) & DT(1)) != 0;
+        p.inb = q.inc && zok;
+        p.n = p.inb ? nidx(q.xc, q.yc, z) : 0u;
+        const bool act = zok && ((d >> ACT) & DT(1)) != 0;
         C cfull = C(0);
         C g[L::Q];
         if (act) {
@@ -2185,9 +2257,11 @@ __device__ __forceinline__ void ad_tile3d2(const AdArgs &a, int tile, unsigned l
             for (int i = 0; i < L::Q; ++i)
                 g[i] = C(0);
         }
-        ad_store<L, S, NT>(a, p, g, a.step + 1);
+        z3_store<L, S, NT, BUF>(a.dst, (unsigned int)a.g.N, p.n, p.inb, g,
+                                sizeof(typename S::T) == 2 ? sr_seed(p.n, (a.step + 1) ^ 0x5bd1e995u) : 0u);
         if constexpr (MODE == MODE_CHECK)
-            ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
+            if (p.inb)
+                ad_check<L, QF, S, DT>(a, p, d, act, cfull, acc);
     }
     if constexpr (MODE == MODE_CHECK) {
         const double r = acc.result();
@@ -3122,7 +3196,8 @@ static hipError_t launch_z3(int mode, const Geo &g, int zseg, int ty, bool nt, u
         if (g.nz < 3 || zseg < 1 || (ty != 8 && ty != 16) || (S::tile_mean && mode != MODE_PLAIN))
             return hipErrorInvalidValue;
         const dim3 grid(z3_blocks(g, zseg, ty));
-        const bool buf = n_elems * sizeof(typename S::T) <= 0xFFFFFFFFull;
+        // z3_store addresses up to (2Q - 1) N elements from the buffer start
+        const bool buf = 2ull * n_elems * sizeof(typename S::T) <= 0xFFFFFFFFull;
         auto go = [&](auto mc, auto ntc, auto bc) {
             constexpr int M = decltype(mc)::value;
             if constexpr (!(S::tile_mean && M != MODE_PLAIN)) {
