@@ -728,6 +728,13 @@ struct lbm_server {
         t.begin[e] = tiles;
         t.n_active = e;
         t.total_tiles = tiles;
+        // invariants the batched kernels rely on: tile offsets ascending
+        // (their binary search), the table within the per-tile check slots
+        for (int k = 0; k < e; ++k)
+            if (t.begin[k] > t.begin[k + 1])
+                return hipErrorInvalidValue;
+        if (tiles > part_cap || tiles != tiles_used)
+            return hipErrorInvalidValue;
         table_tiles = tiles;
         table_dirty = false;
         return lbmk::srv_table_set(d_tab, t, stream);
@@ -748,6 +755,8 @@ struct lbm_server {
             size_t k = 0;
             while ((MIN_GRID << k) < table_tiles && k + 1 < execs.size())
                 ++k;
+            if ((MIN_GRID << k) < table_tiles) // the grid must cover every tile of the table
+                return hipErrorInvalidValue;
             if ((e = hipGraphLaunch(execs[k], stream)) != hipSuccess)
                 return e;
         } else if ((e = enqueue_chunk(std::max(table_tiles, 1))) != hipSuccess) {
