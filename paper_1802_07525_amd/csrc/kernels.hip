@@ -15,8 +15,9 @@
 //    renumbered so that each of the eight XCDs receives a contiguous band of
 //    tiles: neighbouring rows meet in the same L2.
 //  * Storage policies: FP64; FP32; FP32 or FP16 holding the shifted value
-//    h = f - w_i * ref.  Arithmetic is FP32 for the FP32/FP16 forms; FP16
-//    stores round stochastically (see pop_value).
+//    h = f - w_i * ref.  Arithmetic is FP32 for the FP32/FP16 forms, or FP64
+//    over FP32 shifted storage (S::M, the collisions' type); FP16 stores
+//    round stochastically (see pop_value).
 //  * Residual checks are fused into the step kernel: on a check step it takes
 //    max |U(t) - U(t-K)| / K in FP64 against the moments saved at the
 //    previous check (and saves the new ones), reduces it across the wave
