@@ -176,7 +176,8 @@ def profile_main(args, lbm, ctx, cls, w, storage):
     nf = int(lbm.lbm_flow_domain(cls).sum())
     na = int(((cls == 0) | (cls == 3)).sum())
     print(json.dumps({"profile": w["name"], "storage": args.storage, "steps": n,
-                      "fluid_nodes": nf, "ad_nodes": na, "fluid_ms_per_step": f_ms / n,
+                      "fluid_nodes": nf, "ad_nodes": na, "grid_nodes": int(cls.size),
+                      "fluid_ms_per_step": f_ms / n,
                       "ad_ms_per_step": a_ms / n, "copy_bytes": 1 << 30, "copy_ms": copy_ms,
                       "copy_gbs": gbs}), flush=True)
 

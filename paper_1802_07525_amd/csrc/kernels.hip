@@ -993,6 +993,24 @@ constexpr bool rounds_on_store()
     return sizeof(typename S::T) != sizeof(typename S::C) || S::colref;
 }
 
+// Origin of 2-D tile t of 64 x TY nodes in the multi-step launches: tiles
+// are numbered row by row within vertical strips of 16 tile columns, so the
+// tiles one XCD works through (a contiguous range of t) keep a tile row's
+// data small enough to stay in that XCD's L2 until the row below reads its
+// halo (whole-width rows outgrew L2 on wide grids, and every tile read its
+// halo rows from memory again).  The numbering only orders the work.
+template <int TY>
+__device__ __forceinline__ void strip_origin(const Geo &g, int t, int &x0, int &y0)
+{
+    constexpr int SW = 16;
+    const int nty = (g.ny + TY - 1) / TY;
+    const int per = SW * nty;
+    const int s = t / per, l = t - s * per;
+    const int w = min(SW, g.ntx - s * SW);
+    x0 = (s * SW + l % w) * 64;
+    y0 = (l / w) * TY;
+}
+
 template <class S, int MODE, bool NT, int TY, int NTH, int NS>
 __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsigned long long *part_r,
                                             unsigned long long *part_u, void *smem)
@@ -1009,7 +1027,8 @@ __device__ __forceinline__ void fluid_tileN(const FluidArgs &a, int tile, unsign
     DT(*dl)[LX] = reinterpret_cast<DT(*)[LX]>(static_cast<char *>(smem) + 9 * NR * sizeof(C));
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
-    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
+    int x0, y0;
+    strip_origin<TY>(a.g, tile, x0, y0);
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
     // step 1: the whole region from global memory
@@ -1483,7 +1502,8 @@ __device__ __forceinline__ void ad_tileN(const AdArgs &a, int tile, unsigned lon
     DT(*dl)[LX] = reinterpret_cast<DT(*)[LX]>(static_cast<char *>(smem) + L::Q * NR * sizeof(C));
     const long long N = a.g.N;
     const int nx = a.g.nx, ny = a.g.ny;
-    const int x0 = (tile % a.g.ntx) * 64, y0 = (tile / a.g.ntx) * TY;
+    int x0, y0;
+    strip_origin<TY>(a.g, tile, x0, y0);
     const LBM_GLOBAL DT *desc = gmem(static_cast<const DT *>(a.desc));
     const LBM_GLOBAL C *U = gmem(static_cast<const C *>(a.u));
     const auto gsrc = pair_src<S, L::Q>(a.src, N, nx);
