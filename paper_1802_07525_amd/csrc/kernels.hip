@@ -183,9 +183,12 @@ __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
     *p = static_cast<typename S::T>(v);
 }
 // Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a node
-// and a step; each direction then advances a 32-bit linear congruential
-// generator from it (a = 1664525, c = 1013904223: the quick generator of
-// Press et al., Numerical Recipes) and uses its top 13 bits.
+// and a step; each direction then takes the next value of a Weyl sequence
+// from it (steps of 0x9E3779B9, 2^32 divided by the golden ratio) and uses
+// its top 13 bits.  Over the steps the hash makes each direction's addend
+// uniform and independent; within a node the sequence spreads the
+// directions' addends evenly.  (A 32-bit multiply per direction -- a
+// linear congruential step -- ran at a quarter of the add's rate.)
 __device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
 {
     unsigned int x = n * 0x9E3779B1u ^ t * 0xC2B2AE3Du;
@@ -198,7 +201,7 @@ __device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
 }
 __device__ __forceinline__ unsigned int sr_next(unsigned int &state)
 {
-    state = state * 1664525u + 1013904223u;
+    state += 0x9E3779B9u;
     return state >> 19;
 }
 
