@@ -13,9 +13,9 @@
 //    is free and the request's footprint fits the pool (first fit), uploads
 //    the descriptors through a pinned ring, initialises the request on the
 //    device and adds its tiles to the device slot table.
-//  * Work proceeds in chunks of K steps: K/2 launches of the batched step
-//    kernel (each advances every tile of every admitted request by two
-//    steps, in that request's phase) and one batched decide, captured once
+//  * Work proceeds in chunks of K steps: launches of the batched step
+//    kernel (each advances every tile of every admitted request by two or
+//    four steps, in that request's phase) and one batched decide, captured once
 //    as a HIP graph
 //    that reads the slot table from device memory, so admissions never
 //    re-capture it.  After each chunk the control blocks are copied to
@@ -42,6 +42,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -381,7 +382,8 @@ struct lbm_server {
     static const int RING = 8;
     hipEvent_t ev_snap[RING] = {};
     long long snap_chunk[RING] = {};
-    long long chunks = 0, head = 0, tail = 0;
+    std::atomic<long long> chunks{0}; // also read by lbm_server_stats
+    long long head = 0, tail = 0;
     Job *slot_job[lbmk::SRV_MAX_SLOTS] = {};
     int tiles_used = 0;
     bool table_dirty = false;
@@ -671,7 +673,10 @@ struct lbm_server {
         j->phase = PH_RETIRING;
         slot_job[j->sid] = nullptr;
         tiles_used -= j->tiles;
-        alloc.release(j->off, j->lay.total);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            alloc.release(j->off, j->lay.total);
+        }
         table_dirty = true;
         ++n_retiring;
         return hipSuccess;
@@ -777,7 +782,8 @@ struct lbm_server {
     hipError_t enqueue_chunk(int grid)
     {
         hipError_t e;
-        // Steps per launch: FP16 two (64 x 4 tiles); the FP32 forms four
+        // Steps per launch: FP16 storage and FP32 storage with FP64
+        // arithmetic two (64 x 4 tiles); FP32 and FP32-shifted storage four
         // (64 x 16 tiles), the first two launches taking two when K / 4 is
         // odd, so that a chunk has an even number of launches.  The check
         // is taken on the last launch.
@@ -837,30 +843,35 @@ struct lbm_server {
         return hipSuccess;
     }
 
-    // Admit prepared requests in ticket order while the head one fits.
+    // Admit prepared requests in ticket order while the head one fits.  The
+    // head is chosen and taken out of `ready` under one lock: preparation
+    // threads finish out of ticket order, so a lower ticket can enter
+    // `ready` at any moment and become its head.  (Choosing the head in one
+    // critical section and erasing `ready.begin()` in a later one dropped
+    // that newcomer -- it was never admitted and the drain waited for it
+    // forever -- and admitted the chosen request a second time.)
     hipError_t admit_ready()
     {
         for (;;) {
             Job *j = nullptr;
+            int sid = -1;
             {
                 std::lock_guard<std::mutex> lk(mu);
                 if (ready.empty())
                     return hipSuccess;
-                j = ready.begin()->second;
-            }
-            int sid = -1;
-            for (int s = 0; s < cfg.max_slots; ++s)
-                if (!slot_job[s]) {
-                    sid = s;
-                    break;
-                }
-            if (sid < 0 || tiles_used + j->tiles > part_cap)
-                return hipSuccess;
-            if (!alloc.alloc(j->lay.total, &j->off))
-                return hipSuccess;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                ready.erase(ready.begin());
+                auto head = ready.begin();
+                j = head->second;
+                for (int s = 0; s < cfg.max_slots; ++s)
+                    if (!slot_job[s]) {
+                        sid = s;
+                        break;
+                    }
+                if (sid < 0 || tiles_used + j->tiles > part_cap)
+                    return hipSuccess;
+                // the pool counters are read by lbm_server_stats
+                if (!alloc.alloc(j->lay.total, &j->off))
+                    return hipSuccess;
+                ready.erase(head);
                 ++n_active;
             }
             hipError_t e = admit(j, sid);
