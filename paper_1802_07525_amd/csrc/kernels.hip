@@ -3595,13 +3595,12 @@ hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable 
     }
 }
 
-// The 64 x 16 served form (srv_stepN) is switched off: served FP32 requests
-// stalled twice in tests with it (requests never finishing) and no cause
-// has been shown.  Every storage is served by paired 64 x 4 launches.
+// FP32 and FP32-shifted requests are served over 64 x 16 tiles (srv_stepN,
+// up to four steps per launch); FP16 storage keeps the 64 x 4 tiles of its
+// tile means, and FP32 storage with FP64 arithmetic the paired 64 x 4 form.
 int srv_tile_ty(int storage)
 {
-    (void)storage;
-    return PAIR_TY;
+    return storage == ST_F32 || storage == ST_F32S ? WIDE_TY : PAIR_TY;
 }
 
 hipError_t srv_stepN(int storage, int mode, int ns, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
