@@ -37,10 +37,12 @@ HBM_PEAK_GBS = 8000.0
 STORAGES = {"fp32": 0, "fp32s": 1, "fp16s": 2, "fp64": 3, "fp32s-f64": 4}
 DTYPES = {"fp32": "f32", "fp32s": "f32", "fp16s": "f32 (f16 storage)", "fp64": "f64",
           "fp32s-f64": "f64 (f32 storage)"}
-# the step kernels' sources and compiler flags: counters taken for other
-# code are not reported
+# the step kernels' sources, the solver that picks their launch shapes
+# (tile heights, z-segments, steps per launch) and the compiler flags:
+# counters taken for other code are not reported
 KERNEL_SRC = (os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "kernels.hip"),
-              os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "lbm_kernels.h"))
+              os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "lbm_kernels.h"),
+              os.path.join(ROOT, "paper_1802_07525_amd", "csrc", "solver.cpp"))
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 

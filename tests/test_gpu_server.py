@@ -153,6 +153,65 @@ def test_server_graph_equals_direct_launch(srv_env):
         assert np.array_equal(g[i]["u"], d[i]["u"]) and np.array_equal(g[i]["c"], d[i]["c"])
 
 
+def _burst(lbm, ctx, specs, prep_threads):
+    """Submit every spec at once (tol 0, 600 + 600 steps each) and return
+    the results by spec index; every ticket must come back exactly once."""
+    need = [lbm.lbm_server_footprint(s[0], s[1], FP32S) for s in specs]
+    cfg = lbm.make_server_cfg(sum(sorted(need)[-6:]), max_slots=6, storage=FP32S, check_every=100,
+                              prep_threads=prep_threads, solo_nodes=-1)
+    srv = lbm.lbm_server_create(ctx, cfg)
+    try:
+        tickets = {}
+        for i, spec in enumerate(specs):
+            st, t = lbm.lbm_server_submit(srv, _request(lbm, spec, user=i, tol=0.0, max_iter=600))
+            assert st == 0, lbm.lbm_server_error(srv)
+            tickets[t] = i
+        assert lbm.lbm_server_drain(srv, 120.0) == 0, lbm.lbm_server_stats(srv)
+        res = {}
+        for _ in range(200):
+            for r in lbm.lbm_server_poll(srv, 16, 0.1):
+                assert tickets[r["ticket"]] not in res, "a request came back twice"
+                res[tickets[r["ticket"]]] = r
+            if len(res) == len(specs):
+                break
+        stats = lbm.lbm_server_stats(srv)
+    finally:
+        lbm.lbm_server_destroy(srv)
+    assert len(res) == len(specs) and stats["finished"] == len(specs) and stats["pool_used"] == 0
+    return res
+
+
+def test_server_burst_prepared_out_of_order(srv_env):
+    """Regression test of admission: preparation threads finish out of
+    ticket order (large masks take longer than small ones), and a request
+    prepared while the worker admitted a later ticket was once dropped (the
+    drain never returned) while the admitted one ran twice.  A burst of
+    mixed sizes is served with four preparation threads and again with one;
+    every request comes back once, with the same steps and fields."""
+    lbm, ctx = srv_env
+    rng = np.random.default_rng(31)
+    specs = []
+    for i in range(36):
+        nx = int(rng.choice([48, 64, 96, 160, 224]))
+        specs.append((nx, nx // 2, 0.3, 0.8, 0.01, 100 + i))
+    print("burst of", len(specs), "requests, 4 then 1 preparation threads", flush=True)
+    a = _burst(lbm, ctx, specs, 4)
+    b = _burst(lbm, ctx, specs, 1)
+    rejected = 0
+    for i in range(len(specs)):
+        ra, rb = a[i], b[i]
+        nx, ny, solid, _, _, seed = specs[i]
+        if not lbm.lbm_percolates(_mask(lbm, nx, ny, solid, seed)):
+            assert ra["status"] == rb["status"] == lbm.LBM_EINVAL
+            rejected += 1
+            continue
+        assert ra["status"] == rb["status"] == lbm.LBM_NOT_CONVERGED, (i, ra["status"], rb["status"])
+        assert ra["iters_fluid"] == rb["iters_fluid"] == 600 and ra["iters_ad"] == rb["iters_ad"] == 600
+        assert np.array_equal(ra["u"], rb["u"]) and np.array_equal(ra["c"], rb["c"])
+        assert np.array_equal(ra["flux"], rb["flux"])
+    assert 0 < rejected < len(specs) // 4  # media that do not percolate take the rejection path
+
+
 def test_served_request_matches_oracle(srv_env):
     lbm, ctx = srv_env
     spec = MIX[0]
