@@ -286,6 +286,7 @@ struct Job {
     char *staged = nullptr; // pinned result staging
     std::vector<float> u, c;
     double flux[10] = {0};
+    bool preparing = false; // a preparation thread is working on it
     int lane = LBM_LANE_BATCH;
     int first_status = LBM_OK;
     int64_t first_it_fluid = 0, first_it_ad = 0;
@@ -428,11 +429,21 @@ struct lbm_server {
                     return;
                 j = prep_q.front();
                 prep_q.pop_front();
+                j->preparing = true;
             }
             prepare(j);
             std::lock_guard<std::mutex> lk(mu);
-            if (failed || stopping)
-                continue; // already finished by fail(), or abandoned
+            j->preparing = false;
+            if (stopping)
+                continue; // abandoned: lbm_server_destroy frees it
+            if (failed) {
+                // fail() leaves the requests being prepared to their
+                // threads: ending one there could hand it to the caller,
+                // who may release it while it is still being prepared
+                end_by_device_locked(j, err);
+                cv_done.notify_all();
+                continue;
+            }
             if (j->status != LBM_OK) {
                 finish_locked(j);
             } else if (j->lane == LBM_LANE_SOLO) {
@@ -1095,7 +1106,20 @@ struct lbm_server {
             fail(std::string("HIP error in the serving loop: ") + hipGetErrorString(e));
     }
 
+    // caller holds mu
+    void end_by_device_locked(Job *j, const std::string &m)
+    {
+        j->status = LBM_EDEVICE;
+        j->msg = m;
+        j->phase = PH_DONE;
+        j->t_finish = now_s(t0);
+        ++n_finished;
+        finished.push_back(j);
+    }
+
     // Device failure: every request not yet finished ends with EDEVICE.
+    // Those a solo lane or a preparation thread is working on are ended by
+    // that thread when it is done with them.
     void fail(const std::string &m)
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -1103,14 +1127,10 @@ struct lbm_server {
         err = m;
         for (auto &kv : all) {
             Job *j = kv.second.get();
-            if (j->phase == PH_DONE || std::find(solo_cur.begin(), solo_cur.end(), j) != solo_cur.end())
-                continue; // a solo lane finishes its current request itself
-            j->status = LBM_EDEVICE;
-            j->msg = m;
-            j->phase = PH_DONE;
-            j->t_finish = now_s(t0);
-            ++n_finished;
-            finished.push_back(j);
+            if (j->phase == PH_DONE || j->preparing ||
+                std::find(solo_cur.begin(), solo_cur.end(), j) != solo_cur.end())
+                continue;
+            end_by_device_locked(j, m);
         }
         prep_q.clear();
         ready.clear();

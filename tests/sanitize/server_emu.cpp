@@ -73,6 +73,9 @@ static void emu_fail(const char *fmt, ...)
 
 // ------------------------------------------------------- HIP runtime
 static std::atomic<unsigned> g_stream_seed{12345};
+// device failure injection: once g_fail_at operations have been queued,
+// every further operation fails, as after a device fault
+static std::atomic<long long> g_ops{0}, g_fail_at{-1};
 
 struct ihipGraph {
     std::vector<std::function<void()>> ops;
@@ -125,6 +128,8 @@ struct ihipEvent_t {
 static hipError_t enqueue(hipStream_t s, std::function<void()> fn)
 {
     EMU_CHECK(s != nullptr, "work queued on the null stream");
+    if (g_fail_at.load() >= 0 && ++g_ops >= g_fail_at.load())
+        return hipErrorLaunchFailure;
     {
         std::lock_guard<std::mutex> lk(s->m);
         if (s->cap) {
@@ -755,7 +760,7 @@ namespace {
 struct Expect {
     int status, lane, first_status;
     long long it_f, it_a, first_f, first_a;
-    bool ad_ran;
+    bool ad_ran, first_ad_ran;
 };
 
 struct Attempt {
@@ -817,7 +822,8 @@ struct Config {
     size_t pool;
     int n_req;
     uint64_t seed;
-    int burst; // submit without pauses
+    int burst;          // submit without pauses
+    long long fail_after; // > 0: the device fails after this many queued operations
 };
 
 Expect expect(const lbm_request &r, const Config &c)
@@ -838,6 +844,7 @@ Expect expect(const lbm_request &r, const Config &c)
         e.first_status = a.overall;
         e.first_f = a.it_f;
         e.first_a = a.it_a;
+        e.first_ad_ran = a.ad_ran;
         a = attempt(r, LBM_FP32_SHIFTED, 100, lbmh::default_stall_checks(LBM_FP32_SHIFTED, 100));
     }
     e.status = a.overall;
@@ -896,12 +903,17 @@ void run_config(const Config &c)
     cfg.solo_lanes = c.lanes;
     lbm_server *s = nullptr;
     EMU_CHECK(lbm_server_create(ctx, &cfg, &s) == LBM_OK, "%s: server create: %s", c.name, lbm_last_error(ctx));
+    const bool failing = c.fail_after > 0;
+    if (failing) {
+        g_ops = 0;
+        g_fail_at = c.fail_after;
+    }
     const std::vector<lbm_request> reqs = make_requests(c);
     std::vector<Expect> exp;
     for (const auto &r : reqs)
         exp.push_back(expect(r, c));
 
-    std::atomic<int> submitted{0}, received{0}, bad_submit{0};
+    std::atomic<int> submitted{0}, received{0}, bad_submit{0}, accepted{0}, target{-1}, n_device{0};
     std::atomic<bool> stop_stats{false};
     std::thread stats([&] {
         while (!stop_stats.load()) {
@@ -917,7 +929,10 @@ void run_config(const Config &c)
             std::mt19937 rng(77 + k);
             for (size_t i = k; i < reqs.size(); i += NS) {
                 uint64_t t = 0;
-                if (lbm_server_submit(s, &reqs[i], &t) != LBM_OK)
+                const lbm_status st = lbm_server_submit(s, &reqs[i], &t);
+                if (st == LBM_OK)
+                    accepted.fetch_add(1);
+                else if (!(failing && st == LBM_EDEVICE))
                     bad_submit.fetch_add(1);
                 submitted.fetch_add(1);
                 if (!c.burst)
@@ -927,15 +942,30 @@ void run_config(const Config &c)
     std::vector<int> seen(reqs.size(), 0);
     std::thread poller([&] {
         std::vector<lbm_result> out(8);
-        while (received.load() < (int)reqs.size()) {
+        while (target.load() < 0 || received.load() < target.load()) {
             int n = 0;
             EMU_CHECK(lbm_server_poll(s, out.data(), (int)out.size(), &n, 0.05) == LBM_OK, "poll");
             for (int k = 0; k < n; ++k) {
                 lbm_result &r = out[k];
                 EMU_CHECK(r.user < reqs.size(), "%s: unknown user tag %llu", c.name, (unsigned long long)r.user);
                 const lbm_request &q = reqs[r.user];
-                const Expect &e = exp[r.user];
+                Expect e = exp[r.user];
+                if (failing && e.lane == LBM_LANE_ESCALATED && r.lane == LBM_LANE_SOLO) {
+                    // a solo-lane first attempt that ended after the failure
+                    // is returned as it is: nothing is escalated any more
+                    e.status = e.first_status;
+                    e.lane = LBM_LANE_SOLO;
+                    e.it_f = e.first_f;
+                    e.it_a = e.first_a;
+                    e.ad_ran = e.first_ad_ran;
+                }
                 EMU_CHECK(!seen[r.user]++, "%s: request %llu returned twice", c.name, (unsigned long long)r.user);
+                if (failing && r.status == LBM_EDEVICE) {
+                    n_device.fetch_add(1);
+                    lbm_result_release(s, &r);
+                    received.fetch_add(1);
+                    continue;
+                }
                 EMU_CHECK(r.status == e.status, "%s: request %llu status %d, expected %d (%s)", c.name,
                           (unsigned long long)r.user, r.status, e.status, r.message);
                 if (e.status != LBM_EINVAL) {
@@ -969,13 +999,32 @@ void run_config(const Config &c)
     for (auto &t : subs)
         t.join();
     EMU_CHECK(bad_submit.load() == 0, "%s: %d submissions refused", c.name, bad_submit.load());
+    target = accepted.load();
     const lbm_status d = lbm_server_drain(s, 120.0);
-    EMU_CHECK(d == LBM_OK, "%s: drain returned %d (stall)", c.name, (int)d);
+    if (failing) {
+        EMU_CHECK(d == LBM_EDEVICE, "%s: drain returned %d after a device failure", c.name, (int)d);
+        EMU_CHECK(strstr(lbm_server_error(s), "HIP error") != nullptr, "%s: error text '%s'", c.name,
+                  lbm_server_error(s));
+    } else {
+        EMU_CHECK(d == LBM_OK, "%s: drain returned %d (stall)", c.name, (int)d);
+    }
     poller.join();
+    g_fail_at = -1;
     stop_stats = true;
     stats.join();
     lbm_server_stats_t st;
     EMU_CHECK(lbm_server_stats(s, &st) == LBM_OK, "stats");
+    if (failing) {
+        EMU_CHECK(st.finished == (int64_t)accepted.load() && n_device.load() > 0,
+                  "%s: after the failure: %lld finished of %d accepted, %d failed", c.name, (long long)st.finished,
+                  accepted.load(), n_device.load());
+        lbm_server_destroy(s);
+        lbm_ctx_destroy(ctx);
+        printf("%s: %d of %zu requests accepted, %d ended by the device failure\n", c.name, accepted.load(),
+               reqs.size(), n_device.load());
+        fflush(stdout);
+        return;
+    }
     EMU_CHECK(st.finished == (int64_t)reqs.size() && st.active == 0 && st.queued == 0 && st.pool_used == 0,
               "%s: after the drain: finished %lld, active %lld, queued %lld, pool %llu", c.name,
               (long long)st.finished, (long long)st.active, (long long)st.queued, (unsigned long long)st.pool_used);
@@ -1001,12 +1050,18 @@ int main(int argc, char **argv)
     // name, storage, K, stall checks, inflight, direct, escalate, slots, solo lanes, prep threads,
     // solo nodes, pool, requests, seed, burst
     const Config cfgs[] = {
-        {"fp32s graphs", LBM_FP32_SHIFTED, 20, 5, 2, 0, 0, 8, 2, 2, 6000, 2 * MB, 40 * scale, 1, 0},
-        {"fp32s direct depth 3", LBM_FP32_SHIFTED, 16, 4, 3, 1, 0, 4, 1, 1, -1, 2 * MB, 30 * scale, 2, 0},
-        {"fp16s escalate", LBM_FP16_SHIFTED, 20, 5, 2, 0, 1, 8, 3, 3, 6000, 2 * MB, 40 * scale, 3, 0},
-        {"fp32 escalate depth 1", LBM_FP32, 12, 3, 1, 0, 1, 6, 2, 2, 9000, (size_t)3 * MB / 2, 30 * scale, 4, 0},
+        {"fp32s graphs", LBM_FP32_SHIFTED, 20, 5, 2, 0, 0, 8, 2, 2, 6000, 2 * MB, 40 * scale, 1, 0, 0},
+        {"fp32s direct depth 3", LBM_FP32_SHIFTED, 16, 4, 3, 1, 0, 4, 1, 1, -1, 2 * MB, 30 * scale, 2, 0, 0},
+        {"fp16s escalate", LBM_FP16_SHIFTED, 20, 5, 2, 0, 1, 8, 3, 3, 6000, 2 * MB, 40 * scale, 3, 0, 0},
+        {"fp32 escalate depth 1", LBM_FP32, 12, 3, 1, 0, 1, 6, 2, 2, 9000, (size_t)3 * MB / 2, 30 * scale, 4, 0, 0},
         // a burst prepared by four threads, which finish out of ticket order
-        {"fp32s burst", LBM_FP32_SHIFTED, 8, 3, 2, 0, 0, 3, 1, 4, -1, 4 * MB, 60 * scale, 5, 1},
+        {"fp32s burst", LBM_FP32_SHIFTED, 8, 3, 2, 0, 0, 3, 1, 4, -1, 4 * MB, 60 * scale, 5, 1, 0},
+        // the device fails while requests are queued, prepared, stepped,
+        // retiring and on the solo lanes: every accepted request still comes
+        // back once (its result, or EDEVICE) and the drain reports the failure
+        {"fp32s device failure", LBM_FP32_SHIFTED, 20, 5, 2, 0, 0, 6, 2, 4, 6000, 2 * MB, 40 * scale, 6, 1, 300},
+        {"fp16s escalate device failure", LBM_FP16_SHIFTED, 20, 5, 2, 1, 1, 6, 2, 4, 6000, 2 * MB, 40 * scale, 7, 1,
+         900},
     };
     for (const Config &c : cfgs)
         run_config(c);

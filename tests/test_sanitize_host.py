@@ -21,7 +21,12 @@ forms, under AddressSanitizer with UndefinedBehaviorSanitizer, and plainly
 several times over, since some interleavings are rare: the emulation found
 requests lost at admission (a request prepared out of ticket order between
 the worker's choice of the head of the ready queue and its removal), which
-left a drain waiting forever, in about one run in thirty.
+left a drain waiting forever, in about one run in thirty.  Two of its
+streams inject a device failure (every HIP call fails after a given number
+of queued operations): every accepted request must still come back once,
+with its result or EDEVICE, and the drain must report the failure.  Under
+AddressSanitizer that found a request freed by the caller while a
+preparation thread was still building its mask.
 """
 import os
 import shutil
