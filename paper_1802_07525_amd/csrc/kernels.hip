@@ -184,11 +184,11 @@ __device__ __forceinline__ void st(typename S::T *p, typename S::C v)
 }
 // Counter-based integer hash (the "lowbias32" mixer of C. Wellons) of a node
 // and a step; each direction then takes the next value of a Weyl sequence
-// from it (steps of 0x9E3779B9, 2^32 divided by the golden ratio) and uses
-// its top 13 bits.  Over the steps the hash makes each direction's addend
-// uniform and independent; within a node the sequence spreads the
-// directions' addends evenly.  (A 32-bit multiply per direction -- a
-// linear congruential step -- ran at a quarter of the add's rate.)
+// from it (steps of 0x9E3779B9, 2^32 divided by the golden ratio), whose top
+// 13 bits are the rounding addend.  Over the steps the hash makes each
+// direction's addend uniform and independent; within a node the sequence
+// spreads the directions' addends evenly.  (A 32-bit multiply per direction
+// -- a linear congruential step -- ran at a quarter of the add's rate.)
 __device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
 {
     unsigned int x = n * 0x9E3779B1u ^ t * 0xC2B2AE3Du;
@@ -199,11 +199,6 @@ __device__ __forceinline__ unsigned int sr_seed(unsigned int n, unsigned int t)
     x ^= x >> 16;
     return x;
 }
-__device__ __forceinline__ unsigned int sr_next(unsigned int &state)
-{
-    state += 0x9E3779B9u;
-    return state >> 19;
-}
 
 // Stored value of a population.  FP16 storage rounds stochastically: the 13
 // float mantissa bits below the FP16 mantissa get a uniform random addend
@@ -212,15 +207,23 @@ __device__ __forceinline__ unsigned int sr_next(unsigned int &state)
 // repeat the same error every step -- a constant source that slow modes
 // amplify by their relaxation time -- while these errors average to zero.
 // The addends depend only on (node, step, direction): runs are
-// reproducible.  (Values below the FP16 normal range, |v| < 2^-14, get the
-// remaining bits rounded to nearest by the conversion.)
+// reproducible.  gfx950 converts with stochastic rounding in one
+// instruction (v_cvt_sr_f16_f32): it adds the top 13 bits of the random
+// word below the FP16 mantissa and truncates -- bit for bit the add-and-cut
+// on the float's bits, checked on the device over 2^20 normal-range values
+// -- and below the FP16 normal range (|v| < 2^-14) it rounds at the
+// subnormal ulp, also without bias (means of 2^16 draws within sampling
+// noise), where the add-and-cut followed by an ordinary conversion rounded
+// to nearest.
 template <class S>
 __device__ __forceinline__ typename S::T pop_value(typename S::C v, unsigned int &rng)
 {
     if constexpr (sizeof(typename S::T) == 2) {
-        unsigned int b = __float_as_uint(v);
-        b = (b + sr_next(rng)) & ~0x1FFFu;
-        return static_cast<typename S::T>(__uint_as_float(b));
+        typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+        rng += 0x9E3779B9u;
+        half2v any;
+        any = __builtin_nondeterministic_value(any); // the other half is not used
+        return __builtin_amdgcn_cvt_sr_f16_f32(any, v, rng, false)[0];
     } else {
         return static_cast<typename S::T>(v);
     }
