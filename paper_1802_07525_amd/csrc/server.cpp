@@ -518,7 +518,7 @@ struct lbm_server {
             updates += (double)j->it_fluid * j->n_fluid + (double)j->it_ad * j->n_ad;
         else
             ++n_rejected;
-        if (j->lane != LBM_LANE_BATCH && j->status != LBM_EDEVICE) {
+        if (j->lane != LBM_LANE_BATCH && j->status == LBM_OK) { // solved there
             ++n_solo;
             n_escalated += j->lane == LBM_LANE_ESCALATED;
         }

@@ -1036,6 +1036,9 @@ void run_config(const Config &c)
         solo += e.status != LBM_EINVAL && e.lane == LBM_LANE_SOLO;
         inval += e.status == LBM_EINVAL;
     }
+    EMU_CHECK(st.rejected == inval && st.solo == solo + esc && st.escalated == esc,
+              "%s: statistics: rejected %lld, solo %lld, escalated %lld; expected %d, %d, %d", c.name,
+              (long long)st.rejected, (long long)st.solo, (long long)st.escalated, inval, solo + esc, esc);
     printf("%s: %zu requests (%d solo, %d escalated, %d rejected masks), %lld chunks\n", c.name, reqs.size(), solo,
            esc, inval, (long long)st.chunks);
     fflush(stdout);
