@@ -474,6 +474,10 @@ def served_main(args):
                        "solo_lanes": args.solo_lanes or 2},
             "served": {"completed": len(done), "failed": len(results) - len(done) + len(refused),
                        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                       "p50_by_lane_s": {name: float(np.percentile([d["t_finish"] - d["t_submit"] for d in done
+                                                                    if d["lane"] == k], 50))
+                                         for k, name in ((0, "batch"), (1, "solo"), (2, "escalated"))
+                                         if any(d["lane"] == k for d in done)},
                        "mean_s": float(lat.mean()), "makespan_s": makespan,
                        "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
                        "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,

@@ -39,6 +39,7 @@
 // tiles), and, when escalation is on, reduced-storage requests whose
 // batched solves did not both end OK, solved again in FP32-shifted storage.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -259,6 +260,18 @@ private:
     std::deque<Use> uses_;
     std::vector<hipEvent_t> spare_;
 };
+
+// Tile height of the batch: the kernels' choice for the storage form, or 4
+// for every form when LBM_SERVED_TILE_Y = 4 (paired 64 x 4 launches; tuning
+// and comparisons, read once per process)
+int served_tile_ty(int storage)
+{
+    static const bool pair_only = [] {
+        const char *e = getenv("LBM_SERVED_TILE_Y");
+        return e && atoi(e) == 4;
+    }();
+    return pair_only ? 4 : lbmk::srv_tile_ty(storage);
+}
 
 enum { PH_QUEUED = 0, PH_FLUID = 1, PH_AD = 2, PH_RETIRING = 3, PH_DONE = 4 };
 
@@ -497,7 +510,7 @@ struct lbm_server {
             j->n_fluid += d[n] & 1u;
             j->n_ad += (d[n] >> aab) & 1u;
         }
-        j->tiles = lbmk::pair_tiles(j->geo, lbmk::srv_tile_ty(cfg.storage));
+        j->tiles = lbmk::pair_tiles(j->geo, served_tile_ty(cfg.storage));
         if (!may_escalate()) {
             j->cls.clear();
             j->cls.shrink_to_fit();
@@ -799,7 +812,7 @@ struct lbm_server {
         // odd, so that a chunk has an even number of launches.  The check
         // is taken on the last launch.
         std::vector<int> plan;
-        const bool wide = lbmk::srv_tile_ty(cfg.storage) == 16;
+        const bool wide = served_tile_ty(cfg.storage) == 16;
         if (wide) {
             const int m = K / 4;
             plan.assign((size_t)(m & 1 ? 2 : 0), 2);
@@ -1234,7 +1247,7 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     // least 54 pool bytes; ragged tiles at the domain edges add at most
     // ntx + nty per request.  The largest captured grid (the power of two
     // at or above part_cap) times the block size stays within 2^31 threads.
-    const size_t tile_nodes = (size_t)64 * lbmk::srv_tile_ty(c.storage);
+    const size_t tile_nodes = (size_t)64 * served_tile_ty(c.storage);
     const size_t pc = c.pool_bytes / (tile_nodes * 54) + (size_t)c.max_slots * 1024 + 1024;
     s->part_cap = (int)std::min<size_t>(pc, ((size_t)1 << 31) / tile_nodes);
     auto cleanup = [&](lbm_status st) {
@@ -1336,7 +1349,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
         if (s->cfg.solo_nodes > 0 && N >= s->cfg.solo_nodes) // < 0: no solo lane
             j->lane = LBM_LANE_SOLO;
         else if (j->lay.total > s->cfg.pool_bytes ||
-                 lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), lbmk::srv_tile_ty(s->cfg.storage)) >
+                 lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), served_tile_ty(s->cfg.storage)) >
                      s->part_cap)
             m = "request larger than the server pool";
         if (m.empty() && r->cls)
