@@ -566,10 +566,12 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *p, int n_hours, uin
  * is free and their device footprint (lbm_server_footprint) fits the pool;
  * every admitted request's populations stay resident and all of them are
  * stepped by the same kernel launches, each in its own phase, in chunks of
- * check_every steps captured once as a HIP graph (FP32 and FP32-shifted
- * storage: four steps per launch over 64 x 16 tiles, two in the first two
- * launches when check_every / 4 is odd; FP16 storage and FP32 storage with
- * FP64 arithmetic: two steps per launch over 64 x 4 tiles).  The largest
+ * check_every steps captured once as HIP graphs (two steps per launch over
+ * 64 x 4 tiles; for FP32 and FP32-shifted storage, while the batch holds at
+ * least 256 tiles of 64 x 16 nodes and no solo lane is solving, four steps
+ * per launch over such tiles, two in the first two launches when
+ * check_every / 4 is odd -- the choice is made per chunk and does not
+ * change any result).  The largest
  * request the server takes is bounded by pool_bytes and by
  * 2^31 / (64 * tile height) tiles in flight.  A request's arithmetic
  * is that of lbm_solver_fluid followed by lbm_solver_ad (cold, same

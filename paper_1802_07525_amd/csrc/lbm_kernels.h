@@ -279,9 +279,9 @@ struct SrvTable {
 // tab->total_tiles (the extra blocks exit).
 hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                     unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st);
-// Tile height of the served launches: 16 (64 x 16 tiles, 1024-thread
-// blocks, srv_stepN) for FP32 and FP32-shifted storage, 4 (srv_step) for
-// FP16 storage and FP32 storage with FP64 arithmetic.
+// Widest tile height of the served launches: 16 (64 x 16 tiles,
+// 1024-thread blocks, srv_stepN) for FP32 and FP32-shifted storage, 4
+// (srv_step only) for FP16 storage and FP32 storage with FP64 arithmetic.
 int srv_tile_ty(int storage);
 // ns steps (2 or 4) of every request in tab over 64 x 16 tiles: launch j of
 // the current chunk, whose first step is t_off within the chunk.  FP32

@@ -281,7 +281,7 @@ struct Job {
     std::vector<uint8_t> cls;
     std::vector<uint16_t> desc;
     lbmk::Geo geo{};
-    int tiles = 0; // blocks of the two-step kernels over this request
+    int tiles = 0, tiles_wide = 0; // blocks of the batch launches over it: 64 x 4, 64 x 16 tiles
     int64_t n_fluid = 0, n_ad = 0;
     Layout lay{};
     double t_submit = 0, t_admit = 0, t_finish = 0;
@@ -386,8 +386,21 @@ struct lbm_server {
     // one covering the table's tiles is launched (extra blocks exit at once)
     static const int MIN_GRID = 64;
     std::vector<hipGraph_t> graphs;
-    std::vector<hipGraphExec_t> execs;
+    std::vector<hipGraphExec_t> execs[2]; // [0]: 64 x 4 tiles, [1]: 64 x 16
     int table_tiles = 0;
+    // Tile form of each chunk: 64 x 16 tiles (four steps a launch) for the
+    // FP32 forms while the batch holds at least wide_min such tiles and no
+    // solo lane is solving; otherwise paired 64 x 4 launches.  On the
+    // seeded stream at 50 req/s the batch alone served 1.41x faster with
+    // the wide form, but beside busy solo lanes the wide form doubled the
+    // batch requests' median latency for 4% more throughput, and with few
+    // tiles the paired launches finish a chunk sooner.  Both forms run the
+    // same per-node code on the same buffers and step counts, so a
+    // request's results do not depend on the forms its chunks took.
+    std::atomic<int> solo_active{0}; // solo lanes solving a request
+    bool wide_ok = false;
+    int wide_min = 256, wide_grid_max = 0;
+    int table_ty = 4;
 
     // host state owned by the worker
     PoolAlloc alloc;
@@ -399,7 +412,7 @@ struct lbm_server {
     std::atomic<long long> chunks{0}; // also read by lbm_server_stats
     long long head = 0, tail = 0;
     Job *slot_job[lbmk::SRV_MAX_SLOTS] = {};
-    int tiles_used = 0;
+    int tiles_used = 0, tiles_used_wide = 0;
     bool table_dirty = false;
     int n_retiring = 0;
 
@@ -510,7 +523,8 @@ struct lbm_server {
             j->n_fluid += d[n] & 1u;
             j->n_ad += (d[n] >> aab) & 1u;
         }
-        j->tiles = lbmk::pair_tiles(j->geo, served_tile_ty(cfg.storage));
+        j->tiles = lbmk::pair_tiles(j->geo, 4);
+        j->tiles_wide = wide_ok ? lbmk::pair_tiles(j->geo, 16) : j->tiles;
         if (!may_escalate()) {
             j->cls.clear();
             j->cls.shrink_to_fit();
@@ -614,6 +628,7 @@ struct lbm_server {
         j->t_admit = now_s(t0);
         slot_job[sid] = j;
         tiles_used += j->tiles;
+        tiles_used_wide += j->tiles_wide;
         table_dirty = true;
         return hipSuccess;
     }
@@ -697,6 +712,7 @@ struct lbm_server {
         j->phase = PH_RETIRING;
         slot_job[j->sid] = nullptr;
         tiles_used -= j->tiles;
+        tiles_used_wide -= j->tiles_wide;
         {
             std::lock_guard<std::mutex> lk(mu);
             alloc.release(j->off, j->lay.total);
@@ -741,7 +757,7 @@ struct lbm_server {
         finish_locked(j);
     }
 
-    hipError_t write_table()
+    hipError_t write_table(int ty)
     {
         lbmk::SrvTable t{};
         int e = 0, tiles = 0;
@@ -751,7 +767,7 @@ struct lbm_server {
                 continue;
             t.begin[e] = tiles;
             t.slot[e] = s;
-            tiles += j->tiles;
+            tiles += ty == 16 ? j->tiles_wide : j->tiles;
             ++e;
         }
         t.begin[e] = tiles;
@@ -762,9 +778,10 @@ struct lbm_server {
         for (int k = 0; k < e; ++k)
             if (t.begin[k] > t.begin[k + 1])
                 return hipErrorInvalidValue;
-        if (tiles > part_cap || tiles != tiles_used)
+        if (tiles > part_cap || tiles != (ty == 16 ? tiles_used_wide : tiles_used))
             return hipErrorInvalidValue;
         table_tiles = tiles;
+        table_ty = ty;
         table_dirty = false;
         return lbmk::srv_table_set(d_tab, t, stream);
     }
@@ -780,15 +797,16 @@ struct lbm_server {
     hipError_t launch_chunk()
     {
         hipError_t e;
-        if (!execs.empty()) {
+        const std::vector<hipGraphExec_t> &ex = execs[table_ty == 16 ? 1 : 0];
+        if (!ex.empty()) {
             size_t k = 0;
-            while ((MIN_GRID << k) < table_tiles && k + 1 < execs.size())
+            while ((MIN_GRID << k) < table_tiles && k + 1 < ex.size())
                 ++k;
             if ((MIN_GRID << k) < table_tiles) // the grid must cover every tile of the table
                 return hipErrorInvalidValue;
-            if ((e = hipGraphLaunch(execs[k], stream)) != hipSuccess)
+            if ((e = hipGraphLaunch(ex[k], stream)) != hipSuccess)
                 return e;
-        } else if ((e = enqueue_chunk(std::max(table_tiles, 1))) != hipSuccess) {
+        } else if ((e = enqueue_chunk(std::max(table_tiles, 1), table_ty == 16)) != hipSuccess) {
             return e;
         }
         const int r = (int)(head % RING);
@@ -803,7 +821,7 @@ struct lbm_server {
         return hipSuccess;
     }
 
-    hipError_t enqueue_chunk(int grid)
+    hipError_t enqueue_chunk(int grid, bool wide)
     {
         hipError_t e;
         // Steps per launch: FP16 storage and FP32 storage with FP64
@@ -812,7 +830,6 @@ struct lbm_server {
         // odd, so that a chunk has an even number of launches.  The check
         // is taken on the last launch.
         std::vector<int> plan;
-        const bool wide = served_tile_ty(cfg.storage) == 16;
         if (wide) {
             const int m = K / 4;
             plan.assign((size_t)(m & 1 ? 2 : 0), 2);
@@ -890,7 +907,7 @@ struct lbm_server {
                         sid = s;
                         break;
                     }
-                if (sid < 0 || tiles_used + j->tiles > part_cap)
+                if (sid < 0 || tiles_used + j->tiles > part_cap) // 64 x 4: the most tiles
                     return hipSuccess;
                 // the pool counters are read by lbm_server_stats
                 if (!alloc.alloc(j->lay.total, &j->off))
@@ -913,7 +930,11 @@ struct lbm_server {
             return e;
         if ((e = admit_ready()) != hipSuccess)
             return e;
-        if (table_dirty && (e = write_table()) != hipSuccess)
+        const int ty = wide_ok && solo_active.load() == 0 && tiles_used_wide >= wide_min &&
+                               tiles_used_wide <= wide_grid_max
+                           ? 16
+                           : 4;
+        if ((table_dirty || ty != table_ty) && (e = write_table(ty)) != hipSuccess)
             return e;
         const bool running = any_running();
         if (running && head - tail < depth) {
@@ -988,7 +1009,9 @@ struct lbm_server {
                 if (j->t_admit == 0)
                     j->t_admit = now_s(t0);
             }
+            ++solo_active;
             solve_alone(j, solo_ctx[lane]);
+            --solo_active;
             std::lock_guard<std::mutex> lk(mu);
             lane_leave_locked();
             solo_cur[lane] = nullptr;
@@ -1243,13 +1266,20 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
     s->window = c.stall_checks < 0 ? 0 : (c.stall_checks > 0 ? c.stall_checks : default_stall_checks(c.storage, s->K));
     s->depth = c.inflight;
     s->t0 = std::chrono::steady_clock::now();
-    // tiles: each holds 64 x ty nodes (one per thread of a block) of at
-    // least 54 pool bytes; ragged tiles at the domain edges add at most
-    // ntx + nty per request.  The largest captured grid (the power of two
-    // at or above part_cap) times the block size stays within 2^31 threads.
-    const size_t tile_nodes = (size_t)64 * served_tile_ty(c.storage);
-    const size_t pc = c.pool_bytes / (tile_nodes * 54) + (size_t)c.max_slots * 1024 + 1024;
-    s->part_cap = (int)std::min<size_t>(pc, ((size_t)1 << 31) / tile_nodes);
+    // tiles: each 64 x 4 tile holds 256 nodes (one per thread of a block)
+    // of at least 54 pool bytes; ragged tiles at the domain edges add at
+    // most ntx + nty per request.  The largest captured grid (the power of
+    // two at or above part_cap) times the block size stays within 2^31
+    // threads; 64 x 16 tiles (1024 threads) are a quarter as many, plus the
+    // ragged ones, and their form is taken only while the table fits the
+    // largest wide grid.
+    const size_t pc = c.pool_bytes / ((size_t)256 * 54) + (size_t)c.max_slots * 1024 + 1024;
+    s->part_cap = (int)std::min<size_t>(pc, ((size_t)1 << 31) / 256);
+    s->wide_ok = served_tile_ty(c.storage) == 16;
+    if (const char *ev = getenv("LBM_SERVED_WIDE_MIN_TILES")) // tuning and tests
+        if (atoi(ev) > 0)
+            s->wide_min = atoi(ev);
+    s->wide_grid_max = 1 << 21; // direct launches: 2^31 threads of 1024
     auto cleanup = [&](lbm_status st) {
         lbm_server_destroy(s.release());
         return st;
@@ -1304,22 +1334,27 @@ lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server
         // run time, so admissions and retirements never re-capture
         if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
             return cleanup(hip_err(ctx, e, "server init"));
-        for (int64_t grid = lbm_server::MIN_GRID;; grid *= 2) {
-            hipGraph_t g = nullptr;
-            hipGraphExec_t x = nullptr;
-            if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                return cleanup(hip_err(ctx, e, "graph capture"));
-            hipError_t le = s->enqueue_chunk((int)grid);
-            e = hipStreamEndCapture(s->stream, &g);
-            if (g)
-                s->graphs.push_back(g);
-            if (le != hipSuccess || e != hipSuccess)
-                return cleanup(hip_err(ctx, le != hipSuccess ? le : e, "graph capture"));
-            if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
-                return cleanup(hip_err(ctx, e, "graph instantiate"));
-            s->execs.push_back(x);
-            if (grid >= s->part_cap)
-                break;
+        for (int f = 0; f < (s->wide_ok ? 2 : 1); ++f) {
+            const int64_t grid_cap = f ? ((int64_t)1 << 21) : ((int64_t)1 << 23);
+            for (int64_t grid = lbm_server::MIN_GRID;; grid *= 2) {
+                hipGraph_t g = nullptr;
+                hipGraphExec_t x = nullptr;
+                if ((e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                    return cleanup(hip_err(ctx, e, "graph capture"));
+                hipError_t le = s->enqueue_chunk((int)grid, f == 1);
+                e = hipStreamEndCapture(s->stream, &g);
+                if (g)
+                    s->graphs.push_back(g);
+                if (le != hipSuccess || e != hipSuccess)
+                    return cleanup(hip_err(ctx, le != hipSuccess ? le : e, "graph capture"));
+                if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess)
+                    return cleanup(hip_err(ctx, e, "graph instantiate"));
+                s->execs[f].push_back(x);
+                if (f)
+                    s->wide_grid_max = (int)grid;
+                if (grid >= s->part_cap || grid >= grid_cap)
+                    break;
+            }
         }
     }
     if ((e = hipStreamSynchronize(s->stream)) != hipSuccess)
@@ -1349,8 +1384,7 @@ lbm_status lbm_server_submit(lbm_server *s, const lbm_request *r, uint64_t *tick
         if (s->cfg.solo_nodes > 0 && N >= s->cfg.solo_nodes) // < 0: no solo lane
             j->lane = LBM_LANE_SOLO;
         else if (j->lay.total > s->cfg.pool_bytes ||
-                 lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), served_tile_ty(s->cfg.storage)) >
-                     s->part_cap)
+                 lbmk::pair_tiles(lbmk::make_geo(r->nx, r->ny, 1), 4) > s->part_cap)
             m = "request larger than the server pool";
         if (m.empty() && r->cls)
             j->cls.assign(r->cls, r->cls + N);
@@ -1489,8 +1523,9 @@ void lbm_server_destroy(lbm_server *s)
     s->res_ring.reclaim = nullptr;
     s->up_ring.destroy();
     s->res_ring.destroy();
-    for (hipGraphExec_t x : s->execs)
-        (void)hipGraphExecDestroy(x);
+    for (auto &ex : s->execs)
+        for (hipGraphExec_t x : ex)
+            (void)hipGraphExecDestroy(x);
     for (hipGraph_t g : s->graphs)
         (void)hipGraphDestroy(g);
     for (int k = 0; k < lbm_server::RING; ++k)

@@ -76,6 +76,8 @@ static std::atomic<unsigned> g_stream_seed{12345};
 // device failure injection: once g_fail_at operations have been queued,
 // every further operation fails, as after a device fault
 static std::atomic<long long> g_ops{0}, g_fail_at{-1};
+// launches of the batched step per tile form (64 x 4, 64 x 16)
+static std::atomic<long long> g_launch_pair{0}, g_launch_wide{0};
 
 struct ihipGraph {
     std::vector<std::function<void()>> ops;
@@ -632,15 +634,20 @@ static void emu_step(int storage, int mode, int ns, const SrvSlot *slots, const 
 hipError_t srv_step(int storage, int mode, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                     unsigned long long *part, int part_cap, int j, int blocks, hipStream_t st)
 {
-    return enqueue(st, [=] { emu_step(storage, mode, 2, slots, tab, ctrl, part, part_cap, j, 2 * j, blocks, 4); });
+    return enqueue(st, [=] {
+        g_launch_pair.fetch_add(1);
+        emu_step(storage, mode, 2, slots, tab, ctrl, part, part_cap, j, 2 * j, blocks, 4);
+    });
 }
 hipError_t srv_stepN(int storage, int mode, int ns, const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl,
                      unsigned long long *part, int part_cap, int j, int t_off, int blocks, hipStream_t st)
 {
     if (srv_tile_ty(storage) != 16 || (ns != 2 && ns != 4))
         return hipErrorInvalidValue;
-    return enqueue(st,
-                   [=] { emu_step(storage, mode, ns, slots, tab, ctrl, part, part_cap, j, t_off, blocks, 16); });
+    return enqueue(st, [=] {
+        g_launch_wide.fetch_add(1);
+        emu_step(storage, mode, ns, slots, tab, ctrl, part, part_cap, j, t_off, blocks, 16);
+    });
 }
 hipError_t srv_decide(const SrvSlot *slots, const SrvTable *tab, Ctrl *ctrl, const unsigned long long *part,
                       int part_cap, hipStream_t st)
@@ -1039,8 +1046,9 @@ void run_config(const Config &c)
     EMU_CHECK(st.rejected == inval && st.solo == solo + esc && st.escalated == esc,
               "%s: statistics: rejected %lld, solo %lld, escalated %lld; expected %d, %d, %d", c.name,
               (long long)st.rejected, (long long)st.solo, (long long)st.escalated, inval, solo + esc, esc);
-    printf("%s: %zu requests (%d solo, %d escalated, %d rejected masks), %lld chunks\n", c.name, reqs.size(), solo,
-           esc, inval, (long long)st.chunks);
+    printf("%s: %zu requests (%d solo, %d escalated, %d rejected masks), %lld chunks; launches so far: %lld paired, "
+           "%lld wide\n", c.name, reqs.size(), solo, esc, inval, (long long)st.chunks, g_launch_pair.load(),
+           g_launch_wide.load());
     fflush(stdout);
 }
 

@@ -87,7 +87,9 @@ def _emu_build(tmp_path, name, compiler, flags):
 
 
 def _emu_run(exe, scale, ty, extra_env=None):
-    env = dict(os.environ, EMU_SERVED_TILE_TY=str(ty), **(extra_env or {}))
+    # ty 16: the FP32 forms may take 64 x 16 tiles; the server then switches
+    # between the forms as its table crosses 12 such tiles
+    env = dict(os.environ, EMU_SERVED_TILE_TY=str(ty), LBM_SERVED_WIDE_MIN_TILES="12", **(extra_env or {}))
     out = _run([exe, str(scale)], env=env, timeout=600)
     assert out.strip().endswith("ok"), out[-2000:]
     return out
@@ -97,8 +99,9 @@ def _emu_run(exe, scale, ty, extra_env=None):
 @pytest.mark.skipif(not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime.h")),
                     reason="no HIP headers")
 def test_server_emulation_under_tsan(tmp_path):
-    """Both served tile forms: 64 x 4 paired launches and the 64 x 16
-    four-step plan (two-step launches first when K / 4 is odd)."""
+    """Both served tile forms: 64 x 4 paired launches only, and chunks that
+    switch between those and the 64 x 16 four-step plan (two-step launches
+    first when K / 4 is odd) as the table grows and shrinks."""
     exe = _emu_build(tmp_path, "emu_tsan", CLANG, ["-O1", "-fsanitize=thread"])
     for ty in (4, 16):
         _emu_run(exe, 2, ty, {"TSAN_OPTIONS": "halt_on_error=1:abort_on_error=1"})
