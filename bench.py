@@ -602,7 +602,7 @@ def main():
                          "and a 1 GiB copy (counter calibration) instead of the solves")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the served stream and slab decomposition would shard across GPUs; "
               "they are not built).", file=sys.stderr)
         sys.exit(2)
