@@ -23,7 +23,7 @@
  *   - the flow domain: FLUID nodes linked to the outlet column (closed
  *     pores carry no steady flow; reading of Sec. 2.1.1 on the Sec. 3 pore
  *     space);
- *   - steady-state loops (run "until an equilibrium is reached", Sec. 3);
+ *   - steady-state loops (each solver run to equilibrium, Sec. 3);
  *   - seeded geometry (random porous electrode, Sec. 3), biofilm layer,
  *     link masks, percolation and the simplified biofilm growth of the
  *     coupled loop (Sec. 2.3 re-solves fluid and substrate after each
@@ -565,7 +565,7 @@ int orc_fluid_fluxes(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 }
 
 /* Steady-state driver shared by both solvers' loops: residual bookkeeping.
- * Reading of "run until an equilibrium is reached" (Sec. 3): at checks
+ * Reading of running each solver to equilibrium (Sec. 3): at checks
  * t = K, 2K, ... the residual is the largest change per step over the check
  * interval, r(t) = max over active nodes and components of
  * |X(t) - X(t-K)| / (K * scale), X the moments of the stored state (X(0)
@@ -969,7 +969,7 @@ int orc_ad_solve(int lat_id, int nx, int ny, int nz, const uint8_t *cls,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Seeded geometry.  The paper's electrode is "a random geometry" (Sec. 3)
+/* Seeded geometry.  The paper's electrode is a randomly generated medium (Sec. 3)
  * whose figure is not available; these generators produce seeded stand-ins
  * with integer arithmetic only, so that two independent implementations
  * agree byte for byte.                                                      */

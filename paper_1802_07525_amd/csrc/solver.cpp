@@ -1,10 +1,10 @@
 // solver.cpp -- solver objects: device state, steady-state loops, fields,
 // cell updates, checkpoint/resume and the coupled biofilm loop.
 //
-// Steady loop.  The paper runs each LBM "until an equilibrium is reached"
-// (Sec. 3).  Here a solve enqueues chunks of K steps; the last step of each
-// chunk reduces the residual max |U(t) - U(t-K)| / (K |u_in|) on the device
-// against the moments saved at the previous check, and a one-thread kernel
+// Steady loop.  The paper runs each LBM to equilibrium (Sec. 3).  Here a
+// solve enqueues chunks of K steps; the last step of each chunk reduces the
+// residual max |U(t) - U(t-K)| / (K |u_in|) on the device against the
+// moments saved at the previous check, and a one-thread kernel
 // applies the stop rule and raises a stop flag that every later step kernel
 // honours by returning at once.  The host copies the
 // control block into pinned memory after each chunk and keeps at most three

@@ -1,6 +1,6 @@
 """Pins of the oracle's stop rule and of its coupled loop (CPU only).
 
-The paper runs each lattice Boltzmann solver "until an equilibrium" (Sec. 3)
+The paper runs each lattice Boltzmann solver to equilibrium (Sec. 3)
 and re-converges both after every biofilm update (the model loop of Sec. 2).
 The reading made precise: at checks t = K, 2K, ... the residual is the
 largest change per step over the check interval; the solve stops at the
