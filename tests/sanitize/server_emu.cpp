@@ -1052,6 +1052,44 @@ void run_config(const Config &c)
     fflush(stdout);
 }
 
+// Shutdown with work in flight: requests queued, being prepared, stepped,
+// retiring, on the solo lanes and finished but not polled, some results
+// polled and not released.  lbm_server_destroy must stop every thread and
+// free everything (the sanitizers check the rest).
+void run_destroy_in_flight(int storage, uint64_t seed, int wait_ms)
+{
+    lbm_ctx *ctx = nullptr;
+    EMU_CHECK(lbm_ctx_create(0, nullptr, &ctx) == LBM_OK, "context");
+    lbm_server_cfg cfg{};
+    cfg.pool_bytes = (size_t)2 << 20;
+    cfg.max_slots = 6;
+    cfg.storage = storage;
+    cfg.check_every = 20;
+    cfg.stall_checks = 5;
+    cfg.prep_threads = 3;
+    cfg.escalate = storage == LBM_FP16_SHIFTED;
+    cfg.solo_nodes = 6000;
+    cfg.solo_lanes = 2;
+    lbm_server *s = nullptr;
+    EMU_CHECK(lbm_server_create(ctx, &cfg, &s) == LBM_OK, "server create: %s", lbm_last_error(ctx));
+    Config c{"destroy in flight", storage, 20, 5, 2, 0, 0, 6, 2, 3, 6000, (size_t)2 << 20, 60, seed, 1, 0};
+    const std::vector<lbm_request> reqs = make_requests(c);
+    for (const auto &r : reqs) {
+        uint64_t t = 0;
+        EMU_CHECK(lbm_server_submit(s, &r, &t) == LBM_OK, "submit: %s", lbm_server_error(s));
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(wait_ms));
+    lbm_result out[4];
+    int n = 0;
+    EMU_CHECK(lbm_server_poll(s, out, 4, &n, 0.0) == LBM_OK, "poll");
+    if (n > 1)
+        lbm_result_release(s, &out[0]); // the others stay unreleased
+    lbm_server_destroy(s);
+    lbm_ctx_destroy(ctx);
+    printf("destroy in flight (storage %d, after %d ms): %d results polled before\n", storage, wait_ms, n);
+    fflush(stdout);
+}
+
 } // namespace
 
 int main(int argc, char **argv)
@@ -1076,6 +1114,8 @@ int main(int argc, char **argv)
     };
     for (const Config &c : cfgs)
         run_config(c);
+    for (int w : {0, 3, 30})
+        run_destroy_in_flight(w == 3 ? LBM_FP16_SHIFTED : LBM_FP32_SHIFTED, 11 + (uint64_t)w, w);
     printf("ok\n");
     return 0;
 }

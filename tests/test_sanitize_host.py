@@ -26,7 +26,9 @@ streams inject a device failure (every HIP call fails after a given number
 of queued operations): every accepted request must still come back once,
 with its result or EDEVICE, and the drain must report the failure.  Under
 AddressSanitizer that found a request freed by the caller while a
-preparation thread was still building its mask.
+preparation thread was still building its mask.  Each run ends by
+destroying servers with work in flight (queued, being prepared, stepped,
+retiring, on the solo lanes, finished and unpolled, polled and unreleased).
 """
 import os
 import shutil
