@@ -480,7 +480,8 @@ def served_main(args):
                                          if any(d["lane"] == k for d in done)},
                        "mean_s": float(lat.mean()), "makespan_s": makespan,
                        "req_per_s": len(done) / makespan, "busy_s": stats["busy_seconds"],
-                       "chunks": stats["chunks"], "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
+                       "chunks": stats["chunks"], "chunks_wide": stats["chunks_wide"],
+                       "pool_peak_gb": stats["pool_peak"] / 2 ** 30,
                        "lanes": {"batch": int(sum(1 for d in results.values() if d["lane"] == 0)),
                                  "solo": int(sum(1 for d in results.values() if d["lane"] == 1)),
                                  "escalated": int(sum(1 for d in results.values() if d["lane"] == 2))},

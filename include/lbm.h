@@ -658,6 +658,7 @@ typedef struct {
     double clock;           /* seconds since creation */
     int64_t solo, escalated; /* finished requests solved on the solo lane, of which
                                 escalated */
+    int64_t chunks_wide;   /* chunks of `chunks` taken over 64 x 16 tiles */
 } lbm_server_stats_t;
 
 /* Device bytes one request of this size takes from the pool. */

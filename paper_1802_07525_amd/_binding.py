@@ -99,7 +99,7 @@ class lbm_server_stats_t(ct.Structure):
                 ("pool_bytes", ct.c_uint64), ("pool_used", ct.c_uint64),
                 ("pool_peak", ct.c_uint64), ("lattice_updates", ct.c_double),
                 ("busy_seconds", ct.c_double), ("clock", ct.c_double),
-                ("solo", ct.c_int64), ("escalated", ct.c_int64)]
+                ("solo", ct.c_int64), ("escalated", ct.c_int64), ("chunks_wide", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

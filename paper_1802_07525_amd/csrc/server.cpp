@@ -409,7 +409,7 @@ struct lbm_server {
     static const int RING = 8;
     hipEvent_t ev_snap[RING] = {};
     long long snap_chunk[RING] = {};
-    std::atomic<long long> chunks{0}; // also read by lbm_server_stats
+    std::atomic<long long> chunks{0}, chunks_wide{0}; // also read by lbm_server_stats
     long long head = 0, tail = 0;
     Job *slot_job[lbmk::SRV_MAX_SLOTS] = {};
     int tiles_used = 0, tiles_used_wide = 0;
@@ -817,6 +817,7 @@ struct lbm_server {
         if ((e = hipEventRecord(ev_snap[r], stream)) != hipSuccess)
             return e;
         snap_chunk[r] = chunks++;
+        chunks_wide += table_ty == 16;
         ++head;
         return hipSuccess;
     }
@@ -1484,6 +1485,7 @@ lbm_status lbm_server_stats(lbm_server *s, lbm_server_stats_t *o)
     o->clock = now_s(s->t0);
     o->solo = s->n_solo;
     o->escalated = s->n_escalated;
+    o->chunks_wide = s->chunks_wide;
     return LBM_OK;
 }
 

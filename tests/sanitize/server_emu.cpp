@@ -1043,12 +1043,15 @@ void run_config(const Config &c)
         solo += e.status != LBM_EINVAL && e.lane == LBM_LANE_SOLO;
         inval += e.status == LBM_EINVAL;
     }
+    const bool wide_possible = emu::served_ty() == 16 && c.storage != LBM_FP16_SHIFTED;
+    EMU_CHECK(st.chunks_wide <= st.chunks && (wide_possible || st.chunks_wide == 0),
+              "%s: %lld of %lld chunks wide", c.name, (long long)st.chunks_wide, (long long)st.chunks);
     EMU_CHECK(st.rejected == inval && st.solo == solo + esc && st.escalated == esc,
               "%s: statistics: rejected %lld, solo %lld, escalated %lld; expected %d, %d, %d", c.name,
               (long long)st.rejected, (long long)st.solo, (long long)st.escalated, inval, solo + esc, esc);
-    printf("%s: %zu requests (%d solo, %d escalated, %d rejected masks), %lld chunks; launches so far: %lld paired, "
-           "%lld wide\n", c.name, reqs.size(), solo, esc, inval, (long long)st.chunks, g_launch_pair.load(),
-           g_launch_wide.load());
+    printf("%s: %zu requests (%d solo, %d escalated, %d rejected masks), %lld chunks (%lld wide); launches so "
+           "far: %lld paired, %lld wide\n", c.name, reqs.size(), solo, esc, inval, (long long)st.chunks,
+           (long long)st.chunks_wide, g_launch_pair.load(), g_launch_wide.load());
     fflush(stdout);
 }
 
