@@ -708,9 +708,12 @@ lbm_status lbm_solver_create(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const
     s->ctx = ctx;
     s->grid = g;
     s->p = *p;
+    // as the real solver counts them: the fluid updates its flow domain,
+    // the substrate every FLUID and BIOFILM node
     const int64_t N = (int64_t)g.nx * g.ny;
+    const std::vector<uint8_t> dom = lbmh::flow_domain(g, cls);
     for (int64_t n = 0; n < N; ++n) {
-        s->n_fluid += cls[n] == LBM_FLUID;
+        s->n_fluid += dom[n] != 0;
         s->n_ad += cls[n] == LBM_FLUID || cls[n] == LBM_BIOFILM;
     }
     *out = s;
@@ -768,6 +771,7 @@ struct Expect {
     int status, lane, first_status;
     long long it_f, it_a, first_f, first_a;
     bool ad_ran, first_ad_ran;
+    int64_t nf, na; // nodes each solver updates
 };
 
 struct Attempt {
@@ -808,7 +812,9 @@ Attempt attempt(const lbm_request &r, int storage, int K, int window)
     return a;
 }
 
-bool mask_valid(const lbm_request &r)
+// Whether the server accepts the request's medium, and the nodes each
+// solver updates on it
+bool mask_valid(const lbm_request &r, int64_t *nf = nullptr, int64_t *na = nullptr)
 {
     const lbm_grid g{r.nx, r.ny, 1};
     std::vector<uint8_t> cls((size_t)r.nx * r.ny);
@@ -819,7 +825,15 @@ bool mask_valid(const lbm_request &r)
         lbm_biofilm_layer(g, cls.data());
     if (!lbmh::check_mask(g, cls.data()).empty())
         return false;
-    return lbmh::domain_reaches_inlet(g, lbmh::flow_domain(g, cls.data()));
+    const std::vector<uint8_t> dom = lbmh::flow_domain(g, cls.data());
+    if (nf && na) {
+        *nf = *na = 0;
+        for (size_t n = 0; n < cls.size(); ++n) {
+            *nf += dom[n] != 0;
+            *na += cls[n] == LBM_FLUID || cls[n] == LBM_BIOFILM;
+        }
+    }
+    return lbmh::domain_reaches_inlet(g, dom);
 }
 
 struct Config {
@@ -840,7 +854,7 @@ Expect expect(const lbm_request &r, const Config &c)
     const int window = c.stall < 0 ? 0 : (c.stall ? c.stall : lbmh::default_stall_checks(c.storage, K));
     const int64_t N = (int64_t)r.nx * r.ny;
     e.lane = c.solo_nodes > 0 && N >= c.solo_nodes ? LBM_LANE_SOLO : LBM_LANE_BATCH;
-    if (!mask_valid(r)) {
+    if (!mask_valid(r, &e.nf, &e.na)) {
         e.status = LBM_EINVAL;
         return e;
     }
@@ -1046,6 +1060,16 @@ void run_config(const Config &c)
     const bool wide_possible = emu::served_ty() == 16 && c.storage != LBM_FP16_SHIFTED;
     EMU_CHECK(st.chunks_wide <= st.chunks && (wide_possible || st.chunks_wide == 0),
               "%s: %lld of %lld chunks wide", c.name, (long long)st.chunks_wide, (long long)st.chunks);
+    // lattice updates of every solve, the discarded first attempts included
+    double upd = 0.0;
+    for (const auto &e : exp) {
+        if (e.status == LBM_EINVAL)
+            continue;
+        upd += (double)e.it_f * e.nf + (double)e.it_a * e.na;
+        if (e.lane == LBM_LANE_ESCALATED)
+            upd += (double)e.first_f * e.nf + (double)e.first_a * e.na;
+    }
+    EMU_CHECK(st.lattice_updates == upd, "%s: lattice updates %.0f, expected %.0f", c.name, st.lattice_updates, upd);
     EMU_CHECK(st.rejected == inval && st.solo == solo + esc && st.escalated == esc,
               "%s: statistics: rejected %lld, solo %lld, escalated %lld; expected %d, %d, %d", c.name,
               (long long)st.rejected, (long long)st.solo, (long long)st.escalated, inval, solo + esc, esc);
