@@ -664,7 +664,11 @@ typedef struct {
 /* Device bytes one request of this size takes from the pool. */
 size_t lbm_server_footprint(int32_t nx, int32_t ny, int32_t storage);
 /* Allocates the pool and starts the worker threads on ctx's device (the
- * server has its own stream).  EINVAL on a bad configuration, ENOMEM. */
+ * server has its own stream).  EINVAL on a bad configuration, ENOMEM.
+ * Tuning through the environment: LBM_SERVED_TILE_Y=4 (read once per
+ * process) keeps every chunk on paired 64 x 4 launches;
+ * LBM_SERVED_WIDE_MIN_TILES (read by each create) sets the table size, in
+ * 64 x 16 tiles, from which FP32 chunks take the wide form (256). */
 lbm_status lbm_server_create(lbm_ctx *ctx, const lbm_server_cfg *cfg, lbm_server **out);
 /* Queue a request (copied).  EINVAL (see lbm_server_error) for bad
  * parameters or a batch request larger than the pool; mask problems found later
