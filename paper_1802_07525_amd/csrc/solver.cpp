@@ -162,7 +162,12 @@ lbm_status dev_alloc(lbm_solver *s, void **p, size_t bytes, const char *what)
         (void)hipGetLastError();
         return set_err(s->ctx, LBM_ENOMEM, std::string("device allocation failed: ") + what);
     }
-    HIPCHK(hipMemsetAsync(*p, 0, bytes, s->ctx->stream), what);
+    if ((e = hipMemsetAsync(*p, 0, bytes, s->ctx->stream)) != hipSuccess) {
+        // not handed out: a caller holding the pointer in a local would lose it
+        (void)hipFree(*p);
+        *p = nullptr;
+        return hip_err(s->ctx, e, what);
+    }
     return LBM_OK;
 }
 

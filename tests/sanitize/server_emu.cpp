@@ -1,8 +1,9 @@
-// CPU emulation of the serving loop (server.cpp) for the sanitizer builds
+// CPU emulation of the serving loop (server.cpp) and of the single-domain
+// solver's host code (solver.cpp, api.cpp) for the sanitizer builds
 // (ThreadSanitizer; AddressSanitizer with UndefinedBehaviorSanitizer).
 //
-// server.cpp and geom.cpp are linked against this file instead of the HIP
-// runtime, the gfx950 kernels and the single-domain solver:
+// server.cpp, solver.cpp, api.cpp and geom.cpp are linked against this file
+// instead of the HIP runtime and the gfx950 kernels:
 //
 //  * HIP runtime: a stream is a host thread that runs its queued operations
 //    in order (copies, fills, kernels, event markers), with small random
@@ -18,23 +19,25 @@
 //    parameters and the step count (it halves every 100 steps and reaches
 //    tol at a step set by u_in or D; tau and k_sink select a floor at 10 tol,
 //    in every storage or in FP16 storage only, or a divergence).  The stop
-//    rule is applied to that history at each check.
-//  * Solver (solo lanes): the same history run check by check on the
-//    calling thread.
+//    rule is applied to that history at each check.  The batched kernels and
+//    the single-domain solver's step, check, decide, export and flux kernels
+//    are emulated; the solo lanes run the real single-domain solver on them.
 //
 // The stub kernels check what the real ones rely on and abort on a
 // violation: the grid covers the slot table, each table entry spans exactly
 // its request's tiles, a launch finds in its source buffer the state of the
 // step it is to take (so no chunk is lost, repeated or misnumbered and every
-// chunk has an even number of launches), a state belongs to the slot that
-// steps it, and exports read a state of the right phase.
+// chunk has an even number of launches), a state belongs to the slot or
+// solver that steps it, and exports read a state of the right phase.
 //
 // The driver (main) submits seeded request streams from several threads
 // while a poller takes results and another thread reads the statistics, then
 // drains.  Every result is compared with the sequential expectation: status,
 // lane, step counts, the first attempt of an escalated request, and the
 // exported fields and fluxes, which carry the step count of the state they
-// were exported from.  Prints "ok" and exits 0 when all of it holds.
+// were exported from; so are the server's statistics.  Two streams inject a
+// device failure, and the run ends by destroying servers with work in
+// flight.  Prints "ok" and exits 0 when all of it holds.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -453,9 +456,11 @@ Outcome solve(const History &h, bool fluid, double tol, int K, int window, long 
 // State header at the start of a request's population buffer.
 struct Hdr {
     unsigned long long magic;
-    long long steps;
+    long long steps; // the batch: steps since init; the single solver: its step counter
+    long long base;  // the single solver: its step counter at init
     unsigned long long owner;
     int phase;
+    int fresh;       // initialised, not stepped yet
 };
 const unsigned long long MAGIC = 0x5EA7ED5EA7ED0001ull;
 
@@ -509,8 +514,10 @@ static void write_hdr(void *f, const void *desc, const Geo &g, int phase)
     emu::Hdr *h = static_cast<emu::Hdr *>(f);
     h->magic = emu::MAGIC;
     h->steps = 0;
+    h->base = 0;
     h->owner = emu::owner_of(desc, g.N);
     h->phase = phase;
+    h->fresh = 1;
 }
 static const emu::Hdr *read_hdr(const void *f, const void *desc, const Geo &g, int phase, const char *who)
 {
@@ -533,23 +540,30 @@ hipError_t ad_init(int, int, void *gp, const void *desc, const void *, const Geo
 hipError_t fluid_export(int, int, const void *f, const void *desc, const Geo &g, const float *, void *U,
                         void *RHO, int out_double, hipStream_t st)
 {
-    EMU_CHECK(!out_double && !RHO, "served velocity exports are compute-type, no density");
+    EMU_CHECK(!RHO, "no density export is emulated");
     return enqueue(st, [=] {
-        const float v = (float)read_hdr(f, desc, g, SRV_FLUID, "fluid_export")->steps;
-        float *u = static_cast<float *>(U);
-        for (long long n = 0; n < 2 * g.N; ++n)
-            u[n] = v;
+        const emu::Hdr *h = read_hdr(f, desc, g, SRV_FLUID, "fluid_export");
+        const double v = (double)(h->steps - h->base);
+        for (long long n = 0; n < 2 * g.N; ++n) {
+            if (out_double)
+                static_cast<double *>(U)[n] = v;
+            else
+                static_cast<float *>(U)[n] = (float)v;
+        }
     });
 }
 hipError_t ad_export(int, int, const void *gp, const void *desc, const Geo &g, const float *, Sink, void *C,
                      int out_double, hipStream_t st)
 {
-    EMU_CHECK(!out_double, "served concentration exports are compute-type");
     return enqueue(st, [=] {
-        const float v = (float)read_hdr(gp, desc, g, SRV_AD, "ad_export")->steps;
-        float *c = static_cast<float *>(C);
-        for (long long n = 0; n < g.N; ++n)
-            c[n] = v;
+        const emu::Hdr *h = read_hdr(gp, desc, g, SRV_AD, "ad_export");
+        const double v = (double)(h->steps - h->base);
+        for (long long n = 0; n < g.N; ++n) {
+            if (out_double)
+                static_cast<double *>(C)[n] = v;
+            else
+                static_cast<float *>(C)[n] = (float)v;
+        }
     });
 }
 hipError_t fluxes(int, int, const void *f, const void *gp, const void *desc, const Geo &g, const float *,
@@ -559,16 +573,24 @@ hipError_t fluxes(int, int, const void *f, const void *gp, const void *desc, con
     return enqueue(st, [=] {
         for (int k = 0; k < 5; ++k)
             out5[k] = 0.0;
-        if (f)
-            out5[0] = (double)read_hdr(f, desc, g, SRV_FLUID, "fluxes")->steps;
-        if (gp)
-            out5[2] = (double)read_hdr(gp, desc, g, SRV_AD, "fluxes")->steps;
+        if (f) {
+            const emu::Hdr *h = read_hdr(f, desc, g, SRV_FLUID, "fluxes");
+            out5[0] = (double)(h->steps - h->base);
+        }
+        if (gp) {
+            const emu::Hdr *h = read_hdr(gp, desc, g, SRV_AD, "fluxes");
+            out5[2] = (double)(h->steps - h->base);
+        }
     });
 }
-hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, unsigned long long *, int,
+hipError_t ctrl_reset(Ctrl *c, double tol, int window, int is_fluid, int K, unsigned long long *part, int nparts,
                       hipStream_t st, long long t_max)
 {
-    return enqueue(st, [=] { emu::reset(c, tol, window, is_fluid, K, t_max); });
+    return enqueue(st, [=] {
+        emu::reset(c, tol, window, is_fluid, K, t_max);
+        c->part = part;
+        c->nparts = nparts;
+    });
 }
 hipError_t srv_slot_set(SrvSlot *slots, int sid, const SrvSlot &v, hipStream_t st)
 {
@@ -682,87 +704,167 @@ hipError_t srv_ref_roll(const SrvSlot *slots, const SrvTable *tab, const Ctrl *c
     });
 }
 
+// ---- the single-domain solver's kernels (solver.cpp runs on these) -------
+// A launch of ns steps of one solver: the stop flag first, as the real
+// kernels; the source buffer must hold the state at the launch's step
+// counter (the first launch after an init sets the counter's base); the
+// check launch, which ends a chunk, writes every per-block maximum.
+static void emu_solver_step(bool fluid, int mode, int ns, const void *src, void *dst, const void *desc, Ctrl *c,
+                            const Geo &g, unsigned int step, double tau, double u_in, double D, double k_sink,
+                            int storage)
+{
+    if (c->stop != STOP_RUN)
+        return;
+    const emu::Hdr *h = read_hdr(src, desc, g, fluid ? SRV_FLUID : SRV_AD, "solver step");
+    emu::Hdr cur = *h;
+    if (cur.fresh) {
+        cur.fresh = 0;
+        cur.base = cur.steps = (long long)step;
+    }
+    EMU_CHECK(cur.steps == (long long)step, "solver step: the source holds step %lld, the launch takes %u",
+              cur.steps, step);
+    cur.steps += ns;
+    *static_cast<emu::Hdr *>(dst) = cur;
+    if (mode == MODE_CHECK) {
+        const long long t = c->t + c->K; // steps since the reset at the end of this chunk
+        EMU_CHECK(cur.steps - cur.base >= t, "solver check at %lld steps of %lld", t, cur.steps - cur.base);
+        const emu::History hist = emu::history(fluid, storage, tau, u_in, D, k_sink);
+        const unsigned long long rb = emu::bits(emu::residual(hist, fluid, c->tol, t));
+        const unsigned long long ub = emu::bits(emu::umax(hist, fluid, t));
+        EMU_CHECK(c->part && c->nparts > 0, "check launch without per-block slots");
+        for (int b = 0; b < c->nparts; ++b) {
+            c->part[b] = b == (int)(t / c->K) % c->nparts ? rb : emu::bits(emu::from_bits(rb) * 0.5);
+            c->part[c->nparts + b] = b == 0 ? ub : emu::bits(0.0);
+        }
+    }
+}
+static hipError_t fluid_launch(int mode, int ns, const FluidArgs &a, hipStream_t st, int storage)
+{
+    const FluidArgs b = a;
+    return enqueue(st, [=] {
+        emu_solver_step(true, mode, ns, b.src, b.dst, b.desc, b.ctrl, b.g, b.step, 1.0 / b.omega, b.u_in, 0.0, 0.0,
+                        storage);
+    });
+}
+static hipError_t ad_launch(int mode, int ns, const AdArgs &a, hipStream_t st, int storage)
+{
+    const AdArgs b = a;
+    const double cs2 = b.g.nz > 1 ? 0.25 : 1.0 / 3.0;
+    return enqueue(st, [=] {
+        emu_solver_step(false, mode, ns, b.src, b.dst, b.desc, b.ctrl, b.g, b.step, 0.0, 0.0,
+                        (1.0 / b.omega - 0.5) * cs2, b.k_sink, storage);
+    });
+}
+hipError_t fluid_step(int, int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return fluid_launch(mode, 1, a, st, storage);
+}
+hipError_t ad_step(int, int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return ad_launch(mode, 1, a, st, storage);
+}
+hipError_t fluid_step2(int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return fluid_launch(mode, 2, a, st, storage);
+}
+hipError_t ad_step2(int, int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return ad_launch(mode, 2, a, st, storage);
+}
+hipError_t fluid_stepN(int storage, int mode, int ns, const FluidArgs &a, hipStream_t st)
+{
+    EMU_CHECK(ns >= 3 && ns <= 4, "fluid_stepN of %d steps", ns);
+    return fluid_launch(mode, ns, a, st, storage);
+}
+hipError_t ad_stepN(int, int storage, int mode, int ns, const AdArgs &a, hipStream_t st)
+{
+    EMU_CHECK(ns >= 3 && ns <= 4, "ad_stepN of %d steps", ns);
+    return ad_launch(mode, ns, a, st, storage);
+}
+hipError_t fluid_step3d2(int storage, int mode, const FluidArgs &a, hipStream_t st)
+{
+    return fluid_launch(mode, 2, a, st, storage);
+}
+hipError_t ad_step3d2(int storage, int mode, const AdArgs &a, hipStream_t st)
+{
+    return ad_launch(mode, 2, a, st, storage);
+}
+hipError_t decide(Ctrl *c, hipStream_t st)
+{
+    return enqueue(st, [=] {
+        if (c->stop != STOP_RUN)
+            return;
+        unsigned long long mr = 0, mu = 0;
+        for (int b = 0; b < c->nparts; ++b) {
+            mr = std::max(mr, c->part[b]);
+            mu = std::max(mu, c->part[c->nparts + b]);
+        }
+        emu::apply_rule(c, emu::from_bits(mr), emu::from_bits(mu));
+    });
+}
+hipError_t ref_roll(const Ctrl *ctrl, float *cur, const float *next, int n, hipStream_t st)
+{
+    return enqueue(st, [=] {
+        if (ctrl->stop != STOP_RUN)
+            return;
+        for (int k = 0; k < n; ++k)
+            cur[k] = next[k];
+    });
+}
+hipError_t copy_kernel(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    return enqueue(st, [=] { memcpy(dst, src, bytes); });
+}
+hipError_t pops_export(int, int, int, const void *, const void *, const Geo &, const float *, double *, hipStream_t)
+{
+    emu_fail("pops_export is not emulated");
+    return hipErrorInvalidValue;
+}
+hipError_t pops_import(int, int, int, void *, const void *, const Geo &, const float *, const double *, hipStream_t)
+{
+    emu_fail("pops_import is not emulated");
+    return hipErrorInvalidValue;
+}
+hipError_t pops_set_nodes(int, int, int, void *, const Geo &, const float *, const long long *, int, const double *,
+                          hipStream_t)
+{
+    emu_fail("pops_set_nodes is not emulated");
+    return hipErrorInvalidValue;
+}
+size_t compute_bytes(int s) { return s == ST_F64 ? 8 : 4; }
+// four-step launches on larger grids, two-step ones below (both forms of
+// the steady loop's plans)
+int fluid_launch_steps(int storage, const Geo &g) { return storage != ST_F64 && g.N >= 8192 ? 4 : 2; }
+int pair_ty(int, const Geo &) { return 4; }
+int z3_tile_y(const Geo &) { return 16; }
+int z3_planes_per_block(const Geo &g, int, int) { return g.nz < 4 ? g.nz : 4; }
+int z3_blocks(const Geo &g, int zseg, int ty)
+{
+    return ((g.nx + 31) / 32) * ((g.ny + ty - 1) / ty) * ((g.nz + zseg - 1) / zseg);
+}
+
 } // namespace lbmk
 
 // ---------------------------------------------------- single-domain solver
+// solver.cpp and api.cpp run as they are; the HIP calls they add
 extern "C" {
-
-lbm_status lbm_ctx_create(int device, void *, lbm_ctx **out)
+hipError_t hipGetDeviceCount(int *n)
 {
-    lbm_ctx *c = new lbm_ctx();
-    c->device = device;
-    *out = c;
-    return LBM_OK;
+    *n = 1;
+    return hipSuccess;
 }
-void lbm_ctx_destroy(lbm_ctx *ctx) { delete ctx; }
-const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
-
-lbm_status lbm_solver_create(lbm_ctx *ctx, lbm_grid g, const uint8_t *cls, const lbm_params *p, lbm_solver **out)
+hipError_t hipEventCreate(hipEvent_t *e)
 {
-    if (!cls)
-        return lbmh::set_err(ctx, LBM_EINVAL, "no mask");
-    const std::string m = lbmh::check_mask(g, cls);
-    if (!m.empty())
-        return lbmh::set_err(ctx, LBM_EINVAL, m);
-    lbm_solver *s = new lbm_solver();
-    s->ctx = ctx;
-    s->grid = g;
-    s->p = *p;
-    // as the real solver counts them: the fluid updates its flow domain,
-    // the substrate every FLUID and BIOFILM node
-    const int64_t N = (int64_t)g.nx * g.ny;
-    const std::vector<uint8_t> dom = lbmh::flow_domain(g, cls);
-    for (int64_t n = 0; n < N; ++n) {
-        s->n_fluid += dom[n] != 0;
-        s->n_ad += cls[n] == LBM_FLUID || cls[n] == LBM_BIOFILM;
-    }
-    *out = s;
-    return LBM_OK;
+    *e = new ihipEvent_t();
+    return hipSuccess;
 }
-void lbm_solver_destroy(lbm_solver *s) { delete s; }
-
-static lbm_status solver_solve(lbm_solver *s, bool fluid, double tol, int64_t max_iter, lbm_info *info)
+hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b)
 {
-    const lbm_params &p = s->p;
-    const int K = p.check_every ? p.check_every : (p.storage == LBM_FP16_SHIFTED ? 1000 : 100);
-    const int window = p.stall_checks < 0 ? 0 : (p.stall_checks ? p.stall_checks : lbmh::default_stall_checks(p.storage, K));
-    const emu::History h = emu::history(fluid, p.storage, p.tau, p.u_in, p.D, p.k_sink);
-    const emu::Outcome o = emu::solve(h, fluid, tol, K, window, max_iter);
-    (fluid ? s->fsteps : s->gsteps) = (unsigned long long)o.iters;
-    memset(info, 0, sizeof(*info));
-    info->iters = o.iters;
-    info->checks = o.checks;
-    info->residual = o.r_last;
-    info->active_nodes = fluid ? s->n_fluid : s->n_ad;
-    return (lbm_status)o.status;
+    EMU_CHECK(hipEventSynchronize(a) == hipSuccess && hipEventSynchronize(b) == hipSuccess, "event wait");
+    *ms = 1.0f;
+    return hipSuccess;
 }
-lbm_status lbm_solver_fluid(lbm_solver *s, double tol, int64_t max_iter, int, lbm_info *info)
-{
-    return solver_solve(s, true, tol, max_iter, info);
-}
-lbm_status lbm_solver_ad(lbm_solver *s, double tol, int64_t max_iter, int, lbm_info *info)
-{
-    return solver_solve(s, false, tol, max_iter, info);
-}
-lbm_status lbm_solver_fluxes(lbm_solver *s, double *out5)
-{
-    for (int k = 0; k < 5; ++k)
-        out5[k] = 0.0;
-    out5[0] = (double)s->fsteps;
-    out5[2] = (double)s->gsteps;
-    return LBM_OK;
-}
-
 } // extern "C"
-
-lbm_status lbmh::export_f32(lbm_solver *s, int which, float *dst)
-{
-    const int64_t N = (int64_t)s->grid.nx * s->grid.ny;
-    const float v = (float)(which == 0 ? s->fsteps : s->gsteps);
-    for (int64_t n = 0; n < (which == 0 ? 2 * N : N); ++n)
-        dst[n] = v;
-    return LBM_OK;
-}
 
 // ----------------------------------------------------------------- driver
 namespace {
