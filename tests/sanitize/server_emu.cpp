@@ -36,8 +36,10 @@
 // lane, step counts, the first attempt of an escalated request, and the
 // exported fields and fluxes, which carry the step count of the state they
 // were exported from; so are the server's statistics.  Two streams inject a
-// device failure, and the run ends by destroying servers with work in
-// flight.  Prints "ok" and exits 0 when all of it holds.
+// device failure, servers are destroyed with work in flight, and three
+// coupled biofilm loops (growth picks, cell updates, warm re-solves) run at
+// once on contexts of their own.  Prints "ok" and exits 0 when all of it
+// holds.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -825,11 +827,15 @@ hipError_t pops_import(int, int, int, void *, const void *, const Geo &, const f
     emu_fail("pops_import is not emulated");
     return hipErrorInvalidValue;
 }
-hipError_t pops_set_nodes(int, int, int, void *, const Geo &, const float *, const long long *, int, const double *,
-                          hipStream_t)
+// cell updates: the stub state has no populations to set; the node list
+// must lie in the grid
+hipError_t pops_set_nodes(int, int, int, void *, const Geo &g, const float *, const long long *idx, int count,
+                          const double *, hipStream_t st)
 {
-    emu_fail("pops_set_nodes is not emulated");
-    return hipErrorInvalidValue;
+    return enqueue(st, [=] {
+        for (int k = 0; k < count; ++k)
+            EMU_CHECK(idx[k] >= 0 && idx[k] < g.N, "cell update of node %lld outside the grid", idx[k]);
+    });
 }
 size_t compute_bytes(int s) { return s == ST_F64 ? 8 : 4; }
 // four-step launches on larger grids, two-step ones below (both forms of
@@ -1219,6 +1225,57 @@ void run_destroy_in_flight(int storage, uint64_t seed, int wait_ms)
     fflush(stdout);
 }
 
+// The coupled biofilm loop (lbm_coupled_run: growth pick, cell update,
+// warm re-solves) on its own context, with the stub kernels: every re-solve
+// takes the steps the history gives, every pick becomes BIOFILM.
+void run_coupled(uint64_t seed, int n_updates, std::atomic<int> *ran)
+{
+    lbm_ctx *ctx = nullptr;
+    EMU_CHECK(lbm_ctx_create(0, nullptr, &ctx) == LBM_OK, "context");
+    const lbm_grid g{96, 48, 1};
+    lbm_disc_params dp{3, 6, 0.3, 1};
+    std::vector<uint8_t> cls((size_t)g.nx * g.ny);
+    double got = 0;
+    EMU_CHECK(lbm_geom_discs(g, &dp, seed, cls.data(), &got) == LBM_OK, "discs");
+    lbm_biofilm_layer(g, cls.data());
+    if (!lbmh::domain_reaches_inlet(g, lbmh::flow_domain(g, cls.data()))) {
+        lbm_ctx_destroy(ctx);
+        return; // a medium that does not percolate: no loop
+    }
+    lbm_params p{};
+    p.tau = 0.65;
+    p.u_in = 0.0031;
+    p.D = 0.012;
+    p.c_in = 1.0;
+    p.k_sink = 0.2;
+    p.storage = LBM_FP32_SHIFTED;
+    lbm_solver *sv = nullptr;
+    EMU_CHECK(lbm_solver_create(ctx, g, cls.data(), &p, &sv) == LBM_OK, "solver: %s", lbm_last_error(ctx));
+    std::vector<double> xi(n_updates), J(n_updates + 1);
+    std::vector<int64_t> picked(n_updates), itf(n_updates + 1), ita(n_updates + 1);
+    for (int m = 0; m < n_updates; ++m)
+        xi[m] = (double)((seed * 7919 + m * 104729) % 1000) / 1000.0;
+    double Jacc = -1.0;
+    const lbm_status st = lbm_coupled_run(sv, n_updates, xi.data(), 1e-6, 200000, picked.data(), J.data(), &Jacc,
+                                          itf.data(), ita.data());
+    EMU_CHECK(st == LBM_OK, "coupled loop returned %d: %s", (int)st, lbm_last_error(ctx));
+    const emu::Outcome f = emu::solve(emu::history(true, p.storage, p.tau, p.u_in, p.D, p.k_sink), true, 1e-6, 100,
+                                      1000, 200000);
+    const emu::Outcome a = emu::solve(emu::history(false, p.storage, p.tau, p.u_in, p.D, p.k_sink), false, 1e-6,
+                                      100, 1000, 200000);
+    for (int m = 0; m <= n_updates; ++m)
+        EMU_CHECK(itf[m] == f.iters && ita[m] == a.iters, "coupled update %d: %lld + %lld steps, expected %lld + %lld",
+                  m, (long long)itf[m], (long long)ita[m], f.iters, a.iters);
+    std::vector<uint8_t> fin(cls.size());
+    EMU_CHECK(lbm_solver_get(sv, LBM_FIELD_CLASS, fin.data()) == LBM_OK, "class field");
+    for (int m = 0; m < n_updates; ++m)
+        EMU_CHECK(picked[m] >= 0 && fin[(size_t)picked[m]] == LBM_BIOFILM, "pick %d (%lld) is not BIOFILM", m,
+                  (long long)picked[m]);
+    lbm_solver_destroy(sv);
+    lbm_ctx_destroy(ctx);
+    ran->fetch_add(1);
+}
+
 } // namespace
 
 int main(int argc, char **argv)
@@ -1245,6 +1302,17 @@ int main(int argc, char **argv)
         run_config(c);
     for (int w : {0, 3, 30})
         run_destroy_in_flight(w == 3 ? LBM_FP16_SHIFTED : LBM_FP32_SHIFTED, 11 + (uint64_t)w, w);
+    {
+        // three coupled loops at once, each with its own context and stream
+        std::atomic<int> ran{0};
+        std::vector<std::thread> loops;
+        for (uint64_t sd : {21, 22, 23})
+            loops.emplace_back([sd, &ran] { run_coupled(sd, 12, &ran); });
+        for (auto &t : loops)
+            t.join();
+        EMU_CHECK(ran.load() >= 2, "only %d coupled loops ran", ran.load());
+        printf("coupled loops: %d x 12 updates\n", ran.load());
+    }
     printf("ok\n");
     return 0;
 }

@@ -30,7 +30,9 @@ AddressSanitizer that found a request freed by the caller while a
 preparation thread was still building its mask, and, in the solver, a
 staging allocation lost when clearing it failed.  Each run ends by
 destroying servers with work in flight (queued, being prepared, stepped,
-retiring, on the solo lanes, finished and unpolled, polled and unreleased).
+retiring, on the solo lanes, finished and unpolled, polled and unreleased)
+and by three coupled biofilm loops at once (lbm_coupled_run: growth picks,
+cell updates, warm re-solves of the real solver on the emulated kernels).
 """
 import os
 import shutil
