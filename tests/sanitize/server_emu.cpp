@@ -2,8 +2,9 @@
 // solver's host code (solver.cpp, api.cpp) for the sanitizer builds
 // (ThreadSanitizer; AddressSanitizer with UndefinedBehaviorSanitizer).
 //
-// server.cpp, solver.cpp, api.cpp and geom.cpp are linked against this file
-// instead of the HIP runtime and the gfx950 kernels:
+// server.cpp, solver.cpp, api.cpp, biofilm.cpp and geom.cpp are linked
+// against this file instead of the HIP runtime, the gfx950 kernels and the
+// device side of the bio-electrochemical state:
 //
 //  * HIP runtime: a stream is a host thread that runs its queued operations
 //    in order (copies, fills, kernels, event markers), with small random
@@ -36,10 +37,11 @@
 // lane, step counts, the first attempt of an escalated request, and the
 // exported fields and fluxes, which carry the step count of the state they
 // were exported from; so are the server's statistics.  Two streams inject a
-// device failure, servers are destroyed with work in flight, and three
+// device failure, servers are destroyed with work in flight, three
 // coupled biofilm loops (growth picks, cell updates, warm re-solves) run at
-// once on contexts of their own.  Prints "ok" and exits 0 when all of it
-// holds.
+// once on contexts of their own, and the hourly model loop runs the
+// agent-based biofilm (biofilm.cpp) on the real solver.  Prints "ok" and
+// exits 0 when all of it holds.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -872,6 +874,34 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b)
 }
 } // extern "C"
 
+// ------------------------------------------- bio-electrochemical state
+// bio.hip's host side, reduced to the host mirrors the agent-based biofilm
+// (biofilm.cpp) reads and writes: no device arrays and no mediator balance
+lbm_status lbmh::bio_pull_mox(lbm_bio *b)
+{
+    b->mox_stale = false;
+    return LBM_OK;
+}
+lbm_status lbmh::bio_push_cells(lbm_bio *b)
+{
+    b->cells.clear();
+    b->sum_cb = 0.0;
+    for (size_t n = 0; n < b->cb.size(); ++n)
+        if (b->cb[n] > 0.0) {
+            b->cells.push_back((int32_t)n);
+            b->sum_cb += b->cb[n];
+        }
+    b->biomass = b->sum_cb;
+    return LBM_OK;
+}
+extern "C" lbm_status lbm_bio_step(lbm_bio *b, lbm_bio_out *out)
+{
+    memset(out, 0, sizeof(*out));
+    out->n_cells = (int32_t)b->cells.size();
+    out->biomass = b->biomass;
+    return LBM_OK;
+}
+
 // ----------------------------------------------------------------- driver
 namespace {
 
@@ -1276,6 +1306,68 @@ void run_coupled(uint64_t seed, int n_updates, std::atomic<int> *ran)
     ran->fetch_add(1);
 }
 
+// The hourly model loop (lbm_mfc_run: solves, bio step, agent-based
+// biofilm with attachment, growth and spreading by random walks) on the
+// real solver with the stub kernels.  Biomass sits only on BIOFILM nodes,
+// and spreading moves it without loss.
+void run_mfc(uint64_t seed, int hours)
+{
+    lbm_ctx *ctx = nullptr;
+    EMU_CHECK(lbm_ctx_create(0, nullptr, &ctx) == LBM_OK, "context");
+    const lbm_grid g{96, 48, 1};
+    lbm_disc_params dp{3, 6, 0.25, 1};
+    std::vector<uint8_t> cls((size_t)g.nx * g.ny);
+    double got = 0;
+    EMU_CHECK(lbm_geom_discs(g, &dp, seed, cls.data(), &got) == LBM_OK, "discs");
+    if (!lbmh::domain_reaches_inlet(g, lbmh::flow_domain(g, cls.data()))) {
+        lbm_ctx_destroy(ctx);
+        return;
+    }
+    lbm_params p{};
+    p.tau = 0.65;
+    p.u_in = 0.0031;
+    p.D = 0.012;
+    p.c_in = 1.0;
+    p.k_sink = 0.2;
+    p.storage = LBM_FP32_SHIFTED;
+    lbm_solver *sv = nullptr;
+    EMU_CHECK(lbm_solver_create(ctx, g, cls.data(), &p, &sv) == LBM_OK, "solver: %s", lbm_last_error(ctx));
+    lbm_bio b;
+    b.s = sv;
+    b.p.q_max = 8.0;
+    b.p.K_s = 20.0;
+    b.p.M_total = 0.05;
+    b.p.K_Mox = 0.01;
+    b.p.C0_bio = 450.0;
+    b.p.c_scale = 1.0; // the stub concentration is a step count: fast growth
+    b.p.dt_hours = 1.0;
+    b.cb.assign(cls.size(), 0.0);
+    b.mox.assign(cls.size(), 0.0);
+    lbm_biofilm_params fp{};
+    fp.k_ata = 15;
+    fp.C_max = 500.0;
+    fp.fr_spr = 0.4;
+    fp.max_walk = 40;
+    fp.Y_bio = 1.0;
+    std::vector<lbm_mfc_interval> series((size_t)hours);
+    const lbm_status st = lbm_mfc_run(&b, &fp, hours, seed, 1e-6, 200000, series.data());
+    EMU_CHECK(st == LBM_OK || st == LBM_EINVAL, "model loop returned %d: %s", (int)st, lbm_last_error(ctx));
+    std::vector<uint8_t> fin(cls.size());
+    EMU_CHECK(lbm_solver_get(sv, LBM_FIELD_CLASS, fin.data()) == LBM_OK, "class field");
+    for (size_t n = 0; n < fin.size(); ++n)
+        EMU_CHECK(!(b.cb[n] > 0.0) || fin[n] == LBM_BIOFILM, "biomass on node %zu of class %d", n, (int)fin[n]);
+    int spread = 0, walks = 0;
+    for (const auto &r : series) {
+        spread += r.film.spread;
+        walks += r.film.walks;
+    }
+    lbm_solver_destroy(sv);
+    lbm_ctx_destroy(ctx);
+    printf("model loop (seed %llu): %s, %d spreadings, %d random walks\n", (unsigned long long)seed,
+           st == LBM_OK ? "OK" : "stopped (growth would close the flow path)", spread, walks);
+    fflush(stdout);
+}
+
 } // namespace
 
 int main(int argc, char **argv)
@@ -1313,6 +1405,8 @@ int main(int argc, char **argv)
         EMU_CHECK(ran.load() >= 2, "only %d coupled loops ran", ran.load());
         printf("coupled loops: %d x 12 updates\n", ran.load());
     }
+    for (uint64_t sd : {31, 32})
+        run_mfc(sd, 8);
     printf("ok\n");
     return 0;
 }

@@ -32,7 +32,9 @@ staging allocation lost when clearing it failed.  Each run ends by
 destroying servers with work in flight (queued, being prepared, stepped,
 retiring, on the solo lanes, finished and unpolled, polled and unreleased)
 and by three coupled biofilm loops at once (lbm_coupled_run: growth picks,
-cell updates, warm re-solves of the real solver on the emulated kernels).
+cell updates, warm re-solves of the real solver on the emulated kernels)
+and two runs of the hourly model loop with the agent-based biofilm
+(lbm_mfc_run: attachment, growth, spreading by random walks; biofilm.cpp).
 """
 import os
 import shutil
@@ -79,7 +81,7 @@ def test_oracle_under_asan_ubsan(tmp_path):
 
 
 CLANG = os.path.join(ROCM, "llvm", "bin", "clang++")
-EMU_SRC = ["server.cpp", "solver.cpp", "api.cpp", "geom.cpp"]
+EMU_SRC = ["server.cpp", "solver.cpp", "api.cpp", "geom.cpp", "biofilm.cpp"]
 
 
 def _emu_build(tmp_path, name, compiler, flags):
