@@ -1257,7 +1257,8 @@ void run_destroy_in_flight(int storage, uint64_t seed, int wait_ms)
 
 // The coupled biofilm loop (lbm_coupled_run: growth pick, cell update,
 // warm re-solves) on its own context, with the stub kernels: every re-solve
-// takes the steps the history gives, every pick becomes BIOFILM.
+// takes the steps the history gives, every pick becomes BIOFILM; then a
+// checkpoint and restore.
 void run_coupled(uint64_t seed, int n_updates, std::atomic<int> *ran)
 {
     lbm_ctx *ctx = nullptr;
@@ -1301,6 +1302,21 @@ void run_coupled(uint64_t seed, int n_updates, std::atomic<int> *ran)
     for (int m = 0; m < n_updates; ++m)
         EMU_CHECK(picked[m] >= 0 && fin[(size_t)picked[m]] == LBM_BIOFILM, "pick %d (%lld) is not BIOFILM", m,
                   (long long)picked[m]);
+    // checkpoint, two warm re-solves, restore, the same two again: the
+    // restored solver continues from the saved state and step counters
+    size_t bytes = 0;
+    EMU_CHECK(lbm_solver_state_size(sv, &bytes) == LBM_OK && bytes > 0, "state size");
+    std::vector<char> saved(bytes);
+    EMU_CHECK(lbm_solver_get_state(sv, saved.data(), bytes) == LBM_OK, "get state: %s", lbm_last_error(ctx));
+    lbm_info i1{}, i2{}, i3{}, i4{};
+    EMU_CHECK(lbm_solver_fluid(sv, 1e-6, 200000, 1, &i1) == LBM_OK && lbm_solver_ad(sv, 1e-6, 200000, 1, &i2) ==
+                  LBM_OK, "solves after the checkpoint");
+    EMU_CHECK(lbm_solver_put_state(sv, saved.data(), bytes) == LBM_OK, "put state: %s", lbm_last_error(ctx));
+    EMU_CHECK(lbm_solver_fluid(sv, 1e-6, 200000, 1, &i3) == LBM_OK && lbm_solver_ad(sv, 1e-6, 200000, 1, &i4) ==
+                  LBM_OK, "solves after the restore");
+    EMU_CHECK(i1.iters == i3.iters && i2.iters == i4.iters && i1.iters == f.iters,
+              "restored solves took %lld + %lld steps against %lld + %lld", (long long)i3.iters, (long long)i4.iters,
+              (long long)i1.iters, (long long)i2.iters);
     lbm_solver_destroy(sv);
     lbm_ctx_destroy(ctx);
     ran->fetch_add(1);
