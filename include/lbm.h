@@ -47,6 +47,17 @@
  *   and LBM_STALLED still fill every output.  LBM_EDEVICE means a HIP call
  *   failed; lbm_last_error() then holds the HIP message.  No call aborts
  *   the process.
+ * Tracing: with LBM_ROCTX=1 in the environment when the first range opens,
+ *   the library marks its host phases as roctx ranges, which rocprofv3
+ *   --marker-trace records: lbm.fluid.steady, lbm.ad.steady (one steady
+ *   solve), lbm.update_cells, lbm.coupled.initial and lbm.coupled.update
+ *   (one step of the coupled loop), lbm.mfc.hour and lbm.biofilm.step (the
+ *   hourly model loop), lbm.srv.prepare, lbm.srv.step, lbm.srv.solo and
+ *   lbm.srv.escalated (the server's threads).  The marker library
+ *   (librocprofiler-sdk-roctx.so.1, else libroctx64.so.4) is opened with
+ *   dlopen; LBM_ROCTX=<path> names another one.  If it cannot be opened,
+ *   one message goes to stderr and nothing else changes.  Unset or 0: no
+ *   ranges.
  */
 #ifndef LBM_H
 #define LBM_H

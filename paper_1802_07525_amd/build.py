@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lbm.so")
-SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp",
+SOURCES = ["kernels.hip", "bio.hip", "geom.cpp", "solver.cpp", "biofilm.cpp", "api.cpp", "server.cpp", "trace.cpp",
            "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -45,7 +45,7 @@ def build(verbose: bool = False) -> str:
     for obj, log in results:
         if verbose and log.strip():
             print(log, flush=True)
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", LIB + ".tmp"] + \
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-ldl", "-o", LIB + ".tmp"] + \
           [o for o, _ in results]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)

@@ -66,6 +66,7 @@ lbm_status lbm_biofilm_step(lbm_bio *b, const lbm_biofilm_params *fp, uint64_t s
     if (!b || !fp)
         return LBM_EINVAL;
     lbm_solver *s = b->s;
+    Range rg("lbm.biofilm.step");
     std::string msg = check_film(*fp);
     if (!msg.empty())
         return set_err(s->ctx, LBM_EINVAL, msg);
@@ -207,6 +208,7 @@ lbm_status lbm_mfc_run(lbm_bio *b, const lbm_biofilm_params *fp, int n_hours, ui
     using clk = std::chrono::steady_clock;
     auto secs = [](clk::time_point a, clk::time_point z) { return std::chrono::duration<double>(z - a).count(); };
     for (int h = 0; h < n_hours; ++h) {
+        Range rg("lbm.mfc.hour");
         lbm_mfc_interval &r = series[h];
         r = lbm_mfc_interval{};
         lbm_info fi{}, ai{};

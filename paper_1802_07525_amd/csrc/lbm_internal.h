@@ -121,6 +121,21 @@ inline hipError_t stream_copy(lbm_ctx *ctx, void *dst, const void *src, size_t b
 lbm_status set_err(lbm_ctx *ctx, lbm_status st, const std::string &msg);
 lbm_status hip_err(lbm_ctx *ctx, hipError_t e, const char *where);
 
+// ---- roctx ranges (trace.cpp) --------------------------------------------
+// A range named `name` (a string literal) on the calling thread for the
+// object's lifetime, as a roctx push and pop; shown by rocprofv3
+// --marker-trace.  A no-op unless LBM_ROCTX is set (lbm.h).
+class Range {
+  public:
+    explicit Range(const char *name);
+    ~Range();
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+
+  private:
+    bool on_;
+};
+
 } // namespace lbmh
 
 struct lbm_solver {

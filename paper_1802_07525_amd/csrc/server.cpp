@@ -457,7 +457,10 @@ struct lbm_server {
                 prep_q.pop_front();
                 j->preparing = true;
             }
-            prepare(j);
+            {
+                Range rg("lbm.srv.prepare");
+                prepare(j);
+            }
             std::lock_guard<std::mutex> lk(mu);
             j->preparing = false;
             if (stopping)
@@ -1011,7 +1014,10 @@ struct lbm_server {
                     j->t_admit = now_s(t0);
             }
             ++solo_active;
-            solve_alone(j, solo_ctx[lane]);
+            {
+                Range rg(j->lane == LBM_LANE_ESCALATED ? "lbm.srv.escalated" : "lbm.srv.solo");
+                solve_alone(j, solo_ctx[lane]);
+            }
             --solo_active;
             std::lock_guard<std::mutex> lk(mu);
             lane_leave_locked();
@@ -1121,7 +1127,10 @@ struct lbm_server {
         hipError_t e = hipSetDevice(device);
         while (e == hipSuccess) {
             bool idle = false;
-            e = step_once(&idle);
+            {
+                Range rg("lbm.srv.step");
+                e = step_once(&idle);
+            }
             if (e != hipSuccess)
                 break;
             if (idle) {

@@ -409,6 +409,7 @@ lbm_status steady(lbm_solver *s, int which, double tol, int64_t max_iter, int wa
 {
     if (!(tol >= 0.0) || max_iter < 1)
         return set_err(s->ctx, LBM_EINVAL, "tol must be >= 0 and max_iter >= 1");
+    Range rg(which == LBM_SOLVER_FLUID ? "lbm.fluid.steady" : "lbm.ad.steady");
     HIPCHK(hipSetDevice(s->ctx->device), "set device");
     lbm_status stt = which == LBM_SOLVER_FLUID ? ensure_fluid(s) : ensure_ad(s);
     if (stt)
@@ -1080,6 +1081,7 @@ lbm_status lbm_solver_update_cells(lbm_solver *s, const int64_t *idx, const uint
 {
     if (!s || n < 0 || (n > 0 && (!idx || !new_cls)))
         return LBM_EINVAL;
+    Range rg("lbm.update_cells");
     const int64_t N = s->geo.N;
     const lbm_grid &g = s->grid;
     std::vector<uint8_t> trial = s->cls;
@@ -1330,6 +1332,7 @@ lbm_status lbm_coupled_run(lbm_solver *s, int n_updates, const double *xi, doubl
     double acc = 0.0;
     lbm_info fi, ai;
     for (int m = 0; m <= n_updates; ++m) {
+        Range rg(m > 0 ? "lbm.coupled.update" : "lbm.coupled.initial");
         if (m > 0) {
             lbm_status st = get_field(s, LBM_FIELD_C, C.data());
             if (st)

@@ -81,7 +81,7 @@ def test_oracle_under_asan_ubsan(tmp_path):
 
 
 CLANG = os.path.join(ROCM, "llvm", "bin", "clang++")
-EMU_SRC = ["server.cpp", "solver.cpp", "api.cpp", "geom.cpp", "biofilm.cpp"]
+EMU_SRC = ["server.cpp", "solver.cpp", "api.cpp", "geom.cpp", "biofilm.cpp", "trace.cpp"]
 
 
 def _emu_build(tmp_path, name, compiler, flags):
@@ -90,7 +90,7 @@ def _emu_build(tmp_path, name, compiler, flags):
     _run([compiler, "-std=c++17", "-g"] + flags +
          ["-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"), "-I" + os.path.join(ROOT, "include"),
           "-I" + csrc] + [os.path.join(csrc, f) for f in EMU_SRC] +
-         [os.path.join(HERE, "sanitize", "server_emu.cpp"), "-o", exe, "-lpthread"])
+         [os.path.join(HERE, "sanitize", "server_emu.cpp"), "-o", exe, "-lpthread", "-ldl"])
     return exe
 
 
@@ -133,3 +133,44 @@ def test_server_emulation_repeated(tmp_path):
     exe = _emu_build(tmp_path, "emu_plain", "g++", ["-O1"])
     for k in range(4):
         _emu_run(exe, 4, 16 if k % 2 else 4)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or shutil.which("gcc") is None, reason="no g++/gcc")
+@pytest.mark.skipif(not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime.h")),
+                    reason="no HIP headers")
+def test_roctx_ranges_balanced_on_every_thread(tmp_path):
+    """roctx ranges (LBM_ROCTX) around the host phases, loaded by dlopen:
+    the emulated serving loop, coupled loops and hourly model loop run with
+    tests/sanitize/roctx_stub.c as the marker library.  Every phase's range
+    opens, every push has its pop on its own thread, no thread ends with a
+    range open; without LBM_ROCTX the marker library is never loaded."""
+    stub = str(tmp_path / "libroctx_stub.so")
+    _run(["gcc", "-std=c99", "-O1", "-fPIC", "-shared", os.path.join(HERE, "sanitize", "roctx_stub.c"),
+          "-o", stub, "-lpthread"])
+    exe = _emu_build(tmp_path, "emu_roctx", "g++", ["-O1"])
+    out = str(tmp_path / "ranges.txt")
+    _emu_run(exe, 1, 16, {"LBM_ROCTX": stub, "ROCTX_STUB_OUT": out})
+    rec = {}
+    names = {}
+    for line in open(out):
+        f = line.split()
+        if f[0] == "range":
+            names[f[1]] = int(f[2])
+        else:
+            rec[f[0]] = int(f[1])
+    assert rec["pushes"] > 0 and rec["pushes"] == rec["pops"], rec
+    assert rec["bad_pops"] == 0 and rec["unbalanced"] == 0, rec
+    # the steady solves nest inside the served, coupled and hourly phases
+    assert rec["max_depth"] >= 2, rec
+    for n in ("lbm.fluid.steady", "lbm.ad.steady", "lbm.update_cells", "lbm.coupled.initial",
+              "lbm.coupled.update", "lbm.mfc.hour", "lbm.biofilm.step", "lbm.srv.prepare", "lbm.srv.step",
+              "lbm.srv.solo"):
+        assert names.get(n, 0) > 0, (n, names)
+    assert set(names) <= {"lbm.fluid.steady", "lbm.ad.steady", "lbm.update_cells", "lbm.coupled.initial",
+                          "lbm.coupled.update", "lbm.mfc.hour", "lbm.biofilm.step", "lbm.srv.prepare",
+                          "lbm.srv.step", "lbm.srv.solo", "lbm.srv.escalated"}, names
+    # a library that cannot be opened: one message, no ranges, the run unchanged
+    env = dict(os.environ, LBM_ROCTX=str(tmp_path / "missing.so"), EMU_SERVED_TILE_TY="4")
+    r = subprocess.run([exe, "1"], env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
+    assert r.stderr.count("cannot open the roctx library") == 1, r.stderr[-2000:]
