@@ -47,10 +47,12 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def _code_only(text):
-    """Source text without comments and blank space (comment edits do not
-    change the kernels)."""
+    """Source text without comments, blank space and roctx range statements
+    (comment edits and host-side trace ranges change neither the kernels
+    nor their launch shapes)."""
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     text = re.sub(r"//[^\n]*", " ", text)
+    text = re.sub(r"\bRange rg\([^;]*\);", " ", text)
     return " ".join(text.split())
 
 

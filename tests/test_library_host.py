@@ -182,3 +182,21 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_counter_key_ignores_comments_and_trace_ranges():
+    """The key that ties stored HBM counters to the kernels' code changes
+    with code, not with comments or host-side roctx range statements."""
+    import importlib
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    try:
+        bench = importlib.import_module("bench")
+    finally:
+        sys.path.remove(root)
+    base = "int f(int a)\n{\n    return a + 1;\n}\n"
+    ranged = "int f(int a) // one\n{\n    Range rg(a ? \"x.y\" : \"x.z\");\n    /* two */ return a + 1;\n}\n"
+    assert bench._code_only(base) == bench._code_only(ranged)
+    assert bench._code_only(base) != bench._code_only(base.replace("+ 1", "+ 2"))
+    assert bench._code_only(base) != bench._code_only(base.replace("return", "g(); return"))
