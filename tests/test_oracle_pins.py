@@ -164,6 +164,32 @@ def test_channel_inlet_outlet_develops_parabola():
     assert abs(fout - fin) / fin < 1e-6   # residual level: tol 1e-8 per step over ~200 columns
 
 
+@pytest.mark.parametrize("lat,shape,periodic", [(O.D2Q9, (6, 12), (0, 1, 0)),
+                                                 (O.D3Q19, (4, 5, 10), (0, 1, 1))])
+def test_uniform_plug_flow_is_exact_fixed_point_of_inlet_and_outlet(lat, shape, periodic):
+    """Production boundaries on an open duct (periodic across the flow, no
+    walls): the uniform equilibrium at rho = 1, u = (u_in, 0, 0) is an exact
+    fixed point of the whole step.  BGK leaves an equilibrium unchanged;
+    the moving-wall inlet (reading 5) holds because f_i^eq - f_opp^eq is
+    twice the odd part 3 w_i c_i.u; the anti-bounce-back outlet at rho_out = 1
+    (reading 6) holds because f_i^eq + f_opp^eq is twice the even part
+    w_i (1 + 9/2 (c_i.u)^2 - 3/2 u^2).  The equilibrium is built here from
+    the textbook weights and Eqs. 5-8, not from the oracle; a dropped u^2
+    term or a wrong factor in either boundary moves f by O(w u^2) ~ 1e-4."""
+    c = O.lattice_tables(lat)[0]
+    wts = {9: {0: 4 / 9, 1: 1 / 9, 2: 1 / 36}, 19: {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}}[c.shape[0]]
+    w = np.array([wts[int(k)] for k in (c ** 2).sum(1)])
+    uin = 0.05
+    cu = c[:, 0] * uin
+    fe = w * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uin ** 2)
+    cls = np.zeros(shape, np.uint8)
+    f0 = np.repeat(fe[:, None], cls.size, axis=1)
+    f, U, rho = O.fluid_run(cls, f0, 0.8, uin, 50, periodic=periodic)
+    assert np.abs(f - f0).max() < 1e-14
+    assert np.abs(rho - 1.0).max() < 1e-14
+    assert np.abs(U[0] - uin).max() < 1e-14 and np.abs(U[1:]).max() < 1e-14
+
+
 def _porous(nx, ny, seed, frac=0.3):
     st, cls, _ = O.geom_discs(nx, ny, 2, 4, frac, 0, seed)
     assert st == "OK"
