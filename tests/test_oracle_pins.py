@@ -190,6 +190,43 @@ def test_uniform_plug_flow_is_exact_fixed_point_of_inlet_and_outlet(lat, shape, 
     assert np.abs(U[0] - uin).max() < 1e-14 and np.abs(U[1:]).max() < 1e-14
 
 
+@pytest.mark.parametrize("lat,shape,periodic,outlet", [(O.D2Q5, (6, 12), (0, 1, 0), 0),
+                                                        (O.D2Q5, (6, 12), (0, 1, 0), 1),
+                                                        (O.D2Q9, (6, 12), (0, 1, 0), 0),
+                                                        (O.D3Q7, (4, 5, 10), (0, 1, 1), 0),
+                                                        (O.D3Q7, (4, 5, 10), (0, 1, 1), 1)])
+def test_uniform_substrate_is_exact_fixed_point_of_inlet_and_outlet(lat, shape, periodic, outlet):
+    """Substrate boundaries on an open duct in uniform flow: the uniform
+    equilibrium at C = c_in is an exact fixed point of the substrate step.
+    The Dirichlet inlet (anti-bounce-back with the equilibrium's even part)
+    holds because g_i^eq + g_opp^eq is twice that even part; the
+    zero-gradient outlet copies the node's own state; the Dirichlet outlet
+    at c_out = c_in holds as the inlet does.  Equilibria from the textbook:
+    w_i C (1 + c_i.u / c_s^2) with c_s^2 = 1/3 (D2Q5: 1/3, 1/6) and 1/4 (D3Q7:
+    1/4, 1/8), and the second-order Eq. 5 form on D2Q9."""
+    c = O.lattice_tables(lat)[0]
+    q = c.shape[0]
+    uin, c_in = 0.05, 0.8
+    cu = c[:, 0] * uin
+    if q == 9:
+        wts = {0: 4 / 9, 1: 1 / 9, 2: 1 / 36}
+        w = np.array([wts[int(k)] for k in (c ** 2).sum(1)])
+        ge = w * c_in * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * uin ** 2)
+    else:
+        w0, cs2 = (1 / 3, 1 / 3) if q == 5 else (1 / 4, 1 / 4)
+        w = np.where((c ** 2).sum(1) == 0, w0, (1 - w0) / (q - 1))
+        ge = w * c_in * (1 + cu / cs2)
+    cls = np.zeros(shape, np.uint8)
+    dim = 3 if len(shape) == 3 else 2
+    U = np.zeros((dim, cls.size))
+    U[0] = uin
+    g0 = np.repeat(ge[:, None], cls.size, axis=1)
+    D = 0.05
+    g, C = O.ad_run(cls, g0, U, D, c_in, 0.0, 50, outlet=outlet, c_out=c_in, periodic=periodic, lat=lat)
+    assert np.abs(g - g0).max() < 1e-14
+    assert np.abs(C - c_in).max() < 1e-14
+
+
 def _porous(nx, ny, seed, frac=0.3):
     st, cls, _ = O.geom_discs(nx, ny, 2, 4, frac, 0, seed)
     assert st == "OK"
