@@ -49,10 +49,10 @@
  *   the process.
  * Tracing: with LBM_ROCTX=1 in the environment when the first range opens,
  *   the library marks its host phases as roctx ranges, which rocprofv3
- *   --marker-trace records: lbm.fluid.steady, lbm.ad.steady (one steady
- *   solve), lbm.update_cells, lbm.coupled.initial and lbm.coupled.update
- *   (one step of the coupled loop), lbm.mfc.hour and lbm.biofilm.step (the
- *   hourly model loop), lbm.srv.prepare, lbm.srv.step, lbm.srv.solo and
+ *   --marker-trace records: lbm.geometry (a generated electrode),
+ *   lbm.fluid.steady, lbm.ad.steady (one steady solve), lbm.update_cells,
+ *   lbm.coupled.initial and lbm.coupled.update (one step of the coupled
+ *   loop), lbm.mfc.hour and lbm.biofilm.step (the hourly model loop), lbm.srv.prepare, lbm.srv.step, lbm.srv.solo and
  *   lbm.srv.escalated (the server's threads).  The marker library
  *   (librocprofiler-sdk-roctx.so.1, else libroctx64.so.4) is opened with
  *   dlopen; LBM_ROCTX=<path> names another one.  If it cannot be opened,

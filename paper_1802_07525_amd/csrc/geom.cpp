@@ -114,6 +114,7 @@ lbm_status lbm_geom_discs(lbm_grid g, const lbm_disc_params *p, uint64_t seed, u
     if (!p || !cls || g.nz != 1 || g.nx < 4 || g.ny < 3 || p->r_min < 0 || p->r_max < p->r_min ||
         !(p->solid_frac >= 0.0 && p->solid_frac <= 1.0))
         return LBM_EINVAL;
+    Range rg("lbm.geometry");
     fill_chassis(g, cls);
     const int64_t xa = g.nx / 4, xb = 3 * (int64_t)g.nx / 4, ya = 1, yb = g.ny - 1;
     const int64_t region = (xb - xa) * (yb - ya);
@@ -188,6 +189,7 @@ lbm_status lbm_geom_fibres(lbm_grid g, const lbm_fibre_params *p, uint64_t seed,
     if (!p || !cls || g.nx < 4 || g.ny < 3 || g.nz < 3 || p->r_min < 0 || p->r_max < p->r_min ||
         !(p->solid_frac >= 0.0 && p->solid_frac <= 1.0))
         return LBM_EINVAL;
+    Range rg("lbm.geometry");
     fill_chassis(g, cls);
     const int64_t xa = g.nx / 4, xb = 3 * (int64_t)g.nx / 4;
     const int64_t region = (xb - xa) * (int64_t)(g.ny - 2) * (g.nz - 2);

@@ -200,3 +200,38 @@ def test_counter_key_ignores_comments_and_trace_ranges():
     assert bench._code_only(base) == bench._code_only(ranged)
     assert bench._code_only(base) != bench._code_only(base.replace("+ 1", "+ 2"))
     assert bench._code_only(base) != bench._code_only(base.replace("return", "g(); return"))
+
+
+def test_built_library_opens_roctx_ranges(tmp_path):
+    """The built library's roctx ranges (LBM_ROCTX), through the C ABI on
+    the CPU: a generated electrode is one balanced lbm.geometry range on a
+    stub marker library (tests/sanitize/roctx_stub.c); a library that
+    cannot be opened leaves the call's result unchanged."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    stub = str(tmp_path / "libroctx_stub.so")
+    subprocess.run(["gcc", "-std=c99", "-O1", "-fPIC", "-shared",
+                    os.path.join(root, "tests", "sanitize", "roctx_stub.c"), "-o", stub, "-lpthread"],
+                   check=True)
+    code = ("import sys, hashlib; sys.path.insert(0, %r); import paper_1802_07525_amd as lbm; "
+            "st, cls, _ = lbm.lbm_geom_fibres(24, 12, 12, 1, 2, 0.2, 5); "
+            "st2, cls2, _ = lbm.lbm_geom_discs(64, 32, 2, 4, 0.3, 0, 7); "
+            "print(st, st2, hashlib.sha256(cls.tobytes() + cls2.tobytes()).hexdigest())" % root)
+    runs = {}
+    for name, val in (("off", None), ("stub", stub), ("missing", str(tmp_path / "missing.so"))):
+        env = {k: v for k, v in os.environ.items() if k != "LBM_ROCTX"}
+        env["ROCTX_STUB_OUT"] = str(tmp_path / ("%s.txt" % name))
+        if val:
+            env["LBM_ROCTX"] = val
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        runs[name] = r
+    assert runs["off"].stdout == runs["stub"].stdout == runs["missing"].stdout
+    assert runs["off"].stdout.startswith("0 0 ")
+    assert "cannot open the roctx library" in runs["missing"].stderr
+    assert not os.path.exists(str(tmp_path / "off.txt"))
+    rec = dict(line.split(None, 1) for line in open(str(tmp_path / "stub.txt")))
+    assert rec["pushes"].strip() == rec["pops"].strip() == "2"
+    assert rec["bad_pops"].strip() == "0" and rec["unbalanced"].strip() == "0"
+    assert rec["range"].strip() == "lbm.geometry 2"

@@ -62,12 +62,13 @@ def test_geometry_host_code_under_asan_ubsan(tmp_path):
     csrc = os.path.join(ROOT, "paper_1802_07525_amd", "csrc")
     inc = ["-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"),
            "-I" + os.path.join(ROOT, "include"), "-I" + csrc]
-    obj = str(tmp_path / "geom.o")
+    objs = [str(tmp_path / "geom.o"), str(tmp_path / "trace.o")]
     exe = str(tmp_path / "host_driver")
-    _run(["g++", "-std=c++17"] + SAN + inc + ["-c", os.path.join(csrc, "geom.cpp"), "-o", obj])
-    _run(["g++", "-std=c++17"] + SAN + inc + [os.path.join(HERE, "sanitize", "host_driver.cpp"), obj,
-          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib"),
-          "-o", exe])
+    for src, obj in zip(("geom.cpp", "trace.cpp"), objs):
+        _run(["g++", "-std=c++17"] + SAN + inc + ["-c", os.path.join(csrc, src), "-o", obj])
+    _run(["g++", "-std=c++17"] + SAN + inc + [os.path.join(HERE, "sanitize", "host_driver.cpp")] + objs +
+         ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+          "-ldl", "-o", exe])
     assert _run([exe]).strip().endswith("ok")
 
 
@@ -168,7 +169,7 @@ def test_roctx_ranges_balanced_on_every_thread(tmp_path):
         assert names.get(n, 0) > 0, (n, names)
     assert set(names) <= {"lbm.fluid.steady", "lbm.ad.steady", "lbm.update_cells", "lbm.coupled.initial",
                           "lbm.coupled.update", "lbm.mfc.hour", "lbm.biofilm.step", "lbm.srv.prepare",
-                          "lbm.srv.step", "lbm.srv.solo", "lbm.srv.escalated"}, names
+                          "lbm.srv.step", "lbm.srv.solo", "lbm.srv.escalated", "lbm.geometry"}, names
     # a library that cannot be opened: one message, no ranges, the run unchanged
     env = dict(os.environ, LBM_ROCTX=str(tmp_path / "missing.so"), EMU_SERVED_TILE_TY="4")
     r = subprocess.run([exe, "1"], env=env, capture_output=True, text=True, timeout=600)
