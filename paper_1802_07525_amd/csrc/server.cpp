@@ -904,8 +904,8 @@ struct lbm_server {
                 std::lock_guard<std::mutex> lk(mu);
                 if (ready.empty())
                     return hipSuccess;
-                auto head = ready.begin();
-                j = head->second;
+                auto first = ready.begin();
+                j = first->second;
                 for (int s = 0; s < cfg.max_slots; ++s)
                     if (!slot_job[s]) {
                         sid = s;
@@ -916,7 +916,7 @@ struct lbm_server {
                 // the pool counters are read by lbm_server_stats
                 if (!alloc.alloc(j->lay.total, &j->off))
                     return hipSuccess;
-                ready.erase(head);
+                ready.erase(first);
                 ++n_active;
             }
             hipError_t e = admit(j, sid);
