@@ -141,6 +141,41 @@ def test_poiseuille_second_order():
     assert e16 < 3e-3
 
 
+def _poiseuille3d_error(H, tau, axis, g=1e-6):
+    """D3Q19 plane Poiseuille flow between two walls normal to y or to z
+    (periodic in the other two directions), driven by a body force in x."""
+    n = H + 2
+    shape, per = ((n, 4, 4), (1, 1, 0)) if axis == "z" else ((4, n, 4), (1, 0, 1))
+    cls = np.zeros(shape, np.uint8)
+    if axis == "z":
+        cls[0] = O.WALL
+        cls[-1] = O.WALL
+    else:
+        cls[:, 0] = O.WALL
+        cls[:, -1] = O.WALL
+    nu = (tau - 0.5) / 3
+    f, U, _ = O.fluid_run(cls, O.fluid_init(cls), tau, 0.0, int(25 * H * H / nu), periodic=per,
+                          force=(g, 0.0, 0.0))
+    k = np.arange(n)
+    exact = g / (2 * nu) * (k - 0.5) * (n - 1.5 - k)
+    ux = U[0].reshape(shape)
+    prof = ux[:, 1, 1] if axis == "z" else ux[1, :, 1]
+    return np.abs(prof[1:-1] - exact[1:-1]).max() / exact.max(), np.abs(U[1:]).max()
+
+
+@pytest.mark.parametrize("axis", ["y", "z"])
+def test_poiseuille_3d_exact_at_magic_tau_and_second_order(axis):
+    """The 3-D lattice (D3Q19) with half-way bounce-back on walls normal to
+    y and to z: the parabola to round-off at (tau - 1/2)^2 = 3/16, no
+    cross-flow, and second order (error ~4x smaller per doubling) at
+    tau = 0.8 -- the properties the 2-D pins fix for D2Q9."""
+    e, cross = _poiseuille3d_error(8, (2.0 + math.sqrt(3.0)) / 4.0, axis)
+    assert e < 1e-10 and cross < 1e-14
+    e8, e16 = _poiseuille3d_error(8, 0.8, axis)[0], _poiseuille3d_error(16, 0.8, axis)[0]
+    assert 3.6 < e8 / e16 < 4.4
+    assert e16 < 3e-3
+
+
 def test_channel_inlet_outlet_develops_parabola():
     """Production boundaries (velocity inlet, pressure outlet): the
     mid-length momentum profile j = rho u of a long empty channel is the
