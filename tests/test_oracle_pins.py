@@ -398,6 +398,36 @@ def test_gaussian_pulse_exact_moment_recurrences():
     assert abs(V - pred) / pred < 1e-11
 
 
+def test_gaussian_pulse_d3q7_exact_moment_recurrences():
+    """The same recurrences on the 3-D substrate lattice (D3Q7, linear
+    equilibrium, textbook weights 1/4 and 1/8, c_s^2 = 1/4): along the flow
+    with c_s^2 - u^2, across it (u_z = 0) with c_s^2; the centroid moves
+    exactly u per step along x and stays put along z."""
+    nx, ny, nz, tau, ux, T = 160, 4, 96, 0.8, 0.05, 200
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X, Z = X.ravel().astype(float), Z.ravel().astype(float)
+    # centred across the periodic z extent, far (> 7 widths) from its wrap
+    C0 = np.exp(-((X - 50.0) ** 2 + (Z - 47.5) ** 2) / (2 * 4.0 ** 2))
+    c = O.lattice_tables(O.D3Q7)[0]
+    cs2 = 0.25
+    w = np.where((c ** 2).sum(1) == 0, 0.25, 0.125)
+    g = np.array([w[i] * C0 * (1 + c[i, 0] * ux / cs2) for i in range(7)])
+    u = np.zeros((3, X.size))
+    u[0] = ux
+    D = (tau - 0.5) * cs2
+    _, C = O.ad_run(np.zeros((nz, ny, nx), np.uint8), g, u, D, 1.0, 0.0, T, periodic=(1, 1, 1))
+    M0, M = C0.sum(), C.sum()
+    assert abs(M - M0) / M0 < 1e-13
+    assert abs((X * C).sum() / M - (X * C0).sum() / M0 - ux * T) < 1e-10
+    assert abs((Z * C).sum() / M - (Z * C0).sum() / M0) < 1e-10
+    om = 1.0 / tau
+    for A, a2 in ((X, cs2 - ux ** 2), (Z, cs2)):
+        V0 = (A * A * C0).sum() - (A * C0).sum() ** 2 / M0
+        pred = V0 + sum(2 * (1 - om) * a2 * M0 / om * (1 - (1 - om) ** t) + a2 * M0 for t in range(T))
+        V = (A * A * C).sum() - (A * C).sum() ** 2 / M
+        assert abs(V - pred) / pred < 1e-11
+
+
 def test_gaussian_pulse_second_order_exact_recurrences():
     """D2Q9 substrate with the Eq. 5 equilibrium, uniform u, started at
     equilibrium.  Totals over the box obey a closed linear map: the
