@@ -499,18 +499,22 @@ def _ad_channel(N, u, k):
     return cls, uu
 
 
-def _two_mode(N, tau, u, k, outlet, c_in, c_out):
+def _two_mode(N, tau, u, k, outlet, c_in, c_out, w=1.0 / 6.0, cs2=1.0 / 3.0):
     """Exact steady solution of the D2Q5 map on a y-uniform channel: in the
     bulk every population is a combination of r^x modes, r a root of
     (b + G a) r^2 - (a (A + b) + G (1 + a^2)) r + (A + G a) = 0 with
     a = 1 - 1/tau, A = w(1+3u)/tau - w k, b = w(1-3u)/tau - w k,
     G = 1/3 + (2/3) k tau, w = 1/6; the inlet and outlet link rules fix the
-    two amplitudes."""
-    w, om = 1.0 / 6.0, 1.0 / tau
+    two amplitudes.  The rest and transverse populations (weight 1 - 2w
+    together; the transverse ones bounce back off the channel walls) hold
+    (1 - 2w) C (1 - k tau) at steady state, so G = 1 - (1 - 2w)(1 - k tau)
+    in general, and 3u is u / c_s^2: with w = 1/8, c_s^2 = 1/4 the same
+    solution holds for D3Q7 on a y- and z-uniform duct."""
+    om = 1.0 / tau
     a = 1 - om
-    A = om * w * (1 + 3 * u) - w * k
-    B = om * w * (1 - 3 * u) - w * k
-    G = 1.0 / 3.0 + (2.0 / 3.0) * k / om
+    A = om * w * (1 + u / cs2) - w * k
+    B = om * w * (1 - u / cs2) - w * k
+    G = 1.0 - (1.0 - 2.0 * w) * (1.0 - k / om)
     roots = np.roots([B + G * a, -(a * (A + B) + G * (1 + a * a)), A + G * a])
     a1 = lambda r: A * r / (r - a)      # post-collision +x amplitude
     a3 = lambda r: B / (1 - a * r)      # post-collision -x amplitude
@@ -539,6 +543,25 @@ def test_ad_1d_exact_discrete_solution(N, tau, u, k, outlet, c_out):
     _, C = O.ad_run(cls, g, uu, D, 1.0, k, 200000, outlet, c_out)
     C = C.reshape(3, N)[1]
     assert np.abs(C - _two_mode(N, tau, u, k, outlet, 1.0, c_out)).max() < 1e-12
+
+
+@pytest.mark.parametrize("N,tau,u,k,outlet,c_out", [
+    (48, 0.7, 0.01, 1e-3, 0, 0.0),
+    (40, 1.0, 0.03, 1e-2, 0, 0.0),
+    (48, 0.7, 0.01, 1e-3, 1, 0.3),
+])
+def test_ad_1d_exact_discrete_solution_d3q7(N, tau, u, k, outlet, c_out):
+    """D3Q7 on a 3 x 3 duct (walls around one line of nodes, biofilm on it
+    when k > 0): the two-mode solution with the D3Q7 weights."""
+    cls = np.full((3, 3, N), O.WALL, np.uint8)
+    cls[1, 1] = O.BIOFILM if k > 0 else O.FLUID
+    uu = np.zeros((3, cls.size))
+    uu[0] = u
+    D = (tau - 0.5) / 4
+    g = O.ad_init(cls, uu, 1.0)
+    _, C = O.ad_run(cls, g, uu, D, 1.0, k, 200000, outlet, c_out)
+    C = C.reshape(3, 3, N)[1, 1]
+    assert np.abs(C - _two_mode(N, tau, u, k, outlet, 1.0, c_out, w=1.0 / 8.0, cs2=0.25)).max() < 1e-12
 
 
 def test_ad_no_sink_zero_gradient_is_uniform():
