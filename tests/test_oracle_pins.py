@@ -605,6 +605,27 @@ def test_ad_steady_flux_balance_porous():
     assert abs(fi - fo) / fi < 1e-6
 
 
+def test_steady_balances_3d_fibrous():
+    """3-D (D3Q19 + D3Q7) on a seeded fibre electrode with its biofilm
+    layer: each inlet node takes in exactly u_in per step, fluid inflow
+    equals outflow at steady state, and substrate inflow - outflow equals
+    what the biofilm consumes."""
+    st, cls, _ = O.geom_fibres(32, 14, 14, 1, 2, 0.2, 3)
+    assert st == "OK"
+    cls = O.biofilm_layer(cls)
+    assert O.percolates(cls)
+    fl = O.fluid_solve(cls, 0.8, 0.02, 1e-9, 100000)
+    assert fl["status"] == "OK"
+    fi, fo = O.fluid_fluxes(cls, fl["f"], 0.02)
+    assert fi == pytest.approx(0.02 * 12 * 12, rel=1e-14)
+    assert abs(fi - fo) / fi < 1e-6
+    ad = O.ad_solve(cls, fl["U"], 0.1, 1.0, 5e-3, 1e-12, 200000)
+    assert ad["status"] == "OK"
+    fin, fout, sink = O.ad_fluxes(cls, ad["g"], 1.0, 5e-3)
+    assert sink > 0
+    assert abs((fin - fout) - sink) / sink < 1e-6
+
+
 # ---------------------------------------------------------- stop semantics
 def test_blocked_medium_has_no_flow():
     """A medium that does not percolate carries no steady flow: the part
