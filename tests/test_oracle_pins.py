@@ -872,6 +872,122 @@ def test_bruteforce_push_ad():
         g = got
 
 
+def _tiny_mask3d():
+    cls = np.zeros((5, 5, 6), np.uint8)
+    cls[0] = O.WALL
+    cls[-1] = O.WALL
+    cls[:, 0] = O.WALL
+    cls[:, -1] = O.WALL
+    cls[2, 2, 3] = O.SOLID
+    cls[1, 2, 2] = O.BIOFILM
+    return cls
+
+
+def _push3(cls, f, c, send):
+    """Push every stored population of the active nodes along its velocity;
+    send(n, i, p, target) returns (direction, node) for pushes that leave
+    through x or hit a blocked node, else None for a plain move."""
+    nz, ny, nx = cls.shape
+    q = c.shape[0]
+    arr = np.full((q, cls.size), np.nan)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                n = x + nx * (y + ny * z)
+                for i in range(q):
+                    t = (x + c[i, 0], y + c[i, 1], z + c[i, 2])
+                    r = send(n, i, f[i, n], t)
+                    if r is None:
+                        continue
+                    if r is True:
+                        arr[i, t[0] + nx * (t[1] + ny * t[2])] = f[i, n]
+                    else:
+                        arr[r[0], n] = r[1]
+    return arr
+
+
+def test_bruteforce_push_fluid_d3q19():
+    """One D3Q19 fluid step in push form on a 6 x 5 x 5 duct with a solid
+    and a biofilm node, against the oracle's pull form: moving-wall inlet,
+    anti-bounce-back outlet at rho_out = 1 with the node's own velocity,
+    bounce-back on blocked nodes, BGK with the textbook D3Q19 equilibrium
+    (weights 1/3, 1/18, 1/36)."""
+    cls = _tiny_mask3d()
+    nz, ny, nx = cls.shape
+    c, _, opp, _ = O.lattice_tables(O.D3Q19)
+    w = np.array([{0: 1 / 3, 1: 1 / 18, 2: 1 / 36}[int(k)] for k in (c ** 2).sum(1)])
+    fl = cls.ravel() == O.FLUID
+    rng = np.random.default_rng(6)
+    f = np.outer(w, np.ones(cls.size)) * (1 + 0.2 * rng.random((19, cls.size))) * fl
+    tau, u_in = 0.71, 0.03
+    for _ in range(3):
+        def send(n, i, p, t):
+            if not fl[n]:
+                return None
+            j = opp[i]
+            if t[0] < 0:
+                return (j, p + 6 * w[j] * c[j, 0] * u_in)
+            if t[0] >= nx:
+                us = c.T @ f[:, n] / f[:, n].sum()
+                cu = c[j] @ us
+                return (j, -p + 2 * w[j] * (1 + 4.5 * cu * cu - 1.5 * us @ us))
+            if cls[t[2], t[1], t[0]] != O.FLUID:
+                return (j, p)
+            return True
+        arr = _push3(cls, f, c, send)
+        want = np.zeros_like(f)
+        for n in np.flatnonzero(fl):
+            fi = arr[:, n]
+            assert not np.isnan(fi).any()
+            rho = fi.sum()
+            u = c.T @ fi / rho
+            cu = c @ u
+            want[:, n] = fi - (fi - w * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * u @ u)) / tau
+        got, _, _ = O.fluid_step(cls, f, tau, u_in)
+        assert np.abs(got - want).max() < 1e-15
+        f = got
+
+
+def test_bruteforce_push_ad_d3q7():
+    """One D3Q7 substrate step in push form on the same duct: anti-bounce-
+    back Dirichlet inlet, zero-gradient outlet, zero-flux solids and walls,
+    biofilm active with the first-order sink, linear equilibrium with the
+    textbook weights 1/4 and 1/8 (c_s^2 = 1/4)."""
+    cls = _tiny_mask3d()
+    nz, ny, nx = cls.shape
+    c, _, opp, _ = O.lattice_tables(O.D3Q7)
+    w = np.where((c ** 2).sum(1) == 0, 0.25, 0.125)
+    act = ~np.isin(cls.ravel(), [O.SOLID, O.WALL])
+    rng = np.random.default_rng(7)
+    u = 0.05 * (rng.random((3, cls.size)) - 0.5)
+    g = rng.random((7, cls.size)) * act
+    D, c_in, k = 0.06, 0.9, 0.01
+    tau_d = 0.5 + D / 0.25
+    for _ in range(3):
+        def send(n, i, p, t):
+            if not act[n]:
+                return None
+            j = opp[i]
+            if t[0] < 0:
+                return (j, -p + 2 * w[j] * c_in)
+            if t[0] >= nx:
+                return (j, g[j, n])
+            if cls[t[2], t[1], t[0]] in (O.SOLID, O.WALL):
+                return (j, p)
+            return True
+        arr = _push3(cls, g, c, send)
+        want = np.zeros_like(g)
+        for n in np.flatnonzero(act):
+            gi = arr[:, n]
+            assert not np.isnan(gi).any()
+            C = gi.sum()
+            kk = k if cls.ravel()[n] == O.BIOFILM else 0.0
+            want[:, n] = gi - (gi - w * C * (1 + 4 * (c @ u[:, n]))) / tau_d - w * kk * C
+        got, _ = O.ad_step(cls, g, u, D, c_in, k)
+        assert np.abs(got - want).max() < 1e-15
+        g = got
+
+
 def test_inlet_injects_exactly_u_in_per_node():
     cls = _tiny_mask()
     rng = np.random.default_rng(5)
