@@ -6,10 +6,12 @@ Poiseuille flow (exact at the magic relaxation time, second order otherwise:
 Sec. 2.1.1), exact mass conservation, exact moment recurrences and the
 continuum Gaussian for the advection-diffusion LBM (Sec. 2.1.2, Eqs. 12-13),
 the exact discrete two-mode solution of the steady 1-D advection-diffusion-
-sink problem, flux balances at steady state, and an independent push-form
-brute force on tiny grids.  A plausible mistake in the oracle (a wrong weight,
-sign, opposite index, equilibrium term, inlet/outlet rule or sink form) fails
-at least one of them.
+sink problem, flux balances at steady state, uniform flow and uniform
+substrate as exact fixed points of the inlet and outlet rules, and an
+independent push-form brute force on tiny grids; most of them on the 3-D
+lattices (D3Q19, D3Q7) as well as the 2-D ones.  A plausible mistake in the
+oracle (a wrong weight, sign, opposite index, equilibrium term, inlet/outlet
+rule or sink form) fails at least one of them.
 """
 import math
 import os
