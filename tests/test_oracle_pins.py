@@ -329,6 +329,28 @@ def test_ad_closed_box_monod_sink_removes_exactly_q():
         g = g2
 
 
+@pytest.mark.parametrize("K", [0.0, 0.4])
+def test_ad_closed_box_sink_removes_exactly_q_3d(K):
+    """D3Q7 on a periodic fibre box with its biofilm layer: each step
+    removes the sum over biofilm nodes of k C (K = 0) or k C / (C + K)
+    (the Monod form), C the concentration the step collides with."""
+    st, cls, _ = O.geom_fibres(24, 12, 12, 1, 2, 0.2, 8)
+    assert st == "OK"
+    cls = O.biofilm_layer(cls)
+    bf = cls.ravel() == O.BIOFILM
+    assert bf.any()
+    rng = np.random.default_rng(9)
+    u = np.zeros((3, cls.size))
+    u[0] = 0.02 * (cls.ravel() == O.FLUID)
+    g = O.ad_init(cls, u, 1.0) * (1.0 + 0.1 * rng.random((7, cls.size)))
+    k = 3e-3
+    for _ in range(5):
+        g2, C = O.ad_step(cls, g, u, 0.05, 1.0, k, periodic=(1, 0, 0), k_half=K)
+        q = k * C[bf] if K == 0.0 else k * C[bf] / (C[bf] + K)
+        assert abs((g2.sum() - g.sum()) + q.sum()) < 1e-13 * g.sum()
+        g = g2
+
+
 def test_monod_uniform_biofilm_decay_recurrence():
     """A closed, uniform biofilm-filled box at rest: C follows
     C <- C - k C / (C + K) exactly, and each stored state gives back the
