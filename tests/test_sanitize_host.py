@@ -112,8 +112,12 @@ def test_server_emulation_under_tsan(tmp_path):
     switch between those and the 64 x 16 four-step plan (two-step launches
     first when K / 4 is odd) as the table grows and shrinks."""
     exe = _emu_build(tmp_path, "emu_tsan", CLANG, ["-O1", "-fsanitize=thread"])
-    for ty in (4, 16):
-        _emu_run(exe, 2, ty, {"TSAN_OPTIONS": "halt_on_error=1:abort_on_error=1"})
+    # the second run opens roctx ranges on every thread (stub marker library)
+    stub = str(tmp_path / "libroctx_stub.so")
+    _run(["gcc", "-std=c99", "-O1", "-fPIC", "-shared", os.path.join(HERE, "sanitize", "roctx_stub.c"),
+          "-o", stub, "-lpthread"])
+    for ty, extra in ((4, {}), (16, {"LBM_ROCTX": stub})):
+        _emu_run(exe, 2, ty, dict(TSAN_OPTIONS="halt_on_error=1:abort_on_error=1", **extra))
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="no g++")
